@@ -1,0 +1,83 @@
+/*
+ * Plain FP64 CPU oracle for the mollified nonlocal finite-element assembly of
+ * Aulisa, Capodaglio, Chierici, D'Elia, "Efficient quadrature rules for finite
+ * element discretizations of nonlocal equations" (arXiv 2101.08825).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this library.  The GPU library never
+ * links, includes or calls it, and it shares no code, header or table with it.
+ *
+ * Conventions: arrays are row-major and 0-based; element connectivity is int32,
+ * counts int64, all physical data double.  Simplices only (triangles, tets),
+ * P1 Lagrange basis.
+ */
+#ifndef NLQ_ORACLE_H
+#define NLQ_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t dim;
+    int64_t n_nodes;
+    int64_t n_elems;
+    const double *coords;   /* [n_nodes][dim] */
+    const int32_t *conn;    /* [n_elems][dim+1] */
+} or_mesh;
+
+typedef struct {
+    double delta, eps;
+    double scale;           /* > 0: kernel constant; 0: the paper's normalisation */
+    int32_t kernel;         /* 0: eta = 1; 1: eta = exp(-d^2/delta^2) */
+    int32_t lmin, lmax;     /* Algorithm 1 levels, 1 <= lmin <= lmax */
+    int32_t form;           /* 0: four-term integrand; 1: 2*(A21 + A22) */
+} or_params;
+
+double or_xi(double r);
+double or_mu(double d, double delta, double eps);
+double or_kernel_constant(int32_t dim, int32_t kernel, double delta, double eps);
+int32_t or_rule(int32_t dim, double *bary, double *w);
+void or_children(int32_t dim, const double *v, double *child);
+double or_aprxmax(int32_t dim, const double *lo1, const double *hi1,
+                  const double *lo2, const double *hi2);
+double or_aprxmin(int32_t dim, const double *lo1, const double *hi1,
+                  const double *lo2, const double *hi2);
+double or_elem_measure(const or_mesh *m, int64_t e);
+
+int64_t or_pairs(const or_mesh *m, double thr, int32_t nthreads,
+                 int64_t *offsets, int32_t *m_out);
+int64_t or_pairs_of(const or_mesh *m, double thr, int64_t l, int32_t *m_out);
+
+int64_t or_pattern(const or_mesh *m, const int64_t *pair_off, const int32_t *pair_m,
+                   int64_t *row_ptr, int32_t *col);
+
+int32_t or_pair_block(const or_mesh *m, const or_params *p, int64_t l, int64_t mm,
+                      double *E, int64_t *leaves, int64_t *evals);
+
+int32_t or_assemble(const or_mesh *m, const or_params *p, int32_t nthreads,
+                    const int64_t *pair_off, const int32_t *pair_m,
+                    int64_t n_sel, const int64_t *sel,
+                    const int64_t *row_ptr, const int32_t *col, double *val,
+                    int64_t *leaves, int64_t *evals);
+
+int64_t or_rows(const or_mesh *m, const or_params *p, double thr, int32_t nthreads,
+                int64_t n_rows, const int64_t *rows,
+                int64_t *row_len, int32_t *cols, double *vals);
+
+void or_load(const or_mesh *m, const double *f_nodal, const uint8_t *constrained,
+             double *F);
+void or_lift(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+             const uint8_t *constrained, const double *g, const double *F, double *Ft);
+int32_t or_cg(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+              const uint8_t *constrained, const double *rhs, double rtol, int32_t maxit,
+              double *w, double *relres);
+int32_t or_cholesky_solve(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                          const double *val, const uint8_t *constrained,
+                          const double *rhs, double *w);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

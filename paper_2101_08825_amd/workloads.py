@@ -1,0 +1,225 @@
+"""Seeded synthetic inputs shared by the GPU path, the oracle and the benchmark.
+
+This module generates problem *inputs* only: meshes, constrained-node flags,
+manufactured solutions sampled at the nodes, and the serving request stream.
+It holds none of the method's arithmetic (no kernel, quadrature, pair test,
+refinement or assembly), so both the library under test and the oracle can
+consume the same arrays without sharing any computation.
+
+Mesh layout (Kuhn / Freudenthal split of the unit cube into simplices):
+  * nodes x = (i0/n, i1/n[, i2/n]) with one correctly rounded FP64 division;
+    node id = i0 + (n+1)*(i1 + (n+1)*i2);
+  * cell id = c0 + n*(c1 + n*c2);
+  * element id = (#permutations)*cell + p, where p enumerates the
+    permutations pi of {0..N-1} in lexicographic order and the vertices follow
+    the Kuhn path v0 = cell origin, v_{k+1} = v_k + e_{pi(k)}.
+Every simplex contains the cell diagonal, so its bounding box is its cell.
+
+The interaction layer Gamma (Section 2, eq. interaction-domain) of a box mesh is
+the closed layer of width K cells at the boundary of [0,1]^N: a node is
+constrained when some index i_k <= K or i_k >= n - K.  The mesh covers
+Omega u Gamma; Omega is the open interior.
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Mesh:
+    dim: int
+    n: int                      # cells per direction
+    coords: np.ndarray          # [n_nodes, dim] float64
+    conn: np.ndarray            # [n_elems, dim+1] int32
+    constrained: np.ndarray     # [n_nodes] uint8, 1 = node in Gamma
+    k_gamma: int                # width of Gamma in cells
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.coords.shape[0])
+
+    @property
+    def n_elems(self) -> int:
+        return int(self.conn.shape[0])
+
+    @property
+    def h(self) -> float:
+        return 1.0 / self.n
+
+
+def kuhn_mesh(dim: int, n: int, k_gamma: int) -> Mesh:
+    """Kuhn simplicial mesh of [0,1]^dim with n cells per direction."""
+    if dim not in (2, 3):
+        raise ValueError("dim must be 2 or 3")
+    if n < 1 or k_gamma < 0:
+        raise ValueError("bad mesh size")
+    nn = n + 1
+    idx = np.arange(nn, dtype=np.int64)
+    if dim == 2:
+        i1, i0 = np.meshgrid(idx, idx, indexing="ij")
+        ii = [i0.ravel(), i1.ravel()]
+    else:
+        i2, i1, i0 = np.meshgrid(idx, idx, idx, indexing="ij")
+        ii = [i0.ravel(), i1.ravel(), i2.ravel()]
+    coords = np.stack([k.astype(np.float64) / float(n) for k in ii], axis=1)
+    constrained = np.zeros(coords.shape[0], dtype=np.uint8)
+    for k in ii:
+        constrained |= ((k <= k_gamma) | (k >= n - k_gamma)).astype(np.uint8)
+
+    perms = list(itertools.permutations(range(dim)))
+    cidx = np.arange(n, dtype=np.int64)
+    if dim == 2:
+        c1, c0 = np.meshgrid(cidx, cidx, indexing="ij")
+        cc = [c0.ravel(), c1.ravel()]
+    else:
+        c2, c1, c0 = np.meshgrid(cidx, cidx, cidx, indexing="ij")
+        cc = [c0.ravel(), c1.ravel(), c2.ravel()]
+    n_cells = cc[0].shape[0]
+    conn = np.zeros((n_cells, len(perms), dim + 1), dtype=np.int64)
+
+    def node_id(v):
+        out = v[0].copy()
+        mul = nn
+        for k in range(1, dim):
+            out += mul * v[k]
+            mul *= nn
+        return out
+
+    for p, pi in enumerate(perms):
+        v = [c.copy() for c in cc]
+        conn[:, p, 0] = node_id(v)
+        for k in range(dim):
+            v[pi[k]] = v[pi[k]] + 1
+            conn[:, p, k + 1] = node_id(v)
+    conn = conn.reshape(n_cells * len(perms), dim + 1).astype(np.int32)
+    return Mesh(dim=dim, n=n, coords=coords, conn=conn,
+                constrained=constrained, k_gamma=k_gamma)
+
+
+# ---------------------------------------------------------------------------
+# Manufactured data.  A quadratic u = sum a_k x_k^2 + sum_{k<l} b_kl x_k x_l
+# + c.x + d has Laplacian 2*sum a_k; f = -Laplacian(u) is then constant.
+# ---------------------------------------------------------------------------
+@dataclass
+class Quadratic:
+    a: np.ndarray                       # [dim]
+    b: np.ndarray = field(default=None)  # [dim, dim] strictly upper part used
+    c: np.ndarray = field(default=None)  # [dim]
+    d: float = 0.0
+
+    def __post_init__(self):
+        dim = len(self.a)
+        if self.b is None:
+            self.b = np.zeros((dim, dim))
+        if self.c is None:
+            self.c = np.zeros(dim)
+
+    def __call__(self, x: np.ndarray) -> np.ndarray:
+        dim = x.shape[1]
+        out = np.full(x.shape[0], float(self.d))
+        for k in range(dim):
+            out += self.a[k] * x[:, k] * x[:, k] + self.c[k] * x[:, k]
+            for l in range(k + 1, dim):
+                out += self.b[k, l] * x[:, k] * x[:, l]
+        return out
+
+    def laplacian(self) -> float:
+        return float(2.0 * np.sum(self.a))
+
+
+def nodal_data(mesh: Mesh, u: Quadratic):
+    """Nodal u (exact solution), f = -Laplacian(u) and g = u (read on Gamma)."""
+    uu = u(mesh.coords)
+    f = np.full(mesh.n_nodes, -u.laplacian())
+    return uu, f, uu.copy()
+
+
+# ---------------------------------------------------------------------------
+# Workload configurations (sizes of the paper-shaped problems).
+# ---------------------------------------------------------------------------
+@dataclass
+class Workload:
+    name: str
+    dim: int
+    n: int
+    k_delta: int            # delta = k_delta * h
+    eps_div: int            # eps = delta / eps_div
+    lmax: int
+    kernel: int             # 0 = constant eta, 1 = truncated Gaussian eta
+    u: Quadratic
+
+    @property
+    def h(self) -> float:
+        return 1.0 / self.n
+
+    @property
+    def delta(self) -> float:
+        return self.k_delta / self.n
+
+    @property
+    def eps(self) -> float:
+        return self.delta / self.eps_div
+
+    def mesh(self) -> Mesh:
+        return kuhn_mesh(self.dim, self.n, self.k_delta)
+
+
+def _ux1sq(dim):
+    a = np.zeros(dim)
+    a[0] = 1.0
+    return Quadratic(a)
+
+
+WORKLOADS = {
+    # 2D 16x16, delta = 2h, eps = delta/16, depth 3, u = x1^2
+    "c1_2d16": Workload("c1_2d16", 2, 16, 2, 16, 3, 0, _ux1sq(2)),
+    # 2D 128x128, delta in {2h, 4h}, eps = delta/32, depth 5, u = x1^2 + x2^2
+    "c2a_2d128_d2h": Workload("c2a_2d128_d2h", 2, 128, 2, 32, 5, 0, Quadratic(np.ones(2))),
+    "c2b_2d128_d4h": Workload("c2b_2d128_d4h", 2, 128, 4, 32, 5, 0, Quadratic(np.ones(2))),
+    # 3D 24^3 x 6 tets, delta = 3h (= 0.125), eps = delta/16, depth 4, u = x1^2
+    "c3_3d24": Workload("c3_3d24", 3, 24, 3, 16, 4, 0, _ux1sq(3)),
+    # 3D 48^3 x 6 tets, truncated Gaussian, delta = 3h, eps = delta/32, depth 6
+    "c5_3d48_gauss": Workload("c5_3d48_gauss", 3, 48, 3, 32, 6, 1, _ux1sq(3)),
+}
+
+
+def random_quadratic(rng: np.random.Generator, dim: int) -> Quadratic:
+    """u = sum a_k x_k^2 + sum_{k<l} b_kl x_k x_l + c.x + d, all U(-1,1)."""
+    a = rng.uniform(-1, 1, dim)
+    b = np.triu(rng.uniform(-1, 1, (dim, dim)), 1)
+    c = rng.uniform(-1, 1, dim)
+    d = float(rng.uniform(-1, 1))
+    return Quadratic(a, b, c, d)
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival_s: float
+    dim: int
+    n: int
+    k_delta: int
+    eps_div: int
+    lmax: int
+    u: Quadratic
+
+
+def serving_stream(n_requests: int = 256, rate_per_s: float = 20.0, seed: int = 0,
+                   lmax: int = 3, eps_div: int = 16) -> list[Request]:
+    """Poisson arrivals; 2D meshes 8^2..96^2 and 3D 6^3..20^3 with sizes
+    uniform in log; delta in {2h, 3h, 4h}; random quadratic u."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for rid in range(n_requests):
+        t += float(rng.exponential(1.0 / rate_per_s))
+        dim = 2 if rng.uniform() < 0.5 else 3
+        lo, hi = (8, 96) if dim == 2 else (6, 20)
+        n = int(round(float(np.exp(rng.uniform(np.log(lo), np.log(hi))))))
+        k_delta = int(rng.integers(2, 5))
+        out.append(Request(rid, t, dim, n, k_delta, eps_div, lmax,
+                           random_quadratic(rng, dim)))
+    return out

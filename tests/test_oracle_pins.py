@@ -1,0 +1,575 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Every check here uses code independent of the oracle's own arithmetic (scipy
+quadrature, closed forms, numpy brute force, sparse-matrix algebra), so that a
+dropped term, a wrong sign or index, or a transposed operand in the oracle fails
+at least one of them.  No GPU is needed.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.integrate as si
+import scipy.sparse as sp
+
+from paper_2101_08825_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _frac(s):
+    return float(eval(s, {"pi": math.pi}))
+
+
+# ----------------------------------------------------------------- mollifier
+
+def test_xi_endpoints_and_derivative(oracle_lib):
+    """Section 3, eq. (mollifier): xi(1) = 1, xi(-1) = 0 (read with argument
+    (delta-|x-y|)/eps), and xi' = (315/256)(1-r^2)^4, i.e. C^4 at both ends."""
+    O = oracle_lib
+    assert O.xi(1.0) == pytest.approx(1.0, abs=1e-15)
+    assert O.xi(-1.0) == pytest.approx(0.0, abs=1e-15)
+    assert O.xi(0.0) == pytest.approx(0.5, abs=1e-15)
+    # recover the polynomial by exact interpolation at 10 nodes and differentiate
+    r = np.cos(np.pi * (np.arange(10) + 0.5) / 10)
+    coef = np.polyfit(r, [O.xi(x) for x in r], 9)
+    dcoef = np.polyder(coef)
+    target = np.polymul([315.0 / 256.0], np.polynomial.polynomial.polypow([1, 0, -1], 4)[::-1])
+    assert np.allclose(dcoef, target, atol=1e-10)
+    # derivatives 1..4 of xi vanish at r = +-1
+    for k in range(1, 5):
+        dk = np.polyder(coef, k)
+        assert abs(np.polyval(dk, 1.0)) < 1e-8 and abs(np.polyval(dk, -1.0)) < 1e-8
+
+
+def test_mu_band(oracle_lib):
+    O = oracle_lib
+    delta, eps = 0.125, 0.125 / 16
+    assert O.mu(delta - eps, delta, eps) == pytest.approx(1.0, abs=1e-14)
+    assert O.mu(delta + eps, delta, eps) == pytest.approx(0.0, abs=1e-14)
+    assert O.mu(delta, delta, eps) == pytest.approx(0.5, abs=1e-14)
+    d = np.linspace(delta - 2 * eps, delta + 2 * eps, 401)
+    v = np.array([O.mu(x, delta, eps) for x in d])
+    assert np.all(np.diff(v) <= 1e-15) and v.min() >= -1e-15 and v.max() <= 1 + 1e-15
+
+
+def _radial_moment(mu_fn, dim, delta, eps, eta=lambda r: 1.0):
+    f = lambda r: r ** (dim + 1) * eta(r) * mu_fn(r)
+    a = si.quad(f, 0, delta - eps, epsabs=0, epsrel=1e-13, limit=200)[0]
+    b = si.quad(f, delta - eps, delta + eps, epsabs=0, epsrel=1e-13, limit=200)[0]
+    return a + b
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("q", [1 / 32, 1 / 16, 1 / 4, 1 / 2])
+def test_constant_moment_identity(oracle_lib, dim, q):
+    """Section 6 constants: C_{delta,eps} omega_N int rho^{N+1} mu drho = N, the
+    condition L_eps u = Laplacian u for quadratic u.  The printed C_{delta,eps}
+    satisfies it only with the xi argument (delta-|x-y|)/eps."""
+    O = oracle_lib
+    g = json.load(open(os.path.join(GOLD, "kernel_constants.json")))[str(dim)]
+    delta = 0.13
+    eps = q * delta
+    C = O.kernel_constant(dim, 0, delta, eps)
+    printed = _frac(g["num"]) / delta ** (dim + 2) / (
+        1 + _frac(g["q2"]) * q * q + _frac(g["q4"]) * q ** 4)
+    assert C == pytest.approx(printed, rel=1e-14)
+    omega = 2 * math.pi if dim == 2 else 4 * math.pi
+    mom = _radial_moment(lambda r: O.mu(r, delta, eps), dim, delta, eps)
+    assert C * omega * mom == pytest.approx(dim, rel=1e-12)
+    # the argument as printed ((delta-eps)-|x-y|)/eps breaks the identity
+    lit = lambda r: 1.0 if r < delta - eps else (
+        0.0 if r > delta + eps else O.xi(((delta - eps) - r) / eps))
+    assert abs(C * omega * _radial_moment(lit, dim, delta, eps) - dim) > 1e-3
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gauss_constant_moment_identity(oracle_lib, dim):
+    O = oracle_lib
+    delta = 3 / 48
+    eps = delta / 32
+    c = O.kernel_constant(dim, 1, delta, eps)
+    omega = 2 * math.pi if dim == 2 else 4 * math.pi
+    mom = _radial_moment(lambda r: O.mu(r, delta, eps), dim, delta, eps,
+                         eta=lambda r: math.exp(-r * r / delta ** 2))
+    assert c * omega * mom == pytest.approx(dim, rel=1e-12)
+
+
+def _nonlocal_laplacian(O, u, x, dim, delta, eps, C):
+    """2 int (u(x+z) - u(x)) C mu(|z|) dz by polar quadrature (Gauss-Legendre in
+    rho on the two smooth pieces, trapezoid in angle)."""
+    gx, gw = np.polynomial.legendre.leggauss(40)
+    total = 0.0
+    for a, b in ((0.0, delta - eps), (delta - eps, delta + eps)):
+        rho = 0.5 * (a + b) + 0.5 * (b - a) * gx
+        wr = 0.5 * (b - a) * gw
+        for r, wq in zip(rho, wr):
+            m = O.mu(r, delta, eps)
+            if dim == 2:
+                th = np.linspace(0, 2 * np.pi, 64, endpoint=False)
+                z = np.stack([np.cos(th), np.sin(th)], 1) * r
+                s = np.mean(u(x[None, :] + z) - u(x[None, :])) * 2 * np.pi * r
+            else:
+                tg, tw = np.polynomial.legendre.leggauss(16)
+                ph = np.linspace(0, 2 * np.pi, 32, endpoint=False)
+                T, P = np.meshgrid(tg, ph, indexing="ij")
+                st = np.sqrt(1 - T ** 2)
+                z = np.stack([st * np.cos(P), st * np.sin(P), T], -1).reshape(-1, 3) * r
+                wts = (np.repeat(tw, 32) * (2 * np.pi / 32))
+                s = np.sum(wts * (u(x[None, :] + z) - u(x[None, :]))) * r * r
+            total += wq * m * s
+    return 2 * C * total
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_nonlocal_laplacian_of_quadratic(oracle_lib, dim):
+    """L_eps u = Laplacian u exactly for quadratic (and cubic) u."""
+    O = oracle_lib
+    delta, eps = 0.125, 0.125 / 16
+    C = O.kernel_constant(dim, 0, delta, eps)
+    rng = np.random.default_rng(3)
+    q = W.random_quadratic(rng, dim)
+    x = np.full(dim, 0.5)
+    val = _nonlocal_laplacian(O, q, x, dim, delta, eps, C)
+    assert val == pytest.approx(q.laplacian(), rel=1e-10)
+    cubic = lambda p: p[:, 0] ** 3 + 0.5 * p[:, 1] ** 3
+    val = _nonlocal_laplacian(O, cubic, x, dim, delta, eps, C)
+    assert val == pytest.approx(6 * 0.5 + 3 * 0.5, rel=1e-10)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_quartic_forcing_printed(oracle_lib, dim):
+    """Section 6 prints the quartic forcing terms: L x1^4 = 12 x1^2 + c delta^2
+    with c = 1 (2D) and 6/7 (3D) for the exact kernel; the mollified kernel tends
+    to it as eps -> 0 (difference O(eps^2))."""
+    O = oracle_lib
+    g = json.load(open(os.path.join(GOLD, "quartic_forcing.json")))[str(dim)]
+    delta = 0.2
+    x = np.full(dim, 0.3)
+    u = lambda p: p[:, 0] ** 4
+    errs = []
+    for q in (1 / 8, 1 / 16, 1 / 32):
+        eps = q * delta
+        C = O.kernel_constant(dim, 0, delta, eps)
+        val = _nonlocal_laplacian(O, u, x, dim, delta, eps, C)
+        errs.append(abs(val - (12 * x[0] ** 2 + g["c"] * delta ** 2)))
+    assert errs[-1] < 1e-3 * delta ** 2
+    assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0
+
+
+# ----------------------------------------------------------------- quadrature
+
+def _dirichlet(al, dim):
+    """int over the reference simplex (volume 1) of prod lambda_k^al_k."""
+    return math.factorial(dim) * np.prod([math.factorial(a) for a in al]) / math.factorial(
+        sum(al) + dim)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_quadrature_degree5(oracle_lib, dim):
+    bary, w = oracle_lib.rule(dim)
+    assert len(w) == (7 if dim == 2 else 15)
+    assert np.all(w > 0) and abs(w.sum() - 1) < 1e-15
+    assert np.all(bary >= -1e-15) and np.allclose(bary.sum(1), 1, atol=1e-15)
+    for deg in range(7):
+        err = 0.0
+        for al in itertools.product(range(deg + 1), repeat=dim + 1):
+            if sum(al) != deg:
+                continue
+            q = float(np.sum(w * np.prod(bary ** np.array(al), axis=1)))
+            err = max(err, abs(q - _dirichlet(al, dim)))
+        if deg <= 5:
+            assert err < 4e-16, (deg, err)
+        else:
+            assert err > 1e-7  # degree 5 exactly
+
+
+# ----------------------------------------------------------------- refinement
+
+def _measure(v):
+    d = v.shape[1]
+    return abs(np.linalg.det((v[1:] - v[0]).T)) / math.factorial(d)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_children_tile_parent(oracle_lib, dim):
+    """Midpoint refinement: 2^N children of equal measure that tile the parent."""
+    rng = np.random.default_rng(1)
+    v = rng.uniform(size=(dim + 1, dim))
+    ch = oracle_lib.children(v)
+    assert ch.shape[0] == 2 ** dim
+    meas = np.array([_measure(c) for c in ch])
+    assert np.allclose(meas, _measure(v) / 2 ** dim, rtol=1e-12)
+    # random points of the parent lie in exactly one child
+    lam = rng.dirichlet(np.ones(dim + 1), 2000)
+    pts = lam @ v
+    hits = np.zeros(len(pts), dtype=int)
+    for c in ch:
+        T = np.vstack([c.T, np.ones(dim + 1)])
+        b = np.linalg.solve(T, np.vstack([pts.T, np.ones(len(pts))]))
+        hits += np.all(b > -1e-12, axis=0)
+    assert np.all(hits == 1)
+    lo, hi = v.min(0), v.max(0)
+    assert np.all(ch.min(1) >= lo - 1e-15) and np.all(ch.max(1) <= hi + 1e-15)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_children_of_kuhn_are_kuhn(oracle_lib, dim):
+    """For Kuhn simplices the children are Kuhn simplices of the half-size cubes:
+    each child's bbox is a dyadic sub-cube and its vertices form a monotone path."""
+    mesh = W.kuhn_mesh(dim, 1, 0)
+    for e in range(mesh.n_elems):
+        v = mesh.coords[mesh.conn[e]]
+        for c in oracle_lib.children(v):
+            lo, hi = c.min(0), c.max(0)
+            assert np.allclose(hi - lo, 0.5)
+            assert np.allclose(lo * 2, np.round(lo * 2))
+            # sort vertices by coordinate sum: consecutive steps are unit moves
+            order = np.argsort(c.sum(1))
+            steps = np.diff(c[order], axis=0)
+            assert np.all(np.isclose(np.abs(steps).sum(1), 0.5))
+            assert np.all(steps >= -1e-15)
+
+
+# ----------------------------------------------------------------- distances
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_distance_inequalities(oracle_lib, dim):
+    """Section 5.1, eqs. (maxdistin), (mindistin): aprx max >= max distance,
+    aprx min <= min distance, checked on sampled points of random simplices."""
+    O = oracle_lib
+    rng = np.random.default_rng(7)
+    for _ in range(40):
+        a = rng.uniform(size=(dim + 1, dim))
+        b = rng.uniform(size=(dim + 1, dim)) + rng.uniform(-1, 1, dim)
+        la = rng.dirichlet(np.ones(dim + 1), 300) @ a
+        lb = rng.dirichlet(np.ones(dim + 1), 300) @ b
+        la = np.vstack([la, a])
+        lb = np.vstack([lb, b])
+        dd = np.linalg.norm(la[:, None, :] - lb[None, :, :], axis=2)
+        amax = O.aprxmax(a.min(0), a.max(0), b.min(0), b.max(0))
+        amin = O.aprxmin(a.min(0), a.max(0), b.min(0), b.max(0))
+        assert amax >= dd.max() - 1e-14
+        assert amin <= dd.min() + 1e-14
+        # aprx max is the largest distance between opposite bbox corners
+        corners = lambda lo, hi: np.array(list(itertools.product(*zip(lo, hi))))
+        ca, cb = corners(a.min(0), a.max(0)), corners(b.min(0), b.max(0))
+        assert amax == pytest.approx(
+            np.linalg.norm(ca[:, None] - cb[None], axis=2).max(), rel=1e-14)
+
+
+# ----------------------------------------------------------------- pair list
+
+def _kuhn_pair_count(dim, n, thr_over_h):
+    K = 0
+    while max(K + 1 - 1, 0) < thr_over_h:
+        K += 1
+    K -= 1 if max(K - 1, 0) >= thr_over_h else 0
+    # K = max{d : max(d-1, 0) < thr/h}
+    K = max(d for d in range(0, n + 2) if max(d - 1, 0) < thr_over_h)
+    types = math.factorial(dim)
+    return types ** 2 * (n * (2 * K + 1) - K * (K + 1)) ** dim
+
+
+def _numpy_pairs(mesh, thr):
+    v = mesh.coords[mesh.conn]
+    lo, hi = v.min(1), v.max(1)
+    gap = np.maximum(lo[:, None, :] - hi[None, :, :], lo[None, :, :] - hi[:, None, :])
+    gap = np.maximum(gap, 0).max(2)
+    return gap < thr
+
+
+@pytest.mark.parametrize("dim,n,kd,ed", [(2, 16, 2, 16), (2, 12, 3, 32), (3, 5, 2, 16)])
+def test_pairs_bruteforce_and_closed_form(oracle_lib, dim, n, kd, ed):
+    O = oracle_lib
+    mesh = W.kuhn_mesh(dim, n, kd)
+    delta = kd / n
+    thr = delta + delta / ed
+    m = O.OracleMesh(mesh.coords, mesh.conn)
+    off, pm = O.pairs(m, thr)
+    ref = _numpy_pairs(mesh, thr)
+    assert off[-1] == ref.sum()
+    for l in range(mesh.n_elems):
+        assert np.array_equal(pm[off[l]:off[l + 1]], np.nonzero(ref[l])[0])
+    assert off[-1] == _kuhn_pair_count(dim, n, thr * n)
+    assert np.array_equal(ref, ref.T)
+
+
+def test_pair_counts_match_table():
+    """Closed-form pair counts of the 2D 128^2 and 3D configurations."""
+    assert _kuhn_pair_count(2, 16, 2 + 2 / 16) == 40000
+    assert _kuhn_pair_count(2, 128, 2 + 2 / 32) == 3125824
+    assert _kuhn_pair_count(2, 128, 4 + 4 / 32) == 7595536
+    assert _kuhn_pair_count(3, 24, 3 + 3 / 16) == 271063296
+
+
+# ----------------------------------------------------------------- pattern
+
+def _incidence(mesh):
+    ne, nv = mesh.conn.shape
+    return sp.csr_matrix((np.ones(ne * nv), (np.repeat(np.arange(ne), nv), mesh.conn.ravel())),
+                         shape=(ne, mesh.n_nodes))
+
+
+@pytest.mark.parametrize("dim,n,kd", [(2, 16, 2), (3, 5, 2)])
+def test_pattern_sparse_algebra(oracle_lib, dim, n, kd):
+    """pattern = nonzeros of N^T (I + P + P^T) N, N the element-node incidence and
+    P the pair adjacency: (i, j) is an entry iff both lie in nodes(l) u nodes(m)
+    for some pair (l, m)."""
+    O = oracle_lib
+    mesh = W.kuhn_mesh(dim, n, kd)
+    delta = kd / n
+    thr = delta + delta / 16
+    m = O.OracleMesh(mesh.coords, mesh.conn)
+    off, pm = O.pairs(m, thr)
+    rp, col = O.pattern(m, off, pm)
+    ne = mesh.n_elems
+    P = sp.csr_matrix((np.ones(len(pm)), (np.repeat(np.arange(ne), np.diff(off)), pm)),
+                      shape=(ne, ne))
+    N = _incidence(mesh)
+    S = (N.T @ (sp.identity(ne) + P + P.T) @ N).tocsr()
+    S.sort_indices()
+    assert np.array_equal(rp, S.indptr) and np.array_equal(col, S.indices)
+    if (dim, n, kd) == (2, 16, 2):
+        assert rp[-1] == 17689
+
+
+# ----------------------------------------------------------------- assembly
+
+def _dense(rp, col, val, n):
+    A = np.zeros((n, n))
+    for i in range(n):
+        A[i, col[rp[i]:rp[i + 1]]] += val[rp[i]:rp[i + 1]]
+    return A
+
+
+def _assemble(O, mesh, prm):
+    m = O.OracleMesh(mesh.coords, mesh.conn)
+    off, pm = O.pairs(m, prm.delta + prm.eps)
+    rp, col = O.pattern(m, off, pm)
+    val, leaves, evals = O.assemble(m, prm, off, pm, rp, col)
+    return m, off, pm, rp, col, val, leaves, evals
+
+
+@pytest.mark.parametrize("dim,n", [(2, 4), (3, 2)])
+@pytest.mark.parametrize("form", [0, 1])
+def test_plateau_closed_form(oracle_lib, dim, n, form):
+    """When delta - eps exceeds the diameter of the domain, every pair is
+    integrated at level 1 with gamma = C, and eq. (Aij-support2) reduces to
+    A = 2C(|D| M - m m^T), M the P1 mass matrix and m_i = int phi_i (the same for
+    the two-term form 2A21 + 2A22 of the Corollary)."""
+    O = oracle_lib
+    mesh = W.kuhn_mesh(dim, n, 0)
+    delta, eps = 2.5, 0.1
+    prm = O.params(delta, eps, 3, form=form)
+    m, off, pm, rp, col, val, leaves, evals = _assemble(O, mesh, prm)
+    assert leaves[1] == off[-1] and leaves[2:].sum() == 0
+    A = _dense(rp, col, val, mesh.n_nodes)
+    C = O.kernel_constant(dim, 0, delta, eps)
+    nn = mesh.n_nodes
+    M = np.zeros((nn, nn))
+    mvec = np.zeros(nn)
+    for e in range(mesh.n_elems):
+        v = mesh.coords[mesh.conn[e]]
+        meas = _measure(v)
+        loc = meas / ((dim + 1) * (dim + 2)) * (np.ones((dim + 1, dim + 1)) + np.eye(dim + 1))
+        idx = mesh.conn[e]
+        M[np.ix_(idx, idx)] += loc
+        mvec[idx] += meas / (dim + 1)
+    ref = 2 * C * (1.0 * M - np.outer(mvec, mvec))
+    assert np.abs(A - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_c1_counts_and_invariants(oracle_lib):
+    """2D 16^2 configuration: counts, zero row sums, exact symmetry (four-term
+    form), leaves per level."""
+    O = oracle_lib
+    wl = W.WORKLOADS["c1_2d16"]
+    mesh = wl.mesh()
+    prm = O.params(wl.delta, wl.eps, wl.lmax)
+    m, off, pm, rp, col, val, leaves, evals = _assemble(O, mesh, prm)
+    assert off[-1] == 40000 and len(col) == 17689
+    assert list(leaves[1:4]) == [1024, 7680, 437312]
+    assert evals[0] == 446016 * 49
+    A = _dense(rp, col, val, mesh.n_nodes)
+    assert np.abs(A.sum(1)).max() <= 1e-14 * np.abs(A).sum(1).max()
+    assert np.linalg.norm(A - A.T) <= 1e-15 * np.linalg.norm(A)
+    assert np.all(np.diag(A) > 0)
+
+
+def test_two_term_form_vs_four_term(oracle_lib):
+    """The Corollary's two-term form 2A21 + 2A22 has zero row sums.  It equals the
+    four-term form exactly when the outer and inner rules coincide (L_max = 1:
+    the discrete A11 = A22, A12 = A21 of the Corollary hold); with an adaptive
+    outer rule the two differ by the x<->y asymmetry of the composite rule, which
+    is set by the (unrefined) inner rule and shrinks as the band widens."""
+    O = oracle_lib
+    mesh = W.kuhn_mesh(2, 6, 2)
+    delta = 2 / 6
+    dist = []
+    for lmax, q in ((1, 4), (4, 8), (4, 4), (4, 2)):
+        eps = delta / q
+        A4 = _dense(*_assemble(O, mesh, O.params(delta, eps, lmax, form=0))[3:6], mesh.n_nodes)
+        A2 = _dense(*_assemble(O, mesh, O.params(delta, eps, lmax, form=1))[3:6], mesh.n_nodes)
+        assert np.abs(A2.sum(1)).max() <= 1e-13 * np.abs(A2).max()
+        dist.append(np.linalg.norm(A2 - A4) / np.linalg.norm(A4))
+    assert dist[0] < 1e-14
+    assert 1e-3 > dist[1] > dist[2] > dist[3] > 1e-14
+
+
+def _uniform_outer_matrix(mesh, delta, eps, C, depth, bary, w):
+    """Every element as outer element, uniformly subdivided `depth` times (no
+    bbox pruning); every other element as inner element with the Gauss rule on
+    the whole element; four-term integrand.  numpy, independent of the oracle."""
+    dim = mesh.dim
+    nv = dim + 1
+
+    def kids(V):
+        pts = list(V)
+        for i in range(nv):
+            for j in range(i + 1, nv):
+                pts.append((V[i] + V[j]) / 2)
+        P = np.array(pts)
+        if dim == 2:
+            T = [[0, 3, 4], [3, 1, 5], [4, 5, 2], [3, 4, 5]]
+        else:
+            T = [[0, 4, 5, 6], [4, 1, 7, 8], [5, 7, 2, 9], [6, 8, 9, 3], [4, 5, 6, 8],
+                 [4, 5, 7, 8], [5, 6, 8, 9], [5, 7, 8, 9]]
+        return [P[t] for t in T]
+
+    subs = [np.eye(nv)]
+    for _ in range(depth):
+        subs = [c for s in subs for c in kids(s)]
+    lx = np.concatenate([bary @ s for s in subs])      # outer barycentrics
+    wx = np.tile(w, len(subs)) / len(subs)
+    ly, wy = bary, w
+    nn = mesh.n_nodes
+    A = np.zeros((nn, nn))
+    V = mesh.coords[mesh.conn]
+    X = np.einsum("qv,evd->eqd", lx, V)
+    Y = np.einsum("qv,evd->eqd", ly, V)
+    meas = np.array([_measure(v) for v in V])
+    for l in range(mesh.n_elems):
+        for mm in range(mesh.n_elems):
+            d = np.linalg.norm(X[l][:, None, :] - Y[mm][None, :, :], axis=2)
+            r = (delta - d) / eps
+            xi = (128 + 315 * r - 420 * r ** 3 + 378 * r ** 5 - 180 * r ** 7 + 35 * r ** 9) / 256
+            mu = np.where(d < delta - eps, 1.0, np.where(d > delta + eps, 0.0, xi))
+            G = C * mu * np.outer(wx * meas[l], wy * meas[mm])
+            il, im = mesh.conn[l], mesh.conn[mm]
+            A[np.ix_(il, il)] += lx.T @ (G.sum(1)[:, None] * lx)
+            A[np.ix_(im, im)] += ly.T @ (G.sum(0)[:, None] * ly)
+            Blm = -lx.T @ G @ ly
+            A[np.ix_(il, im)] += Blm
+            A[np.ix_(im, il)] += Blm.T
+    return A
+
+
+@pytest.mark.parametrize("dim,n,kd,q,lmax", [(2, 4, 2, 4, 4), (2, 5, 2, 16, 3), (3, 2, 2, 4, 2)])
+def test_algorithm1_equals_uniform_outer_refinement(oracle_lib, dim, n, kd, q, lmax):
+    """Algorithm 1 with eta = 1 integrates a piece at a coarse level only when
+    gamma is constant on it (aprx max < delta - eps: every point pair on the
+    plateau, the integrand of eq. (Aij-support2) is then quadratic in x and the
+    degree-5 rule is exact) or zero (aprx min >= delta + eps).  So the adaptive
+    matrix equals uniform outer refinement to level L_max with no pruning,
+    to round-off."""
+    O = oracle_lib
+    mesh = W.kuhn_mesh(dim, n, 0)
+    delta = kd / n + 0.37 / n
+    eps = delta / q
+    C = O.kernel_constant(dim, 0, delta, eps)
+    bary, w = O.rule(dim)
+    Au = _uniform_outer_matrix(mesh, delta, eps, C, lmax - 1, bary, w)
+    m, off, pm, rp, col, val, leaves, evals = _assemble(O, mesh, O.params(delta, eps, lmax))
+    assert leaves[1:lmax].sum() > 0  # some pieces were settled before L_max
+    Aad = _dense(rp, col, val, mesh.n_nodes)
+    assert np.linalg.norm(Aad - Au) <= 1e-13 * np.linalg.norm(Au)
+    # and a coarser L_max is visibly different (the band is not resolved)
+    A2 = _dense(*_assemble(O, mesh, O.params(delta, eps, 1))[3:6], mesh.n_nodes)
+    assert np.linalg.norm(A2 - Au) > 1e-6 * np.linalg.norm(Au)
+
+
+def test_per_pair_equals_per_element_recursion(oracle_lib):
+    """Algorithm 1 run per outer element with J = J_l gives the same pair blocks
+    as runs with J = {m} (classification of m depends only on (s, m)); checked
+    through the sampled-row path against the full assembly."""
+    O = oracle_lib
+    wl = W.WORKLOADS["c1_2d16"]
+    mesh = wl.mesh()
+    prm = O.params(wl.delta, wl.eps, wl.lmax)
+    m, off, pm, rp, col, val, leaves, evals = _assemble(O, mesh, prm)
+    rows = [0, 37, 144, 150, 288]
+    out = O.rows(m, prm, wl.delta + wl.eps, rows)
+    for r, (c, v) in zip(rows, out):
+        assert np.array_equal(c, col[rp[r]:rp[r + 1]])
+        assert np.allclose(v, val[rp[r]:rp[r + 1]], rtol=1e-13, atol=1e-13 * np.abs(v).max())
+
+
+# ----------------------------------------------------------------- solve
+
+def test_cg_equals_cholesky(oracle_lib):
+    O = oracle_lib
+    wl = W.WORKLOADS["c1_2d16"]
+    mesh = wl.mesh()
+    u, f, g = W.nodal_data(mesh, wl.u)
+    prm = O.params(wl.delta, wl.eps, wl.lmax)
+    s = O.solve_problem((mesh.coords, mesh.conn, mesh.constrained), prm, f, g)
+    w = O.cholesky_solve(s.row_ptr, s.col, s.val, mesh.constrained, s.Ft)
+    free = mesh.constrained == 0
+    assert np.abs(w[free] - s.u[free]).max() <= 1e-12 * np.abs(w[free]).max()
+
+
+def _l2_error(mesh, uh, uex):
+    O_bary = np.array([[1 / 3, 1 / 3, 1 / 3]])
+    err = 0.0
+    dim = mesh.dim
+    import oracle
+    bary, w = oracle.rule(dim)
+    for e in range(mesh.n_elems):
+        v = mesh.coords[mesh.conn[e]]
+        meas = _measure(v)
+        x = bary @ v
+        diff = bary @ uh[mesh.conn[e]] - uex(x)
+        err += meas * np.sum(w * diff ** 2)
+    del O_bary
+    return math.sqrt(err)
+
+
+@pytest.mark.parametrize("lmax,q", [(1, 8), (2, 8), (3, 16), (4, 4)])
+def test_linear_u_reproduced(oracle_lib, lmax, q):
+    """Section 6 (consistency): for u = 1 + x + y (f = 0) the error is zero for
+    any L_max and eps.  Holds here to round-off once the constrained layer covers
+    the kernel support delta + eps (a layer of width exactly delta cuts the
+    mollifier tail and leaves an O(eps) boundary residual)."""
+    O = oracle_lib
+    n, kd = 16, 4
+    mesh = W.kuhn_mesh(2, n, kd + 1)
+    delta = kd / n
+    eps = delta / q
+    u = lambda x: 1 + x[:, 0] + x[:, 1]
+    s = O.solve_problem((mesh.coords, mesh.conn, mesh.constrained),
+                        O.params(delta, eps, lmax), np.zeros(mesh.n_nodes), u(mesh.coords))
+    assert np.abs(s.u - u(mesh.coords)).max() < 1e-12
+
+
+def test_h_convergence_rate(oracle_lib):
+    """Tables tab_mesh_convergence1 (TRI, linear FE): p ~ 2 for u = x^3 + y^3 with
+    f = -6(x+y); Kuhn meshes h = 1/8, 1/16, 1/32, delta = 1/4 fixed."""
+    O = oracle_lib
+    gold = json.load(open(os.path.join(GOLD, "tri_linear_hconv.json")))
+    uex = lambda x: x[:, 0] ** 3 + x[:, 1] ** 3
+    errs = []
+    for n in (8, 16, 32):
+        mesh = W.kuhn_mesh(2, n, n // 4)
+        delta = 0.25
+        eps = delta / 16
+        f = -6.0 * (mesh.coords[:, 0] + mesh.coords[:, 1])
+        s = O.solve_problem((mesh.coords, mesh.conn, mesh.constrained),
+                            O.params(delta, eps, 3), f, uex(mesh.coords))
+        errs.append(_l2_error(mesh, s.u, uex))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(gold["rates_cubic"]) > 1.9
+    assert all(abs(r - 2.0) < 0.3 for r in rates), rates
