@@ -1,0 +1,226 @@
+/*
+ * nlq -- mollified nonlocal finite-element assembly and solve on one AMD MI355X
+ * (gfx950), after Aulisa, Capodaglio, Chierici, D'Elia, "Efficient quadrature
+ * rules for finite element discretizations of nonlocal equations"
+ * (arXiv 2101.08825).
+ *
+ * Problem (Section 2, eqs. (poisson), (A-F); Section 3, eqs. (approx-kernel),
+ * (mollifier), (Aeps)): find u with u = g on the interaction layer Gamma and
+ *     A_eps(u, phi) = int_Omega f phi   for every P1 test function phi
+ * vanishing on Gamma, where
+ *     A_eps(u, phi) = iint (u(y)-u(x)) (phi(y)-phi(x)) gamma_eps(x, y) dy dx,
+ *     gamma_eps = C eta(|x-y|) mu_{delta,eps}(|x-y|),
+ * and mu is the C^4 mollifier that replaces the indicator of the ball B_delta
+ * (band of width 2 eps around |x-y| = delta).  The stiffness entries
+ * (Section 4, eq. (Aij-support2)) are summed over ordered element pairs (l, m)
+ * within the horizon (Section 5, eq. (k_l) with the bbox distance of eq.
+ * (mindist)); each pair is integrated with the adaptive outer quadrature of
+ * Algorithm 1 (Section 5) and a fixed Gauss rule on the inner element.
+ *
+ * Conventions
+ *  - Every call returns nlq_status: 0 = OK, < 0 = error; nothing aborts.  The
+ *    message of the last error of the calling thread is nlq_last_error().
+ *  - Arrays are 0-based and row-major.  Ids are int32, counts int64, physical
+ *    data double.  "host" pointers are CPU memory; "device" pointers are HBM.
+ *  - The library copies every input it keeps.  Outputs are either copied into
+ *    caller-owned buffers (nlq_*_copy) or borrowed device pointers valid until
+ *    the owning handle is destroyed (nlq_csr_device).
+ *  - Handles are not thread-safe, except nlq_submit / nlq_wait / nlq_cancel /
+ *    nlq_result_release, which may be called from any thread.
+ *  - All device work of a context runs on the context's HIP stream (a stream
+ *    of its own unless nlq_ctx_set_stream was called); calls that return host
+ *    data synchronise that stream.
+ */
+#ifndef NLQ_H
+#define NLQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NLQ_OK = 0,
+    NLQ_EINVAL = -1,      /* bad argument (message in nlq_last_error) */
+    NLQ_ENOMEM = -2,      /* would exceed the context's HBM budget, or allocation failed */
+    NLQ_EDEVICE = -3,     /* HIP runtime error */
+    NLQ_ENOTREADY = -4,   /* nlq_wait timed out */
+    NLQ_ECANCELLED = -5,  /* request was cancelled */
+    NLQ_EBUSY = -6,       /* queue full */
+    NLQ_ENOCONV = -7      /* CG did not reach the tolerance; u holds the last iterate */
+} nlq_status;
+
+enum { NLQ_ETA_CONST = 0, NLQ_ETA_GAUSS = 1 };
+enum { NLQ_FORM_SYM4 = 0, NLQ_FORM_PAPER2 = 1 };
+enum { NLQ_FP64_PLAIN = 0, NLQ_FP32_MIXED = 1 };
+
+typedef struct nlq_ctx nlq_ctx;
+typedef struct nlq_mesh nlq_mesh;
+typedef struct nlq_system nlq_system;
+
+/* Method parameters.
+ *  dim        2 (P1 triangles) or 3 (P1 tetrahedra); must match the mesh.
+ *  kernel     NLQ_ETA_CONST: eta = 1.  NLQ_ETA_GAUSS: eta = exp(-|x-y|^2/delta^2).
+ *  delta, eps horizon and mollifier half-width, 0 < eps < delta (Section 3).
+ *  scale      > 0: use as the kernel constant C.  0: C_{delta,eps} of Section 6
+ *             (eta = 1; kappa = 1), or for the Gaussian the constant c with
+ *             c omega_N int rho^{N+1} eta mu = N, i.e. L_eps u = Laplacian u for
+ *             quadratic u (the same normalisation).
+ *  lmin, lmax Algorithm 1 levels, 1 <= lmin <= lmax <= 8 (2D) / 6 (3D).
+ *  form       NLQ_FORM_SYM4: four-term integrand of eq. (Aij-support2) per
+ *             ordered pair (exactly symmetric, zero row sums).  NLQ_FORM_PAPER2:
+ *             2 A21 + 2 A22 of the Corollary in Section 5 (rows of the inner
+ *             test function; zero row sums, symmetric only in the limit).
+ *  precision  NLQ_FP64_PLAIN: FP64 kernel evaluation and contraction.
+ *             NLQ_FP32_MIXED: FP32 evaluation at anchor-relative coordinates,
+ *             FP32 matrix-core contraction per 64-point batch, FP64 per-pair
+ *             blocks and FP64 global accumulation.
+ *  deterministic  reserved, must be 0.
+ */
+typedef struct {
+    int32_t dim;
+    int32_t kernel;
+    double delta, eps;
+    double scale;
+    int32_t lmin, lmax;
+    int32_t form;
+    int32_t precision;
+    int32_t deterministic;
+} nlq_params;
+
+/* Counts and stage timings of one assembly (seconds from HIP events). */
+typedef struct {
+    int64_t n_pairs;          /* ordered element pairs (l, m), m in J_l */
+    int64_t n_leaf[9];        /* Integration(s, m) calls per level 1..8 (index = level) */
+    int64_t n_evals;          /* kernel evaluations gamma_eps(x_a, y_b) */
+    int64_t nnz;
+    double t_tables, t_pairs, t_pattern, t_integrate, t_total;
+} nlq_assemble_info;
+
+typedef struct {
+    int32_t iterations;
+    int32_t converged;
+    double rel_residual;      /* ||r||_2 / ||F~||_2 at exit */
+    double seconds;
+} nlq_solve_info;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * memory the context may hold (0 = 90% of the device's free memory). */
+nlq_status nlq_ctx_create(int32_t device, uint64_t hbm_budget_bytes, nlq_ctx **out);
+/* Run all later device work of this context on `hip_stream` (a hipStream_t,
+ * e.g. torch's current stream); NULL restores the context's own stream. */
+nlq_status nlq_ctx_set_stream(nlq_ctx *ctx, void *hip_stream);
+/* Bytes of device memory currently held by the context. */
+nlq_status nlq_ctx_memory(const nlq_ctx *ctx, uint64_t *used, uint64_t *budget);
+nlq_status nlq_ctx_destroy(nlq_ctx *ctx);
+
+/* ---- mesh --------------------------------------------------------------- */
+
+/* Copy a P1 simplicial mesh of Omega u Gamma to the device (Section 4: a
+ * triangulation of Omega u Gamma into N_L elements).
+ *  coords       host [n_nodes][dim] double
+ *  conn         host [n_elems][dim+1] int32, node ids in [0, n_nodes)
+ *  constrained  host [n_nodes] uint8, 1 = node in Gamma (value fixed by g)
+ * Errors: EINVAL for dim not in {2,3}, ids out of range, zero-measure elements. */
+nlq_status nlq_mesh_create(nlq_ctx *ctx, int32_t dim, int64_t n_nodes, const double *coords,
+                           int64_t n_elems, const int32_t *conn, const uint8_t *constrained,
+                           nlq_mesh **out);
+/* Kuhn mesh of [0,1]^dim with n cells per direction built on the device:
+ * x = i/n, node id = i0 + (n+1)(i1 + (n+1) i2), element id = dim!*cell + p with
+ * p the lexicographic index of the permutation of the Kuhn path; Gamma = nodes
+ * with some index <= k_gamma or >= n - k_gamma. */
+nlq_status nlq_mesh_box(nlq_ctx *ctx, int32_t dim, int32_t n, int32_t k_gamma, nlq_mesh **out);
+nlq_status nlq_mesh_info(const nlq_mesh *mesh, int32_t *dim, int64_t *n_nodes, int64_t *n_elems,
+                         int64_t *n_free);
+/* Host copies of a mesh (coords [n][dim], conn [e][dim+1], constrained [n]). */
+nlq_status nlq_mesh_copy(const nlq_mesh *mesh, double *coords, int32_t *conn, uint8_t *constrained);
+nlq_status nlq_mesh_destroy(nlq_mesh *mesh);
+
+/* ---- assembly ----------------------------------------------------------- */
+
+/* Assemble the stiffness matrix of all nodes (constrained rows included, needed
+ * for the lifting): element tables, pair list J_l, structural CSR pattern,
+ * Algorithm 1 per pair, per-pair blocks, FP64 accumulation.  The system keeps a
+ * reference to the mesh, which must outlive it.
+ * Errors: EINVAL for inconsistent params, ENOMEM when the estimated footprint
+ * exceeds the budget. */
+nlq_status nlq_assemble(nlq_ctx *ctx, const nlq_mesh *mesh, const nlq_params *params,
+                        nlq_system **out);
+nlq_status nlq_assemble_info_get(const nlq_system *sys, nlq_assemble_info *info);
+/* Re-run only the integration step (pair list and pattern kept) -- the hot loop;
+ * values are recomputed from zero. */
+nlq_status nlq_reassemble(nlq_system *sys);
+
+/* Load vector and lifting (Section 2, eqs. (A-F), (weak-homo)):
+ * F_i = int_Omega f_h phi_i with f_h the P1 interpolant of f_nodal, and
+ * F~ = F - A g~ on free rows, with g~ = g on Gamma and 0 elsewhere (the lifting
+ * enters with a minus sign).  f_nodal, g_nodal: host [n_nodes]. */
+nlq_status nlq_set_data(nlq_system *sys, const double *f_nodal, const double *g_nodal);
+/* Jacobi-preconditioned CG on A_{Omega,Omega} w = F~_Omega (FP64 SpMV, dots and
+ * residuals); u = w on free nodes, g on Gamma.  u_out: host [n_nodes] or NULL.
+ * Returns ENOCONV (u = last iterate) when maxit is reached. */
+nlq_status nlq_solve(nlq_system *sys, double rtol, int32_t maxit, double *u_out,
+                     nlq_solve_info *info);
+
+nlq_status nlq_info(const nlq_system *sys, int64_t *n_rows, int64_t *nnz, int64_t *n_pairs,
+                    int64_t *n_free);
+/* Host copies (caller-allocated): row_ptr [n_rows+1], col [nnz], val [nnz]. */
+nlq_status nlq_csr_copy(const nlq_system *sys, int64_t *row_ptr, int32_t *col, double *val);
+/* Borrowed device pointers, valid until nlq_system_destroy. */
+nlq_status nlq_csr_device(const nlq_system *sys, const int64_t **row_ptr, const int32_t **col,
+                          const double **val);
+/* Host copies of the pair list: offsets [n_elems+1], inner ids [n_pairs]. */
+nlq_status nlq_pairs_copy(const nlq_system *sys, int64_t *offsets, int32_t *m);
+/* Host copy of F~ [n_rows] (0 on Gamma rows). */
+nlq_status nlq_rhs_copy(const nlq_system *sys, double *f_tilde);
+/* Per-pair blocks of selected ordered pairs (l[k], m[k]), recomputed with the
+ * assembly kernels: out [n][2N+2][2N+2] in the extended index space
+ * [local nodes of l, local nodes of m] (the four-term form fills all four
+ * blocks, the two-term form the rows of m). */
+nlq_status nlq_pair_blocks(nlq_system *sys, int64_t n, const int32_t *l, const int32_t *m,
+                           double *out);
+nlq_status nlq_system_destroy(nlq_system *sys);
+
+/* ---- serving: continuous batching of assemble + solve requests ------------
+ * A scheduler thread admits queued requests while their estimated HBM
+ * footprint fits the context budget, keeps meshes resident (cache keyed by
+ * dim, n, k_gamma), interleaves the outer elements of every admitted request in
+ * shared persistent launches, and runs each request's CG as soon as its
+ * assembly completes.  Latency = completion time - submission time. */
+typedef struct {
+    int32_t dim, n, k_gamma;     /* box mesh (nlq_mesh_box) */
+    nlq_params params;
+    const double *f_nodal;       /* host [n_nodes], copied at submit */
+    const double *g_nodal;       /* host [n_nodes], copied at submit */
+    double rtol;
+    int32_t maxit;
+} nlq_request;
+
+typedef struct {
+    nlq_status status;
+    int64_t n_nodes, n_pairs, n_free;
+    const double *u;             /* host [n_nodes], library-owned until release */
+    int32_t cg_iterations;
+    double rel_residual;
+    double latency_s;            /* submit -> result ready */
+    double queue_s;              /* submit -> admitted */
+} nlq_result;
+
+nlq_status nlq_serve_start(nlq_ctx *ctx, int32_t max_active);
+nlq_status nlq_submit(nlq_ctx *ctx, const nlq_request *req, uint64_t *ticket);
+/* timeout_ms < 0: wait forever; 0: poll.  ENOTREADY when not finished. */
+nlq_status nlq_wait(nlq_ctx *ctx, uint64_t ticket, int32_t timeout_ms, nlq_result *out);
+nlq_status nlq_cancel(nlq_ctx *ctx, uint64_t ticket);
+nlq_status nlq_result_release(nlq_ctx *ctx, uint64_t ticket);
+nlq_status nlq_serve_stop(nlq_ctx *ctx);
+
+/* Thread-local message of the last failed call ("" if none). */
+const char *nlq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,555 @@
+// C-ABI of libnlq: argument checking, ownership, device memory accounting and
+// the sequencing of the assembly / solve stages.  Every entry point catches
+// errors and returns an nlq_status; nothing aborts.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+
+#include "nlq_internal.hpp"
+
+namespace nlq {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
+[[noreturn]] void fail(nlq_status st, const std::string &msg) { throw Error{st, msg}; }
+
+void DevBuf::alloc(Ctx *ctx, size_t bytes)
+{
+    release();
+    if (bytes == 0) bytes = 8;
+    const uint64_t now = ctx->used.fetch_add(bytes) + bytes;
+    if (now > ctx->budget) {
+        ctx->used.fetch_sub(bytes);
+        fail(NLQ_ENOMEM, "device memory budget exceeded (" + std::to_string(now) + " > " +
+                             std::to_string(ctx->budget) + " bytes)");
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        ctx->used.fetch_sub(bytes);
+        fail(NLQ_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    p_ = p;
+    bytes_ = bytes;
+    ctx_ = ctx;
+}
+
+void DevBuf::release()
+{
+    if (p_) {
+        (void)hipFree(p_);
+        ctx_->used.fetch_sub(bytes_);
+    }
+    p_ = nullptr;
+    bytes_ = 0;
+}
+
+namespace {
+
+template <class F> nlq_status guard(F &&f)
+{
+    try {
+        f();
+        g_last_error.clear();
+        return NLQ_OK;
+    } catch (const Error &e) {
+        g_last_error = e.msg;
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return NLQ_ENOMEM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return NLQ_EINVAL;
+    }
+}
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void check_params(const Mesh &m, const nlq_params &p)
+{
+    if (p.dim != m.dim) fail(NLQ_EINVAL, "params.dim does not match the mesh");
+    if (!(p.delta > 0.0) || !(p.eps > 0.0) || !(p.eps < p.delta))
+        fail(NLQ_EINVAL, "need 0 < eps < delta");
+    if (p.lmin < 1 || p.lmax < p.lmin) fail(NLQ_EINVAL, "need 1 <= lmin <= lmax");
+    if (p.lmax > (m.dim == 2 ? 8 : 6)) fail(NLQ_EINVAL, "lmax too large (max 8 in 2D, 6 in 3D)");
+    if (p.kernel != NLQ_ETA_CONST && p.kernel != NLQ_ETA_GAUSS) fail(NLQ_EINVAL, "unknown kernel");
+    if (p.form != NLQ_FORM_SYM4 && p.form != NLQ_FORM_PAPER2) fail(NLQ_EINVAL, "unknown form");
+    if (p.precision != NLQ_FP64_PLAIN && p.precision != NLQ_FP32_MIXED)
+        fail(NLQ_EINVAL, "unknown precision");
+    if (p.deterministic != 0) fail(NLQ_EINVAL, "deterministic mode is reserved");
+    if (p.scale < 0.0) fail(NLQ_EINVAL, "scale must be >= 0");
+}
+
+void mesh_stats(Mesh &m)
+{
+    const int dim = m.dim, nv = dim + 1;
+    for (int k = 0; k < 3; ++k) {
+        m.gmin[k] = 0.0;
+        m.gmax[k] = 0.0;
+        m.ext_max[k] = 0.0;
+    }
+    for (int k = 0; k < dim; ++k) {
+        m.gmin[k] = INFINITY;
+        m.gmax[k] = -INFINITY;
+    }
+    for (int64_t n = 0; n < m.n_nodes; ++n)
+        for (int k = 0; k < dim; ++k) {
+            const double x = m.h_coords[n * dim + k];
+            if (!std::isfinite(x)) fail(NLQ_EINVAL, "non-finite coordinate");
+            m.gmin[k] = std::min(m.gmin[k], x);
+            m.gmax[k] = std::max(m.gmax[k], x);
+        }
+    for (int64_t e = 0; e < m.n_elems; ++e) {
+        double V[4][3];
+        for (int v = 0; v < nv; ++v) {
+            const int32_t id = m.h_conn[e * nv + v];
+            if (id < 0 || id >= m.n_nodes) fail(NLQ_EINVAL, "node id out of range in element " + std::to_string(e));
+            for (int k = 0; k < dim; ++k) V[v][k] = m.h_coords[static_cast<int64_t>(id) * dim + k];
+        }
+        for (int k = 0; k < dim; ++k) {
+            double a = V[0][k], b = V[0][k];
+            for (int v = 1; v < nv; ++v) {
+                a = std::min(a, V[v][k]);
+                b = std::max(b, V[v][k]);
+            }
+            m.ext_max[k] = std::max(m.ext_max[k], b - a);
+        }
+        double det;
+        if (dim == 2) {
+            det = (V[1][0] - V[0][0]) * (V[2][1] - V[0][1]) - (V[1][1] - V[0][1]) * (V[2][0] - V[0][0]);
+        } else {
+            double a[3], b[3], c[3];
+            for (int k = 0; k < 3; ++k) {
+                a[k] = V[1][k] - V[0][k];
+                b[k] = V[2][k] - V[0][k];
+                c[k] = V[3][k] - V[0][k];
+            }
+            det = a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) +
+                  a[2] * (b[0] * c[1] - b[1] * c[0]);
+        }
+        if (!(std::fabs(det) > 0.0)) fail(NLQ_EINVAL, "element " + std::to_string(e) + " has zero measure");
+    }
+    m.n_free = 0;
+    for (int64_t n = 0; n < m.n_nodes; ++n) m.n_free += m.h_constrained[n] ? 0 : 1;
+}
+
+void upload_mesh(Mesh &m, hipStream_t st)
+{
+    const int nv = m.dim + 1;
+    m.coords.alloc(m.ctx, sizeof(double) * m.n_nodes * m.dim);
+    m.conn.alloc(m.ctx, sizeof(int32_t) * m.n_elems * nv);
+    m.constrained.alloc(m.ctx, m.n_nodes);
+    NLQ_HIP(hipMemcpyAsync(m.coords.as<void>(), m.h_coords.data(), sizeof(double) * m.n_nodes * m.dim,
+                           hipMemcpyHostToDevice, st));
+    NLQ_HIP(hipMemcpyAsync(m.conn.as<void>(), m.h_conn.data(), sizeof(int32_t) * m.n_elems * nv,
+                           hipMemcpyHostToDevice, st));
+    NLQ_HIP(hipMemcpyAsync(m.constrained.as<void>(), m.h_constrained.data(), m.n_nodes,
+                           hipMemcpyHostToDevice, st));
+    NLQ_HIP(hipStreamSynchronize(st));
+}
+
+void run_integrate(System &s, hipStream_t st)
+{
+    const double t0 = now_s();
+    launch_integrate(s, st, 0, nullptr, nullptr, nullptr);
+    AsmCounters c{};
+    NLQ_HIP(hipMemcpyAsync(&c, s.counters.as<void>(), sizeof(AsmCounters), hipMemcpyDeviceToHost, st));
+    NLQ_HIP(hipStreamSynchronize(st));
+    s.info.t_integrate = now_s() - t0;
+    const int nq = s.mesh->dim == 2 ? 7 : 15;
+    int64_t leaves = 0;
+    for (int q = 0; q < 9; ++q) {
+        s.info.n_leaf[q] = (q >= 1 && q <= 8) ? static_cast<int64_t>(c.leaf[q]) : 0;
+        leaves += s.info.n_leaf[q];
+    }
+    s.info.n_evals = leaves * nq * nq;
+    if (static_cast<int64_t>(c.pairs_done) != s.n_pairs)
+        fail(NLQ_EDEVICE, "integration did not visit every pair");
+}
+
+}  // namespace
+
+}  // namespace nlq
+
+using namespace nlq;
+
+extern "C" {
+
+const char *nlq_last_error(void) { return g_last_error.c_str(); }
+
+nlq_status nlq_ctx_create(int32_t device, uint64_t hbm_budget_bytes, nlq_ctx **out)
+{
+    return guard([&] {
+        if (!out) fail(NLQ_EINVAL, "out is NULL");
+        int ndev = 0;
+        NLQ_HIP(hipGetDeviceCount(&ndev));
+        if (device < 0 || device >= ndev) fail(NLQ_EINVAL, "no such device");
+        NLQ_HIP(hipSetDevice(device));
+        auto c = std::make_unique<nlq_ctx>();
+        c->impl.device = device;
+        hipDeviceProp_t prop;
+        NLQ_HIP(hipGetDeviceProperties(&prop, device));
+        c->impl.n_cu = prop.multiProcessorCount;
+        size_t fr = 0, tot = 0;
+        NLQ_HIP(hipMemGetInfo(&fr, &tot));
+        c->impl.budget = hbm_budget_bytes ? hbm_budget_bytes : static_cast<uint64_t>(0.9 * fr);
+        NLQ_HIP(hipStreamCreateWithFlags(&c->impl.own_stream, hipStreamNonBlocking));
+        c->impl.stream = c->impl.own_stream;
+        *out = c.release();
+    });
+}
+
+nlq_status nlq_ctx_set_stream(nlq_ctx *ctx, void *hip_stream)
+{
+    return guard([&] {
+        if (!ctx) fail(NLQ_EINVAL, "ctx is NULL");
+        ctx->impl.stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->impl.own_stream;
+    });
+}
+
+nlq_status nlq_ctx_memory(const nlq_ctx *ctx, uint64_t *used, uint64_t *budget)
+{
+    return guard([&] {
+        if (!ctx) fail(NLQ_EINVAL, "ctx is NULL");
+        if (used) *used = ctx->impl.used.load();
+        if (budget) *budget = ctx->impl.budget;
+    });
+}
+
+nlq_status nlq_serve_stop(nlq_ctx *ctx);
+
+nlq_status nlq_ctx_destroy(nlq_ctx *ctx)
+{
+    return guard([&] {
+        if (!ctx) return;
+        nlq_serve_stop(ctx);
+        (void)hipSetDevice(ctx->impl.device);
+        (void)hipStreamSynchronize(ctx->impl.stream);
+        ctx->impl.tables.clear();
+        (void)hipStreamDestroy(ctx->impl.own_stream);
+        delete ctx;
+    });
+}
+
+nlq_status nlq_mesh_create(nlq_ctx *ctx, int32_t dim, int64_t n_nodes, const double *coords,
+                           int64_t n_elems, const int32_t *conn, const uint8_t *constrained,
+                           nlq_mesh **out)
+{
+    return guard([&] {
+        if (!ctx || !out || !coords || !conn || !constrained) fail(NLQ_EINVAL, "NULL argument");
+        if (dim != 2 && dim != 3) fail(NLQ_EINVAL, "dim must be 2 or 3");
+        if (n_nodes < dim + 1 || n_elems < 1) fail(NLQ_EINVAL, "empty mesh");
+        if (n_nodes > INT32_MAX || n_elems > INT32_MAX) fail(NLQ_EINVAL, "mesh too large for int32 ids");
+        NLQ_HIP(hipSetDevice(ctx->impl.device));
+        auto m = std::make_unique<nlq_mesh>();
+        Mesh &M = m->impl;
+        M.ctx = &ctx->impl;
+        M.dim = dim;
+        M.n_nodes = n_nodes;
+        M.n_elems = n_elems;
+        M.h_coords.assign(coords, coords + n_nodes * dim);
+        M.h_conn.assign(conn, conn + n_elems * (dim + 1));
+        M.h_constrained.assign(constrained, constrained + n_nodes);
+        for (auto &c : M.h_constrained) c = c ? 1 : 0;
+        mesh_stats(M);
+        upload_mesh(M, ctx->impl.stream);
+        *out = m.release();
+    });
+}
+
+nlq_status nlq_mesh_box(nlq_ctx *ctx, int32_t dim, int32_t n, int32_t k_gamma, nlq_mesh **out)
+{
+    return guard([&] {
+        if (!ctx || !out) fail(NLQ_EINVAL, "NULL argument");
+        if (dim != 2 && dim != 3) fail(NLQ_EINVAL, "dim must be 2 or 3");
+        if (n < 1 || k_gamma < 0) fail(NLQ_EINVAL, "bad box size");
+        int64_t nn = 1, ne = 1;
+        for (int k = 0; k < dim; ++k) {
+            nn *= (n + 1);
+            ne *= n;
+        }
+        ne *= (dim == 2 ? 2 : 6);
+        if (nn > INT32_MAX || ne > INT32_MAX) fail(NLQ_EINVAL, "mesh too large for int32 ids");
+        NLQ_HIP(hipSetDevice(ctx->impl.device));
+        auto m = std::make_unique<nlq_mesh>();
+        Mesh &M = m->impl;
+        M.ctx = &ctx->impl;
+        M.dim = dim;
+        M.n_nodes = nn;
+        M.n_elems = ne;
+        M.coords.alloc(M.ctx, sizeof(double) * nn * dim);
+        M.conn.alloc(M.ctx, sizeof(int32_t) * ne * (dim + 1));
+        M.constrained.alloc(M.ctx, nn);
+        hipStream_t st = ctx->impl.stream;
+        launch_box_mesh(dim, n, k_gamma, M.coords.as<double>(), M.conn.as<int32_t>(),
+                        M.constrained.as<uint8_t>(), st);
+        M.h_coords.resize(nn * dim);
+        M.h_conn.resize(ne * (dim + 1));
+        M.h_constrained.resize(nn);
+        NLQ_HIP(hipMemcpyAsync(M.h_coords.data(), M.coords.as<void>(), sizeof(double) * nn * dim,
+                               hipMemcpyDeviceToHost, st));
+        NLQ_HIP(hipMemcpyAsync(M.h_conn.data(), M.conn.as<void>(), sizeof(int32_t) * ne * (dim + 1),
+                               hipMemcpyDeviceToHost, st));
+        NLQ_HIP(hipMemcpyAsync(M.h_constrained.data(), M.constrained.as<void>(), nn,
+                               hipMemcpyDeviceToHost, st));
+        NLQ_HIP(hipStreamSynchronize(st));
+        for (int k = 0; k < 3; ++k) {
+            M.gmin[k] = 0.0;
+            M.gmax[k] = k < dim ? 1.0 : 0.0;
+            M.ext_max[k] = k < dim ? 1.0 / n : 0.0;
+        }
+        M.n_free = 0;
+        for (int64_t q = 0; q < nn; ++q) M.n_free += M.h_constrained[q] ? 0 : 1;
+        *out = m.release();
+    });
+}
+
+nlq_status nlq_mesh_info(const nlq_mesh *mesh, int32_t *dim, int64_t *n_nodes, int64_t *n_elems,
+                         int64_t *n_free)
+{
+    return guard([&] {
+        if (!mesh) fail(NLQ_EINVAL, "mesh is NULL");
+        if (dim) *dim = mesh->impl.dim;
+        if (n_nodes) *n_nodes = mesh->impl.n_nodes;
+        if (n_elems) *n_elems = mesh->impl.n_elems;
+        if (n_free) *n_free = mesh->impl.n_free;
+    });
+}
+
+nlq_status nlq_mesh_copy(const nlq_mesh *mesh, double *coords, int32_t *conn, uint8_t *constrained)
+{
+    return guard([&] {
+        if (!mesh) fail(NLQ_EINVAL, "mesh is NULL");
+        const Mesh &M = mesh->impl;
+        if (coords) std::copy(M.h_coords.begin(), M.h_coords.end(), coords);
+        if (conn) std::copy(M.h_conn.begin(), M.h_conn.end(), conn);
+        if (constrained) std::copy(M.h_constrained.begin(), M.h_constrained.end(), constrained);
+    });
+}
+
+nlq_status nlq_mesh_destroy(nlq_mesh *mesh)
+{
+    return guard([&] {
+        if (!mesh) return;
+        (void)hipSetDevice(mesh->impl.ctx->device);
+        delete mesh;
+    });
+}
+
+nlq_status nlq_assemble(nlq_ctx *ctx, const nlq_mesh *mesh, const nlq_params *params,
+                        nlq_system **out)
+{
+    return guard([&] {
+        if (!ctx || !mesh || !params || !out) fail(NLQ_EINVAL, "NULL argument");
+        if (mesh->impl.ctx != &ctx->impl) fail(NLQ_EINVAL, "mesh belongs to another context");
+        check_params(mesh->impl, *params);
+        NLQ_HIP(hipSetDevice(ctx->impl.device));
+        auto sys = std::make_unique<nlq_system>();
+        System &s = sys->impl;
+        s.ctx = &ctx->impl;
+        s.mesh = &mesh->impl;
+        s.p = *params;
+        s.C = params->scale > 0.0 ? params->scale
+                                  : kernel_constant(params->dim, params->kernel, params->delta, params->eps);
+        hipStream_t st = ctx->impl.stream;
+        (void)ctx->impl.get_tables(s.mesh->dim, s.p.lmax);
+        s.counters.alloc(s.ctx, sizeof(AsmCounters));
+        s.l_counter.alloc(s.ctx, sizeof(unsigned int));
+        NLQ_HIP(hipStreamSynchronize(st));
+        const double t0 = now_s();
+        launch_elem_tables(s, st);
+        NLQ_HIP(hipStreamSynchronize(st));
+        const double t1 = now_s();
+        build_pairs(s, st);
+        const double t2 = now_s();
+        build_pattern(s, st);
+        s.val.alloc(s.ctx, sizeof(double) * std::max<int64_t>(s.nnz, 1));
+        NLQ_HIP(hipStreamSynchronize(st));
+        const double t3 = now_s();
+        run_integrate(s, st);
+        const double t4 = now_s();
+        s.info.n_pairs = s.n_pairs;
+        s.info.nnz = s.nnz;
+        s.info.t_tables = t1 - t0;
+        s.info.t_pairs = t2 - t1;
+        s.info.t_pattern = t3 - t2;
+        s.info.t_total = t4 - t0;
+        *out = sys.release();
+    });
+}
+
+nlq_status nlq_assemble_info_get(const nlq_system *sys, nlq_assemble_info *info)
+{
+    return guard([&] {
+        if (!sys || !info) fail(NLQ_EINVAL, "NULL argument");
+        *info = sys->impl.info;
+    });
+}
+
+nlq_status nlq_reassemble(nlq_system *sys)
+{
+    return guard([&] {
+        if (!sys) fail(NLQ_EINVAL, "sys is NULL");
+        NLQ_HIP(hipSetDevice(sys->impl.ctx->device));
+        run_integrate(sys->impl, sys->impl.ctx->stream);
+        sys->impl.has_rhs = false;
+    });
+}
+
+nlq_status nlq_set_data(nlq_system *sys, const double *f_nodal, const double *g_nodal)
+{
+    return guard([&] {
+        if (!sys || !f_nodal || !g_nodal) fail(NLQ_EINVAL, "NULL argument");
+        System &s = sys->impl;
+        NLQ_HIP(hipSetDevice(s.ctx->device));
+        const int64_t n = s.mesh->n_nodes;
+        hipStream_t st = s.ctx->stream;
+        DevBuf f(s.ctx, sizeof(double) * n);
+        if (s.g.empty()) s.g.alloc(s.ctx, sizeof(double) * n);
+        NLQ_HIP(hipMemcpyAsync(f.as<void>(), f_nodal, sizeof(double) * n, hipMemcpyHostToDevice, st));
+        NLQ_HIP(hipMemcpyAsync(s.g.as<void>(), g_nodal, sizeof(double) * n, hipMemcpyHostToDevice, st));
+        launch_load_lift(s, st, f.as<double>(), s.g.as<double>());
+        NLQ_HIP(hipStreamSynchronize(st));
+        s.has_rhs = true;
+    });
+}
+
+nlq_status nlq_solve(nlq_system *sys, double rtol, int32_t maxit, double *u_out, nlq_solve_info *info)
+{
+    nlq_status conv = NLQ_OK;
+    nlq_status st = guard([&] {
+        if (!sys) fail(NLQ_EINVAL, "sys is NULL");
+        System &s = sys->impl;
+        if (!s.has_rhs) fail(NLQ_EINVAL, "nlq_set_data must be called before nlq_solve");
+        if (!(rtol > 0.0) || maxit < 1) fail(NLQ_EINVAL, "need rtol > 0 and maxit >= 1");
+        NLQ_HIP(hipSetDevice(s.ctx->device));
+        const double t0 = now_s();
+        double relres = 0.0;
+        int converged = 0;
+        const int it = cg_solve(s, s.ctx->stream, rtol, maxit, &relres, &converged);
+        if (u_out)
+            NLQ_HIP(hipMemcpy(u_out, s.u.as<void>(), sizeof(double) * s.mesh->n_nodes,
+                              hipMemcpyDeviceToHost));
+        if (info) {
+            info->iterations = it;
+            info->converged = converged;
+            info->rel_residual = relres;
+            info->seconds = now_s() - t0;
+        }
+        if (!converged) conv = NLQ_ENOCONV;
+    });
+    if (st == NLQ_OK && conv != NLQ_OK) {
+        set_last_error("CG did not reach the tolerance");
+        return conv;
+    }
+    return st;
+}
+
+nlq_status nlq_info(const nlq_system *sys, int64_t *n_rows, int64_t *nnz, int64_t *n_pairs,
+                    int64_t *n_free)
+{
+    return guard([&] {
+        if (!sys) fail(NLQ_EINVAL, "sys is NULL");
+        if (n_rows) *n_rows = sys->impl.mesh->n_nodes;
+        if (nnz) *nnz = sys->impl.nnz;
+        if (n_pairs) *n_pairs = sys->impl.n_pairs;
+        if (n_free) *n_free = sys->impl.mesh->n_free;
+    });
+}
+
+nlq_status nlq_csr_copy(const nlq_system *sys, int64_t *row_ptr, int32_t *col, double *val)
+{
+    return guard([&] {
+        if (!sys) fail(NLQ_EINVAL, "sys is NULL");
+        const System &s = sys->impl;
+        NLQ_HIP(hipSetDevice(s.ctx->device));
+        NLQ_HIP(hipStreamSynchronize(s.ctx->stream));
+        const int64_t n = s.mesh->n_nodes;
+        if (row_ptr)
+            NLQ_HIP(hipMemcpy(row_ptr, s.row_ptr.as<void>(), sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+        if (col) NLQ_HIP(hipMemcpy(col, s.col.as<void>(), sizeof(int32_t) * s.nnz, hipMemcpyDeviceToHost));
+        if (val) NLQ_HIP(hipMemcpy(val, s.val.as<void>(), sizeof(double) * s.nnz, hipMemcpyDeviceToHost));
+    });
+}
+
+nlq_status nlq_csr_device(const nlq_system *sys, const int64_t **row_ptr, const int32_t **col,
+                          const double **val)
+{
+    return guard([&] {
+        if (!sys) fail(NLQ_EINVAL, "sys is NULL");
+        if (row_ptr) *row_ptr = sys->impl.row_ptr.as<int64_t>();
+        if (col) *col = sys->impl.col.as<int32_t>();
+        if (val) *val = sys->impl.val.as<double>();
+    });
+}
+
+nlq_status nlq_pairs_copy(const nlq_system *sys, int64_t *offsets, int32_t *m)
+{
+    return guard([&] {
+        if (!sys) fail(NLQ_EINVAL, "sys is NULL");
+        const System &s = sys->impl;
+        NLQ_HIP(hipSetDevice(s.ctx->device));
+        NLQ_HIP(hipStreamSynchronize(s.ctx->stream));
+        if (offsets)
+            NLQ_HIP(hipMemcpy(offsets, s.pair_off.as<void>(), sizeof(int64_t) * (s.mesh->n_elems + 1),
+                              hipMemcpyDeviceToHost));
+        if (m) NLQ_HIP(hipMemcpy(m, s.pair_m.as<void>(), sizeof(int32_t) * s.n_pairs, hipMemcpyDeviceToHost));
+    });
+}
+
+nlq_status nlq_rhs_copy(const nlq_system *sys, double *f_tilde)
+{
+    return guard([&] {
+        if (!sys || !f_tilde) fail(NLQ_EINVAL, "NULL argument");
+        const System &s = sys->impl;
+        if (!s.has_rhs) fail(NLQ_EINVAL, "nlq_set_data has not been called");
+        NLQ_HIP(hipSetDevice(s.ctx->device));
+        NLQ_HIP(hipStreamSynchronize(s.ctx->stream));
+        NLQ_HIP(hipMemcpy(f_tilde, s.Ft.as<void>(), sizeof(double) * s.mesh->n_nodes, hipMemcpyDeviceToHost));
+    });
+}
+
+nlq_status nlq_pair_blocks(nlq_system *sys, int64_t n, const int32_t *l, const int32_t *m, double *out)
+{
+    return guard([&] {
+        if (!sys || (n > 0 && (!l || !m || !out))) fail(NLQ_EINVAL, "NULL argument");
+        if (n <= 0) return;
+        System &s = sys->impl;
+        const int64_t ne = s.mesh->n_elems;
+        for (int64_t k = 0; k < n; ++k)
+            if (l[k] < 0 || l[k] >= ne || m[k] < 0 || m[k] >= ne) fail(NLQ_EINVAL, "element id out of range");
+        if (n > (1ll << 30)) fail(NLQ_EINVAL, "too many pairs");
+        NLQ_HIP(hipSetDevice(s.ctx->device));
+        hipStream_t st = s.ctx->stream;
+        const int nv = s.mesh->dim + 1;
+        const size_t blk = static_cast<size_t>(4 * nv * nv);
+        DevBuf dl(s.ctx, sizeof(int32_t) * n), dm(s.ctx, sizeof(int32_t) * n),
+            dout(s.ctx, sizeof(double) * n * blk);
+        NLQ_HIP(hipMemcpyAsync(dl.as<void>(), l, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+        NLQ_HIP(hipMemcpyAsync(dm.as<void>(), m, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+        launch_integrate(s, st, n, dl.as<int32_t>(), dm.as<int32_t>(), dout.as<double>());
+        NLQ_HIP(hipMemcpyAsync(out, dout.as<void>(), sizeof(double) * n * blk, hipMemcpyDeviceToHost, st));
+        NLQ_HIP(hipStreamSynchronize(st));
+    });
+}
+
+nlq_status nlq_system_destroy(nlq_system *sys)
+{
+    return guard([&] {
+        if (!sys) return;
+        (void)hipSetDevice(sys->impl.ctx->device);
+        (void)hipStreamSynchronize(sys->impl.ctx->stream);
+        delete sys;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// Device helpers shared by the library's kernels (wave64, gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace nlq {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return static_cast<int>(__lane_id()); }
+
+// number of set bits of `mask` below this lane
+__device__ __forceinline__ int lanes_below(unsigned long long mask)
+{
+    return __popcll(mask & ((1ull << lane_id()) - 1ull));
+}
+
+__device__ __forceinline__ unsigned long long wave_ballot(bool p) { return __ballot(p); }
+
+template <class T> __device__ __forceinline__ T wave_sum(T v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+template <class T> __device__ __forceinline__ T wave_max(T v)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        T w = __shfl_xor(v, o, kWave);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+template <class T> __device__ __forceinline__ T wave_min(T v)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        T w = __shfl_xor(v, o, kWave);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+// inclusive prefix sum across the wave
+template <class T> __device__ __forceinline__ T wave_incl_scan(T v)
+{
+    const int l = lane_id();
+    for (int o = 1; o < kWave; o <<= 1) {
+        T w = __shfl_up(v, o, kWave);
+        if (l >= o) v += w;
+    }
+    return v;
+}
+
+// Approximate bbox distances of Section 5.1 in FP64 with every operation
+// rounded as written (no contraction), so that the classification of Algorithm
+// 1 is reproducible bit for bit.
+//   aprx max = sqrt(sum_k max(d1_k^2, d2_k^2)),  aprx min = max_k max(0, d1_k, d2_k),
+//   d1 = x_min - y_max, d2 = y_min - x_max.
+template <int DIM>
+__device__ __forceinline__ double aprx_max_dist(const double *lo1, const double *hi1,
+                                                const double *lo2, const double *hi2)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        double d1 = __dsub_rn(lo1[k], hi2[k]);
+        double d2 = __dsub_rn(lo2[k], hi1[k]);
+        double a = __dmul_rn(d1, d1), b = __dmul_rn(d2, d2);
+        s = __dadd_rn(s, a > b ? a : b);
+    }
+    return __dsqrt_rn(s);
+}
+
+template <int DIM>
+__device__ __forceinline__ double aprx_min_dist(const double *lo1, const double *hi1,
+                                                const double *lo2, const double *hi2)
+{
+    double r = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        double d1 = __dsub_rn(lo1[k], hi2[k]);
+        double d2 = __dsub_rn(lo2[k], hi1[k]);
+        if (d1 > r) r = d1;
+        if (d2 > r) r = d2;
+    }
+    return r;
+}
+
+}  // namespace nlq

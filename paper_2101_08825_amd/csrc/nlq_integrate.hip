@@ -1,0 +1,812 @@
+// Hot path of the assembly: for every ordered pair (l, m) of the pair list,
+// Algorithm 1 (Section 5) refines the outer element l by midpoints, classifying
+// each sub-element s against the whole inner element m with the bbox distances
+// of Section 5.1; every settled (s, m) is integrated with the degree-5 rule on s
+// and on m, and the four-term integrand of eq. (Aij-support2) (or the two-term
+// form of the Corollary) is accumulated into the pair's blocks.
+//
+// Work decomposition (one GPU, persistent launch):
+//   * a workgroup of kWaves waves takes outer elements l from a global counter;
+//   * its waves take the pairs (l, m), m in J_l, from an LDS counter;
+//   * a wave walks the refinement tree of its pair level by level: lanes
+//     classify sub-elements in FP64 (every rounding as written, so the leaf set
+//     is reproducible bit for bit), wave ballots + prefix counts compact the
+//     integrate / refine lists in LDS;
+//   * leaves are integrated in batches of 64 outer points staged in LDS:
+//       plain  (FP64): each lane owns one inner point and a slice of the batch,
+//                      evaluates gamma_eps in FP64 and accumulates
+//                      H_ib = sum_a P_i(a) g_ab, Q_kb = sum_a P_k(a) g_ab in FP64;
+//       mixed  (FP32): anchor-relative FP32 coordinates, gamma_eps in FP32 and the
+//                      contraction H = P^T G on the matrix cores
+//                      (v_mfma_f32_16x16x4f32), flushed to FP64 every batch;
+//     with P_i(a) = w_a 2^{-N(lev-1)} lambda_i(x_a) (rows i < N+1) and
+//     P_k(a) = w_a 2^{-N(lev-1)} lambda_i lambda_j (k = off-diagonal pair i < j);
+//   * FP64 epilogue: S = C |E_l| |E_m|,
+//       B_lm[i][j] = -S sum_b H_ib w_b psi_j(y_b)
+//       B_mm[i][j] =  S sum_b w_b psi_i psi_j sum_i' H_i'b
+//       B_ll[i][j] =  S sum_b Q_(ij)b w_b  (i != j),
+//       B_ll[i][i] =  S sum_b H_ib w_b - sum_{j != i} B_ll[i][j]
+//     (partition of unity: lambda_i = sum_j lambda_i lambda_j), then FP64
+//     atomics into the CSR values; B_ll is summed per outer element in LDS.
+#include <cmath>
+#include <type_traits>
+
+#include "nlq_device.hpp"
+#include "nlq_internal.hpp"
+#include "nlq_refine.hpp"
+
+namespace nlq {
+
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kThreads = kWaves * kWave;
+constexpr int kLeafCap = 128;
+constexpr int kBatch = 64;
+
+template <int DIM> struct Shape {
+    static constexpr int NV = DIM + 1;
+    static constexpr int NQ = DIM == 2 ? 7 : 15;
+    static constexpr int NCH = 1 << DIM;
+    static constexpr int NOFF = NV * (NV - 1) / 2;
+    static constexpr int NR = NV + NOFF;
+};
+
+struct AsmArgs {
+    int64_t ne;
+    const int64_t *pair_off;
+    const int32_t *pair_m;
+    const double *vert;   // [nv*dim][ne]
+    const double *lo;     // [dim][ne]
+    const double *hi;
+    const double *meas;
+    const int32_t *conn;
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const int32_t *tmap;
+    const int32_t *elpos;
+    double *val;
+    const double *lam64;  // [sub][nq][nv]
+    const float *lam32;
+    const double *rule;   // [nq][nv] barycentric points, then [nq] weights
+    int64_t lvl_off[10];
+    double delta, eps, dme, dpe, dme2, dpe2, C;
+    float f_delta, f_inv_eps, f_delta_over_eps, f_dme2, f_dpe2, f_inv_delta2;
+    int kernel, lmin, lmax, form;
+    int capl;
+    unsigned int *counter;
+    AsmCounters *counters;
+    int64_t n_explicit;
+    const int32_t *ex_l;
+    const int32_t *ex_m;
+    double *ex_out;
+};
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class T> __device__ __forceinline__ T bcast0(T v) { return __shfl(v, 0, kWave); }
+
+// -------------------------------------------------------------- mollifier
+
+// xi of Section 3, eq. (mollifier), Horner form in r^2:
+// xi(r) = 1/2 + r (315 - 420 r^2 + 378 r^4 - 180 r^6 + 35 r^8) / 256,
+// evaluated at r = (delta - d) / eps (1 at the inner band edge, 0 at the outer).
+__device__ __forceinline__ double xi64(double r)
+{
+    const double s = r * r;
+    double p = 35.0 / 256.0;
+    p = fma(p, s, -180.0 / 256.0);
+    p = fma(p, s, 378.0 / 256.0);
+    p = fma(p, s, -420.0 / 256.0);
+    p = fma(p, s, 315.0 / 256.0);
+    return fma(p, r, 0.5);
+}
+
+__device__ __forceinline__ float xi32(float r)
+{
+    const float s = r * r;
+    float p = 35.0f / 256.0f;
+    p = fmaf(p, s, -180.0f / 256.0f);
+    p = fmaf(p, s, 378.0f / 256.0f);
+    p = fmaf(p, s, -420.0f / 256.0f);
+    p = fmaf(p, s, 315.0f / 256.0f);
+    return fmaf(p, r, 0.5f);
+}
+
+// gamma_eps / C at squared distance d2 (FP64): eta * mu
+__device__ __forceinline__ double kernel64(const AsmArgs &A, double d2)
+{
+    double mu;
+    if (d2 < A.dme2) {
+        mu = 1.0;
+    } else if (d2 > A.dpe2) {
+        mu = 0.0;
+    } else {
+        const double d = sqrt(d2);
+        mu = d < A.dme ? 1.0 : (d > A.dpe ? 0.0 : xi64((A.delta - d) / A.eps));
+    }
+    if (A.kernel == NLQ_ETA_GAUSS) mu *= exp(-d2 / (A.delta * A.delta));
+    return mu;
+}
+
+// -------------------------------------------------------------- geometry
+
+template <int DIM> struct Simplex {
+    double v[DIM + 1][DIM];
+};
+
+template <int DIM>
+__device__ __forceinline__ double pick(const Simplex<DIM> &S, int i, int k)
+{
+    double r = S.v[0][k];
+#pragma unroll
+    for (int q = 1; q <= DIM; ++q)
+        if (i == q) r = S.v[q][k];
+    return r;
+}
+
+// child `c` of S by the midpoint rule, (V_i + V_j) * 0.5 rounded as written
+template <int DIM>
+__device__ __forceinline__ Simplex<DIM> child_of(const Simplex<DIM> &S, int c)
+{
+    Simplex<DIM> out;
+#pragma unroll
+    for (int v = 0; v <= DIM; ++v) {
+        const unsigned char s = child_src(DIM, c, v);
+        const int i = s >> 4, j = s & 15;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const double a = pick(S, i, k), b = pick(S, j, k);
+            out.v[v][k] = (i == j) ? a : __dmul_rn(__dadd_rn(a, b), 0.5);
+        }
+    }
+    return out;
+}
+
+// 0 = drop, 1 = integrate now (J^int), 2 = refine (J^ref): Algorithm 1
+template <int DIM>
+__device__ __forceinline__ int classify(const AsmArgs &A, const Simplex<DIM> &root, int lev,
+                                        uint32_t local, const double *mlo, const double *mhi)
+{
+    constexpr int NCH = 1 << DIM;
+    Simplex<DIM> S = root;
+    for (int d = lev - 2; d >= 0; --d) {
+        const int c = (local >> (DIM * d)) & (NCH - 1);
+        S = child_of(S, c);
+    }
+    double slo[DIM], shi[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        double a = S.v[0][k], b = S.v[0][k];
+#pragma unroll
+        for (int v = 1; v <= DIM; ++v) {
+            a = S.v[v][k] < a ? S.v[v][k] : a;
+            b = S.v[v][k] > b ? S.v[v][k] : b;
+        }
+        slo[k] = a;
+        shi[k] = b;
+    }
+    if (aprx_max_dist<DIM>(slo, shi, mlo, mhi) < A.dme) return 1;
+    if (aprx_min_dist<DIM>(slo, shi, mlo, mhi) < A.dpe) return 2;
+    return 0;
+}
+
+// row of the off-diagonal product lambda_a lambda_c (a < c) among the P rows
+template <int NV> __device__ __forceinline__ int offrow(int a, int c)
+{
+    return NV + a * NV - (a * (a + 1)) / 2 + (c - a - 1);
+}
+
+// -------------------------------------------------------------- per-wave LDS
+
+template <int DIM, int PREC> struct WaveMem {
+    using S = Shape<DIM>;
+    // staging of one batch of outer points
+    static constexpr int kStageBytes =
+        PREC == 0 ? kBatch * (DIM + S::NR) * 8 : kBatch * (4 + 16) * 4;
+    static constexpr int kEpiBytes = (S::NR * 16 + (PREC == 1 ? 256 : 0)) * 8;
+    static constexpr int kWorkBytes = kStageBytes > kEpiBytes ? kStageBytes : kEpiBytes;
+    __host__ __device__ static int bytes(int capl)
+    {
+        return (kWorkBytes + kLeafCap * 4 + 2 * capl * 4 + 15) & ~15;
+    }
+};
+
+// -------------------------------------------------------------- integrators
+
+// FP64 plain: lane = (k, b): b = inner point (lane % NYP), k = batch slice
+template <int DIM> struct PlainAcc {
+    using S = Shape<DIM>;
+    static constexpr int NYP = DIM == 2 ? 8 : 16;
+    static constexpr int K = kWave / NYP;
+    double acc[S::NR];
+    double yh[DIM];   // inner point relative to the anchor
+    bool active;
+    __device__ void init(const double *y)
+    {
+#pragma unroll
+        for (int r = 0; r < S::NR; ++r) acc[r] = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) yh[k] = y[k];
+    }
+    // stage: lane t writes point t of the batch
+    __device__ static void stage(char *work, int t, bool valid, const double *xh, const double *P)
+    {
+        double *sx = reinterpret_cast<double *>(work);
+        double *sp = sx + kBatch * DIM;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) sx[t * DIM + k] = valid ? xh[k] : 0.0;
+#pragma unroll
+        for (int r = 0; r < S::NR; ++r) sp[t * S::NR + r] = valid ? P[r] : 0.0;
+    }
+    __device__ void run(const AsmArgs &A, const char *work, int npts)
+    {
+        const double *sx = reinterpret_cast<const double *>(work);
+        const double *sp = sx + kBatch * DIM;
+        const int k0 = lane_id() / NYP;
+        if (!active) return;
+        for (int p = k0; p < npts; p += K) {
+            double d2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                const double dx = sx[p * DIM + k] - yh[k];
+                d2 = fma(dx, dx, d2);
+            }
+            const double g = kernel64(A, d2);
+#pragma unroll
+            for (int r = 0; r < S::NR; ++r) acc[r] = fma(sp[p * S::NR + r], g, acc[r]);
+        }
+    }
+    // totals H/Q for inner point b in lanes with k == 0 -> out[r*16 + b]
+    __device__ void finish(double *out)
+    {
+#pragma unroll
+        for (int r = 0; r < S::NR; ++r) {
+            double v = acc[r];
+            for (int o = NYP; o < kWave; o <<= 1) v += __shfl_xor(v, o, kWave);
+            acc[r] = v;
+        }
+        const int b = lane_id() % NYP;
+        if (lane_id() < NYP && b < S::NQ) {
+#pragma unroll
+            for (int r = 0; r < S::NR; ++r) out[r * 16 + b] = acc[r];
+        }
+    }
+};
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// FP32 mixed: v_mfma_f32_16x16x4f32, A = P (rows x 4 points), B = G (4 points x
+// 16 inner points).  Operand layout: A[i][k] and B[k][j] live in lane i + 16k
+// (resp. j + 16k); D[i][j] in lane j + 16*(i/4), register i%4.
+//  3D: 4 points per step, rows 0..9 = P, columns 0..14 = inner points.
+//  2D: 8 points per step as two independent 8x8 diagonal blocks: lanes with
+//      column < 8 use point set 0, columns >= 8 set 1.
+template <int DIM> struct MixedAcc {
+    using S = Shape<DIM>;
+    static constexpr int PPS = DIM == 2 ? 8 : 4;   // points per MFMA step
+    double dacc[4];
+    float yh[3];
+    int n;       // column / row index of this lane in the 16x16 tile
+    int sub;     // sub-index: inner point (and P row) handled by this lane
+    int poff;    // point offset within a step
+    bool colv, rowv;
+    __device__ void init(const double *y)
+    {
+        const int l = lane_id();
+        n = l & 15;
+        const int k = l >> 4;
+        if (DIM == 2) {
+            sub = n & 7;
+            poff = 4 * (n >> 3) + k;
+        } else {
+            sub = n;
+            poff = k;
+        }
+        colv = sub < S::NQ;
+        rowv = sub < S::NR;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dacc[r] = 0.0;
+        yh[0] = static_cast<float>(y[0]);
+        yh[1] = static_cast<float>(y[1]);
+        yh[2] = DIM == 3 ? static_cast<float>(y[DIM - 1]) : 0.0f;
+    }
+    __device__ static void stage(char *work, int t, bool valid, const double *xh, const double *P)
+    {
+        float *sx = reinterpret_cast<float *>(work);
+        float *sp = sx + kBatch * 4;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sx[t * 4 + k] = (valid && k < DIM) ? static_cast<float>(xh[k < DIM ? k : 0]) : 0.0f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            sp[t * 16 + r] = (valid && r < S::NR) ? static_cast<float>(P[r < S::NR ? r : 0]) : 0.0f;
+    }
+    __device__ void run(const AsmArgs &A, const char *work, int npts)
+    {
+        const float *sx = reinterpret_cast<const float *>(work);
+        const float *sp = sx + kBatch * 4;
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const int steps = (npts + PPS - 1) / PPS;
+        for (int t = 0; t < steps; ++t) {
+            const int p = t * PPS + poff;   // < kBatch always
+            const float4 x = *reinterpret_cast<const float4 *>(sx + p * 4);
+            const float a = rowv ? sp[p * 16 + sub] : 0.0f;
+            const float dx = x.x - yh[0], dy = x.y - yh[1];
+            float d2 = fmaf(dx, dx, dy * dy);
+            if (DIM == 3) {
+                const float dz = x.z - yh[2];
+                d2 = fmaf(dz, dz, d2);
+            }
+            float g;
+            if (d2 < A.f_dme2) {
+                g = 1.0f;
+            } else if (d2 > A.f_dpe2) {
+                g = 0.0f;
+            } else {
+                const float d = __builtin_sqrtf(d2);
+                g = xi32(fmaf(-d, A.f_inv_eps, A.f_delta_over_eps));
+            }
+            if (A.kernel == NLQ_ETA_GAUSS) g *= __expf(-d2 * A.f_inv_delta2);
+            const float b = colv ? g : 0.0f;
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dacc[r] += static_cast<double>(acc[r]);
+    }
+    // D[i][j] (FP64) -> H/Q totals out[r*16 + b]
+    __device__ void finish(double *out, double *tile)
+    {
+        const int l = lane_id();
+        const int j = l & 15, ib = 4 * (l >> 4);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tile[(ib + r) * 16 + j] = dacc[r];
+        wave_sync();
+        for (int t = l; t < S::NR * 16; t += kWave) {
+            const int r = t >> 4, b = t & 15;
+            double v = 0.0;
+            if (DIM == 2) {
+                if (b < S::NQ) v = tile[r * 16 + b] + tile[(r + 8) * 16 + (b + 8)];
+            } else {
+                if (b < S::NQ) v = tile[r * 16 + b];
+            }
+            out[t] = v;
+        }
+    }
+};
+
+// -------------------------------------------------------------- one pair
+
+template <int DIM, int PREC>
+__device__ void process_pair(const AsmArgs &A, int64_t l, int32_t m, char *wmem,
+                             const double *s_rule, double *s_bll, bool explicit_mode,
+                             double *ex_block, unsigned long long *s_leaf)
+{
+    using S = Shape<DIM>;
+    constexpr int NV = S::NV, NQ = S::NQ, NCH = S::NCH, NR = S::NR, NOFF = S::NOFF;
+    const int lane = lane_id();
+    const int64_t ne = A.ne;
+    char *work = wmem;
+    uint32_t *leafbuf = reinterpret_cast<uint32_t *>(wmem + WaveMem<DIM, PREC>::kWorkBytes);
+    uint32_t *listA = leafbuf + kLeafCap;
+    uint32_t *listB = listA + A.capl;
+
+    // geometry of l (root simplex) and m
+    Simplex<DIM> root;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) root.v[v][k] = A.vert[(v * DIM + k) * ne + l];
+    double mlo[DIM], mhi[DIM], Vm[NV][DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        mlo[k] = A.lo[k * ne + m];
+        mhi[k] = A.hi[k * ne + m];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) Vm[v][k] = A.vert[(v * DIM + k) * ne + m];
+    const double meas_l = A.meas[l], meas_m = A.meas[m];
+    const double *bary = s_rule;
+    const double *wq = s_rule + NQ * NV;
+
+    // inner point of this lane, relative to the anchor v0(l)
+    int bsel;
+    if (PREC == 0) bsel = lane % PlainAcc<DIM>::NYP;
+    else bsel = DIM == 2 ? (lane & 7) : (lane & 15);
+    const int bq = bsel < NQ ? bsel : 0;
+    double y[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s = fma(bary[bq * NV + v], Vm[v][k], s);
+        y[k] = s - root.v[0][k];
+    }
+    double E[DIM][DIM];   // edges v_i - v_0 of l
+#pragma unroll
+    for (int i = 1; i <= DIM; ++i)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) E[i - 1][k] = root.v[i][k] - root.v[0][k];
+
+    typename std::conditional<PREC == 0, PlainAcc<DIM>, MixedAcc<DIM>>::type acc;
+    acc.init(y);
+    if constexpr (PREC == 0) acc.active = bsel < NQ;
+
+    // integrate the leaves in leafbuf[0..nleaf)
+    auto integrate = [&](int nleaf) {
+        const int npts_total = nleaf * NQ;
+        for (int p0 = 0; p0 < npts_total; p0 += kBatch) {
+            const int p = p0 + lane;
+            const bool valid = p < npts_total;
+            double xh[DIM], P[NR];
+            if (valid) {
+                const int q = p / NQ, a = p - q * NQ;
+                const uint32_t ent = leafbuf[q];
+                const int lev = static_cast<int>(ent >> 24);
+                const uint32_t local = ent & 0xFFFFFFu;
+                const int64_t sub = A.lvl_off[lev] + local;
+                const double *lam = A.lam64 + (sub * NQ + a) * NV;
+                double lm[NV];
+#pragma unroll
+                for (int i = 0; i < NV; ++i) lm[i] = lam[i];
+                const double wl = ldexp(wq[a], -DIM * (lev - 1));
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int i = 1; i <= DIM; ++i) s = fma(lm[i], E[i - 1][k], s);
+                    xh[k] = s;
+                }
+#pragma unroll
+                for (int i = 0; i < NV; ++i) P[i] = wl * lm[i];
+                int r = NV;
+#pragma unroll
+                for (int i = 0; i < NV; ++i)
+#pragma unroll
+                    for (int j = i + 1; j < NV; ++j) P[r++] = wl * lm[i] * lm[j];
+            } else {
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) xh[k] = 0.0;
+#pragma unroll
+                for (int r = 0; r < NR; ++r) P[r] = 0.0;
+            }
+            wave_sync();
+            decltype(acc)::stage(work, lane, valid, xh, P);
+            wave_sync();
+            const int cnt = npts_total - p0 < kBatch ? npts_total - p0 : kBatch;
+            acc.run(A, work, cnt);
+        }
+    };
+
+    // ---- Algorithm 1, level by level (per pair: J = {m}) -------------------
+    int nleaf = 0;
+    uint32_t *cur = listA, *nxt = listB;
+    int ncur = 1;
+    if (lane == 0) cur[0] = 0u;
+    wave_sync();
+    auto flush = [&]() {
+        if (nleaf > 0) {
+            integrate(nleaf);
+            nleaf = 0;
+        }
+    };
+    auto push_leaf = [&](bool take, uint32_t ent) {
+        const unsigned long long mask = wave_ballot(take);
+        const int c = __popcll(mask);
+        if (c == 0) return;
+        if (nleaf + c > kLeafCap) flush();
+        if (take) leafbuf[nleaf + lanes_below(mask)] = ent;
+        nleaf += c;
+        wave_sync();
+    };
+    for (int lev = 1;; ++lev) {
+        if (lev == A.lmax) {
+            // every node of this level is integrated (no classification at L_max)
+            for (int i0 = 0; i0 < ncur; i0 += kWave) {
+                const int i = i0 + lane;
+                const bool take = i < ncur;
+                const uint32_t ent = take ? ((static_cast<uint32_t>(lev) << 24) | cur[i]) : 0u;
+                push_leaf(take, ent);
+            }
+            if (lane == 0 && s_leaf) atomicAdd(&s_leaf[lev], static_cast<unsigned long long>(ncur));
+            flush();
+            break;
+        }
+        const bool last_split = (lev + 1 == A.lmax);
+        int nn = 0;   // refined nodes (last_split) or children (otherwise) in nxt
+        int nint = 0;
+        for (int i0 = 0; i0 < ncur; i0 += kWave) {
+            const int i = i0 + lane;
+            const bool valid = i < ncur;
+            const uint32_t local = valid ? cur[i] : 0u;
+            int cls = 0;
+            if (valid) cls = (lev < A.lmin) ? 2 : classify<DIM>(A, root, lev, local, mlo, mhi);
+            const unsigned long long mref = wave_ballot(cls == 2);
+            const int rank = lanes_below(mref);
+            if (cls == 2) {
+                if (last_split) {
+                    nxt[nn + rank] = local;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) nxt[(nn + rank) * NCH + c] = local * NCH + c;
+                }
+            }
+            nn += __popcll(mref);
+            const unsigned long long mint = wave_ballot(cls == 1);
+            nint += __popcll(mint);
+            push_leaf(cls == 1, (static_cast<uint32_t>(lev) << 24) | local);
+        }
+        if (lane == 0 && s_leaf && nint) atomicAdd(&s_leaf[lev], static_cast<unsigned long long>(nint));
+        flush();
+        wave_sync();
+        if (nn == 0) break;
+        if (last_split) {
+            // children of the refined nodes are the level-L_max leaves
+            const int nl = nn * NCH;
+            for (int i0 = 0; i0 < nl; i0 += kWave) {
+                const int i = i0 + lane;
+                const bool take = i < nl;
+                const uint32_t ent =
+                    take ? ((static_cast<uint32_t>(lev + 1) << 24) | (nxt[i / NCH] * NCH + (i % NCH))) : 0u;
+                push_leaf(take, ent);
+            }
+            if (lane == 0 && s_leaf) atomicAdd(&s_leaf[lev + 1], static_cast<unsigned long long>(nl));
+            flush();
+            break;
+        }
+        uint32_t *t = cur;
+        cur = nxt;
+        nxt = t;
+        ncur = nn * NCH;
+    }
+
+    // ---- epilogue (FP64) ----------------------------------------------------
+    wave_sync();
+    double *HQ = reinterpret_cast<double *>(work);   // [NR][16]
+    if constexpr (PREC == 0) {
+        acc.finish(HQ);
+    } else {
+        double *tile = reinterpret_cast<double *>(work) + NR * 16;   // 256 doubles
+        acc.finish(HQ, tile);
+    }
+    wave_sync();
+    const double Sc = A.C * meas_l * meas_m;
+    // lanes 0..NV*NV-1: B_lm; NV*NV..2NV*NV-1: B_mm; 2NV*NV..3NV*NV-1: B_ll
+    const int t = lane;
+    const int blk = t / (NV * NV), ij = t % (NV * NV);
+    const int i = ij / NV, j = ij % NV;
+    double v = 0.0;
+    if (blk == 0) {
+        for (int b = 0; b < NQ; ++b) v += HQ[i * 16 + b] * wq[b] * bary[b * NV + j];
+        v = -Sc * v;
+    } else if (blk == 1) {
+        for (int b = 0; b < NQ; ++b) {
+            double cb = 0.0;
+#pragma unroll
+            for (int r = 0; r < NV; ++r) cb += HQ[r * 16 + b];
+            v += wq[b] * bary[b * NV + i] * bary[b * NV + j] * cb;
+        }
+        v = Sc * v;
+    } else if (blk == 2) {
+        if (i != j) {
+            const int r = offrow<NV>(i < j ? i : j, i < j ? j : i);
+            for (int b = 0; b < NQ; ++b) v += HQ[r * 16 + b] * wq[b];
+            v = Sc * v;
+        } else {
+            double h = 0.0;
+            for (int b = 0; b < NQ; ++b) h += HQ[i * 16 + b] * wq[b];
+            double off = 0.0;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                if (q == i) continue;
+                const int r = offrow<NV>(i < q ? i : q, i < q ? q : i);
+                double s2 = 0.0;
+                for (int b = 0; b < NQ; ++b) s2 += HQ[r * 16 + b] * wq[b];
+                off += s2;
+            }
+            v = Sc * (h - off);
+        }
+    }
+    (void)NOFF;
+    const bool four = A.form == NLQ_FORM_SYM4;
+    if (explicit_mode) {
+        constexpr int N2 = 2 * NV;
+        if (blk == 0) {
+            ex_block[i * N2 + NV + j] = four ? v : 0.0;
+            ex_block[(NV + j) * N2 + i] = four ? v : 2.0 * v;
+        } else if (blk == 1) {
+            ex_block[(NV + i) * N2 + NV + j] = four ? v : 2.0 * v;
+        } else if (blk == 2) {
+            ex_block[i * N2 + j] = four ? v : 0.0;
+        }
+        return;
+    }
+    const int32_t li = A.conn[l * NV + i], mj = A.conn[static_cast<int64_t>(m) * NV + j];
+    if (blk == 0) {
+        // B_lm at (l_i, m_j); its transpose B_ml at (m_j, l_i)
+        int64_t a0 = A.row_ptr[li], a1 = A.row_ptr[li + 1] - 1, pos = -1;
+        while (a0 <= a1) {
+            const int64_t mid = (a0 + a1) >> 1;
+            const int32_t cv = A.col[mid];
+            if (cv == mj) { pos = mid; break; }
+            if (cv < mj) a0 = mid + 1; else a1 = mid - 1;
+        }
+        if (pos >= 0) {
+            if (four) unsafeAtomicAdd(&A.val[pos], v);
+            unsafeAtomicAdd(&A.val[A.tmap[pos]], four ? v : 2.0 * v);
+        }
+    } else if (blk == 1) {
+        unsafeAtomicAdd(&A.val[A.elpos[static_cast<int64_t>(m) * NV * NV + i * NV + j]],
+                        four ? v : 2.0 * v);
+    } else if (blk == 2) {
+        if (four) atomicAdd(&s_bll[i * NV + j], v);
+    }
+}
+
+// -------------------------------------------------------------- kernels
+
+template <int DIM, int PREC>
+__global__ void __launch_bounds__(kThreads)
+k_integrate(AsmArgs A)
+{
+    using S = Shape<DIM>;
+    constexpr int NV = S::NV, NQ = S::NQ;
+    extern __shared__ __align__(16) char smem[];
+    __shared__ double s_rule[NQ * NV + NQ];
+    __shared__ double s_bll[NV * NV];
+    __shared__ int64_t s_item;
+    __shared__ int s_next;
+    __shared__ unsigned long long s_leaf[10];
+    const int wid = threadIdx.x / kWave;
+    char *wmem = smem + wid * WaveMem<DIM, PREC>::bytes(A.capl);
+    for (int t = threadIdx.x; t < NQ * NV + NQ; t += kThreads) s_rule[t] = A.rule[t];
+    if (threadIdx.x < 10) s_leaf[threadIdx.x] = 0ull;
+    unsigned long long pairs_done = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            s_item = atomicAdd(A.counter, 1u);
+            s_next = 0;
+        }
+        if (threadIdx.x < NV * NV) s_bll[threadIdx.x] = 0.0;
+        __syncthreads();
+        const int64_t l = s_item;
+        if (l >= A.ne) break;
+        const int64_t b0 = A.pair_off[l];
+        const int nJ = static_cast<int>(A.pair_off[l + 1] - b0);
+        for (;;) {
+            int p = 0;
+            if (lane_id() == 0) p = atomicAdd(&s_next, 1);
+            p = bcast0(p);
+            if (p >= nJ) break;
+            const int32_t m = A.pair_m[b0 + p];
+            process_pair<DIM, PREC>(A, l, m, wmem, s_rule, s_bll, false, nullptr, s_leaf);
+            ++pairs_done;
+        }
+        __syncthreads();
+        if (A.form == NLQ_FORM_SYM4 && threadIdx.x < NV * NV)
+            unsafeAtomicAdd(&A.val[A.elpos[l * NV * NV + threadIdx.x]], s_bll[threadIdx.x]);
+        __syncthreads();
+    }
+    if (lane_id() == 0 && pairs_done) atomicAdd(&A.counters->pairs_done, pairs_done);
+    if (threadIdx.x >= 1 && threadIdx.x <= A.lmax && s_leaf[threadIdx.x])
+        atomicAdd(&A.counters->leaf[threadIdx.x], s_leaf[threadIdx.x]);
+}
+
+// explicit pairs: every wave takes pairs from the global counter and writes the
+// extended block [2N+2][2N+2] of each
+template <int DIM, int PREC>
+__global__ void __launch_bounds__(kThreads)
+k_pair_blocks(AsmArgs A)
+{
+    using S = Shape<DIM>;
+    constexpr int NV = S::NV, NQ = S::NQ;
+    extern __shared__ __align__(16) char smem[];
+    __shared__ double s_rule[NQ * NV + NQ];
+    const int wid = threadIdx.x / kWave;
+    char *wmem = smem + wid * WaveMem<DIM, PREC>::bytes(A.capl);
+    for (int t = threadIdx.x; t < NQ * NV + NQ; t += kThreads) s_rule[t] = A.rule[t];
+    __syncthreads();
+    for (;;) {
+        unsigned int it = 0;
+        if (lane_id() == 0) it = atomicAdd(A.counter, 1u);
+        it = bcast0(it);
+        if (it >= A.n_explicit) break;
+        double *blk = A.ex_out + static_cast<int64_t>(it) * (2 * NV) * (2 * NV);
+        for (int t = lane_id(); t < 4 * NV * NV; t += kWave) blk[t] = 0.0;
+        wave_sync();
+        process_pair<DIM, PREC>(A, A.ex_l[it], A.ex_m[it], wmem, s_rule, nullptr, true, blk,
+                                nullptr);
+    }
+}
+
+template <int DIM, int PREC> void launch_one(System &s, AsmArgs &A, hipStream_t st, bool explicit_mode)
+{
+    const int lds = kWaves * WaveMem<DIM, PREC>::bytes(A.capl);
+    if (lds > 150 * 1024) fail(NLQ_EINVAL, "lmax too large for the per-wave refinement lists");
+    auto kern = explicit_mode ? k_pair_blocks<DIM, PREC> : k_integrate<DIM, PREC>;
+    NLQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    int per_cu = 0;
+    NLQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, lds));
+    if (per_cu < 1) per_cu = 1;
+    int64_t grid = static_cast<int64_t>(s.ctx->n_cu) * per_cu;
+    const int64_t items = explicit_mode ? A.n_explicit : A.ne;
+    if (grid > items) grid = items;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(kThreads), lds, st, A);
+    NLQ_CHECK_LAUNCH();
+}
+
+}  // namespace
+
+void launch_integrate(System &s, hipStream_t st, int64_t n_explicit, const int32_t *ex_l,
+                      const int32_t *ex_m, double *ex_out)
+{
+    const Mesh &m = *s.mesh;
+    const Tables &T = s.ctx->get_tables(m.dim, s.p.lmax);
+    AsmArgs A{};
+    A.ne = m.n_elems;
+    A.pair_off = s.pair_off.as<int64_t>();
+    A.pair_m = s.pair_m.as<int32_t>();
+    A.vert = s.vert.as<double>();
+    A.lo = s.lo.as<double>();
+    A.hi = s.hi.as<double>();
+    A.meas = s.meas.as<double>();
+    A.conn = m.conn.as<int32_t>();
+    A.row_ptr = s.row_ptr.as<int64_t>();
+    A.col = s.col.as<int32_t>();
+    A.tmap = s.tmap.as<int32_t>();
+    A.elpos = s.elpos.as<int32_t>();
+    A.val = s.val.as<double>();
+    A.lam64 = T.lam64.as<double>();
+    A.lam32 = T.lam32.as<float>();
+    A.rule = T.rule.as<double>();
+    for (int q = 0; q < 10; ++q) A.lvl_off[q] = q < static_cast<int>(T.lvl_off.size()) ? T.lvl_off[q] : 0;
+    A.delta = s.p.delta;
+    A.eps = s.p.eps;
+    A.dme = s.p.delta - s.p.eps;
+    A.dpe = s.p.delta + s.p.eps;
+    A.dme2 = A.dme * A.dme * (1.0 - 1e-12);
+    A.dpe2 = A.dpe * A.dpe * (1.0 + 1e-12);
+    A.C = s.C;
+    A.f_delta = static_cast<float>(s.p.delta);
+    A.f_inv_eps = static_cast<float>(1.0 / s.p.eps);
+    A.f_delta_over_eps = static_cast<float>(s.p.delta / s.p.eps);
+    A.f_dme2 = static_cast<float>(A.dme * A.dme);
+    A.f_dpe2 = static_cast<float>(A.dpe * A.dpe);
+    A.f_inv_delta2 = static_cast<float>(1.0 / (s.p.delta * s.p.delta));
+    A.kernel = s.p.kernel;
+    A.lmin = s.p.lmin;
+    A.lmax = s.p.lmax;
+    A.form = s.p.form;
+    int capl = 1;
+    for (int q = 0; q < s.p.lmax - 2; ++q) capl *= (1 << m.dim);
+    A.capl = capl;
+    A.counter = s.l_counter.as<unsigned int>();
+    A.counters = s.counters.as<AsmCounters>();
+    A.n_explicit = n_explicit;
+    A.ex_l = ex_l;
+    A.ex_m = ex_m;
+    A.ex_out = ex_out;
+    NLQ_HIP(hipMemsetAsync(A.counter, 0, sizeof(unsigned int), st));
+    const bool ex = n_explicit > 0;
+    if (!ex) {
+        NLQ_HIP(hipMemsetAsync(A.counters, 0, sizeof(AsmCounters), st));
+        NLQ_HIP(hipMemsetAsync(A.val, 0, sizeof(double) * s.nnz, st));
+    }
+    if (m.dim == 2) {
+        if (s.p.precision == NLQ_FP64_PLAIN) launch_one<2, 0>(s, A, st, ex);
+        else launch_one<2, 1>(s, A, st, ex);
+    } else {
+        if (s.p.precision == NLQ_FP64_PLAIN) launch_one<3, 0>(s, A, st, ex);
+        else launch_one<3, 1>(s, A, st, ex);
+    }
+}
+
+}  // namespace nlq

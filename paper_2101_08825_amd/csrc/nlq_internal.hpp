@@ -1,0 +1,181 @@
+// Internal runtime structures of libnlq (host side).  Not part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "nlq.h"
+
+namespace nlq {
+
+struct Error {
+    nlq_status status;
+    std::string msg;
+};
+
+[[noreturn]] void fail(nlq_status st, const std::string &msg);
+void set_last_error(const std::string &msg);
+
+#define NLQ_HIP(call)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            ::nlq::fail(NLQ_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define NLQ_CHECK_LAUNCH() NLQ_HIP(hipGetLastError())
+
+struct Ctx;
+
+// Device allocation charged against the context budget.
+class DevBuf {
+  public:
+    DevBuf() = default;
+    DevBuf(Ctx *ctx, size_t bytes) { alloc(ctx, bytes); }
+    ~DevBuf() { release(); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept { *this = std::move(o); }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) {
+            release();
+            p_ = o.p_;
+            bytes_ = o.bytes_;
+            ctx_ = o.ctx_;
+            o.p_ = nullptr;
+            o.bytes_ = 0;
+        }
+        return *this;
+    }
+    void alloc(Ctx *ctx, size_t bytes);
+    void release();
+    template <class T> T *as() const { return reinterpret_cast<T *>(p_); }
+    size_t bytes() const { return bytes_; }
+    bool empty() const { return p_ == nullptr; }
+
+  private:
+    void *p_ = nullptr;
+    size_t bytes_ = 0;
+    Ctx *ctx_ = nullptr;
+};
+
+// Quadrature rule and refinement tables for one (dim, lmax): the degree-5 rule
+// on the reference simplex and, for every sub-element of Algorithm 1's
+// midpoint refinement up to lmax, the barycentric coordinates (w.r.t. the root
+// element) of its quadrature points.
+struct Tables {
+    int dim = 0, lmax = 0, nq = 0, nv = 0;
+    std::vector<double> bary;   // [nq][nv]
+    std::vector<double> w;      // [nq], sum 1
+    std::vector<int64_t> lvl_off;  // [lmax+2] first sub index of each level (level 1 at 0)
+    int64_t n_sub = 0;
+    DevBuf rule;                // [nq][nv] points, then [nq] weights (double)
+    DevBuf lam64;               // [n_sub][nq][nv] double
+    DevBuf lam32;               // [n_sub][nq][nv] float
+};
+
+struct Server;
+
+struct Ctx {
+    int device = 0;
+    int n_cu = 0;
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;
+    uint64_t budget = 0;
+    std::atomic<uint64_t> used{0};
+    std::mutex tables_mu;
+    std::map<std::pair<int, int>, std::unique_ptr<Tables>> tables;
+    std::unique_ptr<Server> server;
+    const Tables &get_tables(int dim, int lmax);
+    Ctx();
+    ~Ctx();
+};
+
+struct Mesh {
+    Ctx *ctx = nullptr;
+    int dim = 0;
+    int64_t n_nodes = 0, n_elems = 0, n_free = 0;
+    double gmin[3] = {0, 0, 0}, gmax[3] = {0, 0, 0};
+    double ext_max[3] = {0, 0, 0};   // largest element bbox extent per axis
+    DevBuf coords;                   // [n_nodes][dim] double
+    DevBuf conn;                     // [n_elems][dim+1] int32
+    DevBuf constrained;              // [n_nodes] uint8
+    std::vector<double> h_coords;
+    std::vector<int32_t> h_conn;
+    std::vector<uint8_t> h_constrained;
+};
+
+struct AsmCounters {
+    unsigned long long leaf[9];
+    unsigned long long evals;
+    unsigned long long pairs_done;
+    int error;
+    int pad;
+};
+
+struct System {
+    Ctx *ctx = nullptr;
+    const Mesh *mesh = nullptr;
+    nlq_params p{};
+    double C = 0.0;              // kernel constant
+    int64_t n_pairs = 0, nnz = 0;
+    // element tables
+    DevBuf vert;                 // [nv*dim][ne] SoA double
+    DevBuf lo, hi;               // [dim][ne]
+    DevBuf meas;                 // [ne]
+    // pair list
+    DevBuf pair_off;             // [ne+1] int64
+    DevBuf pair_m;               // [n_pairs] int32
+    // pattern
+    DevBuf row_ptr;              // [n+1] int64
+    DevBuf col;                  // [nnz] int32
+    DevBuf tmap;                 // [nnz] int32: position of the transposed entry
+    DevBuf elpos;                // [ne][nv*nv] int32: positions of the element's own block
+    DevBuf val;                  // [nnz] double
+    // rhs / solution
+    DevBuf F, Ft, u, g;          // [n] double
+    DevBuf counters;             // AsmCounters
+    DevBuf l_counter;            // unsigned int
+    nlq_assemble_info info{};
+    bool has_rhs = false;
+    std::vector<double> h_g;
+};
+
+// kernels launched from the runtime (defined in the .hip files)
+void launch_elem_tables(System &s, hipStream_t st);
+void build_pairs(System &s, hipStream_t st);
+void build_pattern(System &s, hipStream_t st);
+void launch_integrate(System &s, hipStream_t st, int64_t n_explicit, const int32_t *ex_l,
+                      const int32_t *ex_m, double *ex_out);
+void launch_load_lift(System &s, hipStream_t st, const double *f_dev, const double *g_dev);
+int cg_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, int *converged);
+void launch_box_mesh(int dim, int n, int k_gamma, double *coords, int32_t *conn,
+                     uint8_t *constrained, hipStream_t st);
+
+void exclusive_scan_i64(Ctx *ctx, const int64_t *in, int64_t *out, int64_t n, hipStream_t st);
+
+double kernel_constant(int dim, int kernel, double delta, double eps);
+std::unique_ptr<Tables> make_tables(Ctx *ctx, int dim, int lmax);
+
+}  // namespace nlq
+
+struct nlq_ctx {
+    nlq::Ctx impl;
+};
+struct nlq_mesh {
+    nlq::Mesh impl;
+};
+struct nlq_system {
+    nlq::System impl;
+};

@@ -1,0 +1,340 @@
+// Load vector, lifting and the FP64 conjugate-gradient solve of the volume-
+// constrained system (Section 2, eqs. (poisson), (A-F), (weak-homo)).
+//   F_i  = int_Omega f_h phi_i   (f_h the P1 interpolant of the nodal f)
+//   F~_i = F_i - sum_{j in Gamma} A_ij g_j   for free i (lifting, minus sign)
+//   A_{Omega,Omega} w = F~_Omega by Jacobi-preconditioned CG; u = w (free), g (Gamma)
+#include <cmath>
+#include <vector>
+
+#include "nlq_device.hpp"
+#include "nlq_internal.hpp"
+
+namespace nlq {
+
+namespace {
+
+// F_i += sum_q w_q |T| f_h(x_q) lambda_i(x_q) over the elements T containing i
+template <int DIM>
+__global__ void k_load(int64_t ne, const int32_t *__restrict__ conn, const double *__restrict__ meas,
+                       const double *__restrict__ rule, const double *__restrict__ f,
+                       const uint8_t *__restrict__ constrained, double *__restrict__ F)
+{
+    constexpr int NV = DIM + 1, NQ = DIM == 2 ? 7 : 15;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    const double *bary = rule;
+    const double *w = rule + NQ * NV;
+    double fv[NV];
+    int32_t id[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        id[v] = conn[e * NV + v];
+        fv[v] = f[id[v]];
+    }
+    const double me = meas[e];
+#pragma unroll
+    for (int a = 0; a < NV; ++a) {
+        if (constrained[id[a]]) continue;
+        double s = 0.0;
+        for (int q = 0; q < NQ; ++q) {
+            double fq = 0.0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) fq += fv[v] * bary[q * NV + v];
+            s += w[q] * fq * bary[q * NV + a];
+        }
+        unsafeAtomicAdd(&F[id[a]], s * me);
+    }
+}
+
+// one wave per row: F~_i = F_i - sum_{j in Gamma} A_ij g_j (free i), 0 on Gamma
+__global__ void __launch_bounds__(256)
+k_lift(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+       const double *__restrict__ val, const uint8_t *__restrict__ constrained,
+       const double *__restrict__ g, const double *__restrict__ F, double *__restrict__ Ft)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (i >= n) return;
+    double s = 0.0;
+    if (!constrained[i])
+        for (int64_t k = row_ptr[i] + lane_id(); k < row_ptr[i + 1]; k += kWave) {
+            const int32_t j = col[k];
+            if (constrained[j]) s += val[k] * g[j];
+        }
+    s = wave_sum(s);
+    if (lane_id() == 0) Ft[i] = constrained[i] ? 0.0 : F[i] - s;
+}
+
+// ---- CG pieces -------------------------------------------------------------
+
+constexpr int kCgThreads = 256;
+constexpr int kCgRows = kCgThreads / kWave;
+
+struct CgScalars {
+    double rz, rz_new, pq, rr, alpha, beta, bnorm2;
+};
+
+// q = A_ff p on free rows (0 on Gamma); partial sums of p.q per block
+__global__ void __launch_bounds__(kCgThreads)
+k_spmv_dot(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+           const double *__restrict__ val, const uint8_t *__restrict__ constrained,
+           const double *__restrict__ p, double *__restrict__ q, double *__restrict__ partial)
+{
+    __shared__ double red[kCgRows];
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kCgRows + threadIdx.x / kWave;
+    double s = 0.0;
+    bool live = i < n && !constrained[i];
+    if (live)
+        for (int64_t k = row_ptr[i] + lane_id(); k < row_ptr[i + 1]; k += kWave) {
+            const int32_t j = col[k];
+            if (!constrained[j]) s += val[k] * p[j];
+        }
+    s = wave_sum(s);
+    double contrib = 0.0;
+    if (i < n && lane_id() == 0) {
+        q[i] = live ? s : 0.0;
+        contrib = live ? s * p[i] : 0.0;
+    }
+    if (lane_id() == 0) red[threadIdx.x / kWave] = contrib;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int r = 0; r < kCgRows; ++r) t += red[r];
+        partial[blockIdx.x] = t;
+    }
+}
+
+// fixed-order reduction of the block partials (one block): out = sum partial
+__global__ void __launch_bounds__(kCgThreads)
+k_reduce(int64_t nb, const double *__restrict__ partial, double *__restrict__ out, int nvals)
+{
+    __shared__ double red[kCgThreads / kWave];
+    for (int v = 0; v < nvals; ++v) {
+        double s = 0.0;
+        for (int64_t b = threadIdx.x; b < nb; b += kCgThreads) s += partial[v * nb + b];
+        s = wave_sum(s);
+        if (lane_id() == 0) red[threadIdx.x / kWave] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int r = 0; r < kCgThreads / kWave; ++r) t += red[r];
+            out[v] = t;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_alpha(CgScalars *sc)
+{
+    sc->alpha = sc->pq != 0.0 ? sc->rz / sc->pq : 0.0;
+}
+
+// w += alpha p; r -= alpha q; z = D^-1 r; partials of r.z and r.r
+__global__ void __launch_bounds__(kCgThreads)
+k_update(int64_t n, const CgScalars *__restrict__ sc, const double *__restrict__ dinv,
+         const double *__restrict__ p, const double *__restrict__ q, double *__restrict__ w,
+         double *__restrict__ r, double *__restrict__ z, double *__restrict__ partial, int64_t nb)
+{
+    __shared__ double red[2][kCgThreads / kWave];
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kCgThreads + threadIdx.x;
+    double rz = 0.0, rr = 0.0;
+    if (i < n) {
+        const double a = sc->alpha;
+        w[i] += a * p[i];
+        const double ri = r[i] - a * q[i];
+        r[i] = ri;
+        const double zi = dinv[i] * ri;
+        z[i] = zi;
+        rz = ri * zi;
+        rr = ri * ri;
+    }
+    rz = wave_sum(rz);
+    rr = wave_sum(rr);
+    if (lane_id() == 0) {
+        red[0][threadIdx.x / kWave] = rz;
+        red[1][threadIdx.x / kWave] = rr;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < kCgThreads / kWave; ++k) {
+            a += red[0][k];
+            b += red[1][k];
+        }
+        partial[blockIdx.x] = a;
+        partial[nb + blockIdx.x] = b;
+    }
+}
+
+__global__ void k_beta(CgScalars *sc)
+{
+    sc->beta = sc->rz != 0.0 ? sc->rz_new / sc->rz : 0.0;
+    sc->rz = sc->rz_new;
+}
+
+__global__ void k_pupdate(int64_t n, const CgScalars *__restrict__ sc, const double *__restrict__ z,
+                          double *__restrict__ p)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = z[i] + sc->beta * p[i];
+}
+
+// r = F~ (free), z = D^-1 r, p = z, w = 0; dinv from the diagonal; partials r.z, r.r
+__global__ void __launch_bounds__(kCgThreads)
+k_cg_init(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+          const double *__restrict__ val, const uint8_t *__restrict__ constrained,
+          const double *__restrict__ b, double *__restrict__ dinv, double *__restrict__ w,
+          double *__restrict__ r, double *__restrict__ z, double *__restrict__ p,
+          double *__restrict__ partial, int64_t nb)
+{
+    __shared__ double red[2][kCgThreads / kWave];
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kCgThreads + threadIdx.x;
+    double rz = 0.0, rr = 0.0;
+    if (i < n) {
+        double d = 0.0;
+        const bool fr = !constrained[i];
+        if (fr) {
+            int64_t a0 = row_ptr[i], a1 = row_ptr[i + 1] - 1;
+            while (a0 <= a1) {
+                const int64_t mid = (a0 + a1) >> 1;
+                const int32_t c = col[mid];
+                if (c == i) { d = val[mid]; break; }
+                if (c < i) a0 = mid + 1; else a1 = mid - 1;
+            }
+        }
+        const double di = (fr && d != 0.0) ? 1.0 / d : 0.0;
+        dinv[i] = di;
+        const double ri = fr ? b[i] : 0.0;
+        w[i] = 0.0;
+        r[i] = ri;
+        z[i] = di * ri;
+        p[i] = di * ri;
+        rz = ri * di * ri;
+        rr = ri * ri;
+    }
+    rz = wave_sum(rz);
+    rr = wave_sum(rr);
+    if (lane_id() == 0) {
+        red[0][threadIdx.x / kWave] = rz;
+        red[1][threadIdx.x / kWave] = rr;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, c = 0.0;
+        for (int k = 0; k < kCgThreads / kWave; ++k) {
+            a += red[0][k];
+            c += red[1][k];
+        }
+        partial[blockIdx.x] = a;
+        partial[nb + blockIdx.x] = c;
+    }
+}
+
+__global__ void k_compose_u(int64_t n, const uint8_t *__restrict__ constrained,
+                            const double *__restrict__ w, const double *__restrict__ g,
+                            double *__restrict__ u)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) u[i] = constrained[i] ? g[i] : w[i];
+}
+
+}  // namespace
+
+void launch_load_lift(System &s, hipStream_t st, const double *f_dev, const double *g_dev)
+{
+    const Mesh &m = *s.mesh;
+    const Tables &T = s.ctx->get_tables(m.dim, s.p.lmax);
+    const int64_t n = m.n_nodes, ne = m.n_elems;
+    if (s.F.empty()) s.F.alloc(s.ctx, sizeof(double) * n);
+    if (s.Ft.empty()) s.Ft.alloc(s.ctx, sizeof(double) * n);
+    NLQ_HIP(hipMemsetAsync(s.F.as<void>(), 0, sizeof(double) * n, st));
+    dim3 g1((ne + 255) / 256), b1(256);
+    if (m.dim == 2)
+        hipLaunchKernelGGL(k_load<2>, g1, b1, 0, st, ne, m.conn.as<int32_t>(), s.meas.as<double>(),
+                           T.rule.as<double>(), f_dev, m.constrained.as<uint8_t>(), s.F.as<double>());
+    else
+        hipLaunchKernelGGL(k_load<3>, g1, b1, 0, st, ne, m.conn.as<int32_t>(), s.meas.as<double>(),
+                           T.rule.as<double>(), f_dev, m.constrained.as<uint8_t>(), s.F.as<double>());
+    NLQ_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_lift, dim3((n + 3) / 4), dim3(256), 0, st, n, s.row_ptr.as<int64_t>(),
+                       s.col.as<int32_t>(), s.val.as<double>(), m.constrained.as<uint8_t>(), g_dev,
+                       s.F.as<double>(), s.Ft.as<double>());
+    NLQ_CHECK_LAUNCH();
+}
+
+// Returns the iteration count; the solution (u = w on free nodes, g on Gamma)
+// is left in s.u.  The host checks the residual every `check` iterations.
+int cg_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, int *converged)
+{
+    const Mesh &m = *s.mesh;
+    const int64_t n = m.n_nodes;
+    if (s.u.empty()) s.u.alloc(s.ctx, sizeof(double) * n);
+    DevBuf dinv(s.ctx, sizeof(double) * n), w(s.ctx, sizeof(double) * n),
+        r(s.ctx, sizeof(double) * n), z(s.ctx, sizeof(double) * n), p(s.ctx, sizeof(double) * n),
+        q(s.ctx, sizeof(double) * n);
+    const int64_t nb_rows = (n + kCgRows - 1) / kCgRows;
+    const int64_t nb_vec = (n + kCgThreads - 1) / kCgThreads;
+    const int64_t nbmax = nb_rows > nb_vec ? nb_rows : nb_vec;
+    DevBuf partial(s.ctx, sizeof(double) * 2 * nbmax);
+    DevBuf scal(s.ctx, sizeof(CgScalars));
+    CgScalars *sc = scal.as<CgScalars>();
+    NLQ_HIP(hipMemsetAsync(sc, 0, sizeof(CgScalars), st));
+    const uint8_t *cst = m.constrained.as<uint8_t>();
+    hipLaunchKernelGGL(k_cg_init, dim3(nb_vec), dim3(kCgThreads), 0, st, n, s.row_ptr.as<int64_t>(),
+                       s.col.as<int32_t>(), s.val.as<double>(), cst, s.Ft.as<double>(),
+                       dinv.as<double>(), w.as<double>(), r.as<double>(), z.as<double>(),
+                       p.as<double>(), partial.as<double>(), nb_vec);
+    NLQ_CHECK_LAUNCH();
+    // rz -> sc->rz, rr -> sc->rz_new (temporarily)
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kCgThreads), 0, st, nb_vec, partial.as<double>(),
+                       &sc->rz, 2);
+    NLQ_CHECK_LAUNCH();
+    CgScalars h{};
+    NLQ_HIP(hipMemcpyAsync(&h, sc, sizeof(CgScalars), hipMemcpyDeviceToHost, st));
+    NLQ_HIP(hipStreamSynchronize(st));
+    const double bnorm = std::sqrt(h.rz_new);
+    int it = 0;
+    *converged = 0;
+    double rn = bnorm;
+    if (bnorm == 0.0) {
+        *converged = 1;
+        *relres = 0.0;
+    } else {
+        const int check = 8;
+        for (it = 0; it < maxit;) {
+            for (int k = 0; k < check && it < maxit; ++k, ++it) {
+                hipLaunchKernelGGL(k_spmv_dot, dim3(nb_rows), dim3(kCgThreads), 0, st, n,
+                                   s.row_ptr.as<int64_t>(), s.col.as<int32_t>(), s.val.as<double>(),
+                                   cst, p.as<double>(), q.as<double>(), partial.as<double>());
+                hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kCgThreads), 0, st, nb_rows,
+                                   partial.as<double>(), &sc->pq, 1);
+                hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1), 0, st, sc);
+                hipLaunchKernelGGL(k_update, dim3(nb_vec), dim3(kCgThreads), 0, st, n, sc,
+                                   dinv.as<double>(), p.as<double>(), q.as<double>(), w.as<double>(),
+                                   r.as<double>(), z.as<double>(), partial.as<double>(), nb_vec);
+                hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kCgThreads), 0, st, nb_vec,
+                                   partial.as<double>(), &sc->rz_new, 1);
+                hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kCgThreads), 0, st, nb_vec,
+                                   partial.as<double>() + nb_vec, &sc->rr, 1);
+                hipLaunchKernelGGL(k_beta, dim3(1), dim3(1), 0, st, sc);
+                hipLaunchKernelGGL(k_pupdate, dim3(nb_vec), dim3(kCgThreads), 0, st, n, sc,
+                                   z.as<double>(), p.as<double>());
+                NLQ_CHECK_LAUNCH();
+            }
+            NLQ_HIP(hipMemcpyAsync(&h, sc, sizeof(CgScalars), hipMemcpyDeviceToHost, st));
+            NLQ_HIP(hipStreamSynchronize(st));
+            rn = std::sqrt(h.rr);
+            if (rn <= rtol * bnorm) {
+                *converged = 1;
+                break;
+            }
+        }
+        *relres = rn / bnorm;
+    }
+    hipLaunchKernelGGL(k_compose_u, dim3(nb_vec), dim3(kCgThreads), 0, st, n, cst, w.as<double>(),
+                       s.g.as<double>(), s.u.as<double>());
+    NLQ_CHECK_LAUNCH();
+    NLQ_HIP(hipStreamSynchronize(st));
+    return it;
+}
+
+}  // namespace nlq

@@ -1,0 +1,202 @@
+// Host-side tables: quadrature rules, kernel constants and the barycentric
+// coordinates of the quadrature points of every sub-element produced by the
+// midpoint refinement of Algorithm 1 (Section 5).
+#include <cmath>
+
+#include "nlq_internal.hpp"
+#include "nlq_refine.hpp"
+
+namespace nlq {
+
+namespace {
+
+// Degree-5 rules on the reference simplex; barycentric points, weights sum 1.
+// Triangle: the 7-point Radon / Dunavant rule named in Section 6: centroid,
+// then the orbits (1-2a, a, a) and (1-2b, b, b), a,b = (6 -+ sqrt 15)/21, each
+// listed with the distinguished coordinate in position 0, 1, 2.
+// Tetrahedron: Keast's 15-point rule: centroid; (0,1/3,1/3,1/3) orbit;
+// (8/11,1/11,1/11,1/11) orbit (distinguished coordinate in position 0..3);
+// (c,c,d,d) orbit with c = (13 - sqrt 91)/52, d = 1/2 - c, the two c's at the
+// index pairs (0,1),(0,2),(0,3),(1,2),(1,3),(2,3).
+void simplex_rule(int dim, std::vector<double> &bary, std::vector<double> &w)
+{
+    if (dim == 2) {
+        const double r15 = std::sqrt(15.0);
+        const double orbit_a[2] = {(6.0 - r15) / 21.0, (6.0 + r15) / 21.0};
+        const double orbit_w[2] = {(155.0 - r15) / 1200.0, (155.0 + r15) / 1200.0};
+        bary = {1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0};
+        w = {9.0 / 40.0};
+        for (int o = 0; o < 2; ++o)
+            for (int pos = 0; pos < 3; ++pos) {
+                for (int j = 0; j < 3; ++j)
+                    bary.push_back(j == pos ? 1.0 - 2.0 * orbit_a[o] : orbit_a[o]);
+                w.push_back(orbit_w[o]);
+            }
+        return;
+    }
+    const double wc = 0.1817020685825350548382618;
+    const double w_face = 0.03616071428571428571428571;
+    const double w_11 = 0.06987149451617381646536165;
+    const double w_edge = 0.06569484936831875607385811;
+    bary = {0.25, 0.25, 0.25, 0.25};
+    w = {wc};
+    for (int pos = 0; pos < 4; ++pos) {
+        for (int j = 0; j < 4; ++j) bary.push_back(j == pos ? 0.0 : 1.0 / 3.0);
+        w.push_back(w_face);
+    }
+    for (int pos = 0; pos < 4; ++pos) {
+        for (int j = 0; j < 4; ++j) bary.push_back(j == pos ? 8.0 / 11.0 : 1.0 / 11.0);
+        w.push_back(w_11);
+    }
+    const double c = (13.0 - std::sqrt(91.0)) / 52.0;
+    const double d = 0.5 - c;
+    for (int i = 0; i < 4; ++i)
+        for (int j = i + 1; j < 4; ++j) {
+            for (int k = 0; k < 4; ++k) bary.push_back((k == i || k == j) ? c : d);
+            w.push_back(w_edge);
+        }
+}
+
+// Gauss-Legendre rule on [-1, 1]: roots of P_n by Newton from the Tricomi
+// initial guess; weights 2 / ((1 - x^2) P_n'(x)^2).
+void legendre_rule(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const double pi = 3.14159265358979323846;
+    for (int k = 1; k <= n; ++k) {
+        double t = std::cos(pi * (4.0 * k - 1.0) / (4.0 * n + 2.0));
+        double deriv = 1.0;
+        for (int iter = 0; iter < 60; ++iter) {
+            double pm1 = 1.0, p = t;
+            for (int j = 1; j < n; ++j) {
+                double pn = ((2.0 * j + 1.0) * t * p - j * pm1) / (j + 1.0);
+                pm1 = p;
+                p = pn;
+            }
+            deriv = n * (pm1 - t * p) / (1.0 - t * t);
+            double step = p / deriv;
+            t -= step;
+            if (std::fabs(step) <= 1e-17) break;
+        }
+        double pm1 = 1.0, p = t;
+        for (int j = 1; j < n; ++j) {
+            double pn = ((2.0 * j + 1.0) * t * p - j * pm1) / (j + 1.0);
+            pm1 = p;
+            p = pn;
+        }
+        deriv = n * (pm1 - t * p) / (1.0 - t * t);
+        x[k - 1] = t;
+        w[k - 1] = 2.0 / ((1.0 - t * t) * deriv * deriv);
+    }
+}
+
+double xi_host(double r)
+{
+    double s = r * r;
+    return 0.5 + r * (315.0 / 256.0 + s * (-420.0 / 256.0 + s * (378.0 / 256.0 +
+                                            s * (-180.0 / 256.0 + s * (35.0 / 256.0)))));
+}
+
+}  // namespace
+
+// Kernel constant C.  eta = 1: C_{delta,eps} of Section 6 (kappa = 1).  Gaussian
+// eta: c such that c * omega_N * int_0^{delta+eps} rho^{N+1} eta mu drho = N
+// (L_eps u = Laplacian u for quadratic u), 40 Gauss-Legendre points on each
+// smooth piece [0, delta-eps] and [delta-eps, delta+eps].
+double kernel_constant(int dim, int kernel, double delta, double eps)
+{
+    const double pi = 3.14159265358979323846;
+    if (kernel == NLQ_ETA_CONST) {
+        const double q2 = (eps / delta) * (eps / delta);
+        if (dim == 2)
+            return (4.0 / (pi * std::pow(delta, 4))) / (1.0 + q2 * (6.0 / 11.0 + q2 * (3.0 / 143.0)));
+        return (15.0 / (4.0 * pi * std::pow(delta, 5))) /
+               (1.0 + q2 * (10.0 / 11.0 + q2 * (15.0 / 143.0)));
+    }
+    std::vector<double> gx, gw;
+    legendre_rule(40, gx, gw);
+    const double omega = (dim == 2) ? 2.0 * pi : 4.0 * pi;
+    double moment = 0.0;
+    const double a[2] = {0.0, delta - eps}, b[2] = {delta - eps, delta + eps};
+    for (int piece = 0; piece < 2; ++piece) {
+        const double half = 0.5 * (b[piece] - a[piece]), mid = 0.5 * (b[piece] + a[piece]);
+        for (size_t i = 0; i < gx.size(); ++i) {
+            double rho = mid + half * gx[i];
+            double m = (rho < delta - eps) ? 1.0 : (rho > delta + eps ? 0.0 : xi_host((delta - rho) / eps));
+            moment += half * gw[i] * std::pow(rho, dim + 1) * std::exp(-(rho * rho) / (delta * delta)) * m;
+        }
+    }
+    return dim / (omega * moment);
+}
+
+std::unique_ptr<Tables> make_tables(Ctx *ctx, int dim, int lmax)
+{
+    auto t = std::make_unique<Tables>();
+    t->dim = dim;
+    t->lmax = lmax;
+    t->nv = dim + 1;
+    simplex_rule(dim, t->bary, t->w);
+    t->nq = static_cast<int>(t->w.size());
+    const int nv = t->nv, nq = t->nq, nch = 1 << dim;
+    t->lvl_off.assign(lmax + 2, 0);
+    int64_t per_level = 1;
+    for (int lev = 1; lev <= lmax; ++lev) {
+        t->lvl_off[lev + 1] = t->lvl_off[lev] + per_level;
+        per_level *= nch;
+    }
+    t->n_sub = t->lvl_off[lmax + 1];
+    std::vector<double> lam(static_cast<size_t>(t->n_sub) * nq * nv);
+    std::vector<float> lam32(lam.size());
+    // barycentric vertices of every sub-element, level by level
+    std::vector<double> cur(nv * nv, 0.0), next;
+    for (int i = 0; i < nv; ++i) cur[i * nv + i] = 1.0;
+    for (int lev = 1; lev <= lmax; ++lev) {
+        const int64_t count = t->lvl_off[lev + 1] - t->lvl_off[lev];
+        for (int64_t c = 0; c < count; ++c) {
+            const double *V = &cur[static_cast<size_t>(c) * nv * nv];
+            double *out = &lam[static_cast<size_t>(t->lvl_off[lev] + c) * nq * nv];
+            for (int a = 0; a < nq; ++a)
+                for (int i = 0; i < nv; ++i) {
+                    double s = 0.0;
+                    for (int v = 0; v < nv; ++v) s += t->bary[a * nv + v] * V[v * nv + i];
+                    out[a * nv + i] = s;
+                }
+        }
+        if (lev == lmax) break;
+        next.assign(static_cast<size_t>(count) * nch * nv * nv, 0.0);
+        for (int64_t c = 0; c < count; ++c)
+            for (int ch = 0; ch < nch; ++ch)
+                refine_child(dim, nv, &cur[static_cast<size_t>(c) * nv * nv], ch,
+                             &next[(static_cast<size_t>(c) * nch + ch) * nv * nv]);
+        cur.swap(next);
+    }
+    for (size_t k = 0; k < lam.size(); ++k) lam32[k] = static_cast<float>(lam[k]);
+    std::vector<double> rule(t->bary);
+    rule.insert(rule.end(), t->w.begin(), t->w.end());
+    t->rule.alloc(ctx, rule.size() * sizeof(double));
+    NLQ_HIP(hipMemcpy(t->rule.as<void>(), rule.data(), rule.size() * sizeof(double),
+                      hipMemcpyHostToDevice));
+    t->lam64.alloc(ctx, lam.size() * sizeof(double));
+    t->lam32.alloc(ctx, lam32.size() * sizeof(float));
+    NLQ_HIP(hipMemcpy(t->lam64.as<void>(), lam.data(), lam.size() * sizeof(double),
+                      hipMemcpyHostToDevice));
+    NLQ_HIP(hipMemcpy(t->lam32.as<void>(), lam32.data(), lam32.size() * sizeof(float),
+                      hipMemcpyHostToDevice));
+    return t;
+}
+
+const Tables &Ctx::get_tables(int dim, int lmax)
+{
+    std::lock_guard<std::mutex> g(tables_mu);
+    auto key = std::make_pair(dim, lmax);
+    auto it = tables.find(key);
+    if (it != tables.end()) return *it->second;
+    NLQ_HIP(hipSetDevice(device));
+    auto t = make_tables(this, dim, lmax);
+    const Tables &ref = *t;
+    tables.emplace(key, std::move(t));
+    return ref;
+}
+
+}  // namespace nlq

@@ -1,0 +1,303 @@
+"""Thin ctypes binding of libnlq (include/nlq.h): argument marshalling only.
+
+Every step of the assembly and solve runs in the library's HIP kernels; this
+module converts numpy arrays to pointers and status codes to exceptions.  It
+raises ImportError-like errors loudly when the built library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import weakref
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnlq.so")
+
+NLQ_OK, NLQ_EINVAL, NLQ_ENOMEM, NLQ_EDEVICE, NLQ_ENOTREADY, NLQ_ECANCELLED, NLQ_EBUSY, \
+    NLQ_ENOCONV = 0, -1, -2, -3, -4, -5, -6, -7
+NLQ_ETA_CONST, NLQ_ETA_GAUSS = 0, 1
+NLQ_FORM_SYM4, NLQ_FORM_PAPER2 = 0, 1
+NLQ_FP64_PLAIN, NLQ_FP32_MIXED = 0, 1
+
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTREADY",
+                -5: "ECANCELLED", -6: "EBUSY", -7: "ENOCONV"}
+
+# every extern "C" symbol declared in include/nlq.h
+EXPORTS = [
+    "nlq_ctx_create", "nlq_ctx_set_stream", "nlq_ctx_memory", "nlq_ctx_destroy",
+    "nlq_mesh_create", "nlq_mesh_box", "nlq_mesh_info", "nlq_mesh_copy", "nlq_mesh_destroy",
+    "nlq_assemble", "nlq_assemble_info_get", "nlq_reassemble", "nlq_set_data", "nlq_solve",
+    "nlq_info", "nlq_csr_copy", "nlq_csr_device", "nlq_pairs_copy", "nlq_rhs_copy",
+    "nlq_pair_blocks", "nlq_system_destroy", "nlq_serve_start", "nlq_submit", "nlq_wait",
+    "nlq_cancel", "nlq_result_release", "nlq_serve_stop", "nlq_last_error",
+]
+
+
+class NlqError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class nlq_params(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("kernel", C.c_int32), ("delta", C.c_double),
+                ("eps", C.c_double), ("scale", C.c_double), ("lmin", C.c_int32),
+                ("lmax", C.c_int32), ("form", C.c_int32), ("precision", C.c_int32),
+                ("deterministic", C.c_int32)]
+
+
+class nlq_assemble_info(C.Structure):
+    _fields_ = [("n_pairs", C.c_int64), ("n_leaf", C.c_int64 * 9), ("n_evals", C.c_int64),
+                ("nnz", C.c_int64), ("t_tables", C.c_double), ("t_pairs", C.c_double),
+                ("t_pattern", C.c_double), ("t_integrate", C.c_double), ("t_total", C.c_double)]
+
+
+class nlq_solve_info(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32),
+                ("rel_residual", C.c_double), ("seconds", C.c_double)]
+
+
+class nlq_request(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32), ("k_gamma", C.c_int32),
+                ("params", nlq_params), ("f_nodal", C.c_void_p), ("g_nodal", C.c_void_p),
+                ("rtol", C.c_double), ("maxit", C.c_int32)]
+
+
+class nlq_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n_nodes", C.c_int64), ("n_pairs", C.c_int64),
+                ("n_free", C.c_int64), ("u", C.POINTER(C.c_double)), ("cg_iterations", C.c_int32),
+                ("rel_residual", C.c_double), ("latency_s", C.c_double), ("queue_s", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libnlq.so; fail loudly if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run paper_2101_08825_amd/build.py "
+                               "(there is no fallback implementation)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+        P = C.POINTER
+        sig = {
+            "nlq_ctx_create": [i32, u64, P(vp)],
+            "nlq_ctx_set_stream": [vp, vp],
+            "nlq_ctx_memory": [vp, P(u64), P(u64)],
+            "nlq_ctx_destroy": [vp],
+            "nlq_mesh_create": [vp, i32, i64, vp, i64, vp, vp, P(vp)],
+            "nlq_mesh_box": [vp, i32, i32, i32, P(vp)],
+            "nlq_mesh_info": [vp, P(i32), P(i64), P(i64), P(i64)],
+            "nlq_mesh_copy": [vp, vp, vp, vp],
+            "nlq_mesh_destroy": [vp],
+            "nlq_assemble": [vp, vp, P(nlq_params), P(vp)],
+            "nlq_assemble_info_get": [vp, P(nlq_assemble_info)],
+            "nlq_reassemble": [vp],
+            "nlq_set_data": [vp, vp, vp],
+            "nlq_solve": [vp, d, i32, vp, P(nlq_solve_info)],
+            "nlq_info": [vp, P(i64), P(i64), P(i64), P(i64)],
+            "nlq_csr_copy": [vp, vp, vp, vp],
+            "nlq_csr_device": [vp, P(vp), P(vp), P(vp)],
+            "nlq_pairs_copy": [vp, vp, vp],
+            "nlq_rhs_copy": [vp, vp],
+            "nlq_pair_blocks": [vp, i64, vp, vp, vp],
+            "nlq_system_destroy": [vp],
+            "nlq_serve_start": [vp, i32],
+            "nlq_submit": [vp, P(nlq_request), P(u64)],
+            "nlq_wait": [vp, u64, i32, P(nlq_result)],
+            "nlq_cancel": [vp, u64],
+            "nlq_result_release": [vp, u64],
+            "nlq_serve_stop": [vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int32
+        L.nlq_last_error.argtypes = []
+        L.nlq_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != NLQ_OK:
+        raise NlqError(st, lib().nlq_last_error().decode())
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def params(dim, delta, eps, lmax, lmin=1, kernel=NLQ_ETA_CONST, form=NLQ_FORM_SYM4,
+           precision=NLQ_FP64_PLAIN, scale=0.0):
+    return nlq_params(int(dim), int(kernel), float(delta), float(eps), float(scale), int(lmin),
+                      int(lmax), int(form), int(precision), 0)
+
+
+class Context:
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        h = C.c_void_p()
+        _check(lib().nlq_ctx_create(device, hbm_budget_bytes, C.byref(h)))
+        self.h = h
+        self._meshes = weakref.WeakSet()
+
+    def set_stream(self, hip_stream: int | None):
+        _check(lib().nlq_ctx_set_stream(self.h, C.c_void_p(hip_stream or 0)))
+
+    def memory(self):
+        u, b = C.c_uint64(), C.c_uint64()
+        _check(lib().nlq_ctx_memory(self.h, C.byref(u), C.byref(b)))
+        return u.value, b.value
+
+    def close(self):
+        """Destroy the context after every mesh (and system) made from it."""
+        if self.h:
+            for m in list(self._meshes):
+                m.close()
+            _check(lib().nlq_ctx_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Mesh:
+    def __init__(self, ctx: Context, h):
+        self.ctx = ctx
+        self.h = h
+        self._systems = weakref.WeakSet()
+        ctx._meshes.add(self)
+        d, nn, ne, nf = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().nlq_mesh_info(h, C.byref(d), C.byref(nn), C.byref(ne), C.byref(nf)))
+        self.dim, self.n_nodes, self.n_elems, self.n_free = d.value, nn.value, ne.value, nf.value
+
+    @classmethod
+    def create(cls, ctx, coords, conn, constrained):
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        conn = np.ascontiguousarray(conn, dtype=np.int32)
+        cst = np.ascontiguousarray(constrained, dtype=np.uint8)
+        h = C.c_void_p()
+        _check(lib().nlq_mesh_create(ctx.h, coords.shape[1], coords.shape[0], _ptr(coords),
+                                     conn.shape[0], _ptr(conn), _ptr(cst), C.byref(h)))
+        return cls(ctx, h)
+
+    @classmethod
+    def box(cls, ctx, dim, n, k_gamma):
+        h = C.c_void_p()
+        _check(lib().nlq_mesh_box(ctx.h, dim, n, k_gamma, C.byref(h)))
+        return cls(ctx, h)
+
+    def copy(self):
+        coords = np.zeros((self.n_nodes, self.dim))
+        conn = np.zeros((self.n_elems, self.dim + 1), dtype=np.int32)
+        cst = np.zeros(self.n_nodes, dtype=np.uint8)
+        _check(lib().nlq_mesh_copy(self.h, _ptr(coords), _ptr(conn), _ptr(cst)))
+        return coords, conn, cst
+
+    def close(self):
+        """Destroy the mesh after every system assembled on it."""
+        if self.h:
+            for s in list(self._systems):
+                s.close()
+            _check(lib().nlq_mesh_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            if self.ctx.h:
+                self.close()
+        except Exception:
+            pass
+
+
+class System:
+    def __init__(self, ctx: Context, mesh: Mesh, prm: nlq_params):
+        h = C.c_void_p()
+        _check(lib().nlq_assemble(ctx.h, mesh.h, C.byref(prm), C.byref(h)))
+        self.h = h
+        self.ctx, self.mesh, self.prm = ctx, mesh, prm
+        mesh._systems.add(self)
+
+    def info(self):
+        i = nlq_assemble_info()
+        _check(lib().nlq_assemble_info_get(self.h, C.byref(i)))
+        return i
+
+    def sizes(self):
+        a, b, c, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().nlq_info(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+        return dict(n_rows=a.value, nnz=b.value, n_pairs=c.value, n_free=d.value)
+
+    def reassemble(self):
+        _check(lib().nlq_reassemble(self.h))
+
+    def set_data(self, f_nodal, g_nodal):
+        f = np.ascontiguousarray(f_nodal, dtype=np.float64)
+        g = np.ascontiguousarray(g_nodal, dtype=np.float64)
+        _check(lib().nlq_set_data(self.h, _ptr(f), _ptr(g)))
+
+    def solve(self, rtol=1e-12, maxit=20000):
+        u = np.zeros(self.mesh.n_nodes)
+        inf = nlq_solve_info()
+        st = lib().nlq_solve(self.h, float(rtol), int(maxit), _ptr(u), C.byref(inf))
+        if st not in (NLQ_OK, NLQ_ENOCONV):
+            _check(st)
+        return u, inf
+
+    def csr(self):
+        s = self.sizes()
+        rp = np.zeros(s["n_rows"] + 1, dtype=np.int64)
+        col = np.zeros(s["nnz"], dtype=np.int32)
+        val = np.zeros(s["nnz"])
+        _check(lib().nlq_csr_copy(self.h, _ptr(rp), _ptr(col), _ptr(val)))
+        return rp, col, val
+
+    def csr_device(self):
+        rp, col, val = C.c_void_p(), C.c_void_p(), C.c_void_p()
+        _check(lib().nlq_csr_device(self.h, C.byref(rp), C.byref(col), C.byref(val)))
+        return rp.value, col.value, val.value
+
+    def pairs(self):
+        s = self.sizes()
+        off = np.zeros(self.mesh.n_elems + 1, dtype=np.int64)
+        pm = np.zeros(max(s["n_pairs"], 1), dtype=np.int32)
+        _check(lib().nlq_pairs_copy(self.h, _ptr(off), _ptr(pm)))
+        return off, pm[:s["n_pairs"]]
+
+    def rhs(self):
+        out = np.zeros(self.mesh.n_nodes)
+        _check(lib().nlq_rhs_copy(self.h, _ptr(out)))
+        return out
+
+    def pair_blocks(self, l, m):
+        l = np.ascontiguousarray(l, dtype=np.int32)
+        m = np.ascontiguousarray(m, dtype=np.int32)
+        n2 = 2 * (self.mesh.dim + 1)
+        out = np.zeros((l.shape[0], n2, n2))
+        _check(lib().nlq_pair_blocks(self.h, l.shape[0], _ptr(l), _ptr(m), _ptr(out)))
+        return out
+
+    def close(self):
+        if self.h:
+            _check(lib().nlq_system_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            if self.mesh.h and self.ctx.h:
+                self.close()
+        except Exception:
+            pass

@@ -1,0 +1,198 @@
+"""GPU path (through the C-ABI) against the FP64 CPU oracle.
+
+Bars: pair list, CSR pattern and leaf counts bit-exact; values of A with
+relative Frobenius error <= 1e-12 (FP64 path) and <= 1e-5 (FP32 mixed path);
+F~ and u relative 2-norm errors against the oracle.
+"""
+import numpy as np
+import pytest
+
+from paper_2101_08825_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def nlq_ctx():
+    import torch
+    from paper_2101_08825_amd import nlq
+    assert torch.cuda.is_available()
+    ctx = nlq.Context(0)
+    yield ctx
+    ctx.close()
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _oracle_full(O, mesh, prm, u=None):
+    s = None
+    if u is not None:
+        uu, f, g = W.nodal_data(mesh, u)
+        s = O.solve_problem((mesh.coords, mesh.conn, mesh.constrained), prm, f, g)
+        return s, f, g
+    m = O.OracleMesh(mesh.coords, mesh.conn)
+    off, pm = O.pairs(m, prm.delta + prm.eps)
+    rp, col = O.pattern(m, off, pm)
+    val, leaves, evals = O.assemble(m, prm, off, pm, rp, col)
+
+    class R:
+        pass
+    r = R()
+    r.off, r.pm, r.row_ptr, r.col, r.val, r.leaves = off, pm, rp, col, val, leaves
+    return r, None, None
+
+
+def _print_case(name, **kw):
+    print(f"[case] {name} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("form", [0, 1])
+def test_c1_full_parity(nlq_ctx, oracle_lib, precision, form):
+    """2D 16^2, delta = 2h, eps = delta/16, L_max = 3, u = x1^2, f = -2."""
+    from paper_2101_08825_amd import nlq
+    O = oracle_lib
+    wl = W.WORKLOADS["c1_2d16"]
+    _print_case("c1", precision=precision, form=form)
+    mesh = wl.mesh()
+    prm_o = O.params(wl.delta, wl.eps, wl.lmax, form=form)
+    ref, f, g = _oracle_full(O, mesh, prm_o, wl.u)
+    m = nlq.Mesh.create(nlq_ctx, mesh.coords, mesh.conn, mesh.constrained)
+    s = nlq.System(nlq_ctx, m, nlq.params(2, wl.delta, wl.eps, wl.lmax, form=form,
+                                          precision=precision))
+    off, pm = s.pairs()
+    assert np.array_equal(off, ref.off) and np.array_equal(pm, ref.pm)
+    rp, col, val = s.csr()
+    assert np.array_equal(rp, ref.row_ptr) and np.array_equal(col, ref.col)
+    info = s.info()
+    assert list(info.n_leaf)[1:4] == list(ref.leaves[1:4])
+    err = _rel(val, ref.val)
+    print(f"  |A-A_or|_F/|A_or|_F = {err:.3e}", flush=True)
+    assert err <= (TOL64 if precision == 0 else TOL32)
+    s.set_data(f, g)
+    ft = s.rhs()
+    fterr = _rel(ft, ref.Ft)
+    u, sinfo = s.solve(rtol=1e-14 if precision == 0 else 1e-12)
+    uerr = _rel(u, ref.u)
+    print(f"  |F~-F~_or|/|F~_or| = {fterr:.3e}  |u-u_or|/|u_or| = {uerr:.3e}  cg={sinfo.iterations}",
+          flush=True)
+    if precision == 0:
+        assert fterr <= 1e-12 and uerr <= 1e-11
+    else:
+        assert fterr <= 1e-5 and uerr <= 1e-4
+    s.close()
+    m.close()
+
+
+@pytest.mark.parametrize("dim,n,kd,ed,lmax", [(2, 12, 3, 8, 4), (3, 5, 2, 16, 3), (3, 4, 2, 4, 2)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pair_blocks_sampled(nlq_ctx, oracle_lib, dim, n, kd, ed, lmax, precision):
+    """Per-pair extended blocks of seeded sampled pairs vs the oracle."""
+    from paper_2101_08825_amd import nlq
+    O = oracle_lib
+    _print_case("pair_blocks", dim=dim, n=n, kd=kd, ed=ed, lmax=lmax, precision=precision)
+    mesh = W.kuhn_mesh(dim, n, kd)
+    delta = kd / n
+    eps = delta / ed
+    m = nlq.Mesh.create(nlq_ctx, mesh.coords, mesh.conn, mesh.constrained)
+    s = nlq.System(nlq_ctx, m, nlq.params(dim, delta, eps, lmax, precision=precision))
+    off, pm = s.pairs()
+    rng = np.random.default_rng(11)
+    pick = rng.choice(len(pm), size=min(60, len(pm)), replace=False)
+    ls = np.searchsorted(off, pick, side="right") - 1
+    ms = pm[pick]
+    got = s.pair_blocks(ls, ms)
+    om = O.OracleMesh(mesh.coords, mesh.conn)
+    prm = O.params(delta, eps, lmax)
+    ref = np.stack([O.pair_block(om, prm, int(ls[k]), int(ms[k]))[0] for k in range(len(pick))])
+    stacked = _rel(got, ref)
+    scale = max(np.linalg.norm(r) for r in ref)
+    worst = max(np.linalg.norm(g - r) for g, r in zip(got, ref)) / scale
+    print(f"  sampled blocks: stacked rel Frobenius {stacked:.3e}, worst block error / "
+          f"largest block {worst:.3e}", flush=True)
+    tol = TOL64 if precision == 0 else TOL32
+    assert stacked <= tol and worst <= tol
+    s.close()
+    m.close()
+
+
+def _sample_rows(mesh, rng, count):
+    """interior rows, rows next to the constrained layer, constrained rows, corners"""
+    n = mesh.n
+    dim = mesh.dim
+    k = mesh.k_gamma
+    picks = set()
+    idx = lambda ii: int(sum(ii[d] * (n + 1) ** d for d in range(dim)))
+    picks.add(idx([n // 2] * dim))
+    picks.add(idx([k + 1] * dim))
+    picks.add(idx([k] * dim))
+    picks.add(idx([0] * dim))
+    picks.add(idx([n] * dim))
+    while len(picks) < count:
+        picks.add(int(rng.integers(0, mesh.n_nodes)))
+    return sorted(picks)
+
+
+@pytest.mark.parametrize("name", ["c2a_2d128_d2h", "c2b_2d128_d4h"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_c2_full_size(nlq_ctx, oracle_lib, name, precision):
+    """2D 128^2, delta in {2h, 4h}, eps = delta/32, depth 5: pair list and pattern
+    bit-exact over the whole mesh, values on sampled rows, global invariants."""
+    from paper_2101_08825_amd import nlq
+    O = oracle_lib
+    wl = W.WORKLOADS[name]
+    _print_case(name, precision=precision)
+    mesh = wl.mesh()
+    m = nlq.Mesh.create(nlq_ctx, mesh.coords, mesh.conn, mesh.constrained)
+    s = nlq.System(nlq_ctx, m, nlq.params(2, wl.delta, wl.eps, wl.lmax, precision=precision))
+    info = s.info()
+    print(f"  pairs {info.n_pairs} leaves {list(info.n_leaf)[1:6]} evals {info.n_evals} "
+          f"t_pairs {info.t_pairs:.4f}s t_pattern {info.t_pattern:.4f}s "
+          f"t_integrate {info.t_integrate:.4f}s t_total {info.t_total:.4f}s", flush=True)
+    om = O.OracleMesh(mesh.coords, mesh.conn)
+    thr = wl.delta + wl.eps
+    off_o, pm_o = O.pairs(om, thr)
+    off, pm = s.pairs()
+    assert np.array_equal(off, off_o) and np.array_equal(pm, pm_o)
+    rp_o, col_o = O.pattern(om, off_o, pm_o)
+    rp, col, val = s.csr()
+    assert np.array_equal(rp, rp_o) and np.array_equal(col, col_o)
+    rows = _sample_rows(mesh, np.random.default_rng(5), 24)
+    prm = O.params(wl.delta, wl.eps, wl.lmax)
+    ref = O.rows(om, prm, thr, rows)
+    got = np.concatenate([val[rp[r]:rp[r + 1]] for r in rows])
+    exp = np.concatenate([v for c, v in ref])
+    err = _rel(got, exp)
+    print(f"  sampled rows: rel Frobenius {err:.3e}", flush=True)
+    assert err <= (TOL64 if precision == 0 else TOL32)
+    # zero row sums and symmetry over the whole matrix
+    n = mesh.n_nodes
+    rows_of = np.repeat(np.arange(n), np.diff(rp))
+    rowsum = np.bincount(rows_of, weights=val, minlength=n)
+    rowabs = np.bincount(rows_of, weights=np.abs(val), minlength=n)
+    rs = np.max(np.abs(rowsum) / rowabs)
+    import scipy.sparse as sp
+    A = sp.csr_matrix((val, col, rp), shape=(n, n))
+    asym = sp.linalg.norm(A - A.T) / sp.linalg.norm(A)
+    print(f"  max |row sum| / row abs sum {rs:.3e}; |A - A^T|/|A| {asym:.3e}", flush=True)
+    assert rs <= 1e-13 and asym <= 1e-14
+    s.close()
+    m.close()
+
+
+@pytest.mark.parametrize("dim,n,k", [(2, 16, 2), (3, 6, 1)])
+def test_box_mesh_matches_generator(nlq_ctx, dim, n, k):
+    from paper_2101_08825_amd import nlq
+    mesh = W.kuhn_mesh(dim, n, k)
+    m = nlq.Mesh.box(nlq_ctx, dim, n, k)
+    coords, conn, cst = m.copy()
+    assert np.array_equal(coords, mesh.coords)
+    assert np.array_equal(conn, mesh.conn)
+    assert np.array_equal(cst, mesh.constrained)
+    m.close()
