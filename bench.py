@@ -1,0 +1,202 @@
+"""Benchmark of the hot path on one MI355X.
+
+A step is one pass of the whole path (element tables, pair list, CSR pattern,
+Algorithm 1 + leaf integration, FP64 CSR accumulation, load vector + lifting,
+CG solve) for each of the two 2D 128x128 problems (delta = 2h and 4h,
+eps = delta/32, depth <= 5, constant kernel, u = x1^2 + x2^2).  Mesh and data
+are resident in HBM before the timed region.  The value is element-pair
+integrals per second of the FP32-mixed path; the FP64 plain path is timed on the
+same steps; per-request assemble+solve latency percentiles are reported.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2101_08825_amd import workloads as W  # noqa: E402
+
+METRIC = "element-pair integrals/s + p50/p99 assemble+solve latency vs FP64 plain"
+WORKLOADS = ("c2a_2d128_d2h", "c2b_2d128_d4h")
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def flops_per_eval(dim: int) -> int:
+    """Algorithmic flops of one kernel evaluation: distance (dim subtractions,
+    dim multiply-adds) plus the contraction into the N+1 + N(N+1)/2 rows of
+    the per-pair accumulators (one multiply-add each)."""
+    nv = dim + 1
+    rows = nv + nv * (nv - 1) // 2
+    return dim + 2 * dim + 2 * rows - 1
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs), q)) if xs else float("nan")
+
+
+def run_steps(nlq, ctx, setups, precision, steps, warmup, torch):
+    lat = []
+    step_times = []
+    kernel = []
+    pairs_per_step = 0
+    evals_per_step = 0
+    for it in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pairs = evals = 0
+        kt = []
+        for (mesh, wl, f_t, g_t) in setups:
+            r0 = time.perf_counter()
+            s = nlq.System(ctx, mesh, nlq.params(2, wl.delta, wl.eps, wl.lmax, precision=precision))
+            s.set_data_device(f_t.data_ptr(), g_t.data_ptr())
+            _, inf = s.solve(rtol=1e-10, copy=False)
+            info = s.info()
+            s.close()
+            lat.append(time.perf_counter() - r0)
+            pairs += info.n_pairs
+            evals += info.n_evals
+            kt.append((info.t_kernel, info.n_evals))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if it >= warmup:
+            step_times.append(dt)
+            kernel.extend(kt)
+        else:
+            lat.clear()
+        pairs_per_step, evals_per_step = pairs, evals
+    return dict(step_times=step_times, lat=lat, kernel=kernel, pairs=pairs_per_step,
+                evals=evals_per_step)
+
+
+def cpu_baseline(sample_frac=0.01, seed=0):
+    """The oracle on a seeded sample of outer elements of both problems."""
+    import oracle
+    nt = max(1, min(16, os.cpu_count() or 1))
+    pairs = 0
+    secs = 0.0
+    nsel = 0
+    for name in WORKLOADS:
+        wl = W.WORKLOADS[name]
+        mesh = wl.mesh()
+        m = oracle.OracleMesh(mesh.coords, mesh.conn)
+        prm = oracle.params(wl.delta, wl.eps, wl.lmax)
+        off, pm = oracle.pairs(m, wl.delta + wl.eps, nt)
+        rp, col = oracle.pattern(m, off, pm)
+        rng = np.random.default_rng(seed)
+        k = max(1, int(sample_frac * mesh.n_elems))
+        sel = np.sort(rng.choice(mesh.n_elems, k, replace=False))
+        t0 = time.perf_counter()
+        oracle.assemble(m, prm, off, pm, rp, col, sel=sel, nthreads=nt)
+        secs += time.perf_counter() - t0
+        pairs += int(np.sum(off[sel + 1] - off[sel]))
+        nsel += k
+    return {"value": pairs / secs, "unit": "pairs/s", "cores": nt, "kind": "oracle",
+            "sample": f"{nsel} seeded outer elements ({100 * sample_frac:.0f}% of each 128^2 "
+                      f"problem, {pairs} pairs, Algorithm 1 + integration + CSR scatter), "
+                      f"{secs:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("this build runs on one GPU only: the path has no cross-GPU sharding "
+              "(see the design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2101_08825_amd import nlq
+    assert torch.cuda.is_available(), "bench needs the GPU"
+    torch.cuda.init()
+    ctx = nlq.Context(0)
+    ctx.set_stream(torch.cuda.current_stream().cuda_stream)
+    setups = []
+    for name in WORKLOADS:
+        wl = W.WORKLOADS[name]
+        mesh = wl.mesh()
+        _, f, g = W.nodal_data(mesh, wl.u)
+        m = nlq.Mesh.create(ctx, mesh.coords, mesh.conn, mesh.constrained)
+        f_t = torch.as_tensor(f, dtype=torch.float64, device="cuda")
+        g_t = torch.as_tensor(g, dtype=torch.float64, device="cuda")
+        setups.append((m, wl, f_t, g_t))
+    torch.cuda.synchronize()
+
+    mixed = run_steps(nlq, ctx, setups, nlq.NLQ_FP32_MIXED, args.steps, args.warmup, torch)
+    plain = None
+    if not args.skip_fp64:
+        plain = run_steps(nlq, ctx, setups, nlq.NLQ_FP64_PLAIN, args.steps, args.warmup, torch)
+
+    ms = 1e3 * float(np.mean(mixed["step_times"]))
+    value = mixed["pairs"] / (ms * 1e-3)
+    # dominant kernel: the integration launch, timed with HIP events on its stream
+    fpe = flops_per_eval(2)
+    kt = sum(t for t, _ in mixed["kernel"])
+    ke = sum(e for _, e in mixed["kernel"])
+    achieved = ke * fpe / kt / 1e12
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "2D [0,1]^2 Kuhn 128x128 (32768 P1 triangles), delta in {2h,4h}, "
+                        "eps=delta/32, depth<=5, 7-pt rule, constant gamma, u=x1^2+x2^2, "
+                        "f=-4; per step: assemble + load/lift + CG for both horizons",
+            "pairs_per_step": mixed["pairs"],
+            "kernel_evals_per_step": mixed["evals"],
+            "precision": "fp32 kernel evaluation + fp32 matrix-core contraction, fp64 blocks/CSR/CG",
+        },
+        "latency_ms": {"p50": 1e3 * percentile(mixed["lat"], 50),
+                       "p99": 1e3 * percentile(mixed["lat"], 99)},
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+            "traffic": None,
+            "kernel": "k_integrate<2,1>",
+            "flops_per_eval": fpe,
+            "kernel_ms_per_step": 1e3 * kt / args.steps,
+        },
+    }
+    if plain is not None:
+        pms = 1e3 * float(np.mean(plain["step_times"]))
+        pkt = sum(t for t, _ in plain["kernel"])
+        out["fp64_plain"] = {
+            "value": plain["pairs"] / (pms * 1e-3),
+            "ms_per_step": pms,
+            "latency_ms": {"p50": 1e3 * percentile(plain["lat"], 50),
+                           "p99": 1e3 * percentile(plain["lat"], 99)},
+            "kernel_ms_per_step": 1e3 * pkt / args.steps,
+        }
+        out["speedup_vs_fp64_plain"] = out["value"] / out["fp64_plain"]["value"]
+    for (m, *_rest) in setups:
+        m.close()
+    ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -95,7 +95,8 @@ typedef struct {
     int64_t n_leaf[9];        /* Integration(s, m) calls per level 1..8 (index = level) */
     int64_t n_evals;          /* kernel evaluations gamma_eps(x_a, y_b) */
     int64_t nnz;
-    double t_tables, t_pairs, t_pattern, t_integrate, t_total;
+    double t_tables, t_pairs, t_pattern, t_integrate, t_total;  /* host wall clock */
+    double t_kernel;          /* integration kernel alone, HIP events on its stream */
 } nlq_assemble_info;
 
 typedef struct {
@@ -159,11 +160,17 @@ nlq_status nlq_reassemble(nlq_system *sys);
  * F~ = F - A g~ on free rows, with g~ = g on Gamma and 0 elsewhere (the lifting
  * enters with a minus sign).  f_nodal, g_nodal: host [n_nodes]. */
 nlq_status nlq_set_data(nlq_system *sys, const double *f_nodal, const double *g_nodal);
+/* As nlq_set_data with device pointers [n_nodes] (e.g. torch tensors already in
+ * HBM); read on the context's stream, not retained after the call. */
+nlq_status nlq_set_data_device(nlq_system *sys, const double *f_dev, const double *g_dev);
 /* Jacobi-preconditioned CG on A_{Omega,Omega} w = F~_Omega (FP64 SpMV, dots and
  * residuals); u = w on free nodes, g on Gamma.  u_out: host [n_nodes] or NULL.
  * Returns ENOCONV (u = last iterate) when maxit is reached. */
 nlq_status nlq_solve(nlq_system *sys, double rtol, int32_t maxit, double *u_out,
                      nlq_solve_info *info);
+/* Borrowed device pointer to the last solution u [n_nodes], valid until
+ * nlq_system_destroy (NULL before the first nlq_solve). */
+nlq_status nlq_solution_device(const nlq_system *sys, const double **u_dev);
 
 nlq_status nlq_info(const nlq_system *sys, int64_t *n_rows, int64_t *nnz, int64_t *n_pairs,
                     int64_t *n_free);

@@ -160,11 +160,19 @@ void upload_mesh(Mesh &m, hipStream_t st)
 void run_integrate(System &s, hipStream_t st)
 {
     const double t0 = now_s();
-    launch_integrate(s, st, 0, nullptr, nullptr, nullptr);
+    hipEvent_t e0, e1;
+    NLQ_HIP(hipEventCreate(&e0));
+    NLQ_HIP(hipEventCreate(&e1));
+    launch_integrate(s, st, 0, nullptr, nullptr, nullptr, e0, e1);
     AsmCounters c{};
     NLQ_HIP(hipMemcpyAsync(&c, s.counters.as<void>(), sizeof(AsmCounters), hipMemcpyDeviceToHost, st));
     NLQ_HIP(hipStreamSynchronize(st));
     s.info.t_integrate = now_s() - t0;
+    float ms = 0.0f;
+    NLQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+    s.info.t_kernel = 1e-3 * ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     const int nq = s.mesh->dim == 2 ? 7 : 15;
     int64_t leaves = 0;
     for (int q = 0; q < 9; ++q) {
@@ -420,6 +428,30 @@ nlq_status nlq_set_data(nlq_system *sys, const double *f_nodal, const double *g_
         launch_load_lift(s, st, f.as<double>(), s.g.as<double>());
         NLQ_HIP(hipStreamSynchronize(st));
         s.has_rhs = true;
+    });
+}
+
+nlq_status nlq_set_data_device(nlq_system *sys, const double *f_dev, const double *g_dev)
+{
+    return guard([&] {
+        if (!sys || !f_dev || !g_dev) fail(NLQ_EINVAL, "NULL argument");
+        System &s = sys->impl;
+        NLQ_HIP(hipSetDevice(s.ctx->device));
+        const int64_t n = s.mesh->n_nodes;
+        hipStream_t st = s.ctx->stream;
+        if (s.g.empty()) s.g.alloc(s.ctx, sizeof(double) * n);
+        NLQ_HIP(hipMemcpyAsync(s.g.as<void>(), g_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        launch_load_lift(s, st, f_dev, s.g.as<double>());
+        NLQ_HIP(hipStreamSynchronize(st));
+        s.has_rhs = true;
+    });
+}
+
+nlq_status nlq_solution_device(const nlq_system *sys, const double **u_dev)
+{
+    return guard([&] {
+        if (!sys || !u_dev) fail(NLQ_EINVAL, "NULL argument");
+        *u_dev = sys->impl.u.empty() ? nullptr : sys->impl.u.as<double>();
     });
 }
 

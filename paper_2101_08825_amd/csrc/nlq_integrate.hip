@@ -6,13 +6,16 @@
 // form of the Corollary) is accumulated into the pair's blocks.
 //
 // Work decomposition (one GPU, persistent launch):
-//   * a workgroup of kWaves waves takes outer elements l from a global counter;
-//   * its waves take the pairs (l, m), m in J_l, from an LDS counter;
+//   * a workgroup of kWaves waves takes outer elements l from a global counter,
+//     stages the CSR rows of l's nodes in LDS, and its waves take the pairs
+//     (l, m), m in J_l, from an LDS counter;
 //   * a wave walks the refinement tree of its pair level by level: lanes
 //     classify sub-elements in FP64 (every rounding as written, so the leaf set
 //     is reproducible bit for bit), wave ballots + prefix counts compact the
 //     integrate / refine lists in LDS;
-//   * leaves are integrated in batches of 64 outer points staged in LDS:
+//   * the pair's leaves are integrated in batches of 64 outer points staged in
+//     LDS (the table loads of the next batch are issued before the current
+//     batch runs):
 //       plain  (FP64): each lane owns one inner point and a slice of the batch,
 //                      evaluates gamma_eps in FP64 and accumulates
 //                      H_ib = sum_a P_i(a) g_ab, Q_kb = sum_a P_k(a) g_ab in FP64;
@@ -28,6 +31,7 @@
 //       B_ll[i][i] =  S sum_b H_ib w_b - sum_{j != i} B_ll[i][j]
 //     (partition of unity: lambda_i = sum_j lambda_i lambda_j), then FP64
 //     atomics into the CSR values; B_ll is summed per outer element in LDS.
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -69,11 +73,12 @@ struct AsmArgs {
     const double *lam64;  // [sub][nq][nv]
     const float *lam32;
     const double *rule;   // [nq][nv] barycentric points, then [nq] weights
-    int64_t lvl_off[10];
+    int lvl_off[10];
     double delta, eps, dme, dpe, dme2, dpe2, C;
     float f_delta, f_inv_eps, f_delta_over_eps, f_dme2, f_dpe2, f_inv_delta2;
-    int kernel, lmin, lmax, form;
+    int lmin, lmax, form;
     int capl;
+    int rowcap;           // LDS capacity per cached CSR row
     unsigned int *counter;
     AsmCounters *counters;
     int64_t n_explicit;
@@ -90,6 +95,8 @@ __device__ __forceinline__ void wave_sync()
 }
 
 template <class T> __device__ __forceinline__ T bcast0(T v) { return __shfl(v, 0, kWave); }
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // -------------------------------------------------------------- mollifier
 
@@ -118,8 +125,8 @@ __device__ __forceinline__ float xi32(float r)
     return fmaf(p, r, 0.5f);
 }
 
-// gamma_eps / C at squared distance d2 (FP64): eta * mu
-__device__ __forceinline__ double kernel64(const AsmArgs &A, double d2)
+// gamma_eps / C at squared distance d2: eta * mu (FP64)
+template <int ETA> __device__ __forceinline__ double kernel64(const AsmArgs &A, double d2)
 {
     double mu;
     if (d2 < A.dme2) {
@@ -130,8 +137,24 @@ __device__ __forceinline__ double kernel64(const AsmArgs &A, double d2)
         const double d = sqrt(d2);
         mu = d < A.dme ? 1.0 : (d > A.dpe ? 0.0 : xi64((A.delta - d) / A.eps));
     }
-    if (A.kernel == NLQ_ETA_GAUSS) mu *= exp(-d2 / (A.delta * A.delta));
+    if (ETA == NLQ_ETA_GAUSS) mu *= exp(-d2 / (A.delta * A.delta));
     return mu;
+}
+
+// gamma_eps / C at squared distance d2 (FP32; sqrt to ~1 ulp)
+template <int ETA> __device__ __forceinline__ float kernel32(const AsmArgs &A, float d2)
+{
+    float g;
+    if (d2 < A.f_dme2) {
+        g = 1.0f;
+    } else if (d2 > A.f_dpe2) {
+        g = 0.0f;
+    } else {
+        const float d = __builtin_amdgcn_sqrtf(d2);
+        g = xi32(fmaf(-d, A.f_inv_eps, A.f_delta_over_eps));
+    }
+    if (ETA == NLQ_ETA_GAUSS) g *= __expf(-d2 * A.f_inv_delta2);
+    return g;
 }
 
 // -------------------------------------------------------------- geometry
@@ -140,31 +163,34 @@ template <int DIM> struct Simplex {
     double v[DIM + 1][DIM];
 };
 
-template <int DIM>
-__device__ __forceinline__ double pick(const Simplex<DIM> &S, int i, int k)
-{
-    double r = S.v[0][k];
-#pragma unroll
-    for (int q = 1; q <= DIM; ++q)
-        if (i == q) r = S.v[q][k];
-    return r;
-}
-
-// child `c` of S by the midpoint rule, (V_i + V_j) * 0.5 rounded as written
+// child `c` of S by the midpoint rule, (V_i + V_j) * 0.5 rounded as written.
+// Every edge midpoint is formed once; the child's vertices are then chosen by
+// select chains on c, so all table indices are compile-time constants and the
+// simplex stays in registers.
 template <int DIM>
 __device__ __forceinline__ Simplex<DIM> child_of(const Simplex<DIM> &S, int c)
 {
+    constexpr int NV = DIM + 1, NCH = 1 << DIM;
+    double M[NV][NV][DIM];
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k)
+                M[i][j][k] = (i == j) ? S.v[i][k]
+                                      : (i < j ? __dmul_rn(__dadd_rn(S.v[i][k], S.v[j][k]), 0.5) : 0.0);
     Simplex<DIM> out;
 #pragma unroll
-    for (int v = 0; v <= DIM; ++v) {
-        const unsigned char s = child_src(DIM, c, v);
-        const int i = s >> 4, j = s & 15;
+    for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
-            const double a = pick(S, i, k), b = pick(S, j, k);
-            out.v[v][k] = (i == j) ? a : __dmul_rn(__dadd_rn(a, b), 0.5);
+            double r = M[child_src(DIM, 0, v) >> 4][child_src(DIM, 0, v) & 15][k];
+#pragma unroll
+            for (int cc = 1; cc < NCH; ++cc)
+                r = (c == cc) ? M[child_src(DIM, cc, v) >> 4][child_src(DIM, cc, v) & 15][k] : r;
+            out.v[v][k] = r;
         }
-    }
     return out;
 }
 
@@ -197,52 +223,73 @@ __device__ __forceinline__ int classify(const AsmArgs &A, const Simplex<DIM> &ro
 }
 
 // row of the off-diagonal product lambda_a lambda_c (a < c) among the P rows
-template <int NV> __device__ __forceinline__ int offrow(int a, int c)
+template <int NV> __host__ __device__ constexpr int offrow(int a, int c)
 {
     return NV + a * NV - (a * (a + 1)) / 2 + (c - a - 1);
 }
 
-// -------------------------------------------------------------- per-wave LDS
-
-template <int DIM, int PREC> struct WaveMem {
-    using S = Shape<DIM>;
-    // staging of one batch of outer points
-    static constexpr int kStageBytes =
-        PREC == 0 ? kBatch * (DIM + S::NR) * 8 : kBatch * (4 + 16) * 4;
-    static constexpr int kEpiBytes = (S::NR * 16 + (PREC == 1 ? 256 : 0)) * 8;
-    static constexpr int kWorkBytes = kStageBytes > kEpiBytes ? kStageBytes : kEpiBytes;
-    __host__ __device__ static int bytes(int capl)
-    {
-        return (kWorkBytes + kLeafCap * 4 + 2 * capl * 4 + 15) & ~15;
-    }
-};
-
 // -------------------------------------------------------------- integrators
 
+// Leaf entries: (level << 24) | global sub-element index.
+__device__ __forceinline__ uint32_t leaf_entry(int lev, int sub)
+{
+    return (static_cast<uint32_t>(lev) << 24) | static_cast<uint32_t>(sub);
+}
+
 // FP64 plain: lane = (k, b): b = inner point (lane % NYP), k = batch slice
-template <int DIM> struct PlainAcc {
+template <int DIM, int ETA> struct PlainAcc {
     using S = Shape<DIM>;
     static constexpr int NYP = DIM == 2 ? 8 : 16;
     static constexpr int K = kWave / NYP;
+    static constexpr int kStageBytes = kBatch * (DIM + S::NR) * 8;
+    struct In {
+        double lam[S::NV];
+        double w;
+    };
     double acc[S::NR];
     double yh[DIM];   // inner point relative to the anchor
     bool active;
-    __device__ void init(const double *y)
+    __device__ void init(const double *y, int lane, char *)
     {
 #pragma unroll
         for (int r = 0; r < S::NR; ++r) acc[r] = 0.0;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) yh[k] = y[k];
+        active = (lane % NYP) < S::NQ;
     }
-    // stage: lane t writes point t of the batch
-    __device__ static void stage(char *work, int t, bool valid, const double *xh, const double *P)
+    __device__ static In fetch(const AsmArgs &A, bool valid, int sub, int a, int lev, float, double wa)
+    {
+        In in;
+        if (valid) {
+            const double *lam = A.lam64 + (sub * S::NQ + a) * S::NV;
+#pragma unroll
+            for (int i = 0; i < S::NV; ++i) in.lam[i] = lam[i];
+            in.w = ldexp(wa, -DIM * (lev - 1));
+        } else {
+#pragma unroll
+            for (int i = 0; i < S::NV; ++i) in.lam[i] = 0.0;
+            in.w = 0.0;
+        }
+        return in;
+    }
+    template <class Edge> __device__ static void stage(char *work, int t, const In &in, const Edge &E)
     {
         double *sx = reinterpret_cast<double *>(work);
         double *sp = sx + kBatch * DIM;
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) sx[t * DIM + k] = valid ? xh[k] : 0.0;
+        for (int k = 0; k < DIM; ++k) {
+            double s = 0.0;
 #pragma unroll
-        for (int r = 0; r < S::NR; ++r) sp[t * S::NR + r] = valid ? P[r] : 0.0;
+            for (int i = 1; i <= DIM; ++i) s = fma(in.lam[i], E.e[i - 1][k], s);
+            sx[t * DIM + k] = s;
+        }
+#pragma unroll
+        for (int i = 0; i < S::NV; ++i) sp[t * S::NR + i] = in.w * in.lam[i];
+#pragma unroll
+        for (int i = 0; i < S::NV; ++i)
+#pragma unroll
+            for (int j = i + 1; j < S::NV; ++j)
+                sp[t * S::NR + offrow<S::NV>(i, j)] = in.w * in.lam[i] * in.lam[j];
     }
     __device__ void run(const AsmArgs &A, const char *work, int npts)
     {
@@ -257,13 +304,13 @@ template <int DIM> struct PlainAcc {
                 const double dx = sx[p * DIM + k] - yh[k];
                 d2 = fma(dx, dx, d2);
             }
-            const double g = kernel64(A, d2);
+            const double g = kernel64<ETA>(A, d2);
 #pragma unroll
             for (int r = 0; r < S::NR; ++r) acc[r] = fma(sp[p * S::NR + r], g, acc[r]);
         }
     }
-    // totals H/Q for inner point b in lanes with k == 0 -> out[r*16 + b]
-    __device__ void finish(double *out)
+    // totals H/Q for inner point b -> out[r*16 + b]
+    __device__ void finish(double *out, double *)
     {
 #pragma unroll
         for (int r = 0; r < S::NR; ++r) {
@@ -287,20 +334,28 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 //  3D: 4 points per step, rows 0..9 = P, columns 0..14 = inner points.
 //  2D: 8 points per step as two independent 8x8 diagonal blocks: lanes with
 //      column < 8 use point set 0, columns >= 8 set 1.
-template <int DIM> struct MixedAcc {
+// Staging layout: XS floats of coordinates and PS floats of P rows per point;
+// the padding rows stay zero for the whole kernel, and the padding inner
+// columns get a coordinate far outside the horizon, so gamma is 0 there.
+template <int DIM, int ETA> struct MixedAcc {
     using S = Shape<DIM>;
     static constexpr int PPS = DIM == 2 ? 8 : 4;   // points per MFMA step
+    static constexpr int STEPS = kBatch / PPS;
+    static constexpr int XS = DIM == 2 ? 2 : 4;
+    static constexpr int PS = DIM == 2 ? 8 : 16;
+    static constexpr int kStageBytes = kBatch * (XS + PS) * 4;
+    struct In {
+        float lam[S::NV];
+        float w;
+    };
     double dacc[4];
     float yh[3];
-    int n;       // column / row index of this lane in the 16x16 tile
-    int sub;     // sub-index: inner point (and P row) handled by this lane
+    int sub;     // inner point (and P row) handled by this lane
     int poff;    // point offset within a step
-    bool colv, rowv;
-    __device__ void init(const double *y)
+    __device__ void init(const double *y, int lane, char *work)
     {
-        const int l = lane_id();
-        n = l & 15;
-        const int k = l >> 4;
+        const int n = lane & 15;
+        const int k = lane >> 4;
         if (DIM == 2) {
             sub = n & 7;
             poff = 4 * (n >> 3) + k;
@@ -308,52 +363,96 @@ template <int DIM> struct MixedAcc {
             sub = n;
             poff = k;
         }
-        colv = sub < S::NQ;
-        rowv = sub < S::NR;
 #pragma unroll
         for (int r = 0; r < 4; ++r) dacc[r] = 0.0;
-        yh[0] = static_cast<float>(y[0]);
-        yh[1] = static_cast<float>(y[1]);
-        yh[2] = DIM == 3 ? static_cast<float>(y[DIM - 1]) : 0.0f;
+        const bool colv = sub < S::NQ;
+        yh[0] = colv ? static_cast<float>(y[0]) : 1.0e18f;
+        yh[1] = colv ? static_cast<float>(y[1]) : 1.0e18f;
+        yh[2] = (DIM == 3 && colv) ? static_cast<float>(y[DIM - 1]) : 1.0e18f;
+        (void)work;
     }
-    __device__ static void stage(char *work, int t, bool valid, const double *xh, const double *P)
+    __device__ static In fetch(const AsmArgs &A, bool valid, int sub, int a, int lev, float wa, double)
+    {
+        In in;
+        if (valid) {
+            const float *lam = A.lam32 + (sub * S::NQ + a) * S::NV;
+#pragma unroll
+            for (int i = 0; i < S::NV; ++i) in.lam[i] = lam[i];
+            in.w = ldexpf(wa, -DIM * (lev - 1));
+        } else {
+#pragma unroll
+            for (int i = 0; i < S::NV; ++i) in.lam[i] = 0.0f;
+            in.w = 0.0f;
+        }
+        return in;
+    }
+    // zero the P padding rows once (they are never written afterwards)
+    __device__ static void zero_padding(char *work)
+    {
+        float *sp = reinterpret_cast<float *>(work) + kBatch * XS;
+        for (int t = lane_id(); t < kBatch; t += kWave)
+#pragma unroll
+            for (int r = S::NR; r < PS; ++r) sp[t * PS + r] = 0.0f;
+    }
+    // point t of the batch: anchor-relative coordinates and the P rows
+    template <class Edge> __device__ static void stage(char *work, int t, const In &in, const Edge &E)
     {
         float *sx = reinterpret_cast<float *>(work);
-        float *sp = sx + kBatch * 4;
+        float *sp = sx + kBatch * XS;
+        float x[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int k = 0; k < 4; ++k) sx[t * 4 + k] = (valid && k < DIM) ? static_cast<float>(xh[k < DIM ? k : 0]) : 0.0f;
+        for (int k = 0; k < DIM; ++k) {
+            float s = 0.0f;
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-            sp[t * 16 + r] = (valid && r < S::NR) ? static_cast<float>(P[r < S::NR ? r : 0]) : 0.0f;
+            for (int i = 1; i <= DIM; ++i) s = fmaf(in.lam[i], E.e[i - 1][k], s);
+            x[k] = s;
+        }
+        if (DIM == 2) {
+            *reinterpret_cast<float2 *>(sx + t * XS) = make_float2(x[0], x[1]);
+        } else {
+            *reinterpret_cast<float4 *>(sx + t * XS) = make_float4(x[0], x[1], x[2], 0.0f);
+        }
+        float P[S::NR];
+#pragma unroll
+        for (int i = 0; i < S::NV; ++i) P[i] = in.w * in.lam[i];
+#pragma unroll
+        for (int i = 0; i < S::NV; ++i)
+#pragma unroll
+            for (int j = i + 1; j < S::NV; ++j) P[offrow<S::NV>(i, j)] = P[i] * in.lam[j];
+        if (DIM == 2) {
+            *reinterpret_cast<float4 *>(sp + t * PS) = make_float4(P[0], P[1], P[2], P[3]);
+            *reinterpret_cast<float2 *>(sp + t * PS + 4) = make_float2(P[4], P[5 < S::NR ? 5 : 0]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                *reinterpret_cast<float4 *>(sp + t * PS + 4 * q) =
+                    make_float4(P[4 * q], P[4 * q + 1], P[4 * q + 2], P[4 * q + 3]);
+            *reinterpret_cast<float2 *>(sp + t * PS + 8) =
+                make_float2(P[8 < S::NR ? 8 : 0], P[9 < S::NR ? 9 : 0]);
+        }
     }
     __device__ void run(const AsmArgs &A, const char *work, int npts)
     {
-        const float *sx = reinterpret_cast<const float *>(work);
-        const float *sp = sx + kBatch * 4;
+        const float *sx = reinterpret_cast<const float *>(work) + poff * XS;
+        const float *sp = reinterpret_cast<const float *>(work) + kBatch * XS + poff * PS + sub;
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
         const int steps = (npts + PPS - 1) / PPS;
-        for (int t = 0; t < steps; ++t) {
-            const int p = t * PPS + poff;   // < kBatch always
-            const float4 x = *reinterpret_cast<const float4 *>(sx + p * 4);
-            const float a = rowv ? sp[p * 16 + sub] : 0.0f;
-            const float dx = x.x - yh[0], dy = x.y - yh[1];
-            float d2 = fmaf(dx, dx, dy * dy);
-            if (DIM == 3) {
-                const float dz = x.z - yh[2];
-                d2 = fmaf(dz, dz, d2);
-            }
-            float g;
-            if (d2 < A.f_dme2) {
-                g = 1.0f;
-            } else if (d2 > A.f_dpe2) {
-                g = 0.0f;
+#pragma unroll
+        for (int t = 0; t < STEPS; ++t) {
+            if (t >= steps) break;
+            const float a = sp[t * PPS * PS];
+            float d2;
+            if (DIM == 2) {
+                const float2 x = *reinterpret_cast<const float2 *>(sx + t * PPS * XS);
+                const float dx = x.x - yh[0], dy = x.y - yh[1];
+                d2 = fmaf(dx, dx, dy * dy);
             } else {
-                const float d = __builtin_sqrtf(d2);
-                g = xi32(fmaf(-d, A.f_inv_eps, A.f_delta_over_eps));
+                const float4 x = *reinterpret_cast<const float4 *>(sx + t * PPS * XS);
+                const float dx = x.x - yh[0], dy = x.y - yh[1], dz = x.z - yh[2];
+                d2 = fmaf(dz, dz, fmaf(dx, dx, dy * dy));
             }
-            if (A.kernel == NLQ_ETA_GAUSS) g *= __expf(-d2 * A.f_inv_delta2);
-            const float b = colv ? g : 0.0f;
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+            const float g = kernel32<ETA>(A, d2);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, g, acc, 0, 0, 0);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) dacc[r] += static_cast<double>(acc[r]);
@@ -379,45 +478,83 @@ template <int DIM> struct MixedAcc {
     }
 };
 
+// per-wave LDS: staging | epilogue (H/Q and the MFMA tile) | leaves | 2 lists
+template <int DIM, int PREC> struct WaveMem {
+    using S = Shape<DIM>;
+    static constexpr int kStageBytes =
+        PREC == 0 ? PlainAcc<DIM, 0>::kStageBytes : MixedAcc<DIM, 0>::kStageBytes;
+    static constexpr int kEpiBytes = (S::NR * 16 + (PREC == 1 ? 256 : 0)) * 8;
+    __host__ __device__ static int bytes(int capl)
+    {
+        return (kStageBytes + kEpiBytes + kLeafCap * 4 + 2 * capl * 4 + 15) & ~15;
+    }
+};
+
+// binary search of column c in the sorted list cols[0..n)
+__device__ __forceinline__ int64_t search(const int32_t *cols, int64_t n, int32_t c)
+{
+    int64_t a = 0, b = n - 1;
+    while (a <= b) {
+        const int64_t mid = (a + b) >> 1;
+        const int32_t v = cols[mid];
+        if (v == c) return mid;
+        if (v < c) a = mid + 1; else b = mid - 1;
+    }
+    return -1;
+}
+
+// CSR rows of the outer element's nodes, cached in LDS by the workgroup
+struct RowCache {
+    const int32_t *cols[4];   // LDS copy, or the global row when it does not fit
+    int64_t base[4];
+    int64_t len[4];
+};
+
+template <int DIM, class Real> struct Edges {
+    Real e[DIM][DIM];
+};
+
 // -------------------------------------------------------------- one pair
 
-template <int DIM, int PREC>
-__device__ void process_pair(const AsmArgs &A, int64_t l, int32_t m, char *wmem,
-                             const double *s_rule, double *s_bll, bool explicit_mode,
+template <int DIM, int PREC, int ETA>
+__device__ void process_pair(const AsmArgs &A, int l, int m, char *wmem, const double *s_rule,
+                             const float *s_w32, double *s_bll, const RowCache *rc,
                              double *ex_block, unsigned long long *s_leaf)
 {
     using S = Shape<DIM>;
-    constexpr int NV = S::NV, NQ = S::NQ, NCH = S::NCH, NR = S::NR, NOFF = S::NOFF;
+    constexpr int NV = S::NV, NQ = S::NQ, NCH = S::NCH, NR = S::NR;
+    using Acc = typename std::conditional<PREC == 0, PlainAcc<DIM, ETA>, MixedAcc<DIM, ETA>>::type;
+    using Real = typename std::conditional<PREC == 0, double, float>::type;
+    using WM = WaveMem<DIM, PREC>;
     const int lane = lane_id();
     const int64_t ne = A.ne;
+    l = uniform(l);
+    m = uniform(m);
     char *work = wmem;
-    uint32_t *leafbuf = reinterpret_cast<uint32_t *>(wmem + WaveMem<DIM, PREC>::kWorkBytes);
+    double *HQ = reinterpret_cast<double *>(wmem + WM::kStageBytes);   // [NR][16]
+    double *tile = HQ + NR * 16;                                       // 256 doubles (mixed)
+    uint32_t *leafbuf = reinterpret_cast<uint32_t *>(wmem + WM::kStageBytes + WM::kEpiBytes);
     uint32_t *listA = leafbuf + kLeafCap;
     uint32_t *listB = listA + A.capl;
 
-    // geometry of l (root simplex) and m
+    // geometry of l (root simplex) and m: wave-uniform
     Simplex<DIM> root;
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int k = 0; k < DIM; ++k) root.v[v][k] = A.vert[(v * DIM + k) * ne + l];
-    double mlo[DIM], mhi[DIM], Vm[NV][DIM];
+    double mlo[DIM], mhi[DIM];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
         mlo[k] = A.lo[k * ne + m];
         mhi[k] = A.hi[k * ne + m];
     }
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) Vm[v][k] = A.vert[(v * DIM + k) * ne + m];
-    const double meas_l = A.meas[l], meas_m = A.meas[m];
     const double *bary = s_rule;
     const double *wq = s_rule + NQ * NV;
 
     // inner point of this lane, relative to the anchor v0(l)
     int bsel;
-    if (PREC == 0) bsel = lane % PlainAcc<DIM>::NYP;
+    if (PREC == 0) bsel = lane % PlainAcc<DIM, ETA>::NYP;
     else bsel = DIM == 2 ? (lane & 7) : (lane & 15);
     const int bq = bsel < NQ ? bsel : 0;
     double y[DIM];
@@ -425,97 +562,75 @@ __device__ void process_pair(const AsmArgs &A, int64_t l, int32_t m, char *wmem,
     for (int k = 0; k < DIM; ++k) {
         double s = 0.0;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) s = fma(bary[bq * NV + v], Vm[v][k], s);
+        for (int v = 0; v < NV; ++v) s = fma(bary[bq * NV + v], A.vert[(v * DIM + k) * ne + m], s);
         y[k] = s - root.v[0][k];
     }
-    double E[DIM][DIM];   // edges v_i - v_0 of l
+    Edges<DIM, Real> E;   // edges v_i - v_0 of l
 #pragma unroll
     for (int i = 1; i <= DIM; ++i)
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) E[i - 1][k] = root.v[i][k] - root.v[0][k];
+        for (int k = 0; k < DIM; ++k) E.e[i - 1][k] = static_cast<Real>(root.v[i][k] - root.v[0][k]);
 
-    typename std::conditional<PREC == 0, PlainAcc<DIM>, MixedAcc<DIM>>::type acc;
-    acc.init(y);
-    if constexpr (PREC == 0) acc.active = bsel < NQ;
+    Acc acc;
+    acc.init(y, lane, work);
 
     // integrate the leaves in leafbuf[0..nleaf)
     auto integrate = [&](int nleaf) {
-        const int npts_total = nleaf * NQ;
-        for (int p0 = 0; p0 < npts_total; p0 += kBatch) {
+        const int total = nleaf * NQ;
+        auto fetch = [&](int p0) {
             const int p = p0 + lane;
-            const bool valid = p < npts_total;
-            double xh[DIM], P[NR];
+            const bool valid = p < total;
+            int a = 0, lev = 1, sub = 0;
             if (valid) {
-                const int q = p / NQ, a = p - q * NQ;
+                const int q = p / NQ;
+                a = p - q * NQ;
                 const uint32_t ent = leafbuf[q];
-                const int lev = static_cast<int>(ent >> 24);
-                const uint32_t local = ent & 0xFFFFFFu;
-                const int64_t sub = A.lvl_off[lev] + local;
-                const double *lam = A.lam64 + (sub * NQ + a) * NV;
-                double lm[NV];
-#pragma unroll
-                for (int i = 0; i < NV; ++i) lm[i] = lam[i];
-                const double wl = ldexp(wq[a], -DIM * (lev - 1));
-#pragma unroll
-                for (int k = 0; k < DIM; ++k) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int i = 1; i <= DIM; ++i) s = fma(lm[i], E[i - 1][k], s);
-                    xh[k] = s;
-                }
-#pragma unroll
-                for (int i = 0; i < NV; ++i) P[i] = wl * lm[i];
-                int r = NV;
-#pragma unroll
-                for (int i = 0; i < NV; ++i)
-#pragma unroll
-                    for (int j = i + 1; j < NV; ++j) P[r++] = wl * lm[i] * lm[j];
-            } else {
-#pragma unroll
-                for (int k = 0; k < DIM; ++k) xh[k] = 0.0;
-#pragma unroll
-                for (int r = 0; r < NR; ++r) P[r] = 0.0;
+                lev = static_cast<int>(ent >> 24);
+                sub = static_cast<int>(ent & 0xFFFFFFu);
             }
+            return Acc::fetch(A, valid, sub, a, lev, s_w32[a], wq[a]);
+        };
+        auto in = fetch(0);
+        for (int p0 = 0; p0 < total; p0 += kBatch) {
             wave_sync();
-            decltype(acc)::stage(work, lane, valid, xh, P);
+            Acc::stage(work, lane, in, E);
             wave_sync();
-            const int cnt = npts_total - p0 < kBatch ? npts_total - p0 : kBatch;
-            acc.run(A, work, cnt);
+            if (p0 + kBatch < total) in = fetch(p0 + kBatch);
+            acc.run(A, work, total - p0 < kBatch ? total - p0 : kBatch);
         }
     };
 
     // ---- Algorithm 1, level by level (per pair: J = {m}) -------------------
+    // Leaves accumulate in leafbuf and are integrated when it fills and once at
+    // the end, so batches stay full across levels.
     int nleaf = 0;
     uint32_t *cur = listA, *nxt = listB;
     int ncur = 1;
     if (lane == 0) cur[0] = 0u;
     wave_sync();
-    auto flush = [&]() {
-        if (nleaf > 0) {
-            integrate(nleaf);
-            nleaf = 0;
-        }
-    };
     auto push_leaf = [&](bool take, uint32_t ent) {
         const unsigned long long mask = wave_ballot(take);
         const int c = __popcll(mask);
         if (c == 0) return;
-        if (nleaf + c > kLeafCap) flush();
+        if (nleaf + c > kLeafCap) {
+            integrate(nleaf);
+            nleaf = 0;
+        }
+        wave_sync();
         if (take) leafbuf[nleaf + lanes_below(mask)] = ent;
         nleaf += c;
         wave_sync();
     };
     for (int lev = 1;; ++lev) {
+        const int off = A.lvl_off[lev];
         if (lev == A.lmax) {
             // every node of this level is integrated (no classification at L_max)
             for (int i0 = 0; i0 < ncur; i0 += kWave) {
                 const int i = i0 + lane;
                 const bool take = i < ncur;
-                const uint32_t ent = take ? ((static_cast<uint32_t>(lev) << 24) | cur[i]) : 0u;
-                push_leaf(take, ent);
+                push_leaf(take, take ? leaf_entry(lev, off + static_cast<int>(cur[i])) : 0u);
             }
             if (lane == 0 && s_leaf) atomicAdd(&s_leaf[lev], static_cast<unsigned long long>(ncur));
-            flush();
             break;
         }
         const bool last_split = (lev + 1 == A.lmax);
@@ -538,26 +653,23 @@ __device__ void process_pair(const AsmArgs &A, int64_t l, int32_t m, char *wmem,
                 }
             }
             nn += __popcll(mref);
-            const unsigned long long mint = wave_ballot(cls == 1);
-            nint += __popcll(mint);
-            push_leaf(cls == 1, (static_cast<uint32_t>(lev) << 24) | local);
+            nint += __popcll(wave_ballot(cls == 1));
+            push_leaf(cls == 1, leaf_entry(lev, off + static_cast<int>(local)));
         }
         if (lane == 0 && s_leaf && nint) atomicAdd(&s_leaf[lev], static_cast<unsigned long long>(nint));
-        flush();
         wave_sync();
         if (nn == 0) break;
         if (last_split) {
             // children of the refined nodes are the level-L_max leaves
+            const int offn = A.lvl_off[lev + 1];
             const int nl = nn * NCH;
             for (int i0 = 0; i0 < nl; i0 += kWave) {
                 const int i = i0 + lane;
                 const bool take = i < nl;
-                const uint32_t ent =
-                    take ? ((static_cast<uint32_t>(lev + 1) << 24) | (nxt[i / NCH] * NCH + (i % NCH))) : 0u;
-                push_leaf(take, ent);
+                const int sub = take ? offn + static_cast<int>(nxt[i / NCH] * NCH + (i % NCH)) : 0;
+                push_leaf(take, leaf_entry(lev + 1, sub));
             }
             if (lane == 0 && s_leaf) atomicAdd(&s_leaf[lev + 1], static_cast<unsigned long long>(nl));
-            flush();
             break;
         }
         uint32_t *t = cur;
@@ -565,18 +677,13 @@ __device__ void process_pair(const AsmArgs &A, int64_t l, int32_t m, char *wmem,
         nxt = t;
         ncur = nn * NCH;
     }
+    if (nleaf > 0) integrate(nleaf);
 
     // ---- epilogue (FP64) ----------------------------------------------------
     wave_sync();
-    double *HQ = reinterpret_cast<double *>(work);   // [NR][16]
-    if constexpr (PREC == 0) {
-        acc.finish(HQ);
-    } else {
-        double *tile = reinterpret_cast<double *>(work) + NR * 16;   // 256 doubles
-        acc.finish(HQ, tile);
-    }
+    acc.finish(HQ, tile);
     wave_sync();
-    const double Sc = A.C * meas_l * meas_m;
+    const double Sc = A.C * A.meas[l] * A.meas[m];
     // lanes 0..NV*NV-1: B_lm; NV*NV..2NV*NV-1: B_mm; 2NV*NV..3NV*NV-1: B_ll
     const int t = lane;
     const int blk = t / (NV * NV), ij = t % (NV * NV);
@@ -601,21 +708,20 @@ __device__ void process_pair(const AsmArgs &A, int64_t l, int32_t m, char *wmem,
         } else {
             double h = 0.0;
             for (int b = 0; b < NQ; ++b) h += HQ[i * 16 + b] * wq[b];
-            double off = 0.0;
+            double offd = 0.0;
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
                 if (q == i) continue;
                 const int r = offrow<NV>(i < q ? i : q, i < q ? q : i);
                 double s2 = 0.0;
                 for (int b = 0; b < NQ; ++b) s2 += HQ[r * 16 + b] * wq[b];
-                off += s2;
+                offd += s2;
             }
-            v = Sc * (h - off);
+            v = Sc * (h - offd);
         }
     }
-    (void)NOFF;
     const bool four = A.form == NLQ_FORM_SYM4;
-    if (explicit_mode) {
+    if (ex_block) {
         constexpr int N2 = 2 * NV;
         if (blk == 0) {
             ex_block[i * N2 + NV + j] = four ? v : 0.0;
@@ -627,17 +733,12 @@ __device__ void process_pair(const AsmArgs &A, int64_t l, int32_t m, char *wmem,
         }
         return;
     }
-    const int32_t li = A.conn[l * NV + i], mj = A.conn[static_cast<int64_t>(m) * NV + j];
     if (blk == 0) {
-        // B_lm at (l_i, m_j); its transpose B_ml at (m_j, l_i)
-        int64_t a0 = A.row_ptr[li], a1 = A.row_ptr[li + 1] - 1, pos = -1;
-        while (a0 <= a1) {
-            const int64_t mid = (a0 + a1) >> 1;
-            const int32_t cv = A.col[mid];
-            if (cv == mj) { pos = mid; break; }
-            if (cv < mj) a0 = mid + 1; else a1 = mid - 1;
-        }
-        if (pos >= 0) {
+        // B_lm at (l_i, m_j) via the cached row of l_i; B_ml at its transpose
+        const int32_t mj = A.conn[static_cast<int64_t>(m) * NV + j];
+        const int64_t at = search(rc->cols[i], rc->len[i], mj);
+        if (at >= 0) {
+            const int64_t pos = rc->base[i] + at;
             if (four) unsafeAtomicAdd(&A.val[pos], v);
             unsafeAtomicAdd(&A.val[A.tmap[pos]], four ? v : 2.0 * v);
         }
@@ -652,6 +753,13 @@ __device__ void process_pair(const AsmArgs &A, int64_t l, int32_t m, char *wmem,
 // -------------------------------------------------------------- kernels
 
 template <int DIM, int PREC>
+__device__ void wave_setup(char *wmem)
+{
+    if constexpr (PREC == 1) MixedAcc<DIM, 0>::zero_padding(wmem);
+    wave_sync();
+}
+
+template <int DIM, int PREC, int ETA>
 __global__ void __launch_bounds__(kThreads)
 k_integrate(AsmArgs A)
 {
@@ -659,14 +767,19 @@ k_integrate(AsmArgs A)
     constexpr int NV = S::NV, NQ = S::NQ;
     extern __shared__ __align__(16) char smem[];
     __shared__ double s_rule[NQ * NV + NQ];
+    __shared__ float s_w32[16];
     __shared__ double s_bll[NV * NV];
     __shared__ int64_t s_item;
     __shared__ int s_next;
     __shared__ unsigned long long s_leaf[10];
+    __shared__ RowCache s_rc;
     const int wid = threadIdx.x / kWave;
     char *wmem = smem + wid * WaveMem<DIM, PREC>::bytes(A.capl);
+    int32_t *rows_lds = reinterpret_cast<int32_t *>(smem + kWaves * WaveMem<DIM, PREC>::bytes(A.capl));
     for (int t = threadIdx.x; t < NQ * NV + NQ; t += kThreads) s_rule[t] = A.rule[t];
+    if (threadIdx.x < NQ) s_w32[threadIdx.x] = static_cast<float>(A.rule[NQ * NV + threadIdx.x]);
     if (threadIdx.x < 10) s_leaf[threadIdx.x] = 0ull;
+    wave_setup<DIM, PREC>(wmem);
     unsigned long long pairs_done = 0;
     for (;;) {
         if (threadIdx.x == 0) {
@@ -677,6 +790,21 @@ k_integrate(AsmArgs A)
         __syncthreads();
         const int64_t l = s_item;
         if (l >= A.ne) break;
+        // stage the CSR rows of l's nodes
+        if (threadIdx.x < NV) {
+            const int32_t node = A.conn[l * NV + threadIdx.x];
+            const int64_t b = A.row_ptr[node], len = A.row_ptr[node + 1] - b;
+            s_rc.base[threadIdx.x] = b;
+            s_rc.len[threadIdx.x] = len;
+            s_rc.cols[threadIdx.x] = len <= A.rowcap ? rows_lds + threadIdx.x * A.rowcap : A.col + b;
+        }
+        __syncthreads();
+        for (int r = 0; r < NV; ++r) {
+            if (s_rc.len[r] > A.rowcap) continue;
+            for (int64_t k = threadIdx.x; k < s_rc.len[r]; k += kThreads)
+                rows_lds[r * A.rowcap + k] = A.col[s_rc.base[r] + k];
+        }
+        __syncthreads();
         const int64_t b0 = A.pair_off[l];
         const int nJ = static_cast<int>(A.pair_off[l + 1] - b0);
         for (;;) {
@@ -685,7 +813,8 @@ k_integrate(AsmArgs A)
             p = bcast0(p);
             if (p >= nJ) break;
             const int32_t m = A.pair_m[b0 + p];
-            process_pair<DIM, PREC>(A, l, m, wmem, s_rule, s_bll, false, nullptr, s_leaf);
+            process_pair<DIM, PREC, ETA>(A, static_cast<int>(l), m, wmem, s_rule, s_w32, s_bll, &s_rc,
+                                         nullptr, s_leaf);
             ++pairs_done;
         }
         __syncthreads();
@@ -700,7 +829,7 @@ k_integrate(AsmArgs A)
 
 // explicit pairs: every wave takes pairs from the global counter and writes the
 // extended block [2N+2][2N+2] of each
-template <int DIM, int PREC>
+template <int DIM, int PREC, int ETA>
 __global__ void __launch_bounds__(kThreads)
 k_pair_blocks(AsmArgs A)
 {
@@ -708,9 +837,12 @@ k_pair_blocks(AsmArgs A)
     constexpr int NV = S::NV, NQ = S::NQ;
     extern __shared__ __align__(16) char smem[];
     __shared__ double s_rule[NQ * NV + NQ];
+    __shared__ float s_w32[16];
     const int wid = threadIdx.x / kWave;
     char *wmem = smem + wid * WaveMem<DIM, PREC>::bytes(A.capl);
     for (int t = threadIdx.x; t < NQ * NV + NQ; t += kThreads) s_rule[t] = A.rule[t];
+    if (threadIdx.x < NQ) s_w32[threadIdx.x] = static_cast<float>(A.rule[NQ * NV + threadIdx.x]);
+    wave_setup<DIM, PREC>(wmem);
     __syncthreads();
     for (;;) {
         unsigned int it = 0;
@@ -720,16 +852,18 @@ k_pair_blocks(AsmArgs A)
         double *blk = A.ex_out + static_cast<int64_t>(it) * (2 * NV) * (2 * NV);
         for (int t = lane_id(); t < 4 * NV * NV; t += kWave) blk[t] = 0.0;
         wave_sync();
-        process_pair<DIM, PREC>(A, A.ex_l[it], A.ex_m[it], wmem, s_rule, nullptr, true, blk,
-                                nullptr);
+        process_pair<DIM, PREC, ETA>(A, A.ex_l[it], A.ex_m[it], wmem, s_rule, s_w32, nullptr, nullptr,
+                                     blk, nullptr);
     }
 }
 
-template <int DIM, int PREC> void launch_one(System &s, AsmArgs &A, hipStream_t st, bool explicit_mode)
+template <int DIM, int PREC, int ETA>
+void launch_one(System &s, AsmArgs &A, hipStream_t st, bool explicit_mode, hipEvent_t e0, hipEvent_t e1)
 {
-    const int lds = kWaves * WaveMem<DIM, PREC>::bytes(A.capl);
+    const int per_wave = WaveMem<DIM, PREC>::bytes(A.capl);
+    const int lds = kWaves * per_wave + (explicit_mode ? 0 : (DIM + 1) * A.rowcap * 4);
     if (lds > 150 * 1024) fail(NLQ_EINVAL, "lmax too large for the per-wave refinement lists");
-    auto kern = explicit_mode ? k_pair_blocks<DIM, PREC> : k_integrate<DIM, PREC>;
+    auto kern = explicit_mode ? k_pair_blocks<DIM, PREC, ETA> : k_integrate<DIM, PREC, ETA>;
     NLQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     int per_cu = 0;
@@ -739,17 +873,28 @@ template <int DIM, int PREC> void launch_one(System &s, AsmArgs &A, hipStream_t 
     const int64_t items = explicit_mode ? A.n_explicit : A.ne;
     if (grid > items) grid = items;
     if (grid < 1) grid = 1;
+    if (e0) NLQ_HIP(hipEventRecord(e0, st));
     hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(kThreads), lds, st, A);
     NLQ_CHECK_LAUNCH();
+    if (e1) NLQ_HIP(hipEventRecord(e1, st));
+}
+
+template <int DIM, int PREC>
+void launch_eta(System &s, AsmArgs &A, hipStream_t st, bool ex, hipEvent_t e0, hipEvent_t e1)
+{
+    if (s.p.kernel == NLQ_ETA_GAUSS) launch_one<DIM, PREC, NLQ_ETA_GAUSS>(s, A, st, ex, e0, e1);
+    else launch_one<DIM, PREC, NLQ_ETA_CONST>(s, A, st, ex, e0, e1);
 }
 
 }  // namespace
 
 void launch_integrate(System &s, hipStream_t st, int64_t n_explicit, const int32_t *ex_l,
-                      const int32_t *ex_m, double *ex_out)
+                      const int32_t *ex_m, double *ex_out, hipEvent_t e0, hipEvent_t e1)
 {
     const Mesh &m = *s.mesh;
     const Tables &T = s.ctx->get_tables(m.dim, s.p.lmax);
+    if (T.n_sub * T.nq * T.nv >= (int64_t(1) << 31) || T.n_sub >= (1 << 24))
+        fail(NLQ_EINVAL, "refinement table too large");
     AsmArgs A{};
     A.ne = m.n_elems;
     A.pair_off = s.pair_off.as<int64_t>();
@@ -767,7 +912,8 @@ void launch_integrate(System &s, hipStream_t st, int64_t n_explicit, const int32
     A.lam64 = T.lam64.as<double>();
     A.lam32 = T.lam32.as<float>();
     A.rule = T.rule.as<double>();
-    for (int q = 0; q < 10; ++q) A.lvl_off[q] = q < static_cast<int>(T.lvl_off.size()) ? T.lvl_off[q] : 0;
+    for (int q = 0; q < 10; ++q)
+        A.lvl_off[q] = q < static_cast<int>(T.lvl_off.size()) ? static_cast<int>(T.lvl_off[q]) : 0;
     A.delta = s.p.delta;
     A.eps = s.p.eps;
     A.dme = s.p.delta - s.p.eps;
@@ -781,13 +927,14 @@ void launch_integrate(System &s, hipStream_t st, int64_t n_explicit, const int32
     A.f_dme2 = static_cast<float>(A.dme * A.dme);
     A.f_dpe2 = static_cast<float>(A.dpe * A.dpe);
     A.f_inv_delta2 = static_cast<float>(1.0 / (s.p.delta * s.p.delta));
-    A.kernel = s.p.kernel;
     A.lmin = s.p.lmin;
     A.lmax = s.p.lmax;
     A.form = s.p.form;
     int capl = 1;
     for (int q = 0; q < s.p.lmax - 2; ++q) capl *= (1 << m.dim);
     A.capl = capl;
+    // LDS row cache: as long as the longest row, at most 2048 entries per row
+    A.rowcap = static_cast<int>(std::min<int64_t>(std::max<int64_t>(s.max_row, 1), 2048));
     A.counter = s.l_counter.as<unsigned int>();
     A.counters = s.counters.as<AsmCounters>();
     A.n_explicit = n_explicit;
@@ -801,11 +948,11 @@ void launch_integrate(System &s, hipStream_t st, int64_t n_explicit, const int32
         NLQ_HIP(hipMemsetAsync(A.val, 0, sizeof(double) * s.nnz, st));
     }
     if (m.dim == 2) {
-        if (s.p.precision == NLQ_FP64_PLAIN) launch_one<2, 0>(s, A, st, ex);
-        else launch_one<2, 1>(s, A, st, ex);
+        if (s.p.precision == NLQ_FP64_PLAIN) launch_eta<2, 0>(s, A, st, ex, e0, e1);
+        else launch_eta<2, 1>(s, A, st, ex, e0, e1);
     } else {
-        if (s.p.precision == NLQ_FP64_PLAIN) launch_one<3, 0>(s, A, st, ex);
-        else launch_one<3, 1>(s, A, st, ex);
+        if (s.p.precision == NLQ_FP64_PLAIN) launch_eta<3, 0>(s, A, st, ex, e0, e1);
+        else launch_eta<3, 1>(s, A, st, ex, e0, e1);
     }
 }
 

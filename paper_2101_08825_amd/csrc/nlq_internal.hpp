@@ -129,7 +129,7 @@ struct System {
     const Mesh *mesh = nullptr;
     nlq_params p{};
     double C = 0.0;              // kernel constant
-    int64_t n_pairs = 0, nnz = 0;
+    int64_t n_pairs = 0, nnz = 0, max_row = 0;
     // element tables
     DevBuf vert;                 // [nv*dim][ne] SoA double
     DevBuf lo, hi;               // [dim][ne]
@@ -157,7 +157,8 @@ void launch_elem_tables(System &s, hipStream_t st);
 void build_pairs(System &s, hipStream_t st);
 void build_pattern(System &s, hipStream_t st);
 void launch_integrate(System &s, hipStream_t st, int64_t n_explicit, const int32_t *ex_l,
-                      const int32_t *ex_m, double *ex_out);
+                      const int32_t *ex_m, double *ex_out, hipEvent_t ev_start = nullptr,
+                      hipEvent_t ev_stop = nullptr);
 void launch_load_lift(System &s, hipStream_t st, const double *f_dev, const double *g_dev);
 int cg_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, int *converged);
 void launch_box_mesh(int dim, int n, int k_gamma, double *coords, int32_t *conn,

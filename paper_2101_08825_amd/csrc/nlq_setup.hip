@@ -612,7 +612,13 @@ void build_pattern(System &s, hipStream_t st)
     exclusive_scan_i64(s.ctx, row_cnt.as<int64_t>(), s.row_ptr.as<int64_t>(), nn + 1, st);
     NLQ_HIP(hipMemcpyAsync(&s.nnz, s.row_ptr.as<int64_t>() + nn, sizeof(int64_t),
                            hipMemcpyDeviceToHost, st));
-    NLQ_HIP(hipStreamSynchronize(st));
+    {
+        std::vector<int64_t> cnt(nn);
+        NLQ_HIP(hipMemcpyAsync(cnt.data(), row_cnt.as<void>(), sizeof(int64_t) * nn,
+                               hipMemcpyDeviceToHost, st));
+        NLQ_HIP(hipStreamSynchronize(st));
+        s.max_row = nn > 0 ? *std::max_element(cnt.begin(), cnt.end()) : 0;
+    }
     if (s.nnz > INT32_MAX) fail(NLQ_EINVAL, "more than 2^31 stored entries");
     s.col.alloc(s.ctx, sizeof(int32_t) * std::max<int64_t>(s.nnz, 1));
     hipLaunchKernelGGL(k_rows, dim3(nn), dim3(kWave), 0, st, nn, ne_off.as<int64_t>(),

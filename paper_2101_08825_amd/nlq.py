@@ -28,7 +28,8 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTREA
 EXPORTS = [
     "nlq_ctx_create", "nlq_ctx_set_stream", "nlq_ctx_memory", "nlq_ctx_destroy",
     "nlq_mesh_create", "nlq_mesh_box", "nlq_mesh_info", "nlq_mesh_copy", "nlq_mesh_destroy",
-    "nlq_assemble", "nlq_assemble_info_get", "nlq_reassemble", "nlq_set_data", "nlq_solve",
+    "nlq_assemble", "nlq_assemble_info_get", "nlq_reassemble", "nlq_set_data",
+    "nlq_set_data_device", "nlq_solve", "nlq_solution_device",
     "nlq_info", "nlq_csr_copy", "nlq_csr_device", "nlq_pairs_copy", "nlq_rhs_copy",
     "nlq_pair_blocks", "nlq_system_destroy", "nlq_serve_start", "nlq_submit", "nlq_wait",
     "nlq_cancel", "nlq_result_release", "nlq_serve_stop", "nlq_last_error",
@@ -51,7 +52,8 @@ class nlq_params(C.Structure):
 class nlq_assemble_info(C.Structure):
     _fields_ = [("n_pairs", C.c_int64), ("n_leaf", C.c_int64 * 9), ("n_evals", C.c_int64),
                 ("nnz", C.c_int64), ("t_tables", C.c_double), ("t_pairs", C.c_double),
-                ("t_pattern", C.c_double), ("t_integrate", C.c_double), ("t_total", C.c_double)]
+                ("t_pattern", C.c_double), ("t_integrate", C.c_double), ("t_total", C.c_double),
+                ("t_kernel", C.c_double)]
 
 
 class nlq_solve_info(C.Structure):
@@ -98,7 +100,9 @@ def lib():
             "nlq_assemble_info_get": [vp, P(nlq_assemble_info)],
             "nlq_reassemble": [vp],
             "nlq_set_data": [vp, vp, vp],
+            "nlq_set_data_device": [vp, vp, vp],
             "nlq_solve": [vp, d, i32, vp, P(nlq_solve_info)],
+            "nlq_solution_device": [vp, P(vp)],
             "nlq_info": [vp, P(i64), P(i64), P(i64), P(i64)],
             "nlq_csr_copy": [vp, vp, vp, vp],
             "nlq_csr_device": [vp, P(vp), P(vp), P(vp)],
@@ -249,13 +253,22 @@ class System:
         g = np.ascontiguousarray(g_nodal, dtype=np.float64)
         _check(lib().nlq_set_data(self.h, _ptr(f), _ptr(g)))
 
-    def solve(self, rtol=1e-12, maxit=20000):
-        u = np.zeros(self.mesh.n_nodes)
+    def set_data_device(self, f_ptr: int, g_ptr: int):
+        """f, g as device pointers (e.g. torch.Tensor.data_ptr() of float64 tensors)."""
+        _check(lib().nlq_set_data_device(self.h, C.c_void_p(f_ptr), C.c_void_p(g_ptr)))
+
+    def solve(self, rtol=1e-12, maxit=20000, copy=True):
+        u = np.zeros(self.mesh.n_nodes) if copy else None
         inf = nlq_solve_info()
         st = lib().nlq_solve(self.h, float(rtol), int(maxit), _ptr(u), C.byref(inf))
         if st not in (NLQ_OK, NLQ_ENOCONV):
             _check(st)
         return u, inf
+
+    def solution_device(self) -> int:
+        p = C.c_void_p()
+        _check(lib().nlq_solution_device(self.h, C.byref(p)))
+        return p.value or 0
 
     def csr(self):
         s = self.sizes()
