@@ -75,7 +75,7 @@ def run_steps(nlq, ctx, setups, precision, steps, warmup, torch):
                 evals=evals_per_step)
 
 
-def cpu_baseline(sample_frac=0.01, seed=0):
+def cpu_baseline(sample_frac=0.10, seed=0):
     """The oracle on a seeded sample of outer elements of both problems."""
     import oracle
     nt = max(1, min(16, os.cpu_count() or 1))
