@@ -381,6 +381,8 @@ nlq_status nlq_assemble(nlq_ctx *ctx, const nlq_mesh *mesh, const nlq_params *pa
         const double t2 = now_s();
         build_pattern(s, st);
         s.val.alloc(s.ctx, sizeof(double) * std::max<int64_t>(s.nnz, 1));
+        const int nr = s.mesh->dim == 2 ? 6 : 10;
+        s.dmm.alloc(s.ctx, sizeof(double) * std::max<int64_t>(s.mesh->n_elems * nr, 1));
         NLQ_HIP(hipStreamSynchronize(st));
         const double t3 = now_s();
         run_integrate(s, st);

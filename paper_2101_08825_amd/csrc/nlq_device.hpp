@@ -59,9 +59,12 @@ template <class T> __device__ __forceinline__ T wave_incl_scan(T v)
 // 1 is reproducible bit for bit.
 //   aprx max = sqrt(sum_k max(d1_k^2, d2_k^2)),  aprx min = max_k max(0, d1_k, d2_k),
 //   d1 = x_min - y_max, d2 = y_min - x_max.
+// The square of aprx max is returned without the root: the caller compares it
+// with the exact threshold s* = min{s : fl(sqrt(s)) >= t}, which decides
+// fl(sqrt(s)) < t identically because the rounded root is monotone.
 template <int DIM>
-__device__ __forceinline__ double aprx_max_dist(const double *lo1, const double *hi1,
-                                                const double *lo2, const double *hi2)
+__device__ __forceinline__ double aprx_max_sq(const double *lo1, const double *hi1,
+                                              const double *lo2, const double *hi2)
 {
     double s = 0.0;
 #pragma unroll
@@ -71,7 +74,7 @@ __device__ __forceinline__ double aprx_max_dist(const double *lo1, const double 
         double a = __dmul_rn(d1, d1), b = __dmul_rn(d2, d2);
         s = __dadd_rn(s, a > b ? a : b);
     }
-    return __dsqrt_rn(s);
+    return s;
 }
 
 template <int DIM>

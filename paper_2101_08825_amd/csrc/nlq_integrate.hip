@@ -28,9 +28,16 @@
 //       B_lm[i][j] = -S sum_b H_ib w_b psi_j(y_b)
 //       B_mm[i][j] =  S sum_b w_b psi_i psi_j sum_i' H_i'b
 //       B_ll[i][j] =  S sum_b Q_(ij)b w_b  (i != j),
-//       B_ll[i][i] =  S sum_b H_ib w_b - sum_{j != i} B_ll[i][j]
-//     (partition of unity: lambda_i = sum_j lambda_i lambda_j), then FP64
-//     atomics into the CSR values; B_ll is summed per outer element in LDS.
+//       B_ll[i][i] =  S sum_b (H_ib - sum_{j != i} Q_(ij)b) w_b
+//     (partition of unity: lambda_i^2 = lambda_i - sum_{j != i} lambda_i lambda_j),
+//     one output per lane as a dot product over b with a constant row;
+//   * accumulation (FP64): SYM4 blocks are symmetric and B_ml = B_lm^T, so the
+//     launch builds a half matrix R with A = R + R^T: B_lm goes to (l_i, m_j)
+//     through the LDS-cached row of l_i, the upper triangles of B_mm (per pair)
+//     and B_ll (per outer element, summed in LDS) go to a per-element array;
+//     a fold pass adds that array to R and a last pass forms R + R^T in place,
+//     which makes A symmetric bit for bit.  The two-term form writes its
+//     entries where they belong and skips the last pass.
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
@@ -47,6 +54,8 @@ constexpr int kWaves = 4;
 constexpr int kThreads = kWaves * kWave;
 constexpr int kLeafCap = 128;
 constexpr int kBatch = 64;
+// waves per SIMD requested from the register allocator (measured optimum)
+template <int DIM> constexpr int waves_per_eu() { return DIM == 2 ? 5 : 3; }
 
 template <int DIM> struct Shape {
     static constexpr int NV = DIM + 1;
@@ -75,6 +84,8 @@ struct AsmArgs {
     const double *rule;   // [nq][nv] barycentric points, then [nq] weights
     int lvl_off[10];
     double delta, eps, dme, dpe, dme2, dpe2, C;
+    double dme_sq;        // s* with (sqrt(s) < delta - eps) <=> (s < s*), s >= 0
+    double *dmm;          // [ne][NR] upper-triangle diagonal-block sums per element
     float f_delta, f_inv_eps, f_delta_over_eps, f_dme2, f_dpe2, f_inv_delta2;
     int lmin, lmax, form;
     int capl;
@@ -217,7 +228,7 @@ __device__ __forceinline__ int classify(const AsmArgs &A, const Simplex<DIM> &ro
         slo[k] = a;
         shi[k] = b;
     }
-    if (aprx_max_dist<DIM>(slo, shi, mlo, mhi) < A.dme) return 1;
+    if (aprx_max_sq<DIM>(slo, shi, mlo, mhi) < A.dme_sq) return 1;
     if (aprx_min_dist<DIM>(slo, shi, mlo, mhi) < A.dpe) return 2;
     return 0;
 }
@@ -465,15 +476,12 @@ template <int DIM, int ETA> struct MixedAcc {
 #pragma unroll
         for (int r = 0; r < 4; ++r) tile[(ib + r) * 16 + j] = dacc[r];
         wave_sync();
-        for (int t = l; t < S::NR * 16; t += kWave) {
-            const int r = t >> 4, b = t & 15;
-            double v = 0.0;
-            if (DIM == 2) {
-                if (b < S::NQ) v = tile[r * 16 + b] + tile[(r + 8) * 16 + (b + 8)];
-            } else {
-                if (b < S::NQ) v = tile[r * 16 + b];
-            }
-            out[t] = v;
+        // padding columns hold gamma = 0, so their totals are 0 as well
+        constexpr int BW = DIM == 2 ? 8 : 16;
+        for (int t = l; t < S::NR * BW; t += kWave) {
+            const int r = t / BW, b = t % BW;
+            const double v = DIM == 2 ? tile[r * 16 + b] + tile[(r + 8) * 16 + (b + 8)] : tile[r * 16 + b];
+            out[r * 16 + b] = v;
         }
     }
 };
@@ -483,7 +491,8 @@ template <int DIM, int PREC> struct WaveMem {
     using S = Shape<DIM>;
     static constexpr int kStageBytes =
         PREC == 0 ? PlainAcc<DIM, 0>::kStageBytes : MixedAcc<DIM, 0>::kStageBytes;
-    static constexpr int kEpiBytes = (S::NR * 16 + (PREC == 1 ? 256 : 0)) * 8;
+    static constexpr int kEpiRows = S::NR + 1 + S::NV;   // H/Q rows + column sums + diagonal rows
+    static constexpr int kEpiBytes = (kEpiRows * 16 + (PREC == 1 ? 256 : 0)) * 8;
     __host__ __device__ static int bytes(int capl)
     {
         return (kStageBytes + kEpiBytes + kLeafCap * 4 + 2 * capl * 4 + 15) & ~15;
@@ -514,12 +523,111 @@ template <int DIM, class Real> struct Edges {
     Real e[DIM][DIM];
 };
 
+// -------------------------------------------------------------- epilogue tables
+
+// Output kinds of the per-pair epilogue: B_lm entries, upper-triangle entries of
+// B_mm and of B_ll.
+constexpr int kOutNone = 0, kOutLM = 1, kOutMM = 2, kOutLL = 3;
+
+// (i, j), i <= j, of upper-triangle slot u: u < NV is the diagonal (u, u), the
+// others follow the numbering of the product rows lambda_i lambda_j.
+template <int NV> __host__ __device__ constexpr void pair_of(int u, int &i, int &j)
+{
+    i = j = u;
+    for (int a = 0; a < NV; ++a)
+        for (int c = a + 1; c < NV; ++c)
+            if (offrow<NV>(a, c) == u) {
+                i = a;
+                j = c;
+            }
+}
+
+// Constant rows (FP64, stride 16) over the inner points b:
+//   0..NV-1       w_b psi_j(y_b)                  (B_lm)
+//   NV..NV+NR-1   w_b psi_i(y_b) psi_j(y_b), i<=j  (B_mm, slot u)
+//   NV+NR         w_b                             (B_ll)
+// and one descriptor per lane: kind | x-row << 2 | t-row << 7 | i << 12 | j << 14 | u << 16.
+// x-rows index the extended H/Q rows: 0..NR-1 the totals, NR the column sums
+// sum_i H_i, NR+1+i the rows H_i - sum_{q != i} Q_iq (lambda_i^2 through the
+// partition of unity).
+template <int DIM>
+__device__ void epilogue_tables(const double *s_rule, double *s_T, int *s_desc)
+{
+    using S = Shape<DIM>;
+    constexpr int NV = S::NV, NQ = S::NQ, NR = S::NR;
+    const double *bary = s_rule;
+    const double *wq = s_rule + NQ * NV;
+    for (int t = threadIdx.x; t < (NV + NR + 1) * 16; t += kThreads) {
+        const int row = t >> 4, b = t & 15;
+        double v = 0.0;
+        if (b < NQ) {
+            if (row < NV) {
+                v = wq[b] * bary[b * NV + row];
+            } else if (row < NV + NR) {
+                int i, j;
+                pair_of<NV>(row - NV, i, j);
+                v = wq[b] * bary[b * NV + i] * bary[b * NV + j];
+            } else {
+                v = wq[b];
+            }
+        }
+        s_T[t] = v;
+    }
+    for (int o = threadIdx.x; o < kWave; o += kThreads) {
+        int kind = kOutNone, xr = 0, tr = 0, i = 0, j = 0, u = 0;
+        if (o < NV * NV) {
+            kind = kOutLM;
+            i = o / NV;
+            j = o % NV;
+            xr = i;
+            tr = j;
+        } else if (o < NV * NV + NR) {
+            kind = kOutMM;
+            u = o - NV * NV;
+            pair_of<NV>(u, i, j);
+            xr = NR;
+            tr = NV + u;
+        } else if (o < NV * NV + 2 * NR) {
+            kind = kOutLL;
+            u = o - NV * NV - NR;
+            pair_of<NV>(u, i, j);
+            xr = u < NV ? NR + 1 + u : u;
+            tr = NV + NR;
+        }
+        s_desc[o] = kind | (xr << 2) | (tr << 7) | (i << 12) | (j << 14) | (u << 16);
+    }
+}
+
+// rows NR (sum_i H_i) and NR+1+i (H_i - sum_{q != i} Q_iq) of the per-pair totals
+template <int DIM> __device__ __forceinline__ void extend_rows(double *HQ)
+{
+    using S = Shape<DIM>;
+    constexpr int NV = S::NV, NR = S::NR;
+    constexpr int BW = S::NQ <= 8 ? 8 : 16;
+    for (int t = lane_id(); t < (1 + NV) * BW; t += kWave) {
+        const int q = t / BW, b = t % BW;
+        double v;
+        if (q == 0) {
+            v = HQ[b];
+#pragma unroll
+            for (int r = 1; r < NV; ++r) v += HQ[r * 16 + b];
+        } else {
+            const int i = q - 1;
+            v = HQ[i * 16 + b];
+#pragma unroll
+            for (int c = 0; c < NV; ++c)
+                if (c != i) v -= HQ[offrow<NV>(i < c ? i : c, i < c ? c : i) * 16 + b];
+        }
+        HQ[(NR + q) * 16 + b] = v;
+    }
+}
+
 // -------------------------------------------------------------- one pair
 
 template <int DIM, int PREC, int ETA>
 __device__ void process_pair(const AsmArgs &A, int l, int m, char *wmem, const double *s_rule,
-                             const float *s_w32, double *s_bll, const RowCache *rc,
-                             double *ex_block, unsigned long long *s_leaf)
+                             const float *s_w32, const double *s_T, const int *s_desc, double *s_bll,
+                             const RowCache *rc, double *ex_block, unsigned long long *s_leaf)
 {
     using S = Shape<DIM>;
     constexpr int NV = S::NV, NQ = S::NQ, NCH = S::NCH, NR = S::NR;
@@ -551,6 +659,8 @@ __device__ void process_pair(const AsmArgs &A, int l, int m, char *wmem, const d
     }
     const double *bary = s_rule;
     const double *wq = s_rule + NQ * NV;
+    // node m_j of the epilogue's B_lm lane (lane = i * NV + j), read early
+    const int32_t mj = A.conn[static_cast<int64_t>(m) * NV + lane % NV];
 
     // inner point of this lane, relative to the anchor v0(l)
     int bsel;
@@ -683,70 +793,52 @@ __device__ void process_pair(const AsmArgs &A, int l, int m, char *wmem, const d
     wave_sync();
     acc.finish(HQ, tile);
     wave_sync();
-    const double Sc = A.C * A.meas[l] * A.meas[m];
-    // lanes 0..NV*NV-1: B_lm; NV*NV..2NV*NV-1: B_mm; 2NV*NV..3NV*NV-1: B_ll
-    const int t = lane;
-    const int blk = t / (NV * NV), ij = t % (NV * NV);
-    const int i = ij / NV, j = ij % NV;
+    extend_rows<DIM>(HQ);
+    wave_sync();
+    // every output is a dot product over the inner points b of one HQ row with
+    // one constant row of s_T; the lane's descriptor names both
+    const int desc = s_desc[lane];
+    const int kind = desc & 3;
+    const int xr = (desc >> 2) & 31, tr = (desc >> 7) & 31;
+    const int i = (desc >> 12) & 3, j = (desc >> 14) & 3, u = (desc >> 16) & 15;
     double v = 0.0;
-    if (blk == 0) {
-        for (int b = 0; b < NQ; ++b) v += HQ[i * 16 + b] * wq[b] * bary[b * NV + j];
-        v = -Sc * v;
-    } else if (blk == 1) {
-        for (int b = 0; b < NQ; ++b) {
-            double cb = 0.0;
+    {
+        const double *x = HQ + xr * 16;
+        const double *tt = s_T + tr * 16;
 #pragma unroll
-            for (int r = 0; r < NV; ++r) cb += HQ[r * 16 + b];
-            v += wq[b] * bary[b * NV + i] * bary[b * NV + j] * cb;
-        }
-        v = Sc * v;
-    } else if (blk == 2) {
-        if (i != j) {
-            const int r = offrow<NV>(i < j ? i : j, i < j ? j : i);
-            for (int b = 0; b < NQ; ++b) v += HQ[r * 16 + b] * wq[b];
-            v = Sc * v;
-        } else {
-            double h = 0.0;
-            for (int b = 0; b < NQ; ++b) h += HQ[i * 16 + b] * wq[b];
-            double offd = 0.0;
-#pragma unroll
-            for (int q = 0; q < NV; ++q) {
-                if (q == i) continue;
-                const int r = offrow<NV>(i < q ? i : q, i < q ? q : i);
-                double s2 = 0.0;
-                for (int b = 0; b < NQ; ++b) s2 += HQ[r * 16 + b] * wq[b];
-                offd += s2;
-            }
-            v = Sc * (h - offd);
-        }
+        for (int b = 0; b < NQ; ++b) v = fma(x[b], tt[b], v);
     }
+    const double Sc = A.C * A.meas[l] * A.meas[m];
+    v *= kind == kOutLM ? -Sc : Sc;
     const bool four = A.form == NLQ_FORM_SYM4;
     if (ex_block) {
         constexpr int N2 = 2 * NV;
-        if (blk == 0) {
+        if (kind == kOutLM) {
             ex_block[i * N2 + NV + j] = four ? v : 0.0;
             ex_block[(NV + j) * N2 + i] = four ? v : 2.0 * v;
-        } else if (blk == 1) {
+        } else if (kind == kOutMM) {
             ex_block[(NV + i) * N2 + NV + j] = four ? v : 2.0 * v;
-        } else if (blk == 2) {
+            ex_block[(NV + j) * N2 + NV + i] = four ? v : 2.0 * v;
+        } else if (kind == kOutLL) {
             ex_block[i * N2 + j] = four ? v : 0.0;
+            ex_block[j * N2 + i] = four ? v : 0.0;
         }
         return;
     }
-    if (blk == 0) {
-        // B_lm at (l_i, m_j) via the cached row of l_i; B_ml at its transpose
-        const int32_t mj = A.conn[static_cast<int64_t>(m) * NV + j];
+    if (kind == kOutLM) {
+        // B_lm at (l_i, m_j) through the cached row of l_i.  SYM4 adds it to the
+        // half matrix R (A = R + R^T afterwards); the two-term form puts 2 B_lm^T
+        // at (m_j, l_i) directly.
         const int64_t at = search(rc->cols[i], rc->len[i], mj);
         if (at >= 0) {
             const int64_t pos = rc->base[i] + at;
             if (four) unsafeAtomicAdd(&A.val[pos], v);
-            unsafeAtomicAdd(&A.val[A.tmap[pos]], four ? v : 2.0 * v);
+            else unsafeAtomicAdd(&A.val[A.tmap[pos]], 2.0 * v);
         }
-    } else if (blk == 1) {
-        unsafeAtomicAdd(&A.val[A.elpos[static_cast<int64_t>(m) * NV * NV + i * NV + j]],
-                        four ? v : 2.0 * v);
-    } else if (blk == 2) {
-        if (four) atomicAdd(&s_bll[i * NV + j], v);
+    } else if (kind == kOutMM) {
+        unsafeAtomicAdd(&A.dmm[static_cast<int64_t>(m) * NR + u], four ? v : 2.0 * v);
+    } else if (kind == kOutLL) {
+        if (four) atomicAdd(&s_bll[u], v);
     }
 }
 
@@ -759,16 +851,20 @@ __device__ void wave_setup(char *wmem)
     wave_sync();
 }
 
+// Occupancy hint: more waves per SIMD cover LDS and table latency at the cost of
+// registers (5 waves in 2D, 3 in 3D were fastest on the 2D 128^2 and 3D 8^3 cases).
 template <int DIM, int PREC, int ETA>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu<DIM>())))
 k_integrate(AsmArgs A)
 {
     using S = Shape<DIM>;
-    constexpr int NV = S::NV, NQ = S::NQ;
+    constexpr int NV = S::NV, NQ = S::NQ, NR = S::NR;
     extern __shared__ __align__(16) char smem[];
     __shared__ double s_rule[NQ * NV + NQ];
     __shared__ float s_w32[16];
-    __shared__ double s_bll[NV * NV];
+    __shared__ __align__(16) double s_T[(NV + NR + 1) * 16];
+    __shared__ int s_desc[kWave];
+    __shared__ double s_bll[NR];
     __shared__ int64_t s_item;
     __shared__ int s_next;
     __shared__ unsigned long long s_leaf[10];
@@ -779,6 +875,8 @@ k_integrate(AsmArgs A)
     for (int t = threadIdx.x; t < NQ * NV + NQ; t += kThreads) s_rule[t] = A.rule[t];
     if (threadIdx.x < NQ) s_w32[threadIdx.x] = static_cast<float>(A.rule[NQ * NV + threadIdx.x]);
     if (threadIdx.x < 10) s_leaf[threadIdx.x] = 0ull;
+    __syncthreads();
+    epilogue_tables<DIM>(s_rule, s_T, s_desc);
     wave_setup<DIM, PREC>(wmem);
     unsigned long long pairs_done = 0;
     for (;;) {
@@ -786,7 +884,7 @@ k_integrate(AsmArgs A)
             s_item = atomicAdd(A.counter, 1u);
             s_next = 0;
         }
-        if (threadIdx.x < NV * NV) s_bll[threadIdx.x] = 0.0;
+        if (threadIdx.x < NR) s_bll[threadIdx.x] = 0.0;
         __syncthreads();
         const int64_t l = s_item;
         if (l >= A.ne) break;
@@ -813,18 +911,60 @@ k_integrate(AsmArgs A)
             p = bcast0(p);
             if (p >= nJ) break;
             const int32_t m = A.pair_m[b0 + p];
-            process_pair<DIM, PREC, ETA>(A, static_cast<int>(l), m, wmem, s_rule, s_w32, s_bll, &s_rc,
-                                         nullptr, s_leaf);
+            process_pair<DIM, PREC, ETA>(A, static_cast<int>(l), m, wmem, s_rule, s_w32, s_T, s_desc,
+                                         s_bll, &s_rc, nullptr, s_leaf);
             ++pairs_done;
         }
         __syncthreads();
-        if (A.form == NLQ_FORM_SYM4 && threadIdx.x < NV * NV)
-            unsafeAtomicAdd(&A.val[A.elpos[l * NV * NV + threadIdx.x]], s_bll[threadIdx.x]);
+        // B_ll of l (upper triangle) joins the diagonal-block sums of l
+        if (A.form == NLQ_FORM_SYM4 && threadIdx.x < NR)
+            unsafeAtomicAdd(&A.dmm[l * NR + threadIdx.x], s_bll[threadIdx.x]);
         __syncthreads();
     }
     if (lane_id() == 0 && pairs_done) atomicAdd(&A.counters->pairs_done, pairs_done);
     if (threadIdx.x >= 1 && threadIdx.x <= A.lmax && s_leaf[threadIdx.x])
         atomicAdd(&A.counters->leaf[threadIdx.x], s_leaf[threadIdx.x]);
+}
+
+// Diagonal blocks into the CSR values: slot u = (i, j), i <= j, of element e goes
+// to (e_i, e_j).  SYM4 halves the diagonal slots, so that R + R^T restores every
+// symmetric block; the two-term form adds both triangles directly.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_fold_diag(int64_t ne, const double *dmm, const int32_t *elpos,
+                                                  double *val, int four)
+{
+    using S = Shape<DIM>;
+    constexpr int NV = S::NV, NR = S::NR;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= ne * NR) return;
+    const int64_t e = t / NR;
+    const int u = static_cast<int>(t - e * NR);
+    int i, j;
+    pair_of<NV>(u, i, j);
+    const double d = dmm[t];
+    const int32_t *ep = elpos + e * NV * NV;
+    if (four) {
+        unsafeAtomicAdd(&val[ep[i * NV + j]], i == j ? 0.5 * d : d);
+    } else {
+        unsafeAtomicAdd(&val[ep[i * NV + j]], d);
+        if (i != j) unsafeAtomicAdd(&val[ep[j * NV + i]], d);
+    }
+}
+
+// A = R + R^T in place: the entry p and its transpose t are written by the
+// thread of min(p, t) only, diagonal entries are doubled.
+__global__ void __launch_bounds__(256) k_symmetrize(int64_t nnz, const int32_t *tmap, double *val)
+{
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= nnz) return;
+    const int64_t t = tmap[p];
+    if (p < t) {
+        const double s = val[p] + val[t];
+        val[p] = s;
+        val[t] = s;
+    } else if (p == t) {
+        val[p] = 2.0 * val[p];
+    }
 }
 
 // explicit pairs: every wave takes pairs from the global counter and writes the
@@ -840,8 +980,12 @@ k_pair_blocks(AsmArgs A)
     __shared__ float s_w32[16];
     const int wid = threadIdx.x / kWave;
     char *wmem = smem + wid * WaveMem<DIM, PREC>::bytes(A.capl);
+    __shared__ __align__(16) double s_T[(NV + S::NR + 1) * 16];
+    __shared__ int s_desc[kWave];
     for (int t = threadIdx.x; t < NQ * NV + NQ; t += kThreads) s_rule[t] = A.rule[t];
     if (threadIdx.x < NQ) s_w32[threadIdx.x] = static_cast<float>(A.rule[NQ * NV + threadIdx.x]);
+    __syncthreads();
+    epilogue_tables<DIM>(s_rule, s_T, s_desc);
     wave_setup<DIM, PREC>(wmem);
     __syncthreads();
     for (;;) {
@@ -852,8 +996,8 @@ k_pair_blocks(AsmArgs A)
         double *blk = A.ex_out + static_cast<int64_t>(it) * (2 * NV) * (2 * NV);
         for (int t = lane_id(); t < 4 * NV * NV; t += kWave) blk[t] = 0.0;
         wave_sync();
-        process_pair<DIM, PREC, ETA>(A, A.ex_l[it], A.ex_m[it], wmem, s_rule, s_w32, nullptr, nullptr,
-                                     blk, nullptr);
+        process_pair<DIM, PREC, ETA>(A, A.ex_l[it], A.ex_m[it], wmem, s_rule, s_w32, s_T, s_desc, nullptr,
+                                     nullptr, blk, nullptr);
     }
 }
 
@@ -884,6 +1028,15 @@ void launch_eta(System &s, AsmArgs &A, hipStream_t st, bool ex, hipEvent_t e0, h
 {
     if (s.p.kernel == NLQ_ETA_GAUSS) launch_one<DIM, PREC, NLQ_ETA_GAUSS>(s, A, st, ex, e0, e1);
     else launch_one<DIM, PREC, NLQ_ETA_CONST>(s, A, st, ex, e0, e1);
+}
+
+// smallest s >= 0 with fl(sqrt(s)) >= t (t > 0; sqrt correctly rounded)
+double sqrt_threshold(double t)
+{
+    double x = t * t;
+    while (x > 0.0 && std::sqrt(x) >= t) x = std::nextafter(x, 0.0);
+    while (std::sqrt(x) < t) x = std::nextafter(x, HUGE_VAL);
+    return x;
 }
 
 }  // namespace
@@ -918,6 +1071,8 @@ void launch_integrate(System &s, hipStream_t st, int64_t n_explicit, const int32
     A.eps = s.p.eps;
     A.dme = s.p.delta - s.p.eps;
     A.dpe = s.p.delta + s.p.eps;
+    A.dme_sq = sqrt_threshold(A.dme);
+    A.dmm = s.dmm.as<double>();
     A.dme2 = A.dme * A.dme * (1.0 - 1e-12);
     A.dpe2 = A.dpe * A.dpe * (1.0 + 1e-12);
     A.C = s.C;
@@ -946,6 +1101,7 @@ void launch_integrate(System &s, hipStream_t st, int64_t n_explicit, const int32
     if (!ex) {
         NLQ_HIP(hipMemsetAsync(A.counters, 0, sizeof(AsmCounters), st));
         NLQ_HIP(hipMemsetAsync(A.val, 0, sizeof(double) * s.nnz, st));
+        NLQ_HIP(hipMemsetAsync(A.dmm, 0, sizeof(double) * m.n_elems * (m.dim == 2 ? 6 : 10), st));
     }
     if (m.dim == 2) {
         if (s.p.precision == NLQ_FP64_PLAIN) launch_eta<2, 0>(s, A, st, ex, e0, e1);
@@ -953,6 +1109,22 @@ void launch_integrate(System &s, hipStream_t st, int64_t n_explicit, const int32
     } else {
         if (s.p.precision == NLQ_FP64_PLAIN) launch_eta<3, 0>(s, A, st, ex, e0, e1);
         else launch_eta<3, 1>(s, A, st, ex, e0, e1);
+    }
+    if (ex) return;
+    const int four = s.p.form == NLQ_FORM_SYM4;
+    const int64_t nf = m.n_elems * (m.dim == 2 ? 6 : 10);
+    if (nf > 0) {
+        const unsigned gf = static_cast<unsigned>((nf + 255) / 256);
+        if (m.dim == 2)
+            hipLaunchKernelGGL(k_fold_diag<2>, dim3(gf), dim3(256), 0, st, m.n_elems, A.dmm, A.elpos, A.val, four);
+        else
+            hipLaunchKernelGGL(k_fold_diag<3>, dim3(gf), dim3(256), 0, st, m.n_elems, A.dmm, A.elpos, A.val, four);
+        NLQ_CHECK_LAUNCH();
+    }
+    if (four && s.nnz > 0) {
+        hipLaunchKernelGGL(k_symmetrize, dim3(static_cast<unsigned>((s.nnz + 255) / 256)), dim3(256), 0, st,
+                           s.nnz, A.tmap, A.val);
+        NLQ_CHECK_LAUNCH();
     }
 }
 

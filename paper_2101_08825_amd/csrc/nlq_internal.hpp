@@ -143,6 +143,7 @@ struct System {
     DevBuf tmap;                 // [nnz] int32: position of the transposed entry
     DevBuf elpos;                // [ne][nv*nv] int32: positions of the element's own block
     DevBuf val;                  // [nnz] double
+    DevBuf dmm;                  // [ne][NR] double: upper-triangle diagonal-block sums per element
     // rhs / solution
     DevBuf F, Ft, u, g;          // [n] double
     DevBuf counters;             // AsmCounters
