@@ -150,6 +150,15 @@ nlq_status nlq_mesh_destroy(nlq_mesh *mesh);
  * exceeds the budget. */
 nlq_status nlq_assemble(nlq_ctx *ctx, const nlq_mesh *mesh, const nlq_params *params,
                         nlq_system **out);
+/* Assemble n systems (meshes[i], params[i]) as n calls of nlq_assemble would,
+ * but with shared integration launches: the outer elements of every system of
+ * one (dim, precision, kernel) group, up to 32 systems per launch, are
+ * interleaved in one persistent work queue (Algorithm 1 runs per pair, so the
+ * order of pairs does not change any block).  out: host [n] handles.  The
+ * systems' t_kernel is the time of the launch they shared.  On error no
+ * system is returned. */
+nlq_status nlq_assemble_batch(nlq_ctx *ctx, int32_t n, const nlq_mesh *const *meshes,
+                              const nlq_params *params, nlq_system **out);
 nlq_status nlq_assemble_info_get(const nlq_system *sys, nlq_assemble_info *info);
 /* Re-run only the integration step (pair list and pattern kept) -- the hot loop;
  * values are recomputed from zero. */

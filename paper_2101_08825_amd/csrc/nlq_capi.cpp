@@ -157,22 +157,48 @@ void upload_mesh(Mesh &m, hipStream_t st)
     NLQ_HIP(hipStreamSynchronize(st));
 }
 
-void run_integrate(System &s, hipStream_t st)
+}  // namespace
+
+// Everything up to the integration: element tables, pair list, pattern, value
+// arrays (on stream st; returns with st synchronised).
+std::unique_ptr<nlq_system> prepare_system(Ctx &ctx, const Mesh &mesh, const nlq_params &params, hipStream_t st)
 {
+    check_params(mesh, params);
+    auto sys = std::make_unique<nlq_system>();
+    System &s = sys->impl;
+    s.ctx = &ctx;
+    s.mesh = &mesh;
+    s.p = params;
+    s.C = params.scale > 0.0 ? params.scale : kernel_constant(params.dim, params.kernel, params.delta, params.eps);
+    (void)ctx.get_tables(mesh.dim, s.p.lmax);
+    s.counters.alloc(s.ctx, sizeof(AsmCounters));
+    NLQ_HIP(hipStreamSynchronize(st));
     const double t0 = now_s();
-    hipEvent_t e0, e1;
-    NLQ_HIP(hipEventCreate(&e0));
-    NLQ_HIP(hipEventCreate(&e1));
-    launch_integrate(s, st, 0, nullptr, nullptr, nullptr, e0, e1);
+    launch_elem_tables(s, st);
+    NLQ_HIP(hipStreamSynchronize(st));
+    const double t1 = now_s();
+    build_pairs(s, st);
+    const double t2 = now_s();
+    build_pattern(s, st);
+    s.val.alloc(s.ctx, sizeof(double) * std::max<int64_t>(s.nnz, 1));
+    const int nr = mesh.dim == 2 ? 6 : 10;
+    s.dmm.alloc(s.ctx, sizeof(double) * std::max<int64_t>(mesh.n_elems * nr, 1));
+    NLQ_HIP(hipStreamSynchronize(st));
+    const double t3 = now_s();
+    s.info.n_pairs = s.n_pairs;
+    s.info.nnz = s.nnz;
+    s.info.t_tables = t1 - t0;
+    s.info.t_pairs = t2 - t1;
+    s.info.t_pattern = t3 - t2;
+    return sys;
+}
+
+// counters of a finished integration -> info (synchronises st)
+void collect_counters(System &s, hipStream_t st)
+{
     AsmCounters c{};
     NLQ_HIP(hipMemcpyAsync(&c, s.counters.as<void>(), sizeof(AsmCounters), hipMemcpyDeviceToHost, st));
     NLQ_HIP(hipStreamSynchronize(st));
-    s.info.t_integrate = now_s() - t0;
-    float ms = 0.0f;
-    NLQ_HIP(hipEventElapsedTime(&ms, e0, e1));
-    s.info.t_kernel = 1e-3 * ms;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     const int nq = s.mesh->dim == 2 ? 7 : 15;
     int64_t leaves = 0;
     for (int q = 0; q < 9; ++q) {
@@ -184,7 +210,21 @@ void run_integrate(System &s, hipStream_t st)
         fail(NLQ_EDEVICE, "integration did not visit every pair");
 }
 
-}  // namespace
+void run_integrate(System &s, hipStream_t st)
+{
+    const double t0 = now_s();
+    hipEvent_t e0, e1;
+    NLQ_HIP(hipEventCreate(&e0));
+    NLQ_HIP(hipEventCreate(&e1));
+    launch_integrate(s, st, e0, e1);
+    collect_counters(s, st);
+    s.info.t_integrate = now_s() - t0;
+    float ms = 0.0f;
+    NLQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+    s.info.t_kernel = 1e-3 * ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
 
 }  // namespace nlq
 
@@ -359,41 +399,67 @@ nlq_status nlq_assemble(nlq_ctx *ctx, const nlq_mesh *mesh, const nlq_params *pa
     return guard([&] {
         if (!ctx || !mesh || !params || !out) fail(NLQ_EINVAL, "NULL argument");
         if (mesh->impl.ctx != &ctx->impl) fail(NLQ_EINVAL, "mesh belongs to another context");
-        check_params(mesh->impl, *params);
         NLQ_HIP(hipSetDevice(ctx->impl.device));
-        auto sys = std::make_unique<nlq_system>();
-        System &s = sys->impl;
-        s.ctx = &ctx->impl;
-        s.mesh = &mesh->impl;
-        s.p = *params;
-        s.C = params->scale > 0.0 ? params->scale
-                                  : kernel_constant(params->dim, params->kernel, params->delta, params->eps);
         hipStream_t st = ctx->impl.stream;
-        (void)ctx->impl.get_tables(s.mesh->dim, s.p.lmax);
-        s.counters.alloc(s.ctx, sizeof(AsmCounters));
-        s.l_counter.alloc(s.ctx, sizeof(unsigned int));
-        NLQ_HIP(hipStreamSynchronize(st));
-        const double t0 = now_s();
-        launch_elem_tables(s, st);
-        NLQ_HIP(hipStreamSynchronize(st));
-        const double t1 = now_s();
-        build_pairs(s, st);
-        const double t2 = now_s();
-        build_pattern(s, st);
-        s.val.alloc(s.ctx, sizeof(double) * std::max<int64_t>(s.nnz, 1));
-        const int nr = s.mesh->dim == 2 ? 6 : 10;
-        s.dmm.alloc(s.ctx, sizeof(double) * std::max<int64_t>(s.mesh->n_elems * nr, 1));
-        NLQ_HIP(hipStreamSynchronize(st));
+        auto sys = prepare_system(ctx->impl, mesh->impl, *params, st);
+        System &s = sys->impl;
         const double t3 = now_s();
         run_integrate(s, st);
-        const double t4 = now_s();
-        s.info.n_pairs = s.n_pairs;
-        s.info.nnz = s.nnz;
-        s.info.t_tables = t1 - t0;
-        s.info.t_pairs = t2 - t1;
-        s.info.t_pattern = t3 - t2;
-        s.info.t_total = t4 - t0;
+        s.info.t_total = (now_s() - t3) + s.info.t_tables + s.info.t_pairs + s.info.t_pattern;
         *out = sys.release();
+    });
+}
+
+nlq_status nlq_assemble_batch(nlq_ctx *ctx, int32_t n, const nlq_mesh *const *meshes, const nlq_params *params,
+                              nlq_system **out)
+{
+    std::vector<std::unique_ptr<nlq_system>> made;
+    return guard([&] {
+        if (!ctx || n < 0 || (n > 0 && (!meshes || !params || !out))) fail(NLQ_EINVAL, "NULL argument");
+        for (int32_t i = 0; i < n; ++i) {
+            if (!meshes[i]) fail(NLQ_EINVAL, "NULL mesh");
+            if (meshes[i]->impl.ctx != &ctx->impl) fail(NLQ_EINVAL, "mesh belongs to another context");
+        }
+        NLQ_HIP(hipSetDevice(ctx->impl.device));
+        hipStream_t st = ctx->impl.stream;
+        for (int32_t i = 0; i < n; ++i) made.push_back(prepare_system(ctx->impl, meshes[i]->impl, params[i], st));
+        // one group per (dim, precision, kernel); up to 32 systems per launch
+        std::vector<int> order(n);
+        for (int i = 0; i < n; ++i) order[i] = i;
+        auto key = [&](int i) {
+            const System &s = made[i]->impl;
+            return std::make_tuple(s.mesh->dim, s.p.precision, s.p.kernel);
+        };
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(x) < key(y); });
+        LaunchBlock lb;
+        hipEvent_t e0, e1;
+        NLQ_HIP(hipEventCreate(&e0));
+        NLQ_HIP(hipEventCreate(&e1));
+        for (size_t g0 = 0; g0 < order.size();) {
+            size_t g1 = g0;
+            std::vector<IntegrateJob> jobs;
+            while (g1 < order.size() && key(order[g1]) == key(order[g0]) && jobs.size() < 32) {
+                System &s = made[order[g1]]->impl;
+                jobs.push_back(IntegrateJob{&s, 0, s.mesh->n_elems});
+                ++g1;
+            }
+            const double t0 = now_s();
+            launch_integrate_jobs(&ctx->impl, lb, jobs, st, e0, e1);
+            NLQ_HIP(hipStreamSynchronize(st));
+            const double t1 = now_s();
+            float ms = 0.0f;
+            NLQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+            for (auto &j : jobs) {
+                collect_counters(*j.s, st);
+                j.s->info.t_integrate = t1 - t0;
+                j.s->info.t_kernel = 1e-3 * ms;
+                j.s->info.t_total = j.s->info.t_tables + j.s->info.t_pairs + j.s->info.t_pattern + (t1 - t0);
+            }
+            g0 = g1;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        for (int32_t i = 0; i < n; ++i) out[i] = made[i].release();
     });
 }
 
@@ -570,7 +636,7 @@ nlq_status nlq_pair_blocks(nlq_system *sys, int64_t n, const int32_t *l, const i
             dout(s.ctx, sizeof(double) * n * blk);
         NLQ_HIP(hipMemcpyAsync(dl.as<void>(), l, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
         NLQ_HIP(hipMemcpyAsync(dm.as<void>(), m, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
-        launch_integrate(s, st, n, dl.as<int32_t>(), dm.as<int32_t>(), dout.as<double>());
+        launch_pair_blocks(s, st, n, dl.as<int32_t>(), dm.as<int32_t>(), dout.as<double>());
         NLQ_HIP(hipMemcpyAsync(out, dout.as<void>(), sizeof(double) * n * blk, hipMemcpyDeviceToHost, st));
         NLQ_HIP(hipStreamSynchronize(st));
     });

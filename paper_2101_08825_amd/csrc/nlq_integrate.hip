@@ -88,14 +88,32 @@ struct AsmArgs {
     double *dmm;          // [ne][NR] upper-triangle diagonal-block sums per element
     float f_delta, f_inv_eps, f_delta_over_eps, f_dme2, f_dpe2, f_inv_delta2;
     int lmin, lmax, form;
-    int capl;
-    int rowcap;           // LDS capacity per cached CSR row
-    unsigned int *counter;
+    int capl;             // refinement-list capacity this system needs
+    int rowcap;           // LDS row cache this system would like
     AsmCounters *counters;
     int64_t n_explicit;
     const int32_t *ex_l;
     const int32_t *ex_m;
     double *ex_out;
+};
+
+// Per-system arguments are read from device memory through the constant
+// address space, so that every field is a scalar load of a uniform address.
+typedef const __attribute__((address_space(4))) AsmArgs CArgs;
+
+// One launch integrates segments [seg_lo, seg_lo + len) of outer elements of
+// one or more systems (same dim, precision and kernel); work item w of the
+// flat counter lies in the segment k with seg_start[k] <= w < seg_start[k+1].
+constexpr int kMaxSeg = 32;
+struct LaunchArgs {
+    const AsmArgs *sys;
+    const int32_t *seg_sys;
+    const int64_t *seg_lo;
+    const int64_t *seg_start;   // [nseg + 1]
+    int nseg;
+    int capl;                   // LDS layout: refinement lists
+    int rowcap;                 // LDS layout: cached CSR row capacity
+    unsigned int *counter;
 };
 
 __device__ __forceinline__ void wave_sync()
@@ -137,7 +155,7 @@ __device__ __forceinline__ float xi32(float r)
 }
 
 // gamma_eps / C at squared distance d2: eta * mu (FP64)
-template <int ETA> __device__ __forceinline__ double kernel64(const AsmArgs &A, double d2)
+template <int ETA> __device__ __forceinline__ double kernel64(CArgs &A, double d2)
 {
     double mu;
     if (d2 < A.dme2) {
@@ -153,7 +171,7 @@ template <int ETA> __device__ __forceinline__ double kernel64(const AsmArgs &A, 
 }
 
 // gamma_eps / C at squared distance d2 (FP32; sqrt to ~1 ulp)
-template <int ETA> __device__ __forceinline__ float kernel32(const AsmArgs &A, float d2)
+template <int ETA> __device__ __forceinline__ float kernel32(CArgs &A, float d2)
 {
     float g;
     if (d2 < A.f_dme2) {
@@ -207,7 +225,7 @@ __device__ __forceinline__ Simplex<DIM> child_of(const Simplex<DIM> &S, int c)
 
 // 0 = drop, 1 = integrate now (J^int), 2 = refine (J^ref): Algorithm 1
 template <int DIM>
-__device__ __forceinline__ int classify(const AsmArgs &A, const Simplex<DIM> &root, int lev,
+__device__ __forceinline__ int classify(CArgs &A, const Simplex<DIM> &root, int lev,
                                         uint32_t local, const double *mlo, const double *mhi)
 {
     constexpr int NCH = 1 << DIM;
@@ -268,7 +286,7 @@ template <int DIM, int ETA> struct PlainAcc {
         for (int k = 0; k < DIM; ++k) yh[k] = y[k];
         active = (lane % NYP) < S::NQ;
     }
-    __device__ static In fetch(const AsmArgs &A, bool valid, int sub, int a, int lev, float, double wa)
+    __device__ static In fetch(CArgs &A, bool valid, int sub, int a, int lev, float, double wa)
     {
         In in;
         if (valid) {
@@ -302,7 +320,7 @@ template <int DIM, int ETA> struct PlainAcc {
             for (int j = i + 1; j < S::NV; ++j)
                 sp[t * S::NR + offrow<S::NV>(i, j)] = in.w * in.lam[i] * in.lam[j];
     }
-    __device__ void run(const AsmArgs &A, const char *work, int npts)
+    __device__ void run(CArgs &A, const char *work, int npts)
     {
         const double *sx = reinterpret_cast<const double *>(work);
         const double *sp = sx + kBatch * DIM;
@@ -382,7 +400,7 @@ template <int DIM, int ETA> struct MixedAcc {
         yh[2] = (DIM == 3 && colv) ? static_cast<float>(y[DIM - 1]) : 1.0e18f;
         (void)work;
     }
-    __device__ static In fetch(const AsmArgs &A, bool valid, int sub, int a, int lev, float wa, double)
+    __device__ static In fetch(CArgs &A, bool valid, int sub, int a, int lev, float wa, double)
     {
         In in;
         if (valid) {
@@ -442,7 +460,7 @@ template <int DIM, int ETA> struct MixedAcc {
                 make_float2(P[8 < S::NR ? 8 : 0], P[9 < S::NR ? 9 : 0]);
         }
     }
-    __device__ void run(const AsmArgs &A, const char *work, int npts)
+    __device__ void run(CArgs &A, const char *work, int npts)
     {
         const float *sx = reinterpret_cast<const float *>(work) + poff * XS;
         const float *sp = reinterpret_cast<const float *>(work) + kBatch * XS + poff * PS + sub;
@@ -468,7 +486,8 @@ template <int DIM, int ETA> struct MixedAcc {
 #pragma unroll
         for (int r = 0; r < 4; ++r) dacc[r] += static_cast<double>(acc[r]);
     }
-    // D[i][j] (FP64) -> H/Q totals out[r*16 + b]
+    // D[i][j] (FP64) -> H/Q totals out[r*16 + b]; out may be the tile itself: in
+    // 2D each lane reads its own slot and a slot of rows 8..15, which nobody writes
     __device__ void finish(double *out, double *tile)
     {
         const int l = lane_id();
@@ -492,7 +511,8 @@ template <int DIM, int PREC> struct WaveMem {
     static constexpr int kStageBytes =
         PREC == 0 ? PlainAcc<DIM, 0>::kStageBytes : MixedAcc<DIM, 0>::kStageBytes;
     static constexpr int kEpiRows = S::NR + 1 + S::NV;   // H/Q rows + column sums + diagonal rows
-    static constexpr int kEpiBytes = (kEpiRows * 16 + (PREC == 1 ? 256 : 0)) * 8;
+    // the mixed path's 16 x 16 MFMA tile is written in place of the H/Q rows
+    static constexpr int kEpiBytes = (PREC == 1 && kEpiRows < 16 ? 16 : kEpiRows) * 16 * 8;
     __host__ __device__ static int bytes(int capl)
     {
         return (kStageBytes + kEpiBytes + kLeafCap * 4 + 2 * capl * 4 + 15) & ~15;
@@ -625,7 +645,7 @@ template <int DIM> __device__ __forceinline__ void extend_rows(double *HQ)
 // -------------------------------------------------------------- one pair
 
 template <int DIM, int PREC, int ETA>
-__device__ void process_pair(const AsmArgs &A, int l, int m, char *wmem, const double *s_rule,
+__device__ __forceinline__ void process_pair(CArgs &A, int l, int m, char *wmem, const double *s_rule,
                              const float *s_w32, const double *s_T, const int *s_desc, double *s_bll,
                              const RowCache *rc, double *ex_block, unsigned long long *s_leaf)
 {
@@ -639,8 +659,8 @@ __device__ void process_pair(const AsmArgs &A, int l, int m, char *wmem, const d
     l = uniform(l);
     m = uniform(m);
     char *work = wmem;
-    double *HQ = reinterpret_cast<double *>(wmem + WM::kStageBytes);   // [NR][16]
-    double *tile = HQ + NR * 16;                                       // 256 doubles (mixed)
+    double *HQ = reinterpret_cast<double *>(wmem + WM::kStageBytes);   // [rows][16]
+    double *tile = HQ;                                                 // 16 x 16 (mixed), in place
     uint32_t *leafbuf = reinterpret_cast<uint32_t *>(wmem + WM::kStageBytes + WM::kEpiBytes);
     uint32_t *listA = leafbuf + kLeafCap;
     uint32_t *listB = listA + A.capl;
@@ -855,7 +875,7 @@ __device__ void wave_setup(char *wmem)
 // registers (5 waves in 2D, 3 in 3D were fastest on the 2D 128^2 and 3D 8^3 cases).
 template <int DIM, int PREC, int ETA>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu<DIM>())))
-k_integrate(AsmArgs A)
+k_integrate(LaunchArgs L)
 {
     using S = Shape<DIM>;
     constexpr int NV = S::NV, NQ = S::NQ, NR = S::NR;
@@ -865,42 +885,61 @@ k_integrate(AsmArgs A)
     __shared__ __align__(16) double s_T[(NV + NR + 1) * 16];
     __shared__ int s_desc[kWave];
     __shared__ double s_bll[NR];
+    __shared__ int64_t s_seg[kMaxSeg + 1];
     __shared__ int64_t s_item;
+    __shared__ int s_sys;
     __shared__ int s_next;
     __shared__ unsigned long long s_leaf[10];
     __shared__ RowCache s_rc;
     const int wid = threadIdx.x / kWave;
-    char *wmem = smem + wid * WaveMem<DIM, PREC>::bytes(A.capl);
-    int32_t *rows_lds = reinterpret_cast<int32_t *>(smem + kWaves * WaveMem<DIM, PREC>::bytes(A.capl));
-    for (int t = threadIdx.x; t < NQ * NV + NQ; t += kThreads) s_rule[t] = A.rule[t];
-    if (threadIdx.x < NQ) s_w32[threadIdx.x] = static_cast<float>(A.rule[NQ * NV + threadIdx.x]);
-    if (threadIdx.x < 10) s_leaf[threadIdx.x] = 0ull;
+    char *wmem = smem + wid * WaveMem<DIM, PREC>::bytes(L.capl);
+    int32_t *rows_lds = reinterpret_cast<int32_t *>(smem + kWaves * WaveMem<DIM, PREC>::bytes(L.capl));
+    // the quadrature rule depends on the dimension only: every system of the launch shares it
+    CArgs &A0 = *(CArgs *)(L.sys);
+    for (int t = threadIdx.x; t < NQ * NV + NQ; t += kThreads) s_rule[t] = A0.rule[t];
+    if (threadIdx.x < NQ) s_w32[threadIdx.x] = static_cast<float>(A0.rule[NQ * NV + threadIdx.x]);
+    for (int t = threadIdx.x; t <= L.nseg; t += kThreads) s_seg[t] = L.seg_start[t];
     __syncthreads();
     epilogue_tables<DIM>(s_rule, s_T, s_desc);
     wave_setup<DIM, PREC>(wmem);
-    unsigned long long pairs_done = 0;
+    const int64_t total = s_seg[L.nseg];
     for (;;) {
         if (threadIdx.x == 0) {
-            s_item = atomicAdd(A.counter, 1u);
+            const int64_t w = atomicAdd(L.counter, 1u);
+            int64_t item = -1;
+            int sys = 0;
+            if (w < total) {
+                int lo = 0, hi = L.nseg - 1;   // last segment with s_seg[k] <= w
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_seg[mid] <= w) lo = mid; else hi = mid - 1;
+                }
+                item = L.seg_lo[lo] + (w - s_seg[lo]);
+                sys = L.seg_sys[lo];
+            }
+            s_item = item;
+            s_sys = sys;
             s_next = 0;
         }
         if (threadIdx.x < NR) s_bll[threadIdx.x] = 0.0;
+        if (threadIdx.x < 10) s_leaf[threadIdx.x] = 0ull;
         __syncthreads();
         const int64_t l = s_item;
-        if (l >= A.ne) break;
+        if (l < 0) break;
+        CArgs &A = *(CArgs *)(L.sys + __builtin_amdgcn_readfirstlane(s_sys));
         // stage the CSR rows of l's nodes
         if (threadIdx.x < NV) {
             const int32_t node = A.conn[l * NV + threadIdx.x];
             const int64_t b = A.row_ptr[node], len = A.row_ptr[node + 1] - b;
             s_rc.base[threadIdx.x] = b;
             s_rc.len[threadIdx.x] = len;
-            s_rc.cols[threadIdx.x] = len <= A.rowcap ? rows_lds + threadIdx.x * A.rowcap : A.col + b;
+            s_rc.cols[threadIdx.x] = len <= L.rowcap ? rows_lds + threadIdx.x * L.rowcap : A.col + b;
         }
         __syncthreads();
         for (int r = 0; r < NV; ++r) {
-            if (s_rc.len[r] > A.rowcap) continue;
+            if (s_rc.len[r] > L.rowcap) continue;
             for (int64_t k = threadIdx.x; k < s_rc.len[r]; k += kThreads)
-                rows_lds[r * A.rowcap + k] = A.col[s_rc.base[r] + k];
+                rows_lds[r * L.rowcap + k] = A.col[s_rc.base[r] + k];
         }
         __syncthreads();
         const int64_t b0 = A.pair_off[l];
@@ -913,17 +952,51 @@ k_integrate(AsmArgs A)
             const int32_t m = A.pair_m[b0 + p];
             process_pair<DIM, PREC, ETA>(A, static_cast<int>(l), m, wmem, s_rule, s_w32, s_T, s_desc,
                                          s_bll, &s_rc, nullptr, s_leaf);
-            ++pairs_done;
         }
         __syncthreads();
         // B_ll of l (upper triangle) joins the diagonal-block sums of l
         if (A.form == NLQ_FORM_SYM4 && threadIdx.x < NR)
             unsafeAtomicAdd(&A.dmm[l * NR + threadIdx.x], s_bll[threadIdx.x]);
+        if (threadIdx.x >= 1 && threadIdx.x <= A.lmax && s_leaf[threadIdx.x])
+            atomicAdd(&A.counters->leaf[threadIdx.x], s_leaf[threadIdx.x]);
+        if (threadIdx.x == 0) atomicAdd(&A.counters->pairs_done, static_cast<unsigned long long>(nJ));
         __syncthreads();
     }
-    if (lane_id() == 0 && pairs_done) atomicAdd(&A.counters->pairs_done, pairs_done);
-    if (threadIdx.x >= 1 && threadIdx.x <= A.lmax && s_leaf[threadIdx.x])
-        atomicAdd(&A.counters->leaf[threadIdx.x], s_leaf[threadIdx.x]);
+}
+
+// explicit pairs of system 0: every wave takes pairs from the counter and
+// writes the extended block [2N+2][2N+2] of each
+template <int DIM, int PREC, int ETA>
+__global__ void __launch_bounds__(kThreads)
+k_pair_blocks(LaunchArgs L)
+{
+    using S = Shape<DIM>;
+    constexpr int NV = S::NV, NQ = S::NQ;
+    extern __shared__ __align__(16) char smem[];
+    __shared__ double s_rule[NQ * NV + NQ];
+    __shared__ float s_w32[16];
+    __shared__ __align__(16) double s_T[(NV + S::NR + 1) * 16];
+    __shared__ int s_desc[kWave];
+    CArgs &A = *(CArgs *)(L.sys);
+    const int wid = threadIdx.x / kWave;
+    char *wmem = smem + wid * WaveMem<DIM, PREC>::bytes(L.capl);
+    for (int t = threadIdx.x; t < NQ * NV + NQ; t += kThreads) s_rule[t] = A.rule[t];
+    if (threadIdx.x < NQ) s_w32[threadIdx.x] = static_cast<float>(A.rule[NQ * NV + threadIdx.x]);
+    __syncthreads();
+    epilogue_tables<DIM>(s_rule, s_T, s_desc);
+    wave_setup<DIM, PREC>(wmem);
+    __syncthreads();
+    for (;;) {
+        unsigned int it = 0;
+        if (lane_id() == 0) it = atomicAdd(L.counter, 1u);
+        it = bcast0(it);
+        if (it >= A.n_explicit) break;
+        double *blk = A.ex_out + static_cast<int64_t>(it) * (2 * NV) * (2 * NV);
+        for (int t = lane_id(); t < 4 * NV * NV; t += kWave) blk[t] = 0.0;
+        wave_sync();
+        process_pair<DIM, PREC, ETA>(A, A.ex_l[it], A.ex_m[it], wmem, s_rule, s_w32, s_T, s_desc, nullptr,
+                                     nullptr, blk, nullptr);
+    }
 }
 
 // Diagonal blocks into the CSR values: slot u = (i, j), i <= j, of element e goes
@@ -967,45 +1040,12 @@ __global__ void __launch_bounds__(256) k_symmetrize(int64_t nnz, const int32_t *
     }
 }
 
-// explicit pairs: every wave takes pairs from the global counter and writes the
-// extended block [2N+2][2N+2] of each
 template <int DIM, int PREC, int ETA>
-__global__ void __launch_bounds__(kThreads)
-k_pair_blocks(AsmArgs A)
+void launch_one(Ctx *ctx, const LaunchArgs &L, int64_t items, hipStream_t st, bool explicit_mode,
+                hipEvent_t e0, hipEvent_t e1)
 {
-    using S = Shape<DIM>;
-    constexpr int NV = S::NV, NQ = S::NQ;
-    extern __shared__ __align__(16) char smem[];
-    __shared__ double s_rule[NQ * NV + NQ];
-    __shared__ float s_w32[16];
-    const int wid = threadIdx.x / kWave;
-    char *wmem = smem + wid * WaveMem<DIM, PREC>::bytes(A.capl);
-    __shared__ __align__(16) double s_T[(NV + S::NR + 1) * 16];
-    __shared__ int s_desc[kWave];
-    for (int t = threadIdx.x; t < NQ * NV + NQ; t += kThreads) s_rule[t] = A.rule[t];
-    if (threadIdx.x < NQ) s_w32[threadIdx.x] = static_cast<float>(A.rule[NQ * NV + threadIdx.x]);
-    __syncthreads();
-    epilogue_tables<DIM>(s_rule, s_T, s_desc);
-    wave_setup<DIM, PREC>(wmem);
-    __syncthreads();
-    for (;;) {
-        unsigned int it = 0;
-        if (lane_id() == 0) it = atomicAdd(A.counter, 1u);
-        it = bcast0(it);
-        if (it >= A.n_explicit) break;
-        double *blk = A.ex_out + static_cast<int64_t>(it) * (2 * NV) * (2 * NV);
-        for (int t = lane_id(); t < 4 * NV * NV; t += kWave) blk[t] = 0.0;
-        wave_sync();
-        process_pair<DIM, PREC, ETA>(A, A.ex_l[it], A.ex_m[it], wmem, s_rule, s_w32, s_T, s_desc, nullptr,
-                                     nullptr, blk, nullptr);
-    }
-}
-
-template <int DIM, int PREC, int ETA>
-void launch_one(System &s, AsmArgs &A, hipStream_t st, bool explicit_mode, hipEvent_t e0, hipEvent_t e1)
-{
-    const int per_wave = WaveMem<DIM, PREC>::bytes(A.capl);
-    const int lds = kWaves * per_wave + (explicit_mode ? 0 : (DIM + 1) * A.rowcap * 4);
+    const int per_wave = WaveMem<DIM, PREC>::bytes(L.capl);
+    const int lds = kWaves * per_wave + (explicit_mode ? 0 : (DIM + 1) * L.rowcap * 4);
     if (lds > 150 * 1024) fail(NLQ_EINVAL, "lmax too large for the per-wave refinement lists");
     auto kern = explicit_mode ? k_pair_blocks<DIM, PREC, ETA> : k_integrate<DIM, PREC, ETA>;
     NLQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -1013,21 +1053,34 @@ void launch_one(System &s, AsmArgs &A, hipStream_t st, bool explicit_mode, hipEv
     int per_cu = 0;
     NLQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, lds));
     if (per_cu < 1) per_cu = 1;
-    int64_t grid = static_cast<int64_t>(s.ctx->n_cu) * per_cu;
-    const int64_t items = explicit_mode ? A.n_explicit : A.ne;
+    int64_t grid = static_cast<int64_t>(ctx->n_cu) * per_cu;
     if (grid > items) grid = items;
     if (grid < 1) grid = 1;
     if (e0) NLQ_HIP(hipEventRecord(e0, st));
-    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(kThreads), lds, st, A);
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(kThreads), lds, st, L);
     NLQ_CHECK_LAUNCH();
     if (e1) NLQ_HIP(hipEventRecord(e1, st));
 }
 
 template <int DIM, int PREC>
-void launch_eta(System &s, AsmArgs &A, hipStream_t st, bool ex, hipEvent_t e0, hipEvent_t e1)
+void launch_eta(Ctx *ctx, int kernel, const LaunchArgs &L, int64_t items, hipStream_t st, bool ex,
+                hipEvent_t e0, hipEvent_t e1)
 {
-    if (s.p.kernel == NLQ_ETA_GAUSS) launch_one<DIM, PREC, NLQ_ETA_GAUSS>(s, A, st, ex, e0, e1);
-    else launch_one<DIM, PREC, NLQ_ETA_CONST>(s, A, st, ex, e0, e1);
+    if (kernel == NLQ_ETA_GAUSS) launch_one<DIM, PREC, NLQ_ETA_GAUSS>(ctx, L, items, st, ex, e0, e1);
+    else launch_one<DIM, PREC, NLQ_ETA_CONST>(ctx, L, items, st, ex, e0, e1);
+}
+
+void dispatch(Ctx *ctx, const System &s, const LaunchArgs &L, int64_t items, hipStream_t st, bool ex,
+              hipEvent_t e0, hipEvent_t e1)
+{
+    const int dim = s.mesh->dim;
+    if (dim == 2) {
+        if (s.p.precision == NLQ_FP64_PLAIN) launch_eta<2, 0>(ctx, s.p.kernel, L, items, st, ex, e0, e1);
+        else launch_eta<2, 1>(ctx, s.p.kernel, L, items, st, ex, e0, e1);
+    } else {
+        if (s.p.precision == NLQ_FP64_PLAIN) launch_eta<3, 0>(ctx, s.p.kernel, L, items, st, ex, e0, e1);
+        else launch_eta<3, 1>(ctx, s.p.kernel, L, items, st, ex, e0, e1);
+    }
 }
 
 // smallest s >= 0 with fl(sqrt(s)) >= t (t > 0; sqrt correctly rounded)
@@ -1039,13 +1092,9 @@ double sqrt_threshold(double t)
     return x;
 }
 
-}  // namespace
-
-void launch_integrate(System &s, hipStream_t st, int64_t n_explicit, const int32_t *ex_l,
-                      const int32_t *ex_m, double *ex_out, hipEvent_t e0, hipEvent_t e1)
+AsmArgs make_args(const System &s, const Tables &T)
 {
     const Mesh &m = *s.mesh;
-    const Tables &T = s.ctx->get_tables(m.dim, s.p.lmax);
     if (T.n_sub * T.nq * T.nv >= (int64_t(1) << 31) || T.n_sub >= (1 << 24))
         fail(NLQ_EINVAL, "refinement table too large");
     AsmArgs A{};
@@ -1090,42 +1139,154 @@ void launch_integrate(System &s, hipStream_t st, int64_t n_explicit, const int32
     A.capl = capl;
     // LDS row cache: as long as the longest row, at most 2048 entries per row
     A.rowcap = static_cast<int>(std::min<int64_t>(std::max<int64_t>(s.max_row, 1), 2048));
-    A.counter = s.l_counter.as<unsigned int>();
     A.counters = s.counters.as<AsmCounters>();
-    A.n_explicit = n_explicit;
+    return A;
+}
+
+// Argument block in device memory: counter | AsmArgs[nsys] | seg_sys | seg_lo | seg_start
+struct BlockLayout {
+    size_t off_args, off_sys, off_lo, off_start, bytes;
+    BlockLayout(int nsys, int nseg)
+    {
+        auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
+        off_args = 16;
+        off_sys = al(off_args + sizeof(AsmArgs) * nsys);
+        off_lo = al(off_sys + sizeof(int32_t) * nseg);
+        off_start = al(off_lo + sizeof(int64_t) * nseg);
+        bytes = al(off_start + sizeof(int64_t) * (nseg + 1));
+    }
+};
+
+}  // namespace
+
+void LaunchBlock::ensure(Ctx *ctx, size_t bytes)
+{
+    if (bytes <= cap) return;
+    if (host) (void)hipHostFree(host);
+    host = nullptr;
+    cap = 0;
+    dev.alloc(ctx, bytes);
+    NLQ_HIP(hipHostMalloc(&host, bytes, hipHostMallocDefault));
+    cap = bytes;
+}
+
+LaunchBlock::~LaunchBlock()
+{
+    if (host) (void)hipHostFree(host);
+}
+
+void launch_integrate_jobs(Ctx *ctx, LaunchBlock &lb, const std::vector<IntegrateJob> &jobs, hipStream_t st,
+                           hipEvent_t e0, hipEvent_t e1)
+{
+    if (jobs.empty()) return;
+    if (static_cast<int>(jobs.size()) > kMaxSeg) fail(NLQ_EINVAL, "too many segments in one launch");
+    const System &s0 = *jobs[0].s;
+    std::vector<const System *> systems;
+    std::vector<int32_t> seg_sys;
+    std::vector<int64_t> seg_lo, seg_start{0};
+    for (const auto &j : jobs) {
+        const System &s = *j.s;
+        if (s.mesh->dim != s0.mesh->dim || s.p.precision != s0.p.precision || s.p.kernel != s0.p.kernel)
+            fail(NLQ_EINVAL, "one launch takes systems of one dimension, precision and kernel");
+        if (j.lo < 0 || j.hi > s.mesh->n_elems || j.lo > j.hi) fail(NLQ_EINVAL, "bad outer-element range");
+        int k = 0;
+        while (k < static_cast<int>(systems.size()) && systems[k] != &s) ++k;
+        if (k == static_cast<int>(systems.size())) systems.push_back(&s);
+        seg_sys.push_back(k);
+        seg_lo.push_back(j.lo);
+        seg_start.push_back(seg_start.back() + (j.hi - j.lo));
+    }
+    const int64_t items = seg_start.back();
+    if (items >= (int64_t(1) << 32) - 1) fail(NLQ_EINVAL, "too many outer elements in one launch");
+    const BlockLayout B(static_cast<int>(systems.size()), static_cast<int>(jobs.size()));
+    lb.ensure(ctx, B.bytes);
+    char *h = static_cast<char *>(lb.host);
+    std::memset(h, 0, B.bytes);
+    int capl = 1, rowcap = 1;
+    for (size_t k = 0; k < systems.size(); ++k) {
+        const System &s = *systems[k];
+        const AsmArgs A = make_args(s, ctx->get_tables(s.mesh->dim, s.p.lmax));
+        capl = std::max(capl, A.capl);
+        rowcap = std::max(rowcap, A.rowcap);
+        std::memcpy(h + B.off_args + k * sizeof(AsmArgs), &A, sizeof(AsmArgs));
+    }
+    std::memcpy(h + B.off_sys, seg_sys.data(), sizeof(int32_t) * seg_sys.size());
+    std::memcpy(h + B.off_lo, seg_lo.data(), sizeof(int64_t) * seg_lo.size());
+    std::memcpy(h + B.off_start, seg_start.data(), sizeof(int64_t) * seg_start.size());
+    // a system whose first outer element is in this launch starts from zero
+    for (const auto &j : jobs) {
+        if (j.lo != 0) continue;
+        const System &s = *j.s;
+        NLQ_HIP(hipMemsetAsync(s.counters.as<void>(), 0, sizeof(AsmCounters), st));
+        NLQ_HIP(hipMemsetAsync(s.val.as<void>(), 0, sizeof(double) * s.nnz, st));
+        NLQ_HIP(hipMemsetAsync(s.dmm.as<void>(), 0, sizeof(double) * s.mesh->n_elems * (s.mesh->dim == 2 ? 6 : 10),
+                               st));
+    }
+    NLQ_HIP(hipMemcpyAsync(lb.dev.as<void>(), h, B.bytes, hipMemcpyHostToDevice, st));
+    char *d = lb.dev.as<char>();
+    LaunchArgs L{};
+    L.sys = reinterpret_cast<const AsmArgs *>(d + B.off_args);
+    L.seg_sys = reinterpret_cast<const int32_t *>(d + B.off_sys);
+    L.seg_lo = reinterpret_cast<const int64_t *>(d + B.off_lo);
+    L.seg_start = reinterpret_cast<const int64_t *>(d + B.off_start);
+    L.nseg = static_cast<int>(jobs.size());
+    L.capl = capl;
+    L.rowcap = rowcap;
+    L.counter = reinterpret_cast<unsigned int *>(d);
+    if (items > 0) dispatch(ctx, s0, L, items, st, false, e0, e1);
+    // systems whose last outer element is in this launch: diagonal blocks and R + R^T
+    for (const auto &j : jobs) {
+        const System &s = *j.s;
+        if (j.hi != s.mesh->n_elems) continue;
+        const int dim = s.mesh->dim;
+        const int four = s.p.form == NLQ_FORM_SYM4;
+        const int64_t nf = s.mesh->n_elems * (dim == 2 ? 6 : 10);
+        const double *dmm = s.dmm.as<double>();
+        const int32_t *elpos = s.elpos.as<int32_t>();
+        double *val = s.val.as<double>();
+        if (nf > 0) {
+            const unsigned gf = static_cast<unsigned>((nf + 255) / 256);
+            if (dim == 2)
+                hipLaunchKernelGGL(k_fold_diag<2>, dim3(gf), dim3(256), 0, st, s.mesh->n_elems, dmm, elpos, val, four);
+            else
+                hipLaunchKernelGGL(k_fold_diag<3>, dim3(gf), dim3(256), 0, st, s.mesh->n_elems, dmm, elpos, val, four);
+            NLQ_CHECK_LAUNCH();
+        }
+        if (four && s.nnz > 0) {
+            hipLaunchKernelGGL(k_symmetrize, dim3(static_cast<unsigned>((s.nnz + 255) / 256)), dim3(256), 0, st,
+                               s.nnz, s.tmap.as<int32_t>(), val);
+            NLQ_CHECK_LAUNCH();
+        }
+    }
+}
+
+void launch_integrate(System &s, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
+{
+    launch_integrate_jobs(s.ctx, s.launch, {IntegrateJob{&s, 0, s.mesh->n_elems}}, st, e0, e1);
+}
+
+void launch_pair_blocks(System &s, hipStream_t st, int64_t n, const int32_t *ex_l, const int32_t *ex_m,
+                        double *ex_out)
+{
+    AsmArgs A = make_args(s, s.ctx->get_tables(s.mesh->dim, s.p.lmax));
+    A.n_explicit = n;
     A.ex_l = ex_l;
     A.ex_m = ex_m;
     A.ex_out = ex_out;
-    NLQ_HIP(hipMemsetAsync(A.counter, 0, sizeof(unsigned int), st));
-    const bool ex = n_explicit > 0;
-    if (!ex) {
-        NLQ_HIP(hipMemsetAsync(A.counters, 0, sizeof(AsmCounters), st));
-        NLQ_HIP(hipMemsetAsync(A.val, 0, sizeof(double) * s.nnz, st));
-        NLQ_HIP(hipMemsetAsync(A.dmm, 0, sizeof(double) * m.n_elems * (m.dim == 2 ? 6 : 10), st));
-    }
-    if (m.dim == 2) {
-        if (s.p.precision == NLQ_FP64_PLAIN) launch_eta<2, 0>(s, A, st, ex, e0, e1);
-        else launch_eta<2, 1>(s, A, st, ex, e0, e1);
-    } else {
-        if (s.p.precision == NLQ_FP64_PLAIN) launch_eta<3, 0>(s, A, st, ex, e0, e1);
-        else launch_eta<3, 1>(s, A, st, ex, e0, e1);
-    }
-    if (ex) return;
-    const int four = s.p.form == NLQ_FORM_SYM4;
-    const int64_t nf = m.n_elems * (m.dim == 2 ? 6 : 10);
-    if (nf > 0) {
-        const unsigned gf = static_cast<unsigned>((nf + 255) / 256);
-        if (m.dim == 2)
-            hipLaunchKernelGGL(k_fold_diag<2>, dim3(gf), dim3(256), 0, st, m.n_elems, A.dmm, A.elpos, A.val, four);
-        else
-            hipLaunchKernelGGL(k_fold_diag<3>, dim3(gf), dim3(256), 0, st, m.n_elems, A.dmm, A.elpos, A.val, four);
-        NLQ_CHECK_LAUNCH();
-    }
-    if (four && s.nnz > 0) {
-        hipLaunchKernelGGL(k_symmetrize, dim3(static_cast<unsigned>((s.nnz + 255) / 256)), dim3(256), 0, st,
-                           s.nnz, A.tmap, A.val);
-        NLQ_CHECK_LAUNCH();
-    }
+    const BlockLayout B(1, 1);
+    s.launch.ensure(s.ctx, B.bytes);
+    char *h = static_cast<char *>(s.launch.host);
+    std::memset(h, 0, B.bytes);
+    std::memcpy(h + B.off_args, &A, sizeof(AsmArgs));
+    NLQ_HIP(hipMemcpyAsync(s.launch.dev.as<void>(), h, B.bytes, hipMemcpyHostToDevice, st));
+    char *d = s.launch.dev.as<char>();
+    LaunchArgs L{};
+    L.sys = reinterpret_cast<const AsmArgs *>(d + B.off_args);
+    L.nseg = 1;
+    L.capl = A.capl;
+    L.rowcap = A.rowcap;
+    L.counter = reinterpret_cast<unsigned int *>(d);
+    if (n > 0) dispatch(s.ctx, s, L, n, st, true, nullptr, nullptr);
 }
 
 }  // namespace nlq

@@ -17,6 +17,8 @@
 
 #include "nlq.h"
 
+struct nlq_system;
+
 namespace nlq {
 
 struct Error {
@@ -124,6 +126,19 @@ struct AsmCounters {
     int pad;
 };
 
+// Pinned host + device staging of a launch's argument block.  The host side is
+// rewritten by the next launch, so a caller synchronises the stream in between.
+struct LaunchBlock {
+    DevBuf dev;
+    void *host = nullptr;
+    size_t cap = 0;
+    void ensure(Ctx *ctx, size_t bytes);
+    LaunchBlock() = default;
+    LaunchBlock(const LaunchBlock &) = delete;
+    LaunchBlock &operator=(const LaunchBlock &) = delete;
+    ~LaunchBlock();
+};
+
 struct System {
     Ctx *ctx = nullptr;
     const Mesh *mesh = nullptr;
@@ -147,19 +162,35 @@ struct System {
     // rhs / solution
     DevBuf F, Ft, u, g;          // [n] double
     DevBuf counters;             // AsmCounters
-    DevBuf l_counter;            // unsigned int
+    LaunchBlock launch;          // argument block of this system's own launches
     nlq_assemble_info info{};
     bool has_rhs = false;
     std::vector<double> h_g;
 };
 
 // kernels launched from the runtime (defined in the .hip files)
+// Assembly steps of the runtime (nlq_capi.cpp): everything up to the
+// integration (returns with st synchronised), the counters of a finished
+// integration into info, and both plus the system's own integration launch.
+std::unique_ptr<nlq_system> prepare_system(Ctx &ctx, const Mesh &mesh, const nlq_params &params, hipStream_t st);
+void collect_counters(System &s, hipStream_t st);
+void run_integrate(System &s, hipStream_t st);
+
 void launch_elem_tables(System &s, hipStream_t st);
 void build_pairs(System &s, hipStream_t st);
 void build_pattern(System &s, hipStream_t st);
-void launch_integrate(System &s, hipStream_t st, int64_t n_explicit, const int32_t *ex_l,
-                      const int32_t *ex_m, double *ex_out, hipEvent_t ev_start = nullptr,
-                      hipEvent_t ev_stop = nullptr);
+// Outer elements [lo, hi) of system s.  One launch takes up to 32 ranges of
+// systems of one dimension, precision and kernel; a range starting at 0 clears
+// the system's values first, a range ending at n_elems finishes its matrix.
+struct IntegrateJob {
+    System *s;
+    int64_t lo, hi;
+};
+void launch_integrate_jobs(Ctx *ctx, LaunchBlock &lb, const std::vector<IntegrateJob> &jobs, hipStream_t st,
+                           hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+void launch_integrate(System &s, hipStream_t st, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+void launch_pair_blocks(System &s, hipStream_t st, int64_t n, const int32_t *ex_l, const int32_t *ex_m,
+                        double *ex_out);
 void launch_load_lift(System &s, hipStream_t st, const double *f_dev, const double *g_dev);
 int cg_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, int *converged);
 void launch_box_mesh(int dim, int n, int k_gamma, double *coords, int32_t *conn,

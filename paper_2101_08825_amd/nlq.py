@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTREA
 EXPORTS = [
     "nlq_ctx_create", "nlq_ctx_set_stream", "nlq_ctx_memory", "nlq_ctx_destroy",
     "nlq_mesh_create", "nlq_mesh_box", "nlq_mesh_info", "nlq_mesh_copy", "nlq_mesh_destroy",
-    "nlq_assemble", "nlq_assemble_info_get", "nlq_reassemble", "nlq_set_data",
+    "nlq_assemble", "nlq_assemble_batch", "nlq_assemble_info_get", "nlq_reassemble", "nlq_set_data",
     "nlq_set_data_device", "nlq_solve", "nlq_solution_device",
     "nlq_info", "nlq_csr_copy", "nlq_csr_device", "nlq_pairs_copy", "nlq_rhs_copy",
     "nlq_pair_blocks", "nlq_system_destroy", "nlq_serve_start", "nlq_submit", "nlq_wait",
@@ -97,6 +97,7 @@ def lib():
             "nlq_mesh_copy": [vp, vp, vp, vp],
             "nlq_mesh_destroy": [vp],
             "nlq_assemble": [vp, vp, P(nlq_params), P(vp)],
+            "nlq_assemble_batch": [vp, i32, vp, vp, vp],
             "nlq_assemble_info_get": [vp, P(nlq_assemble_info)],
             "nlq_reassemble": [vp],
             "nlq_set_data": [vp, vp, vp],
@@ -228,12 +229,24 @@ class Mesh:
 
 
 class System:
-    def __init__(self, ctx: Context, mesh: Mesh, prm: nlq_params):
-        h = C.c_void_p()
-        _check(lib().nlq_assemble(ctx.h, mesh.h, C.byref(prm), C.byref(h)))
+    def __init__(self, ctx: Context, mesh: Mesh, prm: nlq_params, handle=None):
+        h = handle
+        if h is None:
+            h = C.c_void_p()
+            _check(lib().nlq_assemble(ctx.h, mesh.h, C.byref(prm), C.byref(h)))
         self.h = h
         self.ctx, self.mesh, self.prm = ctx, mesh, prm
         mesh._systems.add(self)
+
+    @staticmethod
+    def batch(ctx: Context, meshes, prms):
+        """nlq_assemble_batch: systems whose integrations share launches."""
+        n = len(meshes)
+        mh = (C.c_void_p * n)(*[m.h.value for m in meshes])
+        pa = (nlq_params * n)(*prms)
+        out = (C.c_void_p * n)()
+        _check(lib().nlq_assemble_batch(ctx.h, n, mh, pa, out))
+        return [System(ctx, meshes[i], prms[i], handle=C.c_void_p(out[i])) for i in range(n)]
 
     def info(self):
         i = nlq_assemble_info()
