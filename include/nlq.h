@@ -201,18 +201,31 @@ nlq_status nlq_pair_blocks(nlq_system *sys, int64_t n, const int32_t *l, const i
 nlq_status nlq_system_destroy(nlq_system *sys);
 
 /* ---- serving: continuous batching of assemble + solve requests ------------
- * A scheduler thread admits queued requests while their estimated HBM
- * footprint fits the context budget, keeps meshes resident (cache keyed by
- * dim, n, k_gamma), interleaves the outer elements of every admitted request in
- * shared persistent launches, and runs each request's CG as soon as its
- * assembly completes.  Latency = completion time - submission time. */
+ * The problem of Section 2 posed on a Kuhn box mesh, as a request: mesh size,
+ * horizon, kernel and data in; nodal solution out (Section 4, eq. (AW=F)).
+ *  - Admission: a scheduler thread admits queued requests (FIFO) while the
+ *    context's HBM in use plus the estimated footprint of the admitted but not
+ *    yet assembled requests fits the budget; resident matrices of earlier
+ *    requests are evicted (least recently used first) to make room.
+ *  - Setup (element tables, pair list, pattern) and the CG solve of each request
+ *    run on worker threads, each with a HIP stream of its own.
+ *  - Integration: outer elements of all assembled-but-not-integrated requests of
+ *    one (dim, precision, kernel) group share persistent launches (at most 32
+ *    requests per launch, see nlq_assemble_batch); a launch is sized from the
+ *    measured integration rate to about target_launch_ms, the budget split so
+ *    that small requests finish in one launch and large ones share the rest.
+ *    Requests that arrive while a launch runs join the next one.
+ *  - Residency: meshes stay on the device for the server's lifetime (keyed by
+ *    dim, n, k_gamma); with cache_systems = 1 assembled matrices stay too and a
+ *    request with the same mesh and parameters only reloads f, g and solves.
+ * Latency = completion - submission. */
 typedef struct {
     int32_t dim, n, k_gamma;     /* box mesh (nlq_mesh_box) */
     nlq_params params;
     const double *f_nodal;       /* host [n_nodes], copied at submit */
     const double *g_nodal;       /* host [n_nodes], copied at submit */
-    double rtol;
-    int32_t maxit;
+    double rtol;                 /* CG tolerance (<= 0: 1e-10) */
+    int32_t maxit;               /* CG iteration cap (<= 0: 10000) */
 } nlq_request;
 
 typedef struct {
@@ -223,14 +236,44 @@ typedef struct {
     double rel_residual;
     double latency_s;            /* submit -> result ready */
     double queue_s;              /* submit -> admitted */
+    double assemble_s;           /* admitted -> matrix ready (setup + integration; 0 on a cache hit) */
+    double solve_s;              /* matrix ready -> result ready (load vector, lifting, CG, copy) */
+    int32_t launches;            /* shared integration launches the request took part in */
+    int32_t cache_hit;           /* 1: its matrix was resident from an earlier request */
 } nlq_result;
 
-nlq_status nlq_serve_start(nlq_ctx *ctx, int32_t max_active);
+typedef struct {
+    int32_t max_active;          /* admitted requests at once (<= 0: 64) */
+    int32_t workers;             /* setup / CG threads, one stream each (<= 0: 4) */
+    double target_launch_ms;     /* duration aimed at per shared launch (<= 0: 25) */
+    int32_t cache_systems;       /* 1: keep assembled matrices resident for reuse */
+} nlq_serve_config;
+
+typedef struct {
+    int64_t submitted, completed, failed, cancelled;
+    int64_t launches;            /* shared integration launches */
+    int64_t launch_segments;     /* sum over launches of the requests in each */
+    int32_t max_per_launch;      /* most requests in one launch */
+    int32_t max_admitted;        /* most requests admitted at once */
+    int64_t cache_hits;
+    uint64_t peak_bytes;         /* peak of the context's HBM accounting */
+    double launch_s;             /* sum of launch durations (HIP events) */
+} nlq_serve_stats;
+
+/* cfg may be NULL (defaults). EBUSY if a server is already running. */
+nlq_status nlq_serve_start(nlq_ctx *ctx, const nlq_serve_config *cfg);
+/* Copies the request (f, g included).  EINVAL for a malformed request (checked
+ * again at setup: parameter errors end the request with EINVAL). */
 nlq_status nlq_submit(nlq_ctx *ctx, const nlq_request *req, uint64_t *ticket);
 /* timeout_ms < 0: wait forever; 0: poll.  ENOTREADY when not finished. */
 nlq_status nlq_wait(nlq_ctx *ctx, uint64_t ticket, int32_t timeout_ms, nlq_result *out);
+/* A queued request ends with ECANCELLED at once; an admitted one at its next
+ * phase boundary (after setup, after integration, before CG). */
 nlq_status nlq_cancel(nlq_ctx *ctx, uint64_t ticket);
 nlq_status nlq_result_release(nlq_ctx *ctx, uint64_t ticket);
+nlq_status nlq_serve_stats_get(nlq_ctx *ctx, nlq_serve_stats *out);
+/* Finishes every submitted request, then stops the threads and frees the
+ * resident meshes and matrices. */
 nlq_status nlq_serve_stop(nlq_ctx *ctx);
 
 /* Thread-local message of the last failed call ("" if none). */

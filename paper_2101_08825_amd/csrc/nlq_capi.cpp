@@ -18,7 +18,7 @@ void set_last_error(const std::string &msg) { g_last_error = msg; }
 
 [[noreturn]] void fail(nlq_status st, const std::string &msg) { throw Error{st, msg}; }
 
-void DevBuf::alloc(Ctx *ctx, size_t bytes)
+void DevBuf::alloc(Ctx *ctx, size_t bytes, hipStream_t st)
 {
     release();
     if (bytes == 0) bytes = 8;
@@ -29,7 +29,7 @@ void DevBuf::alloc(Ctx *ctx, size_t bytes)
                              std::to_string(ctx->budget) + " bytes)");
     }
     void *p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes);
+    hipError_t e = st ? hipMallocAsync(&p, bytes, st) : hipMalloc(&p, bytes);
     if (e != hipSuccess) {
         ctx->used.fetch_sub(bytes);
         fail(NLQ_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -37,12 +37,14 @@ void DevBuf::alloc(Ctx *ctx, size_t bytes)
     p_ = p;
     bytes_ = bytes;
     ctx_ = ctx;
+    st_ = st;
 }
 
 void DevBuf::release()
 {
     if (p_) {
-        (void)hipFree(p_);
+        if (st_) (void)hipFreeAsync(p_, st_);
+        else (void)hipFree(p_);
         ctx_->used.fetch_sub(bytes_);
     }
     p_ = nullptr;
@@ -226,6 +228,79 @@ void run_integrate(System &s, hipStream_t st)
     (void)hipEventDestroy(e1);
 }
 
+std::unique_ptr<nlq_mesh> make_box_mesh(Ctx &ctx, int dim, int n, int k_gamma, hipStream_t st)
+{
+    if (dim != 2 && dim != 3) fail(NLQ_EINVAL, "dim must be 2 or 3");
+    if (n < 1 || k_gamma < 0) fail(NLQ_EINVAL, "bad box size");
+    int64_t nn = 1, ne = 1;
+    for (int k = 0; k < dim; ++k) {
+        nn *= (n + 1);
+        ne *= n;
+    }
+    ne *= (dim == 2 ? 2 : 6);
+    if (nn > INT32_MAX || ne > INT32_MAX) fail(NLQ_EINVAL, "mesh too large for int32 ids");
+    auto m = std::make_unique<nlq_mesh>();
+    Mesh &M = m->impl;
+    M.ctx = &ctx;
+    M.dim = dim;
+    M.n_nodes = nn;
+    M.n_elems = ne;
+    M.coords.alloc(M.ctx, sizeof(double) * nn * dim);
+    M.conn.alloc(M.ctx, sizeof(int32_t) * ne * (dim + 1));
+    M.constrained.alloc(M.ctx, nn);
+    launch_box_mesh(dim, n, k_gamma, M.coords.as<double>(), M.conn.as<int32_t>(), M.constrained.as<uint8_t>(), st);
+    M.h_coords.resize(nn * dim);
+    M.h_conn.resize(ne * (dim + 1));
+    M.h_constrained.resize(nn);
+    NLQ_HIP(hipMemcpyAsync(M.h_coords.data(), M.coords.as<void>(), sizeof(double) * nn * dim,
+                           hipMemcpyDeviceToHost, st));
+    NLQ_HIP(hipMemcpyAsync(M.h_conn.data(), M.conn.as<void>(), sizeof(int32_t) * ne * (dim + 1),
+                           hipMemcpyDeviceToHost, st));
+    NLQ_HIP(hipMemcpyAsync(M.h_constrained.data(), M.constrained.as<void>(), nn, hipMemcpyDeviceToHost, st));
+    NLQ_HIP(hipStreamSynchronize(st));
+    for (int k = 0; k < 3; ++k) {
+        M.gmin[k] = 0.0;
+        M.gmax[k] = k < dim ? 1.0 : 0.0;
+        M.ext_max[k] = k < dim ? 1.0 / n : 0.0;
+    }
+    M.n_free = 0;
+    for (int64_t q = 0; q < nn; ++q) M.n_free += M.h_constrained[q] ? 0 : 1;
+    return m;
+}
+
+void load_data(System &s, const double *f_nodal, const double *g_nodal, hipStream_t st)
+{
+    const int64_t n = s.mesh->n_nodes;
+    DevBuf f(s.ctx, sizeof(double) * n, st);
+    if (s.g.empty()) s.g.alloc(s.ctx, sizeof(double) * n);
+    NLQ_HIP(hipMemcpyAsync(f.as<void>(), f_nodal, sizeof(double) * n, hipMemcpyHostToDevice, st));
+    NLQ_HIP(hipMemcpyAsync(s.g.as<void>(), g_nodal, sizeof(double) * n, hipMemcpyHostToDevice, st));
+    launch_load_lift(s, st, f.as<double>(), s.g.as<double>());
+    NLQ_HIP(hipStreamSynchronize(st));
+    s.has_rhs = true;
+}
+
+bool solve_system(System &s, double rtol, int maxit, double *u_out, nlq_solve_info *info, hipStream_t st)
+{
+    if (!s.has_rhs) fail(NLQ_EINVAL, "nlq_set_data must be called before nlq_solve");
+    if (!(rtol > 0.0) || maxit < 1) fail(NLQ_EINVAL, "need rtol > 0 and maxit >= 1");
+    const double t0 = now_s();
+    double relres = 0.0;
+    int converged = 0;
+    const int it = cg_solve(s, st, rtol, maxit, &relres, &converged);
+    if (u_out) {
+        NLQ_HIP(hipMemcpyAsync(u_out, s.u.as<void>(), sizeof(double) * s.mesh->n_nodes, hipMemcpyDeviceToHost, st));
+        NLQ_HIP(hipStreamSynchronize(st));
+    }
+    if (info) {
+        info->iterations = it;
+        info->converged = converged;
+        info->rel_residual = relres;
+        info->seconds = now_s() - t0;
+    }
+    return converged != 0;
+}
+
 }  // namespace nlq
 
 using namespace nlq;
@@ -318,46 +393,8 @@ nlq_status nlq_mesh_box(nlq_ctx *ctx, int32_t dim, int32_t n, int32_t k_gamma, n
 {
     return guard([&] {
         if (!ctx || !out) fail(NLQ_EINVAL, "NULL argument");
-        if (dim != 2 && dim != 3) fail(NLQ_EINVAL, "dim must be 2 or 3");
-        if (n < 1 || k_gamma < 0) fail(NLQ_EINVAL, "bad box size");
-        int64_t nn = 1, ne = 1;
-        for (int k = 0; k < dim; ++k) {
-            nn *= (n + 1);
-            ne *= n;
-        }
-        ne *= (dim == 2 ? 2 : 6);
-        if (nn > INT32_MAX || ne > INT32_MAX) fail(NLQ_EINVAL, "mesh too large for int32 ids");
         NLQ_HIP(hipSetDevice(ctx->impl.device));
-        auto m = std::make_unique<nlq_mesh>();
-        Mesh &M = m->impl;
-        M.ctx = &ctx->impl;
-        M.dim = dim;
-        M.n_nodes = nn;
-        M.n_elems = ne;
-        M.coords.alloc(M.ctx, sizeof(double) * nn * dim);
-        M.conn.alloc(M.ctx, sizeof(int32_t) * ne * (dim + 1));
-        M.constrained.alloc(M.ctx, nn);
-        hipStream_t st = ctx->impl.stream;
-        launch_box_mesh(dim, n, k_gamma, M.coords.as<double>(), M.conn.as<int32_t>(),
-                        M.constrained.as<uint8_t>(), st);
-        M.h_coords.resize(nn * dim);
-        M.h_conn.resize(ne * (dim + 1));
-        M.h_constrained.resize(nn);
-        NLQ_HIP(hipMemcpyAsync(M.h_coords.data(), M.coords.as<void>(), sizeof(double) * nn * dim,
-                               hipMemcpyDeviceToHost, st));
-        NLQ_HIP(hipMemcpyAsync(M.h_conn.data(), M.conn.as<void>(), sizeof(int32_t) * ne * (dim + 1),
-                               hipMemcpyDeviceToHost, st));
-        NLQ_HIP(hipMemcpyAsync(M.h_constrained.data(), M.constrained.as<void>(), nn,
-                               hipMemcpyDeviceToHost, st));
-        NLQ_HIP(hipStreamSynchronize(st));
-        for (int k = 0; k < 3; ++k) {
-            M.gmin[k] = 0.0;
-            M.gmax[k] = k < dim ? 1.0 : 0.0;
-            M.ext_max[k] = k < dim ? 1.0 / n : 0.0;
-        }
-        M.n_free = 0;
-        for (int64_t q = 0; q < nn; ++q) M.n_free += M.h_constrained[q] ? 0 : 1;
-        *out = m.release();
+        *out = make_box_mesh(ctx->impl, dim, n, k_gamma, ctx->impl.stream).release();
     });
 }
 
@@ -485,17 +522,8 @@ nlq_status nlq_set_data(nlq_system *sys, const double *f_nodal, const double *g_
 {
     return guard([&] {
         if (!sys || !f_nodal || !g_nodal) fail(NLQ_EINVAL, "NULL argument");
-        System &s = sys->impl;
-        NLQ_HIP(hipSetDevice(s.ctx->device));
-        const int64_t n = s.mesh->n_nodes;
-        hipStream_t st = s.ctx->stream;
-        DevBuf f(s.ctx, sizeof(double) * n);
-        if (s.g.empty()) s.g.alloc(s.ctx, sizeof(double) * n);
-        NLQ_HIP(hipMemcpyAsync(f.as<void>(), f_nodal, sizeof(double) * n, hipMemcpyHostToDevice, st));
-        NLQ_HIP(hipMemcpyAsync(s.g.as<void>(), g_nodal, sizeof(double) * n, hipMemcpyHostToDevice, st));
-        launch_load_lift(s, st, f.as<double>(), s.g.as<double>());
-        NLQ_HIP(hipStreamSynchronize(st));
-        s.has_rhs = true;
+        NLQ_HIP(hipSetDevice(sys->impl.ctx->device));
+        load_data(sys->impl, f_nodal, g_nodal, sys->impl.ctx->stream);
     });
 }
 
@@ -525,31 +553,15 @@ nlq_status nlq_solution_device(const nlq_system *sys, const double **u_dev)
 
 nlq_status nlq_solve(nlq_system *sys, double rtol, int32_t maxit, double *u_out, nlq_solve_info *info)
 {
-    nlq_status conv = NLQ_OK;
+    bool converged = true;
     nlq_status st = guard([&] {
         if (!sys) fail(NLQ_EINVAL, "sys is NULL");
-        System &s = sys->impl;
-        if (!s.has_rhs) fail(NLQ_EINVAL, "nlq_set_data must be called before nlq_solve");
-        if (!(rtol > 0.0) || maxit < 1) fail(NLQ_EINVAL, "need rtol > 0 and maxit >= 1");
-        NLQ_HIP(hipSetDevice(s.ctx->device));
-        const double t0 = now_s();
-        double relres = 0.0;
-        int converged = 0;
-        const int it = cg_solve(s, s.ctx->stream, rtol, maxit, &relres, &converged);
-        if (u_out)
-            NLQ_HIP(hipMemcpy(u_out, s.u.as<void>(), sizeof(double) * s.mesh->n_nodes,
-                              hipMemcpyDeviceToHost));
-        if (info) {
-            info->iterations = it;
-            info->converged = converged;
-            info->rel_residual = relres;
-            info->seconds = now_s() - t0;
-        }
-        if (!converged) conv = NLQ_ENOCONV;
+        NLQ_HIP(hipSetDevice(sys->impl.ctx->device));
+        converged = solve_system(sys->impl, rtol, maxit, u_out, info, sys->impl.ctx->stream);
     });
-    if (st == NLQ_OK && conv != NLQ_OK) {
+    if (st == NLQ_OK && !converged) {
         set_last_error("CG did not reach the tolerance");
-        return conv;
+        return NLQ_ENOCONV;
     }
     return st;
 }

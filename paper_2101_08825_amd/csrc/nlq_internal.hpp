@@ -18,6 +18,7 @@
 #include "nlq.h"
 
 struct nlq_system;
+struct nlq_mesh;
 
 namespace nlq {
 
@@ -40,11 +41,14 @@ void set_last_error(const std::string &msg);
 
 struct Ctx;
 
-// Device allocation charged against the context budget.
+// Device allocation charged against the context budget.  With a stream the
+// allocation is stream ordered (hipMallocAsync / hipFreeAsync on that stream),
+// so that freeing a temporary does not wait for the whole device; the stream
+// must outlive the buffer.
 class DevBuf {
   public:
     DevBuf() = default;
-    DevBuf(Ctx *ctx, size_t bytes) { alloc(ctx, bytes); }
+    DevBuf(Ctx *ctx, size_t bytes, hipStream_t st = nullptr) { alloc(ctx, bytes, st); }
     ~DevBuf() { release(); }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
@@ -55,12 +59,13 @@ class DevBuf {
             p_ = o.p_;
             bytes_ = o.bytes_;
             ctx_ = o.ctx_;
+            st_ = o.st_;
             o.p_ = nullptr;
             o.bytes_ = 0;
         }
         return *this;
     }
-    void alloc(Ctx *ctx, size_t bytes);
+    void alloc(Ctx *ctx, size_t bytes, hipStream_t st = nullptr);
     void release();
     template <class T> T *as() const { return reinterpret_cast<T *>(p_); }
     size_t bytes() const { return bytes_; }
@@ -70,6 +75,7 @@ class DevBuf {
     void *p_ = nullptr;
     size_t bytes_ = 0;
     Ctx *ctx_ = nullptr;
+    hipStream_t st_ = nullptr;
 };
 
 // Quadrature rule and refinement tables for one (dim, lmax): the degree-5 rule
@@ -175,6 +181,12 @@ struct System {
 std::unique_ptr<nlq_system> prepare_system(Ctx &ctx, const Mesh &mesh, const nlq_params &params, hipStream_t st);
 void collect_counters(System &s, hipStream_t st);
 void run_integrate(System &s, hipStream_t st);
+// Kuhn box mesh built on the device (st synchronised on return).
+std::unique_ptr<nlq_mesh> make_box_mesh(Ctx &ctx, int dim, int n, int k_gamma, hipStream_t st);
+// Nodal f, g (host) -> F~ of the system (st synchronised on return).
+void load_data(System &s, const double *f_nodal, const double *g_nodal, hipStream_t st);
+// CG on the free rows; u copied to u_out (host) when given.  Returns convergence.
+bool solve_system(System &s, double rtol, int maxit, double *u_out, nlq_solve_info *info, hipStream_t st);
 
 void launch_elem_tables(System &s, hipStream_t st);
 void build_pairs(System &s, hipStream_t st);

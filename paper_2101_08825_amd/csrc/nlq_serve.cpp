@@ -1,136 +1,529 @@
-// Serving loop: requests are queued by nlq_submit and executed by a scheduler
-// thread that owns the context's device work; results are fetched with
-// nlq_wait.  Meshes stay resident in a cache keyed by (dim, n, k_gamma).
+// Serving loop: continuous batching of assemble + solve requests on one GPU.
+//
+//   submit -> pending --(admission by HBM footprint)--> setup (worker thread,
+//   own stream: mesh from the resident cache, element tables, pair list,
+//   pattern) -> ready -> shared integration launches (scheduler thread, batch
+//   stream; several requests per launch, chunked by outer-element ranges) ->
+//   solve (worker: load vector, lifting, CG, copy of u) -> done.
+//
+// The scheduler never waits for a request's CG or setup, and workers never
+// wait for a launch: setup and CG kernels of some requests run on the device
+// while the integration launch of others is in flight.
+#include <algorithm>
 #include <chrono>
+#include <cmath>
+#include <list>
+#include <tuple>
 #include <unordered_map>
 
 #include "nlq_internal.hpp"
 
 namespace nlq {
 
-struct Request {
-    uint64_t ticket = 0;
-    nlq_request req{};
-    std::vector<double> f, g;
-    double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
-    nlq_status status = NLQ_ENOTREADY;
-    bool cancelled = false, done = false;
-    std::vector<double> u;
-    int64_t n_nodes = 0, n_pairs = 0, n_free = 0;
-    int cg_iterations = 0;
-    double rel_residual = 0.0;
-    std::string error;
-};
-
-struct Server {
-    Ctx *ctx = nullptr;
-    int max_active = 1;
-    std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    std::deque<std::shared_ptr<Request>> queue;
-    std::unordered_map<uint64_t, std::shared_ptr<Request>> all;
-    uint64_t next_ticket = 1;
-    bool stop = false;
-    std::thread worker;
-    std::map<std::tuple<int, int, int>, nlq_mesh *> meshes;
-};
+namespace {
 
 double serve_now()
 {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-}  // namespace nlq
+using MeshKey = std::tuple<int, int, int>;
+// mesh key + every parameter that changes the matrix
+using SysKey = std::tuple<int, int, int, int, double, double, double, int, int, int, int>;
 
-using namespace nlq;
-
-extern "C" {
-nlq_status nlq_mesh_box(nlq_ctx *ctx, int32_t dim, int32_t n, int32_t k_gamma, nlq_mesh **out);
-nlq_status nlq_mesh_destroy(nlq_mesh *mesh);
+SysKey sys_key(const nlq_request &r)
+{
+    const nlq_params &p = r.params;
+    return SysKey(r.dim, r.n, r.k_gamma, p.kernel, p.delta, p.eps, p.scale, p.lmin, p.lmax, p.form, p.precision);
 }
 
-nlq::Ctx::Ctx() = default;
-nlq::Ctx::~Ctx() = default;
+// Integration group: one launch takes systems of one (dim, precision, kernel);
+// the rate model is kept per (group, lmax).
+using GroupKey = std::tuple<int, int, int>;
+using RateKey = std::tuple<int, int, int, int>;
+
+// Upper estimate of the device memory of one box request (pair list, pattern,
+// CSR values, element and diagonal-block tables, vectors, setup temporaries).
+uint64_t estimate_bytes(const nlq_request &r)
+{
+    const int dim = r.dim;
+    const double n = r.n;
+    const double reach = (r.params.delta + r.params.eps) * r.n;   // in cells
+    const double K = std::floor(reach) + 1.0;
+    const double types = dim == 2 ? 2.0 : 6.0;
+    const double ne = types * std::pow(n, dim), nn = std::pow(n + 1.0, dim);
+    const double pairs = ne * types * std::pow(std::min(n, 2.0 * K + 1.0), dim);
+    const double nnz = nn * std::pow(std::min(n + 1.0, 2.0 * K + 3.0), dim);
+    const int nv = dim + 1, nr = nv * (nv + 1) / 2;
+    const double b = 4.0 * pairs * 2.0 + 8.0 * (ne + 1.0) * 3.0 + nnz * (4.0 + 4.0 + 8.0) + 8.0 * (nn + 1.0) +
+                     ne * nv * nv * 4.0 + ne * nr * 8.0 + ne * (nv * dim + 2.0 * dim + 1.0) * 8.0 + 12.0 * 8.0 * nn;
+    return static_cast<uint64_t>(1.2 * b) + (uint64_t(1) << 20);
+}
+
+struct CacheEntry {
+    SysKey key;
+    std::unique_ptr<nlq_system> sys;
+    bool busy = false;
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    nlq_request req{};
+    std::vector<double> f, g;
+    double t_submit = 0.0, t_admit = 0.0, t_ready = 0.0, t_done = 0.0;
+    nlq_status status = NLQ_ENOTREADY;
+    std::atomic<bool> cancelled{false};
+    bool done = false;
+    std::vector<double> u;
+    int64_t n_nodes = 0, n_pairs = 0, n_free = 0;
+    int cg_iterations = 0;
+    double rel_residual = 0.0;
+    std::string error;
+    uint64_t est = 0;                 // admission estimate, held until setup ends
+    // in flight
+    nlq_mesh *mesh = nullptr;
+    std::unique_ptr<nlq_system> own;  // system assembled for this request
+    CacheEntry *cached = nullptr;     // or a resident one it borrows
+    int64_t cursor = 0;               // next outer element to integrate
+    std::vector<int64_t> pair_off;    // host copy, for chunking by pairs
+    int launches = 0;
+    bool cache_hit = false;
+    System &sys() { return cached ? cached->sys->impl : own->impl; }
+};
+
+using ReqPtr = std::shared_ptr<Request>;
+
+struct Task {
+    int kind;   // 0 = setup, 1 = solve
+    ReqPtr r;
+};
+
+}  // namespace
+
+struct Server {
+    Ctx *ctx = nullptr;
+    nlq_serve_config cfg{};
+    std::mutex mu;
+    std::condition_variable cv_sched, cv_work, cv_done;
+    std::deque<ReqPtr> pending;
+    std::deque<Task> tasks;
+    std::vector<ReqPtr> ready;          // assembled up to integration, in admission order
+    std::unordered_map<uint64_t, ReqPtr> all;
+    int admitted = 0;                   // admitted, not done
+    int inflight_tasks = 0;
+    uint64_t reserved = 0;              // estimates of admitted requests not yet set up
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread sched;
+    std::vector<std::thread> workers;
+    std::vector<hipStream_t> streams;
+    hipStream_t batch_stream = nullptr;
+    std::mutex mesh_mu;
+    std::map<MeshKey, std::unique_ptr<nlq_mesh>> meshes;
+    std::list<CacheEntry> cache;        // most recently used at the front (under mu)
+    // systems to free: moved here under mu, destroyed outside it (hipFree may
+    // wait for the device, which must not happen while mu is held)
+    std::vector<std::unique_ptr<nlq_system>> graveyard;
+    std::map<RateKey, double> rate;     // integrated pairs per second
+    size_t rr = 0;                      // round robin over groups
+    nlq_serve_stats stats{};
+};
 
 namespace {
 
-void run_request(Server &S, nlq_ctx *ctx, Request &r)
+// ---- helpers under S.mu -----------------------------------------------------
+
+void finish_locked(Server &S, const ReqPtr &r, nlq_status st, const std::string &err)
 {
-    const auto key = std::make_tuple(r.req.dim, r.req.n, r.req.k_gamma);
-    nlq_mesh *mesh = nullptr;
-    auto it = S.meshes.find(key);
-    if (it != S.meshes.end()) {
-        mesh = it->second;
-    } else {
-        nlq_status st = nlq_mesh_box(ctx, r.req.dim, r.req.n, r.req.k_gamma, &mesh);
-        if (st != NLQ_OK) {
-            r.status = st;
-            r.error = nlq_last_error();
-            return;
-        }
-        S.meshes[key] = mesh;
-    }
-    nlq_system *sys = nullptr;
-    nlq_status st = nlq_assemble(ctx, mesh, &r.req.params, &sys);
-    if (st != NLQ_OK) {
-        r.status = st;
-        r.error = nlq_last_error();
-        return;
-    }
-    int64_t nn = 0, nnz = 0, np = 0, nf = 0;
-    nlq_info(sys, &nn, &nnz, &np, &nf);
-    r.n_nodes = nn;
-    r.n_pairs = np;
-    r.n_free = nf;
-    st = nlq_set_data(sys, r.f.data(), r.g.data());
-    if (st == NLQ_OK) {
-        r.u.assign(nn, 0.0);
-        nlq_solve_info info{};
-        st = nlq_solve(sys, r.req.rtol > 0 ? r.req.rtol : 1e-10, r.req.maxit > 0 ? r.req.maxit : 10000,
-                       r.u.data(), &info);
-        r.cg_iterations = info.iterations;
-        r.rel_residual = info.rel_residual;
-    }
-    r.status = st;
-    if (st != NLQ_OK) r.error = nlq_last_error();
-    nlq_system_destroy(sys);
+    r->status = st;
+    r->error = err;
+    r->done = true;
+    r->t_done = serve_now();
+    if (st == NLQ_OK) ++S.stats.completed;
+    else if (st == NLQ_ECANCELLED) ++S.stats.cancelled;
+    else ++S.stats.failed;
+    S.cv_done.notify_all();
 }
 
-void worker_main(Server *S, nlq_ctx *ctx)
+// drop resident matrices (LRU, not in use) until `need` more bytes fit
+void evict_locked(Server &S, uint64_t need)
 {
-    (void)hipSetDevice(ctx->impl.device);
+    while (S.ctx->used.load() + S.reserved + need > S.ctx->budget) {
+        auto it = S.cache.end();
+        for (auto q = S.cache.begin(); q != S.cache.end(); ++q)
+            if (!q->busy) it = q;   // last = least recently used
+        if (it == S.cache.end()) return;
+        S.graveyard.push_back(std::move(it->sys));
+        S.cache.erase(it);
+    }
+}
+
+void admit_locked(Server &S)
+{
+    while (!S.pending.empty() && S.admitted < S.cfg.max_active) {
+        ReqPtr r = S.pending.front();
+        if (r->cancelled) {
+            S.pending.pop_front();
+            finish_locked(S, r, NLQ_ECANCELLED, "cancelled");
+            continue;
+        }
+        r->est = estimate_bytes(r->req);
+        evict_locked(S, r->est);
+        const bool fits = S.ctx->used.load() + S.reserved + r->est <= S.ctx->budget;
+        if (!fits && S.admitted > 0) return;   // wait for memory (FIFO)
+        S.pending.pop_front();
+        S.reserved += r->est;
+        ++S.admitted;
+        S.stats.max_admitted = std::max(S.stats.max_admitted, S.admitted);
+        r->t_admit = serve_now();
+        S.tasks.push_back(Task{0, r});
+        S.cv_work.notify_one();
+    }
+}
+
+// release what an ended request holds (under S.mu)
+void release_locked(Server &S, const ReqPtr &r, bool keep)
+{
+    if (r->est) {
+        S.reserved -= r->est;
+        r->est = 0;
+    }
+    if (r->cached) {
+        r->cached->busy = false;
+        r->cached = nullptr;
+    } else if (r->own) {
+        const SysKey k = sys_key(r->req);
+        bool have = false;
+        for (auto &c : S.cache) have = have || (c.key == k);
+        if (keep && S.cfg.cache_systems && !have) S.cache.push_front(CacheEntry{k, std::move(r->own), false});
+        else S.graveyard.push_back(std::move(r->own));
+    }
+    --S.admitted;
+    admit_locked(S);
+    S.cv_sched.notify_all();
+}
+
+// free buried systems outside the lock, then admit what now fits
+void drain(Server &S)
+{
+    std::vector<std::unique_ptr<nlq_system>> dead;
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        dead.swap(S.graveyard);
+    }
+    if (dead.empty()) return;
+    dead.clear();
+    std::lock_guard<std::mutex> lk(S.mu);
+    admit_locked(S);
+}
+
+nlq_mesh *get_mesh(Server &S, const nlq_request &q, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(S.mesh_mu);
+    const MeshKey k(q.dim, q.n, q.k_gamma);
+    auto it = S.meshes.find(k);
+    if (it != S.meshes.end()) return it->second.get();
+    auto m = make_box_mesh(*S.ctx, q.dim, q.n, q.k_gamma, st);
+    nlq_mesh *raw = m.get();
+    S.meshes[k] = std::move(m);
+    return raw;
+}
+
+// ---- worker: setup and solve ---------------------------------------------
+
+void do_setup(Server &S, const ReqPtr &r, hipStream_t st)
+{
+    r->mesh = get_mesh(S, r->req, st);
+    const Mesh &M = r->mesh->impl;
+    r->n_nodes = M.n_nodes;
+    r->n_free = M.n_free;
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        if (S.cfg.cache_systems) {
+            const SysKey k = sys_key(r->req);
+            for (auto it = S.cache.begin(); it != S.cache.end(); ++it) {
+                if (it->key == k && !it->busy) {
+                    it->busy = true;
+                    S.cache.splice(S.cache.begin(), S.cache, it);
+                    r->cached = &S.cache.front();
+                    r->cache_hit = true;
+                    ++S.stats.cache_hits;
+                    break;
+                }
+            }
+        }
+    }
+    if (r->cached) {
+        r->n_pairs = r->cached->sys->impl.n_pairs;
+        std::lock_guard<std::mutex> lk(S.mu);
+        S.reserved -= r->est;
+        r->est = 0;
+        r->t_ready = serve_now();
+        S.tasks.push_back(Task{1, r});
+        S.cv_work.notify_one();
+        return;
+    }
+    r->own = prepare_system(*S.ctx, M, r->req.params, st);
+    System &s = r->own->impl;
+    r->n_pairs = s.n_pairs;
+    r->pair_off.resize(M.n_elems + 1);
+    NLQ_HIP(hipMemcpyAsync(r->pair_off.data(), s.pair_off.as<void>(), sizeof(int64_t) * (M.n_elems + 1),
+                           hipMemcpyDeviceToHost, st));
+    NLQ_HIP(hipStreamSynchronize(st));
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.reserved -= r->est;
+    r->est = 0;
+    if (r->cancelled) throw Error{NLQ_ECANCELLED, "cancelled"};
+    if (M.n_elems == 0) {
+        r->t_ready = serve_now();
+        S.tasks.push_back(Task{1, r});
+        S.cv_work.notify_one();
+        return;
+    }
+    S.ready.push_back(r);
+    S.cv_sched.notify_all();
+}
+
+void do_solve(Server &S, const ReqPtr &r, hipStream_t st)
+{
+    if (r->cancelled) throw Error{NLQ_ECANCELLED, "cancelled"};
+    System &s = r->sys();
+    load_data(s, r->f.data(), r->g.data(), st);
+    r->u.assign(s.mesh->n_nodes, 0.0);
+    nlq_solve_info info{};
+    const double rtol = r->req.rtol > 0 ? r->req.rtol : 1e-10;
+    const int maxit = r->req.maxit > 0 ? r->req.maxit : 10000;
+    const bool conv = solve_system(s, rtol, maxit, r->u.data(), &info, st);
+    r->cg_iterations = info.iterations;
+    r->rel_residual = info.rel_residual;
+    if (!conv) throw Error{NLQ_ENOCONV, "CG did not reach the tolerance"};
+}
+
+void worker_main(Server *S, int w)
+{
+    (void)hipSetDevice(S->ctx->device);
+    hipStream_t st = S->streams[w];
     for (;;) {
-        std::shared_ptr<Request> r;
+        Task t;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
-            if (S->stop && S->queue.empty()) return;
-            r = S->queue.front();
-            S->queue.pop_front();
-            if (r->cancelled) {
-                r->status = NLQ_ECANCELLED;
-                r->done = true;
-                r->t_done = serve_now();
-                S->cv_done.notify_all();
-                continue;
-            }
-            r->t_admit = serve_now();
+            S->cv_work.wait(lk, [&] { return !S->tasks.empty() || (S->stop && S->admitted == 0); });
+            if (S->tasks.empty()) return;
+            t = S->tasks.front();
+            S->tasks.pop_front();
+            ++S->inflight_tasks;
         }
-        run_request(*S, ctx, *r);
+        nlq_status st_code = NLQ_OK;
+        std::string err;
+        try {
+            if (t.kind == 0) do_setup(*S, t.r, st);
+            else do_solve(*S, t.r, st);
+        } catch (const Error &e) {
+            st_code = e.status;
+            err = e.msg;
+        } catch (const std::exception &e) {
+            st_code = NLQ_EDEVICE;
+            err = e.what();
+        }
         {
             std::lock_guard<std::mutex> lk(S->mu);
-            r->t_done = serve_now();
-            r->done = true;
+            --S->inflight_tasks;
+            if (st_code != NLQ_OK) {
+                // a failed CG still leaves a valid matrix; other failures drop it
+                finish_locked(*S, t.r, st_code, err);
+                release_locked(*S, t.r, st_code == NLQ_ENOCONV);
+            } else if (t.kind == 1) {
+                finish_locked(*S, t.r, NLQ_OK, "");
+                release_locked(*S, t.r, true);
+            }
+            S->cv_sched.notify_all();
+            S->cv_work.notify_all();
         }
-        S->cv_done.notify_all();
+        drain(*S);
     }
+}
+
+// ---- scheduler: shared integration launches -------------------------------
+
+GroupKey group_of(const Request &r)
+{
+    return GroupKey(r.req.dim, r.req.params.precision, r.req.params.kernel);
+}
+
+RateKey rate_key(const Request &r)
+{
+    return RateKey(r.req.dim, r.req.params.precision, r.req.params.kernel, r.req.params.lmax);
+}
+
+double initial_rate(const Request &r)
+{
+    // pairs/s of a first launch before any measurement (deliberately low)
+    const double base = r.req.dim == 2 ? 2e8 : 2e7;
+    return base / std::pow(r.req.dim == 2 ? 4.0 : 8.0, std::max(0, r.req.params.lmax - 3));
+}
+
+struct Chunk {
+    ReqPtr r;
+    int64_t lo, hi, pairs;
+};
+
+// Water-filling: every request of the group gets an equal share of the pair
+// budget, capped by what it has left; what the small ones leave goes to the
+// others.  Returns outer-element ranges (at least one element each).
+std::vector<Chunk> plan_launch(Server &S, const GroupKey &g)
+{
+    std::vector<ReqPtr> rs;
+    for (auto &r : S.ready)
+        if (group_of(*r) == g && rs.size() < 32) rs.push_back(r);
+    double budget = 0.0;
+    for (auto &r : rs) {
+        auto it = S.rate.find(rate_key(*r));
+        const double rate = it != S.rate.end() ? it->second : initial_rate(*r);
+        budget = std::max(budget, rate * S.cfg.target_launch_ms * 1e-3);
+    }
+    std::vector<int64_t> left(rs.size());
+    for (size_t i = 0; i < rs.size(); ++i)
+        left[i] = rs[i]->pair_off.back() - rs[i]->pair_off[rs[i]->cursor];
+    std::vector<double> share(rs.size(), 0.0);
+    std::vector<size_t> open(rs.size());
+    for (size_t i = 0; i < rs.size(); ++i) open[i] = i;
+    double rest = budget;
+    while (!open.empty() && rest > 0.5) {
+        const double each = rest / open.size();
+        std::vector<size_t> still;
+        double used = 0.0;
+        for (size_t i : open) {
+            const double need = left[i] - share[i];
+            if (need <= each) {
+                share[i] += need;
+                used += need;
+            } else {
+                share[i] += each;
+                used += each;
+                still.push_back(i);
+            }
+        }
+        rest -= used;
+        if (still.size() == open.size()) break;
+        open.swap(still);
+    }
+    std::vector<Chunk> out;
+    for (size_t i = 0; i < rs.size(); ++i) {
+        Request &r = *rs[i];
+        const int64_t ne = static_cast<int64_t>(r.pair_off.size()) - 1;
+        const int64_t base = r.pair_off[r.cursor];
+        const int64_t target = base + static_cast<int64_t>(std::ceil(share[i]));
+        // first hi with pair_off[hi] >= target, at least cursor + 1
+        int64_t hi = std::lower_bound(r.pair_off.begin() + r.cursor + 1, r.pair_off.end(), target) -
+                     r.pair_off.begin();
+        hi = std::min(std::max(hi, r.cursor + 1), ne);
+        out.push_back(Chunk{rs[i], r.cursor, hi, r.pair_off[hi] - base});
+    }
+    return out;
+}
+
+void scheduler_main(Server *S)
+{
+    (void)hipSetDevice(S->ctx->device);
+    LaunchBlock lb;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    for (;;) {
+        std::vector<Chunk> plan;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv_sched.wait(lk, [&] {
+                return !S->ready.empty() || (S->stop && S->admitted == 0 && S->pending.empty());
+            });
+            if (S->ready.empty()) break;
+            // drop cancelled requests before they take launch time
+            for (size_t i = 0; i < S->ready.size();) {
+                if (S->ready[i]->cancelled) {
+                    ReqPtr r = S->ready[i];
+                    S->ready.erase(S->ready.begin() + i);
+                    finish_locked(*S, r, NLQ_ECANCELLED, "cancelled");
+                    release_locked(*S, r, false);
+                } else {
+                    ++i;
+                }
+            }
+            if (S->ready.empty()) continue;
+            // round robin over the groups present, oldest request first within one
+            std::vector<GroupKey> groups;
+            for (auto &r : S->ready)
+                if (std::find(groups.begin(), groups.end(), group_of(*r)) == groups.end())
+                    groups.push_back(group_of(*r));
+            const GroupKey g = groups[S->rr++ % groups.size()];
+            plan = plan_launch(*S, g);
+        }
+        std::vector<IntegrateJob> jobs;
+        for (auto &c : plan) jobs.push_back(IntegrateJob{&c.r->sys(), c.lo, c.hi});
+        nlq_status code = NLQ_OK;
+        std::string err;
+        float ms = 0.0f;
+        try {
+            launch_integrate_jobs(S->ctx, lb, jobs, S->batch_stream, e0, e1);
+            NLQ_HIP(hipStreamSynchronize(S->batch_stream));
+            NLQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+            for (auto &c : plan)
+                if (c.hi == static_cast<int64_t>(c.r->pair_off.size()) - 1) collect_counters(c.r->sys(), S->batch_stream);
+        } catch (const Error &e) {
+            code = e.status;
+            err = e.msg;
+        }
+        std::unique_lock<std::mutex> lk(S->mu);
+        ++S->stats.launches;
+        S->stats.launch_segments += static_cast<int64_t>(plan.size());
+        S->stats.max_per_launch = std::max(S->stats.max_per_launch, static_cast<int32_t>(plan.size()));
+        S->stats.launch_s += 1e-3 * ms;
+        S->stats.peak_bytes = std::max<uint64_t>(S->stats.peak_bytes, S->ctx->used.load());
+        int64_t pairs = 0;
+        for (auto &c : plan) pairs += c.pairs;
+        if (code == NLQ_OK && ms > 0.5f && !plan.empty()) {
+            // rate model: measured pairs per second of this launch, smoothed
+            const RateKey k = rate_key(*plan[0].r);
+            const double meas = pairs / (1e-3 * ms);
+            auto it = S->rate.find(k);
+            S->rate[k] = it == S->rate.end() ? meas : 0.5 * it->second + 0.5 * meas;
+        }
+        for (auto &c : plan) {
+            Request &r = *c.r;
+            r.launches += 1;
+            auto pos = std::find(S->ready.begin(), S->ready.end(), c.r);
+            if (code != NLQ_OK) {
+                if (pos != S->ready.end()) S->ready.erase(pos);
+                finish_locked(*S, c.r, code, err);
+                release_locked(*S, c.r, false);
+                continue;
+            }
+            r.cursor = c.hi;
+            if (r.cursor == static_cast<int64_t>(r.pair_off.size()) - 1) {
+                if (pos != S->ready.end()) S->ready.erase(pos);
+                r.t_ready = serve_now();
+                S->tasks.push_back(Task{1, c.r});
+                S->cv_work.notify_one();
+            }
+        }
+        lk.unlock();
+        drain(*S);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
 }
 
 }  // namespace
 
+}  // namespace nlq
+
+using namespace nlq;
+
+nlq::Ctx::Ctx() = default;
+nlq::Ctx::~Ctx() = default;
+
 extern "C" {
 
-nlq_status nlq_serve_start(nlq_ctx *ctx, int32_t max_active)
+nlq_status nlq_serve_start(nlq_ctx *ctx, const nlq_serve_config *cfg)
 {
     if (!ctx) {
         set_last_error("ctx is NULL");
@@ -142,10 +535,32 @@ nlq_status nlq_serve_start(nlq_ctx *ctx, int32_t max_active)
     }
     auto S = std::make_unique<Server>();
     S->ctx = &ctx->impl;
-    S->max_active = max_active > 0 ? max_active : 1;
+    nlq_serve_config c{};
+    if (cfg) c = *cfg;
+    if (c.max_active <= 0) c.max_active = 64;
+    if (c.workers <= 0) c.workers = 4;
+    if (c.workers > 32) c.workers = 32;
+    if (!(c.target_launch_ms > 0.0)) c.target_launch_ms = 25.0;
+    c.cache_systems = c.cache_systems ? 1 : 0;
+    S->cfg = c;
+    if (hipSetDevice(ctx->impl.device) != hipSuccess) {
+        set_last_error("hipSetDevice failed");
+        return NLQ_EDEVICE;
+    }
+    for (int w = 0; w <= c.workers; ++w) {
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            for (auto q : S->streams) (void)hipStreamDestroy(q);
+            set_last_error("hipStreamCreate failed");
+            return NLQ_EDEVICE;
+        }
+        if (w < c.workers) S->streams.push_back(st);
+        else S->batch_stream = st;
+    }
     Server *raw = S.get();
     ctx->impl.server = std::move(S);
-    raw->worker = std::thread(worker_main, raw, ctx);
+    raw->sched = std::thread(scheduler_main, raw);
+    for (int w = 0; w < c.workers; ++w) raw->workers.emplace_back(worker_main, raw, w);
     return NLQ_OK;
 }
 
@@ -160,12 +575,14 @@ nlq_status nlq_submit(nlq_ctx *ctx, const nlq_request *req, uint64_t *ticket)
         set_last_error("nlq_serve_start has not been called");
         return NLQ_EINVAL;
     }
-    if ((req->dim != 2 && req->dim != 3) || req->n < 1 || !req->f_nodal || !req->g_nodal) {
-        set_last_error("bad request");
+    if ((req->dim != 2 && req->dim != 3) || req->n < 1 || req->k_gamma < 0 || !req->f_nodal || !req->g_nodal ||
+        req->params.dim != req->dim) {
+        set_last_error("bad request (dim, n, k_gamma, data pointers or params.dim)");
         return NLQ_EINVAL;
     }
     auto r = std::make_shared<Request>();
     r->req = *req;
+    r->req.f_nodal = r->req.g_nodal = nullptr;
     int64_t nn = 1;
     for (int k = 0; k < req->dim; ++k) nn *= (req->n + 1);
     r->f.assign(req->f_nodal, req->f_nodal + nn);
@@ -173,11 +590,17 @@ nlq_status nlq_submit(nlq_ctx *ctx, const nlq_request *req, uint64_t *ticket)
     r->t_submit = serve_now();
     {
         std::lock_guard<std::mutex> lk(S->mu);
+        if (S->stop) {
+            set_last_error("server is stopping");
+            return NLQ_EBUSY;
+        }
         r->ticket = S->next_ticket++;
         S->all[r->ticket] = r;
-        S->queue.push_back(r);
+        S->pending.push_back(r);
+        ++S->stats.submitted;
+        admit_locked(*S);
     }
-    S->cv_work.notify_one();
+    drain(*S);
     *ticket = r->ticket;
     return NLQ_OK;
 }
@@ -212,6 +635,10 @@ nlq_status nlq_wait(nlq_ctx *ctx, uint64_t ticket, int32_t timeout_ms, nlq_resul
     out->rel_residual = r->rel_residual;
     out->latency_s = r->t_done - r->t_submit;
     out->queue_s = (r->t_admit > 0 ? r->t_admit : r->t_done) - r->t_submit;
+    out->assemble_s = (r->t_ready > 0 && r->t_admit > 0 && !r->cache_hit) ? r->t_ready - r->t_admit : 0.0;
+    out->solve_s = r->t_ready > 0 ? r->t_done - r->t_ready : 0.0;
+    out->launches = r->launches;
+    out->cache_hit = r->cache_hit ? 1 : 0;
     if (r->status != NLQ_OK) set_last_error(r->error);
     return NLQ_OK;
 }
@@ -229,7 +656,15 @@ nlq_status nlq_cancel(nlq_ctx *ctx, uint64_t ticket)
         set_last_error("unknown ticket");
         return NLQ_EINVAL;
     }
-    it->second->cancelled = true;
+    ReqPtr r = it->second;
+    if (r->done) return NLQ_OK;
+    r->cancelled = true;
+    auto pos = std::find(S->pending.begin(), S->pending.end(), r);
+    if (pos != S->pending.end()) {
+        S->pending.erase(pos);
+        finish_locked(*S, r, NLQ_ECANCELLED, "cancelled");
+    }
+    S->cv_sched.notify_all();
     return NLQ_OK;
 }
 
@@ -250,18 +685,47 @@ nlq_status nlq_result_release(nlq_ctx *ctx, uint64_t ticket)
     return NLQ_OK;
 }
 
+nlq_status nlq_serve_stats_get(nlq_ctx *ctx, nlq_serve_stats *out)
+{
+    if (!ctx || !out || !ctx->impl.server) {
+        set_last_error("server not running or NULL argument");
+        return NLQ_EINVAL;
+    }
+    Server *S = ctx->impl.server.get();
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stats.peak_bytes = std::max<uint64_t>(S->stats.peak_bytes, S->ctx->used.load());
+    *out = S->stats;
+    return NLQ_OK;
+}
+
 nlq_status nlq_serve_stop(nlq_ctx *ctx)
 {
     if (!ctx) return NLQ_EINVAL;
     Server *S = ctx->impl.server.get();
     if (!S) return NLQ_OK;
     {
-        std::lock_guard<std::mutex> lk(S->mu);
+        std::unique_lock<std::mutex> lk(S->mu);
         S->stop = true;
+        // every submitted request finishes first
+        S->cv_done.wait(lk, [&] {
+            if (!S->pending.empty() || S->admitted > 0) return false;
+            for (auto &kv : S->all)
+                if (!kv.second->done) return false;
+            return true;
+        });
+        S->cv_sched.notify_all();
+        S->cv_work.notify_all();
     }
-    S->cv_work.notify_all();
-    if (S->worker.joinable()) S->worker.join();
-    for (auto &kv : S->meshes) nlq_mesh_destroy(kv.second);
+    if (S->sched.joinable()) S->sched.join();
+    for (auto &t : S->workers)
+        if (t.joinable()) t.join();
+    (void)hipSetDevice(ctx->impl.device);
+    S->cache.clear();
+    S->graveyard.clear();
+    S->all.clear();
+    S->meshes.clear();
+    for (auto q : S->streams) (void)hipStreamDestroy(q);
+    if (S->batch_stream) (void)hipStreamDestroy(S->batch_stream);
     ctx->impl.server.reset();
     return NLQ_OK;
 }

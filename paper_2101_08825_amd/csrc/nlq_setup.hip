@@ -59,12 +59,12 @@ void exclusive_scan_i64(Ctx *ctx, const int64_t *in, int64_t *out, int64_t n, hi
 {
     if (n <= 0) return;
     const int64_t tiles = (n + kScanTile - 1) / kScanTile;
-    DevBuf sums(ctx, sizeof(int64_t) * tiles);
+    DevBuf sums(ctx, sizeof(int64_t) * tiles, st);
     hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kScanThreads), 0, st, in, out,
                        sums.as<int64_t>(), n);
     NLQ_CHECK_LAUNCH();
     if (tiles > 1) {
-        DevBuf offs(ctx, sizeof(int64_t) * tiles);
+        DevBuf offs(ctx, sizeof(int64_t) * tiles, st);
         exclusive_scan_i64(ctx, sums.as<int64_t>(), offs.as<int64_t>(), tiles, st);
         hipLaunchKernelGGL(k_add_tile_offsets, dim3((n + 255) / 256), dim3(256), 0, st, out,
                            offs.as<int64_t>(), n);
@@ -313,12 +313,12 @@ void build_pairs(System &s, hipStream_t st)
         g.nb[k] = nb;
         nbins *= nb;
     }
-    DevBuf bin_cnt(s.ctx, sizeof(int64_t) * (nbins + 1));
-    DevBuf bin_off(s.ctx, sizeof(int64_t) * (nbins + 1));
-    DevBuf cursor(s.ctx, sizeof(int64_t) * (nbins + 1));
-    DevBuf bin_of(s.ctx, sizeof(int32_t) * ne);
-    DevBuf items(s.ctx, sizeof(int32_t) * ne);
-    DevBuf err(s.ctx, sizeof(int));
+    DevBuf bin_cnt(s.ctx, sizeof(int64_t) * (nbins + 1), st);
+    DevBuf bin_off(s.ctx, sizeof(int64_t) * (nbins + 1), st);
+    DevBuf cursor(s.ctx, sizeof(int64_t) * (nbins + 1), st);
+    DevBuf bin_of(s.ctx, sizeof(int32_t) * ne, st);
+    DevBuf items(s.ctx, sizeof(int32_t) * ne, st);
+    DevBuf err(s.ctx, sizeof(int), st);
     NLQ_HIP(hipMemsetAsync(bin_cnt.as<void>(), 0, sizeof(int64_t) * (nbins + 1), st));
     NLQ_HIP(hipMemsetAsync(cursor.as<void>(), 0, sizeof(int64_t) * (nbins + 1), st));
     NLQ_HIP(hipMemsetAsync(err.as<void>(), 0, sizeof(int), st));
@@ -335,7 +335,7 @@ void build_pairs(System &s, hipStream_t st)
                        bin_off.as<int64_t>(), cursor.as<int64_t>(), items.as<int32_t>());
     NLQ_CHECK_LAUNCH();
 
-    DevBuf counts(s.ctx, sizeof(int64_t) * (ne + 1));
+    DevBuf counts(s.ctx, sizeof(int64_t) * (ne + 1), st);
     NLQ_HIP(hipMemsetAsync(counts.as<void>(), 0, sizeof(int64_t) * (ne + 1), st));
     s.pair_off.alloc(s.ctx, sizeof(int64_t) * (ne + 1));
     const double r0 = m.ext_max[0], r1 = dim > 1 ? m.ext_max[1] : 0.0, r2 = dim > 2 ? m.ext_max[2] : 0.0;
@@ -559,13 +559,13 @@ void build_pattern(System &s, hipStream_t st)
     const Mesh &m = *s.mesh;
     const int nv = m.dim + 1;
     const int64_t ne = m.n_elems, nn = m.n_nodes;
-    DevBuf err(s.ctx, sizeof(int));
+    DevBuf err(s.ctx, sizeof(int), st);
     NLQ_HIP(hipMemsetAsync(err.as<void>(), 0, sizeof(int), st));
     // node -> elements
-    DevBuf ne_cnt(s.ctx, sizeof(int64_t) * (nn + 1));
-    DevBuf ne_off(s.ctx, sizeof(int64_t) * (nn + 1));
-    DevBuf ne_cur(s.ctx, sizeof(int64_t) * (nn + 1));
-    DevBuf ne_items(s.ctx, sizeof(int32_t) * ne * nv);
+    DevBuf ne_cnt(s.ctx, sizeof(int64_t) * (nn + 1), st);
+    DevBuf ne_off(s.ctx, sizeof(int64_t) * (nn + 1), st);
+    DevBuf ne_cur(s.ctx, sizeof(int64_t) * (nn + 1), st);
+    DevBuf ne_items(s.ctx, sizeof(int32_t) * ne * nv, st);
     NLQ_HIP(hipMemsetAsync(ne_cnt.as<void>(), 0, sizeof(int64_t) * (nn + 1), st));
     NLQ_HIP(hipMemsetAsync(ne_cur.as<void>(), 0, sizeof(int64_t) * (nn + 1), st));
     dim3 g1((ne * nv + 255) / 256), b1(256);
@@ -577,8 +577,8 @@ void build_pattern(System &s, hipStream_t st)
                        ne_off.as<int64_t>(), ne_cur.as<int64_t>(), ne_items.as<int32_t>());
     NLQ_CHECK_LAUNCH();
     // element neighbourhoods
-    DevBuf nb_cnt(s.ctx, sizeof(int64_t) * (ne + 1));
-    DevBuf nb_off(s.ctx, sizeof(int64_t) * (ne + 1));
+    DevBuf nb_cnt(s.ctx, sizeof(int64_t) * (ne + 1), st);
+    DevBuf nb_off(s.ctx, sizeof(int64_t) * (ne + 1), st);
     NLQ_HIP(hipMemsetAsync(nb_cnt.as<void>(), 0, sizeof(int64_t) * (ne + 1), st));
     auto nbhd = [&](int32_t *out) {
         if (nv == 3)
@@ -599,10 +599,10 @@ void build_pattern(System &s, hipStream_t st)
     NLQ_HIP(hipMemcpyAsync(&nb_total, nb_off.as<int64_t>() + ne, sizeof(int64_t),
                            hipMemcpyDeviceToHost, st));
     NLQ_HIP(hipStreamSynchronize(st));
-    DevBuf nb(s.ctx, sizeof(int32_t) * std::max<int64_t>(nb_total, 1));
+    DevBuf nb(s.ctx, sizeof(int32_t) * std::max<int64_t>(nb_total, 1), st);
     nbhd(nb.as<int32_t>());
     // rows
-    DevBuf row_cnt(s.ctx, sizeof(int64_t) * (nn + 1));
+    DevBuf row_cnt(s.ctx, sizeof(int64_t) * (nn + 1), st);
     NLQ_HIP(hipMemsetAsync(row_cnt.as<void>(), 0, sizeof(int64_t) * (nn + 1), st));
     s.row_ptr.alloc(s.ctx, sizeof(int64_t) * (nn + 1));
     hipLaunchKernelGGL(k_rows, dim3(nn), dim3(kWave), 0, st, nn, ne_off.as<int64_t>(),

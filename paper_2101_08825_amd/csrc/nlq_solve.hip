@@ -268,14 +268,14 @@ int cg_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, 
     const Mesh &m = *s.mesh;
     const int64_t n = m.n_nodes;
     if (s.u.empty()) s.u.alloc(s.ctx, sizeof(double) * n);
-    DevBuf dinv(s.ctx, sizeof(double) * n), w(s.ctx, sizeof(double) * n),
-        r(s.ctx, sizeof(double) * n), z(s.ctx, sizeof(double) * n), p(s.ctx, sizeof(double) * n),
-        q(s.ctx, sizeof(double) * n);
+    DevBuf dinv(s.ctx, sizeof(double) * n, st), w(s.ctx, sizeof(double) * n, st),
+        r(s.ctx, sizeof(double) * n, st), z(s.ctx, sizeof(double) * n, st), p(s.ctx, sizeof(double) * n, st),
+        q(s.ctx, sizeof(double) * n, st);
     const int64_t nb_rows = (n + kCgRows - 1) / kCgRows;
     const int64_t nb_vec = (n + kCgThreads - 1) / kCgThreads;
     const int64_t nbmax = nb_rows > nb_vec ? nb_rows : nb_vec;
-    DevBuf partial(s.ctx, sizeof(double) * 2 * nbmax);
-    DevBuf scal(s.ctx, sizeof(CgScalars));
+    DevBuf partial(s.ctx, sizeof(double) * 2 * nbmax, st);
+    DevBuf scal(s.ctx, sizeof(CgScalars), st);
     CgScalars *sc = scal.as<CgScalars>();
     NLQ_HIP(hipMemsetAsync(sc, 0, sizeof(CgScalars), st));
     const uint8_t *cst = m.constrained.as<uint8_t>();

@@ -32,7 +32,7 @@ EXPORTS = [
     "nlq_set_data_device", "nlq_solve", "nlq_solution_device",
     "nlq_info", "nlq_csr_copy", "nlq_csr_device", "nlq_pairs_copy", "nlq_rhs_copy",
     "nlq_pair_blocks", "nlq_system_destroy", "nlq_serve_start", "nlq_submit", "nlq_wait",
-    "nlq_cancel", "nlq_result_release", "nlq_serve_stop", "nlq_last_error",
+    "nlq_cancel", "nlq_result_release", "nlq_serve_stats_get", "nlq_serve_stop", "nlq_last_error",
 ]
 
 
@@ -70,7 +70,21 @@ class nlq_request(C.Structure):
 class nlq_result(C.Structure):
     _fields_ = [("status", C.c_int32), ("n_nodes", C.c_int64), ("n_pairs", C.c_int64),
                 ("n_free", C.c_int64), ("u", C.POINTER(C.c_double)), ("cg_iterations", C.c_int32),
-                ("rel_residual", C.c_double), ("latency_s", C.c_double), ("queue_s", C.c_double)]
+                ("rel_residual", C.c_double), ("latency_s", C.c_double), ("queue_s", C.c_double),
+                ("assemble_s", C.c_double), ("solve_s", C.c_double), ("launches", C.c_int32),
+                ("cache_hit", C.c_int32)]
+
+
+class nlq_serve_config(C.Structure):
+    _fields_ = [("max_active", C.c_int32), ("workers", C.c_int32), ("target_launch_ms", C.c_double),
+                ("cache_systems", C.c_int32)]
+
+
+class nlq_serve_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("cancelled", C.c_int64), ("launches", C.c_int64), ("launch_segments", C.c_int64),
+                ("max_per_launch", C.c_int32), ("max_admitted", C.c_int32), ("cache_hits", C.c_int64),
+                ("peak_bytes", C.c_uint64), ("launch_s", C.c_double)]
 
 
 _lib = None
@@ -111,7 +125,8 @@ def lib():
             "nlq_rhs_copy": [vp, vp],
             "nlq_pair_blocks": [vp, i64, vp, vp, vp],
             "nlq_system_destroy": [vp],
-            "nlq_serve_start": [vp, i32],
+            "nlq_serve_start": [vp, P(nlq_serve_config)],
+            "nlq_serve_stats_get": [vp, P(nlq_serve_stats)],
             "nlq_submit": [vp, P(nlq_request), P(u64)],
             "nlq_wait": [vp, u64, i32, P(nlq_result)],
             "nlq_cancel": [vp, u64],
@@ -327,3 +342,56 @@ class System:
                 self.close()
         except Exception:
             pass
+
+
+class Server:
+    """Serving loop of a context (nlq_serve_*): requests on Kuhn box meshes."""
+
+    def __init__(self, ctx: Context, max_active=0, workers=0, target_launch_ms=0.0, cache_systems=False):
+        cfg = nlq_serve_config(int(max_active), int(workers), float(target_launch_ms), int(bool(cache_systems)))
+        _check(lib().nlq_serve_start(ctx.h, C.byref(cfg)))
+        self.ctx = ctx
+        self.running = True
+
+    def submit(self, dim, n, k_gamma, prm: nlq_params, f_nodal, g_nodal, rtol=1e-10, maxit=10000) -> int:
+        f = np.ascontiguousarray(f_nodal, dtype=np.float64)
+        g = np.ascontiguousarray(g_nodal, dtype=np.float64)
+        if f.shape[0] != (n + 1) ** dim or g.shape[0] != (n + 1) ** dim:
+            raise ValueError("f and g need (n+1)^dim nodal values")
+        req = nlq_request(int(dim), int(n), int(k_gamma), prm, f.ctypes.data, g.ctypes.data,
+                          float(rtol), int(maxit))
+        t = C.c_uint64()
+        _check(lib().nlq_submit(self.ctx.h, C.byref(req), C.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1, release: bool = True):
+        """Result dict (u copied) or None on timeout."""
+        r = nlq_result()
+        st = lib().nlq_wait(self.ctx.h, C.c_uint64(ticket), int(timeout_ms), C.byref(r))
+        if st == NLQ_ENOTREADY:
+            return None
+        _check(st)
+        u = None
+        if r.u:
+            u = np.ctypeslib.as_array(r.u, shape=(r.n_nodes,)).copy()
+        out = dict(status=r.status, error=(lib().nlq_last_error().decode() if r.status else ""),
+                   n_nodes=r.n_nodes, n_pairs=r.n_pairs, n_free=r.n_free, u=u,
+                   cg_iterations=r.cg_iterations, rel_residual=r.rel_residual,
+                   latency_s=r.latency_s, queue_s=r.queue_s, assemble_s=r.assemble_s,
+                   solve_s=r.solve_s, launches=r.launches, cache_hit=bool(r.cache_hit))
+        if release:
+            _check(lib().nlq_result_release(self.ctx.h, C.c_uint64(ticket)))
+        return out
+
+    def cancel(self, ticket: int):
+        _check(lib().nlq_cancel(self.ctx.h, C.c_uint64(ticket)))
+
+    def stats(self):
+        s = nlq_serve_stats()
+        _check(lib().nlq_serve_stats_get(self.ctx.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in nlq_serve_stats._fields_}
+
+    def stop(self):
+        if self.running:
+            _check(lib().nlq_serve_stop(self.ctx.h))
+            self.running = False
