@@ -1,12 +1,17 @@
 """Benchmark of the hot path on one MI355X.
 
-A step is one pass of the whole path (element tables, pair list, CSR pattern,
-Algorithm 1 + leaf integration, FP64 CSR accumulation, load vector + lifting,
-CG solve) for each of the two 2D 128x128 problems (delta = 2h and 4h,
-eps = delta/32, depth <= 5, constant kernel, u = x1^2 + x2^2).  Mesh and data
-are resident in HBM before the timed region.  The value is element-pair
-integrals per second of the FP32-mixed path; the FP64 plain path is timed on the
-same steps; per-request assemble+solve latency percentiles are reported.
+Throughput: a step is one pass of the whole path (element tables, pair list,
+CSR pattern, Algorithm 1 + leaf integration, FP64 CSR accumulation, load vector
++ lifting, CG solve) for each of the two 2D 128x128 problems (delta = 2h and
+4h, eps = delta/32, depth <= 5, constant kernel, u = x1^2 + x2^2).  Mesh and
+data are resident in HBM before the timed region.  The value is element-pair
+integrals per second of the FP32-mixed path; the FP64 plain path is timed on
+the same steps.
+
+Latency: the seeded serving stream (Poisson arrivals at 20/s; 2D meshes 8^2 ..
+96^2 and 3D 6^3 .. 20^3, sizes uniform in log; delta in {2h, 3h, 4h},
+eps = delta/16, depth 3; random quadratic u) replayed open loop against the
+library's serving loop, once per precision; p50 / p99 of submit -> solution.
 """
 from __future__ import annotations
 
@@ -35,6 +40,13 @@ def flops_per_eval(dim: int) -> int:
     nv = dim + 1
     rows = nv + nv * (nv - 1) // 2
     return dim + 2 * dim + 2 * rows - 1
+
+
+T0 = time.perf_counter()
+
+
+def progress(msg):
+    print(f"[bench {time.perf_counter() - T0:7.1f}s] {msg}", file=sys.stderr, flush=True)
 
 
 def percentile(xs, q):
@@ -71,8 +83,58 @@ def run_steps(nlq, ctx, setups, precision, steps, warmup, torch):
         else:
             lat.clear()
         pairs_per_step, evals_per_step = pairs, evals
+        progress(f"precision {precision} step {it + 1}/{warmup + steps} {1e3 * dt:.1f} ms")
     return dict(step_times=step_times, lat=lat, kernel=kernel, pairs=pairs_per_step,
                 evals=evals_per_step)
+
+
+def serve_replay(nlq, ctx, precision, n_requests, cache):
+    """Open-loop replay of the first n_requests of the seeded serving stream."""
+    reqs = W.serving_stream()[:n_requests]
+    srv = nlq.Server(ctx, cache_systems=cache)
+    data = []
+    for r in reqs:
+        mesh = W.kuhn_mesh(r.dim, r.n, r.k_delta)
+        _, f, g = W.nodal_data(mesh, r.u)
+        delta = r.k_delta / r.n
+        prm = nlq.params(r.dim, delta, delta / r.eps_div, r.lmax, precision=precision)
+        data.append((r, prm, f, g))
+    t0 = time.perf_counter()
+    tickets = []
+    for (r, prm, f, g) in data:
+        wait = r.arrival_s - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        tickets.append(srv.submit(r.dim, r.n, r.k_delta, prm, f, g, rtol=1e-10))
+    progress(f"serving precision {precision}: {len(tickets)} requests submitted")
+    res = []
+    deadline = time.perf_counter() + 240.0
+    for k, t in enumerate(tickets):
+        while True:
+            x = srv.wait(t, timeout_ms=5000)
+            if x is not None:
+                break
+            st = srv.stats()
+            progress(f"serving precision {precision}: waiting for request {k}: {st}")
+            if time.perf_counter() > deadline:
+                progress("serving did not finish within 240 s; exiting without stopping the server")
+                os._exit(3)
+        res.append(x)
+        progress(f"serving precision {precision}: request {k} done in {1e3 * x['latency_s']:.1f} ms "
+                 f"(dim {reqs[k].dim}, n {reqs[k].n}, {x['n_pairs']} pairs, {x['launches']} launches)")
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.stop()
+    bad = [x for x in res if x["status"] != 0]
+    if bad:
+        raise RuntimeError(f"serving: {len(bad)} requests failed: {bad[0]['error']}")
+    lat = [x["latency_s"] for x in res]
+    pairs = sum(x["n_pairs"] for x in res)
+    return {"requests": len(res), "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
+            "mean_ms": 1e3 * float(np.mean(lat)), "wall_s": wall, "pairs": pairs,
+            "launches": st["launches"], "mean_requests_per_launch": st["launch_segments"] / max(st["launches"], 1),
+            "max_requests_per_launch": st["max_per_launch"], "max_admitted": st["max_admitted"],
+            "cache_hits": st["cache_hits"], "peak_hbm_gib": st["peak_bytes"] / 2**30}
 
 
 def cpu_baseline(sample_frac=0.10, seed=0):
@@ -95,6 +157,7 @@ def cpu_baseline(sample_frac=0.10, seed=0):
         t0 = time.perf_counter()
         oracle.assemble(m, prm, off, pm, rp, col, sel=sel, nthreads=nt)
         secs += time.perf_counter() - t0
+        progress(f"cpu baseline {name} done")
         pairs += int(np.sum(off[sel + 1] - off[sel]))
         nsel += k
     return {"value": pairs / secs, "unit": "pairs/s", "cores": nt, "kind": "oracle",
@@ -110,14 +173,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-cache", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("this build runs on one GPU only: the path has no cross-GPU sharding "
               "(see the design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    progress("importing torch")
     import torch
     from paper_2101_08825_amd import nlq
     assert torch.cuda.is_available(), "bench needs the GPU"
+    progress("torch ready")
     torch.cuda.init()
     ctx = nlq.Context(0)
     ctx.set_stream(torch.cuda.current_stream().cuda_stream)
@@ -136,6 +203,12 @@ def main():
     plain = None
     if not args.skip_fp64:
         plain = run_steps(nlq, ctx, setups, nlq.NLQ_FP64_PLAIN, args.steps, args.warmup, torch)
+
+    serve = serve64 = None
+    if args.serve_requests > 0:
+        serve = serve_replay(nlq, ctx, nlq.NLQ_FP32_MIXED, args.serve_requests, bool(args.serve_cache))
+        if not args.skip_fp64:
+            serve64 = serve_replay(nlq, ctx, nlq.NLQ_FP64_PLAIN, args.serve_requests, bool(args.serve_cache))
 
     ms = 1e3 * float(np.mean(mixed["step_times"]))
     value = mixed["pairs"] / (ms * 1e-3)
@@ -165,8 +238,9 @@ def main():
             "kernel_evals_per_step": mixed["evals"],
             "precision": "fp32 kernel evaluation + fp32 matrix-core contraction, fp64 blocks/CSR/CG",
         },
-        "latency_ms": {"p50": 1e3 * percentile(mixed["lat"], 50),
-                       "p99": 1e3 * percentile(mixed["lat"], 99)},
+        "latency_ms": ({"p50": serve["p50_ms"], "p99": serve["p99_ms"], "source": "serving stream"}
+                       if serve else {"p50": 1e3 * percentile(mixed["lat"], 50),
+                                      "p99": 1e3 * percentile(mixed["lat"], 99), "source": "128^2 steps"}),
         "roofline": {
             "bound": "alu",
             "achieved": achieved,
@@ -179,17 +253,27 @@ def main():
             "kernel_ms_per_step": 1e3 * kt / args.steps,
         },
     }
+    if serve:
+        out["serving"] = dict(serve, workload=f"first {serve['requests']} requests of the seeded stream "
+                              "(Poisson 20/s, 2D 8^2..96^2 / 3D 6^3..20^3, delta 2h..4h, eps delta/16, "
+                              "depth 3), open loop", matrix_cache=bool(args.serve_cache))
+    if serve64:
+        out["serving_fp64_plain"] = serve64
+    out["c2_request_ms"] = {"p50": 1e3 * percentile(mixed["lat"], 50), "p99": 1e3 * percentile(mixed["lat"], 99)}
     if plain is not None:
         pms = 1e3 * float(np.mean(plain["step_times"]))
         pkt = sum(t for t, _ in plain["kernel"])
         out["fp64_plain"] = {
             "value": plain["pairs"] / (pms * 1e-3),
             "ms_per_step": pms,
-            "latency_ms": {"p50": 1e3 * percentile(plain["lat"], 50),
-                           "p99": 1e3 * percentile(plain["lat"], 99)},
+            "latency_ms": ({"p50": serve64["p50_ms"], "p99": serve64["p99_ms"], "source": "serving stream"}
+                           if serve64 else {"p50": 1e3 * percentile(plain["lat"], 50),
+                                            "p99": 1e3 * percentile(plain["lat"], 99), "source": "128^2 steps"}),
             "kernel_ms_per_step": 1e3 * pkt / args.steps,
         }
         out["speedup_vs_fp64_plain"] = out["value"] / out["fp64_plain"]["value"]
+        if serve and serve64:
+            out["p99_speedup_vs_fp64_plain"] = serve64["p99_ms"] / serve["p99_ms"]
     for (m, *_rest) in setups:
         m.close()
     ctx.close()

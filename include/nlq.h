@@ -207,8 +207,10 @@ nlq_status nlq_system_destroy(nlq_system *sys);
  *    context's HBM in use plus the estimated footprint of the admitted but not
  *    yet assembled requests fits the budget; resident matrices of earlier
  *    requests are evicted (least recently used first) to make room.
- *  - Setup (element tables, pair list, pattern) and the CG solve of each request
- *    run on worker threads, each with a HIP stream of its own.
+ *  - One device thread owns the GPU and time-slices it; each pass: the CG of
+ *    every request whose matrix is ready, the setup (element tables, pair list,
+ *    pattern) of the admitted requests (for about two launch targets), then one
+ *    shared integration launch.
  *  - Integration: outer elements of all assembled-but-not-integrated requests of
  *    one (dim, precision, kernel) group share persistent launches (at most 32
  *    requests per launch, see nlq_assemble_batch); a launch is sized from the
@@ -244,7 +246,6 @@ typedef struct {
 
 typedef struct {
     int32_t max_active;          /* admitted requests at once (<= 0: 64) */
-    int32_t workers;             /* setup / CG threads, one stream each (<= 0: 4) */
     double target_launch_ms;     /* duration aimed at per shared launch (<= 0: 25) */
     int32_t cache_systems;       /* 1: keep assembled matrices resident for reuse */
 } nlq_serve_config;

@@ -88,6 +88,7 @@ struct AsmArgs {
     double *dmm;          // [ne][NR] upper-triangle diagonal-block sums per element
     float f_delta, f_inv_eps, f_delta_over_eps, f_dme2, f_dpe2, f_inv_delta2;
     int lmin, lmax, form;
+    int split;            // work items per outer element (pair list cut in equal parts)
     int capl;             // refinement-list capacity this system needs
     int rowcap;           // LDS row cache this system would like
     AsmCounters *counters;
@@ -101,10 +102,14 @@ struct AsmArgs {
 // address space, so that every field is a scalar load of a uniform address.
 typedef const __attribute__((address_space(4))) AsmArgs CArgs;
 
-// One launch integrates segments [seg_lo, seg_lo + len) of outer elements of
-// one or more systems (same dim, precision and kernel); work item w of the
-// flat counter lies in the segment k with seg_start[k] <= w < seg_start[k+1].
+// One launch integrates segments of outer elements [seg_lo, seg_lo + n) of one
+// or more systems (same dim, precision and kernel).  Every outer element of a
+// system is cut into `split` work items (equal parts of its pair list), so a
+// segment holds n * split items; work item w of the flat counter lies in the
+// segment k with seg_start[k] <= w < seg_start[k+1].
 constexpr int kMaxSeg = 32;
+// largest part of one J_l handled as one work item (a workgroup's unit of work)
+constexpr int64_t kPairsPerItem = 512;
 struct LaunchArgs {
     const AsmArgs *sys;
     const int32_t *seg_sys;
@@ -888,6 +893,7 @@ k_integrate(LaunchArgs L)
     __shared__ int64_t s_seg[kMaxSeg + 1];
     __shared__ int64_t s_item;
     __shared__ int s_sys;
+    __shared__ int s_part;
     __shared__ int s_next;
     __shared__ unsigned long long s_leaf[10];
     __shared__ RowCache s_rc;
@@ -907,19 +913,22 @@ k_integrate(LaunchArgs L)
         if (threadIdx.x == 0) {
             const int64_t w = atomicAdd(L.counter, 1u);
             int64_t item = -1;
-            int sys = 0;
+            int sys = 0, part = 0;
             if (w < total) {
                 int lo = 0, hi = L.nseg - 1;   // last segment with s_seg[k] <= w
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
                     if (s_seg[mid] <= w) lo = mid; else hi = mid - 1;
                 }
-                item = L.seg_lo[lo] + (w - s_seg[lo]);
                 sys = L.seg_sys[lo];
+                const int split = L.sys[sys].split;
+                const int64_t i = w - s_seg[lo];
+                item = L.seg_lo[lo] + i / split;
+                part = static_cast<int>(i % split);
             }
             s_item = item;
             s_sys = sys;
-            s_next = 0;
+            s_part = part;
         }
         if (threadIdx.x < NR) s_bll[threadIdx.x] = 0.0;
         if (threadIdx.x < 10) s_leaf[threadIdx.x] = 0ull;
@@ -944,11 +953,16 @@ k_integrate(LaunchArgs L)
         __syncthreads();
         const int64_t b0 = A.pair_off[l];
         const int nJ = static_cast<int>(A.pair_off[l + 1] - b0);
+        // this item's part of J_l
+        const int chunk = (nJ + A.split - 1) / A.split;
+        const int p_lo = min(nJ, s_part * chunk), p_hi = min(nJ, p_lo + chunk);
+        if (threadIdx.x == 0) s_next = p_lo;
+        __syncthreads();
         for (;;) {
             int p = 0;
             if (lane_id() == 0) p = atomicAdd(&s_next, 1);
             p = bcast0(p);
-            if (p >= nJ) break;
+            if (p >= p_hi) break;
             const int32_t m = A.pair_m[b0 + p];
             process_pair<DIM, PREC, ETA>(A, static_cast<int>(l), m, wmem, s_rule, s_w32, s_T, s_desc,
                                          s_bll, &s_rc, nullptr, s_leaf);
@@ -959,7 +973,8 @@ k_integrate(LaunchArgs L)
             unsafeAtomicAdd(&A.dmm[l * NR + threadIdx.x], s_bll[threadIdx.x]);
         if (threadIdx.x >= 1 && threadIdx.x <= A.lmax && s_leaf[threadIdx.x])
             atomicAdd(&A.counters->leaf[threadIdx.x], s_leaf[threadIdx.x]);
-        if (threadIdx.x == 0) atomicAdd(&A.counters->pairs_done, static_cast<unsigned long long>(nJ));
+        if (threadIdx.x == 0 && p_hi > p_lo)
+            atomicAdd(&A.counters->pairs_done, static_cast<unsigned long long>(p_hi - p_lo));
         __syncthreads();
     }
 }
@@ -1040,19 +1055,29 @@ __global__ void __launch_bounds__(256) k_symmetrize(int64_t nnz, const int32_t *
     }
 }
 
+// workgroups per CU of one launch and its dynamic LDS bytes
 template <int DIM, int PREC, int ETA>
-void launch_one(Ctx *ctx, const LaunchArgs &L, int64_t items, hipStream_t st, bool explicit_mode,
-                hipEvent_t e0, hipEvent_t e1)
+int occupancy(int capl, int rowcap, bool explicit_mode, int *lds_out)
 {
-    const int per_wave = WaveMem<DIM, PREC>::bytes(L.capl);
-    const int lds = kWaves * per_wave + (explicit_mode ? 0 : (DIM + 1) * L.rowcap * 4);
+    const int per_wave = WaveMem<DIM, PREC>::bytes(capl);
+    const int lds = kWaves * per_wave + (explicit_mode ? 0 : (DIM + 1) * rowcap * 4);
     if (lds > 150 * 1024) fail(NLQ_EINVAL, "lmax too large for the per-wave refinement lists");
     auto kern = explicit_mode ? k_pair_blocks<DIM, PREC, ETA> : k_integrate<DIM, PREC, ETA>;
     NLQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     int per_cu = 0;
     NLQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, lds));
-    if (per_cu < 1) per_cu = 1;
+    if (lds_out) *lds_out = lds;
+    return per_cu < 1 ? 1 : per_cu;
+}
+
+template <int DIM, int PREC, int ETA>
+void launch_one(Ctx *ctx, const LaunchArgs &L, int64_t items, hipStream_t st, bool explicit_mode,
+                hipEvent_t e0, hipEvent_t e1)
+{
+    int lds = 0;
+    const int per_cu = occupancy<DIM, PREC, ETA>(L.capl, L.rowcap, explicit_mode, &lds);
+    auto kern = explicit_mode ? k_pair_blocks<DIM, PREC, ETA> : k_integrate<DIM, PREC, ETA>;
     int64_t grid = static_cast<int64_t>(ctx->n_cu) * per_cu;
     if (grid > items) grid = items;
     if (grid < 1) grid = 1;
@@ -1081,6 +1106,12 @@ void dispatch(Ctx *ctx, const System &s, const LaunchArgs &L, int64_t items, hip
         if (s.p.precision == NLQ_FP64_PLAIN) launch_eta<3, 0>(ctx, s.p.kernel, L, items, st, ex, e0, e1);
         else launch_eta<3, 1>(ctx, s.p.kernel, L, items, st, ex, e0, e1);
     }
+}
+
+// work items per outer element of a system
+int split_of(const System &s)
+{
+    return static_cast<int>(std::max<int64_t>(1, (s.max_pairs + kPairsPerItem - 1) / kPairsPerItem));
 }
 
 // smallest s >= 0 with fl(sqrt(s)) >= t (t > 0; sqrt correctly rounded)
@@ -1140,6 +1171,7 @@ AsmArgs make_args(const System &s, const Tables &T)
     // LDS row cache: as long as the longest row, at most 2048 entries per row
     A.rowcap = static_cast<int>(std::min<int64_t>(std::max<int64_t>(s.max_row, 1), 2048));
     A.counters = s.counters.as<AsmCounters>();
+    A.split = static_cast<int>(std::max<int64_t>(1, (s.max_pairs + kPairsPerItem - 1) / kPairsPerItem));
     return A;
 }
 
@@ -1194,7 +1226,7 @@ void launch_integrate_jobs(Ctx *ctx, LaunchBlock &lb, const std::vector<Integrat
         if (k == static_cast<int>(systems.size())) systems.push_back(&s);
         seg_sys.push_back(k);
         seg_lo.push_back(j.lo);
-        seg_start.push_back(seg_start.back() + (j.hi - j.lo));
+        seg_start.push_back(seg_start.back() + (j.hi - j.lo) * split_of(s));
     }
     const int64_t items = seg_start.back();
     if (items >= (int64_t(1) << 32) - 1) fail(NLQ_EINVAL, "too many outer elements in one launch");
@@ -1259,6 +1291,28 @@ void launch_integrate_jobs(Ctx *ctx, LaunchBlock &lb, const std::vector<Integrat
         }
     }
 }
+
+int64_t integrate_slots(Ctx *ctx, const System &s)
+{
+    const AsmArgs A = make_args(s, ctx->get_tables(s.mesh->dim, s.p.lmax));
+    int per_cu = 1;
+    const bool gauss = s.p.kernel == NLQ_ETA_GAUSS;
+    const bool plain = s.p.precision == NLQ_FP64_PLAIN;
+    if (s.mesh->dim == 2) {
+        if (plain) per_cu = gauss ? occupancy<2, 0, 1>(A.capl, A.rowcap, false, nullptr)
+                                  : occupancy<2, 0, 0>(A.capl, A.rowcap, false, nullptr);
+        else per_cu = gauss ? occupancy<2, 1, 1>(A.capl, A.rowcap, false, nullptr)
+                            : occupancy<2, 1, 0>(A.capl, A.rowcap, false, nullptr);
+    } else {
+        if (plain) per_cu = gauss ? occupancy<3, 0, 1>(A.capl, A.rowcap, false, nullptr)
+                                  : occupancy<3, 0, 0>(A.capl, A.rowcap, false, nullptr);
+        else per_cu = gauss ? occupancy<3, 1, 1>(A.capl, A.rowcap, false, nullptr)
+                            : occupancy<3, 1, 0>(A.capl, A.rowcap, false, nullptr);
+    }
+    return static_cast<int64_t>(ctx->n_cu) * per_cu;
+}
+
+int integrate_split(const System &s) { return split_of(s); }
 
 void launch_integrate(System &s, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {

@@ -151,6 +151,7 @@ struct System {
     nlq_params p{};
     double C = 0.0;              // kernel constant
     int64_t n_pairs = 0, nnz = 0, max_row = 0;
+    int64_t max_pairs = 0;       // largest |J_l|
     // element tables
     DevBuf vert;                 // [nv*dim][ne] SoA double
     DevBuf lo, hi;               // [dim][ne]
@@ -191,7 +192,8 @@ bool solve_system(System &s, double rtol, int maxit, double *u_out, nlq_solve_in
 void launch_elem_tables(System &s, hipStream_t st);
 void build_pairs(System &s, hipStream_t st);
 void build_pattern(System &s, hipStream_t st);
-// Outer elements [lo, hi) of system s.  One launch takes up to 32 ranges of
+// Outer elements [lo, hi) of system s (each cut into integrate_split(s) work
+// items of at most 512 pairs).  One launch takes up to 32 ranges of
 // systems of one dimension, precision and kernel; a range starting at 0 clears
 // the system's values first, a range ending at n_elems finishes its matrix.
 struct IntegrateJob {
@@ -201,6 +203,9 @@ struct IntegrateJob {
 void launch_integrate_jobs(Ctx *ctx, LaunchBlock &lb, const std::vector<IntegrateJob> &jobs, hipStream_t st,
                            hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 void launch_integrate(System &s, hipStream_t st, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// resident workgroups of one integration launch of s, and work items per outer element
+int64_t integrate_slots(Ctx *ctx, const System &s);
+int integrate_split(const System &s);
 void launch_pair_blocks(System &s, hipStream_t st, int64_t n, const int32_t *ex_l, const int32_t *ex_m,
                         double *ex_out);
 void launch_load_lift(System &s, hipStream_t st, const double *f_dev, const double *g_dev);

@@ -1,14 +1,18 @@
 // Serving loop: continuous batching of assemble + solve requests on one GPU.
 //
-//   submit -> pending --(admission by HBM footprint)--> setup (worker thread,
-//   own stream: mesh from the resident cache, element tables, pair list,
-//   pattern) -> ready -> shared integration launches (scheduler thread, batch
-//   stream; several requests per launch, chunked by outer-element ranges) ->
-//   solve (worker: load vector, lifting, CG, copy of u) -> done.
+//   submit -> pending --(admission by HBM footprint)--> setup (mesh from the
+//   resident cache, element tables, pair list, pattern) -> ready -> shared
+//   integration launches (several requests per launch, chunked by outer-element
+//   ranges) -> solve (load vector, lifting, CG, copy of u) -> done.
 //
-// The scheduler never waits for a request's CG or setup, and workers never
-// wait for a launch: setup and CG kernels of some requests run on the device
-// while the integration launch of others is in flight.
+// One device thread owns the GPU and time-slices it: every pass first finishes
+// the requests whose integration is complete (their CG), then sets up newly
+// admitted requests (for at most about two launch targets), then runs one
+// shared integration launch of about the target duration.  Kernels are never
+// issued from several streams at once: the persistent integration launch holds
+// every CU's registers, so a small kernel on another stream could only start
+// between two launches, which would stretch a CG of hundreds of kernels over
+// hundreds of launches.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -87,16 +91,13 @@ struct Request {
     int64_t cursor = 0;               // next outer element to integrate
     std::vector<int64_t> pair_off;    // host copy, for chunking by pairs
     int launches = 0;
+    int split = 1;                    // work items per outer element
+    int64_t slots = 1;                // resident workgroups of its launches
     bool cache_hit = false;
     System &sys() { return cached ? cached->sys->impl : own->impl; }
 };
 
 using ReqPtr = std::shared_ptr<Request>;
-
-struct Task {
-    int kind;   // 0 = setup, 1 = solve
-    ReqPtr r;
-};
 
 }  // namespace
 
@@ -104,20 +105,18 @@ struct Server {
     Ctx *ctx = nullptr;
     nlq_serve_config cfg{};
     std::mutex mu;
-    std::condition_variable cv_sched, cv_work, cv_done;
-    std::deque<ReqPtr> pending;
-    std::deque<Task> tasks;
-    std::vector<ReqPtr> ready;          // assembled up to integration, in admission order
+    std::condition_variable cv_dev, cv_done;
+    std::deque<ReqPtr> pending;          // submitted, not admitted
+    std::deque<ReqPtr> setup_q;          // admitted, waiting for setup
+    std::deque<ReqPtr> solve_q;          // matrix ready, waiting for CG
+    std::vector<ReqPtr> ready;           // set up, integrating (admission order)
     std::unordered_map<uint64_t, ReqPtr> all;
     int admitted = 0;                   // admitted, not done
-    int inflight_tasks = 0;
     uint64_t reserved = 0;              // estimates of admitted requests not yet set up
     uint64_t next_ticket = 1;
     bool stop = false;
-    std::thread sched;
-    std::vector<std::thread> workers;
-    std::vector<hipStream_t> streams;
-    hipStream_t batch_stream = nullptr;
+    std::thread dev;                    // the device thread
+    hipStream_t stream = nullptr;
     std::mutex mesh_mu;
     std::map<MeshKey, std::unique_ptr<nlq_mesh>> meshes;
     std::list<CacheEntry> cache;        // most recently used at the front (under mu)
@@ -176,8 +175,8 @@ void admit_locked(Server &S)
         ++S.admitted;
         S.stats.max_admitted = std::max(S.stats.max_admitted, S.admitted);
         r->t_admit = serve_now();
-        S.tasks.push_back(Task{0, r});
-        S.cv_work.notify_one();
+        S.setup_q.push_back(r);
+        S.cv_dev.notify_all();
     }
 }
 
@@ -200,7 +199,7 @@ void release_locked(Server &S, const ReqPtr &r, bool keep)
     }
     --S.admitted;
     admit_locked(S);
-    S.cv_sched.notify_all();
+    S.cv_dev.notify_all();
 }
 
 // free buried systems outside the lock, then admit what now fits
@@ -233,6 +232,7 @@ nlq_mesh *get_mesh(Server &S, const nlq_request &q, hipStream_t st)
 
 void do_setup(Server &S, const ReqPtr &r, hipStream_t st)
 {
+    if (r->cancelled) throw Error{NLQ_ECANCELLED, "cancelled"};
     r->mesh = get_mesh(S, r->req, st);
     const Mesh &M = r->mesh->impl;
     r->n_nodes = M.n_nodes;
@@ -259,13 +259,14 @@ void do_setup(Server &S, const ReqPtr &r, hipStream_t st)
         S.reserved -= r->est;
         r->est = 0;
         r->t_ready = serve_now();
-        S.tasks.push_back(Task{1, r});
-        S.cv_work.notify_one();
+        S.solve_q.push_back(r);
         return;
     }
     r->own = prepare_system(*S.ctx, M, r->req.params, st);
     System &s = r->own->impl;
     r->n_pairs = s.n_pairs;
+    r->split = integrate_split(s);
+    r->slots = integrate_slots(S.ctx, s);
     r->pair_off.resize(M.n_elems + 1);
     NLQ_HIP(hipMemcpyAsync(r->pair_off.data(), s.pair_off.as<void>(), sizeof(int64_t) * (M.n_elems + 1),
                            hipMemcpyDeviceToHost, st));
@@ -276,12 +277,10 @@ void do_setup(Server &S, const ReqPtr &r, hipStream_t st)
     if (r->cancelled) throw Error{NLQ_ECANCELLED, "cancelled"};
     if (M.n_elems == 0) {
         r->t_ready = serve_now();
-        S.tasks.push_back(Task{1, r});
-        S.cv_work.notify_one();
+        S.solve_q.push_back(r);
         return;
     }
     S.ready.push_back(r);
-    S.cv_sched.notify_all();
 }
 
 void do_solve(Server &S, const ReqPtr &r, hipStream_t st)
@@ -297,50 +296,6 @@ void do_solve(Server &S, const ReqPtr &r, hipStream_t st)
     r->cg_iterations = info.iterations;
     r->rel_residual = info.rel_residual;
     if (!conv) throw Error{NLQ_ENOCONV, "CG did not reach the tolerance"};
-}
-
-void worker_main(Server *S, int w)
-{
-    (void)hipSetDevice(S->ctx->device);
-    hipStream_t st = S->streams[w];
-    for (;;) {
-        Task t;
-        {
-            std::unique_lock<std::mutex> lk(S->mu);
-            S->cv_work.wait(lk, [&] { return !S->tasks.empty() || (S->stop && S->admitted == 0); });
-            if (S->tasks.empty()) return;
-            t = S->tasks.front();
-            S->tasks.pop_front();
-            ++S->inflight_tasks;
-        }
-        nlq_status st_code = NLQ_OK;
-        std::string err;
-        try {
-            if (t.kind == 0) do_setup(*S, t.r, st);
-            else do_solve(*S, t.r, st);
-        } catch (const Error &e) {
-            st_code = e.status;
-            err = e.msg;
-        } catch (const std::exception &e) {
-            st_code = NLQ_EDEVICE;
-            err = e.what();
-        }
-        {
-            std::lock_guard<std::mutex> lk(S->mu);
-            --S->inflight_tasks;
-            if (st_code != NLQ_OK) {
-                // a failed CG still leaves a valid matrix; other failures drop it
-                finish_locked(*S, t.r, st_code, err);
-                release_locked(*S, t.r, st_code == NLQ_ENOCONV);
-            } else if (t.kind == 1) {
-                finish_locked(*S, t.r, NLQ_OK, "");
-                release_locked(*S, t.r, true);
-            }
-            S->cv_sched.notify_all();
-            S->cv_work.notify_all();
-        }
-        drain(*S);
-    }
 }
 
 // ---- scheduler: shared integration launches -------------------------------
@@ -364,23 +319,14 @@ double initial_rate(const Request &r)
 
 struct Chunk {
     ReqPtr r;
-    int64_t lo, hi, pairs;
+    int64_t lo, hi, pairs, items;
 };
 
-// Water-filling: every request of the group gets an equal share of the pair
-// budget, capped by what it has left; what the small ones leave goes to the
+// Water-filling of a pair budget: every request of the group gets an equal
+// share, capped by what it has left; what the small ones leave goes to the
 // others.  Returns outer-element ranges (at least one element each).
-std::vector<Chunk> plan_launch(Server &S, const GroupKey &g)
+std::vector<Chunk> water_fill(const std::vector<ReqPtr> &rs, double budget)
 {
-    std::vector<ReqPtr> rs;
-    for (auto &r : S.ready)
-        if (group_of(*r) == g && rs.size() < 32) rs.push_back(r);
-    double budget = 0.0;
-    for (auto &r : rs) {
-        auto it = S.rate.find(rate_key(*r));
-        const double rate = it != S.rate.end() ? it->second : initial_rate(*r);
-        budget = std::max(budget, rate * S.cfg.target_launch_ms * 1e-3);
-    }
     std::vector<int64_t> left(rs.size());
     for (size_t i = 0; i < rs.size(); ++i)
         left[i] = rs[i]->pair_off.back() - rs[i]->pair_off[rs[i]->cursor];
@@ -417,12 +363,148 @@ std::vector<Chunk> plan_launch(Server &S, const GroupKey &g)
         int64_t hi = std::lower_bound(r.pair_off.begin() + r.cursor + 1, r.pair_off.end(), target) -
                      r.pair_off.begin();
         hi = std::min(std::max(hi, r.cursor + 1), ne);
-        out.push_back(Chunk{rs[i], r.cursor, hi, r.pair_off[hi] - base});
+        out.push_back(Chunk{rs[i], r.cursor, hi, r.pair_off[hi] - base, (hi - r.cursor) * r.split});
     }
     return out;
 }
 
-void scheduler_main(Server *S)
+// The launch of one group: a pair budget from the measured rate and the target
+// duration, raised until the launch holds at least two work items per resident
+// workgroup (or everything that is left), so that the persistent grid is busy.
+std::vector<Chunk> plan_launch(Server &S, const GroupKey &g)
+{
+    std::vector<ReqPtr> rs;
+    for (auto &r : S.ready)
+        if (group_of(*r) == g && rs.size() < 32) rs.push_back(r);
+    double budget = 0.0;
+    int64_t slots = 1, left_items = 0;
+    for (auto &r : rs) {
+        auto it = S.rate.find(rate_key(*r));
+        const double rate = it != S.rate.end() ? it->second : initial_rate(*r);
+        budget = std::max(budget, rate * S.cfg.target_launch_ms * 1e-3);
+        slots = std::max(slots, r->slots);
+        left_items += (static_cast<int64_t>(r->pair_off.size()) - 1 - r->cursor) * r->split;
+    }
+    const int64_t want = std::min<int64_t>(2 * slots, left_items);
+    std::vector<Chunk> plan;
+    for (int round = 0; round < 40; ++round) {
+        plan = water_fill(rs, budget);
+        int64_t items = 0;
+        for (auto &c : plan) items += c.items;
+        if (items >= want) break;
+        budget *= std::max(1.5, 1.2 * static_cast<double>(want) / std::max<int64_t>(items, 1));
+    }
+    return plan;
+}
+
+// one shared integration launch for the ready requests of the next group
+void run_launch(Server *S, LaunchBlock &lb, hipEvent_t e0, hipEvent_t e1)
+{
+    std::vector<Chunk> plan;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        // drop cancelled requests before they take launch time
+        for (size_t i = 0; i < S->ready.size();) {
+            if (S->ready[i]->cancelled) {
+                ReqPtr r = S->ready[i];
+                S->ready.erase(S->ready.begin() + i);
+                finish_locked(*S, r, NLQ_ECANCELLED, "cancelled");
+                release_locked(*S, r, false);
+            } else {
+                ++i;
+            }
+        }
+        if (S->ready.empty()) return;
+        // round robin over the groups present, oldest request first within one
+        std::vector<GroupKey> groups;
+        for (auto &r : S->ready)
+            if (std::find(groups.begin(), groups.end(), group_of(*r)) == groups.end())
+                groups.push_back(group_of(*r));
+        const GroupKey g = groups[S->rr++ % groups.size()];
+        plan = plan_launch(*S, g);
+    }
+    std::vector<IntegrateJob> jobs;
+    for (auto &c : plan) jobs.push_back(IntegrateJob{&c.r->sys(), c.lo, c.hi});
+    nlq_status code = NLQ_OK;
+    std::string err;
+    float ms = 0.0f;
+    try {
+        launch_integrate_jobs(S->ctx, lb, jobs, S->stream, e0, e1);
+        NLQ_HIP(hipStreamSynchronize(S->stream));
+        NLQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+        for (auto &c : plan)
+            if (c.hi == static_cast<int64_t>(c.r->pair_off.size()) - 1) collect_counters(c.r->sys(), S->stream);
+    } catch (const Error &e) {
+        code = e.status;
+        err = e.msg;
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    ++S->stats.launches;
+    S->stats.launch_segments += static_cast<int64_t>(plan.size());
+    S->stats.max_per_launch = std::max(S->stats.max_per_launch, static_cast<int32_t>(plan.size()));
+    S->stats.launch_s += 1e-3 * ms;
+    S->stats.peak_bytes = std::max<uint64_t>(S->stats.peak_bytes, S->ctx->used.load());
+    int64_t pairs = 0, items = 0, slots = 1;
+    for (auto &c : plan) {
+        pairs += c.pairs;
+        items += c.items;
+        slots = std::max(slots, c.r->slots);
+    }
+    if (code == NLQ_OK && ms > 0.5f && !plan.empty() && items >= slots) {
+        // rate model: measured pairs per second of this launch, smoothed
+        const RateKey k = rate_key(*plan[0].r);
+        const double meas = pairs / (1e-3 * ms);
+        auto it = S->rate.find(k);
+        S->rate[k] = it == S->rate.end() ? meas : 0.5 * it->second + 0.5 * meas;
+    }
+    for (auto &c : plan) {
+        Request &r = *c.r;
+        r.launches += 1;
+        auto pos = std::find(S->ready.begin(), S->ready.end(), c.r);
+        if (code != NLQ_OK) {
+            if (pos != S->ready.end()) S->ready.erase(pos);
+            finish_locked(*S, c.r, code, err);
+            release_locked(*S, c.r, false);
+            continue;
+        }
+        r.cursor = c.hi;
+        if (r.cursor == static_cast<int64_t>(r.pair_off.size()) - 1) {
+            if (pos != S->ready.end()) S->ready.erase(pos);
+            r.t_ready = serve_now();
+            S->solve_q.push_back(c.r);
+        }
+    }
+}
+
+// setup or solve of one request on the device thread; failures end the request
+void run_phase(Server *S, const ReqPtr &r, bool solve)
+{
+    nlq_status code = NLQ_OK;
+    std::string err;
+    try {
+        if (solve) do_solve(*S, r, S->stream);
+        else do_setup(*S, r, S->stream);
+    } catch (const Error &e) {
+        code = e.status;
+        err = e.msg;
+    } catch (const std::exception &e) {
+        code = NLQ_EDEVICE;
+        err = e.what();
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (code != NLQ_OK) {
+        // a failed CG still leaves a valid matrix; other failures drop it
+        finish_locked(*S, r, code, err);
+        release_locked(*S, r, code == NLQ_ENOCONV);
+    } else if (solve) {
+        finish_locked(*S, r, NLQ_OK, "");
+        release_locked(*S, r, true);
+    }
+}
+
+// The device thread: each pass finishes every request whose matrix is ready
+// (CG), sets up admitted requests, then runs one shared integration launch.
+void device_main(Server *S)
 {
     (void)hipSetDevice(S->ctx->device);
     LaunchBlock lb;
@@ -430,82 +512,42 @@ void scheduler_main(Server *S)
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     for (;;) {
-        std::vector<Chunk> plan;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            S->cv_sched.wait(lk, [&] {
-                return !S->ready.empty() || (S->stop && S->admitted == 0 && S->pending.empty());
+            S->cv_dev.wait(lk, [&] {
+                return !S->solve_q.empty() || !S->setup_q.empty() || !S->ready.empty() ||
+                       (S->stop && S->admitted == 0 && S->pending.empty());
             });
-            if (S->ready.empty()) break;
-            // drop cancelled requests before they take launch time
-            for (size_t i = 0; i < S->ready.size();) {
-                if (S->ready[i]->cancelled) {
-                    ReqPtr r = S->ready[i];
-                    S->ready.erase(S->ready.begin() + i);
-                    finish_locked(*S, r, NLQ_ECANCELLED, "cancelled");
-                    release_locked(*S, r, false);
-                } else {
-                    ++i;
-                }
+            if (S->solve_q.empty() && S->setup_q.empty() && S->ready.empty()) break;
+        }
+        for (;;) {
+            ReqPtr r;
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                if (S->solve_q.empty()) break;
+                r = S->solve_q.front();
+                S->solve_q.pop_front();
             }
-            if (S->ready.empty()) continue;
-            // round robin over the groups present, oldest request first within one
-            std::vector<GroupKey> groups;
-            for (auto &r : S->ready)
-                if (std::find(groups.begin(), groups.end(), group_of(*r)) == groups.end())
-                    groups.push_back(group_of(*r));
-            const GroupKey g = groups[S->rr++ % groups.size()];
-            plan = plan_launch(*S, g);
+            run_phase(S, r, true);
+            drain(*S);
         }
-        std::vector<IntegrateJob> jobs;
-        for (auto &c : plan) jobs.push_back(IntegrateJob{&c.r->sys(), c.lo, c.hi});
-        nlq_status code = NLQ_OK;
-        std::string err;
-        float ms = 0.0f;
-        try {
-            launch_integrate_jobs(S->ctx, lb, jobs, S->batch_stream, e0, e1);
-            NLQ_HIP(hipStreamSynchronize(S->batch_stream));
-            NLQ_HIP(hipEventElapsedTime(&ms, e0, e1));
-            for (auto &c : plan)
-                if (c.hi == static_cast<int64_t>(c.r->pair_off.size()) - 1) collect_counters(c.r->sys(), S->batch_stream);
-        } catch (const Error &e) {
-            code = e.status;
-            err = e.msg;
-        }
-        std::unique_lock<std::mutex> lk(S->mu);
-        ++S->stats.launches;
-        S->stats.launch_segments += static_cast<int64_t>(plan.size());
-        S->stats.max_per_launch = std::max(S->stats.max_per_launch, static_cast<int32_t>(plan.size()));
-        S->stats.launch_s += 1e-3 * ms;
-        S->stats.peak_bytes = std::max<uint64_t>(S->stats.peak_bytes, S->ctx->used.load());
-        int64_t pairs = 0;
-        for (auto &c : plan) pairs += c.pairs;
-        if (code == NLQ_OK && ms > 0.5f && !plan.empty()) {
-            // rate model: measured pairs per second of this launch, smoothed
-            const RateKey k = rate_key(*plan[0].r);
-            const double meas = pairs / (1e-3 * ms);
-            auto it = S->rate.find(k);
-            S->rate[k] = it == S->rate.end() ? meas : 0.5 * it->second + 0.5 * meas;
-        }
-        for (auto &c : plan) {
-            Request &r = *c.r;
-            r.launches += 1;
-            auto pos = std::find(S->ready.begin(), S->ready.end(), c.r);
-            if (code != NLQ_OK) {
-                if (pos != S->ready.end()) S->ready.erase(pos);
-                finish_locked(*S, c.r, code, err);
-                release_locked(*S, c.r, false);
-                continue;
+        // set up admitted requests (for up to twice the launch target, at least
+        // one), so that the next launch shares as many as possible
+        const double t_setup = serve_now();
+        const double setup_budget = std::max(2e-3 * S->cfg.target_launch_ms, 0.01);
+        for (;;) {
+            ReqPtr r;
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                if (S->setup_q.empty()) break;
+                r = S->setup_q.front();
+                S->setup_q.pop_front();
             }
-            r.cursor = c.hi;
-            if (r.cursor == static_cast<int64_t>(r.pair_off.size()) - 1) {
-                if (pos != S->ready.end()) S->ready.erase(pos);
-                r.t_ready = serve_now();
-                S->tasks.push_back(Task{1, c.r});
-                S->cv_work.notify_one();
-            }
+            run_phase(S, r, false);
+            drain(*S);
+            if (serve_now() - t_setup > setup_budget) break;
         }
-        lk.unlock();
+        run_launch(S, lb, e0, e1);
         drain(*S);
     }
     (void)hipEventDestroy(e0);
@@ -538,8 +580,6 @@ nlq_status nlq_serve_start(nlq_ctx *ctx, const nlq_serve_config *cfg)
     nlq_serve_config c{};
     if (cfg) c = *cfg;
     if (c.max_active <= 0) c.max_active = 64;
-    if (c.workers <= 0) c.workers = 4;
-    if (c.workers > 32) c.workers = 32;
     if (!(c.target_launch_ms > 0.0)) c.target_launch_ms = 25.0;
     c.cache_systems = c.cache_systems ? 1 : 0;
     S->cfg = c;
@@ -547,20 +587,13 @@ nlq_status nlq_serve_start(nlq_ctx *ctx, const nlq_serve_config *cfg)
         set_last_error("hipSetDevice failed");
         return NLQ_EDEVICE;
     }
-    for (int w = 0; w <= c.workers; ++w) {
-        hipStream_t st = nullptr;
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-            for (auto q : S->streams) (void)hipStreamDestroy(q);
-            set_last_error("hipStreamCreate failed");
-            return NLQ_EDEVICE;
-        }
-        if (w < c.workers) S->streams.push_back(st);
-        else S->batch_stream = st;
+    if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+        set_last_error("hipStreamCreate failed");
+        return NLQ_EDEVICE;
     }
     Server *raw = S.get();
     ctx->impl.server = std::move(S);
-    raw->sched = std::thread(scheduler_main, raw);
-    for (int w = 0; w < c.workers; ++w) raw->workers.emplace_back(worker_main, raw, w);
+    raw->dev = std::thread(device_main, raw);
     return NLQ_OK;
 }
 
@@ -664,7 +697,7 @@ nlq_status nlq_cancel(nlq_ctx *ctx, uint64_t ticket)
         S->pending.erase(pos);
         finish_locked(*S, r, NLQ_ECANCELLED, "cancelled");
     }
-    S->cv_sched.notify_all();
+    S->cv_dev.notify_all();
     return NLQ_OK;
 }
 
@@ -713,19 +746,15 @@ nlq_status nlq_serve_stop(nlq_ctx *ctx)
                 if (!kv.second->done) return false;
             return true;
         });
-        S->cv_sched.notify_all();
-        S->cv_work.notify_all();
+        S->cv_dev.notify_all();
     }
-    if (S->sched.joinable()) S->sched.join();
-    for (auto &t : S->workers)
-        if (t.joinable()) t.join();
+    if (S->dev.joinable()) S->dev.join();
     (void)hipSetDevice(ctx->impl.device);
     S->cache.clear();
     S->graveyard.clear();
     S->all.clear();
     S->meshes.clear();
-    for (auto q : S->streams) (void)hipStreamDestroy(q);
-    if (S->batch_stream) (void)hipStreamDestroy(S->batch_stream);
+    if (S->stream) (void)hipStreamDestroy(S->stream);
     ctx->impl.server.reset();
     return NLQ_OK;
 }

@@ -220,7 +220,8 @@ __device__ void wave_bitonic_sort(int32_t *buf, int n2)
 // One single-wave workgroup per outer element l.  J_l = {m : aprx min dist
 // (bbox_l, bbox_m) < delta + eps} (Section 5, eq. (k_l) with eq. (mindist)),
 // candidates from the uniform bins whose lower-corner range can hold such m.
-// count mode (m_out == nullptr): counts[l] = |J_l|; fill mode: J_l ascending.
+// count mode (m_out == nullptr): counts[l] = |J_l|, err[1] = max |J_l|, err[0] = 1
+// when a list exceeds the LDS capacity; fill mode: J_l ascending.
 template <int DIM>
 __global__ void __launch_bounds__(kWave)
 k_pairs(int64_t ne, const double *__restrict__ lo, const double *__restrict__ hi, BinGrid g,
@@ -271,8 +272,11 @@ k_pairs(int64_t ne, const double *__restrict__ lo, const double *__restrict__ hi
                 }
             }
     if (!m_out) {
-        if (lane_id() == 0) counts[l] = count;
-        if (count > kPairCap && lane_id() == 0) atomicOr(err, 1);
+        if (lane_id() == 0) {
+            counts[l] = count;
+            atomicMax(err + 1, count);
+            if (count > kPairCap) atomicOr(err, 1);
+        }
         return;
     }
     if (count > kPairCap) return;
@@ -318,10 +322,10 @@ void build_pairs(System &s, hipStream_t st)
     DevBuf cursor(s.ctx, sizeof(int64_t) * (nbins + 1), st);
     DevBuf bin_of(s.ctx, sizeof(int32_t) * ne, st);
     DevBuf items(s.ctx, sizeof(int32_t) * ne, st);
-    DevBuf err(s.ctx, sizeof(int), st);
+    DevBuf err(s.ctx, 2 * sizeof(int), st);
     NLQ_HIP(hipMemsetAsync(bin_cnt.as<void>(), 0, sizeof(int64_t) * (nbins + 1), st));
     NLQ_HIP(hipMemsetAsync(cursor.as<void>(), 0, sizeof(int64_t) * (nbins + 1), st));
-    NLQ_HIP(hipMemsetAsync(err.as<void>(), 0, sizeof(int), st));
+    NLQ_HIP(hipMemsetAsync(err.as<void>(), 0, 2 * sizeof(int), st));
     dim3 g1((ne + 255) / 256), b1(256);
     if (dim == 2)
         hipLaunchKernelGGL(k_bin_count<2>, g1, b1, 0, st, ne, s.lo.as<double>(), g,
@@ -353,13 +357,14 @@ void build_pairs(System &s, hipStream_t st)
         NLQ_CHECK_LAUNCH();
     };
     launch(nullptr);
-    int herr = 0;
-    NLQ_HIP(hipMemcpyAsync(&herr, err.as<void>(), sizeof(int), hipMemcpyDeviceToHost, st));
+    int herr[2] = {0, 0};
+    NLQ_HIP(hipMemcpyAsync(herr, err.as<void>(), 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     exclusive_scan_i64(s.ctx, counts.as<int64_t>(), s.pair_off.as<int64_t>(), ne + 1, st);
-    if (herr) fail(NLQ_EINVAL, "an element has more than 8192 neighbours within delta+eps");
     NLQ_HIP(hipMemcpyAsync(&s.n_pairs, s.pair_off.as<int64_t>() + ne, sizeof(int64_t),
                            hipMemcpyDeviceToHost, st));
     NLQ_HIP(hipStreamSynchronize(st));
+    if (herr[0]) fail(NLQ_EINVAL, "an element has more than 8192 neighbours within delta+eps");
+    s.max_pairs = herr[1];
     s.pair_m.alloc(s.ctx, sizeof(int32_t) * std::max<int64_t>(s.n_pairs, 1));
     launch(s.pair_m.as<int32_t>());
     NLQ_HIP(hipStreamSynchronize(st));

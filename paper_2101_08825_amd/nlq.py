@@ -76,8 +76,7 @@ class nlq_result(C.Structure):
 
 
 class nlq_serve_config(C.Structure):
-    _fields_ = [("max_active", C.c_int32), ("workers", C.c_int32), ("target_launch_ms", C.c_double),
-                ("cache_systems", C.c_int32)]
+    _fields_ = [("max_active", C.c_int32), ("target_launch_ms", C.c_double), ("cache_systems", C.c_int32)]
 
 
 class nlq_serve_stats(C.Structure):
@@ -347,8 +346,8 @@ class System:
 class Server:
     """Serving loop of a context (nlq_serve_*): requests on Kuhn box meshes."""
 
-    def __init__(self, ctx: Context, max_active=0, workers=0, target_launch_ms=0.0, cache_systems=False):
-        cfg = nlq_serve_config(int(max_active), int(workers), float(target_launch_ms), int(bool(cache_systems)))
+    def __init__(self, ctx: Context, max_active=0, target_launch_ms=0.0, cache_systems=False):
+        cfg = nlq_serve_config(int(max_active), float(target_launch_ms), int(bool(cache_systems)))
         _check(lib().nlq_serve_start(ctx.h, C.byref(cfg)))
         self.ctx = ctx
         self.running = True

@@ -90,6 +90,38 @@ def test_c1_full_parity(nlq_ctx, oracle_lib, precision, form):
     m.close()
 
 
+_ORACLE_3D = {}
+
+
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_3d_full_parity(nlq_ctx, oracle_lib, precision, form):
+    """3D 5^3 x 6 tets, delta = 2h, eps = delta/16, L_max = 2, u = x1^2: every
+    outer element has up to 750 pairs, so each is cut into two work items."""
+    from paper_2101_08825_amd import nlq
+    O = oracle_lib
+    wl = W.Workload("t3d5", 3, 5, 2, 16, 2, 0, W._ux1sq(3))
+    _print_case("3d_full", precision=precision, form=form)
+    mesh = wl.mesh()
+    if form not in _ORACLE_3D:
+        _ORACLE_3D[form] = _oracle_full(O, mesh, O.params(wl.delta, wl.eps, wl.lmax, form=form))[0]
+    ref = _ORACLE_3D[form]
+    m = nlq.Mesh.create(nlq_ctx, mesh.coords, mesh.conn, mesh.constrained)
+    s = nlq.System(nlq_ctx, m, nlq.params(3, wl.delta, wl.eps, wl.lmax, form=form, precision=precision))
+    off, pm = s.pairs()
+    assert np.array_equal(off, ref.off) and np.array_equal(pm, ref.pm)
+    assert int(np.max(np.diff(off))) > 512
+    rp, col, val = s.csr()
+    assert np.array_equal(rp, ref.row_ptr) and np.array_equal(col, ref.col)
+    info = s.info()
+    assert list(info.n_leaf)[1:3] == list(ref.leaves[1:3])
+    err = _rel(val, ref.val)
+    print(f"  |A-A_or|_F/|A_or|_F = {err:.3e}", flush=True)
+    assert err <= (TOL64 if precision == 0 else TOL32)
+    s.close()
+    m.close()
+
+
 @pytest.mark.parametrize("dim,n,kd,ed,lmax", [(2, 12, 3, 8, 4), (3, 5, 2, 16, 3), (3, 4, 2, 4, 2)])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_pair_blocks_sampled(nlq_ctx, oracle_lib, dim, n, kd, ed, lmax, precision):
