@@ -49,6 +49,28 @@ def progress(msg):
     print(f"[bench {time.perf_counter() - T0:7.1f}s] {msg}", file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per integration launch from the committed counter profile
+    (FETCH_SIZE, WRITE_SIZE scaled by a plain copy), or None when the kernel
+    sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_k_integrate_2d128.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256_16"):
+            k, v = line.split(":", 1)
+            fields[k] = v.strip()
+    h = hashlib.sha256()
+    for f in ("nlq_integrate.hip", "nlq_device.hpp", "nlq_refine.hpp"):
+        with open(os.path.join(ROOT, "paper_2101_08825_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if fields.get("kernel_source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if xs else float("nan")
 
@@ -247,7 +269,7 @@ def main():
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "kernel": "k_integrate<2,1>",
             "flops_per_eval": fpe,
             "kernel_ms_per_step": 1e3 * kt / args.steps,
