@@ -197,6 +197,7 @@ def main():
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-cache", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this build runs on one GPU only: the path has no cross-GPU sharding "
@@ -220,6 +221,17 @@ def main():
         g_t = torch.as_tensor(g, dtype=torch.float64, device="cuda")
         setups.append((m, wl, f_t, g_t))
     torch.cuda.synchronize()
+
+    # autotune the integration launch of each problem and precision (kept in the
+    # context, so the timed steps' assemblies use it); not timed
+    tuned = {}
+    if not args.no_autotune:
+        for precision in (nlq.NLQ_FP32_MIXED, nlq.NLQ_FP64_PLAIN):
+            for (mesh, wl, f_t, g_t) in setups:
+                s = nlq.System(ctx, mesh, nlq.params(2, wl.delta, wl.eps, wl.lmax, precision=precision))
+                tuned[f"{wl.name}/{'fp32' if precision else 'fp64'}"] = s.autotune(budget_s=3.0)
+                s.close()
+        progress(f"autotuned: {tuned}")
 
     mixed = run_steps(nlq, ctx, setups, nlq.NLQ_FP32_MIXED, args.steps, args.warmup, torch)
     plain = None
@@ -281,6 +293,8 @@ def main():
                               "depth 3), open loop", matrix_cache=bool(args.serve_cache))
     if serve64:
         out["serving_fp64_plain"] = serve64
+    if tuned:
+        out["autotune"] = tuned
     out["c2_request_ms"] = {"p50": 1e3 * percentile(mixed["lat"], 50), "p99": 1e3 * percentile(mixed["lat"], 99)}
     if plain is not None:
         pms = 1e3 * float(np.mean(plain["step_times"]))

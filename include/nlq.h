@@ -160,6 +160,24 @@ nlq_status nlq_assemble(nlq_ctx *ctx, const nlq_mesh *mesh, const nlq_params *pa
 nlq_status nlq_assemble_batch(nlq_ctx *ctx, int32_t n, const nlq_mesh *const *meshes,
                               const nlq_params *params, nlq_system **out);
 nlq_status nlq_assemble_info_get(const nlq_system *sys, nlq_assemble_info *info);
+
+/* Autotuner of the integration launch.  Candidate configurations (register
+ * budget variant of the kernel, persistent workgroups per CU, largest part of
+ * one pair list J_l per work item) are timed on a sample of the system's own
+ * outer elements (about four work items per resident workgroup, middle of the
+ * mesh) for about budget_s seconds (<= 0: 2); the fastest is kept in the
+ * context for every later assembly with the same (dim, precision, kernel,
+ * L_max, size class of max |J_l|), including the serving loop's.  The system's
+ * values are recomputed with it (nlq_set_data must be called again). */
+typedef struct {
+    int32_t occupancy_variant;      /* 0: more waves per SIMD, 1: fewer waves, more registers */
+    int32_t workgroups_per_cu;      /* persistent workgroups per CU */
+    int32_t pairs_per_item;         /* largest part of one J_l per work item */
+    int32_t work_items_per_element; /* parts each outer element is cut into */
+    int32_t candidates;             /* configurations timed */
+    double best_ms, default_ms;     /* sample launch time: chosen and default configuration */
+} nlq_tune_info;
+nlq_status nlq_autotune(nlq_system *sys, double budget_s, nlq_tune_info *info);
 /* Re-run only the integration step (pair list and pattern kept) -- the hot loop;
  * values are recomputed from zero. */
 nlq_status nlq_reassemble(nlq_system *sys);

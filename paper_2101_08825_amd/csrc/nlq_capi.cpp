@@ -182,6 +182,7 @@ std::unique_ptr<nlq_system> prepare_system(Ctx &ctx, const Mesh &mesh, const nlq
     build_pairs(s, st);
     const double t2 = now_s();
     build_pattern(s, st);
+    s.cfg = tuned_config(ctx, s);
     s.val.alloc(s.ctx, sizeof(double) * std::max<int64_t>(s.nnz, 1));
     const int nr = mesh.dim == 2 ? 6 : 10;
     s.dmm.alloc(s.ctx, sizeof(double) * std::max<int64_t>(mesh.n_elems * nr, 1));
@@ -497,6 +498,27 @@ nlq_status nlq_assemble_batch(nlq_ctx *ctx, int32_t n, const nlq_mesh *const *me
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         for (int32_t i = 0; i < n; ++i) out[i] = made[i].release();
+    });
+}
+
+nlq_status nlq_autotune(nlq_system *sys, double budget_s, nlq_tune_info *info)
+{
+    return guard([&] {
+        if (!sys) fail(NLQ_EINVAL, "sys is NULL");
+        System &s = sys->impl;
+        NLQ_HIP(hipSetDevice(s.ctx->device));
+        double best = 0.0, def = 0.0;
+        const int n = autotune(s, s.ctx->stream, budget_s > 0.0 ? budget_s : 2.0, &best, &def);
+        s.has_rhs = false;
+        if (info) {
+            info->occupancy_variant = s.cfg.occ;
+            info->workgroups_per_cu = static_cast<int32_t>(integrate_slots(s.ctx, s) / std::max(s.ctx->n_cu, 1));
+            info->pairs_per_item = s.cfg.pairs_per_item;
+            info->work_items_per_element = integrate_split(s);
+            info->candidates = n;
+            info->best_ms = best;
+            info->default_ms = def;
+        }
     });
 }
 

@@ -54,8 +54,10 @@ constexpr int kWaves = 4;
 constexpr int kThreads = kWaves * kWave;
 constexpr int kLeafCap = 128;
 constexpr int kBatch = 64;
-// waves per SIMD requested from the register allocator (measured optimum)
-template <int DIM> constexpr int waves_per_eu() { return DIM == 2 ? 5 : 3; }
+// waves per SIMD requested from the register allocator: variant 0 (the default,
+// fastest on the 2D 128^2 and 3D 8^3 cases) and variant 1 with fewer waves and
+// more registers (no spills); the autotuner picks per workload
+template <int DIM, int OCC> constexpr int waves_per_eu() { return DIM == 2 ? (OCC ? 4 : 5) : (OCC ? 2 : 3); }
 
 template <int DIM> struct Shape {
     static constexpr int NV = DIM + 1;
@@ -878,8 +880,8 @@ __device__ void wave_setup(char *wmem)
 
 // Occupancy hint: more waves per SIMD cover LDS and table latency at the cost of
 // registers (5 waves in 2D, 3 in 3D were fastest on the 2D 128^2 and 3D 8^3 cases).
-template <int DIM, int PREC, int ETA>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu<DIM>())))
+template <int DIM, int PREC, int ETA, int OCC>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu<DIM, OCC>())))
 k_integrate(LaunchArgs L)
 {
     using S = Shape<DIM>;
@@ -1056,13 +1058,13 @@ __global__ void __launch_bounds__(256) k_symmetrize(int64_t nnz, const int32_t *
 }
 
 // workgroups per CU of one launch and its dynamic LDS bytes
-template <int DIM, int PREC, int ETA>
+template <int DIM, int PREC, int ETA, int OCC>
 int occupancy(int capl, int rowcap, bool explicit_mode, int *lds_out)
 {
     const int per_wave = WaveMem<DIM, PREC>::bytes(capl);
     const int lds = kWaves * per_wave + (explicit_mode ? 0 : (DIM + 1) * rowcap * 4);
     if (lds > 150 * 1024) fail(NLQ_EINVAL, "lmax too large for the per-wave refinement lists");
-    auto kern = explicit_mode ? k_pair_blocks<DIM, PREC, ETA> : k_integrate<DIM, PREC, ETA>;
+    auto kern = explicit_mode ? k_pair_blocks<DIM, PREC, ETA> : k_integrate<DIM, PREC, ETA, OCC>;
     NLQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     int per_cu = 0;
@@ -1071,13 +1073,14 @@ int occupancy(int capl, int rowcap, bool explicit_mode, int *lds_out)
     return per_cu < 1 ? 1 : per_cu;
 }
 
-template <int DIM, int PREC, int ETA>
+template <int DIM, int PREC, int ETA, int OCC>
 void launch_one(Ctx *ctx, const LaunchArgs &L, int64_t items, hipStream_t st, bool explicit_mode,
-                hipEvent_t e0, hipEvent_t e1)
+                int wg_per_cu, hipEvent_t e0, hipEvent_t e1)
 {
     int lds = 0;
-    const int per_cu = occupancy<DIM, PREC, ETA>(L.capl, L.rowcap, explicit_mode, &lds);
-    auto kern = explicit_mode ? k_pair_blocks<DIM, PREC, ETA> : k_integrate<DIM, PREC, ETA>;
+    int per_cu = occupancy<DIM, PREC, ETA, OCC>(L.capl, L.rowcap, explicit_mode, &lds);
+    if (wg_per_cu > 0 && wg_per_cu < per_cu) per_cu = wg_per_cu;
+    auto kern = explicit_mode ? k_pair_blocks<DIM, PREC, ETA> : k_integrate<DIM, PREC, ETA, OCC>;
     int64_t grid = static_cast<int64_t>(ctx->n_cu) * per_cu;
     if (grid > items) grid = items;
     if (grid < 1) grid = 1;
@@ -1087,31 +1090,49 @@ void launch_one(Ctx *ctx, const LaunchArgs &L, int64_t items, hipStream_t st, bo
     if (e1) NLQ_HIP(hipEventRecord(e1, st));
 }
 
+// one template instance per (dim, precision, kernel, register variant)
 template <int DIM, int PREC>
-void launch_eta(Ctx *ctx, int kernel, const LaunchArgs &L, int64_t items, hipStream_t st, bool ex,
-                hipEvent_t e0, hipEvent_t e1)
+void launch_var(Ctx *ctx, int kernel, const TuneConfig &c, const LaunchArgs &L, int64_t items, hipStream_t st,
+                bool ex, hipEvent_t e0, hipEvent_t e1)
 {
-    if (kernel == NLQ_ETA_GAUSS) launch_one<DIM, PREC, NLQ_ETA_GAUSS>(ctx, L, items, st, ex, e0, e1);
-    else launch_one<DIM, PREC, NLQ_ETA_CONST>(ctx, L, items, st, ex, e0, e1);
+    const bool gauss = kernel == NLQ_ETA_GAUSS;
+    if (c.occ == 0) {
+        if (gauss) launch_one<DIM, PREC, NLQ_ETA_GAUSS, 0>(ctx, L, items, st, ex, c.wg_per_cu, e0, e1);
+        else launch_one<DIM, PREC, NLQ_ETA_CONST, 0>(ctx, L, items, st, ex, c.wg_per_cu, e0, e1);
+    } else {
+        if (gauss) launch_one<DIM, PREC, NLQ_ETA_GAUSS, 1>(ctx, L, items, st, ex, c.wg_per_cu, e0, e1);
+        else launch_one<DIM, PREC, NLQ_ETA_CONST, 1>(ctx, L, items, st, ex, c.wg_per_cu, e0, e1);
+    }
 }
 
-void dispatch(Ctx *ctx, const System &s, const LaunchArgs &L, int64_t items, hipStream_t st, bool ex,
-              hipEvent_t e0, hipEvent_t e1)
+void dispatch(Ctx *ctx, const System &s, const TuneConfig &c, const LaunchArgs &L, int64_t items, hipStream_t st,
+              bool ex, hipEvent_t e0, hipEvent_t e1)
 {
     const int dim = s.mesh->dim;
     if (dim == 2) {
-        if (s.p.precision == NLQ_FP64_PLAIN) launch_eta<2, 0>(ctx, s.p.kernel, L, items, st, ex, e0, e1);
-        else launch_eta<2, 1>(ctx, s.p.kernel, L, items, st, ex, e0, e1);
+        if (s.p.precision == NLQ_FP64_PLAIN) launch_var<2, 0>(ctx, s.p.kernel, c, L, items, st, ex, e0, e1);
+        else launch_var<2, 1>(ctx, s.p.kernel, c, L, items, st, ex, e0, e1);
     } else {
-        if (s.p.precision == NLQ_FP64_PLAIN) launch_eta<3, 0>(ctx, s.p.kernel, L, items, st, ex, e0, e1);
-        else launch_eta<3, 1>(ctx, s.p.kernel, L, items, st, ex, e0, e1);
+        if (s.p.precision == NLQ_FP64_PLAIN) launch_var<3, 0>(ctx, s.p.kernel, c, L, items, st, ex, e0, e1);
+        else launch_var<3, 1>(ctx, s.p.kernel, c, L, items, st, ex, e0, e1);
     }
+}
+
+template <int DIM, int PREC>
+int occupancy_of(int kernel, int occ, int capl, int rowcap)
+{
+    const bool g = kernel == NLQ_ETA_GAUSS;
+    if (occ == 0) return g ? occupancy<DIM, PREC, 1, 0>(capl, rowcap, false, nullptr)
+                           : occupancy<DIM, PREC, 0, 0>(capl, rowcap, false, nullptr);
+    return g ? occupancy<DIM, PREC, 1, 1>(capl, rowcap, false, nullptr)
+             : occupancy<DIM, PREC, 0, 1>(capl, rowcap, false, nullptr);
 }
 
 // work items per outer element of a system
 int split_of(const System &s)
 {
-    return static_cast<int>(std::max<int64_t>(1, (s.max_pairs + kPairsPerItem - 1) / kPairsPerItem));
+    const int64_t ppi = s.cfg.pairs_per_item > 0 ? s.cfg.pairs_per_item : kPairsPerItem;
+    return static_cast<int>(std::max<int64_t>(1, (s.max_pairs + ppi - 1) / ppi));
 }
 
 // smallest s >= 0 with fl(sqrt(s)) >= t (t > 0; sqrt correctly rounded)
@@ -1171,7 +1192,7 @@ AsmArgs make_args(const System &s, const Tables &T)
     // LDS row cache: as long as the longest row, at most 2048 entries per row
     A.rowcap = static_cast<int>(std::min<int64_t>(std::max<int64_t>(s.max_row, 1), 2048));
     A.counters = s.counters.as<AsmCounters>();
-    A.split = static_cast<int>(std::max<int64_t>(1, (s.max_pairs + kPairsPerItem - 1) / kPairsPerItem));
+    A.split = split_of(s);
     return A;
 }
 
@@ -1265,7 +1286,7 @@ void launch_integrate_jobs(Ctx *ctx, LaunchBlock &lb, const std::vector<Integrat
     L.capl = capl;
     L.rowcap = rowcap;
     L.counter = reinterpret_cast<unsigned int *>(d);
-    if (items > 0) dispatch(ctx, s0, L, items, st, false, e0, e1);
+    if (items > 0) dispatch(ctx, s0, s0.cfg, L, items, st, false, e0, e1);
     // systems whose last outer element is in this launch: diagonal blocks and R + R^T
     for (const auto &j : jobs) {
         const System &s = *j.s;
@@ -1295,20 +1316,15 @@ void launch_integrate_jobs(Ctx *ctx, LaunchBlock &lb, const std::vector<Integrat
 int64_t integrate_slots(Ctx *ctx, const System &s)
 {
     const AsmArgs A = make_args(s, ctx->get_tables(s.mesh->dim, s.p.lmax));
-    int per_cu = 1;
-    const bool gauss = s.p.kernel == NLQ_ETA_GAUSS;
     const bool plain = s.p.precision == NLQ_FP64_PLAIN;
-    if (s.mesh->dim == 2) {
-        if (plain) per_cu = gauss ? occupancy<2, 0, 1>(A.capl, A.rowcap, false, nullptr)
-                                  : occupancy<2, 0, 0>(A.capl, A.rowcap, false, nullptr);
-        else per_cu = gauss ? occupancy<2, 1, 1>(A.capl, A.rowcap, false, nullptr)
-                            : occupancy<2, 1, 0>(A.capl, A.rowcap, false, nullptr);
-    } else {
-        if (plain) per_cu = gauss ? occupancy<3, 0, 1>(A.capl, A.rowcap, false, nullptr)
-                                  : occupancy<3, 0, 0>(A.capl, A.rowcap, false, nullptr);
-        else per_cu = gauss ? occupancy<3, 1, 1>(A.capl, A.rowcap, false, nullptr)
-                            : occupancy<3, 1, 0>(A.capl, A.rowcap, false, nullptr);
-    }
+    int per_cu;
+    if (s.mesh->dim == 2)
+        per_cu = plain ? occupancy_of<2, 0>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap)
+                       : occupancy_of<2, 1>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap);
+    else
+        per_cu = plain ? occupancy_of<3, 0>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap)
+                       : occupancy_of<3, 1>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap);
+    if (s.cfg.wg_per_cu > 0 && s.cfg.wg_per_cu < per_cu) per_cu = s.cfg.wg_per_cu;
     return static_cast<int64_t>(ctx->n_cu) * per_cu;
 }
 
@@ -1340,7 +1356,7 @@ void launch_pair_blocks(System &s, hipStream_t st, int64_t n, const int32_t *ex_
     L.capl = A.capl;
     L.rowcap = A.rowcap;
     L.counter = reinterpret_cast<unsigned int *>(d);
-    if (n > 0) dispatch(s.ctx, s, L, n, st, true, nullptr, nullptr);
+    if (n > 0) dispatch(s.ctx, s, TuneConfig{}, L, n, st, true, nullptr, nullptr);
 }
 
 }  // namespace nlq

@@ -13,6 +13,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "nlq.h"
@@ -95,6 +96,15 @@ struct Tables {
 
 struct Server;
 
+// Launch configuration of the integration kernel (chosen by nlq_autotune).
+struct TuneConfig {
+    int occ = 0;               // register budget: 0 = more waves per SIMD, 1 = fewer, more registers
+    int wg_per_cu = 0;         // persistent workgroups per CU (0 = as many as fit)
+    int pairs_per_item = 512;  // largest part of one J_l handled as one work item
+};
+// dim, precision, kernel, lmax, ceil(log2(max |J_l|))
+using TuneKey = std::tuple<int, int, int, int, int>;
+
 struct Ctx {
     int device = 0;
     int n_cu = 0;
@@ -105,6 +115,8 @@ struct Ctx {
     std::mutex tables_mu;
     std::map<std::pair<int, int>, std::unique_ptr<Tables>> tables;
     std::unique_ptr<Server> server;
+    std::mutex tune_mu;
+    std::map<TuneKey, TuneConfig> tuned;
     const Tables &get_tables(int dim, int lmax);
     Ctx();
     ~Ctx();
@@ -170,6 +182,7 @@ struct System {
     DevBuf F, Ft, u, g;          // [n] double
     DevBuf counters;             // AsmCounters
     LaunchBlock launch;          // argument block of this system's own launches
+    TuneConfig cfg;              // integration launch configuration
     nlq_assemble_info info{};
     bool has_rhs = false;
     std::vector<double> h_g;
@@ -206,6 +219,13 @@ void launch_integrate(System &s, hipStream_t st, hipEvent_t ev_start = nullptr, 
 // resident workgroups of one integration launch of s, and work items per outer element
 int64_t integrate_slots(Ctx *ctx, const System &s);
 int integrate_split(const System &s);
+// key of the tuned configuration of a system, and the configuration to use
+TuneKey tune_key(const System &s);
+TuneConfig tuned_config(Ctx &ctx, const System &s);
+// time candidate configurations on a sample of s's outer elements (about
+// budget_s in total), keep the fastest in ctx and in s; s's values are
+// recomputed with it.  Returns the configurations timed and the two times.
+int autotune(System &s, hipStream_t st, double budget_s, double *best_ms, double *default_ms);
 void launch_pair_blocks(System &s, hipStream_t st, int64_t n, const int32_t *ex_l, const int32_t *ex_m,
                         double *ex_out);
 void launch_load_lift(System &s, hipStream_t st, const double *f_dev, const double *g_dev);

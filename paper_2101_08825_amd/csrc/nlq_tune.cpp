@@ -1,0 +1,114 @@
+// Autotuner of the integration launch: register-budget variant, persistent
+// workgroups per CU and pair-list part per work item, timed on a sample of the
+// system's own outer elements and kept per (dim, precision, kernel, L_max,
+// pair-list size class) in the context.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "nlq_internal.hpp"
+
+namespace nlq {
+
+TuneKey tune_key(const System &s)
+{
+    int lg = 0;
+    while ((int64_t(1) << lg) < std::max<int64_t>(s.max_pairs, 1)) ++lg;
+    return TuneKey(s.mesh->dim, s.p.precision, s.p.kernel, s.p.lmax, lg);
+}
+
+TuneConfig tuned_config(Ctx &ctx, const System &s)
+{
+    std::lock_guard<std::mutex> g(ctx.tune_mu);
+    auto it = ctx.tuned.find(tune_key(s));
+    return it != ctx.tuned.end() ? it->second : TuneConfig{};
+}
+
+namespace {
+
+// milliseconds of one launch over outer elements [lo, hi) with configuration c
+double time_range(System &s, const TuneConfig &c, int64_t lo, int64_t hi, hipStream_t st, LaunchBlock &lb,
+                  hipEvent_t e0, hipEvent_t e1)
+{
+    s.cfg = c;
+    launch_integrate_jobs(s.ctx, lb, {IntegrateJob{&s, lo, hi}}, st, e0, e1);
+    NLQ_HIP(hipStreamSynchronize(st));
+    float ms = 0.0f;
+    NLQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return ms;
+}
+
+}  // namespace
+
+int autotune(System &s, hipStream_t st, double budget_s, double *best_ms, double *default_ms)
+{
+    Ctx &ctx = *s.ctx;
+    const int64_t ne = s.mesh->n_elems;
+    const TuneConfig base{};
+    // candidates: the default first, then the register variant, one workgroup
+    // less per CU, and other work-item sizes where the pair lists get cut
+    std::vector<TuneConfig> cand{base};
+    for (int occ = 0; occ < 2; ++occ)
+        for (int less = 0; less < 2; ++less)
+            for (int ppi : {512, 256, 1024}) {
+                if (ppi != 512 && s.max_pairs <= 256) continue;
+                TuneConfig c;
+                c.occ = occ;
+                c.pairs_per_item = ppi;
+                if (less) {
+                    s.cfg = c;
+                    const int64_t per_cu = integrate_slots(&ctx, s) / std::max(ctx.n_cu, 1);
+                    if (per_cu < 2) continue;
+                    c.wg_per_cu = static_cast<int>(per_cu - 1);
+                }
+                if (occ == 0 && !less && ppi == 512) continue;   // the default
+                cand.push_back(c);
+            }
+    // a sample in the middle of the mesh (away from the first and last element,
+    // whose ranges would clear or finish the values) with about four work items
+    // per resident workgroup
+    s.cfg = base;
+    const int64_t slots = integrate_slots(&ctx, s);
+    const int64_t per_elem = std::max(1, integrate_split(s));
+    int64_t len = std::max<int64_t>(1, 4 * slots / per_elem);
+    len = std::min(len, ne / 2);
+    const int64_t lo = ne / 4, hi = lo + len;
+    *best_ms = *default_ms = 0.0;
+    if (len < 1 || lo < 1 || hi >= ne) {
+        s.cfg = base;
+        return 0;
+    }
+    LaunchBlock lb;
+    hipEvent_t e0, e1;
+    NLQ_HIP(hipEventCreate(&e0));
+    NLQ_HIP(hipEventCreate(&e1));
+    const double t_start = std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+    TuneConfig best = base;
+    double best_t = 1e300;
+    int timed = 0;
+    for (const TuneConfig &c : cand) {
+        (void)time_range(s, c, lo, hi, st, lb, e0, e1);   // warm (code object, caches)
+        const double t = std::min(time_range(s, c, lo, hi, st, lb, e0, e1), time_range(s, c, lo, hi, st, lb, e0, e1));
+        ++timed;
+        if (timed == 1) *default_ms = t;
+        if (t < best_t) {
+            best_t = t;
+            best = c;
+        }
+        const double now = std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+        if (now - t_start > budget_s) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *best_ms = best_t;
+    s.cfg = best;
+    {
+        std::lock_guard<std::mutex> g(ctx.tune_mu);
+        ctx.tuned[tune_key(s)] = best;
+    }
+    // the sample launches added partial sums: recompute the whole system
+    run_integrate(s, st);
+    return timed;
+}
+
+}  // namespace nlq

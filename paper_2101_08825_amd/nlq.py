@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTREA
 EXPORTS = [
     "nlq_ctx_create", "nlq_ctx_set_stream", "nlq_ctx_memory", "nlq_ctx_destroy",
     "nlq_mesh_create", "nlq_mesh_box", "nlq_mesh_info", "nlq_mesh_copy", "nlq_mesh_destroy",
-    "nlq_assemble", "nlq_assemble_batch", "nlq_assemble_info_get", "nlq_reassemble", "nlq_set_data",
+    "nlq_assemble", "nlq_assemble_batch", "nlq_assemble_info_get", "nlq_autotune", "nlq_reassemble", "nlq_set_data",
     "nlq_set_data_device", "nlq_solve", "nlq_solution_device",
     "nlq_info", "nlq_csr_copy", "nlq_csr_device", "nlq_pairs_copy", "nlq_rhs_copy",
     "nlq_pair_blocks", "nlq_system_destroy", "nlq_serve_start", "nlq_submit", "nlq_wait",
@@ -54,6 +54,12 @@ class nlq_assemble_info(C.Structure):
                 ("nnz", C.c_int64), ("t_tables", C.c_double), ("t_pairs", C.c_double),
                 ("t_pattern", C.c_double), ("t_integrate", C.c_double), ("t_total", C.c_double),
                 ("t_kernel", C.c_double)]
+
+
+class nlq_tune_info(C.Structure):
+    _fields_ = [("occupancy_variant", C.c_int32), ("workgroups_per_cu", C.c_int32),
+                ("pairs_per_item", C.c_int32), ("work_items_per_element", C.c_int32),
+                ("candidates", C.c_int32), ("best_ms", C.c_double), ("default_ms", C.c_double)]
 
 
 class nlq_solve_info(C.Structure):
@@ -111,6 +117,7 @@ def lib():
             "nlq_mesh_destroy": [vp],
             "nlq_assemble": [vp, vp, P(nlq_params), P(vp)],
             "nlq_assemble_batch": [vp, i32, vp, vp, vp],
+            "nlq_autotune": [vp, d, P(nlq_tune_info)],
             "nlq_assemble_info_get": [vp, P(nlq_assemble_info)],
             "nlq_reassemble": [vp],
             "nlq_set_data": [vp, vp, vp],
@@ -274,6 +281,12 @@ class System:
 
     def reassemble(self):
         _check(lib().nlq_reassemble(self.h))
+
+    def autotune(self, budget_s=2.0):
+        """nlq_autotune: choose the integration launch configuration (values are recomputed)."""
+        t = nlq_tune_info()
+        _check(lib().nlq_autotune(self.h, float(budget_s), C.byref(t)))
+        return {k: getattr(t, k) for k, _ in nlq_tune_info._fields_}
 
     def set_data(self, f_nodal, g_nodal):
         f = np.ascontiguousarray(f_nodal, dtype=np.float64)
