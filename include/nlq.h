@@ -150,6 +150,19 @@ nlq_status nlq_mesh_destroy(nlq_mesh *mesh);
  * exceeds the budget. */
 nlq_status nlq_assemble(nlq_ctx *ctx, const nlq_mesh *mesh, const nlq_params *params,
                         nlq_system **out);
+/* Set a system up without integrating it: element tables, pair list J_l and CSR
+ * pattern are built, the values are zero (nlq_info and the copies work; the
+ * leaf counts are zero).  For sampled work at sizes too large to integrate
+ * whole: nlq_pair_blocks of chosen pairs, nlq_integrate_range of a slab. */
+nlq_status nlq_prepare(nlq_ctx *ctx, const nlq_mesh *mesh, const nlq_params *params,
+                       nlq_system **out);
+/* Integrate the outer elements lo <= l < hi (0 < lo < hi < n_elems) of a
+ * prepared or assembled system with the assembly kernels, adding their pairs'
+ * contributions to the values (which then hold partial sums; a range touching
+ * the first or last element is refused because those clear and finish the
+ * matrix).  kernel_s: host [1] launch time from HIP events; n_leaf: host [9]
+ * leaf integrations per level of this range (either may be NULL). */
+nlq_status nlq_integrate_range(nlq_system *sys, int64_t lo, int64_t hi, double *kernel_s, int64_t *n_leaf);
 /* Assemble n systems (meshes[i], params[i]) as n calls of nlq_assemble would,
  * but with shared integration launches: the outer elements of every system of
  * one (dim, precision, kernel) group, up to 32 systems per launch, are

@@ -448,6 +448,51 @@ nlq_status nlq_assemble(nlq_ctx *ctx, const nlq_mesh *mesh, const nlq_params *pa
     });
 }
 
+nlq_status nlq_prepare(nlq_ctx *ctx, const nlq_mesh *mesh, const nlq_params *params, nlq_system **out)
+{
+    return guard([&] {
+        if (!ctx || !mesh || !params || !out) fail(NLQ_EINVAL, "NULL argument");
+        if (mesh->impl.ctx != &ctx->impl) fail(NLQ_EINVAL, "mesh belongs to another context");
+        NLQ_HIP(hipSetDevice(ctx->impl.device));
+        hipStream_t st = ctx->impl.stream;
+        auto sys = prepare_system(ctx->impl, mesh->impl, *params, st);
+        System &s = sys->impl;
+        NLQ_HIP(hipMemsetAsync(s.val.as<void>(), 0, sizeof(double) * std::max<int64_t>(s.nnz, 1), st));
+        NLQ_HIP(hipStreamSynchronize(st));
+        s.info.t_total = s.info.t_tables + s.info.t_pairs + s.info.t_pattern;
+        *out = sys.release();
+    });
+}
+
+nlq_status nlq_integrate_range(nlq_system *sys, int64_t lo, int64_t hi, double *kernel_s, int64_t *n_leaf)
+{
+    return guard([&] {
+        if (!sys) fail(NLQ_EINVAL, "sys is NULL");
+        System &s = sys->impl;
+        const int64_t ne = s.mesh->n_elems;
+        if (lo < 1 || hi >= ne || lo >= hi)
+            fail(NLQ_EINVAL, "need 0 < lo < hi < n_elems (a range that neither clears nor finishes the values)");
+        NLQ_HIP(hipSetDevice(s.ctx->device));
+        hipStream_t st = s.ctx->stream;
+        hipEvent_t e0, e1;
+        NLQ_HIP(hipEventCreate(&e0));
+        NLQ_HIP(hipEventCreate(&e1));
+        NLQ_HIP(hipMemsetAsync(s.counters.as<void>(), 0, sizeof(AsmCounters), st));
+        launch_integrate_jobs(s.ctx, s.launch, {IntegrateJob{&s, lo, hi}}, st, e0, e1);
+        AsmCounters c{};
+        NLQ_HIP(hipMemcpyAsync(&c, s.counters.as<void>(), sizeof(AsmCounters), hipMemcpyDeviceToHost, st));
+        NLQ_HIP(hipStreamSynchronize(st));
+        float ms = 0.0f;
+        NLQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (kernel_s) *kernel_s = 1e-3 * ms;
+        if (n_leaf)
+            for (int q = 0; q < 9; ++q) n_leaf[q] = (q >= 1 && q <= 8) ? static_cast<int64_t>(c.leaf[q]) : 0;
+        s.has_rhs = false;
+    });
+}
+
 nlq_status nlq_assemble_batch(nlq_ctx *ctx, int32_t n, const nlq_mesh *const *meshes, const nlq_params *params,
                               nlq_system **out)
 {

@@ -84,14 +84,13 @@ struct AsmArgs {
     const double *lam64;  // [sub][nq][nv]
     const float *lam32;
     const double *rule;   // [nq][nv] barycentric points, then [nq] weights
-    int lvl_off[10];
     double delta, eps, dme, dpe, dme2, dpe2, C;
     double dme_sq;        // s* with (sqrt(s) < delta - eps) <=> (s < s*), s >= 0
     double *dmm;          // [ne][NR] upper-triangle diagonal-block sums per element
     float f_delta, f_inv_eps, f_delta_over_eps, f_dme2, f_dpe2, f_inv_delta2;
     int lmin, lmax, form;
     int split;            // work items per outer element (pair list cut in equal parts)
-    int capl;             // refinement-list capacity this system needs
+    int capl;             // traversal stack entries of this system (see make_args)
     int rowcap;           // LDS row cache this system would like
     AsmCounters *counters;
     int64_t n_explicit;
@@ -112,13 +111,15 @@ typedef const __attribute__((address_space(4))) AsmArgs CArgs;
 constexpr int kMaxSeg = 32;
 // largest part of one J_l handled as one work item (a workgroup's unit of work)
 constexpr int64_t kPairsPerItem = 512;
+// logical capacity of a wave's traversal stack (entries)
+constexpr int kStackCap = 256;
 struct LaunchArgs {
     const AsmArgs *sys;
     const int32_t *seg_sys;
     const int64_t *seg_lo;
     const int64_t *seg_start;   // [nseg + 1]
     int nseg;
-    int capl;                   // LDS layout: refinement lists
+    int capl;                   // LDS layout: traversal stack entries per wave
     int rowcap;                 // LDS layout: cached CSR row capacity
     unsigned int *counter;
 };
@@ -228,6 +229,14 @@ __device__ __forceinline__ Simplex<DIM> child_of(const Simplex<DIM> &S, int c)
             out.v[v][k] = r;
         }
     return out;
+}
+
+// first index of level lev in the sub-element tables (level 1 = the element at
+// 0; children of local index i at local NCH i + c): (NCH^(lev-1) - 1) / (NCH - 1)
+template <int DIM> __device__ __forceinline__ int level_offset(int lev)
+{
+    constexpr int NCH = 1 << DIM;
+    return ((1 << (DIM * (lev - 1))) - 1) / (NCH - 1);
 }
 
 // 0 = drop, 1 = integrate now (J^int), 2 = refine (J^ref): Algorithm 1
@@ -522,7 +531,7 @@ template <int DIM, int PREC> struct WaveMem {
     static constexpr int kEpiBytes = (PREC == 1 && kEpiRows < 16 ? 16 : kEpiRows) * 16 * 8;
     __host__ __device__ static int bytes(int capl)
     {
-        return (kStageBytes + kEpiBytes + kLeafCap * 4 + 2 * capl * 4 + 15) & ~15;
+        return (kStageBytes + kEpiBytes + kLeafCap * 4 + capl * 4 + 15) & ~15;
     }
 };
 
@@ -669,8 +678,7 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, char *wmem,
     double *HQ = reinterpret_cast<double *>(wmem + WM::kStageBytes);   // [rows][16]
     double *tile = HQ;                                                 // 16 x 16 (mixed), in place
     uint32_t *leafbuf = reinterpret_cast<uint32_t *>(wmem + WM::kStageBytes + WM::kEpiBytes);
-    uint32_t *listA = leafbuf + kLeafCap;
-    uint32_t *listB = listA + A.capl;
+    uint32_t *stack = leafbuf + kLeafCap;                              // A.capl entries
 
     // geometry of l (root simplex) and m: wave-uniform
     Simplex<DIM> root;
@@ -737,14 +745,16 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, char *wmem,
         }
     };
 
-    // ---- Algorithm 1, level by level (per pair: J = {m}) -------------------
-    // Leaves accumulate in leafbuf and are integrated when it fills and once at
-    // the end, so batches stay full across levels.
+    // ---- Algorithm 1 (per pair: J = {m}), depth first in batches ------------
+    // A per-wave stack holds the sub-elements still to classify as
+    // (level << 24) | local index.  A pass pops up to 64 from the top (fewer when
+    // the stack is near its capacity, so that the children always fit), sends
+    // the J^int members to the leaf buffer, pushes the children of the J^ref
+    // members, and sends the children of members one level above L_max straight
+    // to the leaf buffer (Algorithm 1 integrates everything at L_max).  Leaves
+    // are integrated when the buffer fills and once at the end, so batches stay
+    // full across levels.
     int nleaf = 0;
-    uint32_t *cur = listA, *nxt = listB;
-    int ncur = 1;
-    if (lane == 0) cur[0] = 0u;
-    wave_sync();
     auto push_leaf = [&](bool take, uint32_t ent) {
         const unsigned long long mask = wave_ballot(take);
         const int c = __popcll(mask);
@@ -758,61 +768,56 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, char *wmem,
         nleaf += c;
         wave_sync();
     };
-    for (int lev = 1;; ++lev) {
-        const int off = A.lvl_off[lev];
-        if (lev == A.lmax) {
-            // every node of this level is integrated (no classification at L_max)
-            for (int i0 = 0; i0 < ncur; i0 += kWave) {
-                const int i = i0 + lane;
-                const bool take = i < ncur;
-                push_leaf(take, take ? leaf_entry(lev, off + static_cast<int>(cur[i])) : 0u);
-            }
-            if (lane == 0 && s_leaf) atomicAdd(&s_leaf[lev], static_cast<unsigned long long>(ncur));
-            break;
-        }
-        const bool last_split = (lev + 1 == A.lmax);
-        int nn = 0;   // refined nodes (last_split) or children (otherwise) in nxt
-        int nint = 0;
-        for (int i0 = 0; i0 < ncur; i0 += kWave) {
-            const int i = i0 + lane;
-            const bool valid = i < ncur;
-            const uint32_t local = valid ? cur[i] : 0u;
-            int cls = 0;
-            if (valid) cls = (lev < A.lmin) ? 2 : classify<DIM>(A, root, lev, local, mlo, mhi);
-            const unsigned long long mref = wave_ballot(cls == 2);
-            const int rank = lanes_below(mref);
-            if (cls == 2) {
-                if (last_split) {
-                    nxt[nn + rank] = local;
-                } else {
-#pragma unroll
-                    for (int c = 0; c < NCH; ++c) nxt[(nn + rank) * NCH + c] = local * NCH + c;
-                }
-            }
-            nn += __popcll(mref);
-            nint += __popcll(wave_ballot(cls == 1));
-            push_leaf(cls == 1, leaf_entry(lev, off + static_cast<int>(local)));
-        }
-        if (lane == 0 && s_leaf && nint) atomicAdd(&s_leaf[lev], static_cast<unsigned long long>(nint));
+    uint32_t *stk = stack;
+    const int lmax = A.lmax, lmin = A.lmin;
+    const int cap = A.capl - NCH * (lmax + 1) - kWave;   // logical capacity (see make_args)
+    int n = 1;
+    if (lane == 0) stk[0] = 1u << 24;
+    wave_sync();
+    while (n > 0) {
+        int k = n < kWave ? n : kWave;
+        const int room = (cap - n) / (NCH - 1);
+        k = min(k, max(room, 1));
+        n -= k;
+        const bool valid = lane < k;
+        const uint32_t ent = valid ? stk[n + lane] : 0u;
         wave_sync();
-        if (nn == 0) break;
-        if (last_split) {
-            // children of the refined nodes are the level-L_max leaves
-            const int offn = A.lvl_off[lev + 1];
-            const int nl = nn * NCH;
+        const int lev = static_cast<int>(ent >> 24);
+        const uint32_t local = ent & 0xFFFFFFu;
+        int cls = 0;
+        if (valid) {
+            if (lev == lmax) cls = 1;                 // the root when L_max = 1
+            else if (lev < lmin) cls = 2;
+            else cls = classify<DIM>(A, root, lev, local, mlo, mhi);
+        }
+        if (cls == 1 && s_leaf) atomicAdd(&s_leaf[lev], 1ull);
+        push_leaf(cls == 1, cls == 1 ? leaf_entry(lev, level_offset<DIM>(lev) + static_cast<int>(local)) : 0u);
+        const bool to_leaves = cls == 2 && lev + 1 == lmax;
+        const bool to_stack = cls == 2 && lev + 1 < lmax;
+        const unsigned long long mpush = wave_ballot(to_stack);
+        if (to_stack) {
+            const uint32_t base = (static_cast<uint32_t>(lev + 1) << 24) | (local * NCH);
+            const int at = n + lanes_below(mpush) * NCH;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) stk[at + c] = base + c;
+        }
+        n += __popcll(mpush) * NCH;
+        const unsigned long long mleaf = wave_ballot(to_leaves);
+        if (mleaf) {
+            // parents above the pushed region, then their children packed across lanes
+            if (to_leaves) stk[n + lanes_below(mleaf)] = local;
+            wave_sync();
+            const int nl = __popcll(mleaf) * NCH;
+            const int offn = level_offset<DIM>(lmax);
             for (int i0 = 0; i0 < nl; i0 += kWave) {
                 const int i = i0 + lane;
                 const bool take = i < nl;
-                const int sub = take ? offn + static_cast<int>(nxt[i / NCH] * NCH + (i % NCH)) : 0;
-                push_leaf(take, leaf_entry(lev + 1, sub));
+                const int sub = take ? offn + static_cast<int>(stk[n + i / NCH] * NCH + (i % NCH)) : 0;
+                push_leaf(take, leaf_entry(lmax, sub));
             }
-            if (lane == 0 && s_leaf) atomicAdd(&s_leaf[lev + 1], static_cast<unsigned long long>(nl));
-            break;
+            if (lane == 0 && s_leaf) atomicAdd(&s_leaf[lmax], static_cast<unsigned long long>(nl));
         }
-        uint32_t *t = cur;
-        cur = nxt;
-        nxt = t;
-        ncur = nn * NCH;
+        wave_sync();
     }
     if (nleaf > 0) integrate(nleaf);
 
@@ -1166,8 +1171,13 @@ AsmArgs make_args(const System &s, const Tables &T)
     A.lam64 = T.lam64.as<double>();
     A.lam32 = T.lam32.as<float>();
     A.rule = T.rule.as<double>();
-    for (int q = 0; q < 10; ++q)
-        A.lvl_off[q] = q < static_cast<int>(T.lvl_off.size()) ? static_cast<int>(T.lvl_off[q]) : 0;
+    // the kernel indexes the sub-element tables by the closed form of the level offsets
+    const int nch = 1 << m.dim;
+    for (int q = 1; q <= s.p.lmax; ++q) {
+        int64_t pw = 1;
+        for (int r = 1; r < q; ++r) pw *= nch;
+        if (T.lvl_off[q] != (pw - 1) / (nch - 1)) fail(NLQ_EDEVICE, "sub-element table layout mismatch");
+    }
     A.delta = s.p.delta;
     A.eps = s.p.eps;
     A.dme = s.p.delta - s.p.eps;
@@ -1186,9 +1196,10 @@ AsmArgs make_args(const System &s, const Tables &T)
     A.lmin = s.p.lmin;
     A.lmax = s.p.lmax;
     A.form = s.p.form;
-    int capl = 1;
-    for (int q = 0; q < s.p.lmax - 2; ++q) capl *= (1 << m.dim);
-    A.capl = capl;
+    // traversal stack: a logical capacity of kStackCap, plus what forced
+    // single pops can add beyond it (NCH - 1 per level), plus one pass of
+    // parents whose children go straight to the leaf buffer
+    A.capl = kStackCap + (1 << m.dim) * (s.p.lmax + 1) + 64;
     // LDS row cache: as long as the longest row, at most 2048 entries per row
     A.rowcap = static_cast<int>(std::min<int64_t>(std::max<int64_t>(s.max_row, 1), 2048));
     A.counters = s.counters.as<AsmCounters>();

@@ -28,7 +28,8 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTREA
 EXPORTS = [
     "nlq_ctx_create", "nlq_ctx_set_stream", "nlq_ctx_memory", "nlq_ctx_destroy",
     "nlq_mesh_create", "nlq_mesh_box", "nlq_mesh_info", "nlq_mesh_copy", "nlq_mesh_destroy",
-    "nlq_assemble", "nlq_assemble_batch", "nlq_assemble_info_get", "nlq_autotune", "nlq_reassemble", "nlq_set_data",
+    "nlq_assemble", "nlq_prepare", "nlq_integrate_range", "nlq_assemble_batch", "nlq_assemble_info_get",
+    "nlq_autotune", "nlq_reassemble", "nlq_set_data",
     "nlq_set_data_device", "nlq_solve", "nlq_solution_device",
     "nlq_info", "nlq_csr_copy", "nlq_csr_device", "nlq_pairs_copy", "nlq_rhs_copy",
     "nlq_pair_blocks", "nlq_system_destroy", "nlq_serve_start", "nlq_submit", "nlq_wait",
@@ -117,6 +118,8 @@ def lib():
             "nlq_mesh_destroy": [vp],
             "nlq_assemble": [vp, vp, P(nlq_params), P(vp)],
             "nlq_assemble_batch": [vp, i32, vp, vp, vp],
+            "nlq_prepare": [vp, vp, P(nlq_params), P(vp)],
+            "nlq_integrate_range": [vp, i64, i64, P(d), vp],
             "nlq_autotune": [vp, d, P(nlq_tune_info)],
             "nlq_assemble_info_get": [vp, P(nlq_assemble_info)],
             "nlq_reassemble": [vp],
@@ -258,6 +261,20 @@ class System:
         self.h = h
         self.ctx, self.mesh, self.prm = ctx, mesh, prm
         mesh._systems.add(self)
+
+    @staticmethod
+    def prepare(ctx: Context, mesh: Mesh, prm: nlq_params):
+        """nlq_prepare: pair list and pattern only (values zero)."""
+        h = C.c_void_p()
+        _check(lib().nlq_prepare(ctx.h, mesh.h, C.byref(prm), C.byref(h)))
+        return System(ctx, mesh, prm, handle=h)
+
+    def integrate_range(self, lo, hi):
+        """nlq_integrate_range: kernel seconds and leaf counts of outer elements [lo, hi)."""
+        t = C.c_double()
+        leaves = np.zeros(9, dtype=np.int64)
+        _check(lib().nlq_integrate_range(self.h, int(lo), int(hi), C.byref(t), _ptr(leaves)))
+        return t.value, leaves
 
     @staticmethod
     def batch(ctx: Context, meshes, prms):
