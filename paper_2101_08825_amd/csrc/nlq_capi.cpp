@@ -209,6 +209,7 @@ void collect_counters(System &s, hipStream_t st)
         leaves += s.info.n_leaf[q];
     }
     s.info.n_evals = leaves * nq * nq;
+    if (c.error) fail(NLQ_EDEVICE, "refinement traversal exceeded its stack");
     if (static_cast<int64_t>(c.pairs_done) != s.n_pairs)
         fail(NLQ_EDEVICE, "integration did not visit every pair");
 }
@@ -486,6 +487,7 @@ nlq_status nlq_integrate_range(nlq_system *sys, int64_t lo, int64_t hi, double *
         NLQ_HIP(hipEventElapsedTime(&ms, e0, e1));
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        if (c.error) fail(NLQ_EDEVICE, "refinement traversal exceeded its stack");
         if (kernel_s) *kernel_s = 1e-3 * ms;
         if (n_leaf)
             for (int q = 0; q < 9; ++q) n_leaf[q] = (q >= 1 && q <= 8) ? static_cast<int64_t>(c.leaf[q]) : 0;
@@ -715,9 +717,13 @@ nlq_status nlq_pair_blocks(nlq_system *sys, int64_t n, const int32_t *l, const i
             dout(s.ctx, sizeof(double) * n * blk);
         NLQ_HIP(hipMemcpyAsync(dl.as<void>(), l, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
         NLQ_HIP(hipMemcpyAsync(dm.as<void>(), m, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+        NLQ_HIP(hipMemsetAsync(s.counters.as<void>(), 0, sizeof(AsmCounters), st));
         launch_pair_blocks(s, st, n, dl.as<int32_t>(), dm.as<int32_t>(), dout.as<double>());
+        AsmCounters c{};
         NLQ_HIP(hipMemcpyAsync(out, dout.as<void>(), sizeof(double) * n * blk, hipMemcpyDeviceToHost, st));
+        NLQ_HIP(hipMemcpyAsync(&c, s.counters.as<void>(), sizeof(AsmCounters), hipMemcpyDeviceToHost, st));
         NLQ_HIP(hipStreamSynchronize(st));
+        if (c.error) fail(NLQ_EDEVICE, "refinement traversal exceeded its stack");
     });
 }
 

@@ -54,10 +54,14 @@ constexpr int kWaves = 4;
 constexpr int kThreads = kWaves * kWave;
 constexpr int kLeafCap = 128;
 constexpr int kBatch = 64;
-// waves per SIMD requested from the register allocator: variant 0 (the default,
-// fastest on the 2D 128^2 and 3D 8^3 cases) and variant 1 with fewer waves and
-// more registers (no spills); the autotuner picks per workload
-template <int DIM, int OCC> constexpr int waves_per_eu() { return DIM == 2 ? (OCC ? 4 : 5) : (OCC ? 2 : 3); }
+// waves per SIMD requested from the register allocator: variant 0 (the default)
+// and variant 1 -- one wave more for the FP32 path (fewer registers, more
+// latency hiding), one less for the FP64 path (more registers, fewer spills);
+// the autotuner picks per workload
+template <int DIM, int PREC, int OCC> constexpr int waves_per_eu()
+{
+    return (DIM == 2 ? 5 : 3) + (OCC ? (PREC == 1 ? 1 : -1) : 0);
+}
 
 template <int DIM> struct Shape {
     static constexpr int NV = DIM + 1;
@@ -112,7 +116,7 @@ constexpr int kMaxSeg = 32;
 // largest part of one J_l handled as one work item (a workgroup's unit of work)
 constexpr int64_t kPairsPerItem = 512;
 // logical capacity of a wave's traversal stack (entries)
-constexpr int kStackCap = 256;
+constexpr int kStackCap = 128;
 struct LaunchArgs {
     const AsmArgs *sys;
     const int32_t *seg_sys;
@@ -387,7 +391,10 @@ template <int DIM, int ETA> struct MixedAcc {
     static constexpr int PPS = DIM == 2 ? 8 : 4;   // points per MFMA step
     static constexpr int STEPS = kBatch / PPS;
     static constexpr int XS = DIM == 2 ? 2 : 4;
-    static constexpr int PS = DIM == 2 ? 8 : 16;
+    // P rows of a point; a lane whose A row is >= NR reads the next point's rows
+    // (or, past the last point, the epilogue area): those rows only feed rows
+    // >= NR of D, which are never used
+    static constexpr int PS = S::NR;
     static constexpr int kStageBytes = kBatch * (XS + PS) * 4;
     struct In {
         float lam[S::NV];
@@ -431,14 +438,6 @@ template <int DIM, int ETA> struct MixedAcc {
         }
         return in;
     }
-    // zero the P padding rows once (they are never written afterwards)
-    __device__ static void zero_padding(char *work)
-    {
-        float *sp = reinterpret_cast<float *>(work) + kBatch * XS;
-        for (int t = lane_id(); t < kBatch; t += kWave)
-#pragma unroll
-            for (int r = S::NR; r < PS; ++r) sp[t * PS + r] = 0.0f;
-    }
     // point t of the batch: anchor-relative coordinates and the P rows
     template <class Edge> __device__ static void stage(char *work, int t, const In &in, const Edge &E)
     {
@@ -464,17 +463,10 @@ template <int DIM, int ETA> struct MixedAcc {
         for (int i = 0; i < S::NV; ++i)
 #pragma unroll
             for (int j = i + 1; j < S::NV; ++j) P[offrow<S::NV>(i, j)] = P[i] * in.lam[j];
-        if (DIM == 2) {
-            *reinterpret_cast<float4 *>(sp + t * PS) = make_float4(P[0], P[1], P[2], P[3]);
-            *reinterpret_cast<float2 *>(sp + t * PS + 4) = make_float2(P[4], P[5 < S::NR ? 5 : 0]);
-        } else {
+        // NR is even and t * NR floats is a multiple of 8 bytes
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
-                *reinterpret_cast<float4 *>(sp + t * PS + 4 * q) =
-                    make_float4(P[4 * q], P[4 * q + 1], P[4 * q + 2], P[4 * q + 3]);
-            *reinterpret_cast<float2 *>(sp + t * PS + 8) =
-                make_float2(P[8 < S::NR ? 8 : 0], P[9 < S::NR ? 9 : 0]);
-        }
+        for (int q = 0; q < S::NR / 2; ++q)
+            *reinterpret_cast<float2 *>(sp + t * PS + 2 * q) = make_float2(P[2 * q], P[2 * q + 1]);
     }
     __device__ void run(CArgs &A, const char *work, int npts)
     {
@@ -548,12 +540,33 @@ __device__ __forceinline__ int64_t search(const int32_t *cols, int64_t n, int32_
     return -1;
 }
 
-// CSR rows of the outer element's nodes, cached in LDS by the workgroup
+// CSR rows of the outer element's nodes, cached in LDS by the workgroup as 16-bit
+// offsets from the row's first column when the row fits (length <= rowcap and
+// column span < 65536); otherwise searched in the global row
 struct RowCache {
-    const int32_t *cols[4];   // LDS copy, or the global row when it does not fit
+    const uint16_t *c16[4];   // LDS copy, or nullptr
+    const int32_t *cols[4];   // the global row
+    int32_t first[4];
     int64_t base[4];
     int64_t len[4];
 };
+
+// position of column c in cached row r, or -1
+__device__ __forceinline__ int64_t row_find(const RowCache *rc, int r, int32_t c)
+{
+    const uint16_t *q = rc->c16[r];
+    if (!q) return search(rc->cols[r], rc->len[r], c);
+    const int32_t d = c - rc->first[r];
+    if (d < 0 || d > 65535) return -1;
+    int64_t a = 0, b = rc->len[r] - 1;
+    while (a <= b) {
+        const int64_t mid = (a + b) >> 1;
+        const int32_t v = q[mid];
+        if (v == d) return mid;
+        if (v < d) a = mid + 1; else b = mid - 1;
+    }
+    return -1;
+}
 
 template <int DIM, class Real> struct Edges {
     Real e[DIM][DIM];
@@ -775,9 +788,22 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, char *wmem,
     if (lane == 0) stk[0] = 1u << 24;
     wave_sync();
     while (n > 0) {
-        int k = n < kWave ? n : kWave;
-        const int room = (cap - n) / (NCH - 1);
-        k = min(k, max(room, 1));
+        // pop the largest top window whose refinable members (level < L_max - 1:
+        // the only ones that push) fit: NCH * pushers - k <= cap - n, at least 1
+        const int w = n < kWave ? n : kWave;
+        int k = 1;
+        {
+            const uint32_t e = lane < w ? stk[n - 1 - lane] : 0u;
+            const bool pusher = lane < w && static_cast<int>(e >> 24) < lmax - 1;
+            const unsigned long long pm = wave_ballot(pusher);
+            const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+            const int kk = lane + 1;
+            // signed: __popcll returns an unsigned count, and cap - n may be negative
+            const int pushers = static_cast<int>(__popcll(pm & upto));
+            const bool ok = lane < w && NCH * pushers - kk <= cap - n;
+            const unsigned long long okm = wave_ballot(ok);
+            if (okm) k = 64 - __clzll(okm);
+        }
         n -= k;
         const bool valid = lane < k;
         const uint32_t ent = valid ? stk[n + lane] : 0u;
@@ -795,14 +821,19 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, char *wmem,
         const bool to_leaves = cls == 2 && lev + 1 == lmax;
         const bool to_stack = cls == 2 && lev + 1 < lmax;
         const unsigned long long mpush = wave_ballot(to_stack);
+        const unsigned long long mleaf = wave_ballot(to_leaves);
+        if (n + static_cast<int>(__popcll(mpush)) * NCH + static_cast<int>(__popcll(mleaf)) > A.capl) {
+            // cannot happen with the pop rule above; never write past the stack
+            if (lane == 0) atomicOr(&A.counters->error, 1);
+            break;
+        }
         if (to_stack) {
             const uint32_t base = (static_cast<uint32_t>(lev + 1) << 24) | (local * NCH);
             const int at = n + lanes_below(mpush) * NCH;
 #pragma unroll
             for (int c = 0; c < NCH; ++c) stk[at + c] = base + c;
         }
-        n += __popcll(mpush) * NCH;
-        const unsigned long long mleaf = wave_ballot(to_leaves);
+        n += static_cast<int>(__popcll(mpush)) * NCH;
         if (mleaf) {
             // parents above the pushed region, then their children packed across lanes
             if (to_leaves) stk[n + lanes_below(mleaf)] = local;
@@ -861,7 +892,7 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, char *wmem,
         // B_lm at (l_i, m_j) through the cached row of l_i.  SYM4 adds it to the
         // half matrix R (A = R + R^T afterwards); the two-term form puts 2 B_lm^T
         // at (m_j, l_i) directly.
-        const int64_t at = search(rc->cols[i], rc->len[i], mj);
+        const int64_t at = row_find(rc, i, mj);
         if (at >= 0) {
             const int64_t pos = rc->base[i] + at;
             if (four) unsafeAtomicAdd(&A.val[pos], v);
@@ -877,16 +908,15 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, char *wmem,
 // -------------------------------------------------------------- kernels
 
 template <int DIM, int PREC>
-__device__ void wave_setup(char *wmem)
+__device__ void wave_setup(char *)
 {
-    if constexpr (PREC == 1) MixedAcc<DIM, 0>::zero_padding(wmem);
     wave_sync();
 }
 
 // Occupancy hint: more waves per SIMD cover LDS and table latency at the cost of
 // registers (5 waves in 2D, 3 in 3D were fastest on the 2D 128^2 and 3D 8^3 cases).
 template <int DIM, int PREC, int ETA, int OCC>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu<DIM, OCC>())))
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu<DIM, PREC, OCC>())))
 k_integrate(LaunchArgs L)
 {
     using S = Shape<DIM>;
@@ -906,7 +936,7 @@ k_integrate(LaunchArgs L)
     __shared__ RowCache s_rc;
     const int wid = threadIdx.x / kWave;
     char *wmem = smem + wid * WaveMem<DIM, PREC>::bytes(L.capl);
-    int32_t *rows_lds = reinterpret_cast<int32_t *>(smem + kWaves * WaveMem<DIM, PREC>::bytes(L.capl));
+    uint16_t *rows_lds = reinterpret_cast<uint16_t *>(smem + kWaves * WaveMem<DIM, PREC>::bytes(L.capl));
     // the quadrature rule depends on the dimension only: every system of the launch shares it
     CArgs &A0 = *(CArgs *)(L.sys);
     for (int t = threadIdx.x; t < NQ * NV + NQ; t += kThreads) s_rule[t] = A0.rule[t];
@@ -947,15 +977,20 @@ k_integrate(LaunchArgs L)
         if (threadIdx.x < NV) {
             const int32_t node = A.conn[l * NV + threadIdx.x];
             const int64_t b = A.row_ptr[node], len = A.row_ptr[node + 1] - b;
+            const int32_t first = len > 0 ? A.col[b] : 0;
+            const bool fits = len <= L.rowcap && (len == 0 || A.col[b + len - 1] - first <= 65535);
             s_rc.base[threadIdx.x] = b;
             s_rc.len[threadIdx.x] = len;
-            s_rc.cols[threadIdx.x] = len <= L.rowcap ? rows_lds + threadIdx.x * L.rowcap : A.col + b;
+            s_rc.first[threadIdx.x] = first;
+            s_rc.cols[threadIdx.x] = A.col + b;
+            s_rc.c16[threadIdx.x] = fits ? rows_lds + threadIdx.x * L.rowcap : nullptr;
         }
         __syncthreads();
         for (int r = 0; r < NV; ++r) {
-            if (s_rc.len[r] > L.rowcap) continue;
+            uint16_t *dst = const_cast<uint16_t *>(s_rc.c16[r]);
+            if (!dst) continue;
             for (int64_t k = threadIdx.x; k < s_rc.len[r]; k += kThreads)
-                rows_lds[r * L.rowcap + k] = A.col[s_rc.base[r] + k];
+                dst[k] = static_cast<uint16_t>(A.col[s_rc.base[r] + k] - s_rc.first[r]);
         }
         __syncthreads();
         const int64_t b0 = A.pair_off[l];
@@ -1067,7 +1102,7 @@ template <int DIM, int PREC, int ETA, int OCC>
 int occupancy(int capl, int rowcap, bool explicit_mode, int *lds_out)
 {
     const int per_wave = WaveMem<DIM, PREC>::bytes(capl);
-    const int lds = kWaves * per_wave + (explicit_mode ? 0 : (DIM + 1) * rowcap * 4);
+    const int lds = kWaves * per_wave + (explicit_mode ? 0 : (((DIM + 1) * rowcap * 2 + 15) & ~15));
     if (lds > 150 * 1024) fail(NLQ_EINVAL, "lmax too large for the per-wave refinement lists");
     auto kern = explicit_mode ? k_pair_blocks<DIM, PREC, ETA> : k_integrate<DIM, PREC, ETA, OCC>;
     NLQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
