@@ -377,16 +377,17 @@ template <int DIM, int ETA> struct PlainAcc {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// FP32 mixed: v_mfma_f32_16x16x4f32, A = P (rows x 4 points), B = G (4 points x
+// FP32 mixed path with distances on the vector ALU (used in 2D, where it is
+// faster than the variant below): v_mfma_f32_16x16x4f32, A = P (rows x 4 points), B = G (4 points x
 // 16 inner points).  Operand layout: A[i][k] and B[k][j] live in lane i + 16k
 // (resp. j + 16k); D[i][j] in lane j + 16*(i/4), register i%4.
 //  3D: 4 points per step, rows 0..9 = P, columns 0..14 = inner points.
 //  2D: 8 points per step as two independent 8x8 diagonal blocks: lanes with
 //      column < 8 use point set 0, columns >= 8 set 1.
 // Staging layout: XS floats of coordinates and PS floats of P rows per point;
-// the padding rows stay zero for the whole kernel, and the padding inner
-// columns get a coordinate far outside the horizon, so gamma is 0 there.
-template <int DIM, int ETA> struct MixedAcc {
+// the padding inner columns get a coordinate far outside the horizon, so gamma
+// is 0 there.
+template <int DIM, int ETA> struct MixedAccDirect {
     using S = Shape<DIM>;
     static constexpr int PPS = DIM == 2 ? 8 : 4;   // points per MFMA step
     static constexpr int STEPS = kBatch / PPS;
@@ -423,6 +424,7 @@ template <int DIM, int ETA> struct MixedAcc {
         yh[2] = (DIM == 3 && colv) ? static_cast<float>(y[DIM - 1]) : 1.0e18f;
         (void)work;
     }
+    __device__ void set_column(CArgs &, const double *, bool) {}
     __device__ static In fetch(CArgs &A, bool valid, int sub, int a, int lev, float wa, double)
     {
         In in;
@@ -512,6 +514,194 @@ template <int DIM, int ETA> struct MixedAcc {
         }
     }
 };
+
+// FP32 mixed path, both products on the matrix cores (used in 3D; v_mfma_f32_16x16x4f32;
+// operand layout: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, C and D
+// [i][j] in lane j + 16(i/4), register i%4):
+//  * distances: D = |x_i|^2 - 2 x_i . y_j for 16 outer points i x 16 columns j.
+//    3D: K = (x, y, z, |x|^2) . (-2y, 1); 15 inner points + 1 padding column.
+//    2D: K is split between two sets of 16 outer points, (x0, y0, x1, y1) .
+//    (-2y_b, 0, 0) for columns j < 8 (set 0) and (0, 0, -2y_b) for j >= 8
+//    (set 1), with |x|^2 of the column's set as C; 7 inner points + 1 padding
+//    column per set.  |y_j|^2 is folded into the lane's thresholds.
+//  * gamma_eps of the four distances a lane holds (its rows 4g..4g+3);
+//  * contraction H = P^T G: register r of the distance tile is exactly the B
+//    operand of step r (K index k <-> row 4k + r), A = the P rows of those
+//    points; in 2D the two sets give two independent 8 x 8 diagonal blocks.
+// Rows >= NR of D (A rows beyond the P rows read neighbouring staged values)
+// are never used; padding columns get thresholds that make gamma 0.
+template <int DIM, int ETA> struct MixedAccMfma {
+    using S = Shape<DIM>;
+    static constexpr int SET = 16;                          // outer points per set
+    static constexpr int SUPER = DIM == 2 ? 32 : 16;        // points per distance tile
+    static constexpr int XS = DIM == 2 ? 2 : 4;             // staged coordinates per point
+    static constexpr int PS = S::NR;
+    static constexpr int kXBytes = kBatch * XS * 4;
+    static constexpr int kNBytes = DIM == 2 ? kBatch * 4 : 0;   // |x|^2 (2D)
+    static constexpr int kStageBytes = kXBytes + kNBytes + kBatch * PS * 4;
+    struct In {
+        float lam[S::NV];
+        float w;
+    };
+    double dacc[4];
+    float bop;       // B operand of the distance MFMA
+    float yb2;       // |y_j|^2 of this lane's column
+    float t_lo, t_hi;  // plateau / outside thresholds on |x|^2 - 2 x.y
+    int arow, acol;  // A operand: row i and K index k of this lane
+    int col;         // column j (C / D layout)
+    __device__ void init(const double *y, int lane, char *)
+    {
+        arow = lane & 15;
+        acol = lane >> 4;
+        col = lane & 15;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dacc[r] = 0.0;
+        (void)y;
+    }
+    // inner point of this lane's column (anchor-relative, FP64) and the
+    // thresholds of the mollifier band, set once per pair
+    __device__ void set_column(CArgs &A, const double *yb, bool valid)
+    {
+        double q = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) q += yb[k] * yb[k];
+        yb2 = static_cast<float>(q);
+        if (DIM == 2) {
+            // lane j + 16k: K index k belongs to set k/2, column j to set j/8
+            const int set_j = col >> 3, set_k = acol >> 1;
+            bop = (valid && set_j == set_k) ? static_cast<float>(-2.0 * yb[acol & 1]) : 0.0f;
+        } else {
+            bop = acol < 3 ? (valid ? static_cast<float>(-2.0 * yb[acol]) : 0.0f) : 1.0f;
+        }
+        if (valid) {
+            t_lo = static_cast<float>(A.dme * A.dme - q);
+            t_hi = static_cast<float>(A.dpe * A.dpe - q);
+        } else {
+            t_lo = -INFINITY;
+            t_hi = -INFINITY;
+        }
+    }
+    __device__ static In fetch(CArgs &A, bool valid, int sub, int a, int lev, float wa, double)
+    {
+        In in;
+        if (valid) {
+            const float *lam = A.lam32 + (sub * S::NQ + a) * S::NV;
+#pragma unroll
+            for (int i = 0; i < S::NV; ++i) in.lam[i] = lam[i];
+            in.w = ldexpf(wa, -DIM * (lev - 1));
+        } else {
+#pragma unroll
+            for (int i = 0; i < S::NV; ++i) in.lam[i] = 0.0f;
+            in.w = 0.0f;
+        }
+        return in;
+    }
+    // point t of the batch: anchor-relative coordinates (and |x|^2) and the P rows
+    template <class Edge> __device__ static void stage(char *work, int t, const In &in, const Edge &E)
+    {
+        float *sx = reinterpret_cast<float *>(work);
+        float *sp = reinterpret_cast<float *>(work + kXBytes + kNBytes);
+        float x[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            float s = 0.0f;
+#pragma unroll
+            for (int i = 1; i <= DIM; ++i) s = fmaf(in.lam[i], E.e[i - 1][k], s);
+            x[k] = s;
+        }
+        float n2 = x[0] * x[0];
+#pragma unroll
+        for (int k = 1; k < DIM; ++k) n2 = fmaf(x[k], x[k], n2);
+        if (DIM == 2) {
+            *reinterpret_cast<float2 *>(sx + t * XS) = make_float2(x[0], x[1]);
+            reinterpret_cast<float *>(work + kXBytes)[t] = n2;
+        } else {
+            *reinterpret_cast<float4 *>(sx + t * XS) = make_float4(x[0], x[1], x[2], n2);
+        }
+        float P[S::NR];
+#pragma unroll
+        for (int i = 0; i < S::NV; ++i) P[i] = in.w * in.lam[i];
+#pragma unroll
+        for (int i = 0; i < S::NV; ++i)
+#pragma unroll
+            for (int j = i + 1; j < S::NV; ++j) P[offrow<S::NV>(i, j)] = P[i] * in.lam[j];
+        // NR is even and t * NR floats is a multiple of 8 bytes
+#pragma unroll
+        for (int q = 0; q < S::NR / 2; ++q)
+            *reinterpret_cast<float2 *>(sp + t * PS + 2 * q) = make_float2(P[2 * q], P[2 * q + 1]);
+    }
+    __device__ __forceinline__ float gamma(CArgs &A, float v) const
+    {
+        float g;
+        if (v < t_lo) {
+            g = 1.0f;
+        } else if (v > t_hi) {
+            g = 0.0f;
+        } else {
+            const float d = __builtin_amdgcn_sqrtf(v + yb2);
+            g = xi32(fmaf(-d, A.f_inv_eps, A.f_delta_over_eps));
+        }
+        if (ETA == NLQ_ETA_GAUSS) g *= __expf(-(v + yb2) * A.f_inv_delta2);
+        return g;
+    }
+    __device__ void run(CArgs &A, const char *work, int npts)
+    {
+        const float *sx = reinterpret_cast<const float *>(work);
+        const float *sn = reinterpret_cast<const float *>(work + kXBytes);
+        const float *sp = reinterpret_cast<const float *>(work + kXBytes + kNBytes);
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const int supers = (npts + SUPER - 1) / SUPER;
+#pragma unroll
+        for (int ss = 0; ss < kBatch / SUPER; ++ss) {
+            if (ss >= supers) break;
+            const int p0 = ss * SUPER;
+            float a_d;
+            floatx4 c;
+            if (DIM == 2) {
+                a_d = sx[(p0 + (acol >> 1) * SET + arow) * XS + (acol & 1)];
+                c = *reinterpret_cast<const floatx4 *>(sn + p0 + (col >> 3) * SET + 4 * acol);
+            } else {
+                a_d = sx[(p0 + arow) * XS + acol];
+                c = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            }
+            const floatx4 v = __builtin_amdgcn_mfma_f32_16x16x4f32(a_d, bop, c, 0, 0, 0);
+            float g[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) g[r] = gamma(A, v[r]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int pt = DIM == 2 ? p0 + (arow >> 3) * SET + 4 * acol + r : p0 + 4 * acol + r;
+                const int row = DIM == 2 ? (arow & 7) : arow;
+                const float a = sp[pt * PS + row];
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, g[r], acc, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dacc[r] += static_cast<double>(acc[r]);
+    }
+    // D[i][j] (FP64) -> H/Q totals out[r*16 + b]; out may be the tile itself: in
+    // 2D each lane reads its own slot and a slot of rows 8..15, which nobody writes
+    __device__ void finish(double *out, double *tile)
+    {
+        const int l = lane_id();
+        const int j = l & 15, ib = 4 * (l >> 4);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tile[(ib + r) * 16 + j] = dacc[r];
+        wave_sync();
+        // padding columns hold gamma = 0, so their totals are 0 as well
+        constexpr int BW = DIM == 2 ? 8 : 16;
+        for (int t = l; t < S::NR * BW; t += kWave) {
+            const int r = t / BW, b = t % BW;
+            const double v = DIM == 2 ? tile[r * 16 + b] + tile[(r + 8) * 16 + (b + 8)] : tile[r * 16 + b];
+            out[r * 16 + b] = v;
+        }
+    }
+};
+
+// the FP32 accumulator of each dimension (measured: distances on the vector ALU
+// are faster in 2D, on the matrix cores in 3D)
+template <int DIM, int ETA>
+using MixedAcc = typename std::conditional<DIM == 2, MixedAccDirect<DIM, ETA>, MixedAccMfma<DIM, ETA>>::type;
 
 // per-wave LDS: staging | epilogue (H/Q and the MFMA tile) | leaves | 2 lists
 template <int DIM, int PREC> struct WaveMem {
@@ -731,6 +921,7 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, char *wmem,
 
     Acc acc;
     acc.init(y, lane, work);
+    if constexpr (PREC == 1) acc.set_column(A, y, bsel < NQ);
 
     // integrate the leaves in leafbuf[0..nleaf)
     auto integrate = [&](int nleaf) {
