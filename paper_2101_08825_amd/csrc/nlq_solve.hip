@@ -4,6 +4,7 @@
 //   F~_i = F_i - sum_{j in Gamma} A_ij g_j   for free i (lifting, minus sign)
 //   A_{Omega,Omega} w = F~_Omega by Jacobi-preconditioned CG; u = w (free), g (Gamma)
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "nlq_device.hpp"
@@ -300,26 +301,48 @@ int cg_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, 
         *relres = 0.0;
     } else {
         const int check = 8;
+        // one CG iteration: 8 kernels, no host work
+        auto iteration = [&]() {
+            hipLaunchKernelGGL(k_spmv_dot, dim3(nb_rows), dim3(kCgThreads), 0, st, n, s.row_ptr.as<int64_t>(),
+                               s.col.as<int32_t>(), s.val.as<double>(), cst, p.as<double>(), q.as<double>(),
+                               partial.as<double>());
+            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kCgThreads), 0, st, nb_rows, partial.as<double>(), &sc->pq, 1);
+            hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1), 0, st, sc);
+            hipLaunchKernelGGL(k_update, dim3(nb_vec), dim3(kCgThreads), 0, st, n, sc, dinv.as<double>(),
+                               p.as<double>(), q.as<double>(), w.as<double>(), r.as<double>(), z.as<double>(),
+                               partial.as<double>(), nb_vec);
+            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kCgThreads), 0, st, nb_vec, partial.as<double>(),
+                               &sc->rz_new, 1);
+            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kCgThreads), 0, st, nb_vec, partial.as<double>() + nb_vec,
+                               &sc->rr, 1);
+            hipLaunchKernelGGL(k_beta, dim3(1), dim3(1), 0, st, sc);
+            hipLaunchKernelGGL(k_pupdate, dim3(nb_vec), dim3(kCgThreads), 0, st, n, sc, z.as<double>(),
+                               p.as<double>());
+        };
+        // The 8 iterations between two residual checks are captured once as a
+        // HIP graph (kernels only: no memset or copy inside) and replayed, which
+        // removes 64 launches per check from the host path; NLQ_CG_GRAPH=0 keeps
+        // the plain launches.
+        hipGraphExec_t exec = nullptr;
+        const char *env = std::getenv("NLQ_CG_GRAPH");
+        if (maxit >= 2 * check && !(env && env[0] == '0')) {
+            hipGraph_t graph = nullptr;
+            NLQ_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            for (int k = 0; k < check; ++k) iteration();
+            const hipError_t e_end = hipStreamEndCapture(st, &graph);
+            if (e_end != hipSuccess) fail(NLQ_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e_end));
+            const hipError_t e_inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e_inst != hipSuccess) fail(NLQ_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e_inst));
+        }
         for (it = 0; it < maxit;) {
-            for (int k = 0; k < check && it < maxit; ++k, ++it) {
-                hipLaunchKernelGGL(k_spmv_dot, dim3(nb_rows), dim3(kCgThreads), 0, st, n,
-                                   s.row_ptr.as<int64_t>(), s.col.as<int32_t>(), s.val.as<double>(),
-                                   cst, p.as<double>(), q.as<double>(), partial.as<double>());
-                hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kCgThreads), 0, st, nb_rows,
-                                   partial.as<double>(), &sc->pq, 1);
-                hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1), 0, st, sc);
-                hipLaunchKernelGGL(k_update, dim3(nb_vec), dim3(kCgThreads), 0, st, n, sc,
-                                   dinv.as<double>(), p.as<double>(), q.as<double>(), w.as<double>(),
-                                   r.as<double>(), z.as<double>(), partial.as<double>(), nb_vec);
-                hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kCgThreads), 0, st, nb_vec,
-                                   partial.as<double>(), &sc->rz_new, 1);
-                hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kCgThreads), 0, st, nb_vec,
-                                   partial.as<double>() + nb_vec, &sc->rr, 1);
-                hipLaunchKernelGGL(k_beta, dim3(1), dim3(1), 0, st, sc);
-                hipLaunchKernelGGL(k_pupdate, dim3(nb_vec), dim3(kCgThreads), 0, st, n, sc,
-                                   z.as<double>(), p.as<double>());
-                NLQ_CHECK_LAUNCH();
+            if (exec && maxit - it >= check) {
+                NLQ_HIP(hipGraphLaunch(exec, st));
+                it += check;
+            } else {
+                for (int k = 0; k < check && it < maxit; ++k, ++it) iteration();
             }
+            NLQ_CHECK_LAUNCH();
             NLQ_HIP(hipMemcpyAsync(&h, sc, sizeof(CgScalars), hipMemcpyDeviceToHost, st));
             NLQ_HIP(hipStreamSynchronize(st));
             rn = std::sqrt(h.rr);
@@ -328,6 +351,7 @@ int cg_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, 
                 break;
             }
         }
+        if (exec) (void)hipGraphExecDestroy(exec);
         *relres = rn / bnorm;
     }
     hipLaunchKernelGGL(k_compose_u, dim3(nb_vec), dim3(kCgThreads), 0, st, n, cst, w.as<double>(),
