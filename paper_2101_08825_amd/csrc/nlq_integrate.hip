@@ -91,7 +91,7 @@ struct AsmArgs {
     double delta, eps, dme, dpe, dme2, dpe2, C;
     double dme_sq;        // s* with (sqrt(s) < delta - eps) <=> (s < s*), s >= 0
     double *dmm;          // [ne][NR] upper-triangle diagonal-block sums per element
-    float f_delta, f_inv_eps, f_delta_over_eps, f_dme2, f_dpe2, f_inv_delta2;
+    float f_delta, f_inv_eps, f_delta_over_eps, f_inv_delta2;
     int lmin, lmax, form;
     int split;            // work items per outer element (pair list cut in equal parts)
     int capl;             // traversal stack entries of this system (see make_args)
@@ -182,18 +182,32 @@ template <int ETA> __device__ __forceinline__ double kernel64(CArgs &A, double d
     return mu;
 }
 
-// gamma_eps / C at squared distance d2 (FP32; sqrt to ~1 ulp)
-template <int ETA> __device__ __forceinline__ float kernel32(CArgs &A, float d2)
+// mu at distance d (FP32), without branches: the band coordinate
+// r = (delta - d) / eps is clamped to [-1, 1], where the Horner form of xi gives
+// exactly 0 and 1 (all its partial sums are multiples of 1/256), so the plateau
+// and the outside need no separate case.  Every evaluation costs the same, but a
+// wave no longer diverges between the three cases (a leaf that straddles the
+// band nearly always holds all three).
+// doe = delta / eps, held in a vector register by the caller (a multiply-add
+// reads at most one scalar register, and 1 / eps is the other operand).
+__device__ __forceinline__ float mu32(CArgs &A, float d, float doe)
 {
-    float g;
-    if (d2 < A.f_dme2) {
-        g = 1.0f;
-    } else if (d2 > A.f_dpe2) {
-        g = 0.0f;
-    } else {
-        const float d = __builtin_amdgcn_sqrtf(d2);
-        g = xi32(fmaf(-d, A.f_inv_eps, A.f_delta_over_eps));
-    }
+    return xi32(__builtin_amdgcn_fmed3f(fmaf(-d, A.f_inv_eps, doe), -1.0f, 1.0f));
+}
+
+// a wave-uniform value copied into a vector register, so that the compiler does
+// not re-copy it from its scalar register inside a loop
+__device__ __forceinline__ float in_vgpr(float x)
+{
+    float r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// gamma_eps / C at squared distance d2 >= 0 (FP32; sqrt to ~1 ulp)
+template <int ETA> __device__ __forceinline__ float kernel32(CArgs &A, float d2, float doe)
+{
+    float g = mu32(A, __builtin_amdgcn_sqrtf(d2), doe);
     if (ETA == NLQ_ETA_GAUSS) g *= __expf(-d2 * A.f_inv_delta2);
     return g;
 }
@@ -403,6 +417,7 @@ template <int DIM, int ETA> struct MixedAccDirect {
     };
     double dacc[4];
     float yh[3];
+    float doe;   // delta / eps (vector register)
     int sub;     // inner point (and P row) handled by this lane
     int poff;    // point offset within a step
     __device__ void init(const double *y, int lane, char *work)
@@ -424,7 +439,7 @@ template <int DIM, int ETA> struct MixedAccDirect {
         yh[2] = (DIM == 3 && colv) ? static_cast<float>(y[DIM - 1]) : 1.0e18f;
         (void)work;
     }
-    __device__ void set_column(CArgs &, const double *, bool) {}
+    __device__ void set_column(CArgs &A, const double *, bool) { doe = in_vgpr(A.f_delta_over_eps); }
     __device__ static In fetch(CArgs &A, bool valid, int sub, int a, int lev, float wa, double)
     {
         In in;
@@ -490,7 +505,7 @@ template <int DIM, int ETA> struct MixedAccDirect {
                 const float dx = x.x - yh[0], dy = x.y - yh[1], dz = x.z - yh[2];
                 d2 = fmaf(dz, dz, fmaf(dx, dx, dy * dy));
             }
-            const float g = kernel32<ETA>(A, d2);
+            const float g = kernel32<ETA>(A, d2, doe);
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, g, acc, 0, 0, 0);
         }
 #pragma unroll
@@ -545,8 +560,8 @@ template <int DIM, int ETA> struct MixedAccMfma {
     };
     double dacc[4];
     float bop;       // B operand of the distance MFMA
-    float yb2;       // |y_j|^2 of this lane's column
-    float t_lo, t_hi;  // plateau / outside thresholds on |x|^2 - 2 x.y
+    float yb2;       // |y_j|^2 of this lane's column (huge for a padding column: gamma 0)
+    float doe;       // delta / eps (vector register)
     int arow, acol;  // A operand: row i and K index k of this lane
     int col;         // column j (C / D layout)
     __device__ void init(const double *y, int lane, char *)
@@ -558,27 +573,20 @@ template <int DIM, int ETA> struct MixedAccMfma {
         for (int r = 0; r < 4; ++r) dacc[r] = 0.0;
         (void)y;
     }
-    // inner point of this lane's column (anchor-relative, FP64) and the
-    // thresholds of the mollifier band, set once per pair
+    // inner point of this lane's column (anchor-relative, FP64), set once per pair
     __device__ void set_column(CArgs &A, const double *yb, bool valid)
     {
+        doe = in_vgpr(A.f_delta_over_eps);
         double q = 0.0;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) q += yb[k] * yb[k];
-        yb2 = static_cast<float>(q);
+        yb2 = valid ? static_cast<float>(q) : 1.0e30f;
         if (DIM == 2) {
             // lane j + 16k: K index k belongs to set k/2, column j to set j/8
             const int set_j = col >> 3, set_k = acol >> 1;
             bop = (valid && set_j == set_k) ? static_cast<float>(-2.0 * yb[acol & 1]) : 0.0f;
         } else {
             bop = acol < 3 ? (valid ? static_cast<float>(-2.0 * yb[acol]) : 0.0f) : 1.0f;
-        }
-        if (valid) {
-            t_lo = static_cast<float>(A.dme * A.dme - q);
-            t_hi = static_cast<float>(A.dpe * A.dpe - q);
-        } else {
-            t_lo = -INFINITY;
-            t_hi = -INFINITY;
         }
     }
     __device__ static In fetch(CArgs &A, bool valid, int sub, int a, int lev, float wa, double)
@@ -630,18 +638,13 @@ template <int DIM, int ETA> struct MixedAccMfma {
         for (int q = 0; q < S::NR / 2; ++q)
             *reinterpret_cast<float2 *>(sp + t * PS + 2 * q) = make_float2(P[2 * q], P[2 * q + 1]);
     }
+    // gamma_eps / C of tile value v = |x|^2 - 2 x.y: |x - y|^2 = v + |y|^2, clamped
+    // at 0 against the cancellation of nearly equal points
     __device__ __forceinline__ float gamma(CArgs &A, float v) const
     {
-        float g;
-        if (v < t_lo) {
-            g = 1.0f;
-        } else if (v > t_hi) {
-            g = 0.0f;
-        } else {
-            const float d = __builtin_amdgcn_sqrtf(v + yb2);
-            g = xi32(fmaf(-d, A.f_inv_eps, A.f_delta_over_eps));
-        }
-        if (ETA == NLQ_ETA_GAUSS) g *= __expf(-(v + yb2) * A.f_inv_delta2);
+        const float d2 = fmaxf(v + yb2, 0.0f);
+        float g = mu32(A, __builtin_amdgcn_sqrtf(d2), doe);
+        if (ETA == NLQ_ETA_GAUSS) g *= __expf(-d2 * A.f_inv_delta2);
         return g;
     }
     __device__ void run(CArgs &A, const char *work, int npts)
@@ -1416,8 +1419,6 @@ AsmArgs make_args(const System &s, const Tables &T)
     A.f_delta = static_cast<float>(s.p.delta);
     A.f_inv_eps = static_cast<float>(1.0 / s.p.eps);
     A.f_delta_over_eps = static_cast<float>(s.p.delta / s.p.eps);
-    A.f_dme2 = static_cast<float>(A.dme * A.dme);
-    A.f_dpe2 = static_cast<float>(A.dpe * A.dpe);
     A.f_inv_delta2 = static_cast<float>(1.0 / (s.p.delta * s.p.delta));
     A.lmin = s.p.lmin;
     A.lmax = s.p.lmax;
