@@ -143,7 +143,10 @@ def serve_replay(nlq, ctx, precision, n_requests, cache):
                 os._exit(3)
         res.append(x)
         progress(f"serving precision {precision}: request {k} done in {1e3 * x['latency_s']:.1f} ms "
-                 f"(dim {reqs[k].dim}, n {reqs[k].n}, {x['n_pairs']} pairs, {x['launches']} launches)")
+                 f"(dim {reqs[k].dim}, n {reqs[k].n}, {x['n_pairs']} pairs, {x['launches']} launches; "
+                 f"queue {1e3 * x['queue_s']:.1f} setup {1e3 * x['setup_s']:.1f} "
+                 f"integrate {1e3 * (x['assemble_s'] - x['setup_s']):.1f} solve {1e3 * x['solve_s']:.1f} ms, "
+                 f"{x['cg_iterations']} CG iterations)")
     wall = time.perf_counter() - t0
     st = srv.stats()
     srv.stop()
@@ -152,7 +155,10 @@ def serve_replay(nlq, ctx, precision, n_requests, cache):
         raise RuntimeError(f"serving: {len(bad)} requests failed: {bad[0]['error']}")
     lat = [x["latency_s"] for x in res]
     pairs = sum(x["n_pairs"] for x in res)
+    phases = {"queue": [x["queue_s"] for x in res], "setup": [x["setup_s"] for x in res],
+              "integrate": [x["assemble_s"] - x["setup_s"] for x in res], "solve": [x["solve_s"] for x in res]}
     return {"requests": len(res), "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
+            "phase_p50_ms": {k: 1e3 * percentile(v, 50) for k, v in phases.items()},
             "mean_ms": 1e3 * float(np.mean(lat)), "wall_s": wall, "pairs": pairs,
             "launches": st["launches"], "mean_requests_per_launch": st["launch_segments"] / max(st["launches"], 1),
             "max_requests_per_launch": st["max_per_launch"], "max_admitted": st["max_admitted"],

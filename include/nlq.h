@@ -240,8 +240,11 @@ nlq_status nlq_system_destroy(nlq_system *sys);
  *    requests are evicted (least recently used first) to make room.
  *  - One device thread owns the GPU and time-slices it; each pass: the CG of
  *    every request whose matrix is ready, the setup (element tables, pair list,
- *    pattern) of the admitted requests (for about two launch targets), then one
- *    shared integration launch.
+ *    pattern) of the admitted requests, smallest first (for about one launch
+ *    target), then one shared integration launch of one group: that of the
+ *    request nearest to completion, in a launch just long enough for it to
+ *    finish -- unless a request has waited for a launch longer than four
+ *    targets: then its group, for the target duration.
  *  - Integration: outer elements of all assembled-but-not-integrated requests of
  *    one (dim, precision, kernel) group share persistent launches (at most 32
  *    requests per launch, see nlq_assemble_batch); a launch is sized from the
@@ -273,6 +276,7 @@ typedef struct {
     double solve_s;              /* matrix ready -> result ready (load vector, lifting, CG, copy) */
     int32_t launches;            /* shared integration launches the request took part in */
     int32_t cache_hit;           /* 1: its matrix was resident from an earlier request */
+    double setup_s;              /* admitted -> set up (mesh, pair list, pattern; the first part of assemble_s) */
 } nlq_result;
 
 typedef struct {

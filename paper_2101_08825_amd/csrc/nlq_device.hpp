@@ -61,7 +61,10 @@ template <class T> __device__ __forceinline__ T wave_incl_scan(T v)
 //   d1 = x_min - y_max, d2 = y_min - x_max.
 // The square of aprx max is returned without the root: the caller compares it
 // with the exact threshold s* = min{s : fl(sqrt(s)) >= t}, which decides
-// fl(sqrt(s)) < t identically because the rounded root is monotone.
+// fl(sqrt(s)) < t identically because the rounded root is monotone.  fmax
+// (one instruction) picks the same value as a comparison for the finite
+// operands here; the two differ only in the sign of a zero, which no later
+// comparison sees.
 template <int DIM>
 __device__ __forceinline__ double aprx_max_sq(const double *lo1, const double *hi1,
                                               const double *lo2, const double *hi2)
@@ -71,8 +74,7 @@ __device__ __forceinline__ double aprx_max_sq(const double *lo1, const double *h
     for (int k = 0; k < DIM; ++k) {
         double d1 = __dsub_rn(lo1[k], hi2[k]);
         double d2 = __dsub_rn(lo2[k], hi1[k]);
-        double a = __dmul_rn(d1, d1), b = __dmul_rn(d2, d2);
-        s = __dadd_rn(s, a > b ? a : b);
+        s = __dadd_rn(s, fmax(__dmul_rn(d1, d1), __dmul_rn(d2, d2)));
     }
     return s;
 }
@@ -86,8 +88,7 @@ __device__ __forceinline__ double aprx_min_dist(const double *lo1, const double 
     for (int k = 0; k < DIM; ++k) {
         double d1 = __dsub_rn(lo1[k], hi2[k]);
         double d2 = __dsub_rn(lo2[k], hi1[k]);
-        if (d1 > r) r = d1;
-        if (d2 > r) r = d2;
+        r = fmax(r, fmax(d1, d2));
     }
     return r;
 }

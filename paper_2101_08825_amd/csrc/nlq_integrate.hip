@@ -87,6 +87,8 @@ struct AsmArgs {
     double *val;
     const double *lam64;  // [sub][nq][nv]
     const float *lam32;
+    const float *pt32;    // 2D: rows of the FP32 contraction per point (see the tables)
+    int pt32_zero;        // its zero row
     const double *rule;   // [nq][nv] barycentric points, then [nq] weights
     double delta, eps, dme, dpe, dme2, dpe2, C;
     double dme_sq;        // s* with (sqrt(s) < delta - eps) <=> (s < s*), s >= 0
@@ -274,8 +276,8 @@ __device__ __forceinline__ int classify(CArgs &A, const Simplex<DIM> &root, int 
         double a = S.v[0][k], b = S.v[0][k];
 #pragma unroll
         for (int v = 1; v <= DIM; ++v) {
-            a = S.v[v][k] < a ? S.v[v][k] : a;
-            b = S.v[v][k] > b ? S.v[v][k] : b;
+            a = fmin(a, S.v[v][k]);
+            b = fmax(b, S.v[v][k]);
         }
         slo[k] = a;
         shi[k] = b;
@@ -391,99 +393,65 @@ template <int DIM, int ETA> struct PlainAcc {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// FP32 mixed path with distances on the vector ALU (used in 2D, where it is
-// faster than the variant below): v_mfma_f32_16x16x4f32, A = P (rows x 4 points), B = G (4 points x
-// 16 inner points).  Operand layout: A[i][k] and B[k][j] live in lane i + 16k
-// (resp. j + 16k); D[i][j] in lane j + 16*(i/4), register i%4.
-//  3D: 4 points per step, rows 0..9 = P, columns 0..14 = inner points.
-//  2D: 8 points per step as two independent 8x8 diagonal blocks: lanes with
-//      column < 8 use point set 0, columns >= 8 set 1.
-// Staging layout: XS floats of coordinates and PS floats of P rows per point;
-// the padding inner columns get a coordinate far outside the horizon, so gamma
-// is 0 there.
+// FP32 mixed path with distances on the vector ALU (2D, where it is faster
+// than the variant below): v_mfma_f32_16x16x4f32, A = P (rows x 4 points),
+// B = G (4 points x 16 inner points).  Operand layout: A[i][k] and B[k][j] live
+// in lane i + 16k (resp. j + 16k); D[i][j] in lane j + 16*(i/4), register i%4.
+// 8 points per step as two independent 8x8 diagonal blocks: lanes with column
+// < 8 use point set 0, columns >= 8 set 1.
+// Staging layout: 2 floats of coordinates and 8 floats of rows per point (the
+// 6 P rows, then lambda_1, lambda_2, read only by A rows >= 6, which feed rows
+// of D that are never used); the padding inner column gets a coordinate far
+// outside the horizon, so gamma is 0 there.
 template <int DIM, int ETA> struct MixedAccDirect {
+    static_assert(DIM == 2, "the vector-ALU distance variant is the 2D accumulator");
     using S = Shape<DIM>;
-    static constexpr int PPS = DIM == 2 ? 8 : 4;   // points per MFMA step
+    static constexpr int PPS = 8;                  // points per MFMA step
     static constexpr int STEPS = kBatch / PPS;
-    static constexpr int XS = DIM == 2 ? 2 : 4;
-    // P rows of a point; a lane whose A row is >= NR reads the next point's rows
-    // (or, past the last point, the epilogue area): those rows only feed rows
-    // >= NR of D, which are never used
-    static constexpr int PS = S::NR;
+    static constexpr int XS = 2;
+    static constexpr int PS = 8;
     static constexpr int kStageBytes = kBatch * (XS + PS) * 4;
+    // one point: its row of the precomputed table (P rows, lambda_1, lambda_2)
     struct In {
-        float lam[S::NV];
-        float w;
+        floatx4 r0, r1;
     };
     double dacc[4];
-    float yh[3];
+    float yh[2];
     float doe;   // delta / eps (vector register)
     int sub;     // inner point (and P row) handled by this lane
     int poff;    // point offset within a step
-    __device__ void init(const double *y, int lane, char *work)
+    __device__ void init(const double *y, int lane, char *)
     {
         const int n = lane & 15;
         const int k = lane >> 4;
-        if (DIM == 2) {
-            sub = n & 7;
-            poff = 4 * (n >> 3) + k;
-        } else {
-            sub = n;
-            poff = k;
-        }
+        sub = n & 7;
+        poff = 4 * (n >> 3) + k;
 #pragma unroll
         for (int r = 0; r < 4; ++r) dacc[r] = 0.0;
         const bool colv = sub < S::NQ;
         yh[0] = colv ? static_cast<float>(y[0]) : 1.0e18f;
         yh[1] = colv ? static_cast<float>(y[1]) : 1.0e18f;
-        yh[2] = (DIM == 3 && colv) ? static_cast<float>(y[DIM - 1]) : 1.0e18f;
-        (void)work;
     }
     __device__ void set_column(CArgs &A, const double *, bool) { doe = in_vgpr(A.f_delta_over_eps); }
-    __device__ static In fetch(CArgs &A, bool valid, int sub, int a, int lev, float wa, double)
+    // the table row of point a of sub-element sub; lanes without a point read
+    // the zero row at the end
+    __device__ static In fetch(CArgs &A, bool valid, int sub, int a, int, float, double)
     {
-        In in;
-        if (valid) {
-            const float *lam = A.lam32 + (sub * S::NQ + a) * S::NV;
-#pragma unroll
-            for (int i = 0; i < S::NV; ++i) in.lam[i] = lam[i];
-            in.w = ldexpf(wa, -DIM * (lev - 1));
-        } else {
-#pragma unroll
-            for (int i = 0; i < S::NV; ++i) in.lam[i] = 0.0f;
-            in.w = 0.0f;
-        }
-        return in;
+        const int row = valid ? sub * S::NQ + a : A.pt32_zero;
+        const floatx4 *t = reinterpret_cast<const floatx4 *>(A.pt32 + static_cast<int64_t>(row) * 8);
+        return In{t[0], t[1]};
     }
-    // point t of the batch: anchor-relative coordinates and the P rows
+    // point t of the batch: anchor-relative coordinates and the table row
     template <class Edge> __device__ static void stage(char *work, int t, const In &in, const Edge &E)
     {
         float *sx = reinterpret_cast<float *>(work);
         float *sp = sx + kBatch * XS;
-        float x[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-            float s = 0.0f;
-#pragma unroll
-            for (int i = 1; i <= DIM; ++i) s = fmaf(in.lam[i], E.e[i - 1][k], s);
-            x[k] = s;
-        }
-        if (DIM == 2) {
-            *reinterpret_cast<float2 *>(sx + t * XS) = make_float2(x[0], x[1]);
-        } else {
-            *reinterpret_cast<float4 *>(sx + t * XS) = make_float4(x[0], x[1], x[2], 0.0f);
-        }
-        float P[S::NR];
-#pragma unroll
-        for (int i = 0; i < S::NV; ++i) P[i] = in.w * in.lam[i];
-#pragma unroll
-        for (int i = 0; i < S::NV; ++i)
-#pragma unroll
-            for (int j = i + 1; j < S::NV; ++j) P[offrow<S::NV>(i, j)] = P[i] * in.lam[j];
-        // NR is even and t * NR floats is a multiple of 8 bytes
-#pragma unroll
-        for (int q = 0; q < S::NR / 2; ++q)
-            *reinterpret_cast<float2 *>(sp + t * PS + 2 * q) = make_float2(P[2 * q], P[2 * q + 1]);
+        const float l1 = in.r1[2], l2 = in.r1[3];
+        const float x0 = fmaf(l2, E.e[1][0], l1 * E.e[0][0]);
+        const float x1 = fmaf(l2, E.e[1][1], l1 * E.e[0][1]);
+        *reinterpret_cast<float2 *>(sx + t * XS) = make_float2(x0, x1);
+        *reinterpret_cast<floatx4 *>(sp + t * PS) = in.r0;
+        *reinterpret_cast<floatx4 *>(sp + t * PS + 4) = in.r1;
     }
     __device__ void run(CArgs &A, const char *work, int npts)
     {
@@ -495,24 +463,17 @@ template <int DIM, int ETA> struct MixedAccDirect {
         for (int t = 0; t < STEPS; ++t) {
             if (t >= steps) break;
             const float a = sp[t * PPS * PS];
-            float d2;
-            if (DIM == 2) {
-                const float2 x = *reinterpret_cast<const float2 *>(sx + t * PPS * XS);
-                const float dx = x.x - yh[0], dy = x.y - yh[1];
-                d2 = fmaf(dx, dx, dy * dy);
-            } else {
-                const float4 x = *reinterpret_cast<const float4 *>(sx + t * PPS * XS);
-                const float dx = x.x - yh[0], dy = x.y - yh[1], dz = x.z - yh[2];
-                d2 = fmaf(dz, dz, fmaf(dx, dx, dy * dy));
-            }
+            const float2 x = *reinterpret_cast<const float2 *>(sx + t * PPS * XS);
+            const float dx = x.x - yh[0], dy = x.y - yh[1];
+            const float d2 = fmaf(dx, dx, dy * dy);
             const float g = kernel32<ETA>(A, d2, doe);
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, g, acc, 0, 0, 0);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) dacc[r] += static_cast<double>(acc[r]);
     }
-    // D[i][j] (FP64) -> H/Q totals out[r*16 + b]; out may be the tile itself: in
-    // 2D each lane reads its own slot and a slot of rows 8..15, which nobody writes
+    // D[i][j] (FP64) -> H/Q totals out[r*16 + b]; out may be the tile itself: each
+    // lane reads its own slot and a slot of rows 8..15, which nobody writes
     __device__ void finish(double *out, double *tile)
     {
         const int l = lane_id();
@@ -521,11 +482,9 @@ template <int DIM, int ETA> struct MixedAccDirect {
         for (int r = 0; r < 4; ++r) tile[(ib + r) * 16 + j] = dacc[r];
         wave_sync();
         // padding columns hold gamma = 0, so their totals are 0 as well
-        constexpr int BW = DIM == 2 ? 8 : 16;
-        for (int t = l; t < S::NR * BW; t += kWave) {
-            const int r = t / BW, b = t % BW;
-            const double v = DIM == 2 ? tile[r * 16 + b] + tile[(r + 8) * 16 + (b + 8)] : tile[r * 16 + b];
-            out[r * 16 + b] = v;
+        for (int t = l; t < S::NR * 8; t += kWave) {
+            const int r = t / 8, b = t % 8;
+            out[r * 16 + b] = tile[r * 16 + b] + tile[(r + 8) * 16 + (b + 8)];
         }
     }
 };
@@ -706,7 +665,7 @@ template <int DIM, int ETA> struct MixedAccMfma {
 template <int DIM, int ETA>
 using MixedAcc = typename std::conditional<DIM == 2, MixedAccDirect<DIM, ETA>, MixedAccMfma<DIM, ETA>>::type;
 
-// per-wave LDS: staging | epilogue (H/Q and the MFMA tile) | leaves | 2 lists
+// per-wave LDS: staging, then the epilogue's H/Q rows and MFMA tile | leaves | stack
 template <int DIM, int PREC> struct WaveMem {
     using S = Shape<DIM>;
     static constexpr int kStageBytes =
@@ -714,9 +673,11 @@ template <int DIM, int PREC> struct WaveMem {
     static constexpr int kEpiRows = S::NR + 1 + S::NV;   // H/Q rows + column sums + diagonal rows
     // the mixed path's 16 x 16 MFMA tile is written in place of the H/Q rows
     static constexpr int kEpiBytes = (PREC == 1 && kEpiRows < 16 ? 16 : kEpiRows) * 16 * 8;
+    // the epilogue runs after the pair's last batch: it shares the staging area
+    static constexpr int kWorkBytes = kStageBytes > kEpiBytes ? kStageBytes : kEpiBytes;
     __host__ __device__ static int bytes(int capl)
     {
-        return (kStageBytes + kEpiBytes + kLeafCap * 4 + capl * 4 + 15) & ~15;
+        return (kWorkBytes + kLeafCap * 4 + capl * 4 + 15) & ~15;
     }
 };
 
@@ -881,9 +842,9 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, char *wmem,
     l = uniform(l);
     m = uniform(m);
     char *work = wmem;
-    double *HQ = reinterpret_cast<double *>(wmem + WM::kStageBytes);   // [rows][16]
-    double *tile = HQ;                                                 // 16 x 16 (mixed), in place
-    uint32_t *leafbuf = reinterpret_cast<uint32_t *>(wmem + WM::kStageBytes + WM::kEpiBytes);
+    double *HQ = reinterpret_cast<double *>(wmem);   // [rows][16], after the last batch
+    double *tile = HQ;                               // 16 x 16 (mixed), in place
+    uint32_t *leafbuf = reinterpret_cast<uint32_t *>(wmem + WM::kWorkBytes);
     uint32_t *stack = leafbuf + kLeafCap;                              // A.capl entries
 
     // geometry of l (root simplex) and m: wave-uniform
@@ -1399,6 +1360,8 @@ AsmArgs make_args(const System &s, const Tables &T)
     A.val = s.val.as<double>();
     A.lam64 = T.lam64.as<double>();
     A.lam32 = T.lam32.as<float>();
+    A.pt32 = T.pt32.as<float>();
+    A.pt32_zero = static_cast<int>(T.n_sub * T.nq);
     A.rule = T.rule.as<double>();
     // the kernel indexes the sub-element tables by the closed form of the level offsets
     const int nch = 1 << m.dim;

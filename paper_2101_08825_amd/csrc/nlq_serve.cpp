@@ -74,7 +74,8 @@ struct Request {
     uint64_t ticket = 0;
     nlq_request req{};
     std::vector<double> f, g;
-    double t_submit = 0.0, t_admit = 0.0, t_ready = 0.0, t_done = 0.0;
+    double t_submit = 0.0, t_admit = 0.0, t_setup = 0.0, t_ready = 0.0, t_done = 0.0;
+    double t_turn = 0.0;              // waiting for a launch since (set up, or its last launch)
     nlq_status status = NLQ_ENOTREADY;
     std::atomic<bool> cancelled{false};
     bool done = false;
@@ -124,7 +125,6 @@ struct Server {
     // wait for the device, which must not happen while mu is held)
     std::vector<std::unique_ptr<nlq_system>> graveyard;
     std::map<RateKey, double> rate;     // integrated pairs per second
-    size_t rr = 0;                      // round robin over groups
     nlq_serve_stats stats{};
 };
 
@@ -258,7 +258,7 @@ void do_setup(Server &S, const ReqPtr &r, hipStream_t st)
         std::lock_guard<std::mutex> lk(S.mu);
         S.reserved -= r->est;
         r->est = 0;
-        r->t_ready = serve_now();
+        r->t_ready = r->t_setup = serve_now();
         S.solve_q.push_back(r);
         return;
     }
@@ -275,8 +275,9 @@ void do_setup(Server &S, const ReqPtr &r, hipStream_t st)
     S.reserved -= r->est;
     r->est = 0;
     if (r->cancelled) throw Error{NLQ_ECANCELLED, "cancelled"};
+    r->t_setup = r->t_turn = serve_now();
     if (M.n_elems == 0) {
-        r->t_ready = serve_now();
+        r->t_ready = r->t_setup;
         S.solve_q.push_back(r);
         return;
     }
@@ -369,9 +370,11 @@ std::vector<Chunk> water_fill(const std::vector<ReqPtr> &rs, double budget)
 }
 
 // The launch of one group: a pair budget from the measured rate and the target
-// duration, raised until the launch holds at least two work items per resident
-// workgroup (or everything that is left), so that the persistent grid is busy.
-std::vector<Chunk> plan_launch(Server &S, const GroupKey &g)
+// duration -- or, when finish_pairs > 0, only what lets a request with that many
+// pairs left finish under water-filling -- raised until the launch holds at least
+// two work items per resident workgroup (or everything that is left), so that
+// the persistent grid is busy.
+std::vector<Chunk> plan_launch(Server &S, const GroupKey &g, int64_t finish_pairs)
 {
     std::vector<ReqPtr> rs;
     for (auto &r : S.ready)
@@ -385,6 +388,8 @@ std::vector<Chunk> plan_launch(Server &S, const GroupKey &g)
         slots = std::max(slots, r->slots);
         left_items += (static_cast<int64_t>(r->pair_off.size()) - 1 - r->cursor) * r->split;
     }
+    if (finish_pairs > 0)
+        budget = std::min(budget, 1.02 * static_cast<double>(finish_pairs) * static_cast<double>(rs.size()) + 1.0);
     const int64_t want = std::min<int64_t>(2 * slots, left_items);
     std::vector<Chunk> plan;
     for (int round = 0; round < 40; ++round) {
@@ -415,13 +420,30 @@ void run_launch(Server *S, LaunchBlock &lb, hipEvent_t e0, hipEvent_t e1)
             }
         }
         if (S->ready.empty()) return;
-        // round robin over the groups present, oldest request first within one
-        std::vector<GroupKey> groups;
+        // the group to launch: that of the request nearest to completion
+        // (remaining pairs / the group's measured rate), in a launch just long
+        // enough for it to finish, so that small requests go through at once;
+        // but once a request has waited for a launch longer than four launch
+        // targets, its group, for the full target, so that no group starves
+        const double now = serve_now();
+        const Request *oldest = S->ready.front().get();
         for (auto &r : S->ready)
-            if (std::find(groups.begin(), groups.end(), group_of(*r)) == groups.end())
-                groups.push_back(group_of(*r));
-        const GroupKey g = groups[S->rr++ % groups.size()];
-        plan = plan_launch(*S, g);
+            if (r->t_turn < oldest->t_turn) oldest = r.get();
+        const bool nearest = now - oldest->t_turn <= 4e-3 * S->cfg.target_launch_ms;
+        const Request *pick = oldest;
+        if (nearest) {
+            double best = 1e300;
+            for (auto &r : S->ready) {
+                auto it = S->rate.find(rate_key(*r));
+                const double rate = it != S->rate.end() ? it->second : initial_rate(*r);
+                const double left = static_cast<double>(r->pair_off.back() - r->pair_off[r->cursor]) / rate;
+                if (left < best) {
+                    best = left;
+                    pick = r.get();
+                }
+            }
+        }
+        plan = plan_launch(*S, group_of(*pick), nearest ? pick->pair_off.back() - pick->pair_off[pick->cursor] : 0);
     }
     std::vector<IntegrateJob> jobs;
     for (auto &c : plan) jobs.push_back(IntegrateJob{&c.r->sys(), c.lo, c.hi});
@@ -468,6 +490,7 @@ void run_launch(Server *S, LaunchBlock &lb, hipEvent_t e0, hipEvent_t e1)
             continue;
         }
         r.cursor = c.hi;
+        r.t_turn = serve_now();
         if (r.cursor == static_cast<int64_t>(r.pair_off.size()) - 1) {
             if (pos != S->ready.end()) S->ready.erase(pos);
             r.t_ready = serve_now();
@@ -531,21 +554,27 @@ void device_main(Server *S)
             run_phase(S, r, true);
             drain(*S);
         }
-        // set up admitted requests (for up to twice the launch target, at least
-        // one), so that the next launch shares as many as possible
-        const double t_setup = serve_now();
-        const double setup_budget = std::max(2e-3 * S->cfg.target_launch_ms, 0.01);
+        // set up admitted requests (for up to one launch target, at least one),
+        // so that the next launch shares as many as possible: the smallest
+        // first (by the admission estimate), unless the longest-waiting one has
+        // waited for more than four launch targets
+        const double t_pass = serve_now();
+        const double setup_budget = std::max(1e-3 * S->cfg.target_launch_ms, 0.005);
         for (;;) {
             ReqPtr r;
             {
                 std::lock_guard<std::mutex> lk(S->mu);
                 if (S->setup_q.empty()) break;
-                r = S->setup_q.front();
-                S->setup_q.pop_front();
+                auto at = S->setup_q.begin();
+                if (serve_now() - (*at)->t_admit <= 4e-3 * S->cfg.target_launch_ms)
+                    for (auto it = S->setup_q.begin(); it != S->setup_q.end(); ++it)
+                        if ((*it)->est < (*at)->est) at = it;
+                r = *at;
+                S->setup_q.erase(at);
             }
             run_phase(S, r, false);
             drain(*S);
-            if (serve_now() - t_setup > setup_budget) break;
+            if (serve_now() - t_pass > setup_budget) break;
         }
         run_launch(S, lb, e0, e1);
         drain(*S);
@@ -672,6 +701,7 @@ nlq_status nlq_wait(nlq_ctx *ctx, uint64_t ticket, int32_t timeout_ms, nlq_resul
     out->solve_s = r->t_ready > 0 ? r->t_done - r->t_ready : 0.0;
     out->launches = r->launches;
     out->cache_hit = r->cache_hit ? 1 : 0;
+    out->setup_s = (r->t_setup > 0 && r->t_admit > 0) ? r->t_setup - r->t_admit : 0.0;
     if (r->status != NLQ_OK) set_last_error(r->error);
     return NLQ_OK;
 }

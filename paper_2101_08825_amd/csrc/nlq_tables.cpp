@@ -172,6 +172,26 @@ std::unique_ptr<Tables> make_tables(Ctx *ctx, int dim, int lmax)
         cur.swap(next);
     }
     for (size_t k = 0; k < lam.size(); ++k) lam32[k] = static_cast<float>(lam[k]);
+    if (dim == 2) {
+        // the same FP32 operations as forming the rows point by point: w scaled
+        // by 4^-(level-1) exactly, then products rounded one at a time
+        std::vector<float> pt(static_cast<size_t>(t->n_sub * nq + 1) * 8, 0.0f);
+        for (int lev = 1; lev <= lmax; ++lev)
+            for (int64_t sub = t->lvl_off[lev]; sub < t->lvl_off[lev + 1]; ++sub)
+                for (int a = 0; a < nq; ++a) {
+                    const float *l = &lam32[(static_cast<size_t>(sub) * nq + a) * nv];
+                    float *o = &pt[(static_cast<size_t>(sub) * nq + a) * 8];
+                    const float w = std::ldexp(static_cast<float>(t->w[a]), -dim * (lev - 1));
+                    for (int i = 0; i < nv; ++i) o[i] = w * l[i];
+                    int r = nv;
+                    for (int i = 0; i < nv; ++i)
+                        for (int j = i + 1; j < nv; ++j) o[r++] = o[i] * l[j];
+                    o[6] = l[1];
+                    o[7] = l[2];
+                }
+        t->pt32.alloc(ctx, pt.size() * sizeof(float));
+        NLQ_HIP(hipMemcpy(t->pt32.as<void>(), pt.data(), pt.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
     std::vector<double> rule(t->bary);
     rule.insert(rule.end(), t->w.begin(), t->w.end());
     t->rule.alloc(ctx, rule.size() * sizeof(double));

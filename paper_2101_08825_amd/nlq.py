@@ -79,7 +79,7 @@ class nlq_result(C.Structure):
                 ("n_free", C.c_int64), ("u", C.POINTER(C.c_double)), ("cg_iterations", C.c_int32),
                 ("rel_residual", C.c_double), ("latency_s", C.c_double), ("queue_s", C.c_double),
                 ("assemble_s", C.c_double), ("solve_s", C.c_double), ("launches", C.c_int32),
-                ("cache_hit", C.c_int32)]
+                ("cache_hit", C.c_int32), ("setup_s", C.c_double)]
 
 
 class nlq_serve_config(C.Structure):
@@ -407,7 +407,7 @@ class Server:
                    n_nodes=r.n_nodes, n_pairs=r.n_pairs, n_free=r.n_free, u=u,
                    cg_iterations=r.cg_iterations, rel_residual=r.rel_residual,
                    latency_s=r.latency_s, queue_s=r.queue_s, assemble_s=r.assemble_s,
-                   solve_s=r.solve_s, launches=r.launches, cache_hit=bool(r.cache_hit))
+                   solve_s=r.solve_s, launches=r.launches, cache_hit=bool(r.cache_hit), setup_s=r.setup_s)
         if release:
             _check(lib().nlq_result_release(self.ctx.h, C.c_uint64(ticket)))
         return out
