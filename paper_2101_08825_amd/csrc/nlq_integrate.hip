@@ -259,14 +259,28 @@ template <int DIM> __device__ __forceinline__ int level_offset(int lev)
     return ((1 << (DIM * (lev - 1))) - 1) / (NCH - 1);
 }
 
-// 0 = drop, 1 = integrate now (J^int), 2 = refine (J^ref): Algorithm 1
+// 0 = drop, 1 = integrate now (J^int), 2 = refine (J^ref): Algorithm 1.
+// The sub-element's vertices are formed by the midpoint recursion from the
+// root, or from its ancestor at level min(lev, memo_lev) whose vertices the
+// memo holds (formed by the same recursion; memo_lev < 2: no memo).
 template <int DIM>
-__device__ __forceinline__ int classify(CArgs &A, const Simplex<DIM> &root, int lev,
-                                        uint32_t local, const double *mlo, const double *mhi)
+__device__ __forceinline__ int classify(CArgs &A, const Simplex<DIM> &root, const double *memo, int memo_lev,
+                                        int lev, uint32_t local, const double *mlo, const double *mhi)
 {
-    constexpr int NCH = 1 << DIM;
+    constexpr int NCH = 1 << DIM, NV = DIM + 1;
     Simplex<DIM> S = root;
-    for (int d = lev - 2; d >= 0; --d) {
+    int d = lev - 2;   // digits of `local` below the start node
+    if (lev >= 2 && memo_lev >= 2) {
+        const int la = lev < memo_lev ? lev : memo_lev;
+        const int idx = level_offset<DIM>(la) - 1 + static_cast<int>(local >> (DIM * (lev - la)));
+        const double *src = memo + idx * NV * DIM;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) S.v[v][k] = src[v * DIM + k];
+        d = lev - la - 1;
+    }
+    for (; d >= 0; --d) {
         const int c = (local >> (DIM * d)) & (NCH - 1);
         S = child_of(S, c);
     }
@@ -489,33 +503,28 @@ template <int DIM, int ETA> struct MixedAccDirect {
     }
 };
 
-// FP32 mixed path, both products on the matrix cores (used in 3D; v_mfma_f32_16x16x4f32;
+// FP32 mixed path, both products on the matrix cores (3D; v_mfma_f32_16x16x4f32;
 // operand layout: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, C and D
 // [i][j] in lane j + 16(i/4), register i%4):
-//  * distances: D = |x_i|^2 - 2 x_i . y_j for 16 outer points i x 16 columns j.
-//    3D: K = (x, y, z, |x|^2) . (-2y, 1); 15 inner points + 1 padding column.
-//    2D: K is split between two sets of 16 outer points, (x0, y0, x1, y1) .
-//    (-2y_b, 0, 0) for columns j < 8 (set 0) and (0, 0, -2y_b) for j >= 8
-//    (set 1), with |x|^2 of the column's set as C; 7 inner points + 1 padding
-//    column per set.  |y_j|^2 is folded into the lane's thresholds.
+//  * distances: D = |x_i|^2 - 2 x_i . y_j for 16 outer points i x 16 columns j,
+//    K = (x, y, z, |x|^2) . (-2y, 1); 15 inner points + 1 padding column;
+//    |y_j|^2 is added per lane;
 //  * gamma_eps of the four distances a lane holds (its rows 4g..4g+3);
 //  * contraction H = P^T G: register r of the distance tile is exactly the B
 //    operand of step r (K index k <-> row 4k + r), A = the P rows of those
-//    points; in 2D the two sets give two independent 8 x 8 diagonal blocks.
+//    points.
 // Rows >= NR of D (A rows beyond the P rows read neighbouring staged values)
-// are never used; padding columns get thresholds that make gamma 0.
+// are never used; the padding column gets |y|^2 huge, so gamma is 0 there.
 template <int DIM, int ETA> struct MixedAccMfma {
+    static_assert(DIM == 3, "the matrix-core distance variant is the 3D accumulator");
     using S = Shape<DIM>;
-    static constexpr int SET = 16;                          // outer points per set
-    static constexpr int SUPER = DIM == 2 ? 32 : 16;        // points per distance tile
-    static constexpr int XS = DIM == 2 ? 2 : 4;             // staged coordinates per point
+    static constexpr int XS = 4;                            // x, y, z, |x|^2 per point
     static constexpr int PS = S::NR;
     static constexpr int kXBytes = kBatch * XS * 4;
-    static constexpr int kNBytes = DIM == 2 ? kBatch * 4 : 0;   // |x|^2 (2D)
-    static constexpr int kStageBytes = kXBytes + kNBytes + kBatch * PS * 4;
+    static constexpr int kStageBytes = kXBytes + kBatch * PS * 4;
+    // one point: its row of the precomputed table (P0..P9, lambda_1..lambda_3)
     struct In {
-        float lam[S::NV];
-        float w;
+        floatx4 r0, r1, r2, r3;
     };
     double dacc[4];
     float bop;       // B operand of the distance MFMA
@@ -540,62 +549,34 @@ template <int DIM, int ETA> struct MixedAccMfma {
 #pragma unroll
         for (int k = 0; k < DIM; ++k) q += yb[k] * yb[k];
         yb2 = valid ? static_cast<float>(q) : 1.0e30f;
-        if (DIM == 2) {
-            // lane j + 16k: K index k belongs to set k/2, column j to set j/8
-            const int set_j = col >> 3, set_k = acol >> 1;
-            bop = (valid && set_j == set_k) ? static_cast<float>(-2.0 * yb[acol & 1]) : 0.0f;
-        } else {
-            bop = acol < 3 ? (valid ? static_cast<float>(-2.0 * yb[acol]) : 0.0f) : 1.0f;
-        }
+        bop = acol < 3 ? (valid ? static_cast<float>(-2.0 * yb[acol]) : 0.0f) : 1.0f;
     }
-    __device__ static In fetch(CArgs &A, bool valid, int sub, int a, int lev, float wa, double)
+    // the table row of point a of sub-element sub; lanes without a point read
+    // the zero row at the end
+    __device__ static In fetch(CArgs &A, bool valid, int sub, int a, int, float, double)
     {
-        In in;
-        if (valid) {
-            const float *lam = A.lam32 + (sub * S::NQ + a) * S::NV;
-#pragma unroll
-            for (int i = 0; i < S::NV; ++i) in.lam[i] = lam[i];
-            in.w = ldexpf(wa, -DIM * (lev - 1));
-        } else {
-#pragma unroll
-            for (int i = 0; i < S::NV; ++i) in.lam[i] = 0.0f;
-            in.w = 0.0f;
-        }
-        return in;
+        const int row = valid ? sub * S::NQ + a : A.pt32_zero;
+        const floatx4 *t = reinterpret_cast<const floatx4 *>(A.pt32 + static_cast<int64_t>(row) * 16);
+        return In{t[0], t[1], t[2], t[3]};
     }
-    // point t of the batch: anchor-relative coordinates (and |x|^2) and the P rows
+    // point t of the batch: anchor-relative coordinates, |x|^2 and the P rows
     template <class Edge> __device__ static void stage(char *work, int t, const In &in, const Edge &E)
     {
         float *sx = reinterpret_cast<float *>(work);
-        float *sp = reinterpret_cast<float *>(work + kXBytes + kNBytes);
-        float x[3] = {0.0f, 0.0f, 0.0f};
+        float *sp = reinterpret_cast<float *>(work + kXBytes);
+        const float l1 = in.r2[2], l2 = in.r2[3], l3 = in.r3[0];
+        float x[3];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-            float s = 0.0f;
-#pragma unroll
-            for (int i = 1; i <= DIM; ++i) s = fmaf(in.lam[i], E.e[i - 1][k], s);
-            x[k] = s;
-        }
-        float n2 = x[0] * x[0];
-#pragma unroll
-        for (int k = 1; k < DIM; ++k) n2 = fmaf(x[k], x[k], n2);
-        if (DIM == 2) {
-            *reinterpret_cast<float2 *>(sx + t * XS) = make_float2(x[0], x[1]);
-            reinterpret_cast<float *>(work + kXBytes)[t] = n2;
-        } else {
-            *reinterpret_cast<float4 *>(sx + t * XS) = make_float4(x[0], x[1], x[2], n2);
-        }
-        float P[S::NR];
-#pragma unroll
-        for (int i = 0; i < S::NV; ++i) P[i] = in.w * in.lam[i];
-#pragma unroll
-        for (int i = 0; i < S::NV; ++i)
-#pragma unroll
-            for (int j = i + 1; j < S::NV; ++j) P[offrow<S::NV>(i, j)] = P[i] * in.lam[j];
-        // NR is even and t * NR floats is a multiple of 8 bytes
-#pragma unroll
-        for (int q = 0; q < S::NR / 2; ++q)
-            *reinterpret_cast<float2 *>(sp + t * PS + 2 * q) = make_float2(P[2 * q], P[2 * q + 1]);
+        for (int k = 0; k < 3; ++k) x[k] = fmaf(l3, E.e[2][k], fmaf(l2, E.e[1][k], l1 * E.e[0][k]));
+        const float n2 = fmaf(x[2], x[2], fmaf(x[1], x[1], x[0] * x[0]));
+        *reinterpret_cast<float4 *>(sx + t * XS) = make_float4(x[0], x[1], x[2], n2);
+        // 10 rows: t * 10 floats is a multiple of 8 bytes
+        float2 *dst = reinterpret_cast<float2 *>(sp + t * PS);
+        dst[0] = make_float2(in.r0[0], in.r0[1]);
+        dst[1] = make_float2(in.r0[2], in.r0[3]);
+        dst[2] = make_float2(in.r1[0], in.r1[1]);
+        dst[3] = make_float2(in.r1[2], in.r1[3]);
+        dst[4] = make_float2(in.r2[0], in.r2[1]);
     }
     // gamma_eps / C of tile value v = |x|^2 - 2 x.y: |x - y|^2 = v + |y|^2, clamped
     // at 0 against the cancellation of nearly equal points
@@ -609,40 +590,29 @@ template <int DIM, int ETA> struct MixedAccMfma {
     __device__ void run(CArgs &A, const char *work, int npts)
     {
         const float *sx = reinterpret_cast<const float *>(work);
-        const float *sn = reinterpret_cast<const float *>(work + kXBytes);
-        const float *sp = reinterpret_cast<const float *>(work + kXBytes + kNBytes);
+        const float *sp = reinterpret_cast<const float *>(work + kXBytes);
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        const int supers = (npts + SUPER - 1) / SUPER;
+        const int tiles = (npts + 15) / 16;
 #pragma unroll
-        for (int ss = 0; ss < kBatch / SUPER; ++ss) {
-            if (ss >= supers) break;
-            const int p0 = ss * SUPER;
-            float a_d;
-            floatx4 c;
-            if (DIM == 2) {
-                a_d = sx[(p0 + (acol >> 1) * SET + arow) * XS + (acol & 1)];
-                c = *reinterpret_cast<const floatx4 *>(sn + p0 + (col >> 3) * SET + 4 * acol);
-            } else {
-                a_d = sx[(p0 + arow) * XS + acol];
-                c = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-            }
-            const floatx4 v = __builtin_amdgcn_mfma_f32_16x16x4f32(a_d, bop, c, 0, 0, 0);
+        for (int ss = 0; ss < kBatch / 16; ++ss) {
+            if (ss >= tiles) break;
+            const int p0 = ss * 16;
+            const float a_d = sx[(p0 + arow) * XS + acol];
+            const floatx4 v = __builtin_amdgcn_mfma_f32_16x16x4f32(a_d, bop, floatx4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
             float g[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) g[r] = gamma(A, v[r]);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int pt = DIM == 2 ? p0 + (arow >> 3) * SET + 4 * acol + r : p0 + 4 * acol + r;
-                const int row = DIM == 2 ? (arow & 7) : arow;
-                const float a = sp[pt * PS + row];
+                const float a = sp[(p0 + 4 * acol + r) * PS + arow];
                 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, g[r], acc, 0, 0, 0);
             }
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) dacc[r] += static_cast<double>(acc[r]);
     }
-    // D[i][j] (FP64) -> H/Q totals out[r*16 + b]; out may be the tile itself: in
-    // 2D each lane reads its own slot and a slot of rows 8..15, which nobody writes
+    // D[i][j] (FP64) -> H/Q totals out[r*16 + b]; out may be the tile itself
+    // (each lane reads back its own slots)
     __device__ void finish(double *out, double *tile)
     {
         const int l = lane_id();
@@ -650,13 +620,8 @@ template <int DIM, int ETA> struct MixedAccMfma {
 #pragma unroll
         for (int r = 0; r < 4; ++r) tile[(ib + r) * 16 + j] = dacc[r];
         wave_sync();
-        // padding columns hold gamma = 0, so their totals are 0 as well
-        constexpr int BW = DIM == 2 ? 8 : 16;
-        for (int t = l; t < S::NR * BW; t += kWave) {
-            const int r = t / BW, b = t % BW;
-            const double v = DIM == 2 ? tile[r * 16 + b] + tile[(r + 8) * 16 + (b + 8)] : tile[r * 16 + b];
-            out[r * 16 + b] = v;
-        }
+        // the padding column holds gamma = 0, so its totals are 0 as well
+        for (int t = l; t < S::NR * 16; t += kWave) out[t] = tile[t];
     }
 };
 
@@ -675,9 +640,13 @@ template <int DIM, int PREC> struct WaveMem {
     static constexpr int kEpiBytes = (PREC == 1 && kEpiRows < 16 ? 16 : kEpiRows) * 16 * 8;
     // the epilogue runs after the pair's last batch: it shares the staging area
     static constexpr int kWorkBytes = kStageBytes > kEpiBytes ? kStageBytes : kEpiBytes;
+    // vertices of the sub-elements of levels 2..kMemoLevel (FP64), formed once per pair
+    static constexpr int kMemoLevel = DIM == 2 ? 3 : 2;
+    static constexpr int kMemoCount = DIM == 2 ? 4 + 16 : 8;
+    static constexpr int kMemoBytes = kMemoCount * S::NV * DIM * 8;
     __host__ __device__ static int bytes(int capl)
     {
-        return (kWorkBytes + kLeafCap * 4 + capl * 4 + 15) & ~15;
+        return (kWorkBytes + kLeafCap * 4 + kMemoBytes + capl * 4 + 15) & ~15;
     }
 };
 
@@ -845,7 +814,8 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, char *wmem,
     double *HQ = reinterpret_cast<double *>(wmem);   // [rows][16], after the last batch
     double *tile = HQ;                               // 16 x 16 (mixed), in place
     uint32_t *leafbuf = reinterpret_cast<uint32_t *>(wmem + WM::kWorkBytes);
-    uint32_t *stack = leafbuf + kLeafCap;                              // A.capl entries
+    double *memo = reinterpret_cast<double *>(leafbuf + kLeafCap);    // WM::kMemoCount simplices
+    uint32_t *stack = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(memo) + WM::kMemoBytes);   // A.capl
 
     // geometry of l (root simplex) and m: wave-uniform
     Simplex<DIM> root;
@@ -939,6 +909,12 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, char *wmem,
     uint32_t *stk = stack;
     const int lmax = A.lmax, lmin = A.lmin;
     const int cap = A.capl - NCH * (lmax + 1) - kWave;   // logical capacity (see make_args)
+    // memo of the vertices of levels 2..memo_lev, formed when the first of them
+    // is classified; only levels below L_max are classified, and a memo pays off
+    // only if some classified level lies below it (its own levels save what
+    // forming it costs)
+    const int memo_lev = WM::kMemoLevel < lmax - 2 ? WM::kMemoLevel : lmax - 2;
+    bool memo_ready = memo_lev < 2;
     int n = 1;
     if (lane == 0) stk[0] = 1u << 24;
     wave_sync();
@@ -965,11 +941,28 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, char *wmem,
         wave_sync();
         const int lev = static_cast<int>(ent >> 24);
         const uint32_t local = ent & 0xFFFFFFu;
+        if (!memo_ready && wave_ballot(valid && lev >= 2)) {
+            // lane t < NCH: level 2, local t; then level 3, local t - NCH
+            const int count = memo_lev == 2 ? NCH : WM::kMemoCount;
+            if (lane < count) {
+                const int tlev = lane < NCH ? 2 : 3;
+                const int tloc = lane < NCH ? lane : lane - NCH;
+                Simplex<DIM> T = root;
+                for (int d = tlev - 2; d >= 0; --d) T = child_of(T, (tloc >> (DIM * d)) & (NCH - 1));
+                double *dst = memo + lane * NV * DIM;
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+#pragma unroll
+                    for (int k = 0; k < DIM; ++k) dst[v * DIM + k] = T.v[v][k];
+            }
+            wave_sync();
+            memo_ready = true;
+        }
         int cls = 0;
         if (valid) {
             if (lev == lmax) cls = 1;                 // the root when L_max = 1
             else if (lev < lmin) cls = 2;
-            else cls = classify<DIM>(A, root, lev, local, mlo, mhi);
+            else cls = classify<DIM>(A, root, memo, memo_lev, lev, local, mlo, mhi);
         }
         if (cls == 1 && s_leaf) atomicAdd(&s_leaf[lev], 1ull);
         push_leaf(cls == 1, cls == 1 ? leaf_entry(lev, level_offset<DIM>(lev) + static_cast<int>(local)) : 0u);

@@ -92,10 +92,10 @@ struct Tables {
     DevBuf rule;                // [nq][nv] points, then [nq] weights (double)
     DevBuf lam64;               // [n_sub][nq][nv] double
     DevBuf lam32;               // [n_sub][nq][nv] float
-    // 2D only: per quadrature point of every sub-element, the FP32 rows of the
+    // per quadrature point of every sub-element, the FP32 rows of the
     // contraction (w lambda_i, then w lambda_i lambda_j, i < j; w the rule weight
-    // scaled by the level's area ratio) and lambda_1, lambda_2: [n_sub*nq + 1][8],
-    // the last row zero (for lanes without a point)
+    // scaled by the level's volume ratio) and lambda_1..lambda_dim:
+    // [n_sub*nq + 1][8 (2D) or 16 (3D)], the last row zero (lanes without a point)
     DevBuf pt32;
 };
 

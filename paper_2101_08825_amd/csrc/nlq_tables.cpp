@@ -172,22 +172,22 @@ std::unique_ptr<Tables> make_tables(Ctx *ctx, int dim, int lmax)
         cur.swap(next);
     }
     for (size_t k = 0; k < lam.size(); ++k) lam32[k] = static_cast<float>(lam[k]);
-    if (dim == 2) {
+    {
         // the same FP32 operations as forming the rows point by point: w scaled
-        // by 4^-(level-1) exactly, then products rounded one at a time
-        std::vector<float> pt(static_cast<size_t>(t->n_sub * nq + 1) * 8, 0.0f);
+        // by 2^-dim(level-1) exactly, then products rounded one at a time
+        const int stride = dim == 2 ? 8 : 16, nr = nv * (nv + 1) / 2;
+        std::vector<float> pt(static_cast<size_t>(t->n_sub * nq + 1) * stride, 0.0f);
         for (int lev = 1; lev <= lmax; ++lev)
             for (int64_t sub = t->lvl_off[lev]; sub < t->lvl_off[lev + 1]; ++sub)
                 for (int a = 0; a < nq; ++a) {
                     const float *l = &lam32[(static_cast<size_t>(sub) * nq + a) * nv];
-                    float *o = &pt[(static_cast<size_t>(sub) * nq + a) * 8];
+                    float *o = &pt[(static_cast<size_t>(sub) * nq + a) * stride];
                     const float w = std::ldexp(static_cast<float>(t->w[a]), -dim * (lev - 1));
                     for (int i = 0; i < nv; ++i) o[i] = w * l[i];
                     int r = nv;
                     for (int i = 0; i < nv; ++i)
                         for (int j = i + 1; j < nv; ++j) o[r++] = o[i] * l[j];
-                    o[6] = l[1];
-                    o[7] = l[2];
+                    for (int i = 1; i < nv; ++i) o[nr + i - 1] = l[i];
                 }
         t->pt32.alloc(ctx, pt.size() * sizeof(float));
         NLQ_HIP(hipMemcpy(t->pt32.as<void>(), pt.data(), pt.size() * sizeof(float), hipMemcpyHostToDevice));
