@@ -76,7 +76,17 @@ typedef struct nlq_system nlq_system;
  *             NLQ_FP32_MIXED: FP32 evaluation at anchor-relative coordinates,
  *             FP32 matrix-core contraction per 64-point batch, FP64 per-pair
  *             blocks and FP64 global accumulation.
- *  deterministic  reserved, must be 0.
+ *  deterministic  0: the per-pair blocks are added to the matrix with FP64
+ *             atomics (the order of additions, and so the last bits of the
+ *             values, vary from run to run).  1: fixed-order sums (each pair's
+ *             block is stored, then every entry sums its contributions in
+ *             element and pair-list order), so the matrix is the same bit for
+ *             bit from run to run and however launches are shared; slower, and
+ *             it needs about (N+1)^2 + (N+1)(N+2) doubles per pair of a slab of
+ *             up to 8M pairs plus one double per entry and element of its
+ *             node.  Such a system is integrated by itself: nlq_integrate_range
+ *             rejects it, nlq_assemble_batch and the serving loop integrate it
+ *             alone, nlq_autotune leaves it untuned.
  */
 typedef struct {
     int32_t dim;

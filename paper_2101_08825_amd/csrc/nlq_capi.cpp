@@ -87,7 +87,7 @@ void check_params(const Mesh &m, const nlq_params &p)
     if (p.form != NLQ_FORM_SYM4 && p.form != NLQ_FORM_PAPER2) fail(NLQ_EINVAL, "unknown form");
     if (p.precision != NLQ_FP64_PLAIN && p.precision != NLQ_FP32_MIXED)
         fail(NLQ_EINVAL, "unknown precision");
-    if (p.deterministic != 0) fail(NLQ_EINVAL, "deterministic mode is reserved");
+    if (p.deterministic != 0 && p.deterministic != 1) fail(NLQ_EINVAL, "deterministic must be 0 or 1");
     if (p.scale < 0.0) fail(NLQ_EINVAL, "scale must be >= 0");
 }
 
@@ -473,6 +473,7 @@ nlq_status nlq_integrate_range(nlq_system *sys, int64_t lo, int64_t hi, double *
         const int64_t ne = s.mesh->n_elems;
         if (lo < 1 || hi >= ne || lo >= hi)
             fail(NLQ_EINVAL, "need 0 < lo < hi < n_elems (a range that neither clears nor finishes the values)");
+        if (s.p.deterministic) fail(NLQ_EINVAL, "a deterministic system is integrated whole");
         NLQ_HIP(hipSetDevice(s.ctx->device));
         hipStream_t st = s.ctx->stream;
         hipEvent_t e0, e1;
@@ -511,9 +512,10 @@ nlq_status nlq_assemble_batch(nlq_ctx *ctx, int32_t n, const nlq_mesh *const *me
         // one group per (dim, precision, kernel); up to 32 systems per launch
         std::vector<int> order(n);
         for (int i = 0; i < n; ++i) order[i] = i;
+        // (a deterministic system is a group of its own)
         auto key = [&](int i) {
             const System &s = made[i]->impl;
-            return std::make_tuple(s.mesh->dim, s.p.precision, s.p.kernel);
+            return std::make_tuple(s.mesh->dim, s.p.precision, s.p.kernel, s.p.deterministic ? i + 1 : 0);
         };
         std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(x) < key(y); });
         LaunchBlock lb;
@@ -529,7 +531,8 @@ nlq_status nlq_assemble_batch(nlq_ctx *ctx, int32_t n, const nlq_mesh *const *me
                 ++g1;
             }
             const double t0 = now_s();
-            launch_integrate_jobs(&ctx->impl, lb, jobs, st, e0, e1);
+            if (jobs.size() == 1 && jobs[0].s->p.deterministic) launch_integrate(*jobs[0].s, st, e0, e1);
+            else launch_integrate_jobs(&ctx->impl, lb, jobs, st, e0, e1);
             NLQ_HIP(hipStreamSynchronize(st));
             const double t1 = now_s();
             float ms = 0.0f;

@@ -87,8 +87,10 @@ struct AsmArgs {
     double *val;
     const double *lam64;  // [sub][nq][nv]
     const float *lam32;
-    const float *pt32;    // 2D: rows of the FP32 contraction per point (see the tables)
+    const float *pt32;    // rows of the FP32 contraction per point (see the tables)
     int pt32_zero;        // its zero row
+    double *pb;           // deterministic mode: per-pair outputs [pair - pb_base][NV^2 + 2 NR], else null
+    int64_t pb_base;
     const double *rule;   // [nq][nv] barycentric points, then [nq] weights
     double delta, eps, dme, dpe, dme2, dpe2, C;
     double dme_sq;        // s* with (sqrt(s) < delta - eps) <=> (s < s*), s >= 0
@@ -797,9 +799,9 @@ template <int DIM> __device__ __forceinline__ void extend_rows(double *HQ)
 // -------------------------------------------------------------- one pair
 
 template <int DIM, int PREC, int ETA>
-__device__ __forceinline__ void process_pair(CArgs &A, int l, int m, char *wmem, const double *s_rule,
-                             const float *s_w32, const double *s_T, const int *s_desc, double *s_bll,
-                             const RowCache *rc, double *ex_block, unsigned long long *s_leaf)
+__device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pidx, char *wmem,
+                             const double *s_rule, const float *s_w32, const double *s_T, const int *s_desc,
+                             double *s_bll, const RowCache *rc, double *ex_block, unsigned long long *s_leaf)
 {
     using S = Shape<DIM>;
     constexpr int NV = S::NV, NQ = S::NQ, NCH = S::NCH, NR = S::NR;
@@ -1036,6 +1038,12 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, char *wmem,
         }
         return;
     }
+    if (A.pb) {
+        // deterministic mode: the outputs of pair pidx, in descriptor order, are
+        // summed later in a fixed order
+        if (kind != kOutNone) A.pb[(pidx - A.pb_base) * (NV * NV + 2 * NR) + lane] = v;
+        return;
+    }
     if (kind == kOutLM) {
         // B_lm at (l_i, m_j) through the cached row of l_i.  SYM4 adds it to the
         // half matrix R (A = R + R^T afterwards); the two-term form puts 2 B_lm^T
@@ -1154,12 +1162,12 @@ k_integrate(LaunchArgs L)
             p = bcast0(p);
             if (p >= p_hi) break;
             const int32_t m = A.pair_m[b0 + p];
-            process_pair<DIM, PREC, ETA>(A, static_cast<int>(l), m, wmem, s_rule, s_w32, s_T, s_desc,
-                                         s_bll, &s_rc, nullptr, s_leaf);
+            process_pair<DIM, PREC, ETA>(A, static_cast<int>(l), m, b0 + p, wmem, s_rule, s_w32, s_T,
+                                         s_desc, s_bll, &s_rc, nullptr, s_leaf);
         }
         __syncthreads();
         // B_ll of l (upper triangle) joins the diagonal-block sums of l
-        if (A.form == NLQ_FORM_SYM4 && threadIdx.x < NR)
+        if (A.form == NLQ_FORM_SYM4 && !A.pb && threadIdx.x < NR)
             unsafeAtomicAdd(&A.dmm[l * NR + threadIdx.x], s_bll[threadIdx.x]);
         if (threadIdx.x >= 1 && threadIdx.x <= A.lmax && s_leaf[threadIdx.x])
             atomicAdd(&A.counters->leaf[threadIdx.x], s_leaf[threadIdx.x]);
@@ -1199,7 +1207,7 @@ k_pair_blocks(LaunchArgs L)
         double *blk = A.ex_out + static_cast<int64_t>(it) * (2 * NV) * (2 * NV);
         for (int t = lane_id(); t < 4 * NV * NV; t += kWave) blk[t] = 0.0;
         wave_sync();
-        process_pair<DIM, PREC, ETA>(A, A.ex_l[it], A.ex_m[it], wmem, s_rule, s_w32, s_T, s_desc, nullptr,
+        process_pair<DIM, PREC, ETA>(A, A.ex_l[it], A.ex_m[it], -1, wmem, s_rule, s_w32, s_T, s_desc, nullptr,
                                      nullptr, blk, nullptr);
     }
 }
@@ -1387,6 +1395,8 @@ AsmArgs make_args(const System &s, const Tables &T)
     A.rowcap = static_cast<int>(std::min<int64_t>(std::max<int64_t>(s.max_row, 1), 2048));
     A.counters = s.counters.as<AsmCounters>();
     A.split = split_of(s);
+    A.pb = s.det_pb;
+    A.pb_base = s.det_pb_base;
     return A;
 }
 
@@ -1435,6 +1445,8 @@ void launch_integrate_jobs(Ctx *ctx, LaunchBlock &lb, const std::vector<Integrat
         const System &s = *j.s;
         if (s.mesh->dim != s0.mesh->dim || s.p.precision != s0.p.precision || s.p.kernel != s0.p.kernel)
             fail(NLQ_EINVAL, "one launch takes systems of one dimension, precision and kernel");
+        if (s.p.deterministic && (!s.det_pb || jobs.size() != 1))
+            fail(NLQ_EINVAL, "a deterministic system is integrated by itself (nlq_assemble)");
         if (j.lo < 0 || j.hi > s.mesh->n_elems || j.lo > j.hi) fail(NLQ_EINVAL, "bad outer-element range");
         int k = 0;
         while (k < static_cast<int>(systems.size()) && systems[k] != &s) ++k;
@@ -1482,9 +1494,10 @@ void launch_integrate_jobs(Ctx *ctx, LaunchBlock &lb, const std::vector<Integrat
     L.counter = reinterpret_cast<unsigned int *>(d);
     if (items > 0) dispatch(ctx, s0, s0.cfg, L, items, st, false, e0, e1);
     // systems whose last outer element is in this launch: diagonal blocks and R + R^T
+    // (in deterministic mode the fixed-order sums do both)
     for (const auto &j : jobs) {
         const System &s = *j.s;
-        if (j.hi != s.mesh->n_elems) continue;
+        if (j.hi != s.mesh->n_elems || s.det_pb) continue;
         const int dim = s.mesh->dim;
         const int four = s.p.form == NLQ_FORM_SYM4;
         const int64_t nf = s.mesh->n_elems * (dim == 2 ? 6 : 10);
@@ -1524,9 +1537,18 @@ int64_t integrate_slots(Ctx *ctx, const System &s)
 
 int integrate_split(const System &s) { return split_of(s); }
 
+void launch_symmetrize(const System &s, hipStream_t st)
+{
+    if (s.nnz <= 0) return;
+    hipLaunchKernelGGL(k_symmetrize, dim3(static_cast<unsigned>((s.nnz + 255) / 256)), dim3(256), 0, st, s.nnz,
+                       s.tmap.as<int32_t>(), s.val.as<double>());
+    NLQ_CHECK_LAUNCH();
+}
+
 void launch_integrate(System &s, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
-    launch_integrate_jobs(s.ctx, s.launch, {IntegrateJob{&s, 0, s.mesh->n_elems}}, st, e0, e1);
+    if (s.p.deterministic) integrate_deterministic(s, st, e0, e1);
+    else launch_integrate_jobs(s.ctx, s.launch, {IntegrateJob{&s, 0, s.mesh->n_elems}}, st, e0, e1);
 }
 
 void launch_pair_blocks(System &s, hipStream_t st, int64_t n, const int32_t *ex_l, const int32_t *ex_m,

@@ -186,6 +186,11 @@ struct System {
     // rhs / solution
     DevBuf F, Ft, u, g;          // [n] double
     DevBuf counters;             // AsmCounters
+    // deterministic mode: node -> elements (ascending), element row offsets, and
+    // the per-pair output buffer of the slab being integrated
+    DevBuf n2e_off, n2e, eoff;
+    double *det_pb = nullptr;
+    int64_t det_pb_base = 0;
     LaunchBlock launch;          // argument block of this system's own launches
     TuneConfig cfg;              // integration launch configuration
     nlq_assemble_info info{};
@@ -221,6 +226,11 @@ struct IntegrateJob {
 void launch_integrate_jobs(Ctx *ctx, LaunchBlock &lb, const std::vector<IntegrateJob> &jobs, hipStream_t st,
                            hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 void launch_integrate(System &s, hipStream_t st, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// deterministic mode (nlq_params.deterministic): the whole integration with
+// fixed-order sums (nlq_det.hip); launch_integrate calls it for such systems
+void integrate_deterministic(System &s, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop);
+// A = R + R^T in place (four-term form)
+void launch_symmetrize(const System &s, hipStream_t st);
 // resident workgroups of one integration launch of s, and work items per outer element
 int64_t integrate_slots(Ctx *ctx, const System &s);
 int integrate_split(const System &s);

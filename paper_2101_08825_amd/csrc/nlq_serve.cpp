@@ -33,12 +33,13 @@ double serve_now()
 
 using MeshKey = std::tuple<int, int, int>;
 // mesh key + every parameter that changes the matrix
-using SysKey = std::tuple<int, int, int, int, double, double, double, int, int, int, int>;
+using SysKey = std::tuple<int, int, int, int, double, double, double, int, int, int, int, int>;
 
 SysKey sys_key(const nlq_request &r)
 {
     const nlq_params &p = r.params;
-    return SysKey(r.dim, r.n, r.k_gamma, p.kernel, p.delta, p.eps, p.scale, p.lmin, p.lmax, p.form, p.precision);
+    return SysKey(r.dim, r.n, r.k_gamma, p.kernel, p.delta, p.eps, p.scale, p.lmin, p.lmax, p.form, p.precision,
+                  p.deterministic);
 }
 
 // Integration group: one launch takes systems of one (dim, precision, kernel);
@@ -264,6 +265,9 @@ void do_setup(Server &S, const ReqPtr &r, hipStream_t st)
     }
     r->own = prepare_system(*S.ctx, M, r->req.params, st);
     System &s = r->own->impl;
+    // a deterministic request is integrated by itself, here
+    const bool det = r->req.params.deterministic != 0;
+    if (det && M.n_elems > 0) run_integrate(s, st);
     r->n_pairs = s.n_pairs;
     r->split = integrate_split(s);
     r->slots = integrate_slots(S.ctx, s);
@@ -276,8 +280,9 @@ void do_setup(Server &S, const ReqPtr &r, hipStream_t st)
     r->est = 0;
     if (r->cancelled) throw Error{NLQ_ECANCELLED, "cancelled"};
     r->t_setup = r->t_turn = serve_now();
-    if (M.n_elems == 0) {
+    if (M.n_elems == 0 || det) {
         r->t_ready = r->t_setup;
+        r->launches = det && M.n_elems > 0 ? 1 : 0;
         S.solve_q.push_back(r);
         return;
     }

@@ -47,6 +47,44 @@ __global__ void k_load(int64_t ne, const int32_t *__restrict__ conn, const doubl
     }
 }
 
+// The same load vector summed per node over its elements in ascending order
+// (deterministic mode: no atomics, so F is the same bit for bit every time).
+template <int DIM>
+__global__ void k_load_ordered(int64_t nn, const int64_t *__restrict__ n2e_off, const int32_t *__restrict__ n2e,
+                               const int32_t *__restrict__ conn, const double *__restrict__ meas,
+                               const double *__restrict__ rule, const double *__restrict__ f,
+                               const uint8_t *__restrict__ constrained, double *__restrict__ F)
+{
+    constexpr int NV = DIM + 1, NQ = DIM == 2 ? 7 : 15;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= nn) return;
+    const double *bary = rule;
+    const double *w = rule + NQ * NV;
+    double acc = 0.0;
+    if (!constrained[i]) {
+        for (int64_t q0 = n2e_off[i]; q0 < n2e_off[i + 1]; ++q0) {
+            const int64_t e = n2e[q0];
+            double fv[NV];
+            int a = 0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const int32_t id = conn[e * NV + v];
+                fv[v] = f[id];
+                if (id == i) a = v;
+            }
+            double s = 0.0;
+            for (int q = 0; q < NQ; ++q) {
+                double fq = 0.0;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) fq += fv[v] * bary[q * NV + v];
+                s += w[q] * fq * bary[q * NV + a];
+            }
+            acc += s * meas[e];
+        }
+    }
+    F[i] = acc;
+}
+
 // one wave per row: F~_i = F_i - sum_{j in Gamma} A_ij g_j (free i), 0 on Gamma
 __global__ void __launch_bounds__(256)
 k_lift(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
@@ -249,7 +287,18 @@ void launch_load_lift(System &s, hipStream_t st, const double *f_dev, const doub
     if (s.Ft.empty()) s.Ft.alloc(s.ctx, sizeof(double) * n);
     NLQ_HIP(hipMemsetAsync(s.F.as<void>(), 0, sizeof(double) * n, st));
     dim3 g1((ne + 255) / 256), b1(256);
-    if (m.dim == 2)
+    if (s.p.deterministic && !s.n2e_off.empty() && n > 0) {
+        const dim3 gn((n + 255) / 256);
+        if (m.dim == 2)
+            hipLaunchKernelGGL(k_load_ordered<2>, gn, b1, 0, st, n, s.n2e_off.as<int64_t>(), s.n2e.as<int32_t>(),
+                               m.conn.as<int32_t>(), s.meas.as<double>(), T.rule.as<double>(), f_dev,
+                               m.constrained.as<uint8_t>(), s.F.as<double>());
+        else
+            hipLaunchKernelGGL(k_load_ordered<3>, gn, b1, 0, st, n, s.n2e_off.as<int64_t>(), s.n2e.as<int32_t>(),
+                               m.conn.as<int32_t>(), s.meas.as<double>(), T.rule.as<double>(), f_dev,
+                               m.constrained.as<uint8_t>(), s.F.as<double>());
+    } else if (ne == 0) {
+    } else if (m.dim == 2)
         hipLaunchKernelGGL(k_load<2>, g1, b1, 0, st, ne, m.conn.as<int32_t>(), s.meas.as<double>(),
                            T.rule.as<double>(), f_dev, m.constrained.as<uint8_t>(), s.F.as<double>());
     else

@@ -45,6 +45,8 @@ int autotune(System &s, hipStream_t st, double budget_s, double *best_ms, double
     Ctx &ctx = *s.ctx;
     const int64_t ne = s.mesh->n_elems;
     const TuneConfig base{};
+    *best_ms = *default_ms = 0.0;
+    if (s.p.deterministic) return 0;   // sample ranges are not integrated on their own in this mode
     // candidates: the default first, then the register variant, one workgroup
     // less per CU, and other work-item sizes where the pair lists get cut
     std::vector<TuneConfig> cand{base};

@@ -162,9 +162,9 @@ def _ptr(a):
 
 
 def params(dim, delta, eps, lmax, lmin=1, kernel=NLQ_ETA_CONST, form=NLQ_FORM_SYM4,
-           precision=NLQ_FP64_PLAIN, scale=0.0):
+           precision=NLQ_FP64_PLAIN, scale=0.0, deterministic=False):
     return nlq_params(int(dim), int(kernel), float(delta), float(eps), float(scale), int(lmin),
-                      int(lmax), int(form), int(precision), 0)
+                      int(lmax), int(form), int(precision), int(bool(deterministic)))
 
 
 class Context:
