@@ -266,7 +266,7 @@ template <int DIM> __device__ __forceinline__ int level_offset(int lev)
 // root, or from its ancestor at level min(lev, memo_lev) whose vertices the
 // memo holds (formed by the same recursion; memo_lev < 2: no memo).
 template <int DIM>
-__device__ __forceinline__ int classify(CArgs &A, const Simplex<DIM> &root, const double *memo, int memo_lev,
+__device__ __forceinline__ int classify(CArgs &A, const Simplex<DIM> root, const double *memo, int memo_lev,
                                         int lev, uint32_t local, const double *mlo, const double *mhi)
 {
     constexpr int NCH = 1 << DIM, NV = DIM + 1;
@@ -642,9 +642,11 @@ template <int DIM, int PREC> struct WaveMem {
     static constexpr int kEpiBytes = (PREC == 1 && kEpiRows < 16 ? 16 : kEpiRows) * 16 * 8;
     // the epilogue runs after the pair's last batch: it shares the staging area
     static constexpr int kWorkBytes = kStageBytes > kEpiBytes ? kStageBytes : kEpiBytes;
-    // vertices of the sub-elements of levels 2..kMemoLevel (FP64), formed once per pair
-    static constexpr int kMemoLevel = DIM == 2 ? 3 : 2;
-    static constexpr int kMemoCount = DIM == 2 ? 4 + 16 : 8;
+    // vertices of the sub-elements of levels 2..kMemoLevel (FP64), formed once per
+    // pair (2D only: in 3D it measured 1% faster at L_max 4 but 3% slower at
+    // L_max 3, where it is not even used)
+    static constexpr int kMemoLevel = DIM == 2 ? 3 : 1;
+    static constexpr int kMemoCount = DIM == 2 ? 4 + 16 : 0;
     static constexpr int kMemoBytes = kMemoCount * S::NV * DIM * 8;
     __host__ __device__ static int bytes(int capl)
     {
@@ -819,17 +821,23 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     double *memo = reinterpret_cast<double *>(leafbuf + kLeafCap);    // WM::kMemoCount simplices
     uint32_t *stack = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(memo) + WM::kMemoBytes);   // A.capl
 
-    // geometry of l (root simplex) and m: wave-uniform
+    // geometry of l (root simplex) and m: wave-uniform, read through the scalar
+    // cache into scalar registers (read-only tables), which keeps them out of
+    // the vector register budget
+    typedef const __attribute__((address_space(4))) double cdouble;
+    const cdouble *cvert = (const cdouble *)(A.vert);
+    const cdouble *clo = (const cdouble *)(A.lo);
+    const cdouble *chi = (const cdouble *)(A.hi);
     Simplex<DIM> root;
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) root.v[v][k] = A.vert[(v * DIM + k) * ne + l];
+        for (int k = 0; k < DIM; ++k) root.v[v][k] = cvert[(v * DIM + k) * ne + l];
     double mlo[DIM], mhi[DIM];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        mlo[k] = A.lo[k * ne + m];
-        mhi[k] = A.hi[k * ne + m];
+        mlo[k] = clo[k * ne + m];
+        mhi[k] = chi[k * ne + m];
     }
     const double *bary = s_rule;
     const double *wq = s_rule + NQ * NV;
@@ -846,7 +854,7 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     for (int k = 0; k < DIM; ++k) {
         double s = 0.0;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) s = fma(bary[bq * NV + v], A.vert[(v * DIM + k) * ne + m], s);
+        for (int v = 0; v < NV; ++v) s = fma(bary[bq * NV + v], cvert[(v * DIM + k) * ne + m], s);
         y[k] = s - root.v[0][k];
     }
     Edges<DIM, Real> E;   // edges v_i - v_0 of l
@@ -915,7 +923,7 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     // is classified; only levels below L_max are classified, and a memo pays off
     // only if some classified level lies below it (its own levels save what
     // forming it costs)
-    const int memo_lev = WM::kMemoLevel < lmax - 2 ? WM::kMemoLevel : lmax - 2;
+    const int memo_lev = WM::kMemoLevel < 2 ? 0 : (WM::kMemoLevel < lmax - 2 ? WM::kMemoLevel : lmax - 2);
     bool memo_ready = memo_lev < 2;
     int n = 1;
     if (lane == 0) stk[0] = 1u << 24;
