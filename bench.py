@@ -130,7 +130,7 @@ def serve_replay(nlq, ctx, precision, n_requests, cache):
         tickets.append(srv.submit(r.dim, r.n, r.k_delta, prm, f, g, rtol=1e-10))
     progress(f"serving precision {precision}: {len(tickets)} requests submitted")
     res = []
-    deadline = time.perf_counter() + 240.0
+    deadline = time.perf_counter() + 420.0
     for k, t in enumerate(tickets):
         while True:
             x = srv.wait(t, timeout_ms=5000)
@@ -139,7 +139,7 @@ def serve_replay(nlq, ctx, precision, n_requests, cache):
             st = srv.stats()
             progress(f"serving precision {precision}: waiting for request {k}: {st}")
             if time.perf_counter() > deadline:
-                progress("serving did not finish within 240 s; exiting without stopping the server")
+                progress("serving did not finish within 420 s; exiting without stopping the server")
                 os._exit(3)
         res.append(x)
         progress(f"serving precision {precision}: request {k} done in {1e3 * x['latency_s']:.1f} ms "
@@ -201,7 +201,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-cache", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
@@ -294,7 +294,8 @@ def main():
         },
     }
     if serve:
-        out["serving"] = dict(serve, workload=f"first {serve['requests']} requests of the seeded stream "
+        which = "all" if serve["requests"] >= 256 else f"first {serve['requests']} of the"
+        out["serving"] = dict(serve, workload=f"{which} 256 requests of the seeded stream "
                               "(Poisson 20/s, 2D 8^2..96^2 / 3D 6^3..20^3, delta 2h..4h, eps delta/16, "
                               "depth 3), open loop", matrix_cache=bool(args.serve_cache))
     if serve64:

@@ -252,9 +252,10 @@ nlq_status nlq_system_destroy(nlq_system *sys);
  *    every request whose matrix is ready, the setup (element tables, pair list,
  *    pattern) of the admitted requests, smallest first (for about one launch
  *    target), then one shared integration launch of one group: that of the
- *    request nearest to completion, in a launch just long enough for it to
- *    finish -- unless a request has waited for a launch longer than four
- *    targets: then its group, for the target duration.
+ *    most urgent request -- least estimated integration time left, minus a
+ *    quarter of its wait for a launch -- in a launch just long enough for it
+ *    to finish (at most the target duration), holding up to 32 requests of
+ *    the group, most urgent first.
  *  - Integration: outer elements of all assembled-but-not-integrated requests of
  *    one (dim, precision, kernel) group share persistent launches (at most 32
  *    requests per launch, see nlq_assemble_batch); a launch is sized from the

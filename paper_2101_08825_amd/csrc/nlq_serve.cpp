@@ -328,6 +328,19 @@ struct Chunk {
     int64_t lo, hi, pairs, items;
 };
 
+// Scheduling score (lower goes first): the estimated integration time left
+// (remaining pairs / the group's measured rate) minus a quarter of the time the
+// request has waited for a launch -- shortest remaining work first, so small
+// requests pass large ones, with aging: a request waits at most about four
+// times its own remaining time before it outranks new arrivals.
+double urgency(const Server &S, const Request &r, double now)
+{
+    auto it = S.rate.find(rate_key(r));
+    const double rate = it != S.rate.end() ? it->second : initial_rate(r);
+    const double left = static_cast<double>(r.pair_off.back() - r.pair_off[r.cursor]) / rate;
+    return left - 0.25 * (now - r.t_turn);
+}
+
 // Water-filling of a pair budget: every request of the group gets an equal
 // share, capped by what it has left; what the small ones leave goes to the
 // others.  Returns outer-element ranges (at least one element each).
@@ -379,11 +392,15 @@ std::vector<Chunk> water_fill(const std::vector<ReqPtr> &rs, double budget)
 // pairs left finish under water-filling -- raised until the launch holds at least
 // two work items per resident workgroup (or everything that is left), so that
 // the persistent grid is busy.
-std::vector<Chunk> plan_launch(Server &S, const GroupKey &g, int64_t finish_pairs)
+std::vector<Chunk> plan_launch(Server &S, const GroupKey &g, int64_t finish_pairs, double now)
 {
+    // up to 32 requests of the group, most urgent first
     std::vector<ReqPtr> rs;
     for (auto &r : S.ready)
-        if (group_of(*r) == g && rs.size() < 32) rs.push_back(r);
+        if (group_of(*r) == g) rs.push_back(r);
+    std::stable_sort(rs.begin(), rs.end(),
+                     [&](const ReqPtr &a, const ReqPtr &b) { return urgency(S, *a, now) < urgency(S, *b, now); });
+    if (rs.size() > 32) rs.resize(32);
     double budget = 0.0;
     int64_t slots = 1, left_items = 0;
     for (auto &r : rs) {
@@ -425,30 +442,20 @@ void run_launch(Server *S, LaunchBlock &lb, hipEvent_t e0, hipEvent_t e1)
             }
         }
         if (S->ready.empty()) return;
-        // the group to launch: that of the request nearest to completion
-        // (remaining pairs / the group's measured rate), in a launch just long
-        // enough for it to finish, so that small requests go through at once;
-        // but once a request has waited for a launch longer than four launch
-        // targets, its group, for the full target, so that no group starves
+        // the group of the most urgent request, in a launch just long enough
+        // for that request to finish (at most the target duration), so that a
+        // small request goes through at once
         const double now = serve_now();
-        const Request *oldest = S->ready.front().get();
-        for (auto &r : S->ready)
-            if (r->t_turn < oldest->t_turn) oldest = r.get();
-        const bool nearest = now - oldest->t_turn <= 4e-3 * S->cfg.target_launch_ms;
-        const Request *pick = oldest;
-        if (nearest) {
-            double best = 1e300;
-            for (auto &r : S->ready) {
-                auto it = S->rate.find(rate_key(*r));
-                const double rate = it != S->rate.end() ? it->second : initial_rate(*r);
-                const double left = static_cast<double>(r->pair_off.back() - r->pair_off[r->cursor]) / rate;
-                if (left < best) {
-                    best = left;
-                    pick = r.get();
-                }
+        const Request *pick = S->ready.front().get();
+        double best = urgency(*S, *pick, now);
+        for (auto &r : S->ready) {
+            const double u = urgency(*S, *r, now);
+            if (u < best) {
+                best = u;
+                pick = r.get();
             }
         }
-        plan = plan_launch(*S, group_of(*pick), nearest ? pick->pair_off.back() - pick->pair_off[pick->cursor] : 0);
+        plan = plan_launch(*S, group_of(*pick), pick->pair_off.back() - pick->pair_off[pick->cursor], now);
     }
     std::vector<IntegrateJob> jobs;
     for (auto &c : plan) jobs.push_back(IntegrateJob{&c.r->sys(), c.lo, c.hi});
@@ -562,7 +569,7 @@ void device_main(Server *S)
         // set up admitted requests (for up to one launch target, at least one),
         // so that the next launch shares as many as possible: the smallest
         // first (by the admission estimate), unless the longest-waiting one has
-        // waited for more than four launch targets
+        // waited for more than a second
         const double t_pass = serve_now();
         const double setup_budget = std::max(1e-3 * S->cfg.target_launch_ms, 0.005);
         for (;;) {
@@ -571,7 +578,7 @@ void device_main(Server *S)
                 std::lock_guard<std::mutex> lk(S->mu);
                 if (S->setup_q.empty()) break;
                 auto at = S->setup_q.begin();
-                if (serve_now() - (*at)->t_admit <= 4e-3 * S->cfg.target_launch_ms)
+                if (serve_now() - (*at)->t_admit <= 1.0)
                     for (auto it = S->setup_q.begin(); it != S->setup_q.end(); ++it)
                         if ((*it)->est < (*at)->est) at = it;
                 r = *at;
