@@ -508,9 +508,9 @@ template <int DIM, int ETA> struct MixedAccDirect {
 // FP32 mixed path, both products on the matrix cores (3D; v_mfma_f32_16x16x4f32;
 // operand layout: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, C and D
 // [i][j] in lane j + 16(i/4), register i%4):
-//  * distances: D = |x_i|^2 - 2 x_i . y_j for 16 outer points i x 16 columns j,
-//    K = (x, y, z, |x|^2) . (-2y, 1); 15 inner points + 1 padding column;
-//    |y_j|^2 is added per lane;
+//  * distances: D = |x_i|^2 - 2 x_i . y_j + |y_j|^2 for 16 outer points i x 16
+//    columns j, K = (x, y, z, |x|^2) . (-2y, 1) and C = |y_j|^2; 15 inner
+//    points + 1 padding column;
 //  * gamma_eps of the four distances a lane holds (its rows 4g..4g+3);
 //  * contraction H = P^T G: register r of the distance tile is exactly the B
 //    operand of step r (K index k <-> row 4k + r), A = the P rows of those
@@ -580,11 +580,11 @@ template <int DIM, int ETA> struct MixedAccMfma {
         dst[3] = make_float2(in.r1[2], in.r1[3]);
         dst[4] = make_float2(in.r2[0], in.r2[1]);
     }
-    // gamma_eps / C of tile value v = |x|^2 - 2 x.y: |x - y|^2 = v + |y|^2, clamped
+    // gamma_eps / C of tile value v = |x|^2 - 2 x.y + |y|^2 = |x - y|^2, clamped
     // at 0 against the cancellation of nearly equal points
     __device__ __forceinline__ float gamma(CArgs &A, float v) const
     {
-        const float d2 = fmaxf(v + yb2, 0.0f);
+        const float d2 = fmaxf(v, 0.0f);
         float g = mu32(A, __builtin_amdgcn_sqrtf(d2), doe);
         if (ETA == NLQ_ETA_GAUSS) g *= __expf(-d2 * A.f_inv_delta2);
         return g;
@@ -600,7 +600,8 @@ template <int DIM, int ETA> struct MixedAccMfma {
             if (ss >= tiles) break;
             const int p0 = ss * 16;
             const float a_d = sx[(p0 + arow) * XS + acol];
-            const floatx4 v = __builtin_amdgcn_mfma_f32_16x16x4f32(a_d, bop, floatx4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+            // C = |y_j|^2 in every row: the tile is |x_i - y_j|^2 directly
+            const floatx4 v = __builtin_amdgcn_mfma_f32_16x16x4f32(a_d, bop, floatx4{yb2, yb2, yb2, yb2}, 0, 0, 0);
             float g[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) g[r] = gamma(A, v[r]);
