@@ -119,7 +119,10 @@ typedef struct {
 /* ---- context ------------------------------------------------------------ */
 
 /* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
- * memory the context may hold (0 = 90% of the device's free memory). */
+ * memory the context may hold (0 = 90% of the device's free memory).
+ * For failure-path tests, the environment variable NLQ_FAIL_ALLOC_AT=k (read
+ * here) makes the k-th device allocation of this context (counted from 0)
+ * fail once with NLQ_ENOMEM. */
 nlq_status nlq_ctx_create(int32_t device, uint64_t hbm_budget_bytes, nlq_ctx **out);
 /* Run all later device work of this context on `hip_stream` (a hipStream_t,
  * e.g. torch's current stream); NULL restores the context's own stream. */

@@ -3,6 +3,7 @@
 // errors and returns an nlq_status; nothing aborts.
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 
@@ -22,6 +23,8 @@ void DevBuf::alloc(Ctx *ctx, size_t bytes, hipStream_t st)
 {
     release();
     if (bytes == 0) bytes = 8;
+    if (ctx->allocs.fetch_add(1) == ctx->alloc_fail_at)
+        fail(NLQ_ENOMEM, "injected allocation failure (NLQ_FAIL_ALLOC_AT)");
     const uint64_t now = ctx->used.fetch_add(bytes) + bytes;
     if (now > ctx->budget) {
         ctx->used.fetch_sub(bytes);
@@ -329,6 +332,7 @@ nlq_status nlq_ctx_create(int32_t device, uint64_t hbm_budget_bytes, nlq_ctx **o
         c->impl.budget = hbm_budget_bytes ? hbm_budget_bytes : static_cast<uint64_t>(0.9 * fr);
         NLQ_HIP(hipStreamCreateWithFlags(&c->impl.own_stream, hipStreamNonBlocking));
         c->impl.stream = c->impl.own_stream;
+        if (const char *env = std::getenv("NLQ_FAIL_ALLOC_AT")) c->impl.alloc_fail_at = std::atoll(env);
         *out = c.release();
     });
 }

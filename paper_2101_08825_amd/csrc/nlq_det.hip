@@ -272,32 +272,33 @@ k_det_gather(int64_t nn, const int64_t *row_ptr, const int32_t *col, const int32
     (void)nn;
 }
 
-// node -> elements (ascending) and the E_l offsets of a system, once
+// node -> elements (ascending) and the E_l offsets of a system, once; built in
+// local buffers and kept only when all of them exist (an allocation failure
+// leaves the system without them, to be built on the next call)
 void det_tables(System &s, hipStream_t st)
 {
-    if (s.n2e_off.bytes() > 0) return;
+    if (!s.eoff.empty()) return;
     const Mesh &M = *s.mesh;
     const int nv = M.dim + 1;
     const int64_t ne = M.n_elems, nn = M.n_nodes, nc = ne * nv;
     DevBuf cnt(s.ctx, sizeof(int64_t) * (nn + 1), st), cur(s.ctx, sizeof(int64_t) * (nn + 1), st);
     NLQ_HIP(hipMemsetAsync(cnt.as<void>(), 0, sizeof(int64_t) * (nn + 1), st));
     NLQ_HIP(hipMemsetAsync(cur.as<void>(), 0, sizeof(int64_t) * (nn + 1), st));
-    s.n2e_off.alloc(s.ctx, sizeof(int64_t) * (nn + 1));
-    s.n2e.alloc(s.ctx, sizeof(int32_t) * std::max<int64_t>(nc, 1));
+    DevBuf n2e_off(s.ctx, sizeof(int64_t) * (nn + 1)), n2e(s.ctx, sizeof(int32_t) * std::max<int64_t>(nc, 1));
     const dim3 b(256);
     if (nc > 0) {
         hipLaunchKernelGGL(k_n2e_count, dim3((nc + 255) / 256), b, 0, st, nc, M.conn.as<int32_t>(), cnt.as<int64_t>());
         NLQ_CHECK_LAUNCH();
     }
-    exclusive_scan_i64(s.ctx, cnt.as<int64_t>(), s.n2e_off.as<int64_t>(), nn + 1, st);
+    exclusive_scan_i64(s.ctx, cnt.as<int64_t>(), n2e_off.as<int64_t>(), nn + 1, st);
     if (nc > 0) {
         hipLaunchKernelGGL(k_n2e_fill, dim3((nc + 255) / 256), b, 0, st, nc, nv, M.conn.as<int32_t>(),
-                           s.n2e_off.as<int64_t>(), cur.as<int64_t>(), s.n2e.as<int32_t>());
+                           n2e_off.as<int64_t>(), cur.as<int64_t>(), n2e.as<int32_t>());
         NLQ_CHECK_LAUNCH();
     }
     if (nn > 0) {
-        hipLaunchKernelGGL(k_n2e_sort, dim3((nn + 255) / 256), b, 0, st, nn, s.n2e_off.as<int64_t>(),
-                           s.n2e.as<int32_t>());
+        hipLaunchKernelGGL(k_n2e_sort, dim3((nn + 255) / 256), b, 0, st, nn, n2e_off.as<int64_t>(),
+                           n2e.as<int32_t>());
         NLQ_CHECK_LAUNCH();
     }
     DevBuf len(s.ctx, sizeof(int64_t) * (ne + 1), st);
@@ -311,9 +312,12 @@ void det_tables(System &s, hipStream_t st)
                                s.row_ptr.as<int64_t>(), len.as<int64_t>());
         NLQ_CHECK_LAUNCH();
     }
-    s.eoff.alloc(s.ctx, sizeof(int64_t) * (ne + 1));
-    exclusive_scan_i64(s.ctx, len.as<int64_t>(), s.eoff.as<int64_t>(), ne + 1, st);
+    DevBuf eoff(s.ctx, sizeof(int64_t) * (ne + 1));
+    exclusive_scan_i64(s.ctx, len.as<int64_t>(), eoff.as<int64_t>(), ne + 1, st);
     NLQ_HIP(hipStreamSynchronize(st));
+    s.n2e_off = std::move(n2e_off);
+    s.n2e = std::move(n2e);
+    s.eoff = std::move(eoff);
 }
 
 template <int DIM>

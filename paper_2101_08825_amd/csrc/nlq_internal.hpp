@@ -117,6 +117,10 @@ struct Ctx {
     hipStream_t stream = nullptr;
     uint64_t budget = 0;
     std::atomic<uint64_t> used{0};
+    // failure injection for tests: the device allocation with this ordinal
+    // (counted per context from 0) fails with NLQ_ENOMEM; -1: none
+    std::atomic<int64_t> allocs{0};
+    int64_t alloc_fail_at = -1;
     std::mutex tables_mu;
     std::map<std::pair<int, int>, std::unique_ptr<Tables>> tables;
     std::unique_ptr<Server> server;
