@@ -204,6 +204,16 @@ typedef struct {
     double best_ms, default_ms;     /* sample launch time: chosen and default configuration */
 } nlq_tune_info;
 nlq_status nlq_autotune(nlq_system *sys, double budget_s, nlq_tune_info *info);
+/* The context's tuned configurations as a text file, so that a later process
+ * can start tuned: a comment line, then one line per class key
+ * "arch dim precision kernel lmax size_class occ wg_per_cu pairs_per_item"
+ * (arch of the device, e.g. gfx950).  nlq_tune_save writes (overwrites) path;
+ * nlq_tune_load reads such a file and keeps the lines of this context's
+ * architecture (others are skipped), setting *n_loaded (may be NULL) to their
+ * number.  A file that cannot be opened, or a line that does not parse, gives
+ * NLQ_EINVAL and loads nothing. */
+nlq_status nlq_tune_save(const nlq_ctx *ctx, const char *path);
+nlq_status nlq_tune_load(nlq_ctx *ctx, const char *path, int32_t *n_loaded);
 /* Re-run only the integration step (pair list and pattern kept) -- the hot loop;
  * values are recomputed from zero. */
 nlq_status nlq_reassemble(nlq_system *sys);

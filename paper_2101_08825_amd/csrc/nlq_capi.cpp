@@ -327,6 +327,8 @@ nlq_status nlq_ctx_create(int32_t device, uint64_t hbm_budget_bytes, nlq_ctx **o
         hipDeviceProp_t prop;
         NLQ_HIP(hipGetDeviceProperties(&prop, device));
         c->impl.n_cu = prop.multiProcessorCount;
+        c->impl.arch = prop.gcnArchName;
+        c->impl.arch = c->impl.arch.substr(0, c->impl.arch.find(':'));
         size_t fr = 0, tot = 0;
         NLQ_HIP(hipMemGetInfo(&fr, &tot));
         c->impl.budget = hbm_budget_bytes ? hbm_budget_bytes : static_cast<uint64_t>(0.9 * fr);
@@ -573,6 +575,68 @@ nlq_status nlq_autotune(nlq_system *sys, double budget_s, nlq_tune_info *info)
             info->best_ms = best;
             info->default_ms = def;
         }
+    });
+}
+
+nlq_status nlq_tune_save(const nlq_ctx *ctx, const char *path)
+{
+    return guard([&] {
+        if (!ctx || !path) fail(NLQ_EINVAL, "NULL argument");
+        const Ctx &c = ctx->impl;
+        std::string text = "# nlq tuning cache v1: arch dim precision kernel lmax size_class occ wg_per_cu pairs_per_item\n";
+        {
+            std::lock_guard<std::mutex> g(const_cast<Ctx &>(c).tune_mu);
+            for (const auto &kv : c.tuned) {
+                const TuneKey &k = kv.first;
+                const TuneConfig &t = kv.second;
+                text += c.arch + " " + std::to_string(std::get<0>(k)) + " " + std::to_string(std::get<1>(k)) + " " +
+                        std::to_string(std::get<2>(k)) + " " + std::to_string(std::get<3>(k)) + " " +
+                        std::to_string(std::get<4>(k)) + " " + std::to_string(t.occ) + " " +
+                        std::to_string(t.wg_per_cu) + " " + std::to_string(t.pairs_per_item) + "\n";
+            }
+        }
+        FILE *f = std::fopen(path, "w");
+        if (!f) fail(NLQ_EINVAL, std::string("cannot open ") + path);
+        const bool ok = std::fwrite(text.data(), 1, text.size(), f) == text.size();
+        if (std::fclose(f) != 0 || !ok) fail(NLQ_EINVAL, std::string("cannot write ") + path);
+    });
+}
+
+nlq_status nlq_tune_load(nlq_ctx *ctx, const char *path, int32_t *n_loaded)
+{
+    return guard([&] {
+        if (!ctx || !path) fail(NLQ_EINVAL, "NULL argument");
+        FILE *f = std::fopen(path, "r");
+        if (!f) fail(NLQ_EINVAL, std::string("cannot open ") + path);
+        std::vector<std::pair<TuneKey, TuneConfig>> got;
+        char line[512];
+        int lineno = 0;
+        bool bad = false;
+        while (std::fgets(line, sizeof line, f)) {
+            ++lineno;
+            if (line[0] == '#' || line[0] == '\n' || line[0] == '\0') continue;
+            char arch[64];
+            int dim, prec, kernel, lmax, lg, occ, wg, ppi;
+            if (std::sscanf(line, "%63s %d %d %d %d %d %d %d %d", arch, &dim, &prec, &kernel, &lmax, &lg, &occ, &wg,
+                            &ppi) != 9 || (dim != 2 && dim != 3) || (prec != 0 && prec != 1) || (occ != 0 && occ != 1) ||
+                wg < 0 || ppi < 1 || lmax < 1 || lg < 0) {
+                bad = true;
+                break;
+            }
+            if (ctx->impl.arch != arch) continue;
+            TuneConfig t;
+            t.occ = occ;
+            t.wg_per_cu = wg;
+            t.pairs_per_item = ppi;
+            got.emplace_back(TuneKey(dim, prec, kernel, lmax, lg), t);
+        }
+        std::fclose(f);
+        if (bad) fail(NLQ_EINVAL, std::string(path) + ": line " + std::to_string(lineno) + " does not parse");
+        {
+            std::lock_guard<std::mutex> g(ctx->impl.tune_mu);
+            for (const auto &kv : got) ctx->impl.tuned[kv.first] = kv.second;
+        }
+        if (n_loaded) *n_loaded = static_cast<int32_t>(got.size());
     });
 }
 

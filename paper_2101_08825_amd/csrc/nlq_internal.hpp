@@ -113,6 +113,7 @@ using TuneKey = std::tuple<int, int, int, int, int>;
 struct Ctx {
     int device = 0;
     int n_cu = 0;
+    std::string arch;                  // e.g. gfx950 (keys the saved tuning cache)
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
     uint64_t budget = 0;

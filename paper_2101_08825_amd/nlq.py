@@ -29,7 +29,7 @@ EXPORTS = [
     "nlq_ctx_create", "nlq_ctx_set_stream", "nlq_ctx_memory", "nlq_ctx_destroy",
     "nlq_mesh_create", "nlq_mesh_box", "nlq_mesh_info", "nlq_mesh_copy", "nlq_mesh_destroy",
     "nlq_assemble", "nlq_prepare", "nlq_integrate_range", "nlq_assemble_batch", "nlq_assemble_info_get",
-    "nlq_autotune", "nlq_reassemble", "nlq_set_data",
+    "nlq_autotune", "nlq_tune_save", "nlq_tune_load", "nlq_reassemble", "nlq_set_data",
     "nlq_set_data_device", "nlq_solve", "nlq_solution_device",
     "nlq_info", "nlq_csr_copy", "nlq_csr_device", "nlq_pairs_copy", "nlq_rhs_copy",
     "nlq_pair_blocks", "nlq_system_destroy", "nlq_serve_start", "nlq_submit", "nlq_wait",
@@ -121,6 +121,8 @@ def lib():
             "nlq_prepare": [vp, vp, P(nlq_params), P(vp)],
             "nlq_integrate_range": [vp, i64, i64, P(d), vp],
             "nlq_autotune": [vp, d, P(nlq_tune_info)],
+            "nlq_tune_save": [vp, C.c_char_p],
+            "nlq_tune_load": [vp, C.c_char_p, P(i32)],
             "nlq_assemble_info_get": [vp, P(nlq_assemble_info)],
             "nlq_reassemble": [vp],
             "nlq_set_data": [vp, vp, vp],
@@ -181,6 +183,16 @@ class Context:
         u, b = C.c_uint64(), C.c_uint64()
         _check(lib().nlq_ctx_memory(self.h, C.byref(u), C.byref(b)))
         return u.value, b.value
+
+    def tune_save(self, path):
+        """nlq_tune_save: write the context's tuned launch configurations."""
+        _check(lib().nlq_tune_save(self.h, os.fsencode(path)))
+
+    def tune_load(self, path):
+        """nlq_tune_load: read tuned configurations of this device's architecture; returns their number."""
+        n = C.c_int32()
+        _check(lib().nlq_tune_load(self.h, os.fsencode(path), C.byref(n)))
+        return n.value
 
     def close(self):
         """Destroy the context after every mesh (and system) made from it."""

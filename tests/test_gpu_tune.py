@@ -55,3 +55,43 @@ def test_autotune_keeps_values(dim, n, kd, ed, lmax, precision):
     ref.close()
     ref_m.close()
     ref_ctx.close()
+
+
+def test_tuning_cache_file(tmp_path):
+    """nlq_tune_save / nlq_tune_load: a new context loads what an earlier one
+    tuned (lines of another architecture are skipped, a malformed line is an
+    error), and saving it again writes the same file."""
+    import torch
+    from paper_2101_08825_amd import nlq
+    assert torch.cuda.is_available()
+    print("[case] tuning cache file", flush=True)
+    wl = W.Workload("tune", 2, 48, 4, 32, 4, 0, W._ux1sq(2))
+    mesh = wl.mesh()
+    ctx = nlq.Context(0)
+    m = nlq.Mesh.create(ctx, mesh.coords, mesh.conn, mesh.constrained)
+    s = nlq.System(ctx, m, nlq.params(2, wl.delta, wl.eps, 4, precision=1))
+    s.autotune(budget_s=1.0)
+    s.close()
+    m.close()
+    a = tmp_path / "a.txt"
+    ctx.tune_save(a)
+    ctx.close()
+    lines = a.read_text().splitlines()
+    assert lines[0].startswith("#") and len(lines) == 2
+    arch = lines[1].split()[0]
+    assert arch.startswith("gfx")
+    other = tmp_path / "other.txt"
+    other.write_text(a.read_text() + "gfx000 2 1 0 4 9 1 3 256\n")
+    ctx2 = nlq.Context(0)
+    assert ctx2.tune_load(other) == 1
+    b = tmp_path / "b.txt"
+    ctx2.tune_save(b)
+    assert b.read_text() == a.read_text()
+    bad = tmp_path / "bad.txt"
+    bad.write_text(a.read_text() + f"{arch} 2 1 0\n")
+    with pytest.raises(nlq.NlqError) as e:
+        ctx2.tune_load(bad)
+    assert e.value.status == nlq.NLQ_EINVAL
+    with pytest.raises(nlq.NlqError):
+        ctx2.tune_load(tmp_path / "missing.txt")
+    ctx2.close()
