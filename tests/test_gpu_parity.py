@@ -90,6 +90,31 @@ def test_c1_full_parity(nlq_ctx, oracle_lib, precision, form):
     m.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("kernel,lmin", [(0, 2), (1, 1), (1, 3)])
+def test_2d_lmin_and_gauss_parity(nlq_ctx, oracle_lib, precision, kernel, lmin):
+    """2D 12^2, delta = 3h, eps = delta/8, L_max = 4: Algorithm 1 with L_min > 1
+    (every sub-element above L_min refined whatever its distance) and the
+    truncated Gaussian kernel, whole matrix and leaf counts against the oracle."""
+    from paper_2101_08825_amd import nlq
+    O = oracle_lib
+    _print_case("2d12", precision=precision, kernel=kernel, lmin=lmin)
+    mesh = W.kuhn_mesh(2, 12, 3)
+    h = 1.0 / 12
+    delta, eps, lmax = 3 * h, 3 * h / 8, 4
+    ref, _, _ = _oracle_full(O, mesh, O.params(delta, eps, lmax, lmin=lmin, kernel=kernel))
+    m = nlq.Mesh.create(nlq_ctx, mesh.coords, mesh.conn, mesh.constrained)
+    s = nlq.System(nlq_ctx, m, nlq.params(2, delta, eps, lmax, lmin=lmin, kernel=kernel, precision=precision))
+    rp, col, val = s.csr()
+    assert np.array_equal(rp, ref.row_ptr) and np.array_equal(col, ref.col)
+    assert list(s.info().n_leaf)[1:lmax + 1] == list(ref.leaves[1:lmax + 1])
+    err = _rel(val, ref.val)
+    print(f"  |A-A_or|_F/|A_or|_F = {err:.3e}  leaves {list(ref.leaves[1:lmax + 1])}", flush=True)
+    assert err <= (TOL64 if precision == 0 else TOL32)
+    s.close()
+    m.close()
+
+
 _ORACLE_3D = {}
 
 
