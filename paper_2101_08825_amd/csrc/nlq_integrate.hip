@@ -240,6 +240,19 @@ __device__ __forceinline__ Simplex<DIM> child_of(const Simplex<DIM> &S, int c)
                 M[i][j][k] = (i == j) ? S.v[i][k]
                                       : (i < j ? __dmul_rn(__dadd_rn(S.v[i][k], S.v[j][k]), 0.5) : 0.0);
     Simplex<DIM> out;
+    if constexpr (DIM == 2) {
+        // the triangle table (corner children, then the middle one) as two-bit
+        // select trees with its repeated entries merged: 7 selects per
+        // coordinate instead of 9
+        const bool b0 = (c & 1) != 0, b1 = (c & 2) != 0;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            out.v[0][k] = b0 ? M[0][1][k] : (b1 ? M[0][2][k] : M[0][0][k]);
+            out.v[1][k] = b1 ? (b0 ? M[0][2][k] : M[1][2][k]) : (b0 ? M[1][1][k] : M[0][1][k]);
+            out.v[2][k] = b0 ? M[1][2][k] : (b1 ? M[2][2][k] : M[0][2][k]);
+        }
+        return out;
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -409,6 +422,11 @@ template <int DIM, int ETA> struct PlainAcc {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// The FP32 matrix-core sums of a pair are added to its FP64 totals every this
+// many batches of 64 outer points (and at the pair's end): each FP32 sum holds
+// at most 64 (2D) or 128 (3D) positive products per entry.
+constexpr int kFlushBatches = 2;
+
 // FP32 mixed path with distances on the vector ALU (2D, where it is faster
 // than the variant below): v_mfma_f32_16x16x4f32, A = P (rows x 4 points),
 // B = G (4 points x 16 inner points).  Operand layout: A[i][k] and B[k][j] live
@@ -432,6 +450,8 @@ template <int DIM, int ETA> struct MixedAccDirect {
         floatx4 r0, r1;
     };
     double dacc[4];
+    floatx4 facc;   // FP32 sums of the batches since the last flush
+    int nb;         // batches since the last flush (wave-uniform)
     float yh[2];
     float doe;   // delta / eps (vector register)
     int sub;     // inner point (and P row) handled by this lane
@@ -444,6 +464,8 @@ template <int DIM, int ETA> struct MixedAccDirect {
         poff = 4 * (n >> 3) + k;
 #pragma unroll
         for (int r = 0; r < 4; ++r) dacc[r] = 0.0;
+        facc = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        nb = 0;
         const bool colv = sub < S::NQ;
         yh[0] = colv ? static_cast<float>(y[0]) : 1.0e18f;
         yh[1] = colv ? static_cast<float>(y[1]) : 1.0e18f;
@@ -473,7 +495,7 @@ template <int DIM, int ETA> struct MixedAccDirect {
     {
         const float *sx = reinterpret_cast<const float *>(work) + poff * XS;
         const float *sp = reinterpret_cast<const float *>(work) + kBatch * XS + poff * PS + sub;
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        floatx4 acc = facc;
         const int steps = (npts + PPS - 1) / PPS;
 #pragma unroll
         for (int t = 0; t < STEPS; ++t) {
@@ -485,13 +507,23 @@ template <int DIM, int ETA> struct MixedAccDirect {
             const float g = kernel32<ETA>(A, d2, doe);
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, g, acc, 0, 0, 0);
         }
+        facc = acc;
+        if (++nb == kFlushBatches) flush();
+    }
+    // FP32 partial sums into the FP64 totals (every kFlushBatches batches and
+    // at the end of the pair)
+    __device__ void flush()
+    {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) dacc[r] += static_cast<double>(acc[r]);
+        for (int r = 0; r < 4; ++r) dacc[r] += static_cast<double>(facc[r]);
+        facc = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        nb = 0;
     }
     // D[i][j] (FP64) -> H/Q totals out[r*16 + b]; out may be the tile itself: each
     // lane reads its own slot and a slot of rows 8..15, which nobody writes
     __device__ void finish(double *out, double *tile)
     {
+        flush();
         const int l = lane_id();
         const int j = l & 15, ib = 4 * (l >> 4);
 #pragma unroll
@@ -529,6 +561,8 @@ template <int DIM, int ETA> struct MixedAccMfma {
         floatx4 r0, r1, r2, r3;
     };
     double dacc[4];
+    floatx4 facc;    // FP32 sums of the batches since the last flush
+    int nb;          // batches since the last flush (wave-uniform)
     float bop;       // B operand of the distance MFMA
     float yb2;       // |y_j|^2 of this lane's column (huge for a padding column: gamma 0)
     float doe;       // delta / eps (vector register)
@@ -541,6 +575,8 @@ template <int DIM, int ETA> struct MixedAccMfma {
         col = lane & 15;
 #pragma unroll
         for (int r = 0; r < 4; ++r) dacc[r] = 0.0;
+        facc = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        nb = 0;
         (void)y;
     }
     // inner point of this lane's column (anchor-relative, FP64), set once per pair
@@ -593,7 +629,7 @@ template <int DIM, int ETA> struct MixedAccMfma {
     {
         const float *sx = reinterpret_cast<const float *>(work);
         const float *sp = reinterpret_cast<const float *>(work + kXBytes);
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        floatx4 acc = facc;
         const int tiles = (npts + 15) / 16;
 #pragma unroll
         for (int ss = 0; ss < kBatch / 16; ++ss) {
@@ -611,13 +647,21 @@ template <int DIM, int ETA> struct MixedAccMfma {
                 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, g[r], acc, 0, 0, 0);
             }
         }
+        facc = acc;
+        if (++nb == kFlushBatches) flush();
+    }
+    __device__ void flush()
+    {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) dacc[r] += static_cast<double>(acc[r]);
+        for (int r = 0; r < 4; ++r) dacc[r] += static_cast<double>(facc[r]);
+        facc = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        nb = 0;
     }
     // D[i][j] (FP64) -> H/Q totals out[r*16 + b]; out may be the tile itself
     // (each lane reads back its own slots)
     __device__ void finish(double *out, double *tile)
     {
+        flush();
         const int l = lane_id();
         const int j = l & 15, ib = 4 * (l >> 4);
 #pragma unroll
