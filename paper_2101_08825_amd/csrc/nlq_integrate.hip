@@ -86,7 +86,6 @@ struct AsmArgs {
     const int32_t *elpos;
     double *val;
     const double *lam64;  // [sub][nq][nv]
-    const float *lam32;
     const float *pt32;    // rows of the FP32 contraction per point (see the tables)
     int pt32_zero;        // its zero row
     double *pb;           // deterministic mode: per-pair outputs [pair - pb_base][NV^2 + 2 NR], else null
@@ -95,7 +94,7 @@ struct AsmArgs {
     double delta, eps, dme, dpe, dme2, dpe2, C;
     double dme_sq;        // s* with (sqrt(s) < delta - eps) <=> (s < s*), s >= 0
     double *dmm;          // [ne][NR] upper-triangle diagonal-block sums per element
-    float f_delta, f_inv_eps, f_delta_over_eps, f_inv_delta2;
+    float f_inv_eps, f_delta_over_eps, f_inv_delta2;
     int lmin, lmax, form;
     int split;            // work items per outer element (pair list cut in equal parts)
     int capl;             // traversal stack entries of this system (see make_args)
@@ -1116,12 +1115,6 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
 
 // -------------------------------------------------------------- kernels
 
-template <int DIM, int PREC>
-__device__ void wave_setup(char *)
-{
-    wave_sync();
-}
-
 // Occupancy hint: more waves per SIMD cover LDS and table latency at the cost of
 // registers (5 waves in 2D, 3 in 3D were fastest on the 2D 128^2 and 3D 8^3 cases).
 template <int DIM, int PREC, int ETA, int OCC>
@@ -1153,7 +1146,6 @@ k_integrate(LaunchArgs L)
     for (int t = threadIdx.x; t <= L.nseg; t += kThreads) s_seg[t] = L.seg_start[t];
     __syncthreads();
     epilogue_tables<DIM>(s_rule, s_T, s_desc);
-    wave_setup<DIM, PREC>(wmem);
     const int64_t total = s_seg[L.nseg];
     for (;;) {
         if (threadIdx.x == 0) {
@@ -1250,7 +1242,6 @@ k_pair_blocks(LaunchArgs L)
     if (threadIdx.x < NQ) s_w32[threadIdx.x] = static_cast<float>(A.rule[NQ * NV + threadIdx.x]);
     __syncthreads();
     epilogue_tables<DIM>(s_rule, s_T, s_desc);
-    wave_setup<DIM, PREC>(wmem);
     __syncthreads();
     for (;;) {
         unsigned int it = 0;
@@ -1413,7 +1404,6 @@ AsmArgs make_args(const System &s, const Tables &T)
     A.elpos = s.elpos.as<int32_t>();
     A.val = s.val.as<double>();
     A.lam64 = T.lam64.as<double>();
-    A.lam32 = T.lam32.as<float>();
     A.pt32 = T.pt32.as<float>();
     A.pt32_zero = static_cast<int>(T.n_sub * T.nq);
     A.rule = T.rule.as<double>();
@@ -1433,7 +1423,6 @@ AsmArgs make_args(const System &s, const Tables &T)
     A.dme2 = A.dme * A.dme * (1.0 - 1e-12);
     A.dpe2 = A.dpe * A.dpe * (1.0 + 1e-12);
     A.C = s.C;
-    A.f_delta = static_cast<float>(s.p.delta);
     A.f_inv_eps = static_cast<float>(1.0 / s.p.eps);
     A.f_delta_over_eps = static_cast<float>(s.p.delta / s.p.eps);
     A.f_inv_delta2 = static_cast<float>(1.0 / (s.p.delta * s.p.delta));

@@ -91,7 +91,6 @@ struct Tables {
     int64_t n_sub = 0;
     DevBuf rule;                // [nq][nv] points, then [nq] weights (double)
     DevBuf lam64;               // [n_sub][nq][nv] double
-    DevBuf lam32;               // [n_sub][nq][nv] float
     // per quadrature point of every sub-element, the FP32 rows of the
     // contraction (w lambda_i, then w lambda_i lambda_j, i < j; w the rule weight
     // scaled by the level's volume ratio) and lambda_1..lambda_dim:

@@ -198,10 +198,7 @@ std::unique_ptr<Tables> make_tables(Ctx *ctx, int dim, int lmax)
     NLQ_HIP(hipMemcpy(t->rule.as<void>(), rule.data(), rule.size() * sizeof(double),
                       hipMemcpyHostToDevice));
     t->lam64.alloc(ctx, lam.size() * sizeof(double));
-    t->lam32.alloc(ctx, lam32.size() * sizeof(float));
     NLQ_HIP(hipMemcpy(t->lam64.as<void>(), lam.data(), lam.size() * sizeof(double),
-                      hipMemcpyHostToDevice));
-    NLQ_HIP(hipMemcpy(t->lam32.as<void>(), lam32.data(), lam32.size() * sizeof(float),
                       hipMemcpyHostToDevice));
     return t;
 }
