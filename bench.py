@@ -75,7 +75,7 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if xs else float("nan")
 
 
-def run_steps(nlq, ctx, setups, precision, steps, warmup, torch):
+def run_steps(nlq, ctx, setups, precision, steps, warmup, torch, min_l2=False):
     lat = []
     step_times = []
     kernel = []
@@ -88,7 +88,8 @@ def run_steps(nlq, ctx, setups, precision, steps, warmup, torch):
         kt = []
         for (mesh, wl, f_t, g_t) in setups:
             r0 = time.perf_counter()
-            s = nlq.System(ctx, mesh, nlq.params(2, wl.delta, wl.eps, wl.lmax, precision=precision))
+            s = nlq.System(ctx, mesh, nlq.params(2, wl.delta, wl.eps, wl.lmax, precision=precision,
+                                                 min_dist_l2=min_l2))
             s.set_data_device(f_t.data_ptr(), g_t.data_ptr())
             _, inf = s.solve(rtol=1e-10, copy=False)
             info = s.info()
@@ -105,7 +106,8 @@ def run_steps(nlq, ctx, setups, precision, steps, warmup, torch):
         else:
             lat.clear()
         pairs_per_step, evals_per_step = pairs, evals
-        progress(f"precision {precision} step {it + 1}/{warmup + steps} {1e3 * dt:.1f} ms")
+        progress(f"precision {precision}{' (L2 box gap)' if min_l2 else ''} step {it + 1}/{warmup + steps} "
+                 f"{1e3 * dt:.1f} ms")
     return dict(step_times=step_times, lat=lat, kernel=kernel, pairs=pairs_per_step,
                 evals=evals_per_step)
 
@@ -204,6 +206,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-cache", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this build runs on one GPU only: the path has no cross-GPU sharding "
@@ -243,6 +246,29 @@ def main():
     plain = None
     if not args.skip_fp64:
         plain = run_steps(nlq, ctx, setups, nlq.NLQ_FP64_PLAIN, args.steps, args.warmup, torch)
+
+    # ablation: Algorithm 1's refine test with the Euclidean box gap (drops only
+    # zero contributions: the same matrices to round-off, fewer leaves)
+    ablation = None
+    if not args.no_ablation:
+        l2 = run_steps(nlq, ctx, setups, nlq.NLQ_FP32_MIXED, args.steps, args.warmup, torch, min_l2=True)
+        mesh, wl, _, _ = setups[-1]
+        vals = []
+        for flag in (False, True):
+            s = nlq.System(ctx, mesh, nlq.params(2, wl.delta, wl.eps, wl.lmax, precision=nlq.NLQ_FP32_MIXED,
+                                                 min_dist_l2=flag))
+            vals.append(s.csr()[2])
+            s.close()
+        ms_l2 = 1e3 * float(np.mean(l2["step_times"]))
+        ablation = {
+            "value": l2["pairs"] / (ms_l2 * 1e-3), "unit": "pairs/s", "ms_per_step": ms_l2,
+            "kernel_ms_per_step": 1e3 * sum(t for t, _ in l2["kernel"]) / args.steps,
+            "kernel_evals_per_step": l2["evals"],
+            "rel_frobenius_vs_paper_test": float(np.linalg.norm(vals[1] - vals[0]) / np.linalg.norm(vals[0])),
+            "what": "FP32-mixed steps with Algorithm 1's refine test on the Euclidean box gap instead of "
+                    "the L_inf gap of Sec. 5.1 (same pair lists; drops sub-elements whose every point pair "
+                    "is beyond delta+eps); matrix difference measured on delta = 4h",
+        }
 
     serve = serve64 = None
     if args.serve_requests > 0:
@@ -302,6 +328,9 @@ def main():
         out["serving_fp64_plain"] = serve64
     if tuned:
         out["autotune"] = tuned
+    if ablation:
+        ablation["speedup_vs_paper_test"] = ablation["value"] / value
+        out["ablation_l2_box_gap"] = ablation
     out["c2_request_ms"] = {"p50": 1e3 * percentile(mixed["lat"], 50), "p99": 1e3 * percentile(mixed["lat"], 99)}
     if plain is not None:
         pms = 1e3 * float(np.mean(plain["step_times"]))

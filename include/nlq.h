@@ -87,6 +87,13 @@ typedef struct nlq_system nlq_system;
  *             node.  Such a system is integrated by itself: nlq_integrate_range
  *             rejects it, nlq_assemble_batch and the serving loop integrate it
  *             alone, nlq_autotune leaves it untuned.
+ *  min_dist_l2  0: Algorithm 1's refine test uses the L_inf box gap of Section
+ *             5.1, eq. (mindist) (the paper).  1: the Euclidean box gap
+ *             (an ablation): a sub-element whose box is at least delta + eps
+ *             from the inner element's box holds no point pair within the
+ *             kernel's support, so dropping it removes only zero contributions
+ *             -- the same matrix to round-off from fewer leaves.  The pair
+ *             list J_l keeps the paper's test either way.
  */
 typedef struct {
     int32_t dim;
@@ -97,6 +104,7 @@ typedef struct {
     int32_t form;
     int32_t precision;
     int32_t deterministic;
+    int32_t min_dist_l2;
 } nlq_params;
 
 /* Counts and stage timings of one assembly (seconds from HIP events). */

@@ -38,7 +38,7 @@ class _Mesh(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("delta", C.c_double), ("eps", C.c_double), ("scale", C.c_double),
                 ("kernel", C.c_int32), ("lmin", C.c_int32), ("lmax", C.c_int32),
-                ("form", C.c_int32)]
+                ("form", C.c_int32), ("min_l2", C.c_int32)]
 
 
 def lib():
@@ -111,9 +111,9 @@ class OracleMesh:
         return C.byref(self.s)
 
 
-def params(delta, eps, lmax, lmin=1, kernel=0, form=0, scale=0.0):
+def params(delta, eps, lmax, lmin=1, kernel=0, form=0, scale=0.0, min_l2=False):
     return _Params(float(delta), float(eps), float(scale), int(kernel), int(lmin),
-                   int(lmax), int(form))
+                   int(lmax), int(form), int(bool(min_l2)))
 
 
 # ------------------------------------------------------------------ scalars

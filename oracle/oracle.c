@@ -251,6 +251,27 @@ double or_aprxmin(int32_t dim, const double *lo1, const double *hi1,
     return r;
 }
 
+/* Euclidean distance of two boxes, sqrt(sum_k max(0, d1_k, d2_k)^2).  Not the
+ * paper's test (Section 5.1 uses the L_inf form above): an ablation of Algorithm
+ * 1's J^ref test.  Every point of a sub-element lies in its box and every inner
+ * point in the inner element's box, so when this distance is at least delta + eps
+ * every point pair is beyond the kernel's support and the sub-element would only
+ * contribute zeros: dropping it leaves the integrals unchanged, with fewer leaves. */
+double or_boxgap_l2(int32_t dim, const double *lo1, const double *hi1,
+                    const double *lo2, const double *hi2)
+{
+    double s = 0.0;
+    for (int k = 0; k < dim; ++k) {
+        double g = 0.0;
+        double d1 = lo1[k] - hi2[k];
+        double d2 = lo2[k] - hi1[k];
+        if (d1 > g) g = d1;
+        if (d2 > g) g = d2;
+        s = s + g * g;
+    }
+    return sqrt(s);
+}
+
 static void bbox_of(int dim, int nv, const double *v, double *lo, double *hi)
 {
     for (int k = 0; k < dim; ++k) {
@@ -635,7 +656,7 @@ static void adaptive(alg_ctx *c, int lcur, const double *V, const double *Lam, c
         const double *lo2 = c->jlo + Jpos[t] * dim, *hi2 = c->jhi + Jpos[t] * dim;
         if (or_aprxmax(dim, lo, hi, lo2, hi2) < c->dme)
             Jint[nint++] = Jpos[t];
-        else if (or_aprxmin(dim, lo, hi, lo2, hi2) < c->dpe)
+        else if ((c->p->min_l2 ? or_boxgap_l2(dim, lo, hi, lo2, hi2) : or_aprxmin(dim, lo, hi, lo2, hi2)) < c->dpe)
             Jref[nref++] = Jpos[t];
     }
     if (nint > 0) integration(c, lcur, V, Lam, Jint, nint);

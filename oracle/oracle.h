@@ -33,6 +33,8 @@ typedef struct {
     int32_t kernel;         /* 0: eta = 1; 1: eta = exp(-d^2/delta^2) */
     int32_t lmin, lmax;     /* Algorithm 1 levels, 1 <= lmin <= lmax */
     int32_t form;           /* 0: four-term integrand; 1: 2*(A21 + A22) */
+    int32_t min_l2;         /* 0: the J^ref test with the L_inf box gap of eq. (mindist);
+                               1: with the Euclidean box gap (ablation, see or_boxgap_l2) */
 } or_params;
 
 double or_xi(double r);
@@ -44,6 +46,8 @@ double or_aprxmax(int32_t dim, const double *lo1, const double *hi1,
                   const double *lo2, const double *hi2);
 double or_aprxmin(int32_t dim, const double *lo1, const double *hi1,
                   const double *lo2, const double *hi2);
+double or_boxgap_l2(int32_t dim, const double *lo1, const double *hi1,
+                    const double *lo2, const double *hi2);
 double or_elem_measure(const or_mesh *m, int64_t e);
 
 int64_t or_pairs(const or_mesh *m, double thr, int32_t nthreads,

@@ -79,6 +79,22 @@ __device__ __forceinline__ double aprx_max_sq(const double *lo1, const double *h
     return s;
 }
 
+// Squared Euclidean distance of two boxes, sum_k max(0, d1_k, d2_k)^2, rounded
+// as written (an ablation of the J^ref test; the paper's is aprx min below):
+// compared with s* = min{s : fl(sqrt(s)) >= delta + eps}.
+template <int DIM>
+__device__ __forceinline__ double box_gap_sq(const double *lo1, const double *hi1, const double *lo2,
+                                             const double *hi2)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        const double g = fmax(0.0, fmax(__dsub_rn(lo1[k], hi2[k]), __dsub_rn(lo2[k], hi1[k])));
+        s = __dadd_rn(s, __dmul_rn(g, g));
+    }
+    return s;
+}
+
 template <int DIM>
 __device__ __forceinline__ double aprx_min_dist(const double *lo1, const double *hi1,
                                                 const double *lo2, const double *hi2)

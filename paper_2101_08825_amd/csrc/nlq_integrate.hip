@@ -89,6 +89,8 @@ struct AsmArgs {
     const float *pt32;    // rows of the FP32 contraction per point (see the tables)
     int pt32_zero;        // its zero row
     double *pb;           // deterministic mode: per-pair outputs [pair - pb_base][NV^2 + 2 NR], else null
+    double dpe_sq;        // s* of delta + eps for the Euclidean box gap
+    int min_l2;           // J^ref test with the Euclidean box gap (ablation)
     int64_t pb_base;
     const double *rule;   // [nq][nv] barycentric points, then [nq] weights
     double delta, eps, dme, dpe, dme2, dpe2, C;
@@ -311,7 +313,8 @@ __device__ __forceinline__ int classify(CArgs &A, const Simplex<DIM> root, const
         shi[k] = b;
     }
     if (aprx_max_sq<DIM>(slo, shi, mlo, mhi) < A.dme_sq) return 1;
-    if (aprx_min_dist<DIM>(slo, shi, mlo, mhi) < A.dpe) return 2;
+    if (A.min_l2 ? box_gap_sq<DIM>(slo, shi, mlo, mhi) < A.dpe_sq : aprx_min_dist<DIM>(slo, shi, mlo, mhi) < A.dpe)
+        return 2;
     return 0;
 }
 
@@ -1419,6 +1422,8 @@ AsmArgs make_args(const System &s, const Tables &T)
     A.dme = s.p.delta - s.p.eps;
     A.dpe = s.p.delta + s.p.eps;
     A.dme_sq = sqrt_threshold(A.dme);
+    A.dpe_sq = sqrt_threshold(A.dpe);
+    A.min_l2 = s.p.min_dist_l2;
     A.dmm = s.dmm.as<double>();
     A.dme2 = A.dme * A.dme * (1.0 - 1e-12);
     A.dpe2 = A.dpe * A.dpe * (1.0 + 1e-12);

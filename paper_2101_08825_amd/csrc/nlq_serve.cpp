@@ -33,13 +33,13 @@ double serve_now()
 
 using MeshKey = std::tuple<int, int, int>;
 // mesh key + every parameter that changes the matrix
-using SysKey = std::tuple<int, int, int, int, double, double, double, int, int, int, int, int>;
+using SysKey = std::tuple<int, int, int, int, double, double, double, int, int, int, int, int, int>;
 
 SysKey sys_key(const nlq_request &r)
 {
     const nlq_params &p = r.params;
     return SysKey(r.dim, r.n, r.k_gamma, p.kernel, p.delta, p.eps, p.scale, p.lmin, p.lmax, p.form, p.precision,
-                  p.deterministic);
+                  p.deterministic, p.min_dist_l2);
 }
 
 // Integration group: one launch takes systems of one (dim, precision, kernel);

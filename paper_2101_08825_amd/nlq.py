@@ -47,7 +47,7 @@ class nlq_params(C.Structure):
     _fields_ = [("dim", C.c_int32), ("kernel", C.c_int32), ("delta", C.c_double),
                 ("eps", C.c_double), ("scale", C.c_double), ("lmin", C.c_int32),
                 ("lmax", C.c_int32), ("form", C.c_int32), ("precision", C.c_int32),
-                ("deterministic", C.c_int32)]
+                ("deterministic", C.c_int32), ("min_dist_l2", C.c_int32)]
 
 
 class nlq_assemble_info(C.Structure):
@@ -164,9 +164,10 @@ def _ptr(a):
 
 
 def params(dim, delta, eps, lmax, lmin=1, kernel=NLQ_ETA_CONST, form=NLQ_FORM_SYM4,
-           precision=NLQ_FP64_PLAIN, scale=0.0, deterministic=False):
+           precision=NLQ_FP64_PLAIN, scale=0.0, deterministic=False, min_dist_l2=False):
     return nlq_params(int(dim), int(kernel), float(delta), float(eps), float(scale), int(lmin),
-                      int(lmax), int(form), int(precision), int(bool(deterministic)))
+                      int(lmax), int(form), int(precision), int(bool(deterministic)),
+                      int(bool(min_dist_l2)))
 
 
 class Context:

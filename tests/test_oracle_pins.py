@@ -573,3 +573,25 @@ def test_h_convergence_rate(oracle_lib):
     rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert min(gold["rates_cubic"]) > 1.9
     assert all(abs(r - 2.0) < 0.3 for r in rates), rates
+
+
+@pytest.mark.parametrize("dim,n,kd,ed,lmax,kernel", [(2, 12, 3, 8, 4, 0), (2, 10, 4, 32, 4, 1), (3, 4, 2, 8, 3, 0)])
+def test_l2_box_gap_drops_only_zeros(oracle_lib, dim, n, kd, ed, lmax, kernel):
+    """The Euclidean box gap in Algorithm 1's J^ref test (an ablation; the paper
+    uses the L_inf gap of Sec. 5.1 eq. mindist) drops only sub-elements whose
+    every point pair lies beyond delta + eps, where the kernel is zero: the
+    matrix equals the paper's to round-off, from fewer leaves."""
+    O = oracle_lib
+    mesh = W.kuhn_mesh(dim, n, kd)
+    h = 1.0 / n
+    delta, eps = kd * h, kd * h / ed
+    m = O.OracleMesh(mesh.coords, mesh.conn)
+    off, pm = O.pairs(m, delta + eps)
+    rp, col = O.pattern(m, off, pm)
+    a, la, _ = O.assemble(m, O.params(delta, eps, lmax, kernel=kernel), off, pm, rp, col)
+    b, lb, _ = O.assemble(m, O.params(delta, eps, lmax, kernel=kernel, min_l2=True), off, pm, rp, col)
+    rel = np.linalg.norm(b - a) / np.linalg.norm(a)
+    print(f"  leaves {int(la.sum())} -> {int(lb.sum())}, |A_l2 - A|/|A| = {rel:.2e}")
+    assert rel <= 1e-14
+    assert lb.sum() < la.sum()
+    assert np.all(lb[:lmax + 1] <= la[:lmax + 1])
