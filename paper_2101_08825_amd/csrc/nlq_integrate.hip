@@ -950,10 +950,12 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     // are integrated when the buffer fills and once at the end, so batches stay
     // full across levels.
     int nleaf = 0;
+    bool any_leaf = false;   // wave-uniform
     auto push_leaf = [&](bool take, uint32_t ent) {
         const unsigned long long mask = wave_ballot(take);
         const int c = __popcll(mask);
         if (c == 0) return;
+        any_leaf = true;
         if (nleaf + c > kLeafCap) {
             integrate(nleaf);
             nleaf = 0;
@@ -1056,6 +1058,9 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
         wave_sync();
     }
     if (nleaf > 0) integrate(nleaf);
+    // a pair without leaves (every sub-element dropped) has zero blocks: nothing to
+    // add (the explicit and deterministic outputs are still written)
+    if (!any_leaf && !ex_block && !A.pb) return;
 
     // ---- epilogue (FP64) ----------------------------------------------------
     wave_sync();
