@@ -280,9 +280,11 @@ nlq_status nlq_system_destroy(nlq_system *sys);
  *  - Integration: outer elements of all assembled-but-not-integrated requests of
  *    one (dim, precision, kernel) group share persistent launches (at most 32
  *    requests per launch, see nlq_assemble_batch); a launch is sized from the
- *    measured integration rate to about target_launch_ms, the budget split so
- *    that small requests finish in one launch and large ones share the rest.
- *    Requests that arrive while a launch runs join the next one.
+ *    measured integration rate to about target_launch_ms (raised until it
+ *    fills the grid) and filled in urgency order, each request taking all it
+ *    has left while the budget lasts: shortest remaining work first, so small
+ *    requests finish in one launch.  Requests that arrive while a launch runs
+ *    join the next one.
  *  - Residency: meshes stay on the device for the server's lifetime (keyed by
  *    dim, n, k_gamma); with cache_systems = 1 assembled matrices stay too and a
  *    request with the same mesh and parameters only reloads f, g and solves.
@@ -312,7 +314,7 @@ typedef struct {
 } nlq_result;
 
 typedef struct {
-    int32_t max_active;          /* admitted requests at once (<= 0: 64) */
+    int32_t max_active;          /* admitted requests at once (<= 0: 256) */
     double target_launch_ms;     /* duration aimed at per shared launch (<= 0: 25) */
     int32_t cache_systems;       /* 1: keep assembled matrices resident for reuse */
 } nlq_serve_config;

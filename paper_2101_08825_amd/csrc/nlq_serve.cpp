@@ -341,57 +341,36 @@ double urgency(const Server &S, const Request &r, double now)
     return left - 0.25 * (now - r.t_turn);
 }
 
-// Water-filling of a pair budget: every request of the group gets an equal
-// share, capped by what it has left; what the small ones leave goes to the
-// others.  Returns outer-element ranges (at least one element each).
-std::vector<Chunk> water_fill(const std::vector<ReqPtr> &rs, double budget)
+// Greedy filling of a pair budget, most urgent request first: each takes all it
+// has left while the budget lasts, so the smallest requests finish in this
+// launch and the rest of the budget goes to the next ones; requests the budget
+// does not reach are left out.  Returns outer-element ranges (at least one
+// element each).
+std::vector<Chunk> greedy_fill(const std::vector<ReqPtr> &rs, double budget)
 {
-    std::vector<int64_t> left(rs.size());
-    for (size_t i = 0; i < rs.size(); ++i)
-        left[i] = rs[i]->pair_off.back() - rs[i]->pair_off[rs[i]->cursor];
-    std::vector<double> share(rs.size(), 0.0);
-    std::vector<size_t> open(rs.size());
-    for (size_t i = 0; i < rs.size(); ++i) open[i] = i;
-    double rest = budget;
-    while (!open.empty() && rest > 0.5) {
-        const double each = rest / open.size();
-        std::vector<size_t> still;
-        double used = 0.0;
-        for (size_t i : open) {
-            const double need = left[i] - share[i];
-            if (need <= each) {
-                share[i] += need;
-                used += need;
-            } else {
-                share[i] += each;
-                used += each;
-                still.push_back(i);
-            }
-        }
-        rest -= used;
-        if (still.size() == open.size()) break;
-        open.swap(still);
-    }
     std::vector<Chunk> out;
-    for (size_t i = 0; i < rs.size(); ++i) {
-        Request &r = *rs[i];
+    double rest = budget;
+    for (const ReqPtr &rp : rs) {
+        if (rest < 0.5) break;
+        Request &r = *rp;
         const int64_t ne = static_cast<int64_t>(r.pair_off.size()) - 1;
         const int64_t base = r.pair_off[r.cursor];
-        const int64_t target = base + static_cast<int64_t>(std::ceil(share[i]));
+        const double share = std::min(static_cast<double>(r.pair_off.back() - base), rest);
+        rest -= share;
+        const int64_t target = base + static_cast<int64_t>(std::ceil(share));
         // first hi with pair_off[hi] >= target, at least cursor + 1
         int64_t hi = std::lower_bound(r.pair_off.begin() + r.cursor + 1, r.pair_off.end(), target) -
                      r.pair_off.begin();
         hi = std::min(std::max(hi, r.cursor + 1), ne);
-        out.push_back(Chunk{rs[i], r.cursor, hi, r.pair_off[hi] - base, (hi - r.cursor) * r.split});
+        out.push_back(Chunk{rp, r.cursor, hi, r.pair_off[hi] - base, (hi - r.cursor) * r.split});
     }
     return out;
 }
 
 // The launch of one group: a pair budget from the measured rate and the target
-// duration -- or, when finish_pairs > 0, only what lets a request with that many
-// pairs left finish under water-filling -- raised until the launch holds at least
-// two work items per resident workgroup (or everything that is left), so that
-// the persistent grid is busy.
+// duration -- or, when finish_pairs > 0, only the most urgent request's remaining
+// pairs -- raised until the launch holds at least two work items per resident
+// workgroup (or everything that is left), so that the persistent grid is busy.
 std::vector<Chunk> plan_launch(Server &S, const GroupKey &g, int64_t finish_pairs, double now)
 {
     // up to 32 requests of the group, most urgent first
@@ -411,11 +390,11 @@ std::vector<Chunk> plan_launch(Server &S, const GroupKey &g, int64_t finish_pair
         left_items += (static_cast<int64_t>(r->pair_off.size()) - 1 - r->cursor) * r->split;
     }
     if (finish_pairs > 0)
-        budget = std::min(budget, 1.02 * static_cast<double>(finish_pairs) * static_cast<double>(rs.size()) + 1.0);
+        budget = std::min(budget, static_cast<double>(finish_pairs) + 1.0);
     const int64_t want = std::min<int64_t>(2 * slots, left_items);
     std::vector<Chunk> plan;
     for (int round = 0; round < 40; ++round) {
-        plan = water_fill(rs, budget);
+        plan = greedy_fill(rs, budget);
         int64_t items = 0;
         for (auto &c : plan) items += c.items;
         if (items >= want) break;
@@ -620,7 +599,7 @@ nlq_status nlq_serve_start(nlq_ctx *ctx, const nlq_serve_config *cfg)
     S->ctx = &ctx->impl;
     nlq_serve_config c{};
     if (cfg) c = *cfg;
-    if (c.max_active <= 0) c.max_active = 64;
+    if (c.max_active <= 0) c.max_active = 256;
     if (!(c.target_launch_ms > 0.0)) c.target_launch_ms = 25.0;
     c.cache_systems = c.cache_systems ? 1 : 0;
     S->cfg = c;
