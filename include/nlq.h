@@ -92,8 +92,11 @@ typedef struct nlq_system nlq_system;
  *             (an ablation): a sub-element whose box is at least delta + eps
  *             from the inner element's box holds no point pair within the
  *             kernel's support, so dropping it removes only zero contributions
- *             -- the same matrix to round-off from fewer leaves.  The pair
- *             list J_l keeps the paper's test either way.
+ *             -- the same matrix to round-off from fewer leaves.  2: the
+ *             Euclidean gap to the box of the inner element's quadrature
+ *             points instead (a tighter test of our own, same argument: every
+ *             inner point lies in that box), fewer leaves still.  The J^int
+ *             test and the pair list J_l keep the paper's form either way.
  */
 typedef struct {
     int32_t dim;

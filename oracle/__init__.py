@@ -111,9 +111,9 @@ class OracleMesh:
         return C.byref(self.s)
 
 
-def params(delta, eps, lmax, lmin=1, kernel=0, form=0, scale=0.0, min_l2=False):
+def params(delta, eps, lmax, lmin=1, kernel=0, form=0, scale=0.0, min_l2=0):
     return _Params(float(delta), float(eps), float(scale), int(kernel), int(lmin),
-                   int(lmax), int(form), int(bool(min_l2)))
+                   int(lmax), int(form), int(min_l2))
 
 
 # ------------------------------------------------------------------ scalars

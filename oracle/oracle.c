@@ -551,6 +551,8 @@ typedef struct {
     const int32_t *J;    /* inner element ids, indexed by position */
     double *E;           /* per position: (2nv)^2 extended block */
     double *jlo, *jhi;   /* bounding boxes of the inner elements, by position */
+    double *qlo, *qhi;   /* boxes the J^ref test measures the gap to (min_l2 = 2:
+                            those of the inner quadrature points; else jlo, jhi) */
     int64_t *leaves;     /* per level */
     int64_t evals[2];    /* all kernel evaluations, evaluations inside the band */
 } alg_ctx;
@@ -654,9 +656,10 @@ static void adaptive(alg_ctx *c, int lcur, const double *V, const double *Lam, c
     int nint = 0, nref = 0;
     for (int t = 0; t < nJ; ++t) {
         const double *lo2 = c->jlo + Jpos[t] * dim, *hi2 = c->jhi + Jpos[t] * dim;
+        const double *glo = c->qlo + Jpos[t] * dim, *ghi = c->qhi + Jpos[t] * dim;
         if (or_aprxmax(dim, lo, hi, lo2, hi2) < c->dme)
             Jint[nint++] = Jpos[t];
-        else if ((c->p->min_l2 ? or_boxgap_l2(dim, lo, hi, lo2, hi2) : or_aprxmin(dim, lo, hi, lo2, hi2)) < c->dpe)
+        else if ((c->p->min_l2 ? or_boxgap_l2(dim, lo, hi, glo, ghi) : or_aprxmin(dim, lo, hi, lo2, hi2)) < c->dpe)
             Jref[nref++] = Jpos[t];
     }
     if (nint > 0) integration(c, lcur, V, Lam, Jint, nint);
@@ -702,6 +705,31 @@ static void run_outer(alg_ctx *c, int64_t l, const int32_t *J, int n, double *E)
         elem_vertices(c->mesh, J[t], V);
         bbox_of(dim, nv, V, c->jlo + t * dim, c->jhi + t * dim);
     }
+    c->qlo = c->jlo;
+    c->qhi = c->jhi;
+    if (c->p->min_l2 == 2) {
+        /* The box of the inner quadrature points y_b, formed exactly as
+         * integration() forms them: no outer point of a sub-element whose box is
+         * at least delta + eps from this box has a y_b within the kernel's
+         * support, so dropping it again removes only zero contributions (a
+         * tighter test than the inner element's own box, of our own) */
+        c->qlo = (double *)malloc(sizeof(double) * (size_t)(n + 1) * dim);
+        c->qhi = (double *)malloc(sizeof(double) * (size_t)(n + 1) * dim);
+        for (int t = 0; t < n; ++t) {
+            elem_vertices(c->mesh, J[t], V);
+            for (int k = 0; k < dim; ++k) {
+                double a = 0.0, b = 0.0;
+                for (int q = 0; q < c->nq; ++q) {
+                    double s = 0.0;
+                    for (int v = 0; v < nv; ++v) s += c->bary[q * nv + v] * V[v * dim + k];
+                    if (q == 0 || s < a) a = s;
+                    if (q == 0 || s > b) b = s;
+                }
+                c->qlo[t * dim + k] = a;
+                c->qhi[t * dim + k] = b;
+            }
+        }
+    }
     elem_vertices(c->mesh, l, V);
     for (int i = 0; i < nv; ++i)
         for (int j = 0; j < nv; ++j) Lam[i * nv + j] = (i == j) ? 1.0 : 0.0;
@@ -709,6 +737,10 @@ static void run_outer(alg_ctx *c, int64_t l, const int32_t *J, int n, double *E)
     for (int t = 0; t < n; ++t) Jpos[t] = t;
     adaptive(c, 1, V, Lam, Jpos, n);
     free(Jpos);
+    if (c->qlo != c->jlo) {
+        free(c->qlo);
+        free(c->qhi);
+    }
     free(c->jlo);
     free(c->jhi);
 }

@@ -34,7 +34,9 @@ typedef struct {
     int32_t lmin, lmax;     /* Algorithm 1 levels, 1 <= lmin <= lmax */
     int32_t form;           /* 0: four-term integrand; 1: 2*(A21 + A22) */
     int32_t min_l2;         /* 0: the J^ref test with the L_inf box gap of eq. (mindist);
-                               1: with the Euclidean box gap (ablation, see or_boxgap_l2) */
+                               1: with the Euclidean box gap (ablation, see or_boxgap_l2);
+                               2: the Euclidean gap to the box of the inner element's
+                                  quadrature points (ablation, see run_outer) */
 } or_params;
 
 double or_xi(double r);

@@ -91,7 +91,7 @@ void check_params(const Mesh &m, const nlq_params &p)
     if (p.precision != NLQ_FP64_PLAIN && p.precision != NLQ_FP32_MIXED)
         fail(NLQ_EINVAL, "unknown precision");
     if (p.deterministic != 0 && p.deterministic != 1) fail(NLQ_EINVAL, "deterministic must be 0 or 1");
-    if (p.min_dist_l2 != 0 && p.min_dist_l2 != 1) fail(NLQ_EINVAL, "min_dist_l2 must be 0 or 1");
+    if (p.min_dist_l2 < 0 || p.min_dist_l2 > 2) fail(NLQ_EINVAL, "min_dist_l2 must be 0, 1 or 2");
     if (p.scale < 0.0) fail(NLQ_EINVAL, "scale must be >= 0");
 }
 

@@ -78,6 +78,8 @@ struct AsmArgs {
     const double *vert;   // [nv*dim][ne]
     const double *lo;     // [dim][ne]
     const double *hi;
+    const double *dlo;    // [dim][ne] boxes the refine test measures the gap to:
+    const double *dhi;    // lo, hi, or the quadrature-point boxes (min_dist_l2 = 2)
     const double *meas;
     const int32_t *conn;
     const int64_t *row_ptr;
@@ -90,7 +92,8 @@ struct AsmArgs {
     int pt32_zero;        // its zero row
     double *pb;           // deterministic mode: per-pair outputs [pair - pb_base][NV^2 + 2 NR], else null
     double dpe_sq;        // s* of delta + eps for the Euclidean box gap
-    int min_l2;           // J^ref test with the Euclidean box gap (ablation)
+    int min_l2;           // J^ref test with the Euclidean box gap (ablation): 1 to the
+                          // inner element's box, 2 to its quadrature points' box
     int64_t pb_base;
     const double *rule;   // [nq][nv] barycentric points, then [nq] weights
     double delta, eps, dme, dpe, dme2, dpe2, C;
@@ -281,7 +284,8 @@ template <int DIM> __device__ __forceinline__ int level_offset(int lev)
 // memo holds (formed by the same recursion; memo_lev < 2: no memo).
 template <int DIM>
 __device__ __forceinline__ int classify(CArgs &A, const Simplex<DIM> root, const double *memo, int memo_lev,
-                                        int lev, uint32_t local, const double *mlo, const double *mhi)
+                                        int lev, uint32_t local, const double *mlo, const double *mhi,
+                                        const double *dlo, const double *dhi)
 {
     constexpr int NCH = 1 << DIM, NV = DIM + 1;
     Simplex<DIM> S = root;
@@ -313,7 +317,7 @@ __device__ __forceinline__ int classify(CArgs &A, const Simplex<DIM> root, const
         shi[k] = b;
     }
     if (aprx_max_sq<DIM>(slo, shi, mlo, mhi) < A.dme_sq) return 1;
-    if (A.min_l2 ? box_gap_sq<DIM>(slo, shi, mlo, mhi) < A.dpe_sq : aprx_min_dist<DIM>(slo, shi, mlo, mhi) < A.dpe)
+    if (A.min_l2 ? box_gap_sq<DIM>(slo, shi, dlo, dhi) < A.dpe_sq : aprx_min_dist<DIM>(slo, shi, mlo, mhi) < A.dpe)
         return 2;
     return 0;
 }
@@ -880,11 +884,15 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int k = 0; k < DIM; ++k) root.v[v][k] = cvert[(v * DIM + k) * ne + l];
-    double mlo[DIM], mhi[DIM];
+    const cdouble *cdlo = (const cdouble *)(A.dlo);
+    const cdouble *cdhi = (const cdouble *)(A.dhi);
+    double mlo[DIM], mhi[DIM], dlo[DIM], dhi[DIM];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
         mlo[k] = clo[k * ne + m];
         mhi[k] = chi[k * ne + m];
+        dlo[k] = cdlo[k * ne + m];
+        dhi[k] = cdhi[k * ne + m];
     }
     const double *bary = s_rule;
     const double *wq = s_rule + NQ * NV;
@@ -1021,7 +1029,7 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
         if (valid) {
             if (lev == lmax) cls = 1;                 // the root when L_max = 1
             else if (lev < lmin) cls = 2;
-            else cls = classify<DIM>(A, root, memo, memo_lev, lev, local, mlo, mhi);
+            else cls = classify<DIM>(A, root, memo, memo_lev, lev, local, mlo, mhi, dlo, dhi);
         }
         if (cls == 1 && s_leaf) atomicAdd(&s_leaf[lev], 1ull);
         push_leaf(cls == 1, cls == 1 ? leaf_entry(lev, level_offset<DIM>(lev) + static_cast<int>(local)) : 0u);
@@ -1404,6 +1412,8 @@ AsmArgs make_args(const System &s, const Tables &T)
     A.vert = s.vert.as<double>();
     A.lo = s.lo.as<double>();
     A.hi = s.hi.as<double>();
+    A.dlo = s.p.min_dist_l2 == 2 ? s.qlo.as<double>() : A.lo;
+    A.dhi = s.p.min_dist_l2 == 2 ? s.qhi.as<double>() : A.hi;
     A.meas = s.meas.as<double>();
     A.conn = m.conn.as<int32_t>();
     A.row_ptr = s.row_ptr.as<int64_t>();

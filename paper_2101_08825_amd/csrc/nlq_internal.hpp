@@ -176,6 +176,7 @@ struct System {
     // element tables
     DevBuf vert;                 // [nv*dim][ne] SoA double
     DevBuf lo, hi;               // [dim][ne]
+    DevBuf qlo, qhi;             // [dim][ne] box of the element's quadrature points (min_dist_l2 = 2)
     DevBuf meas;                 // [ne]
     // pair list
     DevBuf pair_off;             // [ne+1] int64

@@ -127,6 +127,34 @@ __global__ void k_elem_tables(int64_t ne, const double *__restrict__ coords,
     }
 }
 
+// Box of each element's quadrature points y_b = sum_v bary_bv V_v, formed as
+// the oracle and the integration's inner points form them in FP64: products
+// rounded, then added in vertex order (no fused multiply-add), so that the box
+// holds every such point exactly.  Used by the refine test of min_dist_l2 = 2.
+template <int DIM>
+__global__ void k_quad_boxes(int64_t ne, int nq, const double *__restrict__ vert,
+                             const double *__restrict__ bary, double *__restrict__ qlo,
+                             double *__restrict__ qhi)
+{
+#pragma clang fp contract(off)
+    constexpr int NV = DIM + 1;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        double a = 0.0, b = 0.0;
+        for (int q = 0; q < nq; ++q) {
+            double y = 0.0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) y = y + bary[q * NV + v] * vert[(v * DIM + k) * ne + e];
+            a = q == 0 ? y : fmin(a, y);
+            b = q == 0 ? y : fmax(b, y);
+        }
+        qlo[k * ne + e] = a;
+        qhi[k * ne + e] = b;
+    }
+}
+
 }  // namespace
 
 void launch_elem_tables(System &s, hipStream_t st)
@@ -148,6 +176,18 @@ void launch_elem_tables(System &s, hipStream_t st)
                            m.conn.as<int32_t>(), s.vert.as<double>(), s.lo.as<double>(),
                            s.hi.as<double>(), s.meas.as<double>());
     NLQ_CHECK_LAUNCH();
+    if (s.p.min_dist_l2 == 2) {
+        const Tables &T = s.ctx->get_tables(m.dim, s.p.lmax);
+        s.qlo.alloc(s.ctx, sizeof(double) * ne * m.dim);
+        s.qhi.alloc(s.ctx, sizeof(double) * ne * m.dim);
+        if (m.dim == 2)
+            hipLaunchKernelGGL(k_quad_boxes<2>, grid, block, 0, st, ne, T.nq, s.vert.as<double>(),
+                               T.rule.as<double>(), s.qlo.as<double>(), s.qhi.as<double>());
+        else
+            hipLaunchKernelGGL(k_quad_boxes<3>, grid, block, 0, st, ne, T.nq, s.vert.as<double>(),
+                               T.rule.as<double>(), s.qlo.as<double>(), s.qhi.as<double>());
+        NLQ_CHECK_LAUNCH();
+    }
 }
 
 // ---------------------------------------------------------------- pair list

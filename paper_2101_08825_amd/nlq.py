@@ -164,10 +164,10 @@ def _ptr(a):
 
 
 def params(dim, delta, eps, lmax, lmin=1, kernel=NLQ_ETA_CONST, form=NLQ_FORM_SYM4,
-           precision=NLQ_FP64_PLAIN, scale=0.0, deterministic=False, min_dist_l2=False):
+           precision=NLQ_FP64_PLAIN, scale=0.0, deterministic=False, min_dist_l2=0):
     return nlq_params(int(dim), int(kernel), float(delta), float(eps), float(scale), int(lmin),
                       int(lmax), int(form), int(precision), int(bool(deterministic)),
-                      int(bool(min_dist_l2)))
+                      int(min_dist_l2))
 
 
 class Context:

@@ -115,21 +115,23 @@ def test_2d_lmin_and_gauss_parity(nlq_ctx, oracle_lib, precision, kernel, lmin):
     m.close()
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("dim,n,kd,ed,lmax", [(2, 12, 3, 8, 4), (3, 4, 2, 8, 3)])
-def test_l2_box_gap_parity(nlq_ctx, oracle_lib, precision, dim, n, kd, ed, lmax):
-    """The Euclidean box gap in the refine test (ablation): matrix and leaf
-    counts equal the oracle's with the same test, the matrix equals the paper
-    test's to the path's tolerance, from fewer leaves."""
+def test_l2_box_gap_parity(nlq_ctx, oracle_lib, precision, dim, n, kd, ed, lmax, mode):
+    """The Euclidean box gap in the refine test (ablation; mode 1: to the inner
+    element's box, 2: to its quadrature points' box): matrix and leaf counts
+    equal the oracle's with the same test, the matrix equals the paper test's
+    to the path's tolerance, from fewer leaves."""
     from paper_2101_08825_amd import nlq
     O = oracle_lib
-    _print_case("l2gap", dim=dim, n=n, precision=precision)
+    _print_case("l2gap", dim=dim, n=n, precision=precision, mode=mode)
     mesh = W.kuhn_mesh(dim, n, kd)
     h = 1.0 / n
     delta, eps = kd * h, kd * h / ed
-    ref, _, _ = _oracle_full(O, mesh, O.params(delta, eps, lmax, min_l2=True))
+    ref, _, _ = _oracle_full(O, mesh, O.params(delta, eps, lmax, min_l2=mode))
     m = nlq.Mesh.create(nlq_ctx, mesh.coords, mesh.conn, mesh.constrained)
-    a = nlq.System(nlq_ctx, m, nlq.params(dim, delta, eps, lmax, precision=precision, min_dist_l2=True))
+    a = nlq.System(nlq_ctx, m, nlq.params(dim, delta, eps, lmax, precision=precision, min_dist_l2=mode))
     b = nlq.System(nlq_ctx, m, nlq.params(dim, delta, eps, lmax, precision=precision))
     rp, col, va = a.csr()
     assert np.array_equal(rp, ref.row_ptr) and np.array_equal(col, ref.col)

@@ -580,7 +580,9 @@ def test_l2_box_gap_drops_only_zeros(oracle_lib, dim, n, kd, ed, lmax, kernel):
     """The Euclidean box gap in Algorithm 1's J^ref test (an ablation; the paper
     uses the L_inf gap of Sec. 5.1 eq. mindist) drops only sub-elements whose
     every point pair lies beyond delta + eps, where the kernel is zero: the
-    matrix equals the paper's to round-off, from fewer leaves."""
+    matrix equals the paper's to round-off, from fewer leaves.  Measuring the
+    gap to the box of the inner quadrature points (min_l2 = 2, a tighter test
+    of our own) drops a superset of those sub-elements, again only zeros."""
     O = oracle_lib
     mesh = W.kuhn_mesh(dim, n, kd)
     h = 1.0 / n
@@ -589,9 +591,13 @@ def test_l2_box_gap_drops_only_zeros(oracle_lib, dim, n, kd, ed, lmax, kernel):
     off, pm = O.pairs(m, delta + eps)
     rp, col = O.pattern(m, off, pm)
     a, la, _ = O.assemble(m, O.params(delta, eps, lmax, kernel=kernel), off, pm, rp, col)
-    b, lb, _ = O.assemble(m, O.params(delta, eps, lmax, kernel=kernel, min_l2=True), off, pm, rp, col)
+    b, lb, _ = O.assemble(m, O.params(delta, eps, lmax, kernel=kernel, min_l2=1), off, pm, rp, col)
+    c, lc, _ = O.assemble(m, O.params(delta, eps, lmax, kernel=kernel, min_l2=2), off, pm, rp, col)
     rel = np.linalg.norm(b - a) / np.linalg.norm(a)
-    print(f"  leaves {int(la.sum())} -> {int(lb.sum())}, |A_l2 - A|/|A| = {rel:.2e}")
-    assert rel <= 1e-14
-    assert lb.sum() < la.sum()
+    relq = np.linalg.norm(c - a) / np.linalg.norm(a)
+    print(f"  leaves {int(la.sum())} -> {int(lb.sum())} -> {int(lc.sum())}, "
+          f"|A_l2 - A|/|A| = {rel:.2e}, |A_q - A|/|A| = {relq:.2e}")
+    assert rel <= 1e-14 and relq <= 1e-14
+    assert lc.sum() < lb.sum() < la.sum()
     assert np.all(lb[:lmax + 1] <= la[:lmax + 1])
+    assert np.all(lc[:lmax + 1] <= lb[:lmax + 1])
