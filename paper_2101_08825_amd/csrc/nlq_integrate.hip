@@ -982,65 +982,39 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     // forming it costs)
     const int memo_lev = WM::kMemoLevel < 2 ? 0 : (WM::kMemoLevel < lmax - 2 ? WM::kMemoLevel : lmax - 2);
     bool memo_ready = memo_lev < 2;
-    int n = 1;
-    if (lane == 0) stk[0] = 1u << 24;
-    wave_sync();
-    while (n > 0) {
-        // pop the largest top window whose refinable members (level < L_max - 1:
-        // the only ones that push) fit: NCH * pushers - k <= cap - n, at least 1
-        const int w = n < kWave ? n : kWave;
-        int k = 1;
-        {
-            const uint32_t e = lane < w ? stk[n - 1 - lane] : 0u;
-            const bool pusher = lane < w && static_cast<int>(e >> 24) < lmax - 1;
-            const unsigned long long pm = wave_ballot(pusher);
-            const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-            const int kk = lane + 1;
-            // signed: __popcll returns an unsigned count, and cap - n may be negative
-            const int pushers = static_cast<int>(__popcll(pm & upto));
-            const bool ok = lane < w && NCH * pushers - kk <= cap - n;
-            const unsigned long long okm = wave_ballot(ok);
-            if (okm) k = 64 - __clzll(okm);
+    auto build_memo = [&]() {
+        // lane t < NCH: level 2, local t; then level 3, local t - NCH
+        const int count = memo_lev == 2 ? NCH : WM::kMemoCount;
+        if (lane < count) {
+            const int tlev = lane < NCH ? 2 : 3;
+            const int tloc = lane < NCH ? lane : lane - NCH;
+            Simplex<DIM> T = root;
+            for (int d = tlev - 2; d >= 0; --d) T = child_of(T, (tloc >> (DIM * d)) & (NCH - 1));
+            double *dst = memo + lane * NV * DIM;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) dst[v * DIM + k] = T.v[v][k];
         }
-        n -= k;
-        const bool valid = lane < k;
-        const uint32_t ent = valid ? stk[n + lane] : 0u;
         wave_sync();
-        const int lev = static_cast<int>(ent >> 24);
-        const uint32_t local = ent & 0xFFFFFFu;
-        if (!memo_ready && wave_ballot(valid && lev >= 2)) {
-            // lane t < NCH: level 2, local t; then level 3, local t - NCH
-            const int count = memo_lev == 2 ? NCH : WM::kMemoCount;
-            if (lane < count) {
-                const int tlev = lane < NCH ? 2 : 3;
-                const int tloc = lane < NCH ? lane : lane - NCH;
-                Simplex<DIM> T = root;
-                for (int d = tlev - 2; d >= 0; --d) T = child_of(T, (tloc >> (DIM * d)) & (NCH - 1));
-                double *dst = memo + lane * NV * DIM;
-#pragma unroll
-                for (int v = 0; v < NV; ++v)
-#pragma unroll
-                    for (int k = 0; k < DIM; ++k) dst[v * DIM + k] = T.v[v][k];
-            }
-            wave_sync();
-            memo_ready = true;
-        }
-        int cls = 0;
-        if (valid) {
-            if (lev == lmax) cls = 1;                 // the root when L_max = 1
-            else if (lev < lmin) cls = 2;
-            else cls = classify<DIM>(A, root, memo, memo_lev, lev, local, mlo, mhi, dlo, dhi);
-        }
+        memo_ready = true;
+    };
+    int n = 0;
+    // the actions of one classified window: J^int members to the leaf buffer;
+    // children of J^ref members one level above L_max straight to the leaf
+    // buffer, the others' children to the stack when `expand`.  False if the
+    // stack would overflow (the pop rule below prevents it).
+    auto act = [&](int lev, uint32_t local, int cls, bool expand) {
         if (cls == 1 && s_leaf) atomicAdd(&s_leaf[lev], 1ull);
         push_leaf(cls == 1, cls == 1 ? leaf_entry(lev, level_offset<DIM>(lev) + static_cast<int>(local)) : 0u);
         const bool to_leaves = cls == 2 && lev + 1 == lmax;
-        const bool to_stack = cls == 2 && lev + 1 < lmax;
+        const bool to_stack = cls == 2 && lev + 1 < lmax && expand;
         const unsigned long long mpush = wave_ballot(to_stack);
         const unsigned long long mleaf = wave_ballot(to_leaves);
         if (n + static_cast<int>(__popcll(mpush)) * NCH + static_cast<int>(__popcll(mleaf)) > A.capl) {
-            // cannot happen with the pop rule above; never write past the stack
+            // never write past the stack
             if (lane == 0) atomicOr(&A.counters->error, 1);
-            break;
+            return false;
         }
         if (to_stack) {
             const uint32_t base = (static_cast<uint32_t>(lev + 1) << 24) | (local * NCH);
@@ -1064,6 +1038,69 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
             if (lane == 0 && s_leaf) atomicAdd(&s_leaf[lmax], static_cast<unsigned long long>(nl));
         }
         wave_sync();
+        return true;
+    };
+    // The top of the tree without the stack: the root is classified by every lane
+    // alike; if it is refined, levels 2..sl (NCH [+ NCH^2] nodes, a lane each, in
+    // the memo's lane order) are classified in one pass instead of one pop per
+    // level, a node counting only if its level-2 ancestor was refined too -- the
+    // same leaf set as the pops give.
+    constexpr int kTopLevels = DIM == 2 ? 3 : 2;
+    const int sl = kTopLevels < lmax - 1 ? kTopLevels : lmax - 1;
+    bool ok = true;
+    if (sl >= 2) {
+        const int rc = 1 < lmin ? 2 : classify<DIM>(A, root, memo, memo_lev, 1, 0u, mlo, mhi, dlo, dhi);
+        if (rc == 2) {
+            const int ntop = sl == 2 ? NCH : NCH + NCH * NCH;
+            const bool valid = lane < ntop;
+            const int lev = lane < NCH ? 2 : 3;
+            const uint32_t local = static_cast<uint32_t>(lane < NCH ? lane : lane - NCH);
+            if (!memo_ready) build_memo();
+            int cls = 0;
+            if (valid) cls = lev < lmin ? 2 : classify<DIM>(A, root, memo, memo_lev, lev, local, mlo, mhi, dlo, dhi);
+            // the parent of level-3 node `local` is level-2 node local / NCH, in that lane
+            const unsigned long long ref = wave_ballot(valid && cls == 2);
+            const bool reach = lev == 2 || ((ref >> (local >> DIM)) & 1ull) != 0;
+            ok = act(lev, local, valid && reach ? cls : 0, lev == sl);
+        } else {
+            ok = act(1, 0u, lane == 0 ? rc : 0, false);
+        }
+    } else {
+        n = 1;
+        if (lane == 0) stk[0] = 1u << 24;
+        wave_sync();
+    }
+    while (ok && n > 0) {
+        // pop the largest top window whose refinable members (level < L_max - 1:
+        // the only ones that push) fit: NCH * pushers - k <= cap - n, at least 1
+        const int w = n < kWave ? n : kWave;
+        int k = 1;
+        {
+            const uint32_t e = lane < w ? stk[n - 1 - lane] : 0u;
+            const bool pusher = lane < w && static_cast<int>(e >> 24) < lmax - 1;
+            const unsigned long long pm = wave_ballot(pusher);
+            const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+            const int kk = lane + 1;
+            // signed: __popcll returns an unsigned count, and cap - n may be negative
+            const int pushers = static_cast<int>(__popcll(pm & upto));
+            const bool ok = lane < w && NCH * pushers - kk <= cap - n;
+            const unsigned long long okm = wave_ballot(ok);
+            if (okm) k = 64 - __clzll(okm);
+        }
+        n -= k;
+        const bool valid = lane < k;
+        const uint32_t ent = valid ? stk[n + lane] : 0u;
+        wave_sync();
+        const int lev = static_cast<int>(ent >> 24);
+        const uint32_t local = ent & 0xFFFFFFu;
+        if (!memo_ready && wave_ballot(valid && lev >= 2)) build_memo();
+        int cls = 0;
+        if (valid) {
+            if (lev == lmax) cls = 1;                 // the root when L_max = 1
+            else if (lev < lmin) cls = 2;
+            else cls = classify<DIM>(A, root, memo, memo_lev, lev, local, mlo, mhi, dlo, dhi);
+        }
+        ok = act(lev, local, cls, true);
     }
     if (nleaf > 0) integrate(nleaf);
     // a pair without leaves (every sub-element dropped) has zero blocks: nothing to
