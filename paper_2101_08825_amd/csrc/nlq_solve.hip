@@ -106,38 +106,70 @@ k_lift(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict
 // ---- CG pieces -------------------------------------------------------------
 
 constexpr int kCgThreads = 256;
-constexpr int kCgRows = kCgThreads / kWave;
 
 struct CgScalars {
     double rz, rz_new, pq, rr, alpha, beta, bnorm2;
 };
 
-// q = A_ff p on free rows (0 on Gamma); partial sums of p.q per block
-__global__ void __launch_bounds__(kCgThreads)
+constexpr int kSpmvThreads = 1024;
+constexpr int kRowLanes = 16;                               // lanes per matrix row
+constexpr int kSpmvRows = kSpmvThreads / kRowLanes;         // rows per block
+
+// Fixed-order sum of nb block partials by one wave (lane l adds partials l,
+// l + 64, ..., then a butterfly across the lanes), every lane getting the
+// result: the consumers of a reduction compute it themselves, each wave alike
+// and without a barrier, instead of a reduction kernel and a scalar kernel in
+// between.
+__device__ double wave_total(const double *__restrict__ v, int64_t nb)
+{
+    double s = 0.0;
+    for (int64_t b = lane_id(); b < nb; b += kWave) s += v[b];
+    return wave_sum(s);
+}
+
+// The search direction and its product at once: p = z + beta p_old with beta =
+// (new r.z) / (old r.z) from the update's partials (beta = 0 on the first
+// iteration, where p_old = z), formed on the fly wherever the product reads it
+// and stored by the wave of its row into p_new (p is double-buffered, so no
+// row reads a value another row has already replaced); q = A_ff p on free rows
+// (0 on Gamma); partial sums of p.q per block (64 rows, 16 lanes each).
+__global__ void __launch_bounds__(kSpmvThreads)
 k_spmv_dot(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
            const double *__restrict__ val, const uint8_t *__restrict__ constrained,
-           const double *__restrict__ p, double *__restrict__ q, double *__restrict__ partial)
+           const double *__restrict__ rz_new_part, const double *__restrict__ rz_old_part, int64_t nb,
+           int first, const double *__restrict__ z, const double *__restrict__ p_old,
+           double *__restrict__ p_new, double *__restrict__ q, double *__restrict__ partial)
 {
-    __shared__ double red[kCgRows];
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kCgRows + threadIdx.x / kWave;
+    __shared__ double red[kSpmvRows];
+    double beta = 0.0;
+    if (!first) {
+        const double rz_new = wave_total(rz_new_part, nb);
+        const double rz_old = wave_total(rz_old_part, nb);
+        beta = rz_old != 0.0 ? rz_new / rz_old : 0.0;
+    }
+    const int rl = threadIdx.x % kRowLanes;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kSpmvRows + threadIdx.x / kRowLanes;
     double s = 0.0;
     bool live = i < n && !constrained[i];
     if (live)
-        for (int64_t k = row_ptr[i] + lane_id(); k < row_ptr[i + 1]; k += kWave) {
+        for (int64_t k = row_ptr[i] + rl; k < row_ptr[i + 1]; k += kRowLanes) {
             const int32_t j = col[k];
-            if (!constrained[j]) s += val[k] * p[j];
+            if (!constrained[j]) s += val[k] * fma(beta, p_old[j], z[j]);
         }
-    s = wave_sum(s);
+    // sum over the row's 16 lanes (a butterfly within each 16-lane group)
+    for (int o = kRowLanes / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
     double contrib = 0.0;
-    if (i < n && lane_id() == 0) {
+    if (i < n && rl == 0) {
+        const double pi = fma(beta, p_old[i], z[i]);
+        p_new[i] = pi;
         q[i] = live ? s : 0.0;
-        contrib = live ? s * p[i] : 0.0;
+        contrib = live ? s * pi : 0.0;
     }
-    if (lane_id() == 0) red[threadIdx.x / kWave] = contrib;
+    if (rl == 0) red[threadIdx.x / kRowLanes] = contrib;
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
-        for (int r = 0; r < kCgRows; ++r) t += red[r];
+        for (int r = 0; r < kSpmvRows; ++r) t += red[r];
         partial[blockIdx.x] = t;
     }
 }
@@ -162,22 +194,27 @@ k_reduce(int64_t nb, const double *__restrict__ partial, double *__restrict__ ou
     }
 }
 
-__global__ void k_alpha(CgScalars *sc)
-{
-    sc->alpha = sc->pq != 0.0 ? sc->rz / sc->pq : 0.0;
-}
-
-// w += alpha p; r -= alpha q; z = D^-1 r; partials of r.z and r.r
+// alpha = r.z / p.q from the partials of the last update (or the start) and of
+// the SpMV; w += alpha p; r -= alpha q; z = D^-1 r; partials of the new r.z
+// and of r.r
 __global__ void __launch_bounds__(kCgThreads)
-k_update(int64_t n, const CgScalars *__restrict__ sc, const double *__restrict__ dinv,
+k_update(int64_t n, CgScalars *__restrict__ sc, const double *__restrict__ rz_part,
+         const double *__restrict__ pq_part, int64_t nb_rows, const double *__restrict__ dinv,
          const double *__restrict__ p, const double *__restrict__ q, double *__restrict__ w,
-         double *__restrict__ r, double *__restrict__ z, double *__restrict__ partial, int64_t nb)
+         double *__restrict__ r, double *__restrict__ z, double *__restrict__ rz_next,
+         double *__restrict__ rr_part, int64_t nb)
 {
     __shared__ double red[2][kCgThreads / kWave];
+    const double rz_old = wave_total(rz_part, nb);
+    const double pq = wave_total(pq_part, nb_rows);
+    const double a = pq != 0.0 ? rz_old / pq : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->pq = pq;
+        sc->alpha = a;
+    }
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kCgThreads + threadIdx.x;
     double rz = 0.0, rr = 0.0;
     if (i < n) {
-        const double a = sc->alpha;
         w[i] += a * p[i];
         const double ri = r[i] - a * q[i];
         r[i] = ri;
@@ -199,22 +236,9 @@ k_update(int64_t n, const CgScalars *__restrict__ sc, const double *__restrict__
             a += red[0][k];
             b += red[1][k];
         }
-        partial[blockIdx.x] = a;
-        partial[nb + blockIdx.x] = b;
+        rz_next[blockIdx.x] = a;
+        rr_part[blockIdx.x] = b;
     }
-}
-
-__global__ void k_beta(CgScalars *sc)
-{
-    sc->beta = sc->rz != 0.0 ? sc->rz_new / sc->rz : 0.0;
-    sc->rz = sc->rz_new;
-}
-
-__global__ void k_pupdate(int64_t n, const CgScalars *__restrict__ sc, const double *__restrict__ z,
-                          double *__restrict__ p)
-{
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = z[i] + sc->beta * p[i];
 }
 
 // r = F~ (free), z = D^-1 r, p = z, w = 0; dinv from the diagonal; partials r.z, r.r
@@ -320,11 +344,16 @@ int cg_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, 
     if (s.u.empty()) s.u.alloc(s.ctx, sizeof(double) * n);
     DevBuf dinv(s.ctx, sizeof(double) * n, st), w(s.ctx, sizeof(double) * n, st),
         r(s.ctx, sizeof(double) * n, st), z(s.ctx, sizeof(double) * n, st), p(s.ctx, sizeof(double) * n, st),
-        q(s.ctx, sizeof(double) * n, st);
-    const int64_t nb_rows = (n + kCgRows - 1) / kCgRows;
+        p2(s.ctx, sizeof(double) * n, st), q(s.ctx, sizeof(double) * n, st);
+    double *const pbuf[2] = {p.as<double>(), p2.as<double>()};
+    const int64_t nb_rows = (n + kSpmvRows - 1) / kSpmvRows;
     const int64_t nb_vec = (n + kCgThreads - 1) / kCgThreads;
-    const int64_t nbmax = nb_rows > nb_vec ? nb_rows : nb_vec;
-    DevBuf partial(s.ctx, sizeof(double) * 2 * nbmax, st);
+    // block partials: r.z in two slots (the current and the next iteration's),
+    // r.r, p.q
+    DevBuf partial(s.ctx, sizeof(double) * (3 * nb_vec + nb_rows), st);
+    double *const rz_slot[2] = {partial.as<double>(), partial.as<double>() + nb_vec};
+    double *const rr_part = partial.as<double>() + 2 * nb_vec;
+    double *const pq_part = partial.as<double>() + 3 * nb_vec;
     DevBuf scal(s.ctx, sizeof(CgScalars), st);
     CgScalars *sc = scal.as<CgScalars>();
     NLQ_HIP(hipMemsetAsync(sc, 0, sizeof(CgScalars), st));
@@ -350,34 +379,36 @@ int cg_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, 
         *relres = 0.0;
     } else {
         const int check = 8;
-        // one CG iteration: 8 kernels, no host work
-        auto iteration = [&]() {
-            hipLaunchKernelGGL(k_spmv_dot, dim3(nb_rows), dim3(kCgThreads), 0, st, n, s.row_ptr.as<int64_t>(),
-                               s.col.as<int32_t>(), s.val.as<double>(), cst, p.as<double>(), q.as<double>(),
-                               partial.as<double>());
-            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kCgThreads), 0, st, nb_rows, partial.as<double>(), &sc->pq, 1);
-            hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1), 0, st, sc);
-            hipLaunchKernelGGL(k_update, dim3(nb_vec), dim3(kCgThreads), 0, st, n, sc, dinv.as<double>(),
-                               p.as<double>(), q.as<double>(), w.as<double>(), r.as<double>(), z.as<double>(),
-                               partial.as<double>(), nb_vec);
-            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kCgThreads), 0, st, nb_vec, partial.as<double>(),
-                               &sc->rz_new, 1);
-            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kCgThreads), 0, st, nb_vec, partial.as<double>() + nb_vec,
-                               &sc->rr, 1);
-            hipLaunchKernelGGL(k_beta, dim3(1), dim3(1), 0, st, sc);
-            hipLaunchKernelGGL(k_pupdate, dim3(nb_vec), dim3(kCgThreads), 0, st, n, sc, z.as<double>(),
-                               p.as<double>());
+        // CG iteration k: 2 kernels, no host work.  Its parity selects the r.z
+        // slots (the update writes the next r.z where the product has just read
+        // the previous one) and the p buffers (p_old -> p_new).
+        auto iteration = [&](int k) {
+            const int par = k & 1;
+            hipLaunchKernelGGL(k_spmv_dot, dim3(nb_rows), dim3(kSpmvThreads), 0, st, n, s.row_ptr.as<int64_t>(),
+                               s.col.as<int32_t>(), s.val.as<double>(), cst, rz_slot[par], rz_slot[1 - par],
+                               nb_vec, k == 0 ? 1 : 0, z.as<double>(), pbuf[par], pbuf[1 - par], q.as<double>(),
+                               pq_part);
+            hipLaunchKernelGGL(k_update, dim3(nb_vec), dim3(kCgThreads), 0, st, n, sc, rz_slot[par], pq_part,
+                               nb_rows, dinv.as<double>(), pbuf[1 - par], q.as<double>(), w.as<double>(),
+                               r.as<double>(), z.as<double>(), rz_slot[1 - par], rr_part, nb_vec);
         };
-        // The 8 iterations between two residual checks are captured once as a
-        // HIP graph (kernels only: no memset or copy inside) and replayed, which
-        // removes 64 launches per check from the host path; NLQ_CG_GRAPH=0 keeps
-        // the plain launches.
+        // r.r of the last update, for the host's residual check
+        auto residual = [&]() {
+            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kCgThreads), 0, st, nb_vec, rr_part, &sc->rr, 1);
+        };
+        // The residual is checked after iteration 0 and then after every 8
+        // iterations.  Iterations 1..8 (the first iteration's kernels differ)
+        // and the check's reduction are captured once as a HIP graph (kernels
+        // only: no memset or copy inside) and replayed for every later block of
+        // 8, whose parities are the same; NLQ_CG_GRAPH=0 keeps the plain
+        // launches, in the same order.
         hipGraphExec_t exec = nullptr;
         const char *env = std::getenv("NLQ_CG_GRAPH");
         if (maxit >= 2 * check && !(env && env[0] == '0')) {
             hipGraph_t graph = nullptr;
             NLQ_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            for (int k = 0; k < check; ++k) iteration();
+            for (int k = 1; k <= check; ++k) iteration(k);
+            residual();
             const hipError_t e_end = hipStreamEndCapture(st, &graph);
             if (e_end != hipSuccess) fail(NLQ_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e_end));
             const hipError_t e_inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -385,11 +416,16 @@ int cg_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, 
             if (e_inst != hipSuccess) fail(NLQ_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e_inst));
         }
         for (it = 0; it < maxit;) {
-            if (exec && maxit - it >= check) {
+            if (it == 0) {
+                iteration(0);
+                residual();
+                it = 1;
+            } else if (exec && maxit - it >= check) {
                 NLQ_HIP(hipGraphLaunch(exec, st));
                 it += check;
             } else {
-                for (int k = 0; k < check && it < maxit; ++k, ++it) iteration();
+                for (int k = 0; k < check && it < maxit; ++k, ++it) iteration(it);
+                residual();
             }
             NLQ_CHECK_LAUNCH();
             NLQ_HIP(hipMemcpyAsync(&h, sc, sizeof(CgScalars), hipMemcpyDeviceToHost, st));
