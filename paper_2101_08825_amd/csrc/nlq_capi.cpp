@@ -19,26 +19,96 @@ void set_last_error(const std::string &msg) { g_last_error = msg; }
 
 [[noreturn]] void fail(nlq_status st, const std::string &msg) { throw Error{st, msg}; }
 
+namespace {
+
+// size class of a cached block: powers of two up to 1 MiB, then whole MiB
+size_t size_class(size_t b)
+{
+    constexpr size_t kMiB = size_t(1) << 20;
+    if (b > kMiB) return (b + kMiB - 1) / kMiB * kMiB;
+    size_t c = 256;
+    while (c < b) c <<= 1;
+    return c;
+}
+
+}  // namespace
+
+void *Ctx::cache_take(size_t cls)
+{
+    std::lock_guard<std::mutex> lk(cache_mu);
+    auto it = cache.find(cls);
+    if (it == cache.end()) return nullptr;
+    void *p = it->second;
+    cache.erase(it);
+    cached -= cls;
+    return p;
+}
+
+void Ctx::cache_put(void *p, size_t cls)
+{
+    {
+        std::lock_guard<std::mutex> lk(cache_mu);
+        if (cached + cls <= kCacheMax && used.load() + cached + cls <= budget) {
+            cache.emplace(cls, p);
+            cached += cls;
+            return;
+        }
+    }
+    (void)hipFree(p);
+}
+
+void Ctx::cache_trim(uint64_t need)
+{
+    std::vector<void *> drop;
+    {
+        std::lock_guard<std::mutex> lk(cache_mu);
+        while (!cache.empty() && (need == UINT64_MAX || used.load() + cached + need > budget)) {
+            auto it = std::prev(cache.end());   // largest first
+            drop.push_back(it->second);
+            cached -= it->first;
+            cache.erase(it);
+        }
+    }
+    for (void *p : drop) (void)hipFree(p);
+    if (need == UINT64_MAX || !drop.empty()) {
+        hipMemPool_t pool = nullptr;
+        if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess && pool) (void)hipMemPoolTrimTo(pool, 0);
+    }
+}
+
 void DevBuf::alloc(Ctx *ctx, size_t bytes, hipStream_t st)
 {
     release();
     if (bytes == 0) bytes = 8;
     if (ctx->allocs.fetch_add(1) == ctx->alloc_fail_at)
         fail(NLQ_ENOMEM, "injected allocation failure (NLQ_FAIL_ALLOC_AT)");
-    const uint64_t now = ctx->used.fetch_add(bytes) + bytes;
+    const size_t charge = st ? bytes : size_class(bytes);
+    const uint64_t now = ctx->used.fetch_add(charge) + charge;
     if (now > ctx->budget) {
-        ctx->used.fetch_sub(bytes);
+        ctx->used.fetch_sub(charge);
         fail(NLQ_ENOMEM, "device memory budget exceeded (" + std::to_string(now) + " > " +
                              std::to_string(ctx->budget) + " bytes)");
     }
     void *p = nullptr;
-    hipError_t e = st ? hipMallocAsync(&p, bytes, st) : hipMalloc(&p, bytes);
+    hipError_t e = hipSuccess;
+    if (st) {
+        e = hipMallocAsync(&p, bytes, st);
+    } else if (!(p = ctx->cache_take(charge))) {
+        ctx->cache_trim(0);
+        e = hipMalloc(&p, charge);
+        if (e != hipSuccess) {
+            // the device may be short of memory the cache still holds
+            ctx->cache_trim(UINT64_MAX);
+            e = hipMalloc(&p, charge);
+        }
+    }
     if (e != hipSuccess) {
-        ctx->used.fetch_sub(bytes);
+        ctx->used.fetch_sub(charge);
         fail(NLQ_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
     }
     p_ = p;
     bytes_ = bytes;
+    cls_ = st ? 0 : charge;
     ctx_ = ctx;
     st_ = st;
 }
@@ -46,12 +116,19 @@ void DevBuf::alloc(Ctx *ctx, size_t bytes, hipStream_t st)
 void DevBuf::release()
 {
     if (p_) {
-        if (st_) (void)hipFreeAsync(p_, st_);
-        else (void)hipFree(p_);
-        ctx_->used.fetch_sub(bytes_);
+        if (st_) {
+            (void)hipFreeAsync(p_, st_);
+            ctx_->used.fetch_sub(bytes_);
+        } else {
+            // no kernel may still use the block when it is handed out again
+            (void)hipDeviceSynchronize();
+            ctx_->used.fetch_sub(cls_);
+            ctx_->cache_put(p_, cls_);
+        }
     }
     p_ = nullptr;
     bytes_ = 0;
+    cls_ = 0;
 }
 
 namespace {
@@ -336,6 +413,14 @@ nlq_status nlq_ctx_create(int32_t device, uint64_t hbm_budget_bytes, nlq_ctx **o
         NLQ_HIP(hipStreamCreateWithFlags(&c->impl.own_stream, hipStreamNonBlocking));
         c->impl.stream = c->impl.own_stream;
         if (const char *env = std::getenv("NLQ_FAIL_ALLOC_AT")) c->impl.alloc_fail_at = std::atoll(env);
+        // stream-ordered temporaries come from the device's default pool; keep
+        // what they free there instead of unmapping it at every synchronisation
+        // (the pool is trimmed with the block cache when memory runs short)
+        hipMemPool_t pool = nullptr;
+        if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess && pool) {
+            uint64_t keep = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
         *out = c.release();
     });
 }
@@ -367,6 +452,7 @@ nlq_status nlq_ctx_destroy(nlq_ctx *ctx)
         (void)hipSetDevice(ctx->impl.device);
         (void)hipStreamSynchronize(ctx->impl.stream);
         ctx->impl.tables.clear();
+        ctx->impl.cache_trim(UINT64_MAX);
         (void)hipStreamDestroy(ctx->impl.own_stream);
         delete ctx;
     });

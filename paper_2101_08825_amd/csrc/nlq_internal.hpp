@@ -45,7 +45,10 @@ struct Ctx;
 // Device allocation charged against the context budget.  With a stream the
 // allocation is stream ordered (hipMallocAsync / hipFreeAsync on that stream),
 // so that freeing a temporary does not wait for the whole device; the stream
-// must outlive the buffer.
+// must outlive the buffer.  Without one the block comes from the context's
+// cache of released blocks of its size class when there is one (hipMalloc
+// otherwise), and goes back there on release, after the device has finished
+// all work (what hipFree would wait for).
 class DevBuf {
   public:
     DevBuf() = default;
@@ -61,8 +64,10 @@ class DevBuf {
             bytes_ = o.bytes_;
             ctx_ = o.ctx_;
             st_ = o.st_;
+            cls_ = o.cls_;
             o.p_ = nullptr;
             o.bytes_ = 0;
+            o.cls_ = 0;
         }
         return *this;
     }
@@ -75,6 +80,7 @@ class DevBuf {
   private:
     void *p_ = nullptr;
     size_t bytes_ = 0;
+    size_t cls_ = 0;   // size class charged and cached (no stream)
     Ctx *ctx_ = nullptr;
     hipStream_t st_ = nullptr;
 };
@@ -121,6 +127,16 @@ struct Ctx {
     // (counted per context from 0) fails with NLQ_ENOMEM; -1: none
     std::atomic<int64_t> allocs{0};
     int64_t alloc_fail_at = -1;
+    // released device blocks by size class, kept for reuse (a step that builds
+    // and frees the same systems again then maps no memory); live + cached
+    // bytes stay within the budget, cached bytes within kCacheMax
+    static constexpr uint64_t kCacheMax = 8ull << 30;
+    std::mutex cache_mu;
+    std::multimap<size_t, void *> cache;
+    uint64_t cached = 0;
+    void *cache_take(size_t cls);
+    void cache_put(void *p, size_t cls);
+    void cache_trim(uint64_t need);   // free cached blocks until used + cached + need <= budget
     std::mutex tables_mu;
     std::map<std::pair<int, int>, std::unique_ptr<Tables>> tables;
     std::unique_ptr<Server> server;

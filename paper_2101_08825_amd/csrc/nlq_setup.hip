@@ -261,16 +261,19 @@ __device__ void wave_bitonic_sort(int32_t *buf, int n2)
 // (bbox_l, bbox_m) < delta + eps} (Section 5, eq. (k_l) with eq. (mindist)),
 // candidates from the uniform bins whose lower-corner range can hold such m.
 // count mode (m_out == nullptr): counts[l] = |J_l|, err[1] = max |J_l|, err[0] = 1
-// when a list exceeds the LDS capacity; fill mode: J_l ascending.
+// when a list exceeds kPairCap; fill mode: J_l ascending, sorted in a dynamic
+// LDS list of `cap` entries (a power of two >= max |J_l|), so that the count
+// pass needs no LDS and the fill pass only what the longest list needs (LDS
+// bounds how many of these one-wave workgroups a CU holds).
 template <int DIM>
 __global__ void __launch_bounds__(kWave)
 k_pairs(int64_t ne, const double *__restrict__ lo, const double *__restrict__ hi, BinGrid g,
         double thr, double reach_lo0, double reach_lo1, double reach_lo2,
         const int64_t *__restrict__ bin_off, const int32_t *__restrict__ items,
         int64_t *__restrict__ counts, const int64_t *__restrict__ offsets,
-        int32_t *__restrict__ m_out, int *__restrict__ err)
+        int32_t *__restrict__ m_out, int cap, int *__restrict__ err)
 {
-    __shared__ int32_t buf[kPairCap];
+    extern __shared__ int32_t buf[];
     const int64_t l = blockIdx.x;
     if (l >= ne) return;
     double llo[DIM], lhi[DIM];
@@ -284,42 +287,47 @@ k_pairs(int64_t ne, const double *__restrict__ lo, const double *__restrict__ hi
         b1[k] = bin_coord<DIM>(g, k, lhi[k] + thr);
     }
     int count = 0;
+    // the bins x = b0..b1 of one row (y, z) are consecutive in the bin order, so
+    // their items form one range: the wave walks it 64 items at a time
     for (int z = b0[2]; z <= b1[2]; ++z)
-        for (int y = b0[1]; y <= b1[1]; ++y)
-            for (int x = b0[0]; x <= b1[0]; ++x) {
-                const int64_t b = x + static_cast<int64_t>(g.nb[0]) * (y + static_cast<int64_t>(g.nb[1]) * z);
-                const int64_t s0 = bin_off[b], s1 = bin_off[b + 1];
-                for (int64_t i = s0; i < s1; i += kWave) {
-                    const int64_t it = i + lane_id();
-                    bool take = false;
-                    int32_t mm = 0;
-                    if (it < s1) {
-                        mm = items[it];
-                        double mlo[DIM], mhi[DIM];
+        for (int y = b0[1]; y <= b1[1]; ++y) {
+            const int64_t row = static_cast<int64_t>(g.nb[0]) * (y + static_cast<int64_t>(g.nb[1]) * z);
+            const int64_t s0 = bin_off[row + b0[0]], s1 = bin_off[row + b1[0] + 1];
+            for (int64_t i = s0; i < s1; i += kWave) {
+                const int64_t it = i + lane_id();
+                bool take = false;
+                int32_t mm = 0;
+                if (it < s1) {
+                    mm = items[it];
+                    double mlo[DIM], mhi[DIM];
 #pragma unroll
-                        for (int k = 0; k < DIM; ++k) {
-                            mlo[k] = lo[k * ne + mm];
-                            mhi[k] = hi[k * ne + mm];
-                        }
-                        take = aprx_min_dist<DIM>(llo, lhi, mlo, mhi) < thr;
+                    for (int k = 0; k < DIM; ++k) {
+                        mlo[k] = lo[k * ne + mm];
+                        mhi[k] = hi[k * ne + mm];
                     }
-                    const unsigned long long mask = wave_ballot(take);
-                    if (m_out && take) {
-                        const int at = count + lanes_below(mask);
-                        if (at < kPairCap) buf[at] = mm;
-                    }
-                    count += __popcll(mask);
+                    take = aprx_min_dist<DIM>(llo, lhi, mlo, mhi) < thr;
                 }
+                const unsigned long long mask = wave_ballot(take);
+                if (m_out && take) {
+                    const int at = count + lanes_below(mask);
+                    if (at < cap) buf[at] = mm;
+                }
+                count += __popcll(mask);
             }
+        }
     if (!m_out) {
         if (lane_id() == 0) {
             counts[l] = count;
-            atomicMax(err + 1, count);
+            // the longest list: an atomic only when this one is longer than the
+            // maximum seen so far (same-address atomics from every workgroup
+            // serialise; a stale read only costs one more atomic)
+            if (count > __hip_atomic_load(err + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                atomicMax(err + 1, count);
             if (count > kPairCap) atomicOr(err, 1);
         }
         return;
     }
-    if (count > kPairCap) return;
+    if (count > cap) return;
     int n2 = 1;
     while (n2 < count) n2 <<= 1;
     for (int i = count + lane_id(); i < n2; i += kWave) buf[i] = INT_MAX;
@@ -383,20 +391,21 @@ void build_pairs(System &s, hipStream_t st)
     NLQ_HIP(hipMemsetAsync(counts.as<void>(), 0, sizeof(int64_t) * (ne + 1), st));
     s.pair_off.alloc(s.ctx, sizeof(int64_t) * (ne + 1));
     const double r0 = m.ext_max[0], r1 = dim > 1 ? m.ext_max[1] : 0.0, r2 = dim > 2 ? m.ext_max[2] : 0.0;
-    auto launch = [&](int32_t *m_out) {
+    auto launch = [&](int32_t *m_out, int cap) {
+        const size_t lds = m_out ? sizeof(int32_t) * static_cast<size_t>(cap) : 0;
         if (dim == 2)
-            hipLaunchKernelGGL(k_pairs<2>, dim3(ne), dim3(kWave), 0, st, ne, s.lo.as<double>(),
+            hipLaunchKernelGGL(k_pairs<2>, dim3(ne), dim3(kWave), lds, st, ne, s.lo.as<double>(),
                                s.hi.as<double>(), g, thr, r0, r1, r2, bin_off.as<int64_t>(),
                                items.as<int32_t>(), counts.as<int64_t>(),
-                               s.pair_off.as<int64_t>(), m_out, err.as<int>());
+                               s.pair_off.as<int64_t>(), m_out, cap, err.as<int>());
         else
-            hipLaunchKernelGGL(k_pairs<3>, dim3(ne), dim3(kWave), 0, st, ne, s.lo.as<double>(),
+            hipLaunchKernelGGL(k_pairs<3>, dim3(ne), dim3(kWave), lds, st, ne, s.lo.as<double>(),
                                s.hi.as<double>(), g, thr, r0, r1, r2, bin_off.as<int64_t>(),
                                items.as<int32_t>(), counts.as<int64_t>(),
-                               s.pair_off.as<int64_t>(), m_out, err.as<int>());
+                               s.pair_off.as<int64_t>(), m_out, cap, err.as<int>());
         NLQ_CHECK_LAUNCH();
     };
-    launch(nullptr);
+    launch(nullptr, 0);
     int herr[2] = {0, 0};
     NLQ_HIP(hipMemcpyAsync(herr, err.as<void>(), 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     exclusive_scan_i64(s.ctx, counts.as<int64_t>(), s.pair_off.as<int64_t>(), ne + 1, st);
@@ -406,7 +415,9 @@ void build_pairs(System &s, hipStream_t st)
     if (herr[0]) fail(NLQ_EINVAL, "an element has more than 8192 neighbours within delta+eps");
     s.max_pairs = herr[1];
     s.pair_m.alloc(s.ctx, sizeof(int32_t) * std::max<int64_t>(s.n_pairs, 1));
-    launch(s.pair_m.as<int32_t>());
+    int cap = kWave;
+    while (cap < s.max_pairs) cap <<= 1;
+    launch(s.pair_m.as<int32_t>(), cap);
     NLQ_HIP(hipStreamSynchronize(st));
 }
 
