@@ -260,8 +260,8 @@ __device__ void wave_bitonic_sort(int32_t *buf, int n2)
 // One single-wave workgroup per outer element l.  J_l = {m : aprx min dist
 // (bbox_l, bbox_m) < delta + eps} (Section 5, eq. (k_l) with eq. (mindist)),
 // candidates from the uniform bins whose lower-corner range can hold such m.
-// count mode (m_out == nullptr): counts[l] = |J_l|, err[1] = max |J_l|, err[0] = 1
-// when a list exceeds kPairCap; fill mode: J_l ascending, sorted in a dynamic
+// count mode (m_out == nullptr): counts[l] = |J_l|, err[0] = 1 when a list
+// exceeds kPairCap (the longest list comes from k_count_max); fill mode: J_l ascending, sorted in a dynamic
 // LDS list of `cap` entries (a power of two >= max |J_l|), so that the count
 // pass needs no LDS and the fill pass only what the longest list needs (LDS
 // bounds how many of these one-wave workgroups a CU holds).
@@ -318,11 +318,6 @@ k_pairs(int64_t ne, const double *__restrict__ lo, const double *__restrict__ hi
     if (!m_out) {
         if (lane_id() == 0) {
             counts[l] = count;
-            // the longest list: an atomic only when this one is longer than the
-            // maximum seen so far (same-address atomics from every workgroup
-            // serialise; a stale read only costs one more atomic)
-            if (count > __hip_atomic_load(err + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                atomicMax(err + 1, count);
             if (count > kPairCap) atomicOr(err, 1);
         }
         return;
@@ -335,6 +330,23 @@ k_pairs(int64_t ne, const double *__restrict__ lo, const double *__restrict__ hi
     wave_bitonic_sort(buf, n2);
     const int64_t base = offsets[l];
     for (int i = lane_id(); i < count; i += kWave) m_out[base + i] = buf[i];
+}
+
+// err[1] = max counts[0..n) by one block, without atomics (a same-address atomic
+// from every workgroup of the count pass serialised it: 50 ms for 83k tets)
+__global__ void __launch_bounds__(1024) k_count_max(int64_t n, const int64_t *__restrict__ counts, int *err)
+{
+    __shared__ int64_t red[1024 / kWave];
+    int64_t v = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) v = counts[i] > v ? counts[i] : v;
+    v = wave_max(v);
+    if (lane_id() == 0) red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t m = 0;
+        for (int r = 0; r < 1024 / kWave; ++r) m = red[r] > m ? red[r] : m;
+        err[1] = static_cast<int>(m < INT_MAX ? m : INT_MAX);
+    }
 }
 
 }  // namespace
@@ -406,6 +418,8 @@ void build_pairs(System &s, hipStream_t st)
         NLQ_CHECK_LAUNCH();
     };
     launch(nullptr, 0);
+    hipLaunchKernelGGL(k_count_max, dim3(1), dim3(1024), 0, st, ne, counts.as<int64_t>(), err.as<int>());
+    NLQ_CHECK_LAUNCH();
     int herr[2] = {0, 0};
     NLQ_HIP(hipMemcpyAsync(herr, err.as<void>(), 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     exclusive_scan_i64(s.ctx, counts.as<int64_t>(), s.pair_off.as<int64_t>(), ne + 1, st);
