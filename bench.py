@@ -209,8 +209,8 @@ def main():
     ap.add_argument("--no-ablation", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("this build runs on one GPU only: the path has no cross-GPU sharding "
-              "(see the design notes); run with --gpus 1", file=sys.stderr)
+        print("this benchmark runs on one GPU only (the path has no cross-GPU sharding); "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     progress("importing torch")
     import torch
