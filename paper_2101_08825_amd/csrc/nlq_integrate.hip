@@ -226,28 +226,58 @@ template <int DIM> struct Simplex {
     double v[DIM + 1][DIM];
 };
 
+// Child c of a tetrahedron by the midpoint rule: child vertex v is (V_i + V_j)
+// * 0.5, rounded as written, for the pair (i, j) of the child table (i == j: the
+// vertex itself, exactly, as (x + x) * 0.5 = x).  The two parent vertices are
+// picked by selects on i and j, unpacked two bits per child from constants, so
+// only the parent and the child are live (forming all ten points first held
+// sixty more registers).
+__device__ __forceinline__ Simplex<3> tet_child_of(const Simplex<3> &S, int c)
+{
+    Simplex<3> out;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        unsigned pi = 0, pj = 0;
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+            pi |= static_cast<unsigned>(child_src(3, cc, v) >> 4) << (2 * cc);
+            pj |= static_cast<unsigned>(child_src(3, cc, v) & 15) << (2 * cc);
+        }
+        const int i = static_cast<int>((pi >> (2 * c)) & 3u), j = static_cast<int>((pj >> (2 * c)) & 3u);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double x = i == 0 ? S.v[0][k] : (i == 1 ? S.v[1][k] : (i == 2 ? S.v[2][k] : S.v[3][k]));
+            const double y = j == 0 ? S.v[0][k] : (j == 1 ? S.v[1][k] : (j == 2 ? S.v[2][k] : S.v[3][k]));
+            out.v[v][k] = __dmul_rn(__dadd_rn(x, y), 0.5);
+        }
+    }
+    return out;
+}
+
 // child `c` of S by the midpoint rule, (V_i + V_j) * 0.5 rounded as written.
-// Every edge midpoint is formed once; the child's vertices are then chosen by
-// select chains on c, so all table indices are compile-time constants and the
-// simplex stays in registers.
+// Triangles: every edge midpoint is formed once and the child's vertices are
+// chosen by select chains on c, so all table indices are compile-time
+// constants and the simplex stays in registers.
 template <int DIM>
 __device__ __forceinline__ Simplex<DIM> child_of(const Simplex<DIM> &S, int c)
 {
-    constexpr int NV = DIM + 1, NCH = 1 << DIM;
-    double M[NV][NV][DIM];
+    if constexpr (DIM == 3) {
+        return tet_child_of(S, c);
+    } else {
+        constexpr int NV = DIM + 1;
+        double M[NV][NV][DIM];
 #pragma unroll
-    for (int i = 0; i < NV; ++i)
+        for (int i = 0; i < NV; ++i)
 #pragma unroll
-        for (int j = 0; j < NV; ++j)
+            for (int j = 0; j < NV; ++j)
 #pragma unroll
-            for (int k = 0; k < DIM; ++k)
-                M[i][j][k] = (i == j) ? S.v[i][k]
-                                      : (i < j ? __dmul_rn(__dadd_rn(S.v[i][k], S.v[j][k]), 0.5) : 0.0);
-    Simplex<DIM> out;
-    if constexpr (DIM == 2) {
+                for (int k = 0; k < DIM; ++k)
+                    M[i][j][k] = (i == j) ? S.v[i][k]
+                                          : (i < j ? __dmul_rn(__dadd_rn(S.v[i][k], S.v[j][k]), 0.5) : 0.0);
         // the triangle table (corner children, then the middle one) as two-bit
         // select trees with its repeated entries merged: 7 selects per
         // coordinate instead of 9
+        Simplex<DIM> out;
         const bool b0 = (c & 1) != 0, b1 = (c & 2) != 0;
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -257,17 +287,6 @@ __device__ __forceinline__ Simplex<DIM> child_of(const Simplex<DIM> &S, int c)
         }
         return out;
     }
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-            double r = M[child_src(DIM, 0, v) >> 4][child_src(DIM, 0, v) & 15][k];
-#pragma unroll
-            for (int cc = 1; cc < NCH; ++cc)
-                r = (c == cc) ? M[child_src(DIM, cc, v) >> 4][child_src(DIM, cc, v) & 15][k] : r;
-            out.v[v][k] = r;
-        }
-    return out;
 }
 
 // first index of level lev in the sub-element tables (level 1 = the element at
