@@ -207,7 +207,7 @@ nlq_status nlq_assemble_info_get(const nlq_system *sys, nlq_assemble_info *info)
  * L_max, size class of max |J_l|), including the serving loop's.  The system's
  * values are recomputed with it (nlq_set_data must be called again). */
 typedef struct {
-    int32_t occupancy_variant;      /* 0: default waves per SIMD; 1: one more (FP32 path) or one fewer (FP64 path) */
+    int32_t occupancy_variant;      /* 0: default waves per SIMD (2D 5, 3D FP32 4, 3D FP64 3); 1: one more (2D FP32) or one fewer (others) */
     int32_t workgroups_per_cu;      /* persistent workgroups per CU */
     int32_t pairs_per_item;         /* largest part of one J_l per work item */
     int32_t work_items_per_element; /* parts each outer element is cut into */

@@ -54,13 +54,15 @@ constexpr int kWaves = 4;
 constexpr int kThreads = kWaves * kWave;
 constexpr int kLeafCap = 128;
 constexpr int kBatch = 64;
-// waves per SIMD requested from the register allocator: variant 0 (the default)
-// and variant 1 -- one wave more for the FP32 path (fewer registers, more
-// latency hiding), one less for the FP64 path (more registers, fewer spills);
-// the autotuner picks per workload
+// waves per SIMD requested from the register allocator: variant 0 (the default:
+// 5 in 2D, 4 for the 3D FP32 path, 3 for the 3D FP64 path) and variant 1 -- one
+// wave more for the 2D FP32 path (fewer registers, more latency hiding), one
+// fewer for the others (more registers, fewer spills); the autotuner picks per
+// workload
 template <int DIM, int PREC, int OCC> constexpr int waves_per_eu()
 {
-    return (DIM == 2 ? 5 : 3) + (OCC ? (PREC == 1 ? 1 : -1) : 0);
+    constexpr int base = DIM == 2 ? 5 : (PREC == 1 ? 4 : 3);
+    return base + (OCC ? ((DIM == 2 && PREC == 1) ? 1 : -1) : 0);
 }
 
 template <int DIM> struct Shape {

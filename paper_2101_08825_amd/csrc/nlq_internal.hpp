@@ -108,7 +108,7 @@ struct Server;
 
 // Launch configuration of the integration kernel (chosen by nlq_autotune).
 struct TuneConfig {
-    int occ = 0;               // register budget: 0 = default, 1 = one wave more (FP32) / fewer (FP64)
+    int occ = 0;               // register budget: 0 = default, 1 = one wave more (2D FP32) / fewer (others)
     int wg_per_cu = 0;         // persistent workgroups per CU (0 = as many as fit)
     int pairs_per_item = 512;  // largest part of one J_l handled as one work item
 };
