@@ -209,7 +209,7 @@ nlq_status nlq_assemble_info_get(const nlq_system *sys, nlq_assemble_info *info)
 typedef struct {
     int32_t occupancy_variant;      /* 0: default waves per SIMD (2D 5, 3D FP32 4, 3D FP64 3); 1: one more (2D FP32) or one fewer (others) */
     int32_t workgroups_per_cu;      /* persistent workgroups per CU */
-    int32_t pairs_per_item;         /* largest part of one J_l per work item */
+    int32_t pairs_per_item;         /* largest part of one J_l per work item (untuned: 512 in 2D, 256 in 3D) */
     int32_t work_items_per_element; /* parts each outer element is cut into */
     int32_t candidates;             /* configurations timed */
     double best_ms, default_ms;     /* sample launch time: chosen and default configuration */

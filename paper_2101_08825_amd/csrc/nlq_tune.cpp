@@ -17,11 +17,25 @@ TuneKey tune_key(const System &s)
     return TuneKey(s.mesh->dim, s.p.precision, s.p.kernel, s.p.lmax, lg);
 }
 
+namespace {
+
+// the untuned configuration: 3D pair lists are cut into parts of 256 pairs (the
+// autotuner's choice on every 3D case measured; finer work items balance the
+// longer per-pair work of tetrahedra), 2D ones into parts of 512
+TuneConfig default_config(const System &s)
+{
+    TuneConfig c{};
+    if (s.mesh->dim == 3) c.pairs_per_item = 256;
+    return c;
+}
+
+}  // namespace
+
 TuneConfig tuned_config(Ctx &ctx, const System &s)
 {
     std::lock_guard<std::mutex> g(ctx.tune_mu);
     auto it = ctx.tuned.find(tune_key(s));
-    return it != ctx.tuned.end() ? it->second : TuneConfig{};
+    return it != ctx.tuned.end() ? it->second : default_config(s);
 }
 
 namespace {
@@ -44,7 +58,7 @@ int autotune(System &s, hipStream_t st, double budget_s, double *best_ms, double
 {
     Ctx &ctx = *s.ctx;
     const int64_t ne = s.mesh->n_elems;
-    const TuneConfig base{};
+    const TuneConfig base = default_config(s);
     *best_ms = *default_ms = 0.0;
     if (s.p.deterministic) return 0;   // sample ranges are not integrated on their own in this mode
     // candidates: the default first, then the register variant, one workgroup
@@ -63,7 +77,7 @@ int autotune(System &s, hipStream_t st, double budget_s, double *best_ms, double
                     if (per_cu < 2) continue;
                     c.wg_per_cu = static_cast<int>(per_cu - 1);
                 }
-                if (occ == 0 && !less && ppi == 512) continue;   // the default
+                if (occ == 0 && !less && ppi == base.pairs_per_item) continue;   // the default
                 cand.push_back(c);
             }
     // a sample in the middle of the mesh (away from the first and last element,
