@@ -750,21 +750,26 @@ struct RowCache {
     int64_t len[4];
 };
 
-// position of column c in cached row r, or -1
+// position of column c in cached row r, or -1 (a cached row holds at most
+// rowcap < 2^16 entries, so the lower-bound search runs in 32-bit arithmetic)
 __device__ __forceinline__ int64_t row_find(const RowCache *rc, int r, int32_t c)
 {
     const uint16_t *q = rc->c16[r];
     if (!q) return search(rc->cols[r], rc->len[r], c);
     const int32_t d = c - rc->first[r];
     if (d < 0 || d > 65535) return -1;
-    int64_t a = 0, b = rc->len[r] - 1;
-    while (a <= b) {
-        const int64_t mid = (a + b) >> 1;
-        const int32_t v = q[mid];
-        if (v == d) return mid;
-        if (v < d) a = mid + 1; else b = mid - 1;
+    const int len = static_cast<int>(rc->len[r]);
+    int lo = 0, n = len;
+    while (n > 0) {
+        const int half = n >> 1;
+        if (static_cast<int32_t>(q[lo + half]) < d) {
+            lo += half + 1;
+            n -= half + 1;
+        } else {
+            n = half;
+        }
     }
-    return -1;
+    return lo < len && static_cast<int32_t>(q[lo]) == d ? lo : -1;
 }
 
 template <int DIM, class Real> struct Edges {
