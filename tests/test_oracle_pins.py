@@ -420,45 +420,56 @@ def test_two_term_form_vs_four_term(oracle_lib):
     assert 1e-3 > dist[1] > dist[2] > dist[3] > 1e-14
 
 
-def _uniform_outer_matrix(mesh, delta, eps, C, depth, bary, w):
-    """Every element as outer element, uniformly subdivided `depth` times (no
-    bbox pruning); every other element as inner element with the Gauss rule on
-    the whole element; four-term integrand.  numpy, independent of the oracle."""
-    dim = mesh.dim
+def _kids(V, dim):
+    """Midpoint children of a simplex (rows = vertices): triangles 4 children,
+    tetrahedra 8 (corner tets, octahedron cut along m02-m13)."""
     nv = dim + 1
+    pts = list(V)
+    for i in range(nv):
+        for j in range(i + 1, nv):
+            pts.append((V[i] + V[j]) / 2)
+    P = np.array(pts)
+    if dim == 2:
+        T = [[0, 3, 4], [3, 1, 5], [4, 5, 2], [3, 4, 5]]
+    else:
+        T = [[0, 4, 5, 6], [4, 1, 7, 8], [5, 7, 2, 9], [6, 8, 9, 3], [4, 5, 6, 8],
+             [4, 5, 7, 8], [5, 6, 8, 9], [5, 7, 8, 9]]
+    return [P[t] for t in T]
 
-    def kids(V):
-        pts = list(V)
-        for i in range(nv):
-            for j in range(i + 1, nv):
-                pts.append((V[i] + V[j]) / 2)
-        P = np.array(pts)
-        if dim == 2:
-            T = [[0, 3, 4], [3, 1, 5], [4, 5, 2], [3, 4, 5]]
-        else:
-            T = [[0, 4, 5, 6], [4, 1, 7, 8], [5, 7, 2, 9], [6, 8, 9, 3], [4, 5, 6, 8],
-                 [4, 5, 7, 8], [5, 6, 8, 9], [5, 7, 8, 9]]
-        return [P[t] for t in T]
 
-    subs = [np.eye(nv)]
+def _composite_rule(dim, depth, bary, w):
+    """The element rule repeated on every sub-simplex of `depth` uniform midpoint
+    refinements: barycentric points and weights (summing to 1)."""
+    subs = [np.eye(dim + 1)]
     for _ in range(depth):
-        subs = [c for s in subs for c in kids(s)]
-    lx = np.concatenate([bary @ s for s in subs])      # outer barycentrics
-    wx = np.tile(w, len(subs)) / len(subs)
-    ly, wy = bary, w
-    nn = mesh.n_nodes
-    A = np.zeros((nn, nn))
+        subs = [c for s in subs for c in _kids(s, dim)]
+    return np.concatenate([bary @ s for s in subs]), np.tile(w, len(subs)) / len(subs)
+
+
+def _numpy_mu(d, delta, eps):
+    r = np.clip((delta - d) / eps, -1.0, 1.0)
+    return (128 + 315 * r - 420 * r ** 3 + 378 * r ** 5 - 180 * r ** 7 + 35 * r ** 9) / 256
+
+
+def _brute_matrix(mesh, delta, eps, C, dx, dy, bary, w, eta=None):
+    """Four-term integrand of eq. (Aij-support2) over every ordered element pair,
+    the outer element split uniformly dx times and the inner one dy times, the
+    element rule on every piece; no bbox pruning and no adaptivity.  numpy,
+    independent of the oracle."""
+    dim = mesh.dim
+    lx, wx = _composite_rule(dim, dx, bary, w)
+    ly, wy = _composite_rule(dim, dy, bary, w)
     V = mesh.coords[mesh.conn]
     X = np.einsum("qv,evd->eqd", lx, V)
     Y = np.einsum("qv,evd->eqd", ly, V)
     meas = np.array([_measure(v) for v in V])
+    nn = mesh.n_nodes
+    A = np.zeros((nn, nn))
     for l in range(mesh.n_elems):
         for mm in range(mesh.n_elems):
-            d = np.linalg.norm(X[l][:, None, :] - Y[mm][None, :, :], axis=2)
-            r = (delta - d) / eps
-            xi = (128 + 315 * r - 420 * r ** 3 + 378 * r ** 5 - 180 * r ** 7 + 35 * r ** 9) / 256
-            mu = np.where(d < delta - eps, 1.0, np.where(d > delta + eps, 0.0, xi))
-            G = C * mu * np.outer(wx * meas[l], wy * meas[mm])
+            d = np.sqrt(((X[l][:, None, :] - Y[mm][None, :, :]) ** 2).sum(-1))
+            g = _numpy_mu(d, delta, eps) * (1.0 if eta is None else eta(d))
+            G = C * g * np.outer(wx * meas[l], wy * meas[mm])
             il, im = mesh.conn[l], mesh.conn[mm]
             A[np.ix_(il, il)] += lx.T @ (G.sum(1)[:, None] * lx)
             A[np.ix_(im, im)] += ly.T @ (G.sum(0)[:, None] * ly)
@@ -466,6 +477,15 @@ def _uniform_outer_matrix(mesh, delta, eps, C, depth, bary, w):
             A[np.ix_(il, im)] += Blm
             A[np.ix_(im, il)] += Blm.T
     return A
+
+
+def _uniform_outer_matrix(mesh, delta, eps, C, depth, bary, w, eta=None):
+    """Every element as outer element, uniformly subdivided `depth` times (no
+    bbox pruning); every other element as inner element with the Gauss rule on
+    the whole element; four-term integrand.  numpy, independent of the oracle."""
+    return _brute_matrix(mesh, delta, eps, C, depth, 0, bary, w, eta)
+
+
 
 
 @pytest.mark.parametrize("dim,n,kd,q,lmax", [(2, 4, 2, 4, 4), (2, 5, 2, 16, 3), (3, 2, 2, 4, 2)])
@@ -490,6 +510,149 @@ def test_algorithm1_equals_uniform_outer_refinement(oracle_lib, dim, n, kd, q, l
     # and a coarser L_max is visibly different (the band is not resolved)
     A2 = _dense(*_assemble(O, mesh, O.params(delta, eps, 1))[3:6], mesh.n_nodes)
     assert np.linalg.norm(A2 - Au) > 1e-6 * np.linalg.norm(Au)
+
+
+@pytest.mark.parametrize("dim,n,kd,q,lmin,lmax", [(2, 4, 2, 4, 2, 4), (2, 4, 2, 4, 3, 4), (3, 2, 2, 4, 2, 3)])
+def test_algorithm1_lmin_equals_uniform_outer_refinement(oracle_lib, dim, n, kd, q, lmin, lmax):
+    """Algorithm 1 with L_min > 1: every sub-element above level L_min is split
+    with the whole J (nothing is integrated or dropped there), below it the
+    adaptive classification runs as with L_min = 1.  With eta = 1 every settled
+    piece has constant or zero gamma, so the matrix again equals uniform outer
+    refinement to level L_max, and no leaf lies above level L_min."""
+    O = oracle_lib
+    mesh = W.kuhn_mesh(dim, n, 0)
+    delta = kd / n + 0.37 / n
+    eps = delta / q
+    C = O.kernel_constant(dim, 0, delta, eps)
+    bary, w = O.rule(dim)
+    Au = _uniform_outer_matrix(mesh, delta, eps, C, lmax - 1, bary, w)
+    m, off, pm, rp, col, val, leaves, evals = _assemble(O, mesh, O.params(delta, eps, lmax, lmin=lmin))
+    assert leaves[1:lmin].sum() == 0
+    assert leaves[lmin:lmax].sum() > 0   # settled before L_max below L_min
+    A = _dense(rp, col, val, mesh.n_nodes)
+    assert np.linalg.norm(A - Au) <= 1e-13 * np.linalg.norm(Au)
+    # L_min = L_max: Algorithm 1 is plain uniform refinement, every pair at L_max
+    m, off, pm, rp, col, val, leaves, evals = _assemble(O, mesh, O.params(delta, eps, lmax, lmin=lmax))
+    assert leaves[lmax] == off[-1] * (1 << dim) ** (lmax - 1) and leaves[:lmax].sum() == 0
+    assert np.linalg.norm(_dense(rp, col, val, mesh.n_nodes) - Au) <= 1e-13 * np.linalg.norm(Au)
+
+
+@pytest.mark.parametrize("dim,n,dh,q,lmin,lmax,pruned",
+                         [(2, 4, 0.6, 4, 1, 4, True), (2, 4, 2.37, 4, 3, 3, False), (3, 2, 0.8, 4, 1, 3, False)])
+def test_algorithm1_gauss_equals_uniform_outer_refinement(oracle_lib, dim, n, dh, q, lmin, lmax, pruned):
+    """Truncated Gaussian kernel eta = exp(-d^2/delta^2), the integrand as the
+    oracle's integration() forms it for any eta.  Algorithm 1 integrates a piece
+    before L_max only when aprx max < delta - eps; for a Kuhn inner element every
+    per-axis term max(d1^2, d2^2) of eq. (maxdist) is at least (h/2)^2, so with
+    delta - eps < sqrt(N) h / 2 no piece is integrated early, and with
+    L_min = L_max none can be.  Dropped pieces contribute exact zeros, so in both
+    cases the matrix equals uniform outer refinement with numpy's exp(-d^2/delta^2)
+    to round-off: a wrong argument of eta (d^2 for d, a missing square, delta
+    for delta^2) fails it."""
+    O = oracle_lib
+    mesh = W.kuhn_mesh(dim, n, 0)
+    h = 1.0 / n
+    delta = dh * h
+    eps = delta / q
+    C = O.kernel_constant(dim, 1, delta, eps)
+    bary, w = O.rule(dim)
+    eta = lambda d: np.exp(-d * d / delta ** 2)
+    Au = _uniform_outer_matrix(mesh, delta, eps, C, lmax - 1, bary, w, eta)
+    m, off, pm, rp, col, val, leaves, evals = _assemble(
+        O, mesh, O.params(delta, eps, lmax, lmin=lmin, kernel=1))
+    assert leaves[:lmax].sum() == 0
+    if lmin < lmax:
+        assert delta - eps < math.sqrt(dim) * h / 2
+    uniform = off[-1] * (1 << dim) ** (lmax - 1)
+    # pieces were dropped (2D 4^2: fewer leaves than uniform refinement); on the
+    # 3D 2^3 mesh every sub-element stays within delta + eps of every element
+    assert (leaves[lmax] < uniform) if pruned else (leaves[lmax] == uniform)
+    A = _dense(rp, col, val, mesh.n_nodes)
+    assert np.linalg.norm(A - Au) <= 1e-13 * np.linalg.norm(Au)
+    # eta is not constant over these distances: the constant kernel differs
+    A0 = _uniform_outer_matrix(mesh, delta, eps, C, lmax - 1, bary, w)
+    assert np.linalg.norm(A0 - Au) > 0.05 * np.linalg.norm(Au)
+
+
+# (dim, [(cells per direction, the two refinement depths of the brute force)], L_max)
+_BRUTE_CASES = [(2, [(2, (2, 3)), (4, (1, 2))], 5), (3, [(1, (1, 2)), (2, (0, 1))], 4)]
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("dim,meshes,lmax", _BRUTE_CASES)
+def test_brute_force_double_subdivision(oracle_lib, dim, meshes, lmax, kernel):
+    """Tiny meshes against brute force: both the outer and the inner element are
+    split uniformly D times with the element rule on every piece (no pruning, no
+    adaptivity); two depths give a Richardson estimate of the exact double
+    integrals (a degree-5 rule on a smooth integrand: error ~ 2^{-6D}).  Section 6
+    ("sources of numerical error") splits the oracle's error into the mollifier
+    part and the integration error E_i, which vanishes as h -> 0 or L_max grows.
+    With eps = delta/2 (mollifier smooth at the element scale) and a high L_max:
+      * the oracle's matrix equals the brute force with the outer element split
+        deeply and the inner element whole (its outer rule has converged);
+      * its distance to the exact integrals (the inner rule's E_i) is small and
+        shrinks by more than 8x when h halves at fixed delta, eps.
+    Both kernels: with the Gaussian, pieces integrated before L_max are present
+    (aprx max < delta - eps at level 4 of the finer 2D mesh)."""
+    O = oracle_lib
+    delta = 1.0 if dim == 3 else 0.5
+    eps = delta / 2
+    C = O.kernel_constant(dim, kernel, delta, eps)
+    eta = None if kernel == 0 else (lambda d: np.exp(-d * d / delta ** 2))
+    bary, w = O.rule(dim)
+    errs = []
+    for n, (d0, d1) in meshes:
+        mesh = W.kuhn_mesh(dim, n, 0)
+        A0 = _brute_matrix(mesh, delta, eps, C, d0, d0, bary, w, eta)
+        A1 = _brute_matrix(mesh, delta, eps, C, d1, d1, bary, w, eta)
+        exact = A1 + (A1 - A0) / 63.0
+        nrm = np.linalg.norm(exact)
+        rich = np.linalg.norm(A1 - A0) / 63.0 / nrm
+        m, off, pm, rp, col, val, leaves, evals = _assemble(
+            O, mesh, O.params(delta, eps, lmax, kernel=kernel))
+        A = _dense(rp, col, val, mesh.n_nodes)
+        err = np.linalg.norm(A - exact) / nrm
+        outer = _brute_matrix(mesh, delta, eps, C, d1, 0, bary, w, eta)
+        e_outer = np.linalg.norm(A - outer) / nrm
+        print(f"  dim {dim} n {n} kernel {kernel}: Richardson {rich:.1e}, |A - A_exact| {err:.2e}, "
+              f"|A - A_outer-split| {e_outer:.1e}, early leaves {int(leaves[1:lmax].sum())}")
+        assert rich <= 5e-6            # the brute force has converged
+        assert e_outer <= 2e-6         # the oracle's outer rule has converged
+        assert 10 * rich < err <= 5e-3  # what is left is the inner rule's E_i
+        errs.append(err)
+    assert errs[1] * 8 < errs[0]
+
+
+def test_eps_convergence_rate(oracle_lib):
+    """Section 6, eps-convergence (Table tab_eps_conv): with the integration error
+    made negligible (L_max raised until the solution no longer moves), the
+    mollified solution converges at p_2 ~ 2 as eps halves, i.e.
+    |u_eps - u_{eps/2}| shrinks about 4x.  u = x^4 + y^4 with the forcing term
+    of the unmollified kernel (f = -(12(x^2 + y^2) + 2 delta^2), reading R13);
+    P1 on a Kuhn 8^2 mesh, delta = 2h, the constrained layer covering delta + eps.
+    With the argument of xi as printed, or a constant that does not fix the
+    second moment, the rate drops to ~2."""
+    O = oracle_lib
+    n, kd = 8, 2
+    mesh = W.kuhn_mesh(2, n, kd + 1)
+    delta = kd / n
+    x = mesh.coords
+    u = x[:, 0] ** 4 + x[:, 1] ** 4
+    f = -(12.0 * (x[:, 0] ** 2 + x[:, 1] ** 2) + 2.0 * delta ** 2)
+    arrays = (mesh.coords, mesh.conn, mesh.constrained)
+    for kernel in (0, 1):
+        sol = {}
+        for q in (2, 4, 8, 16):
+            sol[q] = O.solve_problem(arrays, O.params(delta, delta / q, 5, kernel=kernel), f, u).u
+        d = [np.linalg.norm(sol[q] - sol[2 * q]) for q in (2, 4, 8)]
+        ratios = [d[0] / d[1], d[1] / d[2]]
+        # the integration error at the smallest eps is negligible next to d
+        u4 = O.solve_problem(arrays, O.params(delta, delta / 16, 4, kernel=kernel), f, u).u
+        print(f"  kernel {kernel}: |u_eps - u_eps/2| = {['%.3e' % v for v in d]}, ratios "
+              f"{['%.2f' % r for r in ratios]}, L_max 4 -> 5 at eps = delta/16: "
+              f"{np.linalg.norm(u4 - sol[16]):.1e}")
+        assert np.linalg.norm(u4 - sol[16]) < 0.02 * d[2]
+        assert all(3.6 < r < 4.6 for r in ratios), ratios
 
 
 def test_per_pair_equals_per_element_recursion(oracle_lib):
