@@ -74,6 +74,10 @@ def lib():
         L.or_pair_block.argtypes = [vp, vp, i64, i64, vp, vp, vp]
         L.or_assemble.restype = i32
         L.or_assemble.argtypes = [vp, vp, i32, vp, vp, i64, vp, vp, vp, vp, vp, vp]
+        L.or_leaf_counts.restype = None
+        L.or_leaf_counts.argtypes = [vp, vp, i32, i64, vp, vp]
+        L.or_outer_blocks.restype = d
+        L.or_outer_blocks.argtypes = [vp, vp, i32, i64, vp, vp, vp]
         L.or_rows.restype = i64
         L.or_rows.argtypes = [vp, vp, d, i32, i64, vp, vp, vp, vp]
         L.or_load.restype = None
@@ -204,6 +208,27 @@ def assemble(mesh: OracleMesh, prm, off, pm, row_ptr, col, sel=None, nthreads=No
     if st != 0:
         raise RuntimeError("oracle assembly: entry outside the pattern")
     return val, leaves, evals
+
+
+def leaf_counts(mesh: OracleMesh, prm, outer, nthreads=None):
+    """Leaf integrations per level (index = level) of Algorithm 1 for the outer
+    elements `outer`, counted without evaluating them."""
+    nt = nthreads or default_threads()
+    sel = np.ascontiguousarray(outer, dtype=np.int64)
+    leaves = np.zeros(16, dtype=np.int64)
+    lib().or_leaf_counts(mesh.ref, C.byref(prm), nt, sel.shape[0], _p(sel), _p(leaves))
+    return leaves
+
+
+def outer_blocks(mesh: OracleMesh, prm, outer, nthreads=None):
+    """Algorithm 1 with evaluation for the outer elements `outer` (each with its
+    brute-force J_l), blocks discarded; returns (leaves, evals, checksum)."""
+    nt = nthreads or default_threads()
+    sel = np.ascontiguousarray(outer, dtype=np.int64)
+    leaves = np.zeros(16, dtype=np.int64)
+    evals = np.zeros(2, dtype=np.int64)
+    cs = lib().or_outer_blocks(mesh.ref, C.byref(prm), nt, sel.shape[0], _p(sel), _p(leaves), _p(evals))
+    return leaves, evals, cs
 
 
 def rows(mesh: OracleMesh, prm, thr, row_ids, values=True, nthreads=None):

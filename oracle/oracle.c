@@ -555,6 +555,7 @@ typedef struct {
                             those of the inner quadrature points; else jlo, jhi) */
     int64_t *leaves;     /* per level */
     int64_t evals[2];    /* all kernel evaluations, evaluations inside the band */
+    int count_only;      /* 1: Integration() only counts its (sub-element, m) leaves */
 } alg_ctx;
 
 static int ext(int nv) { return 2 * nv; }
@@ -570,6 +571,10 @@ static int ext(int nv) { return 2 * nv; }
 static void integration(alg_ctx *c, int level, const double *V, const double *Lam,
                         const int *Jpos, int nJ)
 {
+    if (c->count_only) {
+        c->leaves[level] += nJ;
+        return;
+    }
     int dim = c->dim, nv = c->nv, nq = c->nq, ne2 = ext(nv);
     double ws = ldexp(c->meas_l, -dim * (level - 1));
     double x[MAXQ][3], lam[MAXQ][MAXV];
@@ -872,6 +877,101 @@ int32_t or_assemble(const or_mesh *m, const or_params *p, int32_t nthreads,
     }
     free(jobs);
     return status;
+}
+
+/* ------------------------------------------------------------ leaf counts */
+
+typedef struct {
+    const or_mesh *m;
+    const or_params *p;
+    const double *lo, *hi;
+    const int64_t *sel;
+    int64_t i0, i1;
+    int evaluate;        /* 1: Integration() evaluated, 0: leaves counted only */
+    int64_t leaves[16];
+    int64_t evals[2];
+    double checksum;     /* sum of the blocks' entries (keeps the work observable) */
+} count_job;
+
+static void *count_worker(void *arg)
+{
+    count_job *j = (count_job *)arg;
+    const or_mesh *m = j->m;
+    int ne2 = 2 * (m->dim + 1);
+    alg_ctx c;
+    ctx_init(&c, m, j->p, j->leaves);
+    c.count_only = !j->evaluate;
+    int32_t *J = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m->n_elems + 1));
+    for (int64_t t = j->i0; t < j->i1; ++t) {
+        int64_t l = j->sel[t];
+        int64_t n = pairs_one(m, j->lo, j->hi, j->p->delta + j->p->eps, l, J);
+        double *E = (double *)malloc(sizeof(double) * (size_t)(n + 1) * ne2 * ne2);
+        run_outer(&c, l, J, (int)n, E);
+        if (j->evaluate)
+            for (int64_t k = 0; k < n * ne2 * ne2; ++k) j->checksum += E[k];
+        free(E);
+    }
+    j->evals[0] = c.evals[0];
+    j->evals[1] = c.evals[1];
+    free(J);
+    return NULL;
+}
+
+/* Algorithm 1 for the outer elements sel[0..n_sel), each with its brute-force
+ * J_l, in nthreads threads: leaves per level (and evaluations) summed.  With
+ * evaluate == 0 the leaves are counted without evaluating them (the counts a
+ * full assembly of those elements gives, at the cost of the traversal alone). */
+static double outer_runs(const or_mesh *m, const or_params *p, int32_t nthreads, int64_t n_sel,
+                         const int64_t *sel, int evaluate, int64_t *leaves, int64_t *evals)
+{
+    int64_t ne = m->n_elems;
+    double *lo = (double *)malloc(sizeof(double) * ne * m->dim);
+    double *hi = (double *)malloc(sizeof(double) * ne * m->dim);
+    all_bboxes(m, lo, hi);
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 64) nthreads = 64;
+    count_job *jobs = (count_job *)calloc(nthreads, sizeof(count_job));
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t].m = m;
+        jobs[t].p = p;
+        jobs[t].lo = lo;
+        jobs[t].hi = hi;
+        jobs[t].sel = sel;
+        jobs[t].i0 = n_sel * t / nthreads;
+        jobs[t].i1 = n_sel * (t + 1) / nthreads;
+        jobs[t].evaluate = evaluate;
+    }
+    run_threads(nthreads, count_worker, jobs, sizeof(count_job));
+    double checksum = 0.0;
+    for (int t = 0; t < nthreads; ++t) {
+        if (leaves)
+            for (int lv = 0; lv < 16; ++lv) leaves[lv] += jobs[t].leaves[lv];
+        if (evals) {
+            evals[0] += jobs[t].evals[0];
+            evals[1] += jobs[t].evals[1];
+        }
+        checksum += jobs[t].checksum;
+    }
+    free(jobs);
+    free(lo);
+    free(hi);
+    return checksum;
+}
+
+void or_leaf_counts(const or_mesh *m, const or_params *p, int32_t nthreads, int64_t n_sel,
+                    const int64_t *sel, int64_t *leaves)
+{
+    outer_runs(m, p, nthreads, n_sel, sel, 0, leaves, NULL);
+}
+
+/* Algorithm 1 with every Integration() evaluated for the outer elements
+ * sel[0..n_sel) (each with its brute-force J_l), blocks discarded: the oracle's
+ * assembly work without the global matrix (timed as the CPU baseline).
+ * Returns the sum of all block entries. */
+double or_outer_blocks(const or_mesh *m, const or_params *p, int32_t nthreads, int64_t n_sel,
+                       const int64_t *sel, int64_t *leaves, int64_t *evals)
+{
+    return outer_runs(m, p, nthreads, n_sel, sel, 1, leaves, evals);
 }
 
 /* ------------------------------------------------------------ sampled rows */

@@ -68,6 +68,10 @@ int32_t or_assemble(const or_mesh *m, const or_params *p, int32_t nthreads,
                     const int64_t *row_ptr, const int32_t *col, double *val,
                     int64_t *leaves, int64_t *evals);
 
+void or_leaf_counts(const or_mesh *m, const or_params *p, int32_t nthreads, int64_t n_sel,
+                    const int64_t *sel, int64_t *leaves);
+double or_outer_blocks(const or_mesh *m, const or_params *p, int32_t nthreads, int64_t n_sel,
+                       const int64_t *sel, int64_t *leaves, int64_t *evals);
 int64_t or_rows(const or_mesh *m, const or_params *p, double thr, int32_t nthreads,
                 int64_t n_rows, const int64_t *rows,
                 int64_t *row_len, int32_t *cols, double *vals);

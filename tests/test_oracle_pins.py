@@ -400,6 +400,48 @@ def test_c1_counts_and_invariants(oracle_lib):
     assert np.all(np.diag(A) > 0)
 
 
+# Leaf integrations of the benchmark configurations from the scope table's
+# independent count (a calculator of Algorithm 1 under the same readings on Kuhn
+# meshes, sharing nothing with this oracle): the oracle's traversal reproduces them.
+TABLE_LEAVES = {"c1_2d16": 446016, "c2a_2d128_d2h": 384255024, "c2b_2d128_d4h": 889535344,
+                "c3_3d24": 78429899232}
+
+
+@pytest.mark.parametrize("dim,n,kd,ed,lmax,lmin,kernel,min_l2", [
+    (2, 10, 2, 8, 4, 1, 0, 0), (2, 10, 3, 4, 4, 2, 1, 0), (2, 9, 2, 8, 3, 1, 0, 2),
+    (3, 4, 2, 8, 3, 1, 0, 0), (3, 4, 1, 4, 3, 2, 1, 1)])
+def test_leaf_counts_equal_assembly(oracle_lib, dim, n, kd, ed, lmax, lmin, kernel, min_l2):
+    """The count-only traversal (used for leaf parity at sizes too large to
+    assemble) gives the leaves per level of a full assembly."""
+    O = oracle_lib
+    mesh = W.kuhn_mesh(dim, n, kd)
+    delta = kd / n
+    prm = O.params(delta, delta / ed, lmax, lmin=lmin, kernel=kernel, min_l2=min_l2)
+    m, off, pm, rp, col, val, leaves, evals = _assemble(O, mesh, prm)
+    cnt = O.leaf_counts(m, prm, np.arange(mesh.n_elems))
+    assert list(cnt) == list(leaves)
+    sub = np.arange(1, mesh.n_elems, 3)
+    _, lv_sub, _ = O.assemble(m, prm, off, pm, rp, col, sel=sub)
+    assert list(O.leaf_counts(m, prm, sub)) == list(lv_sub)
+
+
+@pytest.mark.parametrize("name", ["c1_2d16", "c2a_2d128_d2h", "c2b_2d128_d4h", "c3_3d24"])
+def test_leaf_totals_match_table(oracle_lib, name):
+    """Whole-mesh leaf totals of the benchmark configurations equal the
+    independent count; for the 3D 24^3 problem the per-level counts stored in
+    tests/golden/c3_oracle.json (read by the GPU tests) are the oracle's."""
+    O = oracle_lib
+    wl = W.WORKLOADS[name]
+    mesh = wl.mesh()
+    m = O.OracleMesh(mesh.coords, mesh.conn)
+    prm = O.params(wl.delta, wl.eps, wl.lmax, kernel=wl.kernel)
+    cnt = O.leaf_counts(m, prm, np.arange(mesh.n_elems))
+    assert int(cnt.sum()) == TABLE_LEAVES[name]
+    if name == "c3_3d24":
+        gold = json.load(open(os.path.join(GOLD, "c3_oracle.json")))
+        assert gold["leaves_per_level"] == [int(x) for x in cnt[:wl.lmax + 1]]
+
+
 def test_two_term_form_vs_four_term(oracle_lib):
     """The Corollary's two-term form 2A21 + 2A22 has zero row sums.  It equals the
     four-term form exactly when the outer and inner rules coincide (L_max = 1:
