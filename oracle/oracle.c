@@ -40,14 +40,20 @@
 
 /* xi(r) = (128 + 315 r - 420 r^3 + 378 r^5 - 180 r^7 + 35 r^9) / 256,
  * Section 3, eq. (mollifier). */
+/* The same degree-9 polynomial as printed, (128 + 315 r - 420 r^3 + 378 r^5
+ * - 180 r^7 + 35 r^9) / 256, evaluated in factored form so that it keeps its
+ * relative accuracy where it is small: xi' = (315/256)(1 - r^2)^4 makes r = -1 a
+ * zero of order five, and with s = 1 - |r|
+ *   xi(-|r|) = s^5 (1008 - 1680 s + 1080 s^2 - 315 s^3 + 35 s^4) / 256,
+ *   xi(|r|)  = 1 - xi(-|r|)   (xi - 1/2 is odd).
+ * (Expanded, the printed form cancels to an absolute error of ~1e-16 near
+ * r = -1, where xi ~ (1 + r)^5.) */
 double or_xi(double r)
 {
-    double r2 = r * r;
-    double r3 = r2 * r;
-    double r5 = r3 * r2;
-    double r7 = r5 * r2;
-    double r9 = r7 * r2;
-    return (128.0 + 315.0 * r - 420.0 * r3 + 378.0 * r5 - 180.0 * r7 + 35.0 * r9) / 256.0;
+    double s = 1.0 - fabs(r);
+    double s5 = s * s * s * s * s;
+    double w = s5 * (1008.0 - 1680.0 * s + 1080.0 * s * s - 315.0 * s * s * s + 35.0 * s * s * s * s) / 256.0;
+    return r < 0.0 ? w : 1.0 - w;
 }
 
 /* mu_{delta,eps}(d): 1 below delta-eps, xi in the band (reading R1), 0 above

@@ -45,6 +45,54 @@ def test_xi_endpoints_and_derivative(oracle_lib):
         assert abs(np.polyval(dk, 1.0)) < 1e-8 and abs(np.polyval(dk, -1.0)) < 1e-8
 
 
+def test_xi_is_the_printed_polynomial_with_relative_accuracy(oracle_lib):
+    """The oracle evaluates Section 3's polynomial in factored form: expanded
+    with exact rationals, s^5 Q(s) (s = 1 - |r|) and 1 - s^5 Q(s) give the
+    printed coefficients on [-1, 0] and [0, 1]; evaluated, xi matches exact
+    rational evaluation of the printed form to 1e-15 RELATIVE, down to
+    xi ~ 1e-40 at the outer band edge."""
+    from fractions import Fraction as Fr
+    O = oracle_lib
+    printed = [Fr(128, 256), Fr(315, 256), 0, Fr(-420, 256), 0, Fr(378, 256), 0, Fr(-180, 256), 0,
+               Fr(35, 256)]
+    Q = [Fr(1008, 256), Fr(-1680, 256), Fr(1080, 256), Fr(-315, 256), Fr(35, 256)]
+
+    def mul(a, b):
+        out = [Fr(0)] * (len(a) + len(b) - 1)
+        for i, x in enumerate(a):
+            for j, y in enumerate(b):
+                out[i + j] += x * y
+        return out
+
+    def powp(a, k):
+        out = [Fr(1)]
+        for _ in range(k):
+            out = mul(out, a)
+        return out
+
+    def compose(q, inner):   # q(inner(r))
+        out = [Fr(0)]
+        for k, c in enumerate(q):
+            term = [c * x for x in powp(inner, k)]
+            out = [x + y for x, y in zip(out + [Fr(0)] * (len(term) - len(out)),
+                                         term + [Fr(0)] * (len(out) - len(term)))]
+        return out
+    s_neg = [Fr(1), Fr(1)]          # r <= 0: s = 1 + r
+    s_pos = [Fr(1), Fr(-1)]         # r >= 0: s = 1 - r
+    neg = mul(powp(s_neg, 5), compose(Q, s_neg))
+    pos = [-x for x in mul(powp(s_pos, 5), compose(Q, s_pos))]
+    pos[0] += 1
+    pad = lambda a: a + [Fr(0)] * (10 - len(a))
+    assert pad(neg) == pad(printed) and pad(pos) == pad(printed)
+
+    def exact(r):
+        rr = Fr(r)
+        return float(sum(c * rr ** k for k, c in enumerate(printed)))
+    for r in [-1 + 2.0 ** -k for k in range(1, 31)] + list(np.linspace(-0.999, 0.999, 37)):
+        e = exact(r)
+        assert abs(O.xi(r) - e) <= 1e-15 * abs(e), r
+
+
 def test_mu_band(oracle_lib):
     O = oracle_lib
     delta, eps = 0.125, 0.125 / 16
