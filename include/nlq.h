@@ -114,10 +114,13 @@ typedef struct {
 typedef struct {
     int64_t n_pairs;          /* ordered element pairs (l, m), m in J_l */
     int64_t n_leaf[9];        /* Integration(s, m) calls per level 1..8 (index = level) */
-    int64_t n_evals;          /* kernel evaluations gamma_eps(x_a, y_b) */
+    int64_t n_evals;          /* kernel evaluations gamma_eps(x_a, y_b) of those calls */
     int64_t nnz;
     double t_tables, t_pairs, t_pattern, t_integrate, t_total;  /* host wall clock */
     double t_kernel;          /* integration kernel alone, HIP events on its stream */
+    int64_t n_leaf_zero;      /* of the calls at L_max, those not evaluated: the box of the
+                                 sub-element lies at Euclidean distance >= delta + eps from
+                                 the box of m's quadrature points, so every term is zero */
 } nlq_assemble_info;
 
 typedef struct {
@@ -187,6 +190,15 @@ nlq_status nlq_prepare(nlq_ctx *ctx, const nlq_mesh *mesh, const nlq_params *par
  * matrix).  kernel_s: host [1] launch time from HIP events; n_leaf: host [9]
  * leaf integrations per level of this range (either may be NULL). */
 nlq_status nlq_integrate_range(nlq_system *sys, int64_t lo, int64_t hi, double *kernel_s, int64_t *n_leaf);
+/* As nlq_integrate_range for n_ranges (1..32) disjoint ranges lo[k] <= l < hi[k]
+ * (host arrays, each 0 < lo[k] < hi[k] < n_elems) in ONE launch: a sample of outer
+ * elements spread over the mesh, timed and counted together.  kernel_s: host [1]
+ * launch time; n_leaf: host [9] leaf integrations per level summed over the
+ * ranges; n_leaf_zero: host [1] those of them not evaluated (as in
+ * nlq_assemble_info).  Any output may be NULL.  EINVAL for a bad or overlapping
+ * range or a deterministic system. */
+nlq_status nlq_integrate_ranges(nlq_system *sys, int32_t n_ranges, const int64_t *lo, const int64_t *hi,
+                                double *kernel_s, int64_t *n_leaf, int64_t *n_leaf_zero);
 /* Assemble n systems (meshes[i], params[i]) as n calls of nlq_assemble would,
  * but with shared integration launches: the outer elements of every system of
  * one (dim, precision, kernel) group, up to 32 systems per launch, are
@@ -204,8 +216,9 @@ nlq_status nlq_assemble_info_get(const nlq_system *sys, nlq_assemble_info *info)
  * outer elements (about four work items per resident workgroup, middle of the
  * mesh) for about budget_s seconds (<= 0: 2); the fastest is kept in the
  * context for every later assembly with the same (dim, precision, kernel,
- * L_max, size class of max |J_l|), including the serving loop's.  The system's
- * values are recomputed with it (nlq_set_data must be called again). */
+ * L_max, size class of max |J_l|), including the serving loop's.  An assembled
+ * system's values are recomputed with it (nlq_set_data must be called again); a
+ * prepared one's (nlq_prepare) are set back to zero. */
 typedef struct {
     int32_t occupancy_variant;      /* 0: default waves per SIMD (2D 5, 3D FP32 4, 3D FP64 3); 1: one more (2D FP32) or one fewer (others) */
     int32_t workgroups_per_cu;      /* persistent workgroups per CU */

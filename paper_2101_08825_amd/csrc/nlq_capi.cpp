@@ -277,6 +277,16 @@ std::unique_ptr<nlq_system> prepare_system(Ctx &ctx, const Mesh &mesh, const nlq
     return sys;
 }
 
+void check_counter_error(int error)
+{
+    if (!error) return;
+    std::string msg;
+    if (error & kErrStack) msg += "refinement traversal exceeded its stack";
+    if (error & kErrPattern) msg += std::string(msg.empty() ? "" : "; ") + "a block entry fell outside the CSR pattern";
+    if (error & ~(kErrStack | kErrPattern)) msg += std::string(msg.empty() ? "" : "; ") + "unknown integration error";
+    fail(NLQ_EDEVICE, msg);
+}
+
 // counters of a finished integration -> info (synchronises st)
 void collect_counters(System &s, hipStream_t st)
 {
@@ -290,7 +300,8 @@ void collect_counters(System &s, hipStream_t st)
         leaves += s.info.n_leaf[q];
     }
     s.info.n_evals = leaves * nq * nq;
-    if (c.error) fail(NLQ_EDEVICE, "refinement traversal exceeded its stack");
+    s.info.n_leaf_zero = static_cast<int64_t>(c.zero_leaves);
+    check_counter_error(c.error);
     if (static_cast<int64_t>(c.pairs_done) != s.n_pairs)
         fail(NLQ_EDEVICE, "integration did not visit every pair");
 }
@@ -309,6 +320,7 @@ void run_integrate(System &s, hipStream_t st)
     s.info.t_kernel = 1e-3 * ms;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    s.integrated = true;
 }
 
 std::unique_ptr<nlq_mesh> make_box_mesh(Ctx &ctx, int dim, int n, int k_gamma, hipStream_t st)
@@ -558,22 +570,33 @@ nlq_status nlq_prepare(nlq_ctx *ctx, const nlq_mesh *mesh, const nlq_params *par
     });
 }
 
-nlq_status nlq_integrate_range(nlq_system *sys, int64_t lo, int64_t hi, double *kernel_s, int64_t *n_leaf)
+nlq_status nlq_integrate_ranges(nlq_system *sys, int32_t n_ranges, const int64_t *lo, const int64_t *hi,
+                                double *kernel_s, int64_t *n_leaf, int64_t *n_leaf_zero)
 {
     return guard([&] {
         if (!sys) fail(NLQ_EINVAL, "sys is NULL");
+        if (n_ranges < 1 || n_ranges > 32 || !lo || !hi) fail(NLQ_EINVAL, "need 1..32 ranges and both bound arrays");
         System &s = sys->impl;
         const int64_t ne = s.mesh->n_elems;
-        if (lo < 1 || hi >= ne || lo >= hi)
-            fail(NLQ_EINVAL, "need 0 < lo < hi < n_elems (a range that neither clears nor finishes the values)");
+        std::vector<std::pair<int64_t, int64_t>> r;
+        for (int k = 0; k < n_ranges; ++k) {
+            if (lo[k] < 1 || hi[k] >= ne || lo[k] >= hi[k])
+                fail(NLQ_EINVAL, "need 0 < lo < hi < n_elems (a range that neither clears nor finishes the values)");
+            r.emplace_back(lo[k], hi[k]);
+        }
+        std::sort(r.begin(), r.end());
+        for (size_t k = 1; k < r.size(); ++k)
+            if (r[k].first < r[k - 1].second) fail(NLQ_EINVAL, "ranges overlap");
         if (s.p.deterministic) fail(NLQ_EINVAL, "a deterministic system is integrated whole");
         NLQ_HIP(hipSetDevice(s.ctx->device));
         hipStream_t st = s.ctx->stream;
         hipEvent_t e0, e1;
         NLQ_HIP(hipEventCreate(&e0));
         NLQ_HIP(hipEventCreate(&e1));
+        std::vector<IntegrateJob> jobs;
+        for (const auto &q : r) jobs.push_back(IntegrateJob{&s, q.first, q.second});
         NLQ_HIP(hipMemsetAsync(s.counters.as<void>(), 0, sizeof(AsmCounters), st));
-        launch_integrate_jobs(s.ctx, s.launch, {IntegrateJob{&s, lo, hi}}, st, e0, e1);
+        launch_integrate_jobs(s.ctx, s.launch, jobs, st, e0, e1);
         AsmCounters c{};
         NLQ_HIP(hipMemcpyAsync(&c, s.counters.as<void>(), sizeof(AsmCounters), hipMemcpyDeviceToHost, st));
         NLQ_HIP(hipStreamSynchronize(st));
@@ -581,12 +604,18 @@ nlq_status nlq_integrate_range(nlq_system *sys, int64_t lo, int64_t hi, double *
         NLQ_HIP(hipEventElapsedTime(&ms, e0, e1));
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        if (c.error) fail(NLQ_EDEVICE, "refinement traversal exceeded its stack");
+        check_counter_error(c.error);
         if (kernel_s) *kernel_s = 1e-3 * ms;
         if (n_leaf)
             for (int q = 0; q < 9; ++q) n_leaf[q] = (q >= 1 && q <= 8) ? static_cast<int64_t>(c.leaf[q]) : 0;
+        if (n_leaf_zero) *n_leaf_zero = static_cast<int64_t>(c.zero_leaves);
         s.has_rhs = false;
     });
+}
+
+nlq_status nlq_integrate_range(nlq_system *sys, int64_t lo, int64_t hi, double *kernel_s, int64_t *n_leaf)
+{
+    return nlq_integrate_ranges(sys, 1, &lo, &hi, kernel_s, n_leaf, nullptr);
 }
 
 nlq_status nlq_assemble_batch(nlq_ctx *ctx, int32_t n, const nlq_mesh *const *meshes, const nlq_params *params,
@@ -881,7 +910,7 @@ nlq_status nlq_pair_blocks(nlq_system *sys, int64_t n, const int32_t *l, const i
         NLQ_HIP(hipMemcpyAsync(out, dout.as<void>(), sizeof(double) * n * blk, hipMemcpyDeviceToHost, st));
         NLQ_HIP(hipMemcpyAsync(&c, s.counters.as<void>(), sizeof(AsmCounters), hipMemcpyDeviceToHost, st));
         NLQ_HIP(hipStreamSynchronize(st));
-        if (c.error) fail(NLQ_EDEVICE, "refinement traversal exceeded its stack");
+        check_counter_error(c.error);
     });
 }
 

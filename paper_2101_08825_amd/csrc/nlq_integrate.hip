@@ -82,6 +82,8 @@ struct AsmArgs {
     const double *hi;
     const double *dlo;    // [dim][ne] boxes the refine test measures the gap to:
     const double *dhi;    // lo, hi, or the quadrature-point boxes (min_dist_l2 = 2)
+    const double *qlo;    // [dim][ne] boxes of the elements' quadrature points
+    const double *qhi;    // (the zero test of the children at L_max)
     const double *meas;
     const int32_t *conn;
     const int64_t *row_ptr;
@@ -151,29 +153,50 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 
 // -------------------------------------------------------------- mollifier
 
-// xi of Section 3, eq. (mollifier), Horner form in r^2:
-// xi(r) = 1/2 + r (315 - 420 r^2 + 378 r^4 - 180 r^6 + 35 r^8) / 256,
-// evaluated at r = (delta - d) / eps (1 at the inner band edge, 0 at the outer).
+// xi of Section 3, eq. (mollifier), the degree-9 polynomial
+// (128 + 315 r - 420 r^3 + 378 r^5 - 180 r^7 + 35 r^9) / 256 at r = (delta - d) / eps
+// (1 at the inner band edge, 0 at the outer), in the factored form that keeps its
+// relative accuracy where it is small (see xi32 below): with s = 1 - |r|,
+// xi(-|r|) = s^5 Q(s) and xi(|r|) = 1 - xi(-|r|).
 __device__ __forceinline__ double xi64(double r)
 {
-    const double s = r * r;
-    double p = 35.0 / 256.0;
-    p = fma(p, s, -180.0 / 256.0);
-    p = fma(p, s, 378.0 / 256.0);
-    p = fma(p, s, -420.0 / 256.0);
-    p = fma(p, s, 315.0 / 256.0);
-    return fma(p, r, 0.5);
+    const double a = fabs(r);
+    const double t = 0.5 - a;
+    const double sg = 1.0 - a;
+    double q = 35.0 / 256.0;
+    q = fma(q, t, -245.0 / 256.0);
+    q = fma(q, t, 660.0 / 256.0);
+    q = fma(q, t, -3275.0 / 1024.0);
+    q = fma(q, t, 6413.0 / 4096.0);
+    const double s2 = sg * sg;
+    const double w = (s2 * s2) * (sg * q);
+    return r < 0.0 ? w : 1.0 - w;
 }
 
+// xi in FP32 with relative accuracy where it is small.  xi' = (315/256)(1 - r^2)^4
+// has zeros of order four at r = -1 and r = 1, so xi has a zero of order five at
+// r = -1 and, with sigma = 1 - |r|,
+//   xi(-|r|) = sigma^5 Q(sigma),  Q(sigma) = (1008 - 1680 sigma + 1080 sigma^2
+//                                            - 315 sigma^3 + 35 sigma^4) / 256,
+// and xi(|r|) = 1 - xi(-|r|) (xi - 1/2 is odd).  Q is evaluated by Horner in
+// t = sigma - 1/2 = 1/2 - |r| (coefficients exact in FP32), which keeps its
+// cancellation small on [0, 1]: |error| <= 1.8e-7 everywhere and <= 5e-7
+// relative, down to xi = 0 at the outer band edge (the plain Horner form in r,
+// 1/2 + r p(r^2), carries an absolute error of ~1e-7 there, where xi ~ (1+r)^5).
+// At |r| = 1 sigma is 0, so the clamped plateau and outside give exactly 1 and 0.
 __device__ __forceinline__ float xi32(float r)
 {
-    const float s = r * r;
-    float p = 35.0f / 256.0f;
-    p = fmaf(p, s, -180.0f / 256.0f);
-    p = fmaf(p, s, 378.0f / 256.0f);
-    p = fmaf(p, s, -420.0f / 256.0f);
-    p = fmaf(p, s, 315.0f / 256.0f);
-    return fmaf(p, r, 0.5f);
+    const float a = fabsf(r);
+    const float t = 0.5f - a;
+    const float sg = 1.0f - a;
+    float q = 35.0f / 256.0f;
+    q = fmaf(q, t, -245.0f / 256.0f);
+    q = fmaf(q, t, 660.0f / 256.0f);
+    q = fmaf(q, t, -3275.0f / 1024.0f);
+    q = fmaf(q, t, 6413.0f / 4096.0f);
+    const float s2 = sg * sg;
+    const float w = (s2 * s2) * (sg * q);
+    return r < 0.0f ? w : 1.0f - w;
 }
 
 // gamma_eps / C at squared distance d2: eta * mu (FP64)
@@ -299,14 +322,61 @@ template <int DIM> __device__ __forceinline__ int level_offset(int lev)
     return ((1 << (DIM * (lev - 1))) - 1) / (NCH - 1);
 }
 
+// Children of a sub-element whose contributions are all exact zeros: bit c of
+// the result is set when child c's box lies at Euclidean distance >= delta + eps
+// from the box of the inner element's quadrature points (every point pair of
+// the child then lies beyond the kernel's support, so Integration(child, m) adds
+// zeros).  Only children at L_max are tested: Algorithm 1 integrates them all,
+// and skipping such a child changes no value.  Child vertices are the parent's
+// vertices and edge midpoints, (V_i + V_j) * 0.5 rounded as written; each
+// coordinate is formed once and every child box updated from it.
+template <int DIM>
+__device__ __forceinline__ uint32_t zero_children(CArgs &A, const Simplex<DIM> &S, const double *qlo,
+                                                  const double *qhi)
+{
+    constexpr int NV = DIM + 1, NCH = 1 << DIM;
+    double acc[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) acc[c] = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        double P[NV][NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+#pragma unroll
+            for (int j = i; j < NV; ++j)
+                P[i][j] = i == j ? S.v[i][k] : __dmul_rn(__dadd_rn(S.v[i][k], S.v[j][k]), 0.5);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            double lo = 0.0, hi = 0.0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const int src = child_src(DIM, c, v);
+                const double x = P[src >> 4][src & 15];
+                lo = v == 0 ? x : fmin(lo, x);
+                hi = v == 0 ? x : fmax(hi, x);
+            }
+            const double g = fmax(0.0, fmax(__dsub_rn(lo, qhi[k]), __dsub_rn(qlo[k], hi)));
+            acc[c] = __dadd_rn(acc[c], __dmul_rn(g, g));
+        }
+    }
+    uint32_t z = 0;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) z |= acc[c] >= A.dpe_sq ? (1u << c) : 0u;
+    return z;
+}
+
 // 0 = drop, 1 = integrate now (J^int), 2 = refine (J^ref): Algorithm 1.
 // The sub-element's vertices are formed by the midpoint recursion from the
 // root, or from its ancestor at level min(lev, memo_lev) whose vertices the
-// memo holds (formed by the same recursion; memo_lev < 2: no memo).
+// memo holds (formed by the same recursion; memo_lev < 2: no memo).  For a
+// refined sub-element one level above L_max, *zero receives the children whose
+// integrals are all zeros (zero_children); otherwise it is left alone.
 template <int DIM>
 __device__ __forceinline__ int classify(CArgs &A, const Simplex<DIM> root, const double *memo, int memo_lev,
                                         int lev, uint32_t local, const double *mlo, const double *mhi,
-                                        const double *dlo, const double *dhi)
+                                        const double *dlo, const double *dhi, const double *qlo,
+                                        const double *qhi, uint32_t *zero)
 {
     constexpr int NCH = 1 << DIM, NV = DIM + 1;
     Simplex<DIM> S = root;
@@ -338,8 +408,10 @@ __device__ __forceinline__ int classify(CArgs &A, const Simplex<DIM> root, const
         shi[k] = b;
     }
     if (aprx_max_sq<DIM>(slo, shi, mlo, mhi) < A.dme_sq) return 1;
-    if (A.min_l2 ? box_gap_sq<DIM>(slo, shi, dlo, dhi) < A.dpe_sq : aprx_min_dist<DIM>(slo, shi, mlo, mhi) < A.dpe)
+    if (A.min_l2 ? box_gap_sq<DIM>(slo, shi, dlo, dhi) < A.dpe_sq : aprx_min_dist<DIM>(slo, shi, mlo, mhi) < A.dpe) {
+        if (lev + 1 == A.lmax) *zero = zero_children<DIM>(A, S, qlo, qhi);
         return 2;
+    }
     return 0;
 }
 
@@ -912,13 +984,17 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
         for (int k = 0; k < DIM; ++k) root.v[v][k] = cvert[(v * DIM + k) * ne + l];
     const cdouble *cdlo = (const cdouble *)(A.dlo);
     const cdouble *cdhi = (const cdouble *)(A.dhi);
-    double mlo[DIM], mhi[DIM], dlo[DIM], dhi[DIM];
+    const cdouble *cqlo = (const cdouble *)(A.qlo);
+    const cdouble *cqhi = (const cdouble *)(A.qhi);
+    double mlo[DIM], mhi[DIM], dlo[DIM], dhi[DIM], qlo[DIM], qhi[DIM];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
         mlo[k] = clo[k * ne + m];
         mhi[k] = chi[k * ne + m];
         dlo[k] = cdlo[k * ne + m];
         dhi[k] = cdhi[k * ne + m];
+        qlo[k] = cqlo[k * ne + m];
+        qhi[k] = cqhi[k * ne + m];
     }
     const double *bary = s_rule;
     const double *wq = s_rule + NQ * NV;
@@ -1030,7 +1106,7 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     // children of J^ref members one level above L_max straight to the leaf
     // buffer, the others' children to the stack when `expand`.  False if the
     // stack would overflow (the pop rule below prevents it).
-    auto act = [&](int lev, uint32_t local, int cls, bool expand) {
+    auto act = [&](int lev, uint32_t local, int cls, uint32_t zmask, bool expand) {
         if (cls == 1 && s_leaf) atomicAdd(&s_leaf[lev], 1ull);
         push_leaf(cls == 1, cls == 1 ? leaf_entry(lev, level_offset<DIM>(lev) + static_cast<int>(local)) : 0u);
         const bool to_leaves = cls == 2 && lev + 1 == lmax;
@@ -1039,7 +1115,7 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
         const unsigned long long mleaf = wave_ballot(to_leaves);
         if (n + static_cast<int>(__popcll(mpush)) * NCH + static_cast<int>(__popcll(mleaf)) > A.capl) {
             // never write past the stack
-            if (lane == 0) atomicOr(&A.counters->error, 1);
+            if (lane == 0) atomicOr(&A.counters->error, kErrStack);
             return false;
         }
         if (to_stack) {
@@ -1050,18 +1126,29 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
         }
         n += static_cast<int>(__popcll(mpush)) * NCH;
         if (mleaf) {
-            // parents above the pushed region, then their children packed across lanes
-            if (to_leaves) stk[n + lanes_below(mleaf)] = local;
+            // parents above the pushed region (with their zero-children masks in
+            // the top byte: local indices are below 2^24), then their children
+            // packed across lanes; a child whose integrals are all zeros is
+            // counted as Algorithm 1's leaf but not integrated
+            if (to_leaves) stk[n + lanes_below(mleaf)] = (zmask << 24) | local;
             wave_sync();
             const int nl = __popcll(mleaf) * NCH;
             const int offn = level_offset<DIM>(lmax);
+            int nzero = 0;
             for (int i0 = 0; i0 < nl; i0 += kWave) {
                 const int i = i0 + lane;
                 const bool take = i < nl;
-                const int sub = take ? offn + static_cast<int>(stk[n + i / NCH] * NCH + (i % NCH)) : 0;
-                push_leaf(take, leaf_entry(lmax, sub));
+                const uint32_t e = take ? stk[n + i / NCH] : 0u;
+                const int c = i % NCH;
+                const bool live = take && ((e >> (24 + c)) & 1u) == 0u;
+                nzero += __popcll(wave_ballot(take && !live));
+                const int sub = live ? offn + static_cast<int>((e & 0xFFFFFFu) * NCH + c) : 0;
+                push_leaf(live, leaf_entry(lmax, sub));
             }
-            if (lane == 0 && s_leaf) atomicAdd(&s_leaf[lmax], static_cast<unsigned long long>(nl));
+            if (lane == 0 && s_leaf) {
+                atomicAdd(&s_leaf[lmax], static_cast<unsigned long long>(nl));
+                if (nzero) atomicAdd(&s_leaf[0], static_cast<unsigned long long>(nzero));
+            }
         }
         wave_sync();
         return true;
@@ -1075,7 +1162,8 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     const int sl = kTopLevels < lmax - 1 ? kTopLevels : lmax - 1;
     bool ok = true;
     if (sl >= 2) {
-        const int rc = 1 < lmin ? 2 : classify<DIM>(A, root, memo, memo_lev, 1, 0u, mlo, mhi, dlo, dhi);
+        uint32_t z0 = 0u;
+        const int rc = 1 < lmin ? 2 : classify<DIM>(A, root, memo, memo_lev, 1, 0u, mlo, mhi, dlo, dhi, qlo, qhi, &z0);
         if (rc == 2) {
             const int ntop = sl == 2 ? NCH : NCH + NCH * NCH;
             const bool valid = lane < ntop;
@@ -1083,13 +1171,15 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
             const uint32_t local = static_cast<uint32_t>(lane < NCH ? lane : lane - NCH);
             if (!memo_ready) build_memo();
             int cls = 0;
-            if (valid) cls = lev < lmin ? 2 : classify<DIM>(A, root, memo, memo_lev, lev, local, mlo, mhi, dlo, dhi);
+            uint32_t zm = 0u;
+            if (valid)
+                cls = lev < lmin ? 2 : classify<DIM>(A, root, memo, memo_lev, lev, local, mlo, mhi, dlo, dhi, qlo, qhi, &zm);
             // the parent of level-3 node `local` is level-2 node local / NCH, in that lane
             const unsigned long long ref = wave_ballot(valid && cls == 2);
             const bool reach = lev == 2 || ((ref >> (local >> DIM)) & 1ull) != 0;
-            ok = act(lev, local, valid && reach ? cls : 0, lev == sl);
+            ok = act(lev, local, valid && reach ? cls : 0, zm, lev == sl);
         } else {
-            ok = act(1, 0u, lane == 0 ? rc : 0, false);
+            ok = act(1, 0u, lane == 0 ? rc : 0, z0, false);
         }
     } else {
         n = 1;
@@ -1121,12 +1211,13 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
         const uint32_t local = ent & 0xFFFFFFu;
         if (!memo_ready && wave_ballot(valid && lev >= 2)) build_memo();
         int cls = 0;
+        uint32_t zm = 0u;
         if (valid) {
             if (lev == lmax) cls = 1;                 // the root when L_max = 1
             else if (lev < lmin) cls = 2;
-            else cls = classify<DIM>(A, root, memo, memo_lev, lev, local, mlo, mhi, dlo, dhi);
+            else cls = classify<DIM>(A, root, memo, memo_lev, lev, local, mlo, mhi, dlo, dhi, qlo, qhi, &zm);
         }
-        ok = act(lev, local, cls, true);
+        ok = act(lev, local, cls, zm, true);
     }
     if (nleaf > 0) integrate(nleaf);
     // a pair without leaves (every sub-element dropped) has zero blocks: nothing to
@@ -1184,6 +1275,9 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
             const int64_t pos = rc->base[i] + at;
             if (four) unsafeAtomicAdd(&A.val[pos], v);
             else unsafeAtomicAdd(&A.val[A.tmap[pos]], 2.0 * v);
+        } else {
+            // (l_i, m_j) outside the pattern: the pair list and the pattern disagree
+            atomicOr(&A.counters->error, kErrPattern);
         }
     } else if (kind == kOutMM) {
         unsafeAtomicAdd(&A.dmm[static_cast<int64_t>(m) * NR + u], four ? v : 2.0 * v);
@@ -1295,6 +1389,7 @@ k_integrate(LaunchArgs L)
             unsafeAtomicAdd(&A.dmm[l * NR + threadIdx.x], s_bll[threadIdx.x]);
         if (threadIdx.x >= 1 && threadIdx.x <= A.lmax && s_leaf[threadIdx.x])
             atomicAdd(&A.counters->leaf[threadIdx.x], s_leaf[threadIdx.x]);
+        if (threadIdx.x == 0 && s_leaf[0]) atomicAdd(&A.counters->zero_leaves, s_leaf[0]);
         if (threadIdx.x == 0 && p_hi > p_lo)
             atomicAdd(&A.counters->pairs_done, static_cast<unsigned long long>(p_hi - p_lo));
         __syncthreads();
@@ -1477,6 +1572,8 @@ AsmArgs make_args(const System &s, const Tables &T)
     A.hi = s.hi.as<double>();
     A.dlo = s.p.min_dist_l2 == 2 ? s.qlo.as<double>() : A.lo;
     A.dhi = s.p.min_dist_l2 == 2 ? s.qhi.as<double>() : A.hi;
+    A.qlo = s.qlo.as<double>();
+    A.qhi = s.qhi.as<double>();
     A.meas = s.meas.as<double>();
     A.conn = m.conn.as<int32_t>();
     A.row_ptr = s.row_ptr.as<int64_t>();

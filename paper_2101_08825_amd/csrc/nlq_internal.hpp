@@ -163,11 +163,17 @@ struct Mesh {
 
 struct AsmCounters {
     unsigned long long leaf[9];
-    unsigned long long evals;
+    unsigned long long zero_leaves;   // leaves at L_max counted but not integrated (all-zero integrals)
     unsigned long long pairs_done;
-    int error;
+    int error;   // kErr* bits
     int pad;
 };
+// error bits of an integration launch
+constexpr int kErrStack = 1;     // a refinement traversal would have passed its stack
+constexpr int kErrPattern = 2;   // a block entry fell outside the CSR pattern
+
+// throws NLQ_EDEVICE naming every bit set in `error` (no-op for 0)
+void check_counter_error(int error);
 
 // Pinned host + device staging of a launch's argument block.  The host side is
 // rewritten by the next launch, so a caller synchronises the stream in between.
@@ -192,7 +198,7 @@ struct System {
     // element tables
     DevBuf vert;                 // [nv*dim][ne] SoA double
     DevBuf lo, hi;               // [dim][ne]
-    DevBuf qlo, qhi;             // [dim][ne] box of the element's quadrature points (min_dist_l2 = 2)
+    DevBuf qlo, qhi;             // [dim][ne] box of the element's quadrature points
     DevBuf meas;                 // [ne]
     // pair list
     DevBuf pair_off;             // [ne+1] int64
@@ -216,6 +222,7 @@ struct System {
     TuneConfig cfg;              // integration launch configuration
     nlq_assemble_info info{};
     bool has_rhs = false;
+    bool integrated = false;     // the values hold a whole integration (not a prepared system)
     std::vector<double> h_g;
 };
 

@@ -130,7 +130,8 @@ __global__ void k_elem_tables(int64_t ne, const double *__restrict__ coords,
 // Box of each element's quadrature points y_b = sum_v bary_bv V_v, formed as
 // the oracle and the integration's inner points form them in FP64: products
 // rounded, then added in vertex order (no fused multiply-add), so that the box
-// holds every such point exactly.  Used by the refine test of min_dist_l2 = 2.
+// holds every such point exactly.  Used by the zero test of the children at
+// L_max and by the refine test of min_dist_l2 = 2.
 template <int DIM>
 __global__ void k_quad_boxes(int64_t ne, int nq, const double *__restrict__ vert,
                              const double *__restrict__ bary, double *__restrict__ qlo,
@@ -176,7 +177,7 @@ void launch_elem_tables(System &s, hipStream_t st)
                            m.conn.as<int32_t>(), s.vert.as<double>(), s.lo.as<double>(),
                            s.hi.as<double>(), s.meas.as<double>());
     NLQ_CHECK_LAUNCH();
-    if (s.p.min_dist_l2 == 2) {
+    {
         const Tables &T = s.ctx->get_tables(m.dim, s.p.lmax);
         s.qlo.alloc(s.ctx, sizeof(double) * ne * m.dim);
         s.qhi.alloc(s.ctx, sizeof(double) * ne * m.dim);

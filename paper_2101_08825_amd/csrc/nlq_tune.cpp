@@ -122,8 +122,14 @@ int autotune(System &s, hipStream_t st, double budget_s, double *best_ms, double
         std::lock_guard<std::mutex> g(ctx.tune_mu);
         ctx.tuned[tune_key(s)] = best;
     }
-    // the sample launches added partial sums: recompute the whole system
-    run_integrate(s, st);
+    // the sample launches added partial sums: recompute an integrated system
+    // whole; a prepared one (never integrated) gets its zero values back
+    if (s.integrated) {
+        run_integrate(s, st);
+    } else {
+        NLQ_HIP(hipMemsetAsync(s.val.as<void>(), 0, sizeof(double) * std::max<int64_t>(s.nnz, 1), st));
+        NLQ_HIP(hipStreamSynchronize(st));
+    }
     return timed;
 }
 

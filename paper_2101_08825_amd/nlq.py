@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTREA
 EXPORTS = [
     "nlq_ctx_create", "nlq_ctx_set_stream", "nlq_ctx_memory", "nlq_ctx_destroy",
     "nlq_mesh_create", "nlq_mesh_box", "nlq_mesh_info", "nlq_mesh_copy", "nlq_mesh_destroy",
-    "nlq_assemble", "nlq_prepare", "nlq_integrate_range", "nlq_assemble_batch", "nlq_assemble_info_get",
+    "nlq_assemble", "nlq_prepare", "nlq_integrate_range", "nlq_integrate_ranges", "nlq_assemble_batch", "nlq_assemble_info_get",
     "nlq_autotune", "nlq_tune_save", "nlq_tune_load", "nlq_reassemble", "nlq_set_data",
     "nlq_set_data_device", "nlq_solve", "nlq_solution_device",
     "nlq_info", "nlq_csr_copy", "nlq_csr_device", "nlq_pairs_copy", "nlq_rhs_copy",
@@ -54,7 +54,7 @@ class nlq_assemble_info(C.Structure):
     _fields_ = [("n_pairs", C.c_int64), ("n_leaf", C.c_int64 * 9), ("n_evals", C.c_int64),
                 ("nnz", C.c_int64), ("t_tables", C.c_double), ("t_pairs", C.c_double),
                 ("t_pattern", C.c_double), ("t_integrate", C.c_double), ("t_total", C.c_double),
-                ("t_kernel", C.c_double)]
+                ("t_kernel", C.c_double), ("n_leaf_zero", C.c_int64)]
 
 
 class nlq_tune_info(C.Structure):
@@ -120,6 +120,7 @@ def lib():
             "nlq_assemble_batch": [vp, i32, vp, vp, vp],
             "nlq_prepare": [vp, vp, P(nlq_params), P(vp)],
             "nlq_integrate_range": [vp, i64, i64, P(d), vp],
+            "nlq_integrate_ranges": [vp, i32, vp, vp, P(d), vp, vp],
             "nlq_autotune": [vp, d, P(nlq_tune_info)],
             "nlq_tune_save": [vp, C.c_char_p],
             "nlq_tune_load": [vp, C.c_char_p, P(i32)],
@@ -288,6 +289,21 @@ class System:
         leaves = np.zeros(9, dtype=np.int64)
         _check(lib().nlq_integrate_range(self.h, int(lo), int(hi), C.byref(t), _ptr(leaves)))
         return t.value, leaves
+
+    def integrate_ranges(self, lo, hi):
+        """nlq_integrate_ranges: one launch over the disjoint outer-element ranges
+        [lo[k], hi[k]); kernel seconds, leaf counts per level and the leaves not
+        evaluated (all-zero integrals), summed over them."""
+        lo_a = np.ascontiguousarray(lo, dtype=np.int64)
+        hi_a = np.ascontiguousarray(hi, dtype=np.int64)
+        if lo_a.shape != hi_a.shape or lo_a.ndim != 1:
+            raise ValueError("lo and hi must be 1-D of one length")
+        t = C.c_double()
+        leaves = np.zeros(9, dtype=np.int64)
+        zero = np.zeros(1, dtype=np.int64)
+        _check(lib().nlq_integrate_ranges(self.h, int(lo_a.shape[0]), _ptr(lo_a), _ptr(hi_a), C.byref(t),
+                                          _ptr(leaves), _ptr(zero)))
+        return t.value, leaves, int(zero[0])
 
     @staticmethod
     def batch(ctx: Context, meshes, prms):

@@ -99,6 +99,42 @@ def kuhn_mesh(dim: int, n: int, k_gamma: int) -> Mesh:
                 constrained=constrained, k_gamma=k_gamma)
 
 
+def jittered_mesh(dim: int, n: int, k_gamma: int, frac: float = 0.2, seed: int = 0) -> Mesh:
+    """The Kuhn mesh of `kuhn_mesh` with every node that is not on the boundary of
+    [0,1]^dim moved by independent U(-frac h, frac h) offsets per coordinate
+    (seeded PCG64): a general simplicial mesh whose element boxes are no longer
+    its cells.  Connectivity and constrained flags are those of the Kuhn mesh.
+    frac <= 0.2 keeps every simplex positively oriented: the smallest height of a
+    Kuhn simplex is h / sqrt(2), and each of its vertices moves by at most
+    frac h sqrt(dim)."""
+    m = kuhn_mesh(dim, n, k_gamma)
+    rng = np.random.default_rng(seed)
+    off = rng.uniform(-frac, frac, size=m.coords.shape) / float(n)
+    inner = np.all((m.coords > 0.0) & (m.coords < 1.0), axis=1)
+    coords = m.coords.copy()
+    coords[inner] += off[inner]
+    return Mesh(dim=dim, n=n, coords=coords, conn=m.conn, constrained=m.constrained,
+                k_gamma=k_gamma)
+
+
+def stratified_ranges(n_elems: int, fraction: float, n_strata: int = 32, seed: int = 0):
+    """A seeded sample of about `fraction` of the outer elements spread over the
+    whole mesh: the ids 1..n_elems-2 cut into n_strata equal strata, one run of
+    round(fraction * stratum) consecutive ids at a seeded position in each.
+    Returns (lo, hi) arrays of the runs [lo_k, hi_k) (0 < lo_k < hi_k < n_elems)."""
+    rng = np.random.default_rng(seed)
+    first, last = 1, n_elems - 1          # usable ids [first, last)
+    edges = np.linspace(first, last, n_strata + 1).astype(np.int64)
+    lo, hi = [], []
+    for a, b in zip(edges[:-1], edges[1:]):
+        run = max(1, int(round(fraction * (b - a))))
+        run = min(run, int(b - a))
+        start = int(a + rng.integers(0, b - a - run + 1))
+        lo.append(start)
+        hi.append(start + run)
+    return np.array(lo, dtype=np.int64), np.array(hi, dtype=np.int64)
+
+
 # ---------------------------------------------------------------------------
 # Manufactured data.  A quadratic u = sum a_k x_k^2 + sum_{k<l} b_kl x_k x_l
 # + c.x + d has Laplacian 2*sum a_k; f = -Laplacian(u) is then constant.

@@ -2,14 +2,22 @@
 
 * 24^3 x 6 tets, delta = 3h, eps = delta/16, depth 4 (constant kernel): the whole
   matrix is assembled in the FP32-mixed path; the pair count equals the closed
-  Kuhn form, sampled J_l equal the oracle's brute force, sampled per-pair blocks
-  equal the oracle's (both precisions), the matrix is symmetric with zero row sums.
+  Kuhn form, sampled J_l equal the oracle's brute force, the leaf integrations
+  per level over the whole mesh equal the oracle's (tests/golden/c3_oracle.json,
+  written by the committed oracle script beside it) and their total the
+  independent count, four whole rows of the assembled matrix equal the oracle's
+  rows, sampled per-pair blocks equal the oracle's (both precisions), and the
+  matrix is symmetric with zero row sums.
 * 48^3 x 6 tets, truncated Gaussian kernel, delta = 3h, eps = delta/32, depth 6:
   too large to integrate whole in a test (about 9e15 kernel evaluations); the
   system is prepared (pair list, pattern), the pair count is checked against the
-  closed form, sampled J_l and per-pair blocks against the oracle, and a slab of
-  outer elements is integrated and timed.
+  closed form, sampled J_l and per-pair blocks against the oracle, and a seeded
+  sample of outer elements spread over the whole mesh (32 strata) is integrated
+  in one launch and timed; its leaf integrations per level equal the oracle's.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -34,6 +42,19 @@ def _kuhn_pairs(dim, n, delta, eps):
 
 def _blocks_rel(got, exp):
     return float(np.linalg.norm((got - exp).ravel()) / np.linalg.norm(exp.ravel()))
+
+
+def _check_vals(got, exp, tol):
+    err = float(np.linalg.norm(got - exp) / np.linalg.norm(exp))
+    emax = float(np.max(np.abs(got - exp)) / np.max(np.abs(exp)))
+    print(f"  rel Frobenius {err:.3e}, max entry error / max entry {emax:.3e}", flush=True)
+    assert err <= tol and emax <= tol, (err, emax)
+
+
+# leaf integrations of the 24^3 problem from a count independent of both
+# implementations
+C3_LEAVES = 78429899232
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_oracle.json")
 
 
 @pytest.fixture(scope="module")
@@ -75,9 +96,18 @@ def test_c3_full_size(nlq_mod, oracle_lib):
     print(f"  pairs {info.n_pairs} leaves {list(info.n_leaf)[1:5]} evals {info.n_evals:.3e} "
           f"t_kernel {info.t_kernel:.2f}s t_total {info.t_total:.2f}s", flush=True)
     assert info.n_pairs == _kuhn_pairs(3, 24, wl.delta, wl.eps) == 271063296
+    gold = json.load(open(GOLDEN))
+    assert list(info.n_leaf)[1:5] == gold["leaves_per_level"][1:5]
+    assert sum(gold["leaves_per_level"]) == C3_LEAVES
     prm_o = O.params(wl.delta, wl.eps, wl.lmax)
     _sampled_checks(nlq, O, s, mesh, wl, prm_o, 1, 6, 24, seed=3)
     rp, col, val = s.csr()
+    for name, row in gold["rows"].items():
+        r = row["node"]
+        assert np.array_equal(col[rp[r]:rp[r + 1]], np.array(row["cols"], dtype=np.int32)), name
+        exp = np.array([float.fromhex(v) for v in row["vals"]])
+        print(f"  row {name} ({r}, {len(exp)} entries):", flush=True)
+        _check_vals(val[rp[r]:rp[r + 1]], exp, TOL32)
     n = mesh.n_nodes
     rows_of = np.repeat(np.arange(n), np.diff(rp))
     rowsum = np.bincount(rows_of, weights=val, minlength=n)
@@ -115,14 +145,17 @@ def test_c5_sampled(nlq_mod, oracle_lib):
     assert sz["nnz"] == 131872229
     prm_o = O.params(wl.delta, wl.eps, wl.lmax, kernel=1)
     _sampled_checks(nlq, O, s, mesh, wl, prm_o, 1, 4, 8, seed=5)
-    # a slab of 1/4096 of the outer elements, timed
+    # a seeded 1/1024 of the outer elements, spread over the mesh in 32 strata,
+    # integrated in one launch and timed; leaf counts per level against the oracle
     ne = mesh.n_elems
-    lo = ne // 3
-    hi = lo + ne // 4096
-    t, leaves = s.integrate_range(lo, hi)
+    lo, hi = W.stratified_ranges(ne, 1.0 / 1024, 32, seed=5)
+    t, leaves, nzero = s.integrate_ranges(lo, hi)
+    sel = np.concatenate([np.arange(a, b) for a, b in zip(lo, hi)])
+    lv_o = O.leaf_counts(O.OracleMesh(mesh.coords, mesh.conn), prm_o, sel)
     evals = int(np.sum(leaves)) * 15 * 15
-    print(f"  slab [{lo}, {hi}): {t:.3f} s, leaves {list(leaves[1:7])}, {evals / t / 1e9:.1f} Gevals/s, "
-          f"whole mesh extrapolated {t * ne / (hi - lo) / 60:.1f} min", flush=True)
+    print(f"  sample {len(sel)} elements: {t:.3f} s, leaves {list(leaves[1:7])}, {evals / t / 1e9:.1f} Gevals/s, "
+          f"whole mesh extrapolated {t * ne / len(sel) / 60:.1f} min", flush=True)
+    assert list(leaves[1:7]) == list(lv_o[1:7])
     assert evals > 0
     s.close()
     m.close()
