@@ -255,6 +255,20 @@ nlq_status nlq_set_data_device(nlq_system *sys, const double *f_dev, const doubl
  * Returns ENOCONV (u = last iterate) when maxit is reached. */
 nlq_status nlq_solve(nlq_system *sys, double rtol, int32_t maxit, double *u_out,
                      nlq_solve_info *info);
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the solve of nlq_solve
+ * with no allocation at all.  The CG vectors, block partials and scalars live in
+ * a static device scratch array of the library (16 MiB per GPU, held until the
+ * process ends; enough for about 290,000 nodes), whose device address the
+ * context's creation takes once per device.  u_dev: caller-owned DEVICE buffer
+ * [n_nodes] receiving u (w on free nodes, g on Gamma).  Iterations run as plain
+ * launches (no graph), in the same order as nlq_solve's, with the same result.
+ * Calls on one GPU share its scratch: calls that overlap in time on one GPU (two
+ * host threads, two contexts) race and must be serialised by the caller.
+ * Errors: EINVAL when nlq_set_data has not run, for bad rtol/maxit or NULL u_dev,
+ * and when the system needs more scratch than the limit (the message names both
+ * sizes); ENOCONV as nlq_solve. */
+nlq_status nlq_solve_noalloc(nlq_system *sys, double rtol, int32_t maxit, double *u_dev, nlq_solve_info *info);
 /* Borrowed device pointer to the last solution u [n_nodes], valid until
  * nlq_system_destroy (NULL before the first nlq_solve). */
 nlq_status nlq_solution_device(const nlq_system *sys, const double **u_dev);

@@ -412,6 +412,8 @@ nlq_status nlq_ctx_create(int32_t device, uint64_t hbm_budget_bytes, nlq_ctx **o
         NLQ_HIP(hipGetDeviceCount(&ndev));
         if (device < 0 || device >= ndev) fail(NLQ_EINVAL, "no such device");
         NLQ_HIP(hipSetDevice(device));
+        // the device address of the allocation-free solve's scratch, once per device
+        noalloc_scratch_init(device);
         auto c = std::make_unique<nlq_ctx>();
         c->impl.device = device;
         hipDeviceProp_t prop;
@@ -814,6 +816,34 @@ nlq_status nlq_solve(nlq_system *sys, double rtol, int32_t maxit, double *u_out,
         if (!sys) fail(NLQ_EINVAL, "sys is NULL");
         NLQ_HIP(hipSetDevice(sys->impl.ctx->device));
         converged = solve_system(sys->impl, rtol, maxit, u_out, info, sys->impl.ctx->stream);
+    });
+    if (st == NLQ_OK && !converged) {
+        set_last_error("CG did not reach the tolerance");
+        return NLQ_ENOCONV;
+    }
+    return st;
+}
+
+nlq_status nlq_solve_noalloc(nlq_system *sys, double rtol, int32_t maxit, double *u_dev, nlq_solve_info *info)
+{
+    bool converged = true;
+    nlq_status st = guard([&] {
+        if (!sys || !u_dev) fail(NLQ_EINVAL, "NULL argument");
+        System &s = sys->impl;
+        if (!s.has_rhs) fail(NLQ_EINVAL, "nlq_set_data must be called before nlq_solve_noalloc");
+        if (!(rtol > 0.0) || maxit < 1) fail(NLQ_EINVAL, "need rtol > 0 and maxit >= 1");
+        NLQ_HIP(hipSetDevice(s.ctx->device));
+        const double t0 = now_s();
+        double relres = 0.0;
+        int conv = 0;
+        const int it = cg_solve_noalloc(s, s.ctx->stream, rtol, maxit, &relres, &conv, u_dev);
+        if (info) {
+            info->iterations = it;
+            info->converged = conv;
+            info->rel_residual = relres;
+            info->seconds = now_s() - t0;
+        }
+        converged = conv != 0;
     });
     if (st == NLQ_OK && !converged) {
         set_last_error("CG did not reach the tolerance");

@@ -273,6 +273,12 @@ void launch_pair_blocks(System &s, hipStream_t st, int64_t n, const int32_t *ex_
                         double *ex_out);
 void launch_load_lift(System &s, hipStream_t st, const double *f_dev, const double *g_dev);
 int cg_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, int *converged);
+// the allocation-free solve: CG vectors in the library's static device scratch
+// (address taken per device by noalloc_scratch_init), plain launches, u into u_dev
+void noalloc_scratch_init(int device);
+size_t noalloc_scratch_limit();
+int cg_solve_noalloc(System &s, hipStream_t st, double rtol, int maxit, double *relres, int *converged,
+                     double *u_dev);
 void launch_box_mesh(int dim, int n, int k_gamma, double *coords, int32_t *conn,
                      uint8_t *constrained, hipStream_t st);
 

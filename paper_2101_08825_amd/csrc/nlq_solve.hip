@@ -5,6 +5,8 @@
 //   A_{Omega,Omega} w = F~_Omega by Jacobi-preconditioned CG; u = w (free), g (Gamma)
 #include <cmath>
 #include <cstdlib>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "nlq_device.hpp"
@@ -335,37 +337,41 @@ void launch_load_lift(System &s, hipStream_t st, const double *f_dev, const doub
     NLQ_CHECK_LAUNCH();
 }
 
-// Returns the iteration count; the solution (u = w on free nodes, g on Gamma)
-// is left in s.u.  The host checks the residual every `check` iterations.
-int cg_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, int *converged)
+namespace {
+
+// device vectors of one CG solve
+struct CgBuffers {
+    double *dinv, *w, *r, *z, *p, *p2, *q;
+    double *partial;   // block partials: r.z in two slots, r.r, p.q
+    CgScalars *sc;
+};
+
+int64_t cg_nb_rows(int64_t n) { return (n + kSpmvRows - 1) / kSpmvRows; }
+int64_t cg_nb_vec(int64_t n) { return (n + kCgThreads - 1) / kCgThreads; }
+
+// Jacobi CG on the free rows into b; u = w (free), g (Gamma) into u_dst.
+// graph: replay blocks of 8 iterations as a HIP graph (else plain launches, in
+// the same order and with the same results).
+int cg_run(System &s, hipStream_t st, double rtol, int maxit, double *relres, int *converged, const CgBuffers &b,
+           bool graph, double *u_dst)
 {
     const Mesh &m = *s.mesh;
     const int64_t n = m.n_nodes;
-    if (s.u.empty()) s.u.alloc(s.ctx, sizeof(double) * n);
-    DevBuf dinv(s.ctx, sizeof(double) * n, st), w(s.ctx, sizeof(double) * n, st),
-        r(s.ctx, sizeof(double) * n, st), z(s.ctx, sizeof(double) * n, st), p(s.ctx, sizeof(double) * n, st),
-        p2(s.ctx, sizeof(double) * n, st), q(s.ctx, sizeof(double) * n, st);
-    double *const pbuf[2] = {p.as<double>(), p2.as<double>()};
-    const int64_t nb_rows = (n + kSpmvRows - 1) / kSpmvRows;
-    const int64_t nb_vec = (n + kCgThreads - 1) / kCgThreads;
-    // block partials: r.z in two slots (the current and the next iteration's),
-    // r.r, p.q
-    DevBuf partial(s.ctx, sizeof(double) * (3 * nb_vec + nb_rows), st);
-    double *const rz_slot[2] = {partial.as<double>(), partial.as<double>() + nb_vec};
-    double *const rr_part = partial.as<double>() + 2 * nb_vec;
-    double *const pq_part = partial.as<double>() + 3 * nb_vec;
-    DevBuf scal(s.ctx, sizeof(CgScalars), st);
-    CgScalars *sc = scal.as<CgScalars>();
+    double *const pbuf[2] = {b.p, b.p2};
+    const int64_t nb_rows = cg_nb_rows(n);
+    const int64_t nb_vec = cg_nb_vec(n);
+    double *const rz_slot[2] = {b.partial, b.partial + nb_vec};
+    double *const rr_part = b.partial + 2 * nb_vec;
+    double *const pq_part = b.partial + 3 * nb_vec;
+    CgScalars *sc = b.sc;
     NLQ_HIP(hipMemsetAsync(sc, 0, sizeof(CgScalars), st));
     const uint8_t *cst = m.constrained.as<uint8_t>();
     hipLaunchKernelGGL(k_cg_init, dim3(nb_vec), dim3(kCgThreads), 0, st, n, s.row_ptr.as<int64_t>(),
-                       s.col.as<int32_t>(), s.val.as<double>(), cst, s.Ft.as<double>(),
-                       dinv.as<double>(), w.as<double>(), r.as<double>(), z.as<double>(),
-                       p.as<double>(), partial.as<double>(), nb_vec);
+                       s.col.as<int32_t>(), s.val.as<double>(), cst, s.Ft.as<double>(), b.dinv, b.w, b.r, b.z,
+                       b.p, b.partial, nb_vec);
     NLQ_CHECK_LAUNCH();
     // rz -> sc->rz, rr -> sc->rz_new (temporarily)
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kCgThreads), 0, st, nb_vec, partial.as<double>(),
-                       &sc->rz, 2);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kCgThreads), 0, st, nb_vec, b.partial, &sc->rz, 2);
     NLQ_CHECK_LAUNCH();
     CgScalars h{};
     NLQ_HIP(hipMemcpyAsync(&h, sc, sizeof(CgScalars), hipMemcpyDeviceToHost, st));
@@ -386,11 +392,9 @@ int cg_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, 
             const int par = k & 1;
             hipLaunchKernelGGL(k_spmv_dot, dim3(nb_rows), dim3(kSpmvThreads), 0, st, n, s.row_ptr.as<int64_t>(),
                                s.col.as<int32_t>(), s.val.as<double>(), cst, rz_slot[par], rz_slot[1 - par],
-                               nb_vec, k == 0 ? 1 : 0, z.as<double>(), pbuf[par], pbuf[1 - par], q.as<double>(),
-                               pq_part);
+                               nb_vec, k == 0 ? 1 : 0, b.z, pbuf[par], pbuf[1 - par], b.q, pq_part);
             hipLaunchKernelGGL(k_update, dim3(nb_vec), dim3(kCgThreads), 0, st, n, sc, rz_slot[par], pq_part,
-                               nb_rows, dinv.as<double>(), pbuf[1 - par], q.as<double>(), w.as<double>(),
-                               r.as<double>(), z.as<double>(), rz_slot[1 - par], rr_part, nb_vec);
+                               nb_rows, b.dinv, pbuf[1 - par], b.q, b.w, b.r, b.z, rz_slot[1 - par], rr_part, nb_vec);
         };
         // r.r of the last update, for the host's residual check
         auto residual = [&]() {
@@ -400,19 +404,18 @@ int cg_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, 
         // iterations.  Iterations 1..8 (the first iteration's kernels differ)
         // and the check's reduction are captured once as a HIP graph (kernels
         // only: no memset or copy inside) and replayed for every later block of
-        // 8, whose parities are the same; NLQ_CG_GRAPH=0 keeps the plain
-        // launches, in the same order.
+        // 8, whose parities are the same; without the graph the same launches
+        // run one by one, in the same order.
         hipGraphExec_t exec = nullptr;
-        const char *env = std::getenv("NLQ_CG_GRAPH");
-        if (maxit >= 2 * check && !(env && env[0] == '0')) {
-            hipGraph_t graph = nullptr;
+        if (graph && maxit >= 2 * check) {
+            hipGraph_t gr = nullptr;
             NLQ_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
             for (int k = 1; k <= check; ++k) iteration(k);
             residual();
-            const hipError_t e_end = hipStreamEndCapture(st, &graph);
+            const hipError_t e_end = hipStreamEndCapture(st, &gr);
             if (e_end != hipSuccess) fail(NLQ_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e_end));
-            const hipError_t e_inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
+            const hipError_t e_inst = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
             if (e_inst != hipSuccess) fail(NLQ_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e_inst));
         }
         for (it = 0; it < maxit;) {
@@ -439,11 +442,86 @@ int cg_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, 
         if (exec) (void)hipGraphExecDestroy(exec);
         *relres = rn / bnorm;
     }
-    hipLaunchKernelGGL(k_compose_u, dim3(nb_vec), dim3(kCgThreads), 0, st, n, cst, w.as<double>(),
-                       s.g.as<double>(), s.u.as<double>());
+    hipLaunchKernelGGL(k_compose_u, dim3(nb_vec), dim3(kCgThreads), 0, st, n, cst, b.w, s.g.as<double>(), u_dst);
     NLQ_CHECK_LAUNCH();
     NLQ_HIP(hipStreamSynchronize(st));
     return it;
+}
+
+// ---- scratch of the allocation-free solve (nlq_solve_noalloc) -------------
+// A file-scope device array: every GPU the library runs on holds its own copy
+// until the process ends.  Host code never uses its name as an address: the
+// device address is taken once per device with hipGetSymbolAddress (the
+// context's creation, that device current) and kept here.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+__device__ __align__(256) char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// bytes of the CG vectors, partials and scalars for n nodes, carved as below
+size_t cg_scratch_bytes(int64_t n)
+{
+    const size_t vec = al256(sizeof(double) * static_cast<size_t>(n));
+    const size_t part = al256(sizeof(double) * static_cast<size_t>(3 * cg_nb_vec(n) + cg_nb_rows(n)));
+    return 7 * vec + part + al256(sizeof(CgScalars));
+}
+
+}  // namespace
+
+// Returns the iteration count; the solution (u = w on free nodes, g on Gamma)
+// is left in s.u.  The host checks the residual every 8 iterations.
+int cg_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, int *converged)
+{
+    const int64_t n = s.mesh->n_nodes;
+    if (s.u.empty()) s.u.alloc(s.ctx, sizeof(double) * n);
+    DevBuf dinv(s.ctx, sizeof(double) * n, st), w(s.ctx, sizeof(double) * n, st),
+        r(s.ctx, sizeof(double) * n, st), z(s.ctx, sizeof(double) * n, st), p(s.ctx, sizeof(double) * n, st),
+        p2(s.ctx, sizeof(double) * n, st), q(s.ctx, sizeof(double) * n, st);
+    DevBuf partial(s.ctx, sizeof(double) * (3 * cg_nb_vec(n) + cg_nb_rows(n)), st);
+    DevBuf scal(s.ctx, sizeof(CgScalars), st);
+    const CgBuffers b{dinv.as<double>(), w.as<double>(), r.as<double>(), z.as<double>(), p.as<double>(),
+                      p2.as<double>(), q.as<double>(), partial.as<double>(), scal.as<CgScalars>()};
+    const char *env = std::getenv("NLQ_CG_GRAPH");
+    return cg_run(s, st, rtol, maxit, relres, converged, b, !(env && env[0] == '0'), s.u.as<double>());
+}
+
+void noalloc_scratch_init(int device)
+{
+    if (device < 0 || device >= 64) fail(NLQ_EINVAL, "device id beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) fail(NLQ_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+}
+
+size_t noalloc_scratch_limit() { return kScratchBytes; }
+
+int cg_solve_noalloc(System &s, hipStream_t st, double rtol, int maxit, double *relres, int *converged,
+                     double *u_dev)
+{
+    const int64_t n = s.mesh->n_nodes;
+    const size_t need = cg_scratch_bytes(n);
+    if (need > kScratchBytes)
+        fail(NLQ_EINVAL, "nlq_solve_noalloc: " + std::to_string(n) + " nodes need " + std::to_string(need) +
+                             " bytes of scratch, more than its " + std::to_string(kScratchBytes));
+    char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        base = static_cast<char *>(g_scratch_ptr[s.ctx->device]);
+    }
+    if (!base) fail(NLQ_EDEVICE, "scratch of this device not set up (context creation takes its address)");
+    const size_t vec = al256(sizeof(double) * static_cast<size_t>(n));
+    double *v[7];
+    for (int k = 0; k < 7; ++k) v[k] = reinterpret_cast<double *>(base + k * vec);
+    double *partial = reinterpret_cast<double *>(base + 7 * vec);
+    CgScalars *sc = reinterpret_cast<CgScalars *>(
+        base + 7 * vec + al256(sizeof(double) * static_cast<size_t>(3 * cg_nb_vec(n) + cg_nb_rows(n))));
+    const CgBuffers b{v[0], v[1], v[2], v[3], v[4], v[5], v[6], partial, sc};
+    return cg_run(s, st, rtol, maxit, relres, converged, b, false, u_dev);
 }
 
 }  // namespace nlq

@@ -30,7 +30,7 @@ EXPORTS = [
     "nlq_mesh_create", "nlq_mesh_box", "nlq_mesh_info", "nlq_mesh_copy", "nlq_mesh_destroy",
     "nlq_assemble", "nlq_prepare", "nlq_integrate_range", "nlq_integrate_ranges", "nlq_assemble_batch", "nlq_assemble_info_get",
     "nlq_autotune", "nlq_tune_save", "nlq_tune_load", "nlq_reassemble", "nlq_set_data",
-    "nlq_set_data_device", "nlq_solve", "nlq_solution_device",
+    "nlq_set_data_device", "nlq_solve", "nlq_solve_noalloc", "nlq_solution_device",
     "nlq_info", "nlq_csr_copy", "nlq_csr_device", "nlq_pairs_copy", "nlq_rhs_copy",
     "nlq_pair_blocks", "nlq_system_destroy", "nlq_serve_start", "nlq_submit", "nlq_wait",
     "nlq_cancel", "nlq_result_release", "nlq_serve_stats_get", "nlq_serve_stop", "nlq_last_error",
@@ -129,6 +129,7 @@ def lib():
             "nlq_set_data": [vp, vp, vp],
             "nlq_set_data_device": [vp, vp, vp],
             "nlq_solve": [vp, d, i32, vp, P(nlq_solve_info)],
+            "nlq_solve_noalloc": [vp, d, i32, vp, P(nlq_solve_info)],
             "nlq_solution_device": [vp, P(vp)],
             "nlq_info": [vp, P(i64), P(i64), P(i64), P(i64)],
             "nlq_csr_copy": [vp, vp, vp, vp],
@@ -350,6 +351,16 @@ class System:
         if st not in (NLQ_OK, NLQ_ENOCONV):
             _check(st)
         return u, inf
+
+    def solve_noalloc(self, u_dev_ptr: int, rtol=1e-12, maxit=20000):
+        """nlq_solve_noalloc: the solve without any device allocation; u is
+        written to the caller's device buffer u_dev_ptr [n_nodes] (e.g. the
+        data_ptr() of a float64 torch tensor)."""
+        inf = nlq_solve_info()
+        st = lib().nlq_solve_noalloc(self.h, float(rtol), int(maxit), C.c_void_p(u_dev_ptr), C.byref(inf))
+        if st not in (NLQ_OK, NLQ_ENOCONV):
+            _check(st)
+        return inf
 
     def solution_device(self) -> int:
         p = C.c_void_p()
