@@ -104,6 +104,7 @@ struct AsmArgs {
     double dme_sq;        // s* with (sqrt(s) < delta - eps) <=> (s < s*), s >= 0
     double *dmm;          // [ne][NR] upper-triangle diagonal-block sums per element
     float f_inv_eps, f_delta_over_eps, f_inv_delta2;
+    float f_dme2, f_dpe2;  // (delta - eps)^2, (delta + eps)^2 in FP32: the band test of a tile register
     int lmin, lmax, form;
     int split;            // work items per outer element (pair list cut in equal parts)
     int capl;             // traversal stack entries of this system (see make_args)
@@ -242,6 +243,21 @@ template <int ETA> __device__ __forceinline__ float kernel32(CArgs &A, float d2,
 {
     float g = mu32(A, __builtin_amdgcn_sqrtf(d2), doe);
     if (ETA == NLQ_ETA_GAUSS) g *= __expf(-d2 * A.f_inv_delta2);
+    return g;
+}
+
+// gamma_eps / C of the 64 squared distances one register holds across the wave
+// (one per lane).  When no lane's distance is in the band, mu is a step (1 on
+// the plateau, 0 beyond) and the square root and xi are skipped for the whole
+// register: a wave-uniform branch.  Both sides of the branch give the same
+// values up to the band edges, where xi is within (1e-7)^5 of 1 or 0.
+template <int ETA> __device__ __forceinline__ float kernel32_reg(CArgs &A, float d2, float doe)
+{
+    const bool plateau = d2 < A.f_dme2;
+    const bool band = !plateau && d2 <= A.f_dpe2;
+    if (__builtin_amdgcn_ballot_w64(band)) return kernel32<ETA>(A, d2, doe);
+    float g = plateau ? 1.0f : 0.0f;
+    if (ETA == NLQ_ETA_GAUSS) g = plateau ? __expf(-d2 * A.f_inv_delta2) : 0.0f;
     return g;
 }
 
@@ -603,7 +619,7 @@ template <int DIM, int ETA> struct MixedAccDirect {
             const float2 x = *reinterpret_cast<const float2 *>(sx + t * PPS * XS);
             const float dx = x.x - yh[0], dy = x.y - yh[1];
             const float d2 = fmaf(dx, dx, dy * dy);
-            const float g = kernel32<ETA>(A, d2, doe);
+            const float g = kernel32_reg<ETA>(A, d2, doe);
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, g, acc, 0, 0, 0);
         }
         facc = acc;
@@ -719,10 +735,7 @@ template <int DIM, int ETA> struct MixedAccMfma {
     // at 0 against the cancellation of nearly equal points
     __device__ __forceinline__ float gamma(CArgs &A, float v) const
     {
-        const float d2 = fmaxf(v, 0.0f);
-        float g = mu32(A, __builtin_amdgcn_sqrtf(d2), doe);
-        if (ETA == NLQ_ETA_GAUSS) g *= __expf(-d2 * A.f_inv_delta2);
-        return g;
+        return kernel32_reg<ETA>(A, __builtin_amdgcn_fmed3f(v, 0.0f, 3.0e38f), doe);
     }
     __device__ void run(CArgs &A, const char *work, int npts)
     {
@@ -1606,6 +1619,8 @@ AsmArgs make_args(const System &s, const Tables &T)
     A.f_inv_eps = static_cast<float>(1.0 / s.p.eps);
     A.f_delta_over_eps = static_cast<float>(s.p.delta / s.p.eps);
     A.f_inv_delta2 = static_cast<float>(1.0 / (s.p.delta * s.p.delta));
+    A.f_dme2 = static_cast<float>(A.dme * A.dme);
+    A.f_dpe2 = static_cast<float>(A.dpe * A.dpe);
     A.lmin = s.p.lmin;
     A.lmax = s.p.lmax;
     A.form = s.p.form;
