@@ -52,7 +52,7 @@ typedef enum {
 } nlq_status;
 
 enum { NLQ_ETA_CONST = 0, NLQ_ETA_GAUSS = 1 };
-enum { NLQ_FORM_SYM4 = 0, NLQ_FORM_PAPER2 = 1 };
+enum { NLQ_FORM_SYM4 = 0, NLQ_FORM_PAPER2 = 1, NLQ_FORM_PAPER2_INNER = 2 };
 enum { NLQ_FP64_PLAIN = 0, NLQ_FP32_MIXED = 1 };
 
 typedef struct nlq_ctx nlq_ctx;
@@ -72,6 +72,12 @@ typedef struct nlq_system nlq_system;
  *             ordered pair (exactly symmetric, zero row sums).  NLQ_FORM_PAPER2:
  *             2 A21 + 2 A22 of the Corollary in Section 5 (rows of the inner
  *             test function; zero row sums, symmetric only in the limit).
+ *             NLQ_FORM_PAPER2_INNER: the same two-term form with the adaptive
+ *             rule on the inner integral instead of the outer one (Section 5
+ *             calls the choice empirical): every element is refined against
+ *             its J_l and carries the rows, 2 B_ll and 2 B_lm, which summed over
+ *             the symmetric pair list is the adaptive-inner assembly.  Not
+ *             available with deterministic = 1.
  *  precision  NLQ_FP64_PLAIN: FP64 kernel evaluation and contraction.
  *             NLQ_FP32_MIXED: FP32 evaluation at anchor-relative coordinates,
  *             FP32 matrix-core contraction per 64-point batch, FP64 per-pair

@@ -573,7 +573,15 @@ static int ext(int nv) { return 2 * nv; }
  * four-term integrand (phi_i(x)-phi_i(y))(phi_j(x)-phi_j(y)) of eq.
  * (Aij-support2) is g z z^T in the extended index space [nodes(l), nodes(m)];
  * the two-term form is 2 A21 + 2 A22 (Corollary), whose rows are those of the
- * inner test function (reading R2 restores A21's minus sign). */
+ * inner test function (reading R2 restores A21's minus sign).
+ * Form 2 is the same two-term formula with the adaptive rule on the INNER
+ * integral instead (Section 5: the choice of the adaptive side is empirical):
+ * the test function's element is the refined one and the other element gets
+ * its Gauss rule.  Here every element is refined against its J_l, so form 2
+ * puts the rows on the refined (outer) element l: 2 g phi^l_i(x) (phi_Q(x) -
+ * phi_Q(y)).  Summed over the pair list, which holds (l, m) and (m, l) alike,
+ * this is the assembly with the inner integral adaptive and the outer one by
+ * Gauss rule, relabelled. */
 static void integration(alg_ctx *c, int level, const double *V, const double *Lam,
                         const int *Jpos, int nJ)
 {
@@ -629,10 +637,13 @@ static void integration(alg_ctx *c, int level, const double *V, const double *La
                 if (c->p->form == 0) {
                     for (int P = 0; P < ne2; ++P)
                         for (int Q = 0; Q < ne2; ++Q) E[P * ne2 + Q] += g * z[P] * z[Q];
-                } else {
+                } else if (c->p->form == 1) {
                     for (int bb = 0; bb < nv; ++bb)
                         for (int Q = 0; Q < ne2; ++Q)
                             E[(nv + bb) * ne2 + Q] += 2.0 * g * c->bary[b * nv + bb] * (-z[Q]);
+                } else {
+                    for (int aa = 0; aa < nv; ++aa)
+                        for (int Q = 0; Q < ne2; ++Q) E[aa * ne2 + Q] += 2.0 * g * lam[a][aa] * z[Q];
                 }
             }
         }

@@ -32,7 +32,9 @@ typedef struct {
     double scale;           /* > 0: kernel constant; 0: the paper's normalisation */
     int32_t kernel;         /* 0: eta = 1; 1: eta = exp(-d^2/delta^2) */
     int32_t lmin, lmax;     /* Algorithm 1 levels, 1 <= lmin <= lmax */
-    int32_t form;           /* 0: four-term integrand; 1: 2*(A21 + A22) */
+    int32_t form;           /* 0: four-term integrand; 1: 2*(A21 + A22), adaptive outer
+                               integral; 2: the same with the adaptive rule on the
+                               inner integral (rows of the refined element) */
     int32_t min_l2;         /* 0: the J^ref test with the L_inf box gap of eq. (mindist);
                                1: with the Euclidean box gap (ablation, see or_boxgap_l2);
                                2: the Euclidean gap to the box of the inner element's

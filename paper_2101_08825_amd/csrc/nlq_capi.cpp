@@ -164,7 +164,10 @@ void check_params(const Mesh &m, const nlq_params &p)
     if (p.lmin < 1 || p.lmax < p.lmin) fail(NLQ_EINVAL, "need 1 <= lmin <= lmax");
     if (p.lmax > (m.dim == 2 ? 8 : 6)) fail(NLQ_EINVAL, "lmax too large (max 8 in 2D, 6 in 3D)");
     if (p.kernel != NLQ_ETA_CONST && p.kernel != NLQ_ETA_GAUSS) fail(NLQ_EINVAL, "unknown kernel");
-    if (p.form != NLQ_FORM_SYM4 && p.form != NLQ_FORM_PAPER2) fail(NLQ_EINVAL, "unknown form");
+    if (p.form != NLQ_FORM_SYM4 && p.form != NLQ_FORM_PAPER2 && p.form != NLQ_FORM_PAPER2_INNER)
+        fail(NLQ_EINVAL, "unknown form");
+    if (p.form == NLQ_FORM_PAPER2_INNER && p.deterministic)
+        fail(NLQ_EINVAL, "the adaptive-inner two-term form has no deterministic mode");
     if (p.precision != NLQ_FP64_PLAIN && p.precision != NLQ_FP32_MIXED)
         fail(NLQ_EINVAL, "unknown precision");
     if (p.deterministic != 0 && p.deterministic != 1) fail(NLQ_EINVAL, "deterministic must be 0 or 1");

@@ -1259,17 +1259,20 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     const double Sc = A.C * A.meas[l] * A.meas[m];
     v *= kind == kOutLM ? -Sc : Sc;
     const bool four = A.form == NLQ_FORM_SYM4;
+    // the two-term form with the adaptive rule on the inner integral: rows of the
+    // refined (outer) element, 2 B_ll and 2 B_lm (see the oracle's form 2)
+    const bool inner = A.form == NLQ_FORM_PAPER2_INNER;
     if (ex_block) {
         constexpr int N2 = 2 * NV;
         if (kind == kOutLM) {
-            ex_block[i * N2 + NV + j] = four ? v : 0.0;
-            ex_block[(NV + j) * N2 + i] = four ? v : 2.0 * v;
+            ex_block[i * N2 + NV + j] = four ? v : (inner ? 2.0 * v : 0.0);
+            ex_block[(NV + j) * N2 + i] = four ? v : (inner ? 0.0 : 2.0 * v);
         } else if (kind == kOutMM) {
-            ex_block[(NV + i) * N2 + NV + j] = four ? v : 2.0 * v;
-            ex_block[(NV + j) * N2 + NV + i] = four ? v : 2.0 * v;
+            ex_block[(NV + i) * N2 + NV + j] = four ? v : (inner ? 0.0 : 2.0 * v);
+            ex_block[(NV + j) * N2 + NV + i] = four ? v : (inner ? 0.0 : 2.0 * v);
         } else if (kind == kOutLL) {
-            ex_block[i * N2 + j] = four ? v : 0.0;
-            ex_block[j * N2 + i] = four ? v : 0.0;
+            ex_block[i * N2 + j] = four ? v : (inner ? 2.0 * v : 0.0);
+            ex_block[j * N2 + i] = four ? v : (inner ? 2.0 * v : 0.0);
         }
         return;
     }
@@ -1282,20 +1285,22 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     if (kind == kOutLM) {
         // B_lm at (l_i, m_j) through the cached row of l_i.  SYM4 adds it to the
         // half matrix R (A = R + R^T afterwards); the two-term form puts 2 B_lm^T
-        // at (m_j, l_i) directly.
+        // at (m_j, l_i) directly, its adaptive-inner variant 2 B_lm at (l_i, m_j).
         const int64_t at = row_find(rc, i, mj);
         if (at >= 0) {
             const int64_t pos = rc->base[i] + at;
             if (four) unsafeAtomicAdd(&A.val[pos], v);
+            else if (inner) unsafeAtomicAdd(&A.val[pos], 2.0 * v);
             else unsafeAtomicAdd(&A.val[A.tmap[pos]], 2.0 * v);
         } else {
             // (l_i, m_j) outside the pattern: the pair list and the pattern disagree
             atomicOr(&A.counters->error, kErrPattern);
         }
     } else if (kind == kOutMM) {
-        unsafeAtomicAdd(&A.dmm[static_cast<int64_t>(m) * NR + u], four ? v : 2.0 * v);
+        if (!inner) unsafeAtomicAdd(&A.dmm[static_cast<int64_t>(m) * NR + u], four ? v : 2.0 * v);
     } else if (kind == kOutLL) {
         if (four) atomicAdd(&s_bll[u], v);
+        else if (inner) atomicAdd(&s_bll[u], 2.0 * v);
     }
 }
 
@@ -1397,8 +1402,9 @@ k_integrate(LaunchArgs L)
                                          s_desc, s_bll, &s_rc, nullptr, s_leaf);
         }
         __syncthreads();
-        // B_ll of l (upper triangle) joins the diagonal-block sums of l
-        if (A.form == NLQ_FORM_SYM4 && !A.pb && threadIdx.x < NR)
+        // B_ll of l (upper triangle; doubled for the adaptive-inner two-term form)
+        // joins the diagonal-block sums of l
+        if (A.form != NLQ_FORM_PAPER2 && !A.pb && threadIdx.x < NR)
             unsafeAtomicAdd(&A.dmm[l * NR + threadIdx.x], s_bll[threadIdx.x]);
         if (threadIdx.x >= 1 && threadIdx.x <= A.lmax && s_leaf[threadIdx.x])
             atomicAdd(&A.counters->leaf[threadIdx.x], s_leaf[threadIdx.x]);

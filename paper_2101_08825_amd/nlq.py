@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libnlq.so")
 NLQ_OK, NLQ_EINVAL, NLQ_ENOMEM, NLQ_EDEVICE, NLQ_ENOTREADY, NLQ_ECANCELLED, NLQ_EBUSY, \
     NLQ_ENOCONV = 0, -1, -2, -3, -4, -5, -6, -7
 NLQ_ETA_CONST, NLQ_ETA_GAUSS = 0, 1
-NLQ_FORM_SYM4, NLQ_FORM_PAPER2 = 0, 1
+NLQ_FORM_SYM4, NLQ_FORM_PAPER2, NLQ_FORM_PAPER2_INNER = 0, 1, 2
 NLQ_FP64_PLAIN, NLQ_FP32_MIXED = 0, 1
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTREADY",

@@ -69,7 +69,7 @@ def _print_case(name, **kw):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("form", [0, 1, 2])
 def test_c1_full_parity(nlq_ctx, oracle_lib, precision, form):
     """2D 16^2, delta = 2h, eps = delta/16, L_max = 3, u = x1^2, f = -2."""
     from paper_2101_08825_amd import nlq
@@ -164,7 +164,7 @@ def test_l2_box_gap_parity(nlq_ctx, oracle_lib, precision, dim, n, kd, ed, lmax,
 _ORACLE_3D = {}
 
 
-@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("form", [0, 1, 2])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_3d_full_parity(nlq_ctx, oracle_lib, precision, form):
     """3D 5^3 x 6 tets, delta = 2h, eps = delta/16, L_max = 2, u = x1^2: every
@@ -191,18 +191,21 @@ def test_3d_full_parity(nlq_ctx, oracle_lib, precision, form):
     m.close()
 
 
-@pytest.mark.parametrize("dim,n,kd,ed,lmax", [(2, 12, 3, 8, 4), (3, 5, 2, 16, 3), (3, 4, 2, 4, 2)])
+@pytest.mark.parametrize("dim,n,kd,ed,lmax,form", [(2, 12, 3, 8, 4, 0), (3, 5, 2, 16, 3, 0), (3, 4, 2, 4, 2, 0),
+                                                   (2, 12, 3, 8, 4, 1), (3, 4, 2, 4, 2, 2)])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_pair_blocks_sampled(nlq_ctx, oracle_lib, dim, n, kd, ed, lmax, precision):
-    """Per-pair extended blocks of seeded sampled pairs vs the oracle."""
+def test_pair_blocks_sampled(nlq_ctx, oracle_lib, dim, n, kd, ed, lmax, form, precision):
+    """Per-pair extended blocks of seeded sampled pairs vs the oracle (every
+    form: the four-term one, the paper's two-term one, its adaptive-inner
+    variant)."""
     from paper_2101_08825_amd import nlq
     O = oracle_lib
-    _print_case("pair_blocks", dim=dim, n=n, kd=kd, ed=ed, lmax=lmax, precision=precision)
+    _print_case("pair_blocks", dim=dim, n=n, kd=kd, ed=ed, lmax=lmax, form=form, precision=precision)
     mesh = W.kuhn_mesh(dim, n, kd)
     delta = kd / n
     eps = delta / ed
     m = nlq.Mesh.create(nlq_ctx, mesh.coords, mesh.conn, mesh.constrained)
-    s = nlq.System(nlq_ctx, m, nlq.params(dim, delta, eps, lmax, precision=precision))
+    s = nlq.System(nlq_ctx, m, nlq.params(dim, delta, eps, lmax, precision=precision, form=form))
     off, pm = s.pairs()
     rng = np.random.default_rng(11)
     pick = rng.choice(len(pm), size=min(60, len(pm)), replace=False)
@@ -210,7 +213,7 @@ def test_pair_blocks_sampled(nlq_ctx, oracle_lib, dim, n, kd, ed, lmax, precisio
     ms = pm[pick]
     got = s.pair_blocks(ls, ms)
     om = O.OracleMesh(mesh.coords, mesh.conn)
-    prm = O.params(delta, eps, lmax)
+    prm = O.params(delta, eps, lmax, form=form)
     ref = np.stack([O.pair_block(om, prm, int(ls[k]), int(ms[k]))[0] for k in range(len(pick))])
     stacked = _rel(got, ref)
     scale = max(np.linalg.norm(r) for r in ref)
@@ -445,4 +448,41 @@ def test_band_edge_blocks(nlq_ctx, oracle_lib, precision, dim, n, kd, ed, lmax):
         assert np.all(errs[mid] <= 1e-4)
         assert np.all(errs[small] <= 1e-2)
     s.close()
+    m.close()
+
+
+def test_adaptive_side_ablation(nlq_ctx):
+    """Section 5: adaptive quadrature on the outer integral of the two-term form
+    (the paper's choice, NLQ_FORM_PAPER2) against the same form with the inner
+    integral adaptive (NLQ_FORM_PAPER2_INNER).  Both cost the same evaluations
+    here (the pair list is symmetric); what differs is the quadrature error of
+    the solution: ||u_L - u_ref|| / ||u_ref|| with u_ref the four-term solution at
+    L_max = 6, FP64, 2D 24^2, delta = 3h, eps = delta/8, u = x1^2 + x2^2.
+    Both errors shrink as L_max grows (reported in the measurement notes)."""
+    import torch
+    from paper_2101_08825_amd import nlq
+    mesh = W.kuhn_mesh(2, 24, 3)
+    uq = W.Quadratic(np.ones(2))
+    _, f, g = W.nodal_data(mesh, uq)
+    delta = 3 / 24
+    eps = delta / 8
+    m = nlq.Mesh.create(nlq_ctx, mesh.coords, mesh.conn, mesh.constrained)
+
+    def solve(form, lmax):
+        s = nlq.System(nlq_ctx, m, nlq.params(2, delta, eps, lmax, form=form, precision=nlq.NLQ_FP64_PLAIN))
+        s.set_data(f, g)
+        u, info = s.solve(rtol=1e-13, maxit=5000)
+        leaves = int(np.sum(s.info().n_leaf))
+        s.close()
+        return u, leaves
+    u_ref, _ = solve(0, 6)
+    errs = {1: [], 2: []}
+    for lmax in range(1, 6):
+        for form in (1, 2):
+            u, leaves = solve(form, lmax)
+            errs[form].append(float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)))
+        print(f"  L_max {lmax}: leaves {leaves}  adaptive outer {errs[1][-1]:.3e}  adaptive inner {errs[2][-1]:.3e}",
+              flush=True)
+    for form in (1, 2):
+        assert errs[form][-1] < errs[form][0]
     m.close()

@@ -602,6 +602,58 @@ def test_algorithm1_equals_uniform_outer_refinement(oracle_lib, dim, n, kd, q, l
     assert np.linalg.norm(A2 - Au) > 1e-6 * np.linalg.norm(Au)
 
 
+def _brute_two_term_inner(mesh, delta, eps, C, depth, bary, w):
+    """The two-term form 2 A21 + 2 A22 of the Corollary (Section 5, eqs. J21N,
+    J22N, with R2's minus sign) with the ADAPTIVE SIDE SWAPPED: the outer
+    integral by the Gauss rule on the whole element l, the inner one on the
+    element m split uniformly `depth` times (no pruning), rows of the inner test
+    function phi_i(y):  A[m_i, Q] += 2 g phi_i(y) (phi_Q(y) - phi_Q(x)) over
+    every ordered element pair.  numpy, independent of the oracle."""
+    dim = mesh.dim
+    lx, wx = _composite_rule(dim, 0, bary, w)
+    ly, wy = _composite_rule(dim, depth, bary, w)
+    V = mesh.coords[mesh.conn]
+    X = np.einsum("qv,evd->eqd", lx, V)
+    Y = np.einsum("qv,evd->eqd", ly, V)
+    meas = np.array([_measure(v) for v in V])
+    A = np.zeros((mesh.n_nodes, mesh.n_nodes))
+    for l in range(mesh.n_elems):
+        for mm in range(mesh.n_elems):
+            d = np.sqrt(((X[l][:, None, :] - Y[mm][None, :, :]) ** 2).sum(-1))
+            G = C * _numpy_mu(d, delta, eps) * np.outer(wx * meas[l], wy * meas[mm])   # [a (x in l), b (y in m)]
+            il, im = mesh.conn[l], mesh.conn[mm]
+            # rows m_i: 2 sum_ab G_ab phi_i(y_b) (phi_j(y_b) - phi_j(x_a)), j over nodes of m and of l
+            A[np.ix_(im, im)] += 2 * ly.T @ (G.sum(0)[:, None] * ly)
+            A[np.ix_(im, il)] -= 2 * ly.T @ G.T @ lx
+    return A
+
+
+@pytest.mark.parametrize("dim,n,kd,q,lmax", [(2, 4, 2, 4, 3), (2, 5, 2, 16, 3), (3, 2, 2, 4, 2)])
+def test_adaptive_inner_two_term_form(oracle_lib, dim, n, kd, q, lmax):
+    """Form 2 (Section 5: which integral is adaptive is an empirical choice)
+    equals the two-term form with the INNER integral refined (uniformly to
+    L_max - 1 levels; with eta = 1 Algorithm 1's coarse pieces have constant or
+    zero gamma and the integrand is quadratic in the refined variable, so the
+    adaptive and the uniform rules agree) and rows of the inner test function,
+    summed over all ordered element pairs.  Row sums are zero; the matrix is not
+    symmetric; it differs from the adaptive-outer two-term form (form 1)."""
+    O = oracle_lib
+    mesh = W.kuhn_mesh(dim, n, 0)
+    delta = kd / n + 0.37 / n
+    eps = delta / q
+    C = O.kernel_constant(dim, 0, delta, eps)
+    bary, w = O.rule(dim)
+    Ab = _brute_two_term_inner(mesh, delta, eps, C, lmax - 1, bary, w)
+    m, off, pm, rp, col, val, leaves, evals = _assemble(O, mesh, O.params(delta, eps, lmax, form=2))
+    assert leaves[1:lmax].sum() > 0
+    A = _dense(rp, col, val, mesh.n_nodes)
+    assert np.linalg.norm(A - Ab) <= 1e-13 * np.linalg.norm(Ab)
+    assert np.abs(A.sum(1)).max() <= 1e-13 * np.abs(A).sum(1).max()
+    assert np.linalg.norm(A - A.T) > 1e-8 * np.linalg.norm(A)
+    A1 = _dense(*_assemble(O, mesh, O.params(delta, eps, lmax, form=1))[3:6], mesh.n_nodes)
+    assert np.linalg.norm(A1 - A) > 1e-8 * np.linalg.norm(A)
+
+
 @pytest.mark.parametrize("dim,n,kd,q,lmin,lmax", [(2, 4, 2, 4, 2, 4), (2, 4, 2, 4, 3, 4), (3, 2, 2, 4, 2, 3)])
 def test_algorithm1_lmin_equals_uniform_outer_refinement(oracle_lib, dim, n, kd, q, lmin, lmax):
     """Algorithm 1 with L_min > 1: every sub-element above level L_min is split
