@@ -32,7 +32,7 @@ _lib = None
 
 class _Mesh(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_nodes", C.c_int64), ("n_elems", C.c_int64),
-                ("coords", C.c_void_p), ("conn", C.c_void_p)]
+                ("coords", C.c_void_p), ("conn", C.c_void_p), ("order", C.c_int32)]
 
 
 class _Params(C.Structure):
@@ -86,6 +86,8 @@ def lib():
         L.or_lift.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
         L.or_cg.restype = i32
         L.or_cg.argtypes = [i64, vp, vp, vp, vp, vp, d, i32, vp, vp]
+        L.or_lu_solve.restype = i32
+        L.or_lu_solve.argtypes = [i64, vp, vp, vp, vp, vp, vp]
         L.or_cholesky_solve.restype = i32
         L.or_cholesky_solve.argtypes = [i64, vp, vp, vp, vp, vp, vp]
         _lib = L
@@ -103,12 +105,17 @@ def default_threads() -> int:
 class OracleMesh:
     """Holds the arrays alive for the C struct."""
 
-    def __init__(self, coords, conn):
+    def __init__(self, coords, conn, order=1):
         self.coords = np.ascontiguousarray(coords, dtype=np.float64)
         self.conn = np.ascontiguousarray(conn, dtype=np.int32)
         self.dim = int(self.coords.shape[1])
+        self.order = int(order)
+        nb = (self.dim + 1) * (self.dim + 2) // 2 if self.order == 2 else self.dim + 1
+        if self.conn.shape[1] != nb:
+            raise ValueError(f"order {order} elements need {nb} nodes, conn has {self.conn.shape[1]}")
+        self.nb = nb
         self.s = _Mesh(self.dim, self.coords.shape[0], self.conn.shape[0],
-                       self.coords.ctypes.data, self.conn.ctypes.data)
+                       self.coords.ctypes.data, self.conn.ctypes.data, self.order)
 
     @property
     def ref(self):
@@ -187,8 +194,7 @@ def pattern(mesh: OracleMesh, off, pm):
 
 
 def pair_block(mesh: OracleMesh, prm, l: int, m: int, lmax: int | None = None):
-    dim = mesh.dim
-    ne2 = 2 * (dim + 1)
+    ne2 = 2 * mesh.nb
     E = np.zeros((ne2, ne2))
     leaves = np.zeros(16, dtype=np.int64)
     evals = np.zeros(2, dtype=np.int64)
@@ -291,15 +297,27 @@ def cholesky_solve(row_ptr, col, val, constrained, rhs):
     return w
 
 
+def lu_solve(row_ptr, col, val, constrained, rhs):
+    """Dense LU with partial pivoting on the free block (non-symmetric matrices)."""
+    n = row_ptr.shape[0] - 1
+    w = np.zeros(n)
+    cst = np.ascontiguousarray(constrained, dtype=np.uint8)
+    b = np.ascontiguousarray(rhs, dtype=np.float64)
+    st = lib().or_lu_solve(n, _p(row_ptr), _p(col), _p(val), _p(cst), _p(b), _p(w))
+    if st != 0:
+        raise RuntimeError(f"lu failed ({st})")
+    return w
+
+
 class Solution:
     pass
 
 
 def solve_problem(mesh_arrays, prm, f_nodal, g_nodal, rtol=1e-14, nthreads=None,
-                  direct=False):
+                  direct=False, order=1):
     """Full oracle pipeline: pairs, pattern, assembly, load, lifting, solve."""
     coords, conn, constrained = mesh_arrays
-    m = OracleMesh(coords, conn)
+    m = OracleMesh(coords, conn, order)
     thr = prm.delta + prm.eps
     s = Solution()
     s.off, s.pm = pairs(m, thr, nthreads)
@@ -308,7 +326,11 @@ def solve_problem(mesh_arrays, prm, f_nodal, g_nodal, rtol=1e-14, nthreads=None,
                                         nthreads=nthreads)
     s.F = load(m, f_nodal, constrained)
     s.Ft = lift(s.row_ptr, s.col, s.val, constrained, g_nodal, s.F)
-    if direct:
+    if prm.form != 0:
+        # the two-term forms are not symmetric: Gaussian elimination (CG does not apply)
+        w = lu_solve(s.row_ptr, s.col, s.val, constrained, s.Ft)
+        s.iters, s.relres = 0, 0.0
+    elif direct:
         w = cholesky_solve(s.row_ptr, s.col, s.val, constrained, s.Ft)
         s.iters, s.relres = 0, 0.0
     else:

@@ -292,11 +292,13 @@ static void bbox_of(int dim, int nv, const double *v, double *lo, double *hi)
         }
 }
 
+static int nodes_of(const or_mesh *m);
+
 static void elem_vertices(const or_mesh *m, int64_t e, double *v)
 {
-    int nv = m->dim + 1;
+    int nv = m->dim + 1, nb = nodes_of(m);
     for (int i = 0; i < nv; ++i) {
-        int64_t node = m->conn[e * nv + i];
+        int64_t node = m->conn[e * nb + i];
         for (int k = 0; k < m->dim; ++k) v[i * m->dim + k] = m->coords[node * m->dim + k];
     }
 }
@@ -444,7 +446,7 @@ typedef struct {
 static adjacency node_elements(const or_mesh *m)
 {
     adjacency a;
-    int nv = m->dim + 1;
+    int nv = nodes_of(m);
     a.off = (int64_t *)calloc(m->n_nodes + 1, sizeof(int64_t));
     for (int64_t e = 0; e < m->n_elems; ++e)
         for (int i = 0; i < nv; ++i) a.off[m->conn[e * nv + i] + 1]++;
@@ -493,7 +495,7 @@ static int64_t row_columns(const or_mesh *m, const adjacency *ne_adj, const int6
                            const int32_t *pm, const adjacency *tr, int64_t i, int32_t *mark,
                            int32_t *buf)
 {
-    int nv = m->dim + 1;
+    int nv = nodes_of(m);
     int64_t cnt = 0;
 #define ADD_ELEM_NODES(E_)                                   \
     do {                                                     \
@@ -550,6 +552,7 @@ typedef struct {
     const or_mesh *mesh;
     const or_params *p;
     int dim, nv, nq;
+    int nb;              /* nodes per element (the basis functions of one element) */
     double bary[MAXQ * MAXV], w[MAXQ];
     double C, dme, dpe;
     int64_t l;
@@ -564,7 +567,28 @@ typedef struct {
     int count_only;      /* 1: Integration() only counts its (sub-element, m) leaves */
 } alg_ctx;
 
-static int ext(int nv) { return 2 * nv; }
+/* nodes per element: P1 the dim+1 vertices, P2 also the edge midpoints */
+static int nodes_of(const or_mesh *m)
+{
+    return m->order == 2 ? (m->dim + 1) * (m->dim + 2) / 2 : m->dim + 1;
+}
+
+/* Lagrange basis of the element at barycentric coordinates lam (nv = dim+1):
+ * P1 lam_i; P2 lam_i (2 lam_i - 1) at the vertices and 4 lam_i lam_j at the edge
+ * midpoints, edges (i < j) in lexicographic order. */
+static void basis(int order, int nv, const double *lam, double *phi)
+{
+    if (order != 2) {
+        for (int i = 0; i < nv; ++i) phi[i] = lam[i];
+        return;
+    }
+    for (int i = 0; i < nv; ++i) phi[i] = lam[i] * (2.0 * lam[i] - 1.0);
+    int k = nv;
+    for (int i = 0; i < nv; ++i)
+        for (int j = i + 1; j < nv; ++j) phi[k++] = 4.0 * lam[i] * lam[j];
+}
+
+#define MAXB 10   /* nodes per element, P2 tetrahedron */
 
 /* Integration(E_s, J'): the double Gauss loop of eqs. (J21Nr)/(J22Nr) over the
  * outer sub-element s (level `level`) and every whole inner element m in J'.
@@ -589,9 +613,9 @@ static void integration(alg_ctx *c, int level, const double *V, const double *La
         c->leaves[level] += nJ;
         return;
     }
-    int dim = c->dim, nv = c->nv, nq = c->nq, ne2 = ext(nv);
+    int dim = c->dim, nv = c->nv, nq = c->nq, nb = c->nb, ne2 = 2 * nb;
     double ws = ldexp(c->meas_l, -dim * (level - 1));
-    double x[MAXQ][3], lam[MAXQ][MAXV];
+    double x[MAXQ][3], lam[MAXQ][MAXV], phx[MAXQ][MAXB], phy[MAXQ][MAXB];
     for (int a = 0; a < nq; ++a) {
         for (int k = 0; k < dim; ++k) {
             double s = 0.0;
@@ -603,6 +627,8 @@ static void integration(alg_ctx *c, int level, const double *V, const double *La
             for (int v = 0; v < nv; ++v) s += c->bary[a * nv + v] * Lam[v * nv + i];
             lam[a][i] = s;
         }
+        basis(c->mesh->order, nv, lam[a], phx[a]);
+        basis(c->mesh->order, nv, c->bary + a * nv, phy[a]);
     }
     for (int t = 0; t < nJ; ++t) {
         int pos = Jpos[t];
@@ -629,21 +655,21 @@ static void integration(alg_ctx *c, int level, const double *V, const double *La
                            or_mu(d, c->p->delta, c->p->eps) * Wa * Wb;
                 c->evals[0]++;
                 if (d >= c->dme && d <= c->dpe) c->evals[1]++;
-                double z[2 * MAXV];
-                for (int i = 0; i < nv; ++i) {
-                    z[i] = lam[a][i];
-                    z[nv + i] = -c->bary[b * nv + i];
+                double z[2 * MAXB];
+                for (int i = 0; i < nb; ++i) {
+                    z[i] = phx[a][i];
+                    z[nb + i] = -phy[b][i];
                 }
                 if (c->p->form == 0) {
                     for (int P = 0; P < ne2; ++P)
                         for (int Q = 0; Q < ne2; ++Q) E[P * ne2 + Q] += g * z[P] * z[Q];
                 } else if (c->p->form == 1) {
-                    for (int bb = 0; bb < nv; ++bb)
+                    for (int bb = 0; bb < nb; ++bb)
                         for (int Q = 0; Q < ne2; ++Q)
-                            E[(nv + bb) * ne2 + Q] += 2.0 * g * c->bary[b * nv + bb] * (-z[Q]);
+                            E[(nb + bb) * ne2 + Q] += 2.0 * g * phy[b][bb] * (-z[Q]);
                 } else {
-                    for (int aa = 0; aa < nv; ++aa)
-                        for (int Q = 0; Q < ne2; ++Q) E[aa * ne2 + Q] += 2.0 * g * lam[a][aa] * z[Q];
+                    for (int aa = 0; aa < nb; ++aa)
+                        for (int Q = 0; Q < ne2; ++Q) E[aa * ne2 + Q] += 2.0 * g * phx[a][aa] * z[Q];
                 }
             }
         }
@@ -704,6 +730,7 @@ static void ctx_init(alg_ctx *c, const or_mesh *m, const or_params *p, int64_t *
     c->dim = m->dim;
     c->nv = m->dim + 1;
     c->nq = or_rule(m->dim, c->bary, c->w);
+    c->nb = nodes_of(m);
     c->C = (p->scale > 0.0) ? p->scale : or_kernel_constant(m->dim, p->kernel, p->delta, p->eps);
     c->dme = p->delta - p->eps;
     c->dpe = p->delta + p->eps;
@@ -719,7 +746,7 @@ static void run_outer(alg_ctx *c, int64_t l, const int32_t *J, int n, double *E)
     c->meas_l = or_elem_measure(c->mesh, l);
     c->J = J;
     c->E = E;
-    memset(E, 0, sizeof(double) * (size_t)n * ext(nv) * ext(nv));
+    memset(E, 0, sizeof(double) * (size_t)n * (2 * c->nb) * (2 * c->nb));
     double V[MAXV * 3], Lam[MAXV * MAXV];
     c->jlo = (double *)malloc(sizeof(double) * (size_t)(n + 1) * dim);
     c->jhi = (double *)malloc(sizeof(double) * (size_t)(n + 1) * dim);
@@ -813,7 +840,7 @@ static void *asm_worker(void *arg)
 {
     asm_job *j = (asm_job *)arg;
     const or_mesh *m = j->m;
-    int nv = m->dim + 1, ne2 = 2 * nv;
+    int nv = nodes_of(m), ne2 = 2 * nv;
     alg_ctx c;
     ctx_init(&c, m, j->p, j->leaves);
     int64_t maxn = 0;
@@ -914,7 +941,7 @@ static void *count_worker(void *arg)
 {
     count_job *j = (count_job *)arg;
     const or_mesh *m = j->m;
-    int ne2 = 2 * (m->dim + 1);
+    int ne2 = 2 * nodes_of(m);
     alg_ctx c;
     ctx_init(&c, m, j->p, j->leaves);
     c.count_only = !j->evaluate;
@@ -1021,8 +1048,8 @@ static void *rows_worker(void *arg)
 {
     rows_job *j = (rows_job *)arg;
     const or_mesh *m = j->m;
-    int nv = m->dim + 1, ne2 = 2 * nv;
-    double E[64];
+    int nv = nodes_of(m), ne2 = 2 * nv;
+    double E[4 * MAXB * MAXB];
     int64_t leaves[16] = {0};
     for (int64_t t = j->i0; t < j->i1; ++t) {
         int64_t l = j->pairs[t].l, mm = j->pairs[t].m;
@@ -1057,7 +1084,7 @@ int64_t or_rows(const or_mesh *m, const or_params *p, double thr, int32_t nthrea
                 double *vals)
 {
     int64_t ne = m->n_elems;
-    int nv = m->dim + 1;
+    int nv = nodes_of(m);
     double *lo = (double *)malloc(sizeof(double) * ne * m->dim);
     double *hi = (double *)malloc(sizeof(double) * ne * m->dim);
     all_bboxes(m, lo, hi);
@@ -1156,23 +1183,26 @@ int64_t or_rows(const or_mesh *m, const or_params *p, double thr, int32_t nthrea
 /* ------------------------------------------------------------ load, lifting, solve */
 
 /* F_i = int_Omega f_h phi_i for free nodes i (Section 2, eq. (A-F)); f_h is the
- * P1 interpolant of the nodal f; the degree-5 rule integrates f_h phi_i exactly. */
+ * interpolant of the nodal f in the element's space (P1 or P2); the degree-5 rule
+ * integrates f_h phi_i exactly for P1 and for P2 with f_h of degree <= 3 (every
+ * configuration has constant f). */
 void or_load(const or_mesh *m, const double *f_nodal, const uint8_t *constrained, double *F)
 {
-    int nv = m->dim + 1;
-    double bary[MAXQ * MAXV], w[MAXQ];
+    int nv = m->dim + 1, nb = nodes_of(m);
+    double bary[MAXQ * MAXV], w[MAXQ], phi[MAXQ][MAXB];
     int nq = or_rule(m->dim, bary, w);
+    for (int q = 0; q < nq; ++q) basis(m->order, nv, bary + q * nv, phi[q]);
     for (int64_t n = 0; n < m->n_nodes; ++n) F[n] = 0.0;
     for (int64_t e = 0; e < m->n_elems; ++e) {
         double meas = or_elem_measure(m, e);
-        for (int a = 0; a < nv; ++a) {
-            int32_t node = m->conn[e * nv + a];
+        for (int a = 0; a < nb; ++a) {
+            int32_t node = m->conn[e * nb + a];
             if (constrained[node]) continue;
             double s = 0.0;
             for (int q = 0; q < nq; ++q) {
                 double fq = 0.0;
-                for (int j = 0; j < nv; ++j) fq += f_nodal[m->conn[e * nv + j]] * bary[q * nv + j];
-                s += w[q] * meas * fq * bary[q * nv + a];
+                for (int j = 0; j < nb; ++j) fq += f_nodal[m->conn[e * nb + j]] * phi[q][j];
+                s += w[q] * meas * fq * phi[q][a];
             }
             F[node] += s;
         }
@@ -1278,6 +1308,67 @@ done:
     free(q);
     free(dinv);
     return it;
+}
+
+/* Dense Gaussian elimination with partial pivoting on the free block (for the
+ * two-term forms, whose matrices are not symmetric); same arguments as
+ * or_cholesky_solve.  Returns 0, -1 (too large) or -2 (singular). */
+int32_t or_lu_solve(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                    const uint8_t *constrained, const double *rhs, double *w)
+{
+    int64_t *map = (int64_t *)malloc(sizeof(int64_t) * n);
+    int64_t nf = 0;
+    for (int64_t i = 0; i < n; ++i) map[i] = constrained[i] ? -1 : nf++;
+    if (nf > 6000) {
+        free(map);
+        return -1;
+    }
+    double *M = (double *)calloc((size_t)(nf * nf + 1), sizeof(double));
+    double *b = (double *)calloc((size_t)(nf + 1), sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        if (map[i] < 0) continue;
+        b[map[i]] = rhs[i];
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            if (map[col[k]] >= 0) M[map[i] * nf + map[col[k]]] = val[k];
+    }
+    int32_t st = 0;
+    for (int64_t c = 0; c < nf && st == 0; ++c) {
+        int64_t piv = c;
+        for (int64_t r = c + 1; r < nf; ++r)
+            if (fabs(M[r * nf + c]) > fabs(M[piv * nf + c])) piv = r;
+        if (M[piv * nf + c] == 0.0) {
+            st = -2;
+            break;
+        }
+        if (piv != c) {
+            for (int64_t k = 0; k < nf; ++k) {
+                double t = M[c * nf + k];
+                M[c * nf + k] = M[piv * nf + k];
+                M[piv * nf + k] = t;
+            }
+            double t = b[c];
+            b[c] = b[piv];
+            b[piv] = t;
+        }
+        for (int64_t r = c + 1; r < nf; ++r) {
+            double f = M[r * nf + c] / M[c * nf + c];
+            if (f == 0.0) continue;
+            for (int64_t k = c; k < nf; ++k) M[r * nf + k] -= f * M[c * nf + k];
+            b[r] -= f * b[c];
+        }
+    }
+    if (st == 0) {
+        for (int64_t r = nf - 1; r >= 0; --r) {
+            double t = b[r];
+            for (int64_t k = r + 1; k < nf; ++k) t -= M[r * nf + k] * b[k];
+            b[r] = t / M[r * nf + r];
+        }
+        for (int64_t i = 0; i < n; ++i) w[i] = map[i] >= 0 ? b[map[i]] : 0.0;
+    }
+    free(M);
+    free(b);
+    free(map);
+    return st;
 }
 
 /* Dense Cholesky solve of A_{Omega,Omega} w = rhs_Omega (small systems only). */

@@ -24,7 +24,10 @@ typedef struct {
     int64_t n_nodes;
     int64_t n_elems;
     const double *coords;   /* [n_nodes][dim] */
-    const int32_t *conn;    /* [n_elems][dim+1] */
+    const int32_t *conn;    /* [n_elems][nodes per element] */
+    int32_t order;          /* 1: P1 (dim+1 vertices); 2: P2 Lagrange, the vertices then the
+                               edge midpoints in the order (0,1),(0,2),(1,2) [2D],
+                               (0,1),(0,2),(0,3),(1,2),(1,3),(2,3) [3D]; straight sides */
 } or_mesh;
 
 typedef struct {
@@ -85,6 +88,8 @@ void or_lift(int64_t n, const int64_t *row_ptr, const int32_t *col, const double
 int32_t or_cg(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
               const uint8_t *constrained, const double *rhs, double rtol, int32_t maxit,
               double *w, double *relres);
+int32_t or_lu_solve(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                    const uint8_t *constrained, const double *rhs, double *w);
 int32_t or_cholesky_solve(int64_t n, const int64_t *row_ptr, const int32_t *col,
                           const double *val, const uint8_t *constrained,
                           const double *rhs, double *w);

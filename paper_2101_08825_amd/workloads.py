@@ -99,6 +99,40 @@ def kuhn_mesh(dim: int, n: int, k_gamma: int) -> Mesh:
                 constrained=constrained, k_gamma=k_gamma)
 
 
+def kuhn_mesh_p2(dim: int, n: int, k_gamma: int) -> Mesh:
+    """The Kuhn mesh of `kuhn_mesh` with P2 Lagrange elements: nodes on the grid of
+    spacing h/2, x = i/(2n) (one correctly rounded FP64 division), node id =
+    i0 + (2n+1)(i1 + (2n+1) i2); element e has the vertices of the P1 element e
+    (at even grid indices) followed by its edge midpoints in the order (0,1),
+    (0,2), (1,2) [2D] or (0,1), (0,2), (0,3), (1,2), (1,3), (2,3) [3D].  A node
+    is constrained when some index i_k <= 2K or i_k >= 2n - 2K (the same layer of
+    K cells)."""
+    p1 = kuhn_mesh(dim, n, k_gamma)
+    nn = 2 * n + 1
+    idx = np.arange(nn, dtype=np.int64)
+    if dim == 2:
+        i1, i0 = np.meshgrid(idx, idx, indexing="ij")
+        ii = [i0.ravel(), i1.ravel()]
+    else:
+        i2, i1, i0 = np.meshgrid(idx, idx, idx, indexing="ij")
+        ii = [i0.ravel(), i1.ravel(), i2.ravel()]
+    coords = np.stack([k.astype(np.float64) / float(2 * n) for k in ii], axis=1)
+    constrained = np.zeros(coords.shape[0], dtype=np.uint8)
+    for k in ii:
+        constrained |= ((k <= 2 * k_gamma) | (k >= 2 * n - 2 * k_gamma)).astype(np.uint8)
+    # P1 node id -> fine grid index vector (even entries)
+    p1_idx = np.stack(np.unravel_index(np.arange(p1.n_nodes), [n + 1] * dim, order="F"), axis=1) * 2
+    fine = lambda v: sum(v[..., k] * nn ** k for k in range(dim))
+    V = p1_idx[p1.conn]                       # [e, nv, dim] fine indices of the vertices
+    nv = dim + 1
+    cols = [fine(V[:, i, :]) for i in range(nv)]
+    for i in range(nv):
+        for j in range(i + 1, nv):
+            cols.append(fine((V[:, i, :] + V[:, j, :]) // 2))
+    conn = np.stack(cols, axis=1).astype(np.int32)
+    return Mesh(dim=dim, n=n, coords=coords, conn=conn, constrained=constrained, k_gamma=k_gamma)
+
+
 def jittered_mesh(dim: int, n: int, k_gamma: int, frac: float = 0.2, seed: int = 0) -> Mesh:
     """The Kuhn mesh of `kuhn_mesh` with every node that is not on the boundary of
     [0,1]^dim moved by independent U(-frac h, frac h) offsets per coordinate
