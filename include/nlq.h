@@ -162,6 +162,16 @@ nlq_status nlq_ctx_destroy(nlq_ctx *ctx);
 nlq_status nlq_mesh_create(nlq_ctx *ctx, int32_t dim, int64_t n_nodes, const double *coords,
                            int64_t n_elems, const int32_t *conn, const uint8_t *constrained,
                            nlq_mesh **out);
+/* As nlq_mesh_create with element order `order`: 1 (P1, conn [e][dim+1]) or 2
+ * (quadratic Lagrange elements with straight sides, conn [e][(dim+1)(dim+2)/2]:
+ * the dim+1 vertices, then the edge midpoints in the order (0,1), (0,2), (1,2)
+ * in 2D and (0,1), (0,2), (0,3), (1,2), (1,3), (2,3) in 3D).  The geometry (boxes,
+ * pair list, refinement) uses the vertices; the pattern, blocks, load vector and
+ * solution all the nodes (Section 4: Lagrange bases; Section 6.1 uses linear and
+ * quadratic ones).  P2 systems are assembled in FP64 (NLQ_FP64_PLAIN), without
+ * deterministic mode. */
+nlq_status nlq_mesh_create_order(nlq_ctx *ctx, int32_t dim, int32_t order, int64_t n_nodes, const double *coords,
+                                 int64_t n_elems, const int32_t *conn, const uint8_t *constrained, nlq_mesh **out);
 /* Kuhn mesh of [0,1]^dim with n cells per direction built on the device:
  * x = i/n, node id = i0 + (n+1)(i1 + (n+1) i2), element id = dim!*cell + p with
  * p the lexicographic index of the permutation of the Kuhn path; Gamma = nodes
@@ -169,7 +179,7 @@ nlq_status nlq_mesh_create(nlq_ctx *ctx, int32_t dim, int64_t n_nodes, const dou
 nlq_status nlq_mesh_box(nlq_ctx *ctx, int32_t dim, int32_t n, int32_t k_gamma, nlq_mesh **out);
 nlq_status nlq_mesh_info(const nlq_mesh *mesh, int32_t *dim, int64_t *n_nodes, int64_t *n_elems,
                          int64_t *n_free);
-/* Host copies of a mesh (coords [n][dim], conn [e][dim+1], constrained [n]). */
+/* Host copies of a mesh (coords [n][dim], conn [e][nodes per element], constrained [n]). */
 nlq_status nlq_mesh_copy(const nlq_mesh *mesh, double *coords, int32_t *conn, uint8_t *constrained);
 nlq_status nlq_mesh_destroy(nlq_mesh *mesh);
 
@@ -291,9 +301,10 @@ nlq_status nlq_pairs_copy(const nlq_system *sys, int64_t *offsets, int32_t *m);
 /* Host copy of F~ [n_rows] (0 on Gamma rows). */
 nlq_status nlq_rhs_copy(const nlq_system *sys, double *f_tilde);
 /* Per-pair blocks of selected ordered pairs (l[k], m[k]), recomputed with the
- * assembly kernels: out [n][2N+2][2N+2] in the extended index space
- * [local nodes of l, local nodes of m] (the four-term form fills all four
- * blocks, the two-term form the rows of m). */
+ * assembly kernels: out [n][2 nb][2 nb] (nb nodes per element: N+1 for P1,
+ * (N+1)(N+2)/2 for P2) in the extended index space [local nodes of l, local
+ * nodes of m] (the four-term form fills all four blocks, the two-term form the
+ * rows of m, its adaptive-inner variant the rows of l). */
 nlq_status nlq_pair_blocks(nlq_system *sys, int64_t n, const int32_t *l, const int32_t *m,
                            double *out);
 nlq_status nlq_system_destroy(nlq_system *sys);

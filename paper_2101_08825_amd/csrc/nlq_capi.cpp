@@ -168,6 +168,9 @@ void check_params(const Mesh &m, const nlq_params &p)
         fail(NLQ_EINVAL, "unknown form");
     if (p.form == NLQ_FORM_PAPER2_INNER && p.deterministic)
         fail(NLQ_EINVAL, "the adaptive-inner two-term form has no deterministic mode");
+    if (m.order == 2 && p.deterministic) fail(NLQ_EINVAL, "P2 elements have no deterministic mode");
+    if (m.order == 2 && p.precision != NLQ_FP64_PLAIN)
+        fail(NLQ_EINVAL, "P2 elements are integrated in FP64 (precision NLQ_FP64_PLAIN)");
     if (p.precision != NLQ_FP64_PLAIN && p.precision != NLQ_FP32_MIXED)
         fail(NLQ_EINVAL, "unknown precision");
     if (p.deterministic != 0 && p.deterministic != 1) fail(NLQ_EINVAL, "deterministic must be 0 or 1");
@@ -177,7 +180,7 @@ void check_params(const Mesh &m, const nlq_params &p)
 
 void mesh_stats(Mesh &m)
 {
-    const int dim = m.dim, nv = dim + 1;
+    const int dim = m.dim, nv = dim + 1, nb = m.nb;
     for (int k = 0; k < 3; ++k) {
         m.gmin[k] = 0.0;
         m.gmax[k] = 0.0;
@@ -197,7 +200,7 @@ void mesh_stats(Mesh &m)
     for (int64_t e = 0; e < m.n_elems; ++e) {
         double V[4][3];
         for (int v = 0; v < nv; ++v) {
-            const int32_t id = m.h_conn[e * nv + v];
+            const int32_t id = m.h_conn[e * nb + v];
             if (id < 0 || id >= m.n_nodes) fail(NLQ_EINVAL, "node id out of range in element " + std::to_string(e));
             for (int k = 0; k < dim; ++k) V[v][k] = m.h_coords[static_cast<int64_t>(id) * dim + k];
         }
@@ -223,6 +226,10 @@ void mesh_stats(Mesh &m)
                   a[2] * (b[0] * c[1] - b[1] * c[0]);
         }
         if (!(std::fabs(det) > 0.0)) fail(NLQ_EINVAL, "element " + std::to_string(e) + " has zero measure");
+        for (int v = nv; v < nb; ++v) {
+            const int32_t id = m.h_conn[e * nb + v];
+            if (id < 0 || id >= m.n_nodes) fail(NLQ_EINVAL, "node id out of range in element " + std::to_string(e));
+        }
     }
     m.n_free = 0;
     for (int64_t n = 0; n < m.n_nodes; ++n) m.n_free += m.h_constrained[n] ? 0 : 1;
@@ -230,7 +237,7 @@ void mesh_stats(Mesh &m)
 
 void upload_mesh(Mesh &m, hipStream_t st)
 {
-    const int nv = m.dim + 1;
+    const int nv = m.nb;
     m.coords.alloc(m.ctx, sizeof(double) * m.n_nodes * m.dim);
     m.conn.alloc(m.ctx, sizeof(int32_t) * m.n_elems * nv);
     m.constrained.alloc(m.ctx, m.n_nodes);
@@ -268,7 +275,7 @@ std::unique_ptr<nlq_system> prepare_system(Ctx &ctx, const Mesh &mesh, const nlq
     build_pattern(s, st);
     s.cfg = tuned_config(ctx, s);
     s.val.alloc(s.ctx, sizeof(double) * std::max<int64_t>(s.nnz, 1));
-    const int nr = mesh.dim == 2 ? 6 : 10;
+    const int nr = mesh.nb * (mesh.nb + 1) / 2;   // upper-triangle slots of a diagonal block
     s.dmm.alloc(s.ctx, sizeof(double) * std::max<int64_t>(mesh.n_elems * nr, 1));
     NLQ_HIP(hipStreamSynchronize(st));
     const double t3 = now_s();
@@ -341,6 +348,8 @@ std::unique_ptr<nlq_mesh> make_box_mesh(Ctx &ctx, int dim, int n, int k_gamma, h
     Mesh &M = m->impl;
     M.ctx = &ctx;
     M.dim = dim;
+    M.order = 1;
+    M.nb = dim + 1;
     M.n_nodes = nn;
     M.n_elems = ne;
     M.coords.alloc(M.ctx, sizeof(double) * nn * dim);
@@ -385,7 +394,9 @@ bool solve_system(System &s, double rtol, int maxit, double *u_out, nlq_solve_in
     const double t0 = now_s();
     double relres = 0.0;
     int converged = 0;
-    const int it = cg_solve(s, st, rtol, maxit, &relres, &converged);
+    // the two-term forms are not symmetric: BiCGSTAB instead of CG
+    const int it = s.p.form == NLQ_FORM_SYM4 ? cg_solve(s, st, rtol, maxit, &relres, &converged)
+                                             : bicgstab_solve(s, st, rtol, maxit, &relres, &converged);
     if (u_out) {
         NLQ_HIP(hipMemcpyAsync(u_out, s.u.as<void>(), sizeof(double) * s.mesh->n_nodes, hipMemcpyDeviceToHost, st));
         NLQ_HIP(hipStreamSynchronize(st));
@@ -475,13 +486,13 @@ nlq_status nlq_ctx_destroy(nlq_ctx *ctx)
     });
 }
 
-nlq_status nlq_mesh_create(nlq_ctx *ctx, int32_t dim, int64_t n_nodes, const double *coords,
-                           int64_t n_elems, const int32_t *conn, const uint8_t *constrained,
-                           nlq_mesh **out)
+nlq_status nlq_mesh_create_order(nlq_ctx *ctx, int32_t dim, int32_t order, int64_t n_nodes, const double *coords,
+                                 int64_t n_elems, const int32_t *conn, const uint8_t *constrained, nlq_mesh **out)
 {
     return guard([&] {
         if (!ctx || !out || !coords || !conn || !constrained) fail(NLQ_EINVAL, "NULL argument");
         if (dim != 2 && dim != 3) fail(NLQ_EINVAL, "dim must be 2 or 3");
+        if (order != 1 && order != 2) fail(NLQ_EINVAL, "order must be 1 or 2");
         if (n_nodes < dim + 1 || n_elems < 1) fail(NLQ_EINVAL, "empty mesh");
         if (n_nodes > INT32_MAX || n_elems > INT32_MAX) fail(NLQ_EINVAL, "mesh too large for int32 ids");
         NLQ_HIP(hipSetDevice(ctx->impl.device));
@@ -489,16 +500,25 @@ nlq_status nlq_mesh_create(nlq_ctx *ctx, int32_t dim, int64_t n_nodes, const dou
         Mesh &M = m->impl;
         M.ctx = &ctx->impl;
         M.dim = dim;
+        M.order = order;
+        M.nb = order == 2 ? (dim + 1) * (dim + 2) / 2 : dim + 1;
         M.n_nodes = n_nodes;
         M.n_elems = n_elems;
         M.h_coords.assign(coords, coords + n_nodes * dim);
-        M.h_conn.assign(conn, conn + n_elems * (dim + 1));
+        M.h_conn.assign(conn, conn + n_elems * M.nb);
         M.h_constrained.assign(constrained, constrained + n_nodes);
         for (auto &c : M.h_constrained) c = c ? 1 : 0;
         mesh_stats(M);
         upload_mesh(M, ctx->impl.stream);
         *out = m.release();
     });
+}
+
+nlq_status nlq_mesh_create(nlq_ctx *ctx, int32_t dim, int64_t n_nodes, const double *coords,
+                           int64_t n_elems, const int32_t *conn, const uint8_t *constrained,
+                           nlq_mesh **out)
+{
+    return nlq_mesh_create_order(ctx, dim, 1, n_nodes, coords, n_elems, conn, constrained, out);
 }
 
 nlq_status nlq_mesh_box(nlq_ctx *ctx, int32_t dim, int32_t n, int32_t k_gamma, nlq_mesh **out)
@@ -834,6 +854,8 @@ nlq_status nlq_solve_noalloc(nlq_system *sys, double rtol, int32_t maxit, double
         if (!sys || !u_dev) fail(NLQ_EINVAL, "NULL argument");
         System &s = sys->impl;
         if (!s.has_rhs) fail(NLQ_EINVAL, "nlq_set_data must be called before nlq_solve_noalloc");
+        if (s.p.form != NLQ_FORM_SYM4)
+            fail(NLQ_EINVAL, "nlq_solve_noalloc runs CG: four-term form only (the two-term forms need nlq_solve)");
         if (!(rtol > 0.0) || maxit < 1) fail(NLQ_EINVAL, "need rtol > 0 and maxit >= 1");
         NLQ_HIP(hipSetDevice(s.ctx->device));
         const double t0 = now_s();
@@ -931,7 +953,7 @@ nlq_status nlq_pair_blocks(nlq_system *sys, int64_t n, const int32_t *l, const i
         if (n > (1ll << 30)) fail(NLQ_EINVAL, "too many pairs");
         NLQ_HIP(hipSetDevice(s.ctx->device));
         hipStream_t st = s.ctx->stream;
-        const int nv = s.mesh->dim + 1;
+        const int nv = s.mesh->nb;
         const size_t blk = static_cast<size_t>(4 * nv * nv);
         DevBuf dl(s.ctx, sizeof(int32_t) * n), dm(s.ctx, sizeof(int32_t) * n),
             dout(s.ctx, sizeof(double) * n * blk);

@@ -44,6 +44,7 @@
 
 #include "nlq_device.hpp"
 #include "nlq_internal.hpp"
+#include "nlq_p2.hpp"
 #include "nlq_refine.hpp"
 
 namespace nlq {
@@ -73,6 +74,20 @@ template <int DIM> struct Shape {
     static constexpr int NR = NV + NOFF;
 };
 
+// What the element order changes: nodes per element NB, contraction rows NR
+// (P1: lambda_i and lambda_i lambda_j; P2: the quartic monomials of nlq_p2.hpp),
+// upper-triangle slots NU of a diagonal block, per-pair outputs NOUT
+// (B_lm, then the upper triangles of B_mm and B_ll).
+template <int DIM, int ORD> struct OShape {
+    static constexpr int NV = DIM + 1;
+    static constexpr int NB = ORD == 1 ? NV : p2_nodes(DIM);
+    static constexpr int NR = ORD == 1 ? Shape<DIM>::NR : p2_monomials(DIM);
+    static constexpr int NU = NB * (NB + 1) / 2;
+    static constexpr int NOUT = NB * NB + 2 * NU;
+    // P2 epilogue rows mapped from the monomial rows (make_p2_map)
+    static constexpr int NRX = NU + NB + 1;
+};
+
 struct AsmArgs {
     int64_t ne;
     const int64_t *pair_off;
@@ -91,6 +106,8 @@ struct AsmArgs {
     const int32_t *tmap;
     const int32_t *elpos;
     double *val;
+    int nb;               // nodes per element (conn stride): dim + 1 (P1) or (dim+1)(dim+2)/2 (P2)
+    const double *p2map;  // P2: [NRX][NR] map from the monomial rows to the epilogue rows
     const double *lam64;  // [sub][nq][nv]
     const float *pt32;    // rows of the FP32 contraction per point (see the tables)
     int pt32_zero;        // its zero row
@@ -102,7 +119,7 @@ struct AsmArgs {
     const double *rule;   // [nq][nv] barycentric points, then [nq] weights
     double delta, eps, dme, dpe, dme2, dpe2, C;
     double dme_sq;        // s* with (sqrt(s) < delta - eps) <=> (s < s*), s >= 0
-    double *dmm;          // [ne][NR] upper-triangle diagonal-block sums per element
+    double *dmm;          // [ne][NU] upper-triangle diagonal-block sums per element
     float f_inv_eps, f_delta_over_eps, f_inv_delta2;
     float f_dme2, f_dpe2;  // (delta - eps)^2, (delta + eps)^2 in FP32: the band test of a tile register
     int lmin, lmax, form;
@@ -446,8 +463,10 @@ __device__ __forceinline__ uint32_t leaf_entry(int lev, int sub)
 }
 
 // FP64 plain: lane = (k, b): b = inner point (lane % NYP), k = batch slice
-template <int DIM, int ETA> struct PlainAcc {
-    using S = Shape<DIM>;
+template <int DIM, int ETA, int ORD = 1> struct PlainAcc {
+    struct S : Shape<DIM> {
+        static constexpr int NR = OShape<DIM, ORD>::NR;   // contraction rows of the order
+    };
     static constexpr int NYP = DIM == 2 ? 8 : 16;
     static constexpr int K = kWave / NYP;
     static constexpr int kStageBytes = kBatch * (DIM + S::NR) * 8;
@@ -492,13 +511,32 @@ template <int DIM, int ETA> struct PlainAcc {
             for (int i = 1; i <= DIM; ++i) s = fma(in.lam[i], E.e[i - 1][k], s);
             sx[t * DIM + k] = s;
         }
+        if constexpr (ORD == 1) {
 #pragma unroll
-        for (int i = 0; i < S::NV; ++i) sp[t * S::NR + i] = in.w * in.lam[i];
+            for (int i = 0; i < S::NV; ++i) sp[t * S::NR + i] = in.w * in.lam[i];
 #pragma unroll
-        for (int i = 0; i < S::NV; ++i)
+            for (int i = 0; i < S::NV; ++i)
 #pragma unroll
-            for (int j = i + 1; j < S::NV; ++j)
-                sp[t * S::NR + offrow<S::NV>(i, j)] = in.w * in.lam[i] * in.lam[j];
+                for (int j = i + 1; j < S::NV; ++j)
+                    sp[t * S::NR + offrow<S::NV>(i, j)] = in.w * in.lam[i] * in.lam[j];
+        } else {
+            // P2: w times the quartic monomials of lambda, in Mono4's order
+            constexpr Mono4<S::NV> mono{};
+            double pw[S::NV][5];
+#pragma unroll
+            for (int v = 0; v < S::NV; ++v) {
+                pw[v][0] = 1.0;
+#pragma unroll
+                for (int q = 1; q <= 4; ++q) pw[v][q] = pw[v][q - 1] * in.lam[v];
+            }
+#pragma unroll
+            for (int k = 0; k < S::NR; ++k) {
+                double x = in.w;
+#pragma unroll
+                for (int v = 0; v < S::NV; ++v) x *= pw[v][mono.e[k][v]];
+                sp[t * S::NR + k] = x;
+            }
+        }
     }
     __device__ void run(CArgs &A, const char *work, int npts)
     {
@@ -790,11 +828,14 @@ template <int DIM, int ETA>
 using MixedAcc = typename std::conditional<DIM == 2, MixedAccDirect<DIM, ETA>, MixedAccMfma<DIM, ETA>>::type;
 
 // per-wave LDS: staging, then the epilogue's H/Q rows and MFMA tile | leaves | stack
-template <int DIM, int PREC> struct WaveMem {
+template <int DIM, int PREC, int ORD = 1> struct WaveMem {
     using S = Shape<DIM>;
+    using O = OShape<DIM, ORD>;
     static constexpr int kStageBytes =
-        PREC == 0 ? PlainAcc<DIM, 0>::kStageBytes : MixedAcc<DIM, 0>::kStageBytes;
-    static constexpr int kEpiRows = S::NR + 1 + S::NV;   // H/Q rows + column sums + diagonal rows
+        PREC == 0 ? PlainAcc<DIM, 0, ORD>::kStageBytes : MixedAcc<DIM, 0>::kStageBytes;
+    // P1: H/Q rows + column sums + diagonal rows; P2: the monomial rows, then the
+    // rows mapped from them
+    static constexpr int kEpiRows = ORD == 1 ? S::NR + 1 + S::NV : O::NR + O::NRX;
     // the mixed path's 16 x 16 MFMA tile is written in place of the H/Q rows
     static constexpr int kEpiBytes = (PREC == 1 && kEpiRows < 16 ? 16 : kEpiRows) * 16 * 8;
     // the epilogue runs after the pair's last batch: it shares the staging area
@@ -828,11 +869,11 @@ __device__ __forceinline__ int64_t search(const int32_t *cols, int64_t n, int32_
 // offsets from the row's first column when the row fits (length <= rowcap and
 // column span < 65536); otherwise searched in the global row
 struct RowCache {
-    const uint16_t *c16[4];   // LDS copy, or nullptr
-    const int32_t *cols[4];   // the global row
-    int32_t first[4];
-    int64_t base[4];
-    int64_t len[4];
+    const uint16_t *c16[10];   // LDS copy, or nullptr (one row per node of l: up to 10 for P2 in 3D)
+    const int32_t *cols[10];   // the global row
+    int32_t first[10];
+    int64_t base[10];
+    int64_t len[10];
 };
 
 // position of column c in cached row r, or -1 (a cached row holds at most
@@ -867,76 +908,96 @@ template <int DIM, class Real> struct Edges {
 // B_mm and of B_ll.
 constexpr int kOutNone = 0, kOutLM = 1, kOutMM = 2, kOutLL = 3;
 
-// (i, j), i <= j, of upper-triangle slot u: u < NV is the diagonal (u, u), the
-// others follow the numbering of the product rows lambda_i lambda_j.
-template <int NV> __host__ __device__ constexpr void pair_of(int u, int &i, int &j)
+// (i, j), i <= j, of upper-triangle slot u of an N x N block: u < N is the
+// diagonal (u, u), the others follow (i, j), i < j, in lexicographic order (the
+// numbering of the product rows lambda_i lambda_j for P1 elements)
+template <int N> __host__ __device__ constexpr void pair_of(int u, int &i, int &j)
 {
     i = j = u;
-    for (int a = 0; a < NV; ++a)
-        for (int c = a + 1; c < NV; ++c)
-            if (offrow<NV>(a, c) == u) {
+    for (int a = 0; a < N; ++a)
+        for (int c = a + 1; c < N; ++c)
+            if (offrow<N>(a, c) == u) {
                 i = a;
                 j = c;
             }
 }
 
-// Constant rows (FP64, stride 16) over the inner points b:
-//   0..NV-1       w_b psi_j(y_b)                  (B_lm)
-//   NV..NV+NR-1   w_b psi_i(y_b) psi_j(y_b), i<=j  (B_mm, slot u)
-//   NV+NR         w_b                             (B_ll)
-// and one descriptor per lane: kind | x-row << 2 | t-row << 7 | i << 12 | j << 14 | u << 16.
-// x-rows index the extended H/Q rows: 0..NR-1 the totals, NR the column sums
-// sum_i H_i, NR+1+i the rows H_i - sum_{q != i} Q_iq (lambda_i^2 through the
-// partition of unity).
-template <int DIM>
+// Epilogue descriptor of one output: kind | x-row << 2 | t-row << 9 | i << 16 | j << 20 | u << 24
+__host__ __device__ constexpr int epi_desc(int kind, int xr, int tr, int i, int j, int u)
+{
+    return kind | (xr << 2) | (tr << 9) | (i << 16) | (j << 20) | (u << 24);
+}
+
+// Constant rows (FP64, stride 16) over the inner points b, with psi the NB basis
+// functions of the inner element:
+//   0..NB-1          w_b psi_j(y_b)                  (B_lm)
+//   NB..NB+NU-1      w_b psi_i(y_b) psi_j(y_b), i<=j  (B_mm, slot u)
+//   NB+NU            w_b                             (B_ll)
+// and one descriptor per output o < NOUT (B_lm, then the B_mm and B_ll slots).
+// x-rows index the rows after the contraction.  P1: 0..NR-1 the totals H_i and
+// Q_ij, NR the column sums sum_i H_i, NR+1+i the rows H_i - sum_{q != i} Q_iq
+// (lambda_i^2 through the partition of unity).  P2: 0..NR-1 the monomial totals,
+// NR + k the k-th row of make_p2_map's image (phi_I phi_J, then
+// phi_I (sum lambda)^2, then (sum lambda)^4).
+template <int DIM, int ORD>
 __device__ void epilogue_tables(const double *s_rule, double *s_T, int *s_desc)
 {
-    using S = Shape<DIM>;
-    constexpr int NV = S::NV, NQ = S::NQ, NR = S::NR;
+    using O = OShape<DIM, ORD>;
+    constexpr int NV = O::NV, NQ = Shape<DIM>::NQ, NR = O::NR, NB = O::NB, NU = O::NU;
+    constexpr int NPASS = (O::NOUT + kWave - 1) / kWave;
     const double *bary = s_rule;
     const double *wq = s_rule + NQ * NV;
-    for (int t = threadIdx.x; t < (NV + NR + 1) * 16; t += kThreads) {
+    // inner basis function I at point b
+    auto psi = [&](int I, int b) {
+        const double *lb = bary + b * NV;
+        if (ORD == 1) return lb[I];
+        if (I < NV) return lb[I] * (2.0 * lb[I] - 1.0);
+        int a, c;
+        pair_of<NV>(I, a, c);
+        return 4.0 * lb[a] * lb[c];
+    };
+    for (int t = threadIdx.x; t < (NB + NU + 1) * 16; t += kThreads) {
         const int row = t >> 4, b = t & 15;
         double v = 0.0;
         if (b < NQ) {
-            if (row < NV) {
-                v = wq[b] * bary[b * NV + row];
-            } else if (row < NV + NR) {
+            if (row < NB) {
+                v = wq[b] * psi(row, b);
+            } else if (row < NB + NU) {
                 int i, j;
-                pair_of<NV>(row - NV, i, j);
-                v = wq[b] * bary[b * NV + i] * bary[b * NV + j];
+                pair_of<NB>(row - NB, i, j);
+                v = wq[b] * psi(i, b) * psi(j, b);
             } else {
                 v = wq[b];
             }
         }
         s_T[t] = v;
     }
-    for (int o = threadIdx.x; o < kWave; o += kThreads) {
+    for (int o = threadIdx.x; o < NPASS * kWave; o += kThreads) {
         int kind = kOutNone, xr = 0, tr = 0, i = 0, j = 0, u = 0;
-        if (o < NV * NV) {
+        if (o < NB * NB) {
             kind = kOutLM;
-            i = o / NV;
-            j = o % NV;
-            xr = i;
+            i = o / NB;
+            j = o % NB;
+            xr = ORD == 1 ? i : NR + NU + i;
             tr = j;
-        } else if (o < NV * NV + NR) {
+        } else if (o < NB * NB + NU) {
             kind = kOutMM;
-            u = o - NV * NV;
-            pair_of<NV>(u, i, j);
-            xr = NR;
-            tr = NV + u;
-        } else if (o < NV * NV + 2 * NR) {
+            u = o - NB * NB;
+            pair_of<NB>(u, i, j);
+            xr = ORD == 1 ? NR : NR + NU + NB;
+            tr = NB + u;
+        } else if (o < NB * NB + 2 * NU) {
             kind = kOutLL;
-            u = o - NV * NV - NR;
-            pair_of<NV>(u, i, j);
-            xr = u < NV ? NR + 1 + u : u;
-            tr = NV + NR;
+            u = o - NB * NB - NU;
+            pair_of<NB>(u, i, j);
+            xr = ORD == 1 ? (u < NV ? NR + 1 + u : u) : NR + u;
+            tr = NB + NU;
         }
-        s_desc[o] = kind | (xr << 2) | (tr << 7) | (i << 12) | (j << 14) | (u << 16);
+        s_desc[o] = epi_desc(kind, xr, tr, i, j, u);
     }
 }
 
-// rows NR (sum_i H_i) and NR+1+i (H_i - sum_{q != i} Q_iq) of the per-pair totals
+// P1: rows NR (sum_i H_i) and NR+1+i (H_i - sum_{q != i} Q_iq) of the per-pair totals
 template <int DIM> __device__ __forceinline__ void extend_rows(double *HQ)
 {
     using S = Shape<DIM>;
@@ -960,18 +1021,36 @@ template <int DIM> __device__ __forceinline__ void extend_rows(double *HQ)
     }
 }
 
+// P2: rows NR + k = sum_r map[k][r] * (monomial total r), k < NRX
+template <int DIM> __device__ __forceinline__ void map_rows(double *HQ, const double *map)
+{
+    using O = OShape<DIM, 2>;
+    constexpr int BW = Shape<DIM>::NQ <= 8 ? 8 : 16;
+    for (int t = lane_id(); t < O::NRX * BW; t += kWave) {
+        const int k = t / BW, b = t % BW;
+        const double *mk = map + k * O::NR;
+        double v = 0.0;
+#pragma unroll
+        for (int r = 0; r < O::NR; ++r) v = fma(mk[r], HQ[r * 16 + b], v);
+        HQ[(O::NR + k) * 16 + b] = v;
+    }
+}
+
 // -------------------------------------------------------------- one pair
 
-template <int DIM, int PREC, int ETA>
+template <int DIM, int PREC, int ETA, int ORD>
 __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pidx, char *wmem,
                              const double *s_rule, const float *s_w32, const double *s_T, const int *s_desc,
-                             double *s_bll, const RowCache *rc, double *ex_block, unsigned long long *s_leaf)
+                             const double *s_map, double *s_bll, const RowCache *rc, double *ex_block,
+                             unsigned long long *s_leaf)
 {
     using S = Shape<DIM>;
-    constexpr int NV = S::NV, NQ = S::NQ, NCH = S::NCH, NR = S::NR;
-    using Acc = typename std::conditional<PREC == 0, PlainAcc<DIM, ETA>, MixedAcc<DIM, ETA>>::type;
+    using O = OShape<DIM, ORD>;
+    constexpr int NV = S::NV, NQ = S::NQ, NCH = S::NCH;
+    constexpr int NB = O::NB, NU = O::NU;
+    using Acc = typename std::conditional<PREC == 0, PlainAcc<DIM, ETA, ORD>, MixedAcc<DIM, ETA>>::type;
     using Real = typename std::conditional<PREC == 0, double, float>::type;
-    using WM = WaveMem<DIM, PREC>;
+    using WM = WaveMem<DIM, PREC, ORD>;
     const int lane = lane_id();
     const int64_t ne = A.ne;
     l = uniform(l);
@@ -1011,8 +1090,8 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     }
     const double *bary = s_rule;
     const double *wq = s_rule + NQ * NV;
-    // node m_j of the epilogue's B_lm lane (lane = i * NV + j), read early
-    const int32_t mj = A.conn[static_cast<int64_t>(m) * NV + lane % NV];
+    // P1: node m_j of the epilogue's B_lm lane (lane = i * NV + j), read early
+    const int32_t mj1 = ORD == 1 ? A.conn[static_cast<int64_t>(m) * NV + lane % NV] : 0;
 
     // inner point of this lane, relative to the anchor v0(l)
     int bsel;
@@ -1241,66 +1320,72 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     wave_sync();
     acc.finish(HQ, tile);
     wave_sync();
-    extend_rows<DIM>(HQ);
+    if constexpr (ORD == 1) extend_rows<DIM>(HQ);
+    else map_rows<DIM>(HQ, s_map);
     wave_sync();
-    // every output is a dot product over the inner points b of one HQ row with
-    // one constant row of s_T; the lane's descriptor names both
-    const int desc = s_desc[lane];
-    const int kind = desc & 3;
-    const int xr = (desc >> 2) & 31, tr = (desc >> 7) & 31;
-    const int i = (desc >> 12) & 3, j = (desc >> 14) & 3, u = (desc >> 16) & 15;
-    double v = 0.0;
-    {
-        const double *x = HQ + xr * 16;
-        const double *tt = s_T + tr * 16;
-#pragma unroll
-        for (int b = 0; b < NQ; ++b) v = fma(x[b], tt[b], v);
-    }
     const double Sc = A.C * A.meas[l] * A.meas[m];
-    v *= kind == kOutLM ? -Sc : Sc;
     const bool four = A.form == NLQ_FORM_SYM4;
     // the two-term form with the adaptive rule on the inner integral: rows of the
     // refined (outer) element, 2 B_ll and 2 B_lm (see the oracle's form 2)
     const bool inner = A.form == NLQ_FORM_PAPER2_INNER;
-    if (ex_block) {
-        constexpr int N2 = 2 * NV;
+    constexpr int NPASS = (O::NOUT + kWave - 1) / kWave;
+    for (int pass = 0; pass < NPASS; ++pass) {
+        // every output is a dot product over the inner points b of one row after
+        // the contraction with one constant row of s_T; the descriptor names both
+        const int o = pass * kWave + lane;
+        const int desc = s_desc[o];
+        const int kind = desc & 3;
+        const int xr = (desc >> 2) & 127, tr = (desc >> 9) & 127;
+        const int i = (desc >> 16) & 15, j = (desc >> 20) & 15, u = (desc >> 24) & 63;
+        double v = 0.0;
+        {
+            const double *x = HQ + xr * 16;
+            const double *tt = s_T + tr * 16;
+#pragma unroll
+            for (int b = 0; b < NQ; ++b) v = fma(x[b], tt[b], v);
+        }
+        v *= kind == kOutLM ? -Sc : Sc;
+        if (ex_block) {
+            constexpr int N2 = 2 * NB;
+            if (kind == kOutLM) {
+                ex_block[i * N2 + NB + j] = four ? v : (inner ? 2.0 * v : 0.0);
+                ex_block[(NB + j) * N2 + i] = four ? v : (inner ? 0.0 : 2.0 * v);
+            } else if (kind == kOutMM) {
+                ex_block[(NB + i) * N2 + NB + j] = four ? v : (inner ? 0.0 : 2.0 * v);
+                ex_block[(NB + j) * N2 + NB + i] = four ? v : (inner ? 0.0 : 2.0 * v);
+            } else if (kind == kOutLL) {
+                ex_block[i * N2 + j] = four ? v : (inner ? 2.0 * v : 0.0);
+                ex_block[j * N2 + i] = four ? v : (inner ? 2.0 * v : 0.0);
+            }
+            continue;
+        }
+        if (A.pb) {
+            // deterministic mode: the outputs of pair pidx, in descriptor order, are
+            // summed later in a fixed order
+            if (kind != kOutNone) A.pb[(pidx - A.pb_base) * O::NOUT + o] = v;
+            continue;
+        }
         if (kind == kOutLM) {
-            ex_block[i * N2 + NV + j] = four ? v : (inner ? 2.0 * v : 0.0);
-            ex_block[(NV + j) * N2 + i] = four ? v : (inner ? 0.0 : 2.0 * v);
+            // B_lm at (l_i, m_j) through the cached row of l_i.  SYM4 adds it to the
+            // half matrix R (A = R + R^T afterwards); the two-term form puts 2 B_lm^T
+            // at (m_j, l_i) directly, its adaptive-inner variant 2 B_lm at (l_i, m_j).
+            const int32_t mj = ORD == 1 ? mj1 : A.conn[static_cast<int64_t>(m) * NB + j];
+            const int64_t at = row_find(rc, i, mj);
+            if (at >= 0) {
+                const int64_t pos = rc->base[i] + at;
+                if (four) unsafeAtomicAdd(&A.val[pos], v);
+                else if (inner) unsafeAtomicAdd(&A.val[pos], 2.0 * v);
+                else unsafeAtomicAdd(&A.val[A.tmap[pos]], 2.0 * v);
+            } else {
+                // (l_i, m_j) outside the pattern: the pair list and the pattern disagree
+                atomicOr(&A.counters->error, kErrPattern);
+            }
         } else if (kind == kOutMM) {
-            ex_block[(NV + i) * N2 + NV + j] = four ? v : (inner ? 0.0 : 2.0 * v);
-            ex_block[(NV + j) * N2 + NV + i] = four ? v : (inner ? 0.0 : 2.0 * v);
+            if (!inner) unsafeAtomicAdd(&A.dmm[static_cast<int64_t>(m) * NU + u], four ? v : 2.0 * v);
         } else if (kind == kOutLL) {
-            ex_block[i * N2 + j] = four ? v : (inner ? 2.0 * v : 0.0);
-            ex_block[j * N2 + i] = four ? v : (inner ? 2.0 * v : 0.0);
+            if (four) atomicAdd(&s_bll[u], v);
+            else if (inner) atomicAdd(&s_bll[u], 2.0 * v);
         }
-        return;
-    }
-    if (A.pb) {
-        // deterministic mode: the outputs of pair pidx, in descriptor order, are
-        // summed later in a fixed order
-        if (kind != kOutNone) A.pb[(pidx - A.pb_base) * (NV * NV + 2 * NR) + lane] = v;
-        return;
-    }
-    if (kind == kOutLM) {
-        // B_lm at (l_i, m_j) through the cached row of l_i.  SYM4 adds it to the
-        // half matrix R (A = R + R^T afterwards); the two-term form puts 2 B_lm^T
-        // at (m_j, l_i) directly, its adaptive-inner variant 2 B_lm at (l_i, m_j).
-        const int64_t at = row_find(rc, i, mj);
-        if (at >= 0) {
-            const int64_t pos = rc->base[i] + at;
-            if (four) unsafeAtomicAdd(&A.val[pos], v);
-            else if (inner) unsafeAtomicAdd(&A.val[pos], 2.0 * v);
-            else unsafeAtomicAdd(&A.val[A.tmap[pos]], 2.0 * v);
-        } else {
-            // (l_i, m_j) outside the pattern: the pair list and the pattern disagree
-            atomicOr(&A.counters->error, kErrPattern);
-        }
-    } else if (kind == kOutMM) {
-        if (!inner) unsafeAtomicAdd(&A.dmm[static_cast<int64_t>(m) * NR + u], four ? v : 2.0 * v);
-    } else if (kind == kOutLL) {
-        if (four) atomicAdd(&s_bll[u], v);
-        else if (inner) atomicAdd(&s_bll[u], 2.0 * v);
     }
 }
 
@@ -1308,18 +1393,21 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
 
 // Occupancy hint: more waves per SIMD cover LDS and table latency at the cost of
 // registers (5 waves in 2D, 3 in 3D were fastest on the 2D 128^2 and 3D 8^3 cases).
-template <int DIM, int PREC, int ETA, int OCC>
+template <int DIM, int PREC, int ETA, int OCC, int ORD>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu<DIM, PREC, OCC>())))
 k_integrate(LaunchArgs L)
 {
     using S = Shape<DIM>;
-    constexpr int NV = S::NV, NQ = S::NQ, NR = S::NR;
+    using O = OShape<DIM, ORD>;
+    using WM = WaveMem<DIM, PREC, ORD>;
+    constexpr int NV = S::NV, NQ = S::NQ, NB = O::NB, NU = O::NU;
     extern __shared__ __align__(16) char smem[];
     __shared__ double s_rule[NQ * NV + NQ];
     __shared__ float s_w32[16];
-    __shared__ __align__(16) double s_T[(NV + NR + 1) * 16];
-    __shared__ int s_desc[kWave];
-    __shared__ double s_bll[NR];
+    __shared__ __align__(16) double s_T[(NB + NU + 1) * 16];
+    __shared__ int s_desc[(O::NOUT + kWave - 1) / kWave * kWave];
+    __shared__ double s_map[ORD == 1 ? 1 : O::NRX * O::NR];
+    __shared__ double s_bll[NU];
     __shared__ int64_t s_seg[kMaxSeg + 1];
     __shared__ int64_t s_item;
     __shared__ int s_sys;
@@ -1328,15 +1416,18 @@ k_integrate(LaunchArgs L)
     __shared__ unsigned long long s_leaf[10];
     __shared__ RowCache s_rc;
     const int wid = threadIdx.x / kWave;
-    char *wmem = smem + wid * WaveMem<DIM, PREC>::bytes(L.capl);
-    uint16_t *rows_lds = reinterpret_cast<uint16_t *>(smem + kWaves * WaveMem<DIM, PREC>::bytes(L.capl));
-    // the quadrature rule depends on the dimension only: every system of the launch shares it
+    char *wmem = smem + wid * WM::bytes(L.capl);
+    uint16_t *rows_lds = reinterpret_cast<uint16_t *>(smem + kWaves * WM::bytes(L.capl));
+    // the quadrature rule (and the P2 map) depends on the dimension only: every
+    // system of the launch shares it
     CArgs &A0 = *(CArgs *)(L.sys);
     for (int t = threadIdx.x; t < NQ * NV + NQ; t += kThreads) s_rule[t] = A0.rule[t];
+    if constexpr (ORD == 2)
+        for (int t = threadIdx.x; t < O::NRX * O::NR; t += kThreads) s_map[t] = A0.p2map[t];
     if (threadIdx.x < NQ) s_w32[threadIdx.x] = static_cast<float>(A0.rule[NQ * NV + threadIdx.x]);
     for (int t = threadIdx.x; t <= L.nseg; t += kThreads) s_seg[t] = L.seg_start[t];
     __syncthreads();
-    epilogue_tables<DIM>(s_rule, s_T, s_desc);
+    epilogue_tables<DIM, ORD>(s_rule, s_T, s_desc);
     const int64_t total = s_seg[L.nseg];
     for (;;) {
         if (threadIdx.x == 0) {
@@ -1359,15 +1450,15 @@ k_integrate(LaunchArgs L)
             s_sys = sys;
             s_part = part;
         }
-        if (threadIdx.x < NR) s_bll[threadIdx.x] = 0.0;
+        if (threadIdx.x < NU) s_bll[threadIdx.x] = 0.0;
         if (threadIdx.x < 10) s_leaf[threadIdx.x] = 0ull;
         __syncthreads();
         const int64_t l = s_item;
         if (l < 0) break;
         CArgs &A = *(CArgs *)(L.sys + __builtin_amdgcn_readfirstlane(s_sys));
         // stage the CSR rows of l's nodes
-        if (threadIdx.x < NV) {
-            const int32_t node = A.conn[l * NV + threadIdx.x];
+        if (threadIdx.x < NB) {
+            const int32_t node = A.conn[l * NB + threadIdx.x];
             const int64_t b = A.row_ptr[node], len = A.row_ptr[node + 1] - b;
             const int32_t first = len > 0 ? A.col[b] : 0;
             const bool fits = len <= L.rowcap && (len == 0 || A.col[b + len - 1] - first <= 65535);
@@ -1378,7 +1469,7 @@ k_integrate(LaunchArgs L)
             s_rc.c16[threadIdx.x] = fits ? rows_lds + threadIdx.x * L.rowcap : nullptr;
         }
         __syncthreads();
-        for (int r = 0; r < NV; ++r) {
+        for (int r = 0; r < NB; ++r) {
             uint16_t *dst = const_cast<uint16_t *>(s_rc.c16[r]);
             if (!dst) continue;
             for (int64_t k = threadIdx.x; k < s_rc.len[r]; k += kThreads)
@@ -1398,14 +1489,14 @@ k_integrate(LaunchArgs L)
             p = bcast0(p);
             if (p >= p_hi) break;
             const int32_t m = A.pair_m[b0 + p];
-            process_pair<DIM, PREC, ETA>(A, static_cast<int>(l), m, b0 + p, wmem, s_rule, s_w32, s_T,
-                                         s_desc, s_bll, &s_rc, nullptr, s_leaf);
+            process_pair<DIM, PREC, ETA, ORD>(A, static_cast<int>(l), m, b0 + p, wmem, s_rule, s_w32, s_T,
+                                              s_desc, s_map, s_bll, &s_rc, nullptr, s_leaf);
         }
         __syncthreads();
         // B_ll of l (upper triangle; doubled for the adaptive-inner two-term form)
         // joins the diagonal-block sums of l
-        if (A.form != NLQ_FORM_PAPER2 && !A.pb && threadIdx.x < NR)
-            unsafeAtomicAdd(&A.dmm[l * NR + threadIdx.x], s_bll[threadIdx.x]);
+        if (A.form != NLQ_FORM_PAPER2 && !A.pb && threadIdx.x < NU)
+            unsafeAtomicAdd(&A.dmm[l * NU + threadIdx.x], s_bll[threadIdx.x]);
         if (threadIdx.x >= 1 && threadIdx.x <= A.lmax && s_leaf[threadIdx.x])
             atomicAdd(&A.counters->leaf[threadIdx.x], s_leaf[threadIdx.x]);
         if (threadIdx.x == 0 && s_leaf[0]) atomicAdd(&A.counters->zero_leaves, s_leaf[0]);
@@ -1417,60 +1508,63 @@ k_integrate(LaunchArgs L)
 
 // explicit pairs of system 0: every wave takes pairs from the counter and
 // writes the extended block [2N+2][2N+2] of each
-template <int DIM, int PREC, int ETA>
+template <int DIM, int PREC, int ETA, int ORD>
 __global__ void __launch_bounds__(kThreads)
 k_pair_blocks(LaunchArgs L)
 {
     using S = Shape<DIM>;
-    constexpr int NV = S::NV, NQ = S::NQ;
+    using O = OShape<DIM, ORD>;
+    constexpr int NV = S::NV, NQ = S::NQ, NB = O::NB;
     extern __shared__ __align__(16) char smem[];
     __shared__ double s_rule[NQ * NV + NQ];
     __shared__ float s_w32[16];
-    __shared__ __align__(16) double s_T[(NV + S::NR + 1) * 16];
-    __shared__ int s_desc[kWave];
+    __shared__ __align__(16) double s_T[(NB + O::NU + 1) * 16];
+    __shared__ int s_desc[(O::NOUT + kWave - 1) / kWave * kWave];
+    __shared__ double s_map[ORD == 1 ? 1 : O::NRX * O::NR];
     CArgs &A = *(CArgs *)(L.sys);
     const int wid = threadIdx.x / kWave;
-    char *wmem = smem + wid * WaveMem<DIM, PREC>::bytes(L.capl);
+    char *wmem = smem + wid * WaveMem<DIM, PREC, ORD>::bytes(L.capl);
     for (int t = threadIdx.x; t < NQ * NV + NQ; t += kThreads) s_rule[t] = A.rule[t];
     if (threadIdx.x < NQ) s_w32[threadIdx.x] = static_cast<float>(A.rule[NQ * NV + threadIdx.x]);
+    if constexpr (ORD == 2)
+        for (int t = threadIdx.x; t < O::NRX * O::NR; t += kThreads) s_map[t] = A.p2map[t];
     __syncthreads();
-    epilogue_tables<DIM>(s_rule, s_T, s_desc);
+    epilogue_tables<DIM, ORD>(s_rule, s_T, s_desc);
     __syncthreads();
     for (;;) {
         unsigned int it = 0;
         if (lane_id() == 0) it = atomicAdd(L.counter, 1u);
         it = bcast0(it);
         if (it >= A.n_explicit) break;
-        double *blk = A.ex_out + static_cast<int64_t>(it) * (2 * NV) * (2 * NV);
-        for (int t = lane_id(); t < 4 * NV * NV; t += kWave) blk[t] = 0.0;
+        double *blk = A.ex_out + static_cast<int64_t>(it) * (2 * NB) * (2 * NB);
+        for (int t = lane_id(); t < 4 * NB * NB; t += kWave) blk[t] = 0.0;
         wave_sync();
-        process_pair<DIM, PREC, ETA>(A, A.ex_l[it], A.ex_m[it], -1, wmem, s_rule, s_w32, s_T, s_desc, nullptr,
-                                     nullptr, blk, nullptr);
+        process_pair<DIM, PREC, ETA, ORD>(A, A.ex_l[it], A.ex_m[it], -1, wmem, s_rule, s_w32, s_T, s_desc, s_map,
+                                          nullptr, nullptr, blk, nullptr);
     }
 }
 
 // Diagonal blocks into the CSR values: slot u = (i, j), i <= j, of element e goes
 // to (e_i, e_j).  SYM4 halves the diagonal slots, so that R + R^T restores every
 // symmetric block; the two-term form adds both triangles directly.
-template <int DIM>
+template <int NB>
 __global__ void __launch_bounds__(256) k_fold_diag(int64_t ne, const double *dmm, const int32_t *elpos,
                                                   double *val, int four)
 {
-    using S = Shape<DIM>;
-    constexpr int NV = S::NV, NR = S::NR;
+    constexpr int NU = NB * (NB + 1) / 2;
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= ne * NR) return;
-    const int64_t e = t / NR;
-    const int u = static_cast<int>(t - e * NR);
+    if (t >= ne * NU) return;
+    const int64_t e = t / NU;
+    const int u = static_cast<int>(t - e * NU);
     int i, j;
-    pair_of<NV>(u, i, j);
+    pair_of<NB>(u, i, j);
     const double d = dmm[t];
-    const int32_t *ep = elpos + e * NV * NV;
+    const int32_t *ep = elpos + e * NB * NB;
     if (four) {
-        unsafeAtomicAdd(&val[ep[i * NV + j]], i == j ? 0.5 * d : d);
+        unsafeAtomicAdd(&val[ep[i * NB + j]], i == j ? 0.5 * d : d);
     } else {
-        unsafeAtomicAdd(&val[ep[i * NV + j]], d);
-        if (i != j) unsafeAtomicAdd(&val[ep[j * NV + i]], d);
+        unsafeAtomicAdd(&val[ep[i * NB + j]], d);
+        if (i != j) unsafeAtomicAdd(&val[ep[j * NB + i]], d);
     }
 }
 
@@ -1491,13 +1585,14 @@ __global__ void __launch_bounds__(256) k_symmetrize(int64_t nnz, const int32_t *
 }
 
 // workgroups per CU of one launch and its dynamic LDS bytes
-template <int DIM, int PREC, int ETA, int OCC>
+template <int DIM, int PREC, int ETA, int OCC, int ORD>
 int occupancy(int capl, int rowcap, bool explicit_mode, int *lds_out)
 {
-    const int per_wave = WaveMem<DIM, PREC>::bytes(capl);
-    const int lds = kWaves * per_wave + (explicit_mode ? 0 : (((DIM + 1) * rowcap * 2 + 15) & ~15));
+    const int per_wave = WaveMem<DIM, PREC, ORD>::bytes(capl);
+    const int nb = OShape<DIM, ORD>::NB;
+    const int lds = kWaves * per_wave + (explicit_mode ? 0 : ((nb * rowcap * 2 + 15) & ~15));
     if (lds > 150 * 1024) fail(NLQ_EINVAL, "lmax too large for the per-wave refinement lists");
-    auto kern = explicit_mode ? k_pair_blocks<DIM, PREC, ETA> : k_integrate<DIM, PREC, ETA, OCC>;
+    auto kern = explicit_mode ? k_pair_blocks<DIM, PREC, ETA, ORD> : k_integrate<DIM, PREC, ETA, OCC, ORD>;
     NLQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     int per_cu = 0;
@@ -1506,14 +1601,14 @@ int occupancy(int capl, int rowcap, bool explicit_mode, int *lds_out)
     return per_cu < 1 ? 1 : per_cu;
 }
 
-template <int DIM, int PREC, int ETA, int OCC>
+template <int DIM, int PREC, int ETA, int OCC, int ORD = 1>
 void launch_one(Ctx *ctx, const LaunchArgs &L, int64_t items, hipStream_t st, bool explicit_mode,
                 int wg_per_cu, hipEvent_t e0, hipEvent_t e1)
 {
     int lds = 0;
-    int per_cu = occupancy<DIM, PREC, ETA, OCC>(L.capl, L.rowcap, explicit_mode, &lds);
+    int per_cu = occupancy<DIM, PREC, ETA, OCC, ORD>(L.capl, L.rowcap, explicit_mode, &lds);
     if (wg_per_cu > 0 && wg_per_cu < per_cu) per_cu = wg_per_cu;
-    auto kern = explicit_mode ? k_pair_blocks<DIM, PREC, ETA> : k_integrate<DIM, PREC, ETA, OCC>;
+    auto kern = explicit_mode ? k_pair_blocks<DIM, PREC, ETA, ORD> : k_integrate<DIM, PREC, ETA, OCC, ORD>;
     int64_t grid = static_cast<int64_t>(ctx->n_cu) * per_cu;
     if (grid > items) grid = items;
     if (grid < 1) grid = 1;
@@ -1542,6 +1637,20 @@ void dispatch(Ctx *ctx, const System &s, const TuneConfig &c, const LaunchArgs &
               bool ex, hipEvent_t e0, hipEvent_t e1)
 {
     const int dim = s.mesh->dim;
+    if (s.mesh->order == 2) {
+        // P2 elements: FP64 plain path only, one register variant
+        if (s.p.precision != NLQ_FP64_PLAIN) fail(NLQ_EINVAL, "P2 elements take the FP64 plain path");
+        const bool g = s.p.kernel == NLQ_ETA_GAUSS;
+        const int wpc = c.wg_per_cu;
+        if (dim == 2) {
+            if (g) launch_one<2, 0, NLQ_ETA_GAUSS, 0, 2>(ctx, L, items, st, ex, wpc, e0, e1);
+            else launch_one<2, 0, NLQ_ETA_CONST, 0, 2>(ctx, L, items, st, ex, wpc, e0, e1);
+        } else {
+            if (g) launch_one<3, 0, NLQ_ETA_GAUSS, 0, 2>(ctx, L, items, st, ex, wpc, e0, e1);
+            else launch_one<3, 0, NLQ_ETA_CONST, 0, 2>(ctx, L, items, st, ex, wpc, e0, e1);
+        }
+        return;
+    }
     if (dim == 2) {
         if (s.p.precision == NLQ_FP64_PLAIN) launch_var<2, 0>(ctx, s.p.kernel, c, L, items, st, ex, e0, e1);
         else launch_var<2, 1>(ctx, s.p.kernel, c, L, items, st, ex, e0, e1);
@@ -1552,13 +1661,18 @@ void dispatch(Ctx *ctx, const System &s, const TuneConfig &c, const LaunchArgs &
 }
 
 template <int DIM, int PREC>
-int occupancy_of(int kernel, int occ, int capl, int rowcap)
+int occupancy_of(int kernel, int occ, int capl, int rowcap, int order)
 {
     const bool g = kernel == NLQ_ETA_GAUSS;
-    if (occ == 0) return g ? occupancy<DIM, PREC, 1, 0>(capl, rowcap, false, nullptr)
-                           : occupancy<DIM, PREC, 0, 0>(capl, rowcap, false, nullptr);
-    return g ? occupancy<DIM, PREC, 1, 1>(capl, rowcap, false, nullptr)
-             : occupancy<DIM, PREC, 0, 1>(capl, rowcap, false, nullptr);
+    if (order == 2) {
+        if (PREC != 0) fail(NLQ_EINVAL, "P2 elements take the FP64 plain path");
+        return g ? occupancy<DIM, 0, 1, 0, 2>(capl, rowcap, false, nullptr)
+                 : occupancy<DIM, 0, 0, 0, 2>(capl, rowcap, false, nullptr);
+    }
+    if (occ == 0) return g ? occupancy<DIM, PREC, 1, 0, 1>(capl, rowcap, false, nullptr)
+                           : occupancy<DIM, PREC, 0, 0, 1>(capl, rowcap, false, nullptr);
+    return g ? occupancy<DIM, PREC, 1, 1, 1>(capl, rowcap, false, nullptr)
+             : occupancy<DIM, PREC, 0, 1, 1>(capl, rowcap, false, nullptr);
 }
 
 // work items per outer element of a system
@@ -1595,6 +1709,8 @@ AsmArgs make_args(const System &s, const Tables &T)
     A.qhi = s.qhi.as<double>();
     A.meas = s.meas.as<double>();
     A.conn = m.conn.as<int32_t>();
+    A.nb = m.nb;
+    A.p2map = T.p2map.as<double>();
     A.row_ptr = s.row_ptr.as<int64_t>();
     A.col = s.col.as<int32_t>();
     A.tmap = s.tmap.as<int32_t>();
@@ -1686,8 +1802,9 @@ void launch_integrate_jobs(Ctx *ctx, LaunchBlock &lb, const std::vector<Integrat
     std::vector<int64_t> seg_lo, seg_start{0};
     for (const auto &j : jobs) {
         const System &s = *j.s;
-        if (s.mesh->dim != s0.mesh->dim || s.p.precision != s0.p.precision || s.p.kernel != s0.p.kernel)
-            fail(NLQ_EINVAL, "one launch takes systems of one dimension, precision and kernel");
+        if (s.mesh->dim != s0.mesh->dim || s.p.precision != s0.p.precision || s.p.kernel != s0.p.kernel ||
+            s.mesh->order != s0.mesh->order)
+            fail(NLQ_EINVAL, "one launch takes systems of one dimension, element order, precision and kernel");
         if (s.p.deterministic && (!s.det_pb || jobs.size() != 1))
             fail(NLQ_EINVAL, "a deterministic system is integrated by itself (nlq_assemble)");
         if (j.lo < 0 || j.hi > s.mesh->n_elems || j.lo > j.hi) fail(NLQ_EINVAL, "bad outer-element range");
@@ -1721,8 +1838,8 @@ void launch_integrate_jobs(Ctx *ctx, LaunchBlock &lb, const std::vector<Integrat
         const System &s = *j.s;
         NLQ_HIP(hipMemsetAsync(s.counters.as<void>(), 0, sizeof(AsmCounters), st));
         NLQ_HIP(hipMemsetAsync(s.val.as<void>(), 0, sizeof(double) * s.nnz, st));
-        NLQ_HIP(hipMemsetAsync(s.dmm.as<void>(), 0, sizeof(double) * s.mesh->n_elems * (s.mesh->dim == 2 ? 6 : 10),
-                               st));
+        const int64_t nu = static_cast<int64_t>(s.mesh->nb) * (s.mesh->nb + 1) / 2;
+        NLQ_HIP(hipMemsetAsync(s.dmm.as<void>(), 0, sizeof(double) * s.mesh->n_elems * nu, st));
     }
     NLQ_HIP(hipMemcpyAsync(lb.dev.as<void>(), h, B.bytes, hipMemcpyHostToDevice, st));
     char *d = lb.dev.as<char>();
@@ -1741,18 +1858,16 @@ void launch_integrate_jobs(Ctx *ctx, LaunchBlock &lb, const std::vector<Integrat
     for (const auto &j : jobs) {
         const System &s = *j.s;
         if (j.hi != s.mesh->n_elems || s.det_pb) continue;
-        const int dim = s.mesh->dim;
+        const int nb = s.mesh->nb;
         const int four = s.p.form == NLQ_FORM_SYM4;
-        const int64_t nf = s.mesh->n_elems * (dim == 2 ? 6 : 10);
+        const int64_t nf = s.mesh->n_elems * (static_cast<int64_t>(nb) * (nb + 1) / 2);
         const double *dmm = s.dmm.as<double>();
         const int32_t *elpos = s.elpos.as<int32_t>();
         double *val = s.val.as<double>();
         if (nf > 0) {
             const unsigned gf = static_cast<unsigned>((nf + 255) / 256);
-            if (dim == 2)
-                hipLaunchKernelGGL(k_fold_diag<2>, dim3(gf), dim3(256), 0, st, s.mesh->n_elems, dmm, elpos, val, four);
-            else
-                hipLaunchKernelGGL(k_fold_diag<3>, dim3(gf), dim3(256), 0, st, s.mesh->n_elems, dmm, elpos, val, four);
+            auto kern = nb == 3 ? k_fold_diag<3> : nb == 4 ? k_fold_diag<4> : nb == 6 ? k_fold_diag<6> : k_fold_diag<10>;
+            hipLaunchKernelGGL(kern, dim3(gf), dim3(256), 0, st, s.mesh->n_elems, dmm, elpos, val, four);
             NLQ_CHECK_LAUNCH();
         }
         if (four && s.nnz > 0) {
@@ -1768,12 +1883,13 @@ int64_t integrate_slots(Ctx *ctx, const System &s)
     const AsmArgs A = make_args(s, ctx->get_tables(s.mesh->dim, s.p.lmax));
     const bool plain = s.p.precision == NLQ_FP64_PLAIN;
     int per_cu;
+    const int ord = s.mesh->order;
     if (s.mesh->dim == 2)
-        per_cu = plain ? occupancy_of<2, 0>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap)
-                       : occupancy_of<2, 1>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap);
+        per_cu = plain ? occupancy_of<2, 0>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, ord)
+                       : occupancy_of<2, 1>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, ord);
     else
-        per_cu = plain ? occupancy_of<3, 0>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap)
-                       : occupancy_of<3, 1>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap);
+        per_cu = plain ? occupancy_of<3, 0>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, ord)
+                       : occupancy_of<3, 1>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, ord);
     if (s.cfg.wg_per_cu > 0 && s.cfg.wg_per_cu < per_cu) per_cu = s.cfg.wg_per_cu;
     return static_cast<int64_t>(ctx->n_cu) * per_cu;
 }

@@ -102,6 +102,8 @@ struct Tables {
     // scaled by the level's volume ratio) and lambda_1..lambda_dim:
     // [n_sub*nq + 1][8 (2D) or 16 (3D)], the last row zero (lanes without a point)
     DevBuf pt32;
+    // P2 elements: the monomial rows -> epilogue rows map of make_p2_map (double)
+    DevBuf p2map;
 };
 
 struct Server;
@@ -154,7 +156,9 @@ struct Mesh {
     double gmin[3] = {0, 0, 0}, gmax[3] = {0, 0, 0};
     double ext_max[3] = {0, 0, 0};   // largest element bbox extent per axis
     DevBuf coords;                   // [n_nodes][dim] double
-    DevBuf conn;                     // [n_elems][dim+1] int32
+    int order = 1;                   // 1: P1; 2: P2 (vertices, then edge midpoints)
+    int nb = 0;                      // nodes per element: dim + 1 (P1), (dim+1)(dim+2)/2 (P2)
+    DevBuf conn;                     // [n_elems][nb] int32
     DevBuf constrained;              // [n_nodes] uint8
     std::vector<double> h_coords;
     std::vector<int32_t> h_conn;
@@ -273,6 +277,7 @@ void launch_pair_blocks(System &s, hipStream_t st, int64_t n, const int32_t *ex_
                         double *ex_out);
 void launch_load_lift(System &s, hipStream_t st, const double *f_dev, const double *g_dev);
 int cg_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, int *converged);
+int bicgstab_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, int *converged);
 // the allocation-free solve: CG vectors in the library's static device scratch
 // (address taken per device by noalloc_scratch_init), plain launches, u into u_dev
 void noalloc_scratch_init(int device);
@@ -286,6 +291,7 @@ void exclusive_scan_i64(Ctx *ctx, const int64_t *in, int64_t *out, int64_t n, hi
 
 double kernel_constant(int dim, int kernel, double delta, double eps);
 std::unique_ptr<Tables> make_tables(Ctx *ctx, int dim, int lmax);
+std::vector<double> make_p2_map(int dim);
 
 }  // namespace nlq
 

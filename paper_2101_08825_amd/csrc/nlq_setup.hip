@@ -80,7 +80,7 @@ void exclusive_scan_i64(Ctx *ctx, const int64_t *in, int64_t *out, int64_t n, hi
 namespace {
 
 template <int DIM>
-__global__ void k_elem_tables(int64_t ne, const double *__restrict__ coords,
+__global__ void k_elem_tables(int64_t ne, int nb, const double *__restrict__ coords,
                               const int32_t *__restrict__ conn, double *__restrict__ vert,
                               double *__restrict__ lo, double *__restrict__ hi,
                               double *__restrict__ meas)
@@ -89,9 +89,10 @@ __global__ void k_elem_tables(int64_t ne, const double *__restrict__ coords,
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= ne) return;
     double V[NV][DIM];
+    // the vertices are the first NV of the element's nb nodes (P1 or P2)
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        const int64_t node = conn[e * NV + v];
+        const int64_t node = conn[e * nb + v];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             V[v][k] = coords[node * DIM + k];
@@ -169,11 +170,11 @@ void launch_elem_tables(System &s, hipStream_t st)
     s.meas.alloc(s.ctx, sizeof(double) * ne);
     dim3 grid((ne + 255) / 256), block(256);
     if (m.dim == 2)
-        hipLaunchKernelGGL(k_elem_tables<2>, grid, block, 0, st, ne, m.coords.as<double>(),
+        hipLaunchKernelGGL(k_elem_tables<2>, grid, block, 0, st, ne, m.nb, m.coords.as<double>(),
                            m.conn.as<int32_t>(), s.vert.as<double>(), s.lo.as<double>(),
                            s.hi.as<double>(), s.meas.as<double>());
     else
-        hipLaunchKernelGGL(k_elem_tables<3>, grid, block, 0, st, ne, m.coords.as<double>(),
+        hipLaunchKernelGGL(k_elem_tables<3>, grid, block, 0, st, ne, m.nb, m.coords.as<double>(),
                            m.conn.as<int32_t>(), s.vert.as<double>(), s.lo.as<double>(),
                            s.hi.as<double>(), s.meas.as<double>());
     NLQ_CHECK_LAUNCH();
@@ -628,7 +629,7 @@ __global__ void k_elem_block_pos(int64_t ne, const int32_t *__restrict__ conn,
 void build_pattern(System &s, hipStream_t st)
 {
     const Mesh &m = *s.mesh;
-    const int nv = m.dim + 1;
+    const int nv = m.nb;   // nodes per element (P1 or P2)
     const int64_t ne = m.n_elems, nn = m.n_nodes;
     DevBuf err(s.ctx, sizeof(int), st);
     NLQ_HIP(hipMemsetAsync(err.as<void>(), 0, sizeof(int), st));
@@ -652,16 +653,9 @@ void build_pattern(System &s, hipStream_t st)
     DevBuf nb_off(s.ctx, sizeof(int64_t) * (ne + 1), st);
     NLQ_HIP(hipMemsetAsync(nb_cnt.as<void>(), 0, sizeof(int64_t) * (ne + 1), st));
     auto nbhd = [&](int32_t *out) {
-        if (nv == 3)
-            hipLaunchKernelGGL(k_elem_nbhd<3>, dim3(ne), dim3(kWave), 0, st, ne,
-                               m.conn.as<int32_t>(), s.pair_off.as<int64_t>(),
-                               s.pair_m.as<int32_t>(), nb_cnt.as<int64_t>(), nb_off.as<int64_t>(),
-                               out, err.as<int>());
-        else
-            hipLaunchKernelGGL(k_elem_nbhd<4>, dim3(ne), dim3(kWave), 0, st, ne,
-                               m.conn.as<int32_t>(), s.pair_off.as<int64_t>(),
-                               s.pair_m.as<int32_t>(), nb_cnt.as<int64_t>(), nb_off.as<int64_t>(),
-                               out, err.as<int>());
+        auto kern = nv == 3 ? k_elem_nbhd<3> : nv == 4 ? k_elem_nbhd<4> : nv == 6 ? k_elem_nbhd<6> : k_elem_nbhd<10>;
+        hipLaunchKernelGGL(kern, dim3(ne), dim3(kWave), 0, st, ne, m.conn.as<int32_t>(), s.pair_off.as<int64_t>(),
+                           s.pair_m.as<int32_t>(), nb_cnt.as<int64_t>(), nb_off.as<int64_t>(), out, err.as<int>());
         NLQ_CHECK_LAUNCH();
     };
     nbhd(nullptr);
@@ -705,14 +699,12 @@ void build_pattern(System &s, hipStream_t st)
     NLQ_CHECK_LAUNCH();
     s.elpos.alloc(s.ctx, sizeof(int32_t) * ne * nv * nv);
     dim3 g2((ne * nv * nv + 255) / 256);
-    if (nv == 3)
-        hipLaunchKernelGGL(k_elem_block_pos<3>, g2, b1, 0, st, ne, m.conn.as<int32_t>(),
-                           s.row_ptr.as<int64_t>(), s.col.as<int32_t>(), s.elpos.as<int32_t>(),
-                           err.as<int>());
-    else
-        hipLaunchKernelGGL(k_elem_block_pos<4>, g2, b1, 0, st, ne, m.conn.as<int32_t>(),
-                           s.row_ptr.as<int64_t>(), s.col.as<int32_t>(), s.elpos.as<int32_t>(),
-                           err.as<int>());
+    {
+        auto kern = nv == 3 ? k_elem_block_pos<3>
+                            : nv == 4 ? k_elem_block_pos<4> : nv == 6 ? k_elem_block_pos<6> : k_elem_block_pos<10>;
+        hipLaunchKernelGGL(kern, g2, b1, 0, st, ne, m.conn.as<int32_t>(), s.row_ptr.as<int64_t>(),
+                           s.col.as<int32_t>(), s.elpos.as<int32_t>(), err.as<int>());
+    }
     NLQ_CHECK_LAUNCH();
     int herr = 0;
     NLQ_HIP(hipMemcpyAsync(&herr, err.as<void>(), sizeof(int), hipMemcpyDeviceToHost, st));

@@ -16,37 +16,63 @@ namespace nlq {
 
 namespace {
 
-// F_i += sum_q w_q |T| f_h(x_q) lambda_i(x_q) over the elements T containing i
-template <int DIM>
+// Lagrange basis of order ORD at barycentric point lam: P1 lambda_i; P2
+// lambda_i (2 lambda_i - 1) at the vertices, 4 lambda_i lambda_j at the edges
+// (i < j, lexicographic)
+template <int DIM, int ORD>
+__device__ __forceinline__ void lagrange_basis(const double *lam, double *phi)
+{
+    constexpr int NV = DIM + 1;
+    if constexpr (ORD == 1) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) phi[i] = lam[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) phi[i] = lam[i] * (2.0 * lam[i] - 1.0);
+        int k = NV;
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+#pragma unroll
+            for (int j = i + 1; j < NV; ++j) phi[k++] = 4.0 * lam[i] * lam[j];
+    }
+}
+
+// F_i += sum_q w_q |T| f_h(x_q) phi_i(x_q) over the elements T containing i, with
+// f_h the interpolant of the nodal f in the element's space (P1 or P2)
+template <int DIM, int ORD = 1>
 __global__ void k_load(int64_t ne, const int32_t *__restrict__ conn, const double *__restrict__ meas,
                        const double *__restrict__ rule, const double *__restrict__ f,
                        const uint8_t *__restrict__ constrained, double *__restrict__ F)
 {
     constexpr int NV = DIM + 1, NQ = DIM == 2 ? 7 : 15;
+    constexpr int NB = ORD == 1 ? NV : NV * (NV + 1) / 2;
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= ne) return;
     const double *bary = rule;
     const double *w = rule + NQ * NV;
-    double fv[NV];
-    int32_t id[NV];
+    double fv[NB];
+    int32_t id[NB];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        id[v] = conn[e * NV + v];
+    for (int v = 0; v < NB; ++v) {
+        id[v] = conn[e * NB + v];
         fv[v] = f[id[v]];
     }
     const double me = meas[e];
+    double s[NB];
 #pragma unroll
-    for (int a = 0; a < NV; ++a) {
-        if (constrained[id[a]]) continue;
-        double s = 0.0;
-        for (int q = 0; q < NQ; ++q) {
-            double fq = 0.0;
+    for (int a = 0; a < NB; ++a) s[a] = 0.0;
+    for (int q = 0; q < NQ; ++q) {
+        double phi[NB];
+        lagrange_basis<DIM, ORD>(bary + q * NV, phi);
+        double fq = 0.0;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) fq += fv[v] * bary[q * NV + v];
-            s += w[q] * fq * bary[q * NV + a];
-        }
-        unsafeAtomicAdd(&F[id[a]], s * me);
+        for (int v = 0; v < NB; ++v) fq += fv[v] * phi[v];
+#pragma unroll
+        for (int a = 0; a < NB; ++a) s[a] += w[q] * fq * phi[a];
     }
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+        if (!constrained[id[a]]) unsafeAtomicAdd(&F[id[a]], s[a] * me);
 }
 
 // The same load vector summed per node over its elements in ascending order
@@ -294,6 +320,92 @@ k_cg_init(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restr
     }
 }
 
+// ---- BiCGSTAB pieces (the two-term forms: A is not symmetric) -------------
+
+// y = A x on the free block: y_i = sum_{j free} A_ij x_j for free i, 0 on Gamma;
+// one thread per row
+__global__ void __launch_bounds__(256) k_spmv_free(int64_t n, const int64_t *__restrict__ row_ptr,
+                                                   const int32_t *__restrict__ col,
+                                                   const double *__restrict__ val,
+                                                   const uint8_t *__restrict__ cst,
+                                                   const double *__restrict__ x, double *__restrict__ y)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    if (!cst[i])
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            const int32_t j = col[k];
+            if (!cst[j]) s = fma(val[k], x[j], s);
+        }
+    y[i] = s;
+}
+
+// block partials of a.b and c.d (c may be null), a fixed order within a block
+__global__ void __launch_bounds__(kCgThreads) k_dot2(int64_t n, const double *__restrict__ a,
+                                                      const double *__restrict__ b,
+                                                      const double *__restrict__ c,
+                                                      const double *__restrict__ d, double *__restrict__ part)
+{
+    __shared__ double red[2][kCgThreads / kWave];
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    double x = i < n ? a[i] * b[i] : 0.0;
+    double y = (c && i < n) ? c[i] * d[i] : 0.0;
+    x = wave_sum(x);
+    y = wave_sum(y);
+    if (lane_id() == 0) {
+        red[0][threadIdx.x / kWave] = x;
+        red[1][threadIdx.x / kWave] = y;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sx = 0.0, sy = 0.0;
+        for (int w = 0; w < kCgThreads / kWave; ++w) {
+            sx += red[0][w];
+            sy += red[1][w];
+        }
+        part[2 * blockIdx.x] = sx;
+        part[2 * blockIdx.x + 1] = sy;
+    }
+}
+
+// p = r + beta (p - omega v), y = D^{-1} p   (free rows; 0 on Gamma)
+__global__ void __launch_bounds__(256) k_bicg_p(int64_t n, const uint8_t *__restrict__ cst,
+                                                const double *__restrict__ dinv, const double *__restrict__ r,
+                                                const double *__restrict__ v, double beta, double omega,
+                                                double *__restrict__ p, double *__restrict__ y)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double pi = cst[i] ? 0.0 : r[i] + beta * (p[i] - omega * v[i]);
+    p[i] = pi;
+    y[i] = dinv[i] * pi;
+}
+
+// s = r - alpha v, z = D^{-1} s
+__global__ void __launch_bounds__(256) k_bicg_s(int64_t n, const double *__restrict__ dinv,
+                                                const double *__restrict__ r, const double *__restrict__ v,
+                                                double alpha, double *__restrict__ s, double *__restrict__ z)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double si = r[i] - alpha * v[i];
+    s[i] = si;
+    z[i] = dinv[i] * si;
+}
+
+// x += alpha y + omega z, r = s - omega t
+__global__ void __launch_bounds__(256) k_bicg_x(int64_t n, const double *__restrict__ y,
+                                                const double *__restrict__ z, const double *__restrict__ s,
+                                                const double *__restrict__ t, double alpha, double omega,
+                                                double *__restrict__ x, double *__restrict__ r)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    x[i] += alpha * y[i] + omega * z[i];
+    r[i] = s[i] - omega * t[i];
+}
+
 __global__ void k_compose_u(int64_t n, const uint8_t *__restrict__ constrained,
                             const double *__restrict__ w, const double *__restrict__ g,
                             double *__restrict__ u)
@@ -324,12 +436,12 @@ void launch_load_lift(System &s, hipStream_t st, const double *f_dev, const doub
                                m.conn.as<int32_t>(), s.meas.as<double>(), T.rule.as<double>(), f_dev,
                                m.constrained.as<uint8_t>(), s.F.as<double>());
     } else if (ne == 0) {
-    } else if (m.dim == 2)
-        hipLaunchKernelGGL(k_load<2>, g1, b1, 0, st, ne, m.conn.as<int32_t>(), s.meas.as<double>(),
-                           T.rule.as<double>(), f_dev, m.constrained.as<uint8_t>(), s.F.as<double>());
-    else
-        hipLaunchKernelGGL(k_load<3>, g1, b1, 0, st, ne, m.conn.as<int32_t>(), s.meas.as<double>(),
-                           T.rule.as<double>(), f_dev, m.constrained.as<uint8_t>(), s.F.as<double>());
+    } else {
+        auto kern = m.dim == 2 ? (m.order == 2 ? k_load<2, 2> : k_load<2, 1>)
+                               : (m.order == 2 ? k_load<3, 2> : k_load<3, 1>);
+        hipLaunchKernelGGL(kern, g1, b1, 0, st, ne, m.conn.as<int32_t>(), s.meas.as<double>(), T.rule.as<double>(),
+                           f_dev, m.constrained.as<uint8_t>(), s.F.as<double>());
+    }
     NLQ_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_lift, dim3((n + 3) / 4), dim3(256), 0, st, n, s.row_ptr.as<int64_t>(),
                        s.col.as<int32_t>(), s.val.as<double>(), m.constrained.as<uint8_t>(), g_dev,
@@ -485,6 +597,99 @@ int cg_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, 
                       p2.as<double>(), q.as<double>(), partial.as<double>(), scal.as<CgScalars>()};
     const char *env = std::getenv("NLQ_CG_GRAPH");
     return cg_run(s, st, rtol, maxit, relres, converged, b, !(env && env[0] == '0'), s.u.as<double>());
+}
+
+// Jacobi-preconditioned BiCGSTAB on A_{Omega,Omega} w = F~_Omega for the
+// two-term forms (A not symmetric, so CG does not apply); the same stopping rule
+// as the CG (||r||_2 <= rtol ||F~||_2, checked every iteration); u into s.u.
+int bicgstab_solve(System &s, hipStream_t st, double rtol, int maxit, double *relres, int *converged)
+{
+    const Mesh &m = *s.mesh;
+    const int64_t n = m.n_nodes;
+    if (s.u.empty()) s.u.alloc(s.ctx, sizeof(double) * n);
+    const int64_t nb_vec = cg_nb_vec(n);
+    DevBuf dinv(s.ctx, sizeof(double) * n, st), x(s.ctx, sizeof(double) * n, st), r(s.ctx, sizeof(double) * n, st),
+        rh(s.ctx, sizeof(double) * n, st), p(s.ctx, sizeof(double) * n, st), v(s.ctx, sizeof(double) * n, st),
+        y(s.ctx, sizeof(double) * n, st), sv(s.ctx, sizeof(double) * n, st), z(s.ctx, sizeof(double) * n, st),
+        t(s.ctx, sizeof(double) * n, st), part(s.ctx, sizeof(double) * 2 * nb_vec, st);
+    const uint8_t *cst = m.constrained.as<uint8_t>();
+    std::vector<double> hp(2 * nb_vec);
+    auto dot2 = [&](const double *a, const double *b, const double *c, const double *d, double *o0, double *o1) {
+        hipLaunchKernelGGL(k_dot2, dim3(nb_vec), dim3(kCgThreads), 0, st, n, a, b, c, d, part.as<double>());
+        NLQ_CHECK_LAUNCH();
+        NLQ_HIP(hipMemcpyAsync(hp.data(), part.as<void>(), sizeof(double) * 2 * nb_vec, hipMemcpyDeviceToHost, st));
+        NLQ_HIP(hipStreamSynchronize(st));
+        double a0 = 0.0, a1 = 0.0;
+        for (int64_t k = 0; k < nb_vec; ++k) {
+            a0 += hp[2 * k];
+            a1 += hp[2 * k + 1];
+        }
+        *o0 = a0;
+        if (o1) *o1 = a1;
+    };
+    // the CG's initialisation gives D^{-1}, x = 0, r = F~ (free rows); its
+    // other outputs are overwritten below
+    hipLaunchKernelGGL(k_cg_init, dim3(nb_vec), dim3(kCgThreads), 0, st, n, s.row_ptr.as<int64_t>(),
+                       s.col.as<int32_t>(), s.val.as<double>(), cst, s.Ft.as<double>(), dinv.as<double>(),
+                       x.as<double>(), r.as<double>(), z.as<double>(), p.as<double>(), part.as<double>(), nb_vec);
+    NLQ_CHECK_LAUNCH();
+    NLQ_HIP(hipMemcpyAsync(rh.as<void>(), r.as<void>(), sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    NLQ_HIP(hipMemsetAsync(p.as<void>(), 0, sizeof(double) * n, st));
+    NLQ_HIP(hipMemsetAsync(v.as<void>(), 0, sizeof(double) * n, st));
+    double bb = 0.0;
+    dot2(r.as<double>(), r.as<double>(), nullptr, nullptr, &bb, nullptr);
+    const double bnorm = std::sqrt(bb);
+    *converged = 0;
+    int it = 0;
+    double rn = bnorm;
+    const dim3 g((n + 255) / 256), b(256);
+    if (bnorm == 0.0) {
+        *converged = 1;
+    } else {
+        double rho = 1.0, alpha = 1.0, omega = 1.0;
+        for (it = 0; it < maxit; ++it) {
+            double rho_new = 0.0;
+            dot2(rh.as<double>(), r.as<double>(), nullptr, nullptr, &rho_new, nullptr);
+            if (rho_new == 0.0) break;
+            const double beta = it == 0 ? 0.0 : (rho_new / rho) * (alpha / omega);
+            hipLaunchKernelGGL(k_bicg_p, g, b, 0, st, n, cst, dinv.as<double>(), r.as<double>(), v.as<double>(), beta,
+                               omega, p.as<double>(), y.as<double>());
+            hipLaunchKernelGGL(k_spmv_free, g, b, 0, st, n, s.row_ptr.as<int64_t>(), s.col.as<int32_t>(),
+                               s.val.as<double>(), cst, y.as<double>(), v.as<double>());
+            NLQ_CHECK_LAUNCH();
+            double rv = 0.0;
+            dot2(rh.as<double>(), v.as<double>(), nullptr, nullptr, &rv, nullptr);
+            if (rv == 0.0) break;
+            alpha = rho_new / rv;
+            hipLaunchKernelGGL(k_bicg_s, g, b, 0, st, n, dinv.as<double>(), r.as<double>(), v.as<double>(), alpha,
+                               sv.as<double>(), z.as<double>());
+            hipLaunchKernelGGL(k_spmv_free, g, b, 0, st, n, s.row_ptr.as<int64_t>(), s.col.as<int32_t>(),
+                               s.val.as<double>(), cst, z.as<double>(), t.as<double>());
+            NLQ_CHECK_LAUNCH();
+            double ts = 0.0, tt = 0.0;
+            dot2(t.as<double>(), sv.as<double>(), t.as<double>(), t.as<double>(), &ts, &tt);
+            omega = tt > 0.0 ? ts / tt : 0.0;
+            hipLaunchKernelGGL(k_bicg_x, g, b, 0, st, n, y.as<double>(), z.as<double>(), sv.as<double>(),
+                               t.as<double>(), alpha, omega, x.as<double>(), r.as<double>());
+            NLQ_CHECK_LAUNCH();
+            double rr = 0.0;
+            dot2(r.as<double>(), r.as<double>(), nullptr, nullptr, &rr, nullptr);
+            rn = std::sqrt(rr);
+            rho = rho_new;
+            if (rn <= rtol * bnorm) {
+                *converged = 1;
+                ++it;
+                break;
+            }
+            if (omega == 0.0) break;
+        }
+    }
+    *relres = bnorm > 0.0 ? rn / bnorm : 0.0;
+    hipLaunchKernelGGL(k_compose_u, dim3(nb_vec), dim3(kCgThreads), 0, st, n, cst, x.as<double>(),
+                       s.g.as<double>(), s.u.as<double>());
+    NLQ_CHECK_LAUNCH();
+    NLQ_HIP(hipStreamSynchronize(st));
+    return it;
 }
 
 void noalloc_scratch_init(int device)

@@ -3,7 +3,11 @@
 // midpoint refinement of Algorithm 1 (Section 5).
 #include <cmath>
 
+#include <map>
+#include <vector>
+
 #include "nlq_internal.hpp"
+#include "nlq_p2.hpp"
 #include "nlq_refine.hpp"
 
 namespace nlq {
@@ -98,7 +102,101 @@ double xi_host(double r)
                                             s * (-180.0 / 256.0 + s * (35.0 / 256.0)))));
 }
 
+// Polynomials in the barycentric coordinates: exponent vector -> coefficient.
+using Poly = std::map<std::vector<int>, double>;
+
+Poly poly_mul(const Poly &a, const Poly &b)
+{
+    Poly out;
+    for (const auto &x : a)
+        for (const auto &y : b) {
+            std::vector<int> e(x.first.size());
+            for (size_t k = 0; k < e.size(); ++k) e[k] = x.first[k] + y.first[k];
+            out[e] += x.second * y.second;
+        }
+    return out;
+}
+
+// P2 basis function I as a homogeneous quadratic (sum lambda = 1 inserted where
+// the degree is lower): vertex i: 2 lambda_i^2 - lambda_i sum_k lambda_k; edge
+// (i, j): 4 lambda_i lambda_j (edges in lexicographic order).
+Poly p2_basis_hom(int nv, int I)
+{
+    Poly p;
+    auto unit = [&](int i, int j) {
+        std::vector<int> e(nv, 0);
+        e[i] += 1;
+        e[j] += 1;
+        return e;
+    };
+    if (I < nv) {
+        p[unit(I, I)] += 2.0;
+        for (int k = 0; k < nv; ++k) p[unit(I, k)] -= 1.0;
+        return p;
+    }
+    int r = nv;
+    for (int i = 0; i < nv; ++i)
+        for (int j = i + 1; j < nv; ++j, ++r)
+            if (r == I) p[unit(i, j)] = 4.0;
+    return p;
+}
+
 }  // namespace
+
+// Map from the monomial rows accumulated for P2 elements to the rows the
+// epilogue needs (see nlq_p2.hpp): [NU + NB + 1][NR] with rows
+//   u < NU          phi_I phi_J for the upper-triangle slot u = (I, J) (u < NB the
+//                   diagonal, then I < J in lexicographic order),
+//   NU + I          phi_I (sum lambda)^2,
+//   NU + NB         (sum lambda)^4,
+// every one a homogeneous quartic written in the monomials of Mono4.
+std::vector<double> make_p2_map(int dim)
+{
+    const int nv = dim + 1, nb = p2_nodes(dim), nu = nb * (nb + 1) / 2, nr = p2_monomials(dim);
+    std::vector<std::vector<int>> mono;
+    if (nv == 3) {
+        constexpr Mono4<3> m{};
+        for (int k = 0; k < m.N; ++k) mono.emplace_back(m.e[k], m.e[k] + 3);
+    } else {
+        constexpr Mono4<4> m{};
+        for (int k = 0; k < m.N; ++k) mono.emplace_back(m.e[k], m.e[k] + 4);
+    }
+    std::map<std::vector<int>, int> index;
+    for (int k = 0; k < nr; ++k) index[mono[k]] = k;
+    Poly sum1;
+    for (int k = 0; k < nv; ++k) {
+        std::vector<int> e(nv, 0);
+        e[k] = 1;
+        sum1[e] = 1.0;
+    }
+    const Poly sum2 = poly_mul(sum1, sum1), sum4 = poly_mul(sum2, sum2);
+    std::vector<Poly> rows(nu + nb + 1);
+    std::vector<Poly> phi(nb);
+    for (int I = 0; I < nb; ++I) phi[I] = p2_basis_hom(nv, I);
+    for (int u = 0; u < nu; ++u) {
+        int I = u, J = u;
+        if (u >= nb) {
+            int r = nb;
+            for (int a = 0; a < nb; ++a)
+                for (int c = a + 1; c < nb; ++c, ++r)
+                    if (r == u) {
+                        I = a;
+                        J = c;
+                    }
+        }
+        rows[u] = poly_mul(phi[I], phi[J]);
+    }
+    for (int I = 0; I < nb; ++I) rows[nu + I] = poly_mul(phi[I], sum2);
+    rows[nu + nb] = sum4;
+    std::vector<double> map(static_cast<size_t>(nu + nb + 1) * nr, 0.0);
+    for (size_t r = 0; r < rows.size(); ++r)
+        for (const auto &t : rows[r]) {
+            auto it = index.find(t.first);
+            if (it == index.end()) fail(NLQ_EDEVICE, "P2 map: a product is not a quartic");
+            map[r * nr + it->second] += t.second;
+        }
+    return map;
+}
 
 // Kernel constant C.  eta = 1: C_{delta,eps} of Section 6 (kappa = 1).  Gaussian
 // eta: c such that c * omega_N * int_0^{delta+eps} rho^{N+1} eta mu drho = N
@@ -200,6 +298,9 @@ std::unique_ptr<Tables> make_tables(Ctx *ctx, int dim, int lmax)
     t->lam64.alloc(ctx, lam.size() * sizeof(double));
     NLQ_HIP(hipMemcpy(t->lam64.as<void>(), lam.data(), lam.size() * sizeof(double),
                       hipMemcpyHostToDevice));
+    const std::vector<double> p2 = make_p2_map(dim);
+    t->p2map.alloc(ctx, p2.size() * sizeof(double));
+    NLQ_HIP(hipMemcpy(t->p2map.as<void>(), p2.data(), p2.size() * sizeof(double), hipMemcpyHostToDevice));
     return t;
 }
 

@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTREA
 # every extern "C" symbol declared in include/nlq.h
 EXPORTS = [
     "nlq_ctx_create", "nlq_ctx_set_stream", "nlq_ctx_memory", "nlq_ctx_destroy",
-    "nlq_mesh_create", "nlq_mesh_box", "nlq_mesh_info", "nlq_mesh_copy", "nlq_mesh_destroy",
+    "nlq_mesh_create", "nlq_mesh_create_order", "nlq_mesh_box", "nlq_mesh_info", "nlq_mesh_copy", "nlq_mesh_destroy",
     "nlq_assemble", "nlq_prepare", "nlq_integrate_range", "nlq_integrate_ranges", "nlq_assemble_batch", "nlq_assemble_info_get",
     "nlq_autotune", "nlq_tune_save", "nlq_tune_load", "nlq_reassemble", "nlq_set_data",
     "nlq_set_data_device", "nlq_solve", "nlq_solve_noalloc", "nlq_solution_device",
@@ -112,6 +112,7 @@ def lib():
             "nlq_ctx_memory": [vp, P(u64), P(u64)],
             "nlq_ctx_destroy": [vp],
             "nlq_mesh_create": [vp, i32, i64, vp, i64, vp, vp, P(vp)],
+            "nlq_mesh_create_order": [vp, i32, i32, i64, vp, i64, vp, vp, P(vp)],
             "nlq_mesh_box": [vp, i32, i32, i32, P(vp)],
             "nlq_mesh_info": [vp, P(i32), P(i64), P(i64), P(i64)],
             "nlq_mesh_copy": [vp, vp, vp, vp],
@@ -219,24 +220,29 @@ class Context:
 
 
 class Mesh:
-    def __init__(self, ctx: Context, h):
+    def __init__(self, ctx: Context, h, order: int = 1):
         self.ctx = ctx
         self.h = h
+        self.order = order
         self._systems = weakref.WeakSet()
         ctx._meshes.add(self)
         d, nn, ne, nf = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64()
         _check(lib().nlq_mesh_info(h, C.byref(d), C.byref(nn), C.byref(ne), C.byref(nf)))
         self.dim, self.n_nodes, self.n_elems, self.n_free = d.value, nn.value, ne.value, nf.value
+        # nodes per element: the vertices, then (P2) the edge midpoints
+        self.nb = (self.dim + 1) if order == 1 else (self.dim + 1) * (self.dim + 2) // 2
 
     @classmethod
-    def create(cls, ctx, coords, conn, constrained):
+    def create(cls, ctx, coords, conn, constrained, order: int = 1):
+        """P1 (order 1, conn [e][dim+1]) or P2 (order 2, conn [e][(dim+1)(dim+2)/2]:
+        vertices, then the edge midpoints of edges (0,1),(0,2),... in lexicographic order)."""
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         conn = np.ascontiguousarray(conn, dtype=np.int32)
         cst = np.ascontiguousarray(constrained, dtype=np.uint8)
         h = C.c_void_p()
-        _check(lib().nlq_mesh_create(ctx.h, coords.shape[1], coords.shape[0], _ptr(coords),
-                                     conn.shape[0], _ptr(conn), _ptr(cst), C.byref(h)))
-        return cls(ctx, h)
+        _check(lib().nlq_mesh_create_order(ctx.h, coords.shape[1], order, coords.shape[0], _ptr(coords),
+                                           conn.shape[0], _ptr(conn), _ptr(cst), C.byref(h)))
+        return cls(ctx, h, order)
 
     @classmethod
     def box(cls, ctx, dim, n, k_gamma):
@@ -246,7 +252,7 @@ class Mesh:
 
     def copy(self):
         coords = np.zeros((self.n_nodes, self.dim))
-        conn = np.zeros((self.n_elems, self.dim + 1), dtype=np.int32)
+        conn = np.zeros((self.n_elems, self.nb), dtype=np.int32)
         cst = np.zeros(self.n_nodes, dtype=np.uint8)
         _check(lib().nlq_mesh_copy(self.h, _ptr(coords), _ptr(conn), _ptr(cst)))
         return coords, conn, cst
@@ -395,7 +401,7 @@ class System:
     def pair_blocks(self, l, m):
         l = np.ascontiguousarray(l, dtype=np.int32)
         m = np.ascontiguousarray(m, dtype=np.int32)
-        n2 = 2 * (self.mesh.dim + 1)
+        n2 = 2 * self.mesh.nb
         out = np.zeros((l.shape[0], n2, n2))
         _check(lib().nlq_pair_blocks(self.h, l.shape[0], _ptr(l), _ptr(m), _ptr(out)))
         return out
