@@ -226,13 +226,17 @@ nlq_status nlq_assemble_batch(nlq_ctx *ctx, int32_t n, const nlq_mesh *const *me
                               const nlq_params *params, nlq_system **out);
 nlq_status nlq_assemble_info_get(const nlq_system *sys, nlq_assemble_info *info);
 
-/* Autotuner of the integration launch.  Candidate configurations (register
- * budget variant of the kernel, persistent workgroups per CU, largest part of
- * one pair list J_l per work item) are timed on a sample of the system's own
- * outer elements (about four work items per resident workgroup, middle of the
- * mesh) for about budget_s seconds (<= 0: 2); the fastest is kept in the
- * context for every later assembly with the same (dim, precision, kernel,
- * L_max, size class of max |J_l|), including the serving loop's.  An assembled
+/* Autotuner of the integration launch.  Candidate configurations are timed on a
+ * sample of the system's own outer elements (about four work items per resident
+ * workgroup, middle of the mesh) for about budget_s seconds (<= 0: 2): first the
+ * launch shape (register budget variant of the kernel, persistent workgroups
+ * per CU, largest part of one pair list J_l per work item), then, from the best
+ * shape, the capacity of each wave's traversal stack (64..512 entries: how many
+ * sub-elements of Algorithm 1 one pass may pop and refine) and of its leaf
+ * buffer (64..256: how many leaves are integrated per flush).  The fastest is
+ * kept in the context for every later assembly with the same (dim, element
+ * order, precision, kernel, L_max, size class of max |J_l|), including the
+ * serving loop's.  An assembled
  * system's values are recomputed with it (nlq_set_data must be called again); a
  * prepared one's (nlq_prepare) are set back to zero. */
 typedef struct {
@@ -242,12 +246,15 @@ typedef struct {
     int32_t work_items_per_element; /* parts each outer element is cut into */
     int32_t candidates;             /* configurations timed */
     double best_ms, default_ms;     /* sample launch time: chosen and default configuration */
+    int32_t stack_capacity;         /* traversal stack entries per wave (untuned: 128) */
+    int32_t leaf_capacity;          /* leaf buffer entries per wave (untuned: 128) */
 } nlq_tune_info;
 nlq_status nlq_autotune(nlq_system *sys, double budget_s, nlq_tune_info *info);
 /* The context's tuned configurations as a text file, so that a later process
  * can start tuned: a comment line, then one line per class key
- * "arch dim precision kernel lmax size_class occ wg_per_cu pairs_per_item"
- * (arch of the device, e.g. gfx950).  nlq_tune_save writes (overwrites) path;
+ * "arch dim order precision kernel lmax size_class occ wg_per_cu pairs_per_item
+ * stack_cap leaf_cap" (arch of the device, e.g. gfx950; lines of the earlier
+ * format without order and capacities load as P1 with the untuned capacities).  nlq_tune_save writes (overwrites) path;
  * nlq_tune_load reads such a file and keeps the lines of this context's
  * architecture (others are skipped), setting *n_loaded (may be NULL) to their
  * number.  A file that cannot be opened, or a line that does not parse, gives

@@ -712,6 +712,8 @@ nlq_status nlq_autotune(nlq_system *sys, double budget_s, nlq_tune_info *info)
             info->workgroups_per_cu = static_cast<int32_t>(integrate_slots(s.ctx, s) / std::max(s.ctx->n_cu, 1));
             info->pairs_per_item = s.cfg.pairs_per_item;
             info->work_items_per_element = integrate_split(s);
+            info->stack_capacity = s.cfg.stack_cap;
+            info->leaf_capacity = s.cfg.leaf_cap;
             info->candidates = n;
             info->best_ms = best;
             info->default_ms = def;
@@ -724,16 +726,20 @@ nlq_status nlq_tune_save(const nlq_ctx *ctx, const char *path)
     return guard([&] {
         if (!ctx || !path) fail(NLQ_EINVAL, "NULL argument");
         const Ctx &c = ctx->impl;
-        std::string text = "# nlq tuning cache v1: arch dim precision kernel lmax size_class occ wg_per_cu pairs_per_item\n";
+        std::string text =
+            "# nlq tuning cache v2: arch dim order precision kernel lmax size_class occ wg_per_cu pairs_per_item "
+            "stack_cap leaf_cap\n";
         {
             std::lock_guard<std::mutex> g(const_cast<Ctx &>(c).tune_mu);
             for (const auto &kv : c.tuned) {
                 const TuneKey &k = kv.first;
                 const TuneConfig &t = kv.second;
-                text += c.arch + " " + std::to_string(std::get<0>(k)) + " " + std::to_string(std::get<1>(k)) + " " +
-                        std::to_string(std::get<2>(k)) + " " + std::to_string(std::get<3>(k)) + " " +
-                        std::to_string(std::get<4>(k)) + " " + std::to_string(t.occ) + " " +
-                        std::to_string(t.wg_per_cu) + " " + std::to_string(t.pairs_per_item) + "\n";
+                const int fields[] = {std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
+                                      std::get<4>(k), std::get<5>(k), t.occ, t.wg_per_cu, t.pairs_per_item,
+                                      t.stack_cap, t.leaf_cap};
+                text += c.arch;
+                for (int v : fields) text += " " + std::to_string(v);
+                text += "\n";
             }
         }
         FILE *f = std::fopen(path, "w");
@@ -756,20 +762,32 @@ nlq_status nlq_tune_load(nlq_ctx *ctx, const char *path, int32_t *n_loaded)
         while (std::fgets(line, sizeof line, f)) {
             ++lineno;
             if (line[0] == '#' || line[0] == '\n' || line[0] == '\0') continue;
+            // v2 lines: arch and 11 fields; v1 lines (P1 only, default capacities):
+            // arch dim precision kernel lmax size_class occ wg_per_cu pairs_per_item
             char arch[64];
-            int dim, prec, kernel, lmax, lg, occ, wg, ppi;
-            if (std::sscanf(line, "%63s %d %d %d %d %d %d %d %d", arch, &dim, &prec, &kernel, &lmax, &lg, &occ, &wg,
-                            &ppi) != 9 || (dim != 2 && dim != 3) || (prec != 0 && prec != 1) || (occ != 0 && occ != 1) ||
-                wg < 0 || ppi < 1 || lmax < 1 || lg < 0) {
+            int v[11];
+            const int got_n = std::sscanf(line, "%63s %d %d %d %d %d %d %d %d %d %d %d", arch, &v[0], &v[1], &v[2],
+                                          &v[3], &v[4], &v[5], &v[6], &v[7], &v[8], &v[9], &v[10]);
+            int dim, order = 1, prec, kernel, lmax, lg;
+            TuneConfig t;
+            if (got_n == 12) {
+                dim = v[0], order = v[1], prec = v[2], kernel = v[3], lmax = v[4], lg = v[5];
+                t.occ = v[6], t.wg_per_cu = v[7], t.pairs_per_item = v[8], t.stack_cap = v[9], t.leaf_cap = v[10];
+            } else if (got_n == 9) {
+                dim = v[0], prec = v[1], kernel = v[2], lmax = v[3], lg = v[4];
+                t.occ = v[5], t.wg_per_cu = v[6], t.pairs_per_item = v[7];
+            } else {
+                bad = true;
+                break;
+            }
+            if ((dim != 2 && dim != 3) || (order != 1 && order != 2) || (prec != 0 && prec != 1) ||
+                (t.occ != 0 && t.occ != 1) || t.wg_per_cu < 0 || t.pairs_per_item < 1 || lmax < 1 || lg < 0 ||
+                t.stack_cap < 64 || t.stack_cap > 1024 || t.leaf_cap < 64 || t.leaf_cap > 512) {
                 bad = true;
                 break;
             }
             if (ctx->impl.arch != arch) continue;
-            TuneConfig t;
-            t.occ = occ;
-            t.wg_per_cu = wg;
-            t.pairs_per_item = ppi;
-            got.emplace_back(TuneKey(dim, prec, kernel, lmax, lg), t);
+            got.emplace_back(TuneKey(dim, order, prec, kernel, lmax, lg), t);
         }
         std::fclose(f);
         if (bad) fail(NLQ_EINVAL, std::string(path) + ": line " + std::to_string(lineno) + " does not parse");

@@ -6,9 +6,10 @@
 // form of the Corollary) is accumulated into the pair's blocks.
 //
 // Work decomposition (one GPU, persistent launch):
-//   * a workgroup of kWaves waves takes outer elements l from a global counter,
-//     stages the CSR rows of l's nodes in LDS, and its waves take the pairs
-//     (l, m), m in J_l, from an LDS counter;
+//   * a workgroup of kWaves waves takes work items (an outer element l, or a
+//     part of its pair list) from a global counter, stages the CSR rows of l's
+//     nodes in LDS, and its waves take the pairs (l, m), m in J_l, from an LDS
+//     counter;
 //   * a wave walks the refinement tree of its pair level by level: lanes
 //     classify sub-elements in FP64 (every rounding as written, so the leaf set
 //     is reproducible bit for bit), wave ballots + prefix counts compact the
@@ -53,7 +54,8 @@ namespace {
 
 constexpr int kWaves = 4;
 constexpr int kThreads = kWaves * kWave;
-constexpr int kLeafCap = 128;
+// leaf buffer entries per wave (a launch parameter; at least one wave's pushes)
+constexpr int kLeafCapMin = 64, kLeafCapMax = 512;
 constexpr int kBatch = 64;
 // waves per SIMD requested from the register allocator: variant 0 (the default:
 // 5 in 2D, 4 for the 3D FP32 path, 3 for the 3D FP64 path) and variant 1 -- one
@@ -145,8 +147,8 @@ typedef const __attribute__((address_space(4))) AsmArgs CArgs;
 constexpr int kMaxSeg = 32;
 // largest part of one J_l handled as one work item (a workgroup's unit of work)
 constexpr int64_t kPairsPerItem = 512;
-// logical capacity of a wave's traversal stack (entries)
-constexpr int kStackCap = 128;
+// logical capacity of a wave's traversal stack (entries): a tuning parameter
+constexpr int kStackCapMin = 64, kStackCapMax = 1024;
 struct LaunchArgs {
     const AsmArgs *sys;
     const int32_t *seg_sys;
@@ -155,6 +157,7 @@ struct LaunchArgs {
     int nseg;
     int capl;                   // LDS layout: traversal stack entries per wave
     int rowcap;                 // LDS layout: cached CSR row capacity
+    int leafcap;                // LDS layout: leaf buffer entries per wave
     unsigned int *counter;
 };
 
@@ -846,9 +849,9 @@ template <int DIM, int PREC, int ORD = 1> struct WaveMem {
     static constexpr int kMemoLevel = DIM == 2 ? 3 : 1;
     static constexpr int kMemoCount = DIM == 2 ? 4 + 16 : 0;
     static constexpr int kMemoBytes = kMemoCount * S::NV * DIM * 8;
-    __host__ __device__ static int bytes(int capl)
+    __host__ __device__ static int bytes(int capl, int leafcap)
     {
-        return (kWorkBytes + kLeafCap * 4 + kMemoBytes + capl * 4 + 15) & ~15;
+        return (kWorkBytes + leafcap * 4 + kMemoBytes + capl * 4 + 15) & ~15;
     }
 };
 
@@ -1042,7 +1045,7 @@ template <int DIM, int PREC, int ETA, int ORD>
 __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pidx, char *wmem,
                              const double *s_rule, const float *s_w32, const double *s_T, const int *s_desc,
                              const double *s_map, double *s_bll, const RowCache *rc, double *ex_block,
-                             unsigned long long *s_leaf)
+                             unsigned long long *s_leaf, int leafcap)
 {
     using S = Shape<DIM>;
     using O = OShape<DIM, ORD>;
@@ -1059,7 +1062,7 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     double *HQ = reinterpret_cast<double *>(wmem);   // [rows][16], after the last batch
     double *tile = HQ;                               // 16 x 16 (mixed), in place
     uint32_t *leafbuf = reinterpret_cast<uint32_t *>(wmem + WM::kWorkBytes);
-    double *memo = reinterpret_cast<double *>(leafbuf + kLeafCap);    // WM::kMemoCount simplices
+    double *memo = reinterpret_cast<double *>(leafbuf + leafcap);     // WM::kMemoCount simplices
     uint32_t *stack = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(memo) + WM::kMemoBytes);   // A.capl
 
     // geometry of l (root simplex) and m: wave-uniform, read through the scalar
@@ -1158,7 +1161,7 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
         const int c = __popcll(mask);
         if (c == 0) return;
         any_leaf = true;
-        if (nleaf + c > kLeafCap) {
+        if (nleaf + c > leafcap) {
             integrate(nleaf);
             nleaf = 0;
         }
@@ -1416,8 +1419,8 @@ k_integrate(LaunchArgs L)
     __shared__ unsigned long long s_leaf[10];
     __shared__ RowCache s_rc;
     const int wid = threadIdx.x / kWave;
-    char *wmem = smem + wid * WM::bytes(L.capl);
-    uint16_t *rows_lds = reinterpret_cast<uint16_t *>(smem + kWaves * WM::bytes(L.capl));
+    char *wmem = smem + wid * WM::bytes(L.capl, L.leafcap);
+    uint16_t *rows_lds = reinterpret_cast<uint16_t *>(smem + kWaves * WM::bytes(L.capl, L.leafcap));
     // the quadrature rule (and the P2 map) depends on the dimension only: every
     // system of the launch shares it
     CArgs &A0 = *(CArgs *)(L.sys);
@@ -1490,7 +1493,7 @@ k_integrate(LaunchArgs L)
             if (p >= p_hi) break;
             const int32_t m = A.pair_m[b0 + p];
             process_pair<DIM, PREC, ETA, ORD>(A, static_cast<int>(l), m, b0 + p, wmem, s_rule, s_w32, s_T,
-                                              s_desc, s_map, s_bll, &s_rc, nullptr, s_leaf);
+                                              s_desc, s_map, s_bll, &s_rc, nullptr, s_leaf, L.leafcap);
         }
         __syncthreads();
         // B_ll of l (upper triangle; doubled for the adaptive-inner two-term form)
@@ -1523,7 +1526,7 @@ k_pair_blocks(LaunchArgs L)
     __shared__ double s_map[ORD == 1 ? 1 : O::NRX * O::NR];
     CArgs &A = *(CArgs *)(L.sys);
     const int wid = threadIdx.x / kWave;
-    char *wmem = smem + wid * WaveMem<DIM, PREC, ORD>::bytes(L.capl);
+    char *wmem = smem + wid * WaveMem<DIM, PREC, ORD>::bytes(L.capl, L.leafcap);
     for (int t = threadIdx.x; t < NQ * NV + NQ; t += kThreads) s_rule[t] = A.rule[t];
     if (threadIdx.x < NQ) s_w32[threadIdx.x] = static_cast<float>(A.rule[NQ * NV + threadIdx.x]);
     if constexpr (ORD == 2)
@@ -1540,7 +1543,7 @@ k_pair_blocks(LaunchArgs L)
         for (int t = lane_id(); t < 4 * NB * NB; t += kWave) blk[t] = 0.0;
         wave_sync();
         process_pair<DIM, PREC, ETA, ORD>(A, A.ex_l[it], A.ex_m[it], -1, wmem, s_rule, s_w32, s_T, s_desc, s_map,
-                                          nullptr, nullptr, blk, nullptr);
+                                          nullptr, nullptr, blk, nullptr, L.leafcap);
     }
 }
 
@@ -1586,9 +1589,9 @@ __global__ void __launch_bounds__(256) k_symmetrize(int64_t nnz, const int32_t *
 
 // workgroups per CU of one launch and its dynamic LDS bytes
 template <int DIM, int PREC, int ETA, int OCC, int ORD>
-int occupancy(int capl, int rowcap, bool explicit_mode, int *lds_out)
+int occupancy(int capl, int rowcap, int leafcap, bool explicit_mode, int *lds_out)
 {
-    const int per_wave = WaveMem<DIM, PREC, ORD>::bytes(capl);
+    const int per_wave = WaveMem<DIM, PREC, ORD>::bytes(capl, leafcap);
     const int nb = OShape<DIM, ORD>::NB;
     const int lds = kWaves * per_wave + (explicit_mode ? 0 : ((nb * rowcap * 2 + 15) & ~15));
     if (lds > 150 * 1024) fail(NLQ_EINVAL, "lmax too large for the per-wave refinement lists");
@@ -1606,7 +1609,7 @@ void launch_one(Ctx *ctx, const LaunchArgs &L, int64_t items, hipStream_t st, bo
                 int wg_per_cu, hipEvent_t e0, hipEvent_t e1)
 {
     int lds = 0;
-    int per_cu = occupancy<DIM, PREC, ETA, OCC, ORD>(L.capl, L.rowcap, explicit_mode, &lds);
+    int per_cu = occupancy<DIM, PREC, ETA, OCC, ORD>(L.capl, L.rowcap, L.leafcap, explicit_mode, &lds);
     if (wg_per_cu > 0 && wg_per_cu < per_cu) per_cu = wg_per_cu;
     auto kern = explicit_mode ? k_pair_blocks<DIM, PREC, ETA, ORD> : k_integrate<DIM, PREC, ETA, OCC, ORD>;
     int64_t grid = static_cast<int64_t>(ctx->n_cu) * per_cu;
@@ -1661,18 +1664,26 @@ void dispatch(Ctx *ctx, const System &s, const TuneConfig &c, const LaunchArgs &
 }
 
 template <int DIM, int PREC>
-int occupancy_of(int kernel, int occ, int capl, int rowcap, int order)
+int occupancy_of(int kernel, int occ, int capl, int rowcap, int leafcap, int order)
 {
     const bool g = kernel == NLQ_ETA_GAUSS;
     if (order == 2) {
         if (PREC != 0) fail(NLQ_EINVAL, "P2 elements take the FP64 plain path");
-        return g ? occupancy<DIM, 0, 1, 0, 2>(capl, rowcap, false, nullptr)
-                 : occupancy<DIM, 0, 0, 0, 2>(capl, rowcap, false, nullptr);
+        return g ? occupancy<DIM, 0, 1, 0, 2>(capl, rowcap, leafcap, false, nullptr)
+                 : occupancy<DIM, 0, 0, 0, 2>(capl, rowcap, leafcap, false, nullptr);
     }
-    if (occ == 0) return g ? occupancy<DIM, PREC, 1, 0, 1>(capl, rowcap, false, nullptr)
-                           : occupancy<DIM, PREC, 0, 0, 1>(capl, rowcap, false, nullptr);
-    return g ? occupancy<DIM, PREC, 1, 1, 1>(capl, rowcap, false, nullptr)
-             : occupancy<DIM, PREC, 0, 1, 1>(capl, rowcap, false, nullptr);
+    if (occ == 0) return g ? occupancy<DIM, PREC, 1, 0, 1>(capl, rowcap, leafcap, false, nullptr)
+                           : occupancy<DIM, PREC, 0, 0, 1>(capl, rowcap, leafcap, false, nullptr);
+    return g ? occupancy<DIM, PREC, 1, 1, 1>(capl, rowcap, leafcap, false, nullptr)
+             : occupancy<DIM, PREC, 0, 1, 1>(capl, rowcap, leafcap, false, nullptr);
+}
+
+// leaf buffer entries per wave of a system's configuration
+int leaf_cap_of(const System &s)
+{
+    const int c = s.cfg.leaf_cap;
+    if (c < kLeafCapMin || c > kLeafCapMax) fail(NLQ_EINVAL, "leaf buffer capacity out of range");
+    return c;
 }
 
 // work items per outer element of a system
@@ -1746,10 +1757,12 @@ AsmArgs make_args(const System &s, const Tables &T)
     A.lmin = s.p.lmin;
     A.lmax = s.p.lmax;
     A.form = s.p.form;
-    // traversal stack: a logical capacity of kStackCap, plus what forced
+    // traversal stack: the tuned logical capacity, plus what forced
     // single pops can add beyond it (NCH - 1 per level), plus one pass of
     // parents whose children go straight to the leaf buffer
-    A.capl = kStackCap + (1 << m.dim) * (s.p.lmax + 1) + 64;
+    const int stack_cap = s.cfg.stack_cap;
+    if (stack_cap < kStackCapMin || stack_cap > kStackCapMax) fail(NLQ_EINVAL, "stack capacity out of range");
+    A.capl = stack_cap + (1 << m.dim) * (s.p.lmax + 1) + 64;
     // LDS row cache: as long as the longest row, at most 2048 entries per row
     A.rowcap = static_cast<int>(std::min<int64_t>(std::max<int64_t>(s.max_row, 1), 2048));
     A.counters = s.counters.as<AsmCounters>();
@@ -1821,12 +1834,13 @@ void launch_integrate_jobs(Ctx *ctx, LaunchBlock &lb, const std::vector<Integrat
     lb.ensure(ctx, B.bytes);
     char *h = static_cast<char *>(lb.host);
     std::memset(h, 0, B.bytes);
-    int capl = 1, rowcap = 1;
+    int capl = 1, rowcap = 1, leafcap = kLeafCapMin;
     for (size_t k = 0; k < systems.size(); ++k) {
         const System &s = *systems[k];
         const AsmArgs A = make_args(s, ctx->get_tables(s.mesh->dim, s.p.lmax));
         capl = std::max(capl, A.capl);
         rowcap = std::max(rowcap, A.rowcap);
+        leafcap = std::max(leafcap, leaf_cap_of(s));
         std::memcpy(h + B.off_args + k * sizeof(AsmArgs), &A, sizeof(AsmArgs));
     }
     std::memcpy(h + B.off_sys, seg_sys.data(), sizeof(int32_t) * seg_sys.size());
@@ -1851,6 +1865,7 @@ void launch_integrate_jobs(Ctx *ctx, LaunchBlock &lb, const std::vector<Integrat
     L.nseg = static_cast<int>(jobs.size());
     L.capl = capl;
     L.rowcap = rowcap;
+    L.leafcap = leafcap;
     L.counter = reinterpret_cast<unsigned int *>(d);
     if (items > 0) dispatch(ctx, s0, s0.cfg, L, items, st, false, e0, e1);
     // systems whose last outer element is in this launch: diagonal blocks and R + R^T
@@ -1883,13 +1898,13 @@ int64_t integrate_slots(Ctx *ctx, const System &s)
     const AsmArgs A = make_args(s, ctx->get_tables(s.mesh->dim, s.p.lmax));
     const bool plain = s.p.precision == NLQ_FP64_PLAIN;
     int per_cu;
-    const int ord = s.mesh->order;
+    const int ord = s.mesh->order, lc = leaf_cap_of(s);
     if (s.mesh->dim == 2)
-        per_cu = plain ? occupancy_of<2, 0>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, ord)
-                       : occupancy_of<2, 1>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, ord);
+        per_cu = plain ? occupancy_of<2, 0>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, lc, ord)
+                       : occupancy_of<2, 1>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, lc, ord);
     else
-        per_cu = plain ? occupancy_of<3, 0>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, ord)
-                       : occupancy_of<3, 1>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, ord);
+        per_cu = plain ? occupancy_of<3, 0>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, lc, ord)
+                       : occupancy_of<3, 1>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, lc, ord);
     if (s.cfg.wg_per_cu > 0 && s.cfg.wg_per_cu < per_cu) per_cu = s.cfg.wg_per_cu;
     return static_cast<int64_t>(ctx->n_cu) * per_cu;
 }
@@ -1930,6 +1945,7 @@ void launch_pair_blocks(System &s, hipStream_t st, int64_t n, const int32_t *ex_
     L.nseg = 1;
     L.capl = A.capl;
     L.rowcap = A.rowcap;
+    L.leafcap = leaf_cap_of(s);
     L.counter = reinterpret_cast<unsigned int *>(d);
     if (n > 0) dispatch(s.ctx, s, TuneConfig{}, L, n, st, true, nullptr, nullptr);
 }

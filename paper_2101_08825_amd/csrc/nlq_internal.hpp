@@ -113,9 +113,11 @@ struct TuneConfig {
     int occ = 0;               // register budget: 0 = default, 1 = one wave more (2D FP32) / fewer (others)
     int wg_per_cu = 0;         // persistent workgroups per CU (0 = as many as fit)
     int pairs_per_item = 512;  // largest part of one J_l handled as one work item
+    int stack_cap = 128;       // logical traversal stack entries per wave (64 .. 1024)
+    int leaf_cap = 128;        // leaf buffer entries per wave (64 .. 512)
 };
-// dim, precision, kernel, lmax, ceil(log2(max |J_l|))
-using TuneKey = std::tuple<int, int, int, int, int>;
+// dim, element order, precision, kernel, lmax, ceil(log2(max |J_l|))
+using TuneKey = std::tuple<int, int, int, int, int, int>;
 
 struct Ctx {
     int device = 0;

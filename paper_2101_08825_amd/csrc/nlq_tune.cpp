@@ -14,7 +14,7 @@ TuneKey tune_key(const System &s)
 {
     int lg = 0;
     while ((int64_t(1) << lg) < std::max<int64_t>(s.max_pairs, 1)) ++lg;
-    return TuneKey(s.mesh->dim, s.p.precision, s.p.kernel, s.p.lmax, lg);
+    return TuneKey(s.mesh->dim, s.mesh->order, s.p.precision, s.p.kernel, s.p.lmax, lg);
 }
 
 namespace {
@@ -61,10 +61,11 @@ int autotune(System &s, hipStream_t st, double budget_s, double *best_ms, double
     const TuneConfig base = default_config(s);
     *best_ms = *default_ms = 0.0;
     if (s.p.deterministic) return 0;   // sample ranges are not integrated on their own in this mode
-    // candidates: the default first, then the register variant, one workgroup
-    // less per CU, and other work-item sizes where the pair lists get cut
+    // stage 1 candidates: the default first, then the register variant (P1
+    // only: P2 has one), one workgroup less per CU, and other work-item sizes
+    // where the pair lists get cut
     std::vector<TuneConfig> cand{base};
-    for (int occ = 0; occ < 2; ++occ)
+    for (int occ = 0; occ < (s.mesh->order == 1 ? 2 : 1); ++occ)
         for (int less = 0; less < 2; ++less)
             for (int ppi : {512, 256, 1024}) {
                 if (ppi != 512 && s.max_pairs <= 256) continue;
@@ -102,7 +103,11 @@ int autotune(System &s, hipStream_t st, double budget_s, double *best_ms, double
     TuneConfig best = base;
     double best_t = 1e300;
     int timed = 0;
-    for (const TuneConfig &c : cand) {
+    bool out_of_time = false;
+    // times c and keeps it if it is the fastest so far; its time (huge once the
+    // budget is spent and nothing more is timed)
+    auto try_config = [&](const TuneConfig &c) {
+        if (out_of_time) return 1e300;
         (void)time_range(s, c, lo, hi, st, lb, e0, e1);   // warm (code object, caches)
         const double t = std::min(time_range(s, c, lo, hi, st, lb, e0, e1), time_range(s, c, lo, hi, st, lb, e0, e1));
         ++timed;
@@ -112,7 +117,40 @@ int autotune(System &s, hipStream_t st, double budget_s, double *best_ms, double
             best = c;
         }
         const double now = std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-        if (now - t_start > budget_s) break;
+        if (now - t_start > budget_s) out_of_time = true;
+        return t;
+    };
+    for (const TuneConfig &c : cand) try_config(c);
+    // stage 2, from the best launch shape: the traversal stack's logical capacity
+    // (how many sub-elements one pass may pop and expand) and the leaf buffer's
+    // (how many leaves are integrated per flush), one at a time, then together if
+    // both helped
+    const TuneConfig shape = best;
+    TuneConfig best_stack = shape, best_leaf = shape;
+    double t_stack = best_t, t_leaf = best_t;
+    for (int sc : {64, 256, 512}) {
+        TuneConfig c = shape;
+        c.stack_cap = sc;
+        const double t = try_config(c);
+        if (t < t_stack) {
+            t_stack = t;
+            best_stack = c;
+        }
+    }
+    for (int lc : {64, 256}) {
+        TuneConfig c = shape;
+        c.leaf_cap = lc;
+        const double t = try_config(c);
+        if (t < t_leaf) {
+            t_leaf = t;
+            best_leaf = c;
+        }
+    }
+    if (best_stack.stack_cap != shape.stack_cap && best_leaf.leaf_cap != shape.leaf_cap) {
+        TuneConfig c = shape;
+        c.stack_cap = best_stack.stack_cap;
+        c.leaf_cap = best_leaf.leaf_cap;
+        try_config(c);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -60,7 +60,8 @@ class nlq_assemble_info(C.Structure):
 class nlq_tune_info(C.Structure):
     _fields_ = [("occupancy_variant", C.c_int32), ("workgroups_per_cu", C.c_int32),
                 ("pairs_per_item", C.c_int32), ("work_items_per_element", C.c_int32),
-                ("candidates", C.c_int32), ("best_ms", C.c_double), ("default_ms", C.c_double)]
+                ("candidates", C.c_int32), ("best_ms", C.c_double), ("default_ms", C.c_double),
+                ("stack_capacity", C.c_int32), ("leaf_capacity", C.c_int32)]
 
 
 class nlq_solve_info(C.Structure):
