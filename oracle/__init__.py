@@ -32,7 +32,8 @@ _lib = None
 
 class _Mesh(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_nodes", C.c_int64), ("n_elems", C.c_int64),
-                ("coords", C.c_void_p), ("conn", C.c_void_p), ("order", C.c_int32)]
+                ("coords", C.c_void_p), ("conn", C.c_void_p), ("order", C.c_int32),
+                ("shape", C.c_int32)]
 
 
 class _Params(C.Structure):
@@ -58,6 +59,12 @@ def lib():
         L.or_rule.argtypes = [i32, vp, vp]
         L.or_children.restype = None
         L.or_children.argtypes = [i32, vp, vp]
+        L.or_box_rule.restype = i32
+        L.or_box_rule.argtypes = [i32, vp, vp]
+        L.or_box_basis.restype = None
+        L.or_box_basis.argtypes = [i32, i32, vp, vp]
+        L.or_box_children.restype = None
+        L.or_box_children.argtypes = [i32, vp, vp]
         L.or_aprxmax.restype = d
         L.or_aprxmax.argtypes = [i32, vp, vp, vp, vp]
         L.or_aprxmin.restype = d
@@ -105,17 +112,23 @@ def default_threads() -> int:
 class OracleMesh:
     """Holds the arrays alive for the C struct."""
 
-    def __init__(self, coords, conn, order=1):
+    def __init__(self, coords, conn, order=1, shape=0):
+        """shape 0: simplices (P1 / P2); shape 1: quadrilaterals / hexahedra
+        (Q1 / serendipity), corners in tensor order, then the edge midpoints."""
         self.coords = np.ascontiguousarray(coords, dtype=np.float64)
         self.conn = np.ascontiguousarray(conn, dtype=np.int32)
         self.dim = int(self.coords.shape[1])
         self.order = int(order)
-        nb = (self.dim + 1) * (self.dim + 2) // 2 if self.order == 2 else self.dim + 1
+        self.shape = int(shape)
+        if self.shape:
+            nb = (8 if self.dim == 2 else 20) if self.order == 2 else 1 << self.dim
+        else:
+            nb = (self.dim + 1) * (self.dim + 2) // 2 if self.order == 2 else self.dim + 1
         if self.conn.shape[1] != nb:
             raise ValueError(f"order {order} elements need {nb} nodes, conn has {self.conn.shape[1]}")
         self.nb = nb
         self.s = _Mesh(self.dim, self.coords.shape[0], self.conn.shape[0],
-                       self.coords.ctypes.data, self.conn.ctypes.data, self.order)
+                       self.coords.ctypes.data, self.conn.ctypes.data, self.order, self.shape)
 
     @property
     def ref(self):
@@ -146,6 +159,29 @@ def rule(dim):
     w = np.zeros(15)
     n = lib().or_rule(int(dim), _p(bary), _p(w))
     return bary.reshape(-1)[: n * (dim + 1)].reshape(n, dim + 1).copy(), w[:n].copy()
+
+
+def box_rule(dim):
+    xi = np.zeros((27, 3))
+    w = np.zeros(27)
+    n = lib().or_box_rule(int(dim), _p(xi), _p(w))
+    return xi.reshape(-1)[: n * dim].reshape(n, dim).copy(), w[:n].copy()
+
+
+def box_basis(dim, order, xi):
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    nb = (8 if dim == 2 else 20) if order == 2 else 1 << dim
+    phi = np.zeros(nb)
+    lib().or_box_basis(int(dim), int(order), _p(xi), _p(phi))
+    return phi
+
+
+def box_children(P: np.ndarray) -> np.ndarray:
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    dim = P.shape[1]
+    out = np.zeros((1 << dim, 1 << dim, dim))
+    lib().or_box_children(dim, _p(P), _p(out))
+    return out
 
 
 def children(v: np.ndarray) -> np.ndarray:
@@ -314,10 +350,10 @@ class Solution:
 
 
 def solve_problem(mesh_arrays, prm, f_nodal, g_nodal, rtol=1e-14, nthreads=None,
-                  direct=False, order=1):
+                  direct=False, order=1, shape=0):
     """Full oracle pipeline: pairs, pattern, assembly, load, lifting, solve."""
     coords, conn, constrained = mesh_arrays
-    m = OracleMesh(coords, conn, order)
+    m = OracleMesh(coords, conn, order, shape)
     thr = prm.delta + prm.eps
     s = Solution()
     s.off, s.pm = pairs(m, thr, nthreads)

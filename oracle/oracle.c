@@ -33,8 +33,8 @@
 #include <string.h>
 
 #define OR_PI 3.14159265358979323846
-#define MAXQ 15
-#define MAXV 4
+#define MAXQ 27   /* quadrature points per element: 27 for the 3x3x3 hexahedron rule */
+#define MAXV 8    /* geometric vertices: 8 for a hexahedron */
 
 /* ---------------------------------------------------------------- mollifier */
 
@@ -226,6 +226,191 @@ void or_children(int32_t dim, const double *v, double *child)
     children_n(dim, dim, v, child);
 }
 
+/* ------------------------------------------------------------ quadrilaterals, hexahedra */
+
+/* Tensor-product elements (Section 4 allows quadrilaterals and hexahedra; Section 6
+ * integrates them with the 3x3 and 3x3x3 Gauss-Legendre product rules).  The
+ * reference element is [0,1]^N.  Corner c (c = c_0 + 2 c_1 + 4 c_2, "tensor
+ * order") sits at the reference point (c_0, c_1, c_2), and the element map is the
+ * multilinear interpolation of the corners,
+ *   F(xi) = sum_c N_c(xi) P_c,   N_c(xi) = prod_k (c_k ? xi_k : 1 - xi_k).
+ * Linear elements (Q1) have the corners as nodes.  Quadratic ones are the
+ * serendipity elements (8-node quadrilateral, 20-node hexahedron: the node counts
+ * of the paper's Section 6 meshes, 35 -> 93 and 175 -> 605 unknowns): the corners,
+ * then the edge midpoints, each node named by its position t in half-units
+ * (t_k in {0,1,2}; an edge midpoint has exactly one odd t_k), edge midpoints in
+ * increasing t_0 + 3 t_1 + 9 t_2. */
+
+/* 3^N Gauss-Legendre product rule on [0,1]^N: point q = i_0 + 3 i_1 + 9 i_2 at
+ * ((1 + z_{i_0})/2, ...), weight prod_k w_{i_k}/2 (the weights sum to 1) */
+static int box_rule(int dim, double *xi, double *w)
+{
+    double z[3], wz[3];
+    gauss_legendre(3, z, wz);
+    int nq = dim == 2 ? 9 : 27;
+    for (int q = 0; q < nq; ++q) {
+        int i[3] = {q % 3, (q / 3) % 3, q / 9};
+        double ww = 1.0;
+        for (int k = 0; k < dim; ++k) {
+            xi[q * dim + k] = (1.0 + z[i[k]]) / 2.0;
+            ww *= wz[i[k]] / 2.0;
+        }
+        w[q] = ww;
+    }
+    return nq;
+}
+
+int32_t or_box_rule(int32_t dim, double *xi, double *w)
+{
+    return box_rule(dim, xi, w);
+}
+
+/* multilinear weights N_c(xi), products taken over k = 0..N-1 in order */
+static void box_corner_weights(int dim, const double *xi, double *N)
+{
+    for (int c = 0; c < (1 << dim); ++c) {
+        double p = 1.0;
+        for (int k = 0; k < dim; ++k) p = p * (((c >> k) & 1) ? xi[k] : 1.0 - xi[k]);
+        N[c] = p;
+    }
+}
+
+/* x = F(xi): products N_c(xi) * P_c[k] rounded, then added in corner order */
+static void box_map(int dim, const double *P, const double *xi, double *x)
+{
+    double N[8];
+    box_corner_weights(dim, xi, N);
+    for (int k = 0; k < dim; ++k) {
+        double sum = 0.0;
+        for (int c = 0; c < (1 << dim); ++c) sum = sum + N[c] * P[c * dim + k];
+        x[k] = sum;
+    }
+}
+
+/* |det dF/dxi| at xi */
+static double box_jacdet(int dim, const double *P, const double *xi)
+{
+    double J[3][3];
+    for (int k = 0; k < dim; ++k)
+        for (int i = 0; i < dim; ++i) {
+            double sum = 0.0;
+            for (int c = 0; c < (1 << dim); ++c) {
+                /* d N_c / d xi_i */
+                double p = 1.0;
+                for (int j = 0; j < dim; ++j) {
+                    int cj = (c >> j) & 1;
+                    if (j == i) p *= cj ? 1.0 : -1.0;
+                    else p *= cj ? xi[j] : 1.0 - xi[j];
+                }
+                sum += p * P[c * dim + k];
+            }
+            J[k][i] = sum;
+        }
+    double det;
+    if (dim == 2) {
+        det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    } else {
+        det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+              J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+              J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    }
+    return fabs(det);
+}
+
+/* node positions in half-units, in node order */
+static int box_nodes(int dim, int order, int t[20][3])
+{
+    int n = 0;
+    for (int c = 0; c < (1 << dim); ++c, ++n)
+        for (int k = 0; k < 3; ++k) t[n][k] = k < dim ? 2 * ((c >> k) & 1) : 0;
+    if (order != 2) return n;
+    int n3 = dim == 2 ? 9 : 27;
+    for (int q = 0; q < n3; ++q) {
+        int tt[3] = {q % 3, (q / 3) % 3, q / 9}, odd = 0;
+        for (int k = 0; k < dim; ++k) odd += tt[k] == 1;
+        if (odd != 1) continue;
+        for (int k = 0; k < 3; ++k) t[n][k] = tt[k];
+        ++n;
+    }
+    return n;
+}
+
+/* Basis functions at reference point xi.  Q1: N_c.  Serendipity, with
+ * zeta = 2 xi - 1 and the node at p = t - 1 in {-1,0,1}^N:
+ *   corner:           prod_k (1 + zeta_k p_k)/2 * (sum_k zeta_k p_k - (N - 1)),
+ *   midpoint (p_j=0): (1 - zeta_j^2) prod_{k != j} (1 + zeta_k p_k)/2. */
+static void box_basis(int dim, int order, const double *xi, double *phi)
+{
+    if (order != 2) {
+        box_corner_weights(dim, xi, phi);
+        return;
+    }
+    int t[20][3];
+    int nb = box_nodes(dim, order, t);
+    double zeta[3];
+    for (int k = 0; k < dim; ++k) zeta[k] = 2.0 * xi[k] - 1.0;
+    for (int a = 0; a < nb; ++a) {
+        int j = -1;
+        double prod = 1.0, sum = 0.0;
+        for (int k = 0; k < dim; ++k) {
+            int p = t[a][k] - 1;
+            if (p == 0) {
+                j = k;
+                continue;
+            }
+            prod *= (1.0 + zeta[k] * p) / 2.0;
+            sum += zeta[k] * p;
+        }
+        phi[a] = j < 0 ? prod * (sum - (dim - 1)) : (1.0 - zeta[j] * zeta[j]) * prod;
+    }
+}
+
+void or_box_basis(int32_t dim, int32_t order, const double *xi, double *phi)
+{
+    box_basis(dim, order, xi, phi);
+}
+
+/* Midpoint refinement of a quadrilateral or hexahedron into 2^N children
+ * (Section 5: "split E_l into 2^N sub-elements using the midpoint rule").  The
+ * 3^N lattice Q[t], t in {0,1,2}^N, holds the corners at even t; the other points
+ * are formed axis by axis: for k = 0, 1, 2 every point with t_k = 1 and even t_j
+ * (j > k) is (Q[t_k = 0] + Q[t_k = 2]) * 0.5, so edge midpoints come first, then
+ * face and cell centres as midpoints of earlier midpoints.  Child i (i_k in {0,1})
+ * has corner c at Q[i + c]. */
+static void box_children(int dim, const double *P, double *child)
+{
+    double Q[27][3];
+    int n3 = dim == 2 ? 9 : 27;
+    for (int q = 0; q < n3; ++q) {
+        int t[3] = {q % 3, (q / 3) % 3, q / 9}, even = 1;
+        for (int k = 0; k < dim; ++k) even = even && t[k] != 1;
+        if (!even) continue;
+        int c = 0;
+        for (int k = 0; k < dim; ++k) c |= (t[k] / 2) << k;
+        for (int k = 0; k < dim; ++k) Q[q][k] = P[c * dim + k];
+    }
+    const int stride[3] = {1, 3, 9};
+    for (int ax = 0; ax < dim; ++ax)
+        for (int q = 0; q < n3; ++q) {
+            int t[3] = {q % 3, (q / 3) % 3, q / 9}, ok = t[ax] == 1;
+            for (int j = ax + 1; j < dim; ++j) ok = ok && t[j] != 1;
+            if (!ok) continue;
+            for (int k = 0; k < dim; ++k)
+                Q[q][k] = (Q[q - stride[ax]][k] + Q[q + stride[ax]][k]) * 0.5;
+        }
+    for (int i = 0; i < (1 << dim); ++i)
+        for (int c = 0; c < (1 << dim); ++c) {
+            int q = 0;
+            for (int k = 0; k < dim; ++k) q += (((i >> k) & 1) + ((c >> k) & 1)) * stride[k];
+            for (int k = 0; k < dim; ++k) child[(i * (1 << dim) + c) * dim + k] = Q[q][k];
+        }
+}
+
+void or_box_children(int32_t dim, const double *P, double *child)
+{
+    box_children(dim, P, child);
+}
+
 /* ------------------------------------------------------------ distances */
 
 /* Section 5.1, eq. (maxdist): sqrt(sum_k max(d1_k^2, d2_k^2)),
@@ -293,21 +478,39 @@ static void bbox_of(int dim, int nv, const double *v, double *lo, double *hi)
 }
 
 static int nodes_of(const or_mesh *m);
+static double box_jacdet(int dim, const double *P, const double *xi);
+static int box_rule(int dim, double *xi, double *w);
+
+/* geometric vertices: a simplex's dim+1, a quadrilateral's or hexahedron's 2^dim
+ * corners (the first nodes of the element either way) */
+static int geo_vertices(const or_mesh *m)
+{
+    return m->shape ? 1 << m->dim : m->dim + 1;
+}
 
 static void elem_vertices(const or_mesh *m, int64_t e, double *v)
 {
-    int nv = m->dim + 1, nb = nodes_of(m);
+    int nv = geo_vertices(m), nb = nodes_of(m);
     for (int i = 0; i < nv; ++i) {
         int64_t node = m->conn[e * nb + i];
         for (int k = 0; k < m->dim; ++k) v[i * m->dim + k] = m->coords[node * m->dim + k];
     }
 }
 
-/* |E| = |det J| / N! */
+/* |E| = |det J| / N! for a simplex; for a quadrilateral or hexahedron the
+ * integral of |det J| of its multilinear map over [0,1]^N by the 3^N Gauss rule
+ * (exact: |det J| has degree <= N-1 in each variable) */
 double or_elem_measure(const or_mesh *m, int64_t e)
 {
     double v[MAXV * 3];
     elem_vertices(m, e, v);
+    if (m->shape) {
+        double xi[MAXQ * 3], w[MAXQ];
+        int nq = box_rule(m->dim, xi, w);
+        double s = 0.0;
+        for (int q = 0; q < nq; ++q) s += w[q] * box_jacdet(m->dim, v, xi + q * m->dim);
+        return s;
+    }
     if (m->dim == 2) {
         double ax = v[2] - v[0], ay = v[3] - v[1];
         double bx = v[4] - v[0], by = v[5] - v[1];
@@ -371,7 +574,7 @@ static void all_bboxes(const or_mesh *m, double *lo, double *hi)
     double v[MAXV * 3];
     for (int64_t e = 0; e < m->n_elems; ++e) {
         elem_vertices(m, e, v);
-        bbox_of(m->dim, m->dim + 1, v, lo + e * m->dim, hi + e * m->dim);
+        bbox_of(m->dim, geo_vertices(m), v, lo + e * m->dim, hi + e * m->dim);
     }
 }
 
@@ -553,7 +756,10 @@ typedef struct {
     const or_params *p;
     int dim, nv, nq;
     int nb;              /* nodes per element (the basis functions of one element) */
-    double bary[MAXQ * MAXV], w[MAXQ];
+    int shape;           /* 0: simplices; 1: quadrilaterals / hexahedra */
+    double bary[MAXQ * MAXV], w[MAXQ];   /* simplices: barycentric points; boxes: the
+                                            reference points xi in [0,1]^N */
+    double P_l[MAXV * 3];                /* boxes: the corners of the root element l */
     double C, dme, dpe;
     int64_t l;
     double meas_l;
@@ -567,9 +773,11 @@ typedef struct {
     int count_only;      /* 1: Integration() only counts its (sub-element, m) leaves */
 } alg_ctx;
 
-/* nodes per element: P1 the dim+1 vertices, P2 also the edge midpoints */
+/* nodes per element: P1 the dim+1 vertices, P2 also the edge midpoints; Q1 the
+ * 2^dim corners, serendipity also the edge midpoints (8 and 20) */
 static int nodes_of(const or_mesh *m)
 {
+    if (m->shape) return m->order == 2 ? (m->dim == 2 ? 8 : 20) : 1 << m->dim;
     return m->order == 2 ? (m->dim + 1) * (m->dim + 2) / 2 : m->dim + 1;
 }
 
@@ -588,7 +796,48 @@ static void basis(int order, int nv, const double *lam, double *phi)
         for (int j = i + 1; j < nv; ++j) phi[k++] = 4.0 * lam[i] * lam[j];
 }
 
-#define MAXB 10   /* nodes per element, P2 tetrahedron */
+#define MAXB 20   /* nodes per element, 20-node hexahedron */
+
+/* The double Gauss loop over outer points (x_a, weight Wa_a, basis values phx_a)
+ * and inner points (y_b, Wb_b, phy_b) of one (sub-element, m) leaf, added to
+ * the pair's extended block E.  With z = [phi^l(x_a); -phi^m(y_b)] the
+ * four-term integrand (phi_i(x)-phi_i(y))(phi_j(x)-phi_j(y)) of eq.
+ * (Aij-support2) is g z z^T in the extended index space [nodes(l), nodes(m)];
+ * the two-term form is 2 A21 + 2 A22 (Corollary), whose rows are those of the
+ * inner test function (reading R2 restores A21's minus sign); form 2 puts the
+ * rows on the outer element (see integration()). */
+static void point_pairs(alg_ctx *c, double *E, int nq, double (*x)[3], const double *Wa,
+                        double (*phx)[MAXB], double (*y)[3], const double *Wb, double (*phy)[MAXB])
+{
+    int dim = c->dim, nb = c->nb, ne2 = 2 * nb;
+    for (int a = 0; a < nq; ++a) {
+        for (int b = 0; b < nq; ++b) {
+            double d2 = 0.0;
+            for (int k = 0; k < dim; ++k) d2 += (x[a][k] - y[b][k]) * (x[a][k] - y[b][k]);
+            double d = sqrt(d2);
+            double g = c->C * eta(c->p->kernel, d, c->p->delta) *
+                       or_mu(d, c->p->delta, c->p->eps) * Wa[a] * Wb[b];
+            c->evals[0]++;
+            if (d >= c->dme && d <= c->dpe) c->evals[1]++;
+            double z[2 * MAXB];
+            for (int i = 0; i < nb; ++i) {
+                z[i] = phx[a][i];
+                z[nb + i] = -phy[b][i];
+            }
+            if (c->p->form == 0) {
+                for (int P = 0; P < ne2; ++P)
+                    for (int Q = 0; Q < ne2; ++Q) E[P * ne2 + Q] += g * z[P] * z[Q];
+            } else if (c->p->form == 1) {
+                for (int bb = 0; bb < nb; ++bb)
+                    for (int Q = 0; Q < ne2; ++Q)
+                        E[(nb + bb) * ne2 + Q] += 2.0 * g * phy[b][bb] * (-z[Q]);
+            } else {
+                for (int aa = 0; aa < nb; ++aa)
+                    for (int Q = 0; Q < ne2; ++Q) E[aa * ne2 + Q] += 2.0 * g * phx[a][aa] * z[Q];
+            }
+        }
+    }
+}
 
 /* Integration(E_s, J'): the double Gauss loop of eqs. (J21Nr)/(J22Nr) over the
  * outer sub-element s (level `level`) and every whole inner element m in J'.
@@ -615,7 +864,7 @@ static void integration(alg_ctx *c, int level, const double *V, const double *La
     }
     int dim = c->dim, nv = c->nv, nq = c->nq, nb = c->nb, ne2 = 2 * nb;
     double ws = ldexp(c->meas_l, -dim * (level - 1));
-    double x[MAXQ][3], lam[MAXQ][MAXV], phx[MAXQ][MAXB], phy[MAXQ][MAXB];
+    double x[MAXQ][3], lam[MAXQ][MAXV], phx[MAXQ][MAXB], phy[MAXQ][MAXB], Wa[MAXQ];
     for (int a = 0; a < nq; ++a) {
         for (int k = 0; k < dim; ++k) {
             double s = 0.0;
@@ -629,6 +878,7 @@ static void integration(alg_ctx *c, int level, const double *V, const double *La
         }
         basis(c->mesh->order, nv, lam[a], phx[a]);
         basis(c->mesh->order, nv, c->bary + a * nv, phy[a]);
+        Wa[a] = c->w[a] * ws;
     }
     for (int t = 0; t < nJ; ++t) {
         int pos = Jpos[t];
@@ -636,43 +886,53 @@ static void integration(alg_ctx *c, int level, const double *V, const double *La
         double Vm[MAXV * 3];
         elem_vertices(c->mesh, mm, Vm);
         double meas_m = or_elem_measure(c->mesh, mm);
-        double y[MAXQ][3];
-        for (int b = 0; b < nq; ++b)
+        double y[MAXQ][3], Wb[MAXQ];
+        for (int b = 0; b < nq; ++b) {
             for (int k = 0; k < dim; ++k) {
                 double s = 0.0;
                 for (int v = 0; v < nv; ++v) s += c->bary[b * nv + v] * Vm[v * dim + k];
                 y[b][k] = s;
             }
-        double *E = c->E + (size_t)pos * ne2 * ne2;
-        for (int a = 0; a < nq; ++a) {
-            double Wa = c->w[a] * ws;
-            for (int b = 0; b < nq; ++b) {
-                double Wb = c->w[b] * meas_m;
-                double d2 = 0.0;
-                for (int k = 0; k < dim; ++k) d2 += (x[a][k] - y[b][k]) * (x[a][k] - y[b][k]);
-                double d = sqrt(d2);
-                double g = c->C * eta(c->p->kernel, d, c->p->delta) *
-                           or_mu(d, c->p->delta, c->p->eps) * Wa * Wb;
-                c->evals[0]++;
-                if (d >= c->dme && d <= c->dpe) c->evals[1]++;
-                double z[2 * MAXB];
-                for (int i = 0; i < nb; ++i) {
-                    z[i] = phx[a][i];
-                    z[nb + i] = -phy[b][i];
-                }
-                if (c->p->form == 0) {
-                    for (int P = 0; P < ne2; ++P)
-                        for (int Q = 0; Q < ne2; ++Q) E[P * ne2 + Q] += g * z[P] * z[Q];
-                } else if (c->p->form == 1) {
-                    for (int bb = 0; bb < nb; ++bb)
-                        for (int Q = 0; Q < ne2; ++Q)
-                            E[(nb + bb) * ne2 + Q] += 2.0 * g * phy[b][bb] * (-z[Q]);
-                } else {
-                    for (int aa = 0; aa < nb; ++aa)
-                        for (int Q = 0; Q < ne2; ++Q) E[aa * ne2 + Q] += 2.0 * g * phx[a][aa] * z[Q];
-                }
-            }
+            Wb[b] = c->w[b] * meas_m;
         }
+        point_pairs(c, c->E + (size_t)pos * ne2 * ne2, nq, x, Wa, phx, y, Wb, phy);
+        c->leaves[level]++;
+    }
+}
+
+/* Integration(E_s, J') for quadrilaterals and hexahedra: the sub-element s of
+ * level `level` is the reference box xi0 + [0, h]^N, h = 2^{1-level}, of the root
+ * element l.  Its points are the images F_l(xi0 + h g_a) of the 3^N Gauss points
+ * g_a, with weights w_a h^N |det F_l'| there (the composite rule mapped by l's
+ * multilinear map), and l's basis is evaluated at xi0 + h g_a.  Inner element m:
+ * y_b = F_m(g_b), weights w_b |det F_m'(g_b)|. */
+static void integration_box(alg_ctx *c, int level, const double *xi0, const int *Jpos, int nJ)
+{
+    if (c->count_only) {
+        c->leaves[level] += nJ;
+        return;
+    }
+    int dim = c->dim, nq = c->nq, nb = c->nb, ne2 = 2 * nb;
+    double h = ldexp(1.0, 1 - level), hN = ldexp(1.0, -dim * (level - 1));
+    double x[MAXQ][3], phx[MAXQ][MAXB], phy[MAXQ][MAXB], Wa[MAXQ];
+    for (int a = 0; a < nq; ++a) {
+        double xi[3];
+        for (int k = 0; k < dim; ++k) xi[k] = xi0[k] + h * c->bary[a * dim + k];
+        box_map(dim, c->P_l, xi, x[a]);
+        box_basis(dim, c->mesh->order, xi, phx[a]);
+        box_basis(dim, c->mesh->order, c->bary + a * dim, phy[a]);
+        Wa[a] = c->w[a] * hN * box_jacdet(dim, c->P_l, xi);
+    }
+    for (int t = 0; t < nJ; ++t) {
+        int pos = Jpos[t];
+        double Pm[MAXV * 3];
+        elem_vertices(c->mesh, c->J[pos], Pm);
+        double y[MAXQ][3], Wb[MAXQ];
+        for (int b = 0; b < nq; ++b) {
+            box_map(dim, Pm, c->bary + b * dim, y[b]);
+            Wb[b] = c->w[b] * box_jacdet(dim, Pm, c->bary + b * dim);
+        }
+        point_pairs(c, c->E + (size_t)pos * ne2 * ne2, nq, x, Wa, phx, y, Wb, phy);
         c->leaves[level]++;
     }
 }
@@ -722,14 +982,63 @@ static void adaptive(alg_ctx *c, int lcur, const double *V, const double *Lam, c
     free(Jref);
 }
 
+/* Algorithm 1 for quadrilaterals and hexahedra: P holds the physical corners of
+ * the current sub-element (formed by box_children from the root's), xi0 its
+ * reference origin in the root element, h = 2^{1-lcur} its reference size. */
+static void adaptive_box(alg_ctx *c, int lcur, const double *P, const double *xi0, const int *Jpos,
+                         int nJ)
+{
+    int dim = c->dim, nc = 1 << dim;
+    int lmin = c->p->lmin, lmax = c->p->lmax;
+    double CP[8 * 8 * 3];
+    if (lcur < lmin) {
+        box_children(dim, P, CP);
+        for (int ch = 0; ch < nc; ++ch) {
+            double cxi[3];
+            for (int k = 0; k < dim; ++k) cxi[k] = xi0[k] + (((ch >> k) & 1) ? ldexp(1.0, -lcur) : 0.0);
+            adaptive_box(c, lcur + 1, CP + ch * nc * dim, cxi, Jpos, nJ);
+        }
+        return;
+    }
+    if (lcur == lmax) {
+        integration_box(c, lcur, xi0, Jpos, nJ);
+        return;
+    }
+    double lo[3], hi[3];
+    bbox_of(dim, nc, P, lo, hi);
+    int *Jint = (int *)malloc(sizeof(int) * (nJ + 1));
+    int *Jref = (int *)malloc(sizeof(int) * (nJ + 1));
+    int nint = 0, nref = 0;
+    for (int t = 0; t < nJ; ++t) {
+        const double *lo2 = c->jlo + Jpos[t] * dim, *hi2 = c->jhi + Jpos[t] * dim;
+        const double *glo = c->qlo + Jpos[t] * dim, *ghi = c->qhi + Jpos[t] * dim;
+        if (or_aprxmax(dim, lo, hi, lo2, hi2) < c->dme)
+            Jint[nint++] = Jpos[t];
+        else if ((c->p->min_l2 ? or_boxgap_l2(dim, lo, hi, glo, ghi) : or_aprxmin(dim, lo, hi, lo2, hi2)) < c->dpe)
+            Jref[nref++] = Jpos[t];
+    }
+    if (nint > 0) integration_box(c, lcur, xi0, Jint, nint);
+    if (nref > 0) {
+        box_children(dim, P, CP);
+        for (int ch = 0; ch < nc; ++ch) {
+            double cxi[3];
+            for (int k = 0; k < dim; ++k) cxi[k] = xi0[k] + (((ch >> k) & 1) ? ldexp(1.0, -lcur) : 0.0);
+            adaptive_box(c, lcur + 1, CP + ch * nc * dim, cxi, Jref, nref);
+        }
+    }
+    free(Jint);
+    free(Jref);
+}
+
 static void ctx_init(alg_ctx *c, const or_mesh *m, const or_params *p, int64_t *leaves)
 {
     memset(c, 0, sizeof(*c));
     c->mesh = m;
     c->p = p;
     c->dim = m->dim;
-    c->nv = m->dim + 1;
-    c->nq = or_rule(m->dim, c->bary, c->w);
+    c->shape = m->shape;
+    c->nv = geo_vertices(m);
+    c->nq = m->shape ? box_rule(m->dim, c->bary, c->w) : or_rule(m->dim, c->bary, c->w);
     c->nb = nodes_of(m);
     c->C = (p->scale > 0.0) ? p->scale : or_kernel_constant(m->dim, p->kernel, p->delta, p->eps);
     c->dme = p->delta - p->eps;
@@ -770,7 +1079,13 @@ static void run_outer(alg_ctx *c, int64_t l, const int32_t *J, int n, double *E)
                 double a = 0.0, b = 0.0;
                 for (int q = 0; q < c->nq; ++q) {
                     double s = 0.0;
-                    for (int v = 0; v < nv; ++v) s += c->bary[q * nv + v] * V[v * dim + k];
+                    if (c->shape) {
+                        double y[3];
+                        box_map(dim, V, c->bary + q * dim, y);
+                        s = y[k];
+                    } else {
+                        for (int v = 0; v < nv; ++v) s += c->bary[q * nv + v] * V[v * dim + k];
+                    }
                     if (q == 0 || s < a) a = s;
                     if (q == 0 || s > b) b = s;
                 }
@@ -780,11 +1095,17 @@ static void run_outer(alg_ctx *c, int64_t l, const int32_t *J, int n, double *E)
         }
     }
     elem_vertices(c->mesh, l, V);
-    for (int i = 0; i < nv; ++i)
-        for (int j = 0; j < nv; ++j) Lam[i * nv + j] = (i == j) ? 1.0 : 0.0;
     int *Jpos = (int *)malloc(sizeof(int) * (n + 1));
     for (int t = 0; t < n; ++t) Jpos[t] = t;
-    adaptive(c, 1, V, Lam, Jpos, n);
+    if (c->shape) {
+        const double xi0[3] = {0.0, 0.0, 0.0};
+        memcpy(c->P_l, V, sizeof(double) * nv * dim);
+        adaptive_box(c, 1, V, xi0, Jpos, n);
+    } else {
+        for (int i = 0; i < nv; ++i)
+            for (int j = 0; j < nv; ++j) Lam[i * nv + j] = (i == j) ? 1.0 : 0.0;
+        adaptive(c, 1, V, Lam, Jpos, n);
+    }
     free(Jpos);
     if (c->qlo != c->jlo) {
         free(c->qlo);
@@ -1183,18 +1504,30 @@ int64_t or_rows(const or_mesh *m, const or_params *p, double thr, int32_t nthrea
 /* ------------------------------------------------------------ load, lifting, solve */
 
 /* F_i = int_Omega f_h phi_i for free nodes i (Section 2, eq. (A-F)); f_h is the
- * interpolant of the nodal f in the element's space (P1 or P2); the degree-5 rule
- * integrates f_h phi_i exactly for P1 and for P2 with f_h of degree <= 3 (every
- * configuration has constant f). */
+ * interpolant of the nodal f in the element's space.  Simplices (P1, P2): the
+ * degree-5 rule integrates f_h phi_i exactly for P1 and for P2 with f_h of
+ * degree <= 3 (every configuration has constant f).  Quadrilaterals and
+ * hexahedra (Q1, serendipity): the 3^N Gauss rule with the weights
+ * w_q |det F'(xi_q)|, exact for affine elements. */
 void or_load(const or_mesh *m, const double *f_nodal, const uint8_t *constrained, double *F)
 {
-    int nv = m->dim + 1, nb = nodes_of(m);
+    int nv = geo_vertices(m), nb = nodes_of(m), dim = m->dim;
     double bary[MAXQ * MAXV], w[MAXQ], phi[MAXQ][MAXB];
-    int nq = or_rule(m->dim, bary, w);
-    for (int q = 0; q < nq; ++q) basis(m->order, nv, bary + q * nv, phi[q]);
+    int nq;
+    if (m->shape) {
+        nq = box_rule(dim, bary, w);
+        for (int q = 0; q < nq; ++q) box_basis(dim, m->order, bary + q * dim, phi[q]);
+    } else {
+        nq = or_rule(dim, bary, w);
+        for (int q = 0; q < nq; ++q) basis(m->order, nv, bary + q * nv, phi[q]);
+    }
     for (int64_t n = 0; n < m->n_nodes; ++n) F[n] = 0.0;
     for (int64_t e = 0; e < m->n_elems; ++e) {
         double meas = or_elem_measure(m, e);
+        /* per-point weights: w_q |E| (simplices), w_q |det F_e'(xi_q)| (boxes) */
+        double W[MAXQ], P[MAXV * 3];
+        if (m->shape) elem_vertices(m, e, P);
+        for (int q = 0; q < nq; ++q) W[q] = m->shape ? w[q] * box_jacdet(dim, P, bary + q * dim) : w[q] * meas;
         for (int a = 0; a < nb; ++a) {
             int32_t node = m->conn[e * nb + a];
             if (constrained[node]) continue;
@@ -1202,7 +1535,7 @@ void or_load(const or_mesh *m, const double *f_nodal, const uint8_t *constrained
             for (int q = 0; q < nq; ++q) {
                 double fq = 0.0;
                 for (int j = 0; j < nb; ++j) fq += f_nodal[m->conn[e * nb + j]] * phi[q][j];
-                s += w[q] * meas * fq * phi[q][a];
+                s += W[q] * fq * phi[q][a];
             }
             F[node] += s;
         }

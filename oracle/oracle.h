@@ -8,8 +8,9 @@
  * links, includes or calls it, and it shares no code, header or table with it.
  *
  * Conventions: arrays are row-major and 0-based; element connectivity is int32,
- * counts int64, all physical data double.  Simplices only (triangles, tets),
- * P1 Lagrange basis.
+ * counts int64, all physical data double.  Simplices (triangles, tets; P1 or P2
+ * Lagrange) and quadrilaterals / hexahedra (Q1 or serendipity, multilinear
+ * geometry).
  */
 #ifndef NLQ_ORACLE_H
 #define NLQ_ORACLE_H
@@ -28,6 +29,10 @@ typedef struct {
     int32_t order;          /* 1: P1 (dim+1 vertices); 2: P2 Lagrange, the vertices then the
                                edge midpoints in the order (0,1),(0,2),(1,2) [2D],
                                (0,1),(0,2),(0,3),(1,2),(1,3),(2,3) [3D]; straight sides */
+    int32_t shape;          /* 0: simplices; 1: quadrilaterals / hexahedra on [0,1]^N with
+                               the corners in tensor order (corner c at (c&1, c>>1&1,
+                               c>>2&1)), order 1 = Q1, order 2 = serendipity (then the
+                               edge midpoints by position, see or_box_basis) */
 } or_mesh;
 
 typedef struct {
@@ -56,6 +61,13 @@ double or_aprxmin(int32_t dim, const double *lo1, const double *hi1,
 double or_boxgap_l2(int32_t dim, const double *lo1, const double *hi1,
                     const double *lo2, const double *hi2);
 double or_elem_measure(const or_mesh *m, int64_t e);
+/* quadrilaterals / hexahedra: the 3^N Gauss-Legendre rule on [0,1]^N (points
+ * [nq][dim], weights summing to 1; returns nq), the basis at a reference point
+ * (Q1: 2^N values; serendipity: 8 or 20), the 2^N children [2^N][2^N][dim] of a
+ * box given by its corners [2^N][dim] */
+int32_t or_box_rule(int32_t dim, double *xi, double *w);
+void or_box_basis(int32_t dim, int32_t order, const double *xi, double *phi);
+void or_box_children(int32_t dim, const double *P, double *child);
 
 int64_t or_pairs(const or_mesh *m, double thr, int32_t nthreads,
                  int64_t *offsets, int32_t *m_out);

@@ -151,6 +151,69 @@ def jittered_mesh(dim: int, n: int, k_gamma: int, frac: float = 0.2, seed: int =
                 k_gamma=k_gamma)
 
 
+def box_mesh(dim: int, n: int, k_gamma: int, order: int = 1, frac: float = 0.0, seed: int = 0) -> Mesh:
+    """Structured mesh of [0,1]^dim into n^dim squares / cubes (cell id
+    c0 + n*(c1 + n*c2)), quadrilateral or hexahedral elements.
+      * order 1 (Q1): nodes x = i/n (one correctly rounded FP64 division), node id
+        i0 + (n+1)*(i1 + (n+1)*i2); element nodes = the cell's corners in tensor
+        order (corner c = c0 + 2 c1 + 4 c2 at offset (c0, c1, c2));
+      * order 2 (serendipity, 8 / 20 nodes): nodes on the half grid x = j/(2n),
+        j_k in 0..2n, with at most one odd j_k (no face or cell centres), ids in
+        increasing j0 + (2n+1)*(j1 + (2n+1)*j2); element nodes = the corners in
+        tensor order, then the edge midpoints in increasing t0 + 3 t1 + 9 t2 of
+        their offset t in half cells (exactly one t_k = 1).
+    A node is constrained when some coordinate index lies in the layer of K =
+    k_gamma cells (i_k <= K or >= n - K; half-grid j_k <= 2K or >= 2n - 2K).
+    frac > 0 moves every corner node not on the boundary of [0,1]^dim by
+    independent U(-frac h, frac h) offsets per coordinate (seeded PCG64), giving
+    non-affine (bilinear / trilinear) elements; edge midpoints are then placed
+    at the midpoints of their moved corners (straight edges)."""
+    if dim not in (2, 3) or order not in (1, 2):
+        raise ValueError("dim must be 2 or 3, order 1 or 2")
+    if n < 1 or k_gamma < 0:
+        raise ValueError("bad mesh size")
+    rng = np.random.default_rng(seed)
+    s = 2 if order == 2 else 1          # grid steps per cell
+    ng = s * n + 1
+    grid = np.array(list(itertools.product(range(ng), repeat=dim)))[:, ::-1]   # j0 fastest
+    if order == 2:
+        keep = (grid % 2 == 1).sum(axis=1) <= 1
+        grid = grid[keep]
+    key = sum(grid[:, k].astype(np.int64) * ng ** k for k in range(dim))
+    ident = -np.ones(ng ** dim, dtype=np.int64)
+    ident[key] = np.arange(grid.shape[0])
+    coords = grid.astype(np.float64) / float(s * n)
+    constrained = np.zeros(grid.shape[0], dtype=np.uint8)
+    for k in range(dim):
+        constrained |= ((grid[:, k] <= s * k_gamma) | (grid[:, k] >= s * (n - k_gamma))).astype(np.uint8)
+    cells = np.array(list(itertools.product(range(n), repeat=dim)))[:, ::-1]     # c0 fastest
+    offsets = [tuple(2 * ((c >> k) & 1) for k in range(dim)) for c in range(1 << dim)]
+    if order == 2:
+        offsets += [t for t in (tuple((q // 3 ** k) % 3 for k in range(dim)) for q in range(3 ** dim))
+                    if sum(x == 1 for x in t) == 1]
+    cols = []
+    for t in offsets:
+        j = cells * s + np.array(t) * s // 2
+        cols.append(ident[sum(j[:, k].astype(np.int64) * ng ** k for k in range(dim))])
+    conn = np.stack(cols, axis=1).astype(np.int32)
+    if frac > 0.0:
+        off = rng.uniform(-frac, frac, size=coords.shape) / float(n)
+        even = np.all(grid % s == 0, axis=1)
+        inner = np.all((coords > 0.0) & (coords < 1.0), axis=1) & even
+        coords[inner] += off[inner]
+        if order == 2:
+            for e_col in range(1 << dim, conn.shape[1]):
+                t = np.array(offsets[e_col])
+                ax = int(np.argmax(t == 1))
+                a = t.copy()
+                b = t.copy()
+                a[ax], b[ax] = 0, 2
+                ca = conn[:, offsets.index(tuple(int(x) for x in a))]
+                cb = conn[:, offsets.index(tuple(int(x) for x in b))]
+                coords[conn[:, e_col]] = (coords[ca] + coords[cb]) * 0.5
+    return Mesh(dim=dim, n=n, coords=coords, conn=conn, constrained=constrained, k_gamma=k_gamma)
+
+
 def stratified_ranges(n_elems: int, fraction: float, n_strata: int = 32, seed: int = 0):
     """A seeded sample of about `fraction` of the outer elements spread over the
     whole mesh: the ids 1..n_elems-2 cut into n_strata equal strata, one run of

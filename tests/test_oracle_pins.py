@@ -1077,3 +1077,282 @@ def test_p2_consistency_quadratic(oracle_lib):
     assert all(b < a for a, b in zip(two[1:], two[2:]))
     assert two[-1] < 1e-8 and two[1] / two[-1] > 1e4
     assert min(errs[0]) > 1e-5
+
+
+# ----------------------------------------------------------------- quadrilaterals and hexahedra
+
+def _box_space(dim, order):
+    """Monomial exponents of the element's space on [0,1]^dim: Q1 = {e_k <= 1};
+    serendipity = {e_k <= 2 with at most one e_k = 2} (superlinear degree <= 2:
+    8 monomials in 2D, 20 in 3D)."""
+    if order == 1:
+        return [e for e in itertools.product(range(2), repeat=dim)]
+    return [e for e in itertools.product(range(3), repeat=dim) if sum(k == 2 for k in e) <= 1]
+
+
+def _box_nodes(dim, order):
+    """Node positions: corners in tensor order (c = c0 + 2 c1 + 4 c2), then the
+    edge midpoints by increasing t0 + 3 t1 + 9 t2 (t the position in half units)."""
+    nodes = [tuple(float((c >> k) & 1) for k in range(dim)) for c in range(1 << dim)]
+    if order == 2:
+        for q in range(3 ** dim):
+            t = [(q // 3 ** k) % 3 for k in range(dim)]
+            if sum(x == 1 for x in t) == 1:
+                nodes.append(tuple(x / 2 for x in t))
+    return np.array(nodes)
+
+
+def _box_reference(dim, order):
+    """The nodal basis from its definition (phi_i in the space, phi_i(node_j) =
+    delta_ij) by inverting the Vandermonde matrix: phi(xi) = mono(xi) @ Cf."""
+    exps = _box_space(dim, order)
+    nodes = _box_nodes(dim, order)
+    Vd = np.array([[np.prod(x ** np.array(e)) for e in exps] for x in nodes])
+    return exps, np.linalg.inv(Vd)
+
+
+def _box_phi(exps, Cf, xi):
+    mono = np.stack([np.prod(xi ** np.array(e), axis=1) for e in exps], axis=1)
+    return mono @ Cf
+
+
+def _box_map_np(P, xi):
+    """multilinear map of the corners P [2^dim, dim] at points xi [n, dim], and
+    |det| of its Jacobian (numpy)"""
+    dim = P.shape[1]
+    N = np.ones((xi.shape[0], 1 << dim))
+    dN = np.ones((dim, xi.shape[0], 1 << dim))
+    for c in range(1 << dim):
+        for k in range(dim):
+            ck = (c >> k) & 1
+            f = xi[:, k] if ck else 1.0 - xi[:, k]
+            N[:, c] *= f
+            for i in range(dim):
+                dN[i, :, c] *= (1.0 if ck else -1.0) if i == k else f
+    X = N @ P
+    J = np.stack([dN[i] @ P for i in range(dim)], axis=2)     # [n, dim(k), dim(i)]
+    return X, np.abs(np.linalg.det(J))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_box_rule_degree5(oracle_lib, dim):
+    """The 3^N Gauss-Legendre product rule (Section 6: 3x3 for quadrilaterals)
+    integrates xi^e on [0,1]^N exactly for every e_k <= 5 and not for e_k = 6."""
+    xi, w = oracle_lib.box_rule(dim)
+    assert xi.shape == (3 ** dim, dim) and abs(w.sum() - 1.0) < 1e-14
+    for e in itertools.product(range(7), repeat=dim):
+        q = float(np.sum(w * np.prod(xi ** np.array(e), axis=1)))
+        exact = float(np.prod([1.0 / (k + 1) for k in e]))
+        if max(e) <= 5:
+            assert abs(q - exact) < 1e-14, e
+        elif sum(k == 6 for k in e) == 1 and max(e) == 6 and sum(e) == 6:
+            assert abs(q - exact) > 1e-6, e
+
+
+@pytest.mark.parametrize("dim,order", [(2, 1), (2, 2), (3, 1), (3, 2)])
+def test_box_basis_is_the_nodal_basis(oracle_lib, dim, order):
+    """Q1 and serendipity bases equal the Vandermonde-built nodal basis of their
+    space at random points (which fixes the closed forms' signs, factors and node
+    order); they are nodal (Kronecker delta) and sum to one; the serendipity
+    space reproduces every quadratic and nothing of degree 2 in two variables at
+    once (xi_0^2 xi_1^2)."""
+    O = oracle_lib
+    exps, Cf = _box_reference(dim, order)
+    rng = np.random.default_rng(1)
+    pts = rng.uniform(0, 1, size=(40, dim))
+    got = np.array([O.box_basis(dim, order, p) for p in pts])
+    assert np.abs(got - _box_phi(exps, Cf, pts)).max() < 1e-13
+    nodes = _box_nodes(dim, order)
+    K = np.array([O.box_basis(dim, order, p) for p in nodes])
+    assert np.abs(K - np.eye(len(nodes))).max() < 1e-14
+    assert np.abs(got.sum(1) - 1).max() < 1e-14
+    if order == 2:
+        for e in itertools.product(range(3), repeat=dim):
+            if sum(e) > 2:
+                continue
+            f_nodes = np.prod(nodes ** np.array(e), axis=1)
+            assert np.abs(got @ f_nodes - np.prod(pts ** np.array(e), axis=1)).max() < 1e-13
+        bad = np.prod(nodes[:, :2] ** 2, axis=1)
+        assert np.abs(got @ bad - np.prod(pts[:, :2] ** 2, axis=1)).max() > 1e-3
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_box_children_and_measure(oracle_lib, dim):
+    """Midpoint refinement of a non-affine (bilinear / trilinear) element: the
+    children's corners are the parent map at the children's reference corners,
+    and the children's measures (the oracle's integral of |det F'|) add up to the
+    parent's.  In 2D the measure of a quadrilateral equals the shoelace area of
+    its corners; a parallelepiped's equals |det| of its edges."""
+    O = oracle_lib
+    rng = np.random.default_rng(2)
+    ref = np.array([[float((c >> k) & 1) for k in range(dim)] for c in range(1 << dim)])
+    P = ref + rng.uniform(-0.2, 0.2, size=ref.shape)
+    kids = O.box_children(P)
+    for i in range(1 << dim):
+        off = np.array([(i >> k) & 1 for k in range(dim)]) * 0.5
+        X, _ = _box_map_np(P, off + 0.5 * ref)
+        assert np.abs(kids[i] - X).max() < 1e-15
+    def meas(Q):
+        mesh = O.OracleMesh(Q, np.arange(1 << dim, dtype=np.int32)[None, :], shape=1)
+        return O.lib().or_elem_measure(mesh.ref, 0)
+    assert abs(sum(meas(k) for k in kids) - meas(P)) < 1e-14 * meas(P) * 10
+    if dim == 2:
+        x, y = P[[0, 1, 3, 2], 0], P[[0, 1, 3, 2], 1]
+        shoelace = 0.5 * abs(np.dot(x, np.roll(y, -1)) - np.dot(y, np.roll(x, -1)))
+        assert abs(meas(P) - shoelace) < 1e-14
+    E = rng.uniform(-1, 1, size=(dim, dim)) + 2 * np.eye(dim)
+    Pa = np.array([sum(((c >> k) & 1) * E[k] for k in range(dim)) for c in range(1 << dim)])
+    assert abs(meas(Pa) - abs(np.linalg.det(E))) < 1e-13
+
+
+def _box_mass_and_mean(mesh, order):
+    """Mass matrix and int phi_i of an axis-aligned box mesh from the Vandermonde
+    basis and exact monomial integrals (prod 1/(e_k+1)) scaled by h^dim."""
+    dim = mesh.dim
+    exps, Cf = _box_reference(dim, order)
+    nb = Cf.shape[1]
+    Mref = np.zeros((nb, nb))
+    mref = np.zeros(nb)
+    mint = lambda e: float(np.prod([1.0 / (k + 1) for k in e]))
+    for a, ea in enumerate(exps):
+        mref += Cf[a] * mint(ea)
+        for b, eb in enumerate(exps):
+            Mref += np.outer(Cf[a], Cf[b]) * mint(tuple(x + y for x, y in zip(ea, eb)))
+    hN = mesh.h ** dim
+    M = np.zeros((mesh.n_nodes, mesh.n_nodes))
+    mv = np.zeros(mesh.n_nodes)
+    for e in range(mesh.n_elems):
+        idx = mesh.conn[e]
+        M[np.ix_(idx, idx)] += hN * Mref
+        mv[idx] += hN * mref
+    return M, mv
+
+
+@pytest.mark.parametrize("dim,n,order", [(2, 3, 1), (2, 2, 2), (3, 2, 1), (3, 1, 2)])
+@pytest.mark.parametrize("form", [0, 1])
+def test_box_plateau_closed_form(oracle_lib, dim, n, order, form):
+    """Quadrilaterals / hexahedra, every pair on the plateau: A = 2C(|D| M - m m^T)
+    with M and m from the Vandermonde basis and exact monomial integrals --
+    independent of the oracle's closed-form basis, rule and map."""
+    O = oracle_lib
+    mesh = W.box_mesh(dim, n, 0, order)
+    delta, eps = 4.0, 0.5
+    C = O.kernel_constant(dim, 0, delta, eps)
+    m = O.OracleMesh(mesh.coords, mesh.conn, order=order, shape=1)
+    off, pm = O.pairs(m, delta + eps)
+    rp, col = O.pattern(m, off, pm)
+    val, leaves, evals = O.assemble(m, O.params(delta, eps, 2, form=form), off, pm, rp, col)
+    A = _dense(rp, col, val, mesh.n_nodes)
+    M, mv = _box_mass_and_mean(mesh, order)
+    ref = 2 * C * (1.0 * M - np.outer(mv, mv))
+    assert abs(mv.sum() - 1.0) < 1e-14
+    # (the 20 x 20 Vandermonde inverse of the 3D serendipity basis carries ~1e-14)
+    assert np.abs(A - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("dim,n,order,frac,kd,q,lmax", [
+    (2, 4, 1, 0.0, 2, 4, 4), (2, 4, 1, 0.2, 2, 4, 3), (2, 3, 2, 0.2, 2, 4, 3), (3, 2, 1, 0.15, 2, 4, 2)])
+def test_box_algorithm1_equals_uniform_outer_refinement(oracle_lib, dim, n, order, frac, kd, q, lmax):
+    """Quadrilaterals / hexahedra, eta = 1: Algorithm 1 equals uniform outer
+    refinement to L_max (pieces settled early have constant or zero gamma, and
+    the integrand times |det F'| is of degree <= 5 per variable, which the 3-point
+    rule integrates exactly), on affine and on jittered (non-affine) meshes.
+    numpy: sub-boxes of the reference element, the multilinear map and its
+    Jacobian, the Vandermonde-built basis."""
+    O = oracle_lib
+    mesh = W.box_mesh(dim, n, 0, order, frac=frac, seed=3)
+    delta = kd / n + 0.37 / n
+    eps = delta / q
+    C = O.kernel_constant(dim, 0, delta, eps)
+    g, wg = O.box_rule(dim)
+    exps, Cf = _box_reference(dim, order)
+    depth = lmax - 1
+    hs = 0.5 ** depth
+    origins = np.array(list(itertools.product(range(2 ** depth), repeat=dim)), dtype=float) * hs
+    xi_x = (origins[:, None, :] + hs * g[None, :, :]).reshape(-1, dim)
+    w_x = np.tile(wg, len(origins)) * hs ** dim
+    px, py = _box_phi(exps, Cf, xi_x), _box_phi(exps, Cf, g)
+    P = mesh.coords[mesh.conn[:, :1 << dim]]
+    XJ = [_box_map_np(P[e], xi_x) for e in range(mesh.n_elems)]
+    YJ = [_box_map_np(P[e], g) for e in range(mesh.n_elems)]
+    Au = np.zeros((mesh.n_nodes, mesh.n_nodes))
+    for l in range(mesh.n_elems):
+        X, Jx = XJ[l]
+        for mm in range(mesh.n_elems):
+            Y, Jy = YJ[mm]
+            d = np.sqrt(((X[:, None, :] - Y[None, :, :]) ** 2).sum(-1))
+            G = C * _numpy_mu(d, delta, eps) * np.outer(w_x * Jx, wg * Jy)
+            il, im = mesh.conn[l], mesh.conn[mm]
+            Au[np.ix_(il, il)] += px.T @ (G.sum(1)[:, None] * px)
+            Au[np.ix_(im, im)] += py.T @ (G.sum(0)[:, None] * py)
+            B = -px.T @ G @ py
+            Au[np.ix_(il, im)] += B
+            Au[np.ix_(im, il)] += B.T
+    m = O.OracleMesh(mesh.coords, mesh.conn, order=order, shape=1)
+    off, pm = O.pairs(m, delta + eps)
+    rp, col = O.pattern(m, off, pm)
+    val, leaves, evals = O.assemble(m, O.params(delta, eps, lmax), off, pm, rp, col)
+    assert leaves[1:lmax].sum() > 0
+    A = _dense(rp, col, val, mesh.n_nodes)
+    assert np.linalg.norm(A - Au) <= 1e-13 * np.linalg.norm(Au)
+    assert np.abs(A.sum(1)).max() <= 1e-13 * np.abs(A).sum(1).max()
+
+
+def test_box_pairs_bruteforce(oracle_lib):
+    """Pair list of a jittered quadrilateral mesh: every (l, m) whose corner boxes
+    are closer than delta + eps in the L_inf gap of eq. (mindist), by numpy."""
+    O = oracle_lib
+    mesh = W.box_mesh(2, 6, 1, 1, frac=0.2, seed=4)
+    thr = 0.3
+    P = mesh.coords[mesh.conn]
+    lo, hi = P.min(1), P.max(1)
+    gap = np.maximum(np.maximum(lo[:, None, :] - hi[None, :, :], lo[None, :, :] - hi[:, None, :]), 0).max(-1)
+    off, pm = O.pairs(O.OracleMesh(mesh.coords, mesh.conn, shape=1), thr)
+    for l in range(mesh.n_elems):
+        assert list(pm[off[l]:off[l + 1]]) == list(np.nonzero(gap[l] < thr)[0])
+
+
+def _box_solve(O, mesh, order, u, f_const, delta, eps, lmax, form=0):
+    uu = u(mesh.coords)
+    s = O.solve_problem((mesh.coords, mesh.conn, mesh.constrained), O.params(delta, eps, lmax, form=form),
+                        np.full(mesh.n_nodes, f_const), uu, order=order, shape=1, direct=True)
+    free = mesh.constrained == 0
+    return float(np.max(np.abs(s.u - uu)[free]) / np.max(np.abs(uu)[free]))
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_box_linear_u_reproduced(oracle_lib, order):
+    """Q1 and serendipity quadrilaterals, u = 1 + x + y (f = 0): reproduced to
+    round-off at L_max 1 and 3 in both forms once the constrained layer covers
+    delta + eps (Section 6, consistency paragraph; reading R14)."""
+    O = oracle_lib
+    mesh = W.box_mesh(2, 8, 3, order)
+    delta = 2 / 8
+    for form in (0, 1):
+        for lmax in (1, 3):
+            err = _box_solve(O, mesh, order, lambda x: 1 + x[:, 0] + x[:, 1], 0.0, delta, delta / 16, lmax, form)
+            assert err < 1e-12, (form, lmax, err)
+
+
+def test_box_consistency_quadratic(oracle_lib):
+    """Section 6.1 "Consistency" (Table tab_consistency1, QUAD column):
+    serendipity quadrilaterals reproduce u = x^2 + y^2 (f = -4) up to the
+    integration and mollifier errors, which vanish as L_max grows with
+    eps = eps0 (3/4)^{L_max - 3}, eps0 = delta/16; 8^2 mesh, delta = 2h.  The
+    paper's two-term form falls from 3.8e-5 (L_max 3) to ~1e-8 (L_max 6) -- the
+    paper's column: 8.1e-5 ... 1.8e-9 on its own mesh; the four-term form stops
+    near 8.5e-5 (the inner Gauss rule on the outer element's rows, as for P2)."""
+    O = oracle_lib
+    mesh = W.box_mesh(2, 8, 3, 2)
+    delta = 2 / 8
+    u = lambda x: x[:, 0] ** 2 + x[:, 1] ** 2
+    errs = {0: [], 1: []}
+    for lmax in (3, 4, 5, 6):
+        eps = delta / 16 * 0.75 ** (lmax - 3)
+        for form in (0, 1):
+            errs[form].append(_box_solve(O, mesh, 2, u, -4.0, delta, eps, lmax, form))
+    print("serendipity consistency, four-term:", errs[0], "two-term:", errs[1])
+    two = errs[1]
+    assert all(b < a for a, b in zip(two, two[1:]))
+    assert two[-1] < 1e-7 and two[0] / two[-1] > 1e3
+    assert min(errs[0]) > 5e-5
