@@ -172,6 +172,26 @@ nlq_status nlq_mesh_create(nlq_ctx *ctx, int32_t dim, int64_t n_nodes, const dou
  * deterministic mode. */
 nlq_status nlq_mesh_create_order(nlq_ctx *ctx, int32_t dim, int32_t order, int64_t n_nodes, const double *coords,
                                  int64_t n_elems, const int32_t *conn, const uint8_t *constrained, nlq_mesh **out);
+/* Element shapes (Section 4: the triangulation may consist of triangles or
+ * quadrilaterals in 2D, tetrahedra or hexahedra in 3D). */
+#define NLQ_SHAPE_SIMPLEX 0
+#define NLQ_SHAPE_BOX 1
+/* As nlq_mesh_create_order with an element shape.  NLQ_SHAPE_SIMPLEX: as above.
+ * NLQ_SHAPE_BOX: quadrilaterals / hexahedra on the reference box [0,1]^dim with
+ * the multilinear map of their 2^dim corners; the corners come first in tensor
+ * order (corner c = c0 + 2 c1 + 4 c2 at the reference point (c0, c1, c2), i.e.
+ * (0,0), (1,0), (0,1), (1,1) in 2D), then, for order 2 (serendipity: 8 nodes in
+ * 2D, 20 in 3D, the quadratic elements of Section 6's quadrilateral and
+ * hexahedral meshes), the edge midpoints in increasing t0 + 3 t1 + 9 t2 of
+ * their position t in half units (exactly one t_k = 1).  Both sides of every
+ * pair are integrated with the 3 x 3 (x 3) Gauss-Legendre product rule
+ * (Section 6); Algorithm 1 splits a box into its 2^dim half boxes.  Box
+ * systems are assembled in FP64 (NLQ_FP64_PLAIN), without deterministic mode.
+ * Errors: EINVAL for an unknown shape or order, ids out of range, degenerate
+ * elements (zero edge determinant at corner 0). */
+nlq_status nlq_mesh_create_shape(nlq_ctx *ctx, int32_t dim, int32_t shape, int32_t order, int64_t n_nodes,
+                                 const double *coords, int64_t n_elems, const int32_t *conn,
+                                 const uint8_t *constrained, nlq_mesh **out);
 /* Kuhn mesh of [0,1]^dim with n cells per direction built on the device:
  * x = i/n, node id = i0 + (n+1)(i1 + (n+1) i2), element id = dim!*cell + p with
  * p the lexicographic index of the permutation of the Kuhn path; Gamma = nodes
@@ -235,7 +255,7 @@ nlq_status nlq_assemble_info_get(const nlq_system *sys, nlq_assemble_info *info)
  * sub-elements of Algorithm 1 one pass may pop and refine) and of its leaf
  * buffer (64..256: how many leaves are integrated per flush).  The fastest is
  * kept in the context for every later assembly with the same (dim, element
- * order, precision, kernel, L_max, size class of max |J_l|), including the
+ * type, precision, kernel, L_max, size class of max |J_l|), including the
  * serving loop's.  An assembled
  * system's values are recomputed with it (nlq_set_data must be called again); a
  * prepared one's (nlq_prepare) are set back to zero. */
@@ -252,9 +272,10 @@ typedef struct {
 nlq_status nlq_autotune(nlq_system *sys, double budget_s, nlq_tune_info *info);
 /* The context's tuned configurations as a text file, so that a later process
  * can start tuned: a comment line, then one line per class key
- * "arch dim order precision kernel lmax size_class occ wg_per_cu pairs_per_item
- * stack_cap leaf_cap" (arch of the device, e.g. gfx950; lines of the earlier
- * format without order and capacities load as P1 with the untuned capacities).  nlq_tune_save writes (overwrites) path;
+ * "arch dim element precision kernel lmax size_class occ wg_per_cu
+ * pairs_per_item stack_cap leaf_cap" (arch of the device, e.g. gfx950; element
+ * 1 = P1, 2 = P2, 3 = Q1, 4 = serendipity; lines of the earlier format without
+ * element and capacities load as P1 with the untuned capacities).  nlq_tune_save writes (overwrites) path;
  * nlq_tune_load reads such a file and keeps the lines of this context's
  * architecture (others are skipped), setting *n_loaded (may be NULL) to their
  * number.  A file that cannot be opened, or a line that does not parse, gives

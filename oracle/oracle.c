@@ -242,11 +242,13 @@ void or_children(int32_t dim, const double *v, double *child)
  * increasing t_0 + 3 t_1 + 9 t_2. */
 
 /* 3^N Gauss-Legendre product rule on [0,1]^N: point q = i_0 + 3 i_1 + 9 i_2 at
- * ((1 + z_{i_0})/2, ...), weight prod_k w_{i_k}/2 (the weights sum to 1) */
+ * ((1 + z_{i_0})/2, ...), weight prod_k w_{i_k}/2 (the weights sum to 1), with
+ * the closed-form 3-point nodes z = -sqrt(3/5), 0, sqrt(3/5) and weights 5/9,
+ * 8/9, 5/9 */
 static int box_rule(int dim, double *xi, double *w)
 {
-    double z[3], wz[3];
-    gauss_legendre(3, z, wz);
+    const double r = sqrt(3.0 / 5.0);
+    const double z[3] = {-r, 0.0, r}, wz[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
     int nq = dim == 2 ? 9 : 27;
     for (int q = 0; q < nq; ++q) {
         int i[3] = {q % 3, (q / 3) % 3, q / 9};

@@ -168,9 +168,10 @@ void check_params(const Mesh &m, const nlq_params &p)
         fail(NLQ_EINVAL, "unknown form");
     if (p.form == NLQ_FORM_PAPER2_INNER && p.deterministic)
         fail(NLQ_EINVAL, "the adaptive-inner two-term form has no deterministic mode");
-    if (m.order == 2 && p.deterministic) fail(NLQ_EINVAL, "P2 elements have no deterministic mode");
-    if (m.order == 2 && p.precision != NLQ_FP64_PLAIN)
-        fail(NLQ_EINVAL, "P2 elements are integrated in FP64 (precision NLQ_FP64_PLAIN)");
+    if ((m.order == 2 || m.shape == 1) && p.deterministic)
+        fail(NLQ_EINVAL, "P2, quadrilateral and hexahedral elements have no deterministic mode");
+    if ((m.order == 2 || m.shape == 1) && p.precision != NLQ_FP64_PLAIN)
+        fail(NLQ_EINVAL, "P2, quadrilateral and hexahedral elements are integrated in FP64 (NLQ_FP64_PLAIN)");
     if (p.precision != NLQ_FP64_PLAIN && p.precision != NLQ_FP32_MIXED)
         fail(NLQ_EINVAL, "unknown precision");
     if (p.deterministic != 0 && p.deterministic != 1) fail(NLQ_EINVAL, "deterministic must be 0 or 1");
@@ -180,7 +181,7 @@ void check_params(const Mesh &m, const nlq_params &p)
 
 void mesh_stats(Mesh &m)
 {
-    const int dim = m.dim, nv = dim + 1, nb = m.nb;
+    const int dim = m.dim, nv = m.ngeo, nb = m.nb;
     for (int k = 0; k < 3; ++k) {
         m.gmin[k] = 0.0;
         m.gmax[k] = 0.0;
@@ -198,7 +199,7 @@ void mesh_stats(Mesh &m)
             m.gmax[k] = std::max(m.gmax[k], x);
         }
     for (int64_t e = 0; e < m.n_elems; ++e) {
-        double V[4][3];
+        double V[8][3];
         for (int v = 0; v < nv; ++v) {
             const int32_t id = m.h_conn[e * nb + v];
             if (id < 0 || id >= m.n_nodes) fail(NLQ_EINVAL, "node id out of range in element " + std::to_string(e));
@@ -212,15 +213,18 @@ void mesh_stats(Mesh &m)
             }
             m.ext_max[k] = std::max(m.ext_max[k], b - a);
         }
+        // the simplex's edges from vertex 0; a box's edges from corner 0 (corners
+        // 1, 2 and 4 in tensor order)
+        const int i1 = 1, i2 = 2, i3 = m.shape ? 4 : 3;
         double det;
         if (dim == 2) {
-            det = (V[1][0] - V[0][0]) * (V[2][1] - V[0][1]) - (V[1][1] - V[0][1]) * (V[2][0] - V[0][0]);
+            det = (V[i1][0] - V[0][0]) * (V[i2][1] - V[0][1]) - (V[i1][1] - V[0][1]) * (V[i2][0] - V[0][0]);
         } else {
             double a[3], b[3], c[3];
             for (int k = 0; k < 3; ++k) {
-                a[k] = V[1][k] - V[0][k];
-                b[k] = V[2][k] - V[0][k];
-                c[k] = V[3][k] - V[0][k];
+                a[k] = V[i1][k] - V[0][k];
+                b[k] = V[i2][k] - V[0][k];
+                c[k] = V[i3][k] - V[0][k];
             }
             det = a[0] * (b[1] * c[2] - b[2] * c[1]) - a[1] * (b[0] * c[2] - b[2] * c[0]) +
                   a[2] * (b[0] * c[1] - b[1] * c[0]);
@@ -350,6 +354,7 @@ std::unique_ptr<nlq_mesh> make_box_mesh(Ctx &ctx, int dim, int n, int k_gamma, h
     M.dim = dim;
     M.order = 1;
     M.nb = dim + 1;
+    M.ngeo = dim + 1;
     M.n_nodes = nn;
     M.n_elems = ne;
     M.coords.alloc(M.ctx, sizeof(double) * nn * dim);
@@ -486,22 +491,28 @@ nlq_status nlq_ctx_destroy(nlq_ctx *ctx)
     });
 }
 
-nlq_status nlq_mesh_create_order(nlq_ctx *ctx, int32_t dim, int32_t order, int64_t n_nodes, const double *coords,
-                                 int64_t n_elems, const int32_t *conn, const uint8_t *constrained, nlq_mesh **out)
+nlq_status nlq_mesh_create_shape(nlq_ctx *ctx, int32_t dim, int32_t shape, int32_t order, int64_t n_nodes,
+                                 const double *coords, int64_t n_elems, const int32_t *conn,
+                                 const uint8_t *constrained, nlq_mesh **out)
 {
     return guard([&] {
         if (!ctx || !out || !coords || !conn || !constrained) fail(NLQ_EINVAL, "NULL argument");
         if (dim != 2 && dim != 3) fail(NLQ_EINVAL, "dim must be 2 or 3");
+        if (shape != NLQ_SHAPE_SIMPLEX && shape != NLQ_SHAPE_BOX) fail(NLQ_EINVAL, "unknown element shape");
         if (order != 1 && order != 2) fail(NLQ_EINVAL, "order must be 1 or 2");
-        if (n_nodes < dim + 1 || n_elems < 1) fail(NLQ_EINVAL, "empty mesh");
+        const int ngeo = shape == NLQ_SHAPE_BOX ? 1 << dim : dim + 1;
+        if (n_nodes < ngeo || n_elems < 1) fail(NLQ_EINVAL, "empty mesh");
         if (n_nodes > INT32_MAX || n_elems > INT32_MAX) fail(NLQ_EINVAL, "mesh too large for int32 ids");
         NLQ_HIP(hipSetDevice(ctx->impl.device));
         auto m = std::make_unique<nlq_mesh>();
         Mesh &M = m->impl;
         M.ctx = &ctx->impl;
         M.dim = dim;
+        M.shape = shape;
         M.order = order;
-        M.nb = order == 2 ? (dim + 1) * (dim + 2) / 2 : dim + 1;
+        M.ngeo = ngeo;
+        M.nb = shape == NLQ_SHAPE_BOX ? (order == 2 ? (dim == 2 ? 8 : 20) : 1 << dim)
+                                      : (order == 2 ? (dim + 1) * (dim + 2) / 2 : dim + 1);
         M.n_nodes = n_nodes;
         M.n_elems = n_elems;
         M.h_coords.assign(coords, coords + n_nodes * dim);
@@ -512,6 +523,13 @@ nlq_status nlq_mesh_create_order(nlq_ctx *ctx, int32_t dim, int32_t order, int64
         upload_mesh(M, ctx->impl.stream);
         *out = m.release();
     });
+}
+
+nlq_status nlq_mesh_create_order(nlq_ctx *ctx, int32_t dim, int32_t order, int64_t n_nodes, const double *coords,
+                                 int64_t n_elems, const int32_t *conn, const uint8_t *constrained, nlq_mesh **out)
+{
+    return nlq_mesh_create_shape(ctx, dim, NLQ_SHAPE_SIMPLEX, order, n_nodes, coords, n_elems, conn, constrained,
+                                 out);
 }
 
 nlq_status nlq_mesh_create(nlq_ctx *ctx, int32_t dim, int64_t n_nodes, const double *coords,
@@ -727,7 +745,7 @@ nlq_status nlq_tune_save(const nlq_ctx *ctx, const char *path)
         if (!ctx || !path) fail(NLQ_EINVAL, "NULL argument");
         const Ctx &c = ctx->impl;
         std::string text =
-            "# nlq tuning cache v2: arch dim order precision kernel lmax size_class occ wg_per_cu pairs_per_item "
+            "# nlq tuning cache v2: arch dim element precision kernel lmax size_class occ wg_per_cu pairs_per_item "
             "stack_cap leaf_cap\n";
         {
             std::lock_guard<std::mutex> g(const_cast<Ctx &>(c).tune_mu);
@@ -780,7 +798,7 @@ nlq_status nlq_tune_load(nlq_ctx *ctx, const char *path, int32_t *n_loaded)
                 bad = true;
                 break;
             }
-            if ((dim != 2 && dim != 3) || (order != 1 && order != 2) || (prec != 0 && prec != 1) ||
+            if ((dim != 2 && dim != 3) || order < 1 || order > 4 || (prec != 0 && prec != 1) ||
                 (t.occ != 0 && t.occ != 1) || t.wg_per_cu < 0 || t.pairs_per_item < 1 || lmax < 1 || lg < 0 ||
                 t.stack_cap < 64 || t.stack_cap > 1024 || t.leaf_cap < 64 || t.leaf_cap > 512) {
                 bad = true;

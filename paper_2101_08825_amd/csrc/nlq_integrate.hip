@@ -43,6 +43,7 @@
 #include <cmath>
 #include <type_traits>
 
+#include "nlq_box.hpp"
 #include "nlq_device.hpp"
 #include "nlq_internal.hpp"
 #include "nlq_p2.hpp"
@@ -108,8 +109,13 @@ struct AsmArgs {
     const int32_t *tmap;
     const int32_t *elpos;
     double *val;
-    int nb;               // nodes per element (conn stride): dim + 1 (P1) or (dim+1)(dim+2)/2 (P2)
+    int nb;               // nodes per element (conn stride): dim + 1 (P1), (dim+1)(dim+2)/2 (P2),
+                          // 2^dim (Q1), 8 / 20 (serendipity)
     const double *p2map;  // P2: [NRX][NR] map from the monomial rows to the epilogue rows
+    const double *boxrule;   // boxes: the 3^dim rule, [nq][dim] points then [nq] weights
+    const double *boxpsi;    // boxes: [nb][qs] basis at the rule points
+    const double *boxphi;    // boxes: [nb][nr] basis functions over the product monomials
+    const double *boxprod;   // boxes: [nu][nr] products of two basis functions
     const double *lam64;  // [sub][nq][nv]
     const float *pt32;    // rows of the FP32 contraction per point (see the tables)
     int pt32_zero;        // its zero row
@@ -358,6 +364,52 @@ template <int DIM> __device__ __forceinline__ int level_offset(int lev)
     return ((1 << (DIM * (lev - 1))) - 1) / (NCH - 1);
 }
 
+// The geometry of an element by shape: a simplex (DIM + 1 vertices, midpoint
+// children of child_of) or a box (2^DIM corners in tensor order, children of
+// box_child_of).
+template <int DIM, int SHP> struct Geo {
+    using type = Simplex<DIM>;
+    static constexpr int NV = DIM + 1;
+};
+template <int DIM> struct Geo<DIM, 1> {
+    using type = BoxVerts<DIM>;
+    static constexpr int NV = 1 << DIM;
+};
+template <int DIM, int SHP>
+__device__ __forceinline__ typename Geo<DIM, SHP>::type geo_child_of(const typename Geo<DIM, SHP>::type &S, int c)
+{
+    if constexpr (SHP == 1) return box_child_of<DIM>(S, c);
+    else return child_of<DIM>(S, c);
+}
+
+// Children of a box whose contributions are all exact zeros (as zero_children
+// below): each child formed by box_child_of, its box against the quadrature
+// points' box.
+template <int DIM>
+__device__ __forceinline__ uint32_t zero_children_box(CArgs &A, const BoxVerts<DIM> &S, const double *qlo,
+                                                      const double *qhi)
+{
+    uint32_t z = 0;
+#pragma unroll 1
+    for (int c = 0; c < (1 << DIM); ++c) {
+        const BoxVerts<DIM> B = box_child_of<DIM>(S, c);
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            double lo = B.v[0][k], hi = B.v[0][k];
+#pragma unroll
+            for (int v = 1; v < (1 << DIM); ++v) {
+                lo = fmin(lo, B.v[v][k]);
+                hi = fmax(hi, B.v[v][k]);
+            }
+            const double g = fmax(0.0, fmax(__dsub_rn(lo, qhi[k]), __dsub_rn(qlo[k], hi)));
+            acc = __dadd_rn(acc, __dmul_rn(g, g));
+        }
+        z |= acc >= A.dpe_sq ? (1u << c) : 0u;
+    }
+    return z;
+}
+
 // Children of a sub-element whose contributions are all exact zeros: bit c of
 // the result is set when child c's box lies at Euclidean distance >= delta + eps
 // from the box of the inner element's quadrature points (every point pair of
@@ -408,14 +460,14 @@ __device__ __forceinline__ uint32_t zero_children(CArgs &A, const Simplex<DIM> &
 // memo holds (formed by the same recursion; memo_lev < 2: no memo).  For a
 // refined sub-element one level above L_max, *zero receives the children whose
 // integrals are all zeros (zero_children); otherwise it is left alone.
-template <int DIM>
-__device__ __forceinline__ int classify(CArgs &A, const Simplex<DIM> root, const double *memo, int memo_lev,
-                                        int lev, uint32_t local, const double *mlo, const double *mhi,
-                                        const double *dlo, const double *dhi, const double *qlo,
-                                        const double *qhi, uint32_t *zero)
+template <int DIM, int SHP = 0>
+__device__ __forceinline__ int classify(CArgs &A, const typename Geo<DIM, SHP>::type root, const double *memo,
+                                        int memo_lev, int lev, uint32_t local, const double *mlo,
+                                        const double *mhi, const double *dlo, const double *dhi,
+                                        const double *qlo, const double *qhi, uint32_t *zero)
 {
-    constexpr int NCH = 1 << DIM, NV = DIM + 1;
-    Simplex<DIM> S = root;
+    constexpr int NCH = 1 << DIM, NV = Geo<DIM, SHP>::NV;
+    typename Geo<DIM, SHP>::type S = root;
     int d = lev - 2;   // digits of `local` below the start node
     if (lev >= 2 && memo_lev >= 2) {
         const int la = lev < memo_lev ? lev : memo_lev;
@@ -429,14 +481,14 @@ __device__ __forceinline__ int classify(CArgs &A, const Simplex<DIM> root, const
     }
     for (; d >= 0; --d) {
         const int c = (local >> (DIM * d)) & (NCH - 1);
-        S = child_of(S, c);
+        S = geo_child_of<DIM, SHP>(S, c);
     }
     double slo[DIM], shi[DIM];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
         double a = S.v[0][k], b = S.v[0][k];
 #pragma unroll
-        for (int v = 1; v <= DIM; ++v) {
+        for (int v = 1; v < NV; ++v) {
             a = fmin(a, S.v[v][k]);
             b = fmax(b, S.v[v][k]);
         }
@@ -445,7 +497,10 @@ __device__ __forceinline__ int classify(CArgs &A, const Simplex<DIM> root, const
     }
     if (aprx_max_sq<DIM>(slo, shi, mlo, mhi) < A.dme_sq) return 1;
     if (A.min_l2 ? box_gap_sq<DIM>(slo, shi, dlo, dhi) < A.dpe_sq : aprx_min_dist<DIM>(slo, shi, mlo, mhi) < A.dpe) {
-        if (lev + 1 == A.lmax) *zero = zero_children<DIM>(A, S, qlo, qhi);
+        if (lev + 1 == A.lmax) {
+            if constexpr (SHP == 1) *zero = zero_children_box<DIM>(A, S, qlo, qhi);
+            else *zero = zero_children<DIM>(A, S, qlo, qhi);
+        }
         return 2;
     }
     return 0;
@@ -572,6 +627,197 @@ template <int DIM, int ETA, int ORD = 1> struct PlainAcc {
         if (lane_id() < NYP && b < S::NQ) {
 #pragma unroll
             for (int r = 0; r < S::NR; ++r) out[r * 16 + b] = acc[r];
+        }
+    }
+};
+
+// Sizes of a box element of order ORD: NB nodes, NU upper-triangle slots, NOUT
+// per-pair outputs, NR product-monomial rows, NQ rule points, QS the stride of
+// the per-inner-point rows (a power of two >= NQ).
+template <int DIM, int ORD> struct BoxShape {
+    static constexpr int NB = box_node_count(DIM, ORD);
+    static constexpr int NU = NB * (NB + 1) / 2;
+    static constexpr int NOUT = NB * NB + 2 * NU;
+    static constexpr int NR = BoxMono<DIM, ORD>::N;
+    static constexpr int NQ = box_nq(DIM);
+    static constexpr int QS = DIM == 2 ? 16 : 32;
+};
+
+// The frame of the outer box l for its points: the corner differences
+// D_c = P_c - P_0 (c >= 1), so that x(xi) - P_0 = sum_{c >= 1} N_c(xi) D_c and
+// dx/dxi_i = sum_{c >= 1} dN_c/dxi_i D_c, and 1/|E_l|.
+template <int DIM> struct BoxFrame {
+    double d[(1 << DIM) - 1][DIM];
+    double inv_meas;
+};
+
+// FP64 accumulator of box elements.  Lane = (b, k): b = inner point (lane %
+// QS), k = group.  A leaf point a of sub-box `sub` at level lev is the root
+// reference point xi = (X + g_a) 2^{1-lev}, X the sub-box's integer origin
+// (the base-2^DIM digits of its local index, one bit per axis and level), g_a
+// the rule point; staging maps it through the root's multilinear map and
+// weighs it with w_a 2^{-DIM(lev-1)} |det F_l'(xi)| / |E_l|, then forms the
+// NR product monomials xi^e.  The groups split the points (K slices), or, for
+// the 90 rows of the 20-node hexahedron, the rows (each group all points, half
+// of the rows, so that the accumulators fit the registers; its batches hold 32
+// points to fit the staging in LDS).
+template <int DIM, int ETA, int ORD> struct BoxAcc {
+    using BS = BoxShape<DIM, ORD>;
+    static constexpr int NR = BS::NR, NQ = BS::NQ, NYP = BS::QS;
+    static constexpr int K = kWave / NYP;
+    static constexpr bool ROWS = NR > 48;
+    static constexpr int NRL = ROWS ? (NR + K - 1) / K : NR;
+    static constexpr int kPoints = ROWS ? 32 : 64;
+    static constexpr int kStageBytes = kPoints * (DIM + NR) * 8;
+    static constexpr int NCH = 1 << DIM;
+    struct In {
+        double xi[DIM];
+        double w;
+    };
+    double acc[NRL];
+    double yh[DIM];
+    bool active;
+    int grp;
+    const double *g;   // rule points [NQ][DIM] (LDS)
+    __device__ void init(const double *y, int lane, char *)
+    {
+#pragma unroll
+        for (int r = 0; r < NRL; ++r) acc[r] = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) yh[k] = y[k];
+        active = (lane % NYP) < NQ;
+        grp = lane / NYP;
+    }
+    __device__ In fetch(CArgs &A, bool valid, int sub, int a, int lev, float, double wa) const
+    {
+        In in;
+        if (valid) {
+            const int local = sub - level_offset<DIM>(lev);
+            int X[DIM];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) X[k] = 0;
+            for (int d = 0; d < lev - 1; ++d) {
+                const int c = (local >> (DIM * d)) & (NCH - 1);
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) X[k] |= ((c >> k) & 1) << d;
+            }
+#pragma unroll
+            for (int k = 0; k < DIM; ++k)
+                in.xi[k] = ldexp(__dadd_rn(static_cast<double>(X[k]), g[a * DIM + k]), 1 - lev);
+            in.w = ldexp(wa, -DIM * (lev - 1));
+        } else {
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) in.xi[k] = 0.0;
+            in.w = 0.0;
+        }
+        return in;
+    }
+    __device__ static void stage(char *work, int t, const In &in, const BoxFrame<DIM> &F)
+    {
+        double *sx = reinterpret_cast<double *>(work);
+        double *sp = sx + kPoints * DIM;
+        double x[DIM], J[DIM][DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            x[k] = 0.0;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) J[k][i] = 0.0;
+        }
+#pragma unroll
+        for (int c = 1; c < NCH; ++c) {
+            double N = 1.0, dN[DIM];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) dN[i] = 1.0;
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) {
+                const bool cj = ((c >> j) & 1) != 0;
+                const double f = cj ? in.xi[j] : 1.0 - in.xi[j];
+                N *= f;
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) dN[i] *= i == j ? (cj ? 1.0 : -1.0) : f;
+            }
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                x[k] = fma(N, F.d[c - 1][k], x[k]);
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) J[k][i] = fma(dN[i], F.d[c - 1][k], J[k][i]);
+            }
+        }
+        double det;
+        if constexpr (DIM == 2) {
+            det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        } else {
+            det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                  J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        }
+        const double w = in.w * fabs(det) * F.inv_meas;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) sx[t * DIM + k] = x[k];
+        double pw[DIM][5];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            pw[k][0] = 1.0;
+#pragma unroll
+            for (int q = 1; q <= 4; ++q) pw[k][q] = pw[k][q - 1] * in.xi[k];
+        }
+        constexpr BoxMono<DIM, ORD> mono{};
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            double v = w;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) v *= pw[k][mono.e[r][k]];
+            sp[t * NR + r] = v;
+        }
+    }
+    __device__ void run(CArgs &A, const char *work, int npts)
+    {
+        const double *sx = reinterpret_cast<const double *>(work);
+        const double *sp = sx + kPoints * DIM;
+        if (!active) return;
+        const int p0 = ROWS ? 0 : grp, dp = ROWS ? 1 : K;
+        for (int p = p0; p < npts; p += dp) {
+            double d2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                const double dx = sx[p * DIM + k] - yh[k];
+                d2 = fma(dx, dx, d2);
+            }
+            const double gv = kernel64<ETA>(A, d2);
+            if constexpr (ROWS) {
+#pragma unroll
+                for (int r = 0; r < NRL; ++r) {
+                    const int rr = grp * NRL + r;
+                    if (rr < NR) acc[r] = fma(sp[p * NR + rr], gv, acc[r]);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < NR; ++r) acc[r] = fma(sp[p * NR + r], gv, acc[r]);
+            }
+        }
+    }
+    // totals for inner point b, times jm = |det F_m'(g_b)| / |E_m| -> out[r*QS + b]
+    __device__ void finish(double *out, double jm)
+    {
+        const int b = lane_id() % NYP;
+        if constexpr (ROWS) {
+            if (b < NQ) {
+#pragma unroll
+                for (int r = 0; r < NRL; ++r) {
+                    const int rr = grp * NRL + r;
+                    if (rr < NR) out[rr * NYP + b] = acc[r] * jm;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                double v = acc[r];
+                for (int o = NYP; o < kWave; o <<= 1) v += __shfl_xor(v, o, kWave);
+                acc[r] = v;
+            }
+            if (lane_id() < NYP && b < NQ) {
+#pragma unroll
+                for (int r = 0; r < NR; ++r) out[r * NYP + b] = acc[r] * jm;
+            }
         }
     }
 };
@@ -831,16 +1077,20 @@ template <int DIM, int ETA>
 using MixedAcc = typename std::conditional<DIM == 2, MixedAccDirect<DIM, ETA>, MixedAccMfma<DIM, ETA>>::type;
 
 // per-wave LDS: staging, then the epilogue's H/Q rows and MFMA tile | leaves | stack
-template <int DIM, int PREC, int ORD = 1> struct WaveMem {
+template <int DIM, int PREC, int ORD = 1, int SHP = 0> struct WaveMem {
     using S = Shape<DIM>;
     using O = OShape<DIM, ORD>;
+    using BS = BoxShape<DIM, ORD>;
     static constexpr int kStageBytes =
-        PREC == 0 ? PlainAcc<DIM, 0, ORD>::kStageBytes : MixedAcc<DIM, 0>::kStageBytes;
+        SHP == 1 ? BoxAcc<DIM, 0, ORD>::kStageBytes
+                 : (PREC == 0 ? PlainAcc<DIM, 0, ORD>::kStageBytes : MixedAcc<DIM, 0>::kStageBytes);
     // P1: H/Q rows + column sums + diagonal rows; P2: the monomial rows, then the
-    // rows mapped from them
+    // rows mapped from them; boxes: the monomial rows, the basis-function rows and
+    // the weighted row sums
     static constexpr int kEpiRows = ORD == 1 ? S::NR + 1 + S::NV : O::NR + O::NRX;
+    static constexpr int kBoxEpiBytes = (BS::NR + BS::NB + (BS::NR + BS::QS - 1) / BS::QS) * BS::QS * 8;
     // the mixed path's 16 x 16 MFMA tile is written in place of the H/Q rows
-    static constexpr int kEpiBytes = (PREC == 1 && kEpiRows < 16 ? 16 : kEpiRows) * 16 * 8;
+    static constexpr int kEpiBytes = SHP == 1 ? kBoxEpiBytes : (PREC == 1 && kEpiRows < 16 ? 16 : kEpiRows) * 16 * 8;
     // the epilogue runs after the pair's last batch: it shares the staging area
     static constexpr int kWorkBytes = kStageBytes > kEpiBytes ? kStageBytes : kEpiBytes;
     // vertices of the sub-elements of levels 2..kMemoLevel (FP64), formed once per
@@ -848,7 +1098,7 @@ template <int DIM, int PREC, int ORD = 1> struct WaveMem {
     // L_max 3, where it is not even used)
     static constexpr int kMemoLevel = DIM == 2 ? 3 : 1;
     static constexpr int kMemoCount = DIM == 2 ? 4 + 16 : 0;
-    static constexpr int kMemoBytes = kMemoCount * S::NV * DIM * 8;
+    static constexpr int kMemoBytes = kMemoCount * Geo<DIM, SHP>::NV * DIM * 8;
     __host__ __device__ static int bytes(int capl, int leafcap)
     {
         return (kWorkBytes + leafcap * 4 + kMemoBytes + capl * 4 + 15) & ~15;
@@ -872,11 +1122,11 @@ __device__ __forceinline__ int64_t search(const int32_t *cols, int64_t n, int32_
 // offsets from the row's first column when the row fits (length <= rowcap and
 // column span < 65536); otherwise searched in the global row
 struct RowCache {
-    const uint16_t *c16[10];   // LDS copy, or nullptr (one row per node of l: up to 10 for P2 in 3D)
-    const int32_t *cols[10];   // the global row
-    int32_t first[10];
-    int64_t base[10];
-    int64_t len[10];
+    const uint16_t *c16[20];   // LDS copy, or nullptr (one row per node of l: up to 20, the serendipity hexahedron)
+    const int32_t *cols[20];   // the global row
+    int32_t first[20];
+    int64_t base[20];
+    int64_t len[20];
 };
 
 // position of column c in cached row r, or -1 (a cached row holds at most
@@ -1039,9 +1289,85 @@ template <int DIM> __device__ __forceinline__ void map_rows(double *HQ, const do
     }
 }
 
+// Boxes: the rows after the contraction.  HQ rows r < NR hold, per inner point
+// b, sum_a w_a xi_a^{e_r} g_ab (times |det F_m'(g_b)| / |E_m|).  Then
+//   PHI[I][b] = sum_r phi_I[r] HQ[r][b]   (the outer basis function phi_I),
+//   R1[r]     = sum_b w_b HQ[r][b]        (the rows summed against the inner weights).
+template <int DIM, int ORD> __device__ __forceinline__ void box_rows(CArgs &A, double *HQ, const double *wq)
+{
+    using BS = BoxShape<DIM, ORD>;
+    constexpr int NR = BS::NR, NB = BS::NB, NQ = BS::NQ, QS = BS::QS;
+    double *PHI = HQ + NR * QS, *R1 = PHI + NB * QS;
+    for (int t = lane_id(); t < NB * NQ; t += kWave) {
+        const int I = t / NQ, b = t - I * NQ;
+        const double *ph = A.boxphi + I * NR;
+        double v = 0.0;
+        for (int r = 0; r < NR; ++r) v = fma(ph[r], HQ[r * QS + b], v);
+        PHI[I * QS + b] = v;
+    }
+    for (int r = lane_id(); r < NR; r += kWave) {
+        double v = 0.0;
+#pragma unroll
+        for (int b = 0; b < NQ; ++b) v = fma(wq[b], HQ[r * QS + b], v);
+        R1[r] = v;
+    }
+}
+
+// Boxes: one per-pair output before the factor +-C |E_l| |E_m| (psi = the inner
+// basis at the rule points, [NB][QS]):
+//   B_lm[i][j] = sum_b w_b psi_j(b) PHI[i][b]
+//   B_mm[u]    = sum_b w_b psi_i(b) psi_j(b) HQ[0][b]   (row 0: the monomial 1)
+//   B_ll[u]    = sum_r prod_u[r] R1[r]
+template <int DIM, int ORD>
+__device__ __forceinline__ double box_output(CArgs &A, const double *HQ, const double *psi, const double *wq,
+                                             int kind, int i, int j, int u)
+{
+    using BS = BoxShape<DIM, ORD>;
+    constexpr int NR = BS::NR, NB = BS::NB, NQ = BS::NQ, QS = BS::QS;
+    const double *PHI = HQ + NR * QS, *R1 = PHI + NB * QS;
+    double v = 0.0;
+    if (kind == kOutLM) {
+#pragma unroll
+        for (int b = 0; b < NQ; ++b) v = fma(wq[b] * psi[j * QS + b], PHI[i * QS + b], v);
+    } else if (kind == kOutMM) {
+#pragma unroll
+        for (int b = 0; b < NQ; ++b) v = fma(wq[b] * psi[i * QS + b] * psi[j * QS + b], HQ[b], v);
+    } else if (kind == kOutLL) {
+        const double *pr = A.boxprod + u * NR;
+        for (int r = 0; r < NR; ++r) v = fma(pr[r], R1[r], v);
+    }
+    return v;
+}
+
+// Boxes: the basis at the rule points into LDS and one descriptor per output
+// (B_lm, then the B_mm and B_ll slots): kind | i << 2 | j << 7 | u << 12
+template <int DIM, int ORD> __device__ void box_epilogue_tables(CArgs &A0, double *s_psi, int *s_desc)
+{
+    using BS = BoxShape<DIM, ORD>;
+    constexpr int NB = BS::NB, NU = BS::NU, NPASS = (BS::NOUT + kWave - 1) / kWave;
+    for (int t = threadIdx.x; t < NB * BS::QS; t += kThreads) s_psi[t] = A0.boxpsi[t];
+    for (int o = threadIdx.x; o < NPASS * kWave; o += kThreads) {
+        int kind = kOutNone, i = 0, j = 0, u = 0;
+        if (o < NB * NB) {
+            kind = kOutLM;
+            i = o / NB;
+            j = o % NB;
+        } else if (o < NB * NB + NU) {
+            kind = kOutMM;
+            u = o - NB * NB;
+            pair_of<NB>(u, i, j);
+        } else if (o < NB * NB + 2 * NU) {
+            kind = kOutLL;
+            u = o - NB * NB - NU;
+            pair_of<NB>(u, i, j);
+        }
+        s_desc[o] = kind | (i << 2) | (j << 7) | (u << 12);   // i, j < 32, u < 2^19
+    }
+}
+
 // -------------------------------------------------------------- one pair
 
-template <int DIM, int PREC, int ETA, int ORD>
+template <int DIM, int PREC, int ETA, int ORD, int SHP = 0>
 __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pidx, char *wmem,
                              const double *s_rule, const float *s_w32, const double *s_T, const int *s_desc,
                              const double *s_map, double *s_bll, const RowCache *rc, double *ex_block,
@@ -1049,11 +1375,19 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
 {
     using S = Shape<DIM>;
     using O = OShape<DIM, ORD>;
-    constexpr int NV = S::NV, NQ = S::NQ, NCH = S::NCH;
-    constexpr int NB = O::NB, NU = O::NU;
-    using Acc = typename std::conditional<PREC == 0, PlainAcc<DIM, ETA, ORD>, MixedAcc<DIM, ETA>>::type;
+    using BS = BoxShape<DIM, ORD>;
+    using GV = typename Geo<DIM, SHP>::type;
+    constexpr int NV = S::NV, NCH = S::NCH, NVG = Geo<DIM, SHP>::NV;
+    // rule points (stride RS: barycentric for simplices, reference coordinates for boxes)
+    constexpr int NQ = SHP == 1 ? BS::NQ : S::NQ, RS = SHP == 1 ? DIM : NV;
+    constexpr int NB = SHP == 1 ? BS::NB : O::NB, NU = SHP == 1 ? BS::NU : O::NU;
+    constexpr int NOUT = SHP == 1 ? BS::NOUT : O::NOUT;
+    using Acc = typename std::conditional<
+        SHP == 1, BoxAcc<DIM, ETA, ORD>,
+        typename std::conditional<PREC == 0, PlainAcc<DIM, ETA, ORD>, MixedAcc<DIM, ETA>>::type>::type;
+    constexpr int BATCH = SHP == 1 ? BoxAcc<DIM, ETA, ORD>::kPoints : kBatch;
     using Real = typename std::conditional<PREC == 0, double, float>::type;
-    using WM = WaveMem<DIM, PREC, ORD>;
+    using WM = WaveMem<DIM, PREC, ORD, SHP>;
     const int lane = lane_id();
     const int64_t ne = A.ne;
     l = uniform(l);
@@ -1072,9 +1406,9 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     const cdouble *cvert = (const cdouble *)(A.vert);
     const cdouble *clo = (const cdouble *)(A.lo);
     const cdouble *chi = (const cdouble *)(A.hi);
-    Simplex<DIM> root;
+    GV root;
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
+    for (int v = 0; v < NVG; ++v)
 #pragma unroll
         for (int k = 0; k < DIM; ++k) root.v[v][k] = cvert[(v * DIM + k) * ne + l];
     const cdouble *cdlo = (const cdouble *)(A.dlo);
@@ -1092,31 +1426,63 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
         qhi[k] = cqhi[k * ne + m];
     }
     const double *bary = s_rule;
-    const double *wq = s_rule + NQ * NV;
-    // P1: node m_j of the epilogue's B_lm lane (lane = i * NV + j), read early
-    const int32_t mj1 = ORD == 1 ? A.conn[static_cast<int64_t>(m) * NV + lane % NV] : 0;
+    const double *wq = s_rule + NQ * RS;
+    // P1 simplices: node m_j of the epilogue's B_lm lane (lane = i * NV + j), read early
+    constexpr bool kP1 = ORD == 1 && SHP == 0;
+    const int32_t mj1 = kP1 ? A.conn[static_cast<int64_t>(m) * NV + lane % NV] : 0;
 
     // inner point of this lane, relative to the anchor v0(l)
     int bsel;
-    if (PREC == 0) bsel = lane % PlainAcc<DIM, ETA>::NYP;
+    if (SHP == 1) bsel = lane % BS::QS;
+    else if (PREC == 0) bsel = lane % PlainAcc<DIM, ETA>::NYP;
     else bsel = DIM == 2 ? (lane & 7) : (lane & 15);
     const int bq = bsel < NQ ? bsel : 0;
     double y[DIM];
+    double jm = 1.0;   // boxes: |det F_m'(g_b)| / |E_m|
+    if constexpr (SHP == 1) {
+        BoxVerts<DIM> Pm;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        double s = 0.0;
+        for (int c = 0; c < NVG; ++c)
 #pragma unroll
-        for (int v = 0; v < NV; ++v) s = fma(bary[bq * NV + v], cvert[(v * DIM + k) * ne + m], s);
-        y[k] = s - root.v[0][k];
+            for (int k = 0; k < DIM; ++k) Pm.v[c][k] = cvert[(c * DIM + k) * ne + m];
+        double N[1 << DIM];
+        box_corner_weights<DIM>(bary + bq * DIM, N);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < NVG; ++c) s = fma(N[c], Pm.v[c][k], s);
+            y[k] = s - root.v[0][k];
+        }
+        jm = box_jacdet<DIM>(Pm, bary + bq * DIM) / A.meas[m];
+    } else {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) s = fma(bary[bq * NV + v], cvert[(v * DIM + k) * ne + m], s);
+            y[k] = s - root.v[0][k];
+        }
     }
-    Edges<DIM, Real> E;   // edges v_i - v_0 of l
+    // the outer element's frame: the edges v_i - v_0 of a simplex, or a box's
+    // corner differences and 1/|E_l|
+    typename std::conditional<SHP == 1, BoxFrame<DIM>, Edges<DIM, Real>>::type E;
+    if constexpr (SHP == 1) {
 #pragma unroll
-    for (int i = 1; i <= DIM; ++i)
+        for (int c = 1; c < NVG; ++c)
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) E.e[i - 1][k] = static_cast<Real>(root.v[i][k] - root.v[0][k]);
+            for (int k = 0; k < DIM; ++k) E.d[c - 1][k] = root.v[c][k] - root.v[0][k];
+        E.inv_meas = 1.0 / A.meas[l];
+    } else {
+#pragma unroll
+        for (int i = 1; i <= DIM; ++i)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) E.e[i - 1][k] = static_cast<Real>(root.v[i][k] - root.v[0][k]);
+    }
 
     Acc acc;
     acc.init(y, lane, work);
+    if constexpr (SHP == 1) acc.g = bary;
     if constexpr (PREC == 1) acc.set_column(A, y, bsel < NQ);
 
     // integrate the leaves in leafbuf[0..nleaf)
@@ -1124,7 +1490,7 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
         const int total = nleaf * NQ;
         auto fetch = [&](int p0) {
             const int p = p0 + lane;
-            const bool valid = p < total;
+            const bool valid = p < total && lane < BATCH;
             int a = 0, lev = 1, sub = 0;
             if (valid) {
                 const int q = p / NQ;
@@ -1133,15 +1499,15 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
                 lev = static_cast<int>(ent >> 24);
                 sub = static_cast<int>(ent & 0xFFFFFFu);
             }
-            return Acc::fetch(A, valid, sub, a, lev, s_w32[a], wq[a]);
+            return acc.fetch(A, valid, sub, a, lev, SHP == 1 ? 0.0f : s_w32[a], wq[a]);
         };
         auto in = fetch(0);
-        for (int p0 = 0; p0 < total; p0 += kBatch) {
+        for (int p0 = 0; p0 < total; p0 += BATCH) {
             wave_sync();
-            Acc::stage(work, lane, in, E);
+            if (lane < BATCH) Acc::stage(work, lane, in, E);
             wave_sync();
-            if (p0 + kBatch < total) in = fetch(p0 + kBatch);
-            acc.run(A, work, total - p0 < kBatch ? total - p0 : kBatch);
+            if (p0 + BATCH < total) in = fetch(p0 + BATCH);
+            acc.run(A, work, total - p0 < BATCH ? total - p0 : BATCH);
         }
     };
 
@@ -1185,11 +1551,11 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
         if (lane < count) {
             const int tlev = lane < NCH ? 2 : 3;
             const int tloc = lane < NCH ? lane : lane - NCH;
-            Simplex<DIM> T = root;
-            for (int d = tlev - 2; d >= 0; --d) T = child_of(T, (tloc >> (DIM * d)) & (NCH - 1));
-            double *dst = memo + lane * NV * DIM;
+            GV T = root;
+            for (int d = tlev - 2; d >= 0; --d) T = geo_child_of<DIM, SHP>(T, (tloc >> (DIM * d)) & (NCH - 1));
+            double *dst = memo + lane * NVG * DIM;
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
+            for (int v = 0; v < NVG; ++v)
 #pragma unroll
                 for (int k = 0; k < DIM; ++k) dst[v * DIM + k] = T.v[v][k];
         }
@@ -1258,7 +1624,7 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     bool ok = true;
     if (sl >= 2) {
         uint32_t z0 = 0u;
-        const int rc = 1 < lmin ? 2 : classify<DIM>(A, root, memo, memo_lev, 1, 0u, mlo, mhi, dlo, dhi, qlo, qhi, &z0);
+        const int rc = 1 < lmin ? 2 : classify<DIM, SHP>(A, root, memo, memo_lev, 1, 0u, mlo, mhi, dlo, dhi, qlo, qhi, &z0);
         if (rc == 2) {
             const int ntop = sl == 2 ? NCH : NCH + NCH * NCH;
             const bool valid = lane < ntop;
@@ -1268,7 +1634,7 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
             int cls = 0;
             uint32_t zm = 0u;
             if (valid)
-                cls = lev < lmin ? 2 : classify<DIM>(A, root, memo, memo_lev, lev, local, mlo, mhi, dlo, dhi, qlo, qhi, &zm);
+                cls = lev < lmin ? 2 : classify<DIM, SHP>(A, root, memo, memo_lev, lev, local, mlo, mhi, dlo, dhi, qlo, qhi, &zm);
             // the parent of level-3 node `local` is level-2 node local / NCH, in that lane
             const unsigned long long ref = wave_ballot(valid && cls == 2);
             const bool reach = lev == 2 || ((ref >> (local >> DIM)) & 1ull) != 0;
@@ -1310,7 +1676,7 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
         if (valid) {
             if (lev == lmax) cls = 1;                 // the root when L_max = 1
             else if (lev < lmin) cls = 2;
-            else cls = classify<DIM>(A, root, memo, memo_lev, lev, local, mlo, mhi, dlo, dhi, qlo, qhi, &zm);
+            else cls = classify<DIM, SHP>(A, root, memo, memo_lev, lev, local, mlo, mhi, dlo, dhi, qlo, qhi, &zm);
         }
         ok = act(lev, local, cls, zm, true);
     }
@@ -1321,27 +1687,42 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
 
     // ---- epilogue (FP64) ----------------------------------------------------
     wave_sync();
-    acc.finish(HQ, tile);
-    wave_sync();
-    if constexpr (ORD == 1) extend_rows<DIM>(HQ);
-    else map_rows<DIM>(HQ, s_map);
+    if constexpr (SHP == 1) {
+        acc.finish(HQ, jm);
+        wave_sync();
+        box_rows<DIM, ORD>(A, HQ, wq);
+    } else {
+        acc.finish(HQ, tile);
+        wave_sync();
+        if constexpr (ORD == 1) extend_rows<DIM>(HQ);
+        else map_rows<DIM>(HQ, s_map);
+    }
     wave_sync();
     const double Sc = A.C * A.meas[l] * A.meas[m];
     const bool four = A.form == NLQ_FORM_SYM4;
     // the two-term form with the adaptive rule on the inner integral: rows of the
     // refined (outer) element, 2 B_ll and 2 B_lm (see the oracle's form 2)
     const bool inner = A.form == NLQ_FORM_PAPER2_INNER;
-    constexpr int NPASS = (O::NOUT + kWave - 1) / kWave;
+    constexpr int NPASS = (NOUT + kWave - 1) / kWave;
     for (int pass = 0; pass < NPASS; ++pass) {
-        // every output is a dot product over the inner points b of one row after
-        // the contraction with one constant row of s_T; the descriptor names both
         const int o = pass * kWave + lane;
         const int desc = s_desc[o];
         const int kind = desc & 3;
-        const int xr = (desc >> 2) & 127, tr = (desc >> 9) & 127;
-        const int i = (desc >> 16) & 15, j = (desc >> 20) & 15, u = (desc >> 24) & 63;
+        int i, j, u;
         double v = 0.0;
-        {
+        if constexpr (SHP == 1) {
+            i = (desc >> 2) & 31;
+            j = (desc >> 7) & 31;
+            u = desc >> 12;
+            v = box_output<DIM, ORD>(A, HQ, s_T, wq, kind, i, j, u);
+        } else {
+            // every output is a dot product over the inner points b of one row
+            // after the contraction with one constant row of s_T; the descriptor
+            // names both
+            const int xr = (desc >> 2) & 127, tr = (desc >> 9) & 127;
+            i = (desc >> 16) & 15;
+            j = (desc >> 20) & 15;
+            u = (desc >> 24) & 63;
             const double *x = HQ + xr * 16;
             const double *tt = s_T + tr * 16;
 #pragma unroll
@@ -1365,14 +1746,14 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
         if (A.pb) {
             // deterministic mode: the outputs of pair pidx, in descriptor order, are
             // summed later in a fixed order
-            if (kind != kOutNone) A.pb[(pidx - A.pb_base) * O::NOUT + o] = v;
+            if (kind != kOutNone) A.pb[(pidx - A.pb_base) * NOUT + o] = v;
             continue;
         }
         if (kind == kOutLM) {
             // B_lm at (l_i, m_j) through the cached row of l_i.  SYM4 adds it to the
             // half matrix R (A = R + R^T afterwards); the two-term form puts 2 B_lm^T
             // at (m_j, l_i) directly, its adaptive-inner variant 2 B_lm at (l_i, m_j).
-            const int32_t mj = ORD == 1 ? mj1 : A.conn[static_cast<int64_t>(m) * NB + j];
+            const int32_t mj = kP1 ? mj1 : A.conn[static_cast<int64_t>(m) * NB + j];
             const int64_t at = row_find(rc, i, mj);
             if (at >= 0) {
                 const int64_t pos = rc->base[i] + at;
@@ -1396,20 +1777,27 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
 
 // Occupancy hint: more waves per SIMD cover LDS and table latency at the cost of
 // registers (5 waves in 2D, 3 in 3D were fastest on the 2D 128^2 and 3D 8^3 cases).
-template <int DIM, int PREC, int ETA, int OCC, int ORD>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu<DIM, PREC, OCC>())))
+// (box elements: 2 waves per SIMD in 2D, 1 in 3D, so that their wider
+// accumulators and frames stay in registers instead of spilling)
+template <int DIM, int PREC, int ETA, int OCC, int ORD, int SHP = 0>
+__global__ void __launch_bounds__(kThreads)
+    __attribute__((amdgpu_waves_per_eu(SHP == 1 ? (DIM == 2 ? 2 : 1) : waves_per_eu<DIM, PREC, OCC>())))
 k_integrate(LaunchArgs L)
 {
     using S = Shape<DIM>;
     using O = OShape<DIM, ORD>;
-    using WM = WaveMem<DIM, PREC, ORD>;
-    constexpr int NV = S::NV, NQ = S::NQ, NB = O::NB, NU = O::NU;
+    using BS = BoxShape<DIM, ORD>;
+    using WM = WaveMem<DIM, PREC, ORD, SHP>;
+    constexpr int NV = S::NV, RS = SHP == 1 ? DIM : NV, NQ = SHP == 1 ? BS::NQ : S::NQ;
+    constexpr int NB = SHP == 1 ? BS::NB : O::NB, NU = SHP == 1 ? BS::NU : O::NU;
+    constexpr int NOUT = SHP == 1 ? BS::NOUT : O::NOUT;
     extern __shared__ __align__(16) char smem[];
-    __shared__ double s_rule[NQ * NV + NQ];
+    __shared__ double s_rule[NQ * RS + NQ];
     __shared__ float s_w32[16];
-    __shared__ __align__(16) double s_T[(NB + NU + 1) * 16];
-    __shared__ int s_desc[(O::NOUT + kWave - 1) / kWave * kWave];
-    __shared__ double s_map[ORD == 1 ? 1 : O::NRX * O::NR];
+    // simplices: the constant rows of epilogue_tables; boxes: the inner basis [NB][QS]
+    __shared__ __align__(16) double s_T[SHP == 1 ? NB * BS::QS : (NB + NU + 1) * 16];
+    __shared__ int s_desc[(NOUT + kWave - 1) / kWave * kWave];
+    __shared__ double s_map[ORD == 1 || SHP == 1 ? 1 : O::NRX * O::NR];
     __shared__ double s_bll[NU];
     __shared__ int64_t s_seg[kMaxSeg + 1];
     __shared__ int64_t s_item;
@@ -1424,13 +1812,15 @@ k_integrate(LaunchArgs L)
     // the quadrature rule (and the P2 map) depends on the dimension only: every
     // system of the launch shares it
     CArgs &A0 = *(CArgs *)(L.sys);
-    for (int t = threadIdx.x; t < NQ * NV + NQ; t += kThreads) s_rule[t] = A0.rule[t];
-    if constexpr (ORD == 2)
+    const double *rule0 = SHP == 1 ? A0.boxrule : A0.rule;
+    for (int t = threadIdx.x; t < NQ * RS + NQ; t += kThreads) s_rule[t] = rule0[t];
+    if constexpr (ORD == 2 && SHP == 0)
         for (int t = threadIdx.x; t < O::NRX * O::NR; t += kThreads) s_map[t] = A0.p2map[t];
-    if (threadIdx.x < NQ) s_w32[threadIdx.x] = static_cast<float>(A0.rule[NQ * NV + threadIdx.x]);
+    if (SHP == 0 && threadIdx.x < NQ) s_w32[threadIdx.x] = static_cast<float>(A0.rule[NQ * NV + threadIdx.x]);
     for (int t = threadIdx.x; t <= L.nseg; t += kThreads) s_seg[t] = L.seg_start[t];
     __syncthreads();
-    epilogue_tables<DIM, ORD>(s_rule, s_T, s_desc);
+    if constexpr (SHP == 1) box_epilogue_tables<DIM, ORD>(A0, s_T, s_desc);
+    else epilogue_tables<DIM, ORD>(s_rule, s_T, s_desc);
     const int64_t total = s_seg[L.nseg];
     for (;;) {
         if (threadIdx.x == 0) {
@@ -1492,8 +1882,8 @@ k_integrate(LaunchArgs L)
             p = bcast0(p);
             if (p >= p_hi) break;
             const int32_t m = A.pair_m[b0 + p];
-            process_pair<DIM, PREC, ETA, ORD>(A, static_cast<int>(l), m, b0 + p, wmem, s_rule, s_w32, s_T,
-                                              s_desc, s_map, s_bll, &s_rc, nullptr, s_leaf, L.leafcap);
+            process_pair<DIM, PREC, ETA, ORD, SHP>(A, static_cast<int>(l), m, b0 + p, wmem, s_rule, s_w32, s_T,
+                                                   s_desc, s_map, s_bll, &s_rc, nullptr, s_leaf, L.leafcap);
         }
         __syncthreads();
         // B_ll of l (upper triangle; doubled for the adaptive-inner two-term form)
@@ -1511,28 +1901,33 @@ k_integrate(LaunchArgs L)
 
 // explicit pairs of system 0: every wave takes pairs from the counter and
 // writes the extended block [2N+2][2N+2] of each
-template <int DIM, int PREC, int ETA, int ORD>
+template <int DIM, int PREC, int ETA, int ORD, int SHP = 0>
 __global__ void __launch_bounds__(kThreads)
 k_pair_blocks(LaunchArgs L)
 {
     using S = Shape<DIM>;
     using O = OShape<DIM, ORD>;
-    constexpr int NV = S::NV, NQ = S::NQ, NB = O::NB;
+    using BS = BoxShape<DIM, ORD>;
+    constexpr int NV = S::NV, RS = SHP == 1 ? DIM : NV, NQ = SHP == 1 ? BS::NQ : S::NQ;
+    constexpr int NB = SHP == 1 ? BS::NB : O::NB, NU = SHP == 1 ? BS::NU : O::NU;
+    constexpr int NOUT = SHP == 1 ? BS::NOUT : O::NOUT;
     extern __shared__ __align__(16) char smem[];
-    __shared__ double s_rule[NQ * NV + NQ];
+    __shared__ double s_rule[NQ * RS + NQ];
     __shared__ float s_w32[16];
-    __shared__ __align__(16) double s_T[(NB + O::NU + 1) * 16];
-    __shared__ int s_desc[(O::NOUT + kWave - 1) / kWave * kWave];
-    __shared__ double s_map[ORD == 1 ? 1 : O::NRX * O::NR];
+    __shared__ __align__(16) double s_T[SHP == 1 ? NB * BS::QS : (NB + NU + 1) * 16];
+    __shared__ int s_desc[(NOUT + kWave - 1) / kWave * kWave];
+    __shared__ double s_map[ORD == 1 || SHP == 1 ? 1 : O::NRX * O::NR];
     CArgs &A = *(CArgs *)(L.sys);
     const int wid = threadIdx.x / kWave;
-    char *wmem = smem + wid * WaveMem<DIM, PREC, ORD>::bytes(L.capl, L.leafcap);
-    for (int t = threadIdx.x; t < NQ * NV + NQ; t += kThreads) s_rule[t] = A.rule[t];
-    if (threadIdx.x < NQ) s_w32[threadIdx.x] = static_cast<float>(A.rule[NQ * NV + threadIdx.x]);
-    if constexpr (ORD == 2)
+    char *wmem = smem + wid * WaveMem<DIM, PREC, ORD, SHP>::bytes(L.capl, L.leafcap);
+    const double *rule0 = SHP == 1 ? A.boxrule : A.rule;
+    for (int t = threadIdx.x; t < NQ * RS + NQ; t += kThreads) s_rule[t] = rule0[t];
+    if (SHP == 0 && threadIdx.x < NQ) s_w32[threadIdx.x] = static_cast<float>(A.rule[NQ * NV + threadIdx.x]);
+    if constexpr (ORD == 2 && SHP == 0)
         for (int t = threadIdx.x; t < O::NRX * O::NR; t += kThreads) s_map[t] = A.p2map[t];
     __syncthreads();
-    epilogue_tables<DIM, ORD>(s_rule, s_T, s_desc);
+    if constexpr (SHP == 1) box_epilogue_tables<DIM, ORD>(A, s_T, s_desc);
+    else epilogue_tables<DIM, ORD>(s_rule, s_T, s_desc);
     __syncthreads();
     for (;;) {
         unsigned int it = 0;
@@ -1542,8 +1937,8 @@ k_pair_blocks(LaunchArgs L)
         double *blk = A.ex_out + static_cast<int64_t>(it) * (2 * NB) * (2 * NB);
         for (int t = lane_id(); t < 4 * NB * NB; t += kWave) blk[t] = 0.0;
         wave_sync();
-        process_pair<DIM, PREC, ETA, ORD>(A, A.ex_l[it], A.ex_m[it], -1, wmem, s_rule, s_w32, s_T, s_desc, s_map,
-                                          nullptr, nullptr, blk, nullptr, L.leafcap);
+        process_pair<DIM, PREC, ETA, ORD, SHP>(A, A.ex_l[it], A.ex_m[it], -1, wmem, s_rule, s_w32, s_T, s_desc,
+                                               s_map, nullptr, nullptr, blk, nullptr, L.leafcap);
     }
 }
 
@@ -1588,14 +1983,38 @@ __global__ void __launch_bounds__(256) k_symmetrize(int64_t nnz, const int32_t *
 }
 
 // workgroups per CU of one launch and its dynamic LDS bytes
-template <int DIM, int PREC, int ETA, int OCC, int ORD>
+// LDS of a workgroup: static tables plus the dynamic per-wave areas and cached
+// CSR rows within 160 KiB
+constexpr int kLdsBytes = 160 * 1024;
+
+// the cached CSR row capacity that fits the LDS next to the per-wave areas
+// (rows longer than that are searched in global memory)
+template <int DIM, int PREC, int ETA, int OCC, int ORD, int SHP>
+int fit_rowcap(int capl, int rowcap, int leafcap)
+{
+    auto kern = k_integrate<DIM, PREC, ETA, OCC, ORD, SHP>;
+    hipFuncAttributes fa{};
+    NLQ_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(kern)));
+    const int nb = SHP == 1 ? BoxShape<DIM, ORD>::NB : OShape<DIM, ORD>::NB;
+    const int room = kLdsBytes - static_cast<int>(fa.sharedSizeBytes) - 16 -
+                     kWaves * WaveMem<DIM, PREC, ORD, SHP>::bytes(capl, leafcap);
+    const int fit = room / (2 * nb) - 8;
+    return std::max(1, std::min(rowcap, fit));
+}
+
+template <int DIM, int PREC, int ETA, int OCC, int ORD, int SHP = 0>
 int occupancy(int capl, int rowcap, int leafcap, bool explicit_mode, int *lds_out)
 {
-    const int per_wave = WaveMem<DIM, PREC, ORD>::bytes(capl, leafcap);
-    const int nb = OShape<DIM, ORD>::NB;
+    const int per_wave = WaveMem<DIM, PREC, ORD, SHP>::bytes(capl, leafcap);
+    const int nb = SHP == 1 ? BoxShape<DIM, ORD>::NB : OShape<DIM, ORD>::NB;
     const int lds = kWaves * per_wave + (explicit_mode ? 0 : ((nb * rowcap * 2 + 15) & ~15));
-    if (lds > 150 * 1024) fail(NLQ_EINVAL, "lmax too large for the per-wave refinement lists");
-    auto kern = explicit_mode ? k_pair_blocks<DIM, PREC, ETA, ORD> : k_integrate<DIM, PREC, ETA, OCC, ORD>;
+    auto kern = explicit_mode ? k_pair_blocks<DIM, PREC, ETA, ORD, SHP> : k_integrate<DIM, PREC, ETA, OCC, ORD, SHP>;
+    {
+        hipFuncAttributes fa{};
+        NLQ_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(kern)));
+        if (lds + static_cast<int>(fa.sharedSizeBytes) > kLdsBytes)
+            fail(NLQ_EINVAL, "lmax too large for the per-wave refinement lists");
+    }
     NLQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     int per_cu = 0;
@@ -1604,14 +2023,16 @@ int occupancy(int capl, int rowcap, int leafcap, bool explicit_mode, int *lds_ou
     return per_cu < 1 ? 1 : per_cu;
 }
 
-template <int DIM, int PREC, int ETA, int OCC, int ORD = 1>
-void launch_one(Ctx *ctx, const LaunchArgs &L, int64_t items, hipStream_t st, bool explicit_mode,
+template <int DIM, int PREC, int ETA, int OCC, int ORD = 1, int SHP = 0>
+void launch_one(Ctx *ctx, const LaunchArgs &L0, int64_t items, hipStream_t st, bool explicit_mode,
                 int wg_per_cu, hipEvent_t e0, hipEvent_t e1)
 {
+    LaunchArgs L = L0;
+    if (!explicit_mode) L.rowcap = fit_rowcap<DIM, PREC, ETA, OCC, ORD, SHP>(L.capl, L.rowcap, L.leafcap);
     int lds = 0;
-    int per_cu = occupancy<DIM, PREC, ETA, OCC, ORD>(L.capl, L.rowcap, L.leafcap, explicit_mode, &lds);
+    int per_cu = occupancy<DIM, PREC, ETA, OCC, ORD, SHP>(L.capl, L.rowcap, L.leafcap, explicit_mode, &lds);
     if (wg_per_cu > 0 && wg_per_cu < per_cu) per_cu = wg_per_cu;
-    auto kern = explicit_mode ? k_pair_blocks<DIM, PREC, ETA, ORD> : k_integrate<DIM, PREC, ETA, OCC, ORD>;
+    auto kern = explicit_mode ? k_pair_blocks<DIM, PREC, ETA, ORD, SHP> : k_integrate<DIM, PREC, ETA, OCC, ORD, SHP>;
     int64_t grid = static_cast<int64_t>(ctx->n_cu) * per_cu;
     if (grid > items) grid = items;
     if (grid < 1) grid = 1;
@@ -1640,6 +2061,31 @@ void dispatch(Ctx *ctx, const System &s, const TuneConfig &c, const LaunchArgs &
               bool ex, hipEvent_t e0, hipEvent_t e1)
 {
     const int dim = s.mesh->dim;
+    if (s.mesh->shape == 1) {
+        // quadrilaterals / hexahedra: FP64 plain path only, one register variant
+        if (s.p.precision != NLQ_FP64_PLAIN) fail(NLQ_EINVAL, "box elements take the FP64 plain path");
+        const bool g = s.p.kernel == NLQ_ETA_GAUSS;
+        const int wpc = c.wg_per_cu;
+        const bool q2 = s.mesh->order == 2;
+        if (dim == 2) {
+            if (q2) {
+                if (g) launch_one<2, 0, NLQ_ETA_GAUSS, 0, 2, 1>(ctx, L, items, st, ex, wpc, e0, e1);
+                else launch_one<2, 0, NLQ_ETA_CONST, 0, 2, 1>(ctx, L, items, st, ex, wpc, e0, e1);
+            } else {
+                if (g) launch_one<2, 0, NLQ_ETA_GAUSS, 0, 1, 1>(ctx, L, items, st, ex, wpc, e0, e1);
+                else launch_one<2, 0, NLQ_ETA_CONST, 0, 1, 1>(ctx, L, items, st, ex, wpc, e0, e1);
+            }
+        } else {
+            if (q2) {
+                if (g) launch_one<3, 0, NLQ_ETA_GAUSS, 0, 2, 1>(ctx, L, items, st, ex, wpc, e0, e1);
+                else launch_one<3, 0, NLQ_ETA_CONST, 0, 2, 1>(ctx, L, items, st, ex, wpc, e0, e1);
+            } else {
+                if (g) launch_one<3, 0, NLQ_ETA_GAUSS, 0, 1, 1>(ctx, L, items, st, ex, wpc, e0, e1);
+                else launch_one<3, 0, NLQ_ETA_CONST, 0, 1, 1>(ctx, L, items, st, ex, wpc, e0, e1);
+            }
+        }
+        return;
+    }
     if (s.mesh->order == 2) {
         // P2 elements: FP64 plain path only, one register variant
         if (s.p.precision != NLQ_FP64_PLAIN) fail(NLQ_EINVAL, "P2 elements take the FP64 plain path");
@@ -1664,9 +2110,22 @@ void dispatch(Ctx *ctx, const System &s, const TuneConfig &c, const LaunchArgs &
 }
 
 template <int DIM, int PREC>
-int occupancy_of(int kernel, int occ, int capl, int rowcap, int leafcap, int order)
+int occupancy_of(int kernel, int occ, int capl, int rowcap, int leafcap, int order, int shape)
 {
     const bool g = kernel == NLQ_ETA_GAUSS;
+    if (shape == 1) {
+        if (PREC != 0) fail(NLQ_EINVAL, "box elements take the FP64 plain path");
+        if (order == 2) {
+            rowcap = g ? fit_rowcap<DIM, 0, 1, 0, 2, 1>(capl, rowcap, leafcap)
+                       : fit_rowcap<DIM, 0, 0, 0, 2, 1>(capl, rowcap, leafcap);
+            return g ? occupancy<DIM, 0, 1, 0, 2, 1>(capl, rowcap, leafcap, false, nullptr)
+                     : occupancy<DIM, 0, 0, 0, 2, 1>(capl, rowcap, leafcap, false, nullptr);
+        }
+        rowcap = g ? fit_rowcap<DIM, 0, 1, 0, 1, 1>(capl, rowcap, leafcap)
+                   : fit_rowcap<DIM, 0, 0, 0, 1, 1>(capl, rowcap, leafcap);
+        return g ? occupancy<DIM, 0, 1, 0, 1, 1>(capl, rowcap, leafcap, false, nullptr)
+                 : occupancy<DIM, 0, 0, 0, 1, 1>(capl, rowcap, leafcap, false, nullptr);
+    }
     if (order == 2) {
         if (PREC != 0) fail(NLQ_EINVAL, "P2 elements take the FP64 plain path");
         return g ? occupancy<DIM, 0, 1, 0, 2>(capl, rowcap, leafcap, false, nullptr)
@@ -1722,6 +2181,10 @@ AsmArgs make_args(const System &s, const Tables &T)
     A.conn = m.conn.as<int32_t>();
     A.nb = m.nb;
     A.p2map = T.p2map.as<double>();
+    A.boxrule = T.boxrule.as<double>();
+    A.boxpsi = T.boxpsi[m.order - 1].as<double>();
+    A.boxphi = T.boxphi[m.order - 1].as<double>();
+    A.boxprod = T.boxprod[m.order - 1].as<double>();
     A.row_ptr = s.row_ptr.as<int64_t>();
     A.col = s.col.as<int32_t>();
     A.tmap = s.tmap.as<int32_t>();
@@ -1816,8 +2279,8 @@ void launch_integrate_jobs(Ctx *ctx, LaunchBlock &lb, const std::vector<Integrat
     for (const auto &j : jobs) {
         const System &s = *j.s;
         if (s.mesh->dim != s0.mesh->dim || s.p.precision != s0.p.precision || s.p.kernel != s0.p.kernel ||
-            s.mesh->order != s0.mesh->order)
-            fail(NLQ_EINVAL, "one launch takes systems of one dimension, element order, precision and kernel");
+            s.mesh->order != s0.mesh->order || s.mesh->shape != s0.mesh->shape)
+            fail(NLQ_EINVAL, "one launch takes systems of one dimension, element type, precision and kernel");
         if (s.p.deterministic && (!s.det_pb || jobs.size() != 1))
             fail(NLQ_EINVAL, "a deterministic system is integrated by itself (nlq_assemble)");
         if (j.lo < 0 || j.hi > s.mesh->n_elems || j.lo > j.hi) fail(NLQ_EINVAL, "bad outer-element range");
@@ -1881,7 +2344,11 @@ void launch_integrate_jobs(Ctx *ctx, LaunchBlock &lb, const std::vector<Integrat
         double *val = s.val.as<double>();
         if (nf > 0) {
             const unsigned gf = static_cast<unsigned>((nf + 255) / 256);
-            auto kern = nb == 3 ? k_fold_diag<3> : nb == 4 ? k_fold_diag<4> : nb == 6 ? k_fold_diag<6> : k_fold_diag<10>;
+            auto kern = nb == 3    ? k_fold_diag<3>
+                        : nb == 4  ? k_fold_diag<4>
+                        : nb == 6  ? k_fold_diag<6>
+                        : nb == 8  ? k_fold_diag<8>
+                        : nb == 10 ? k_fold_diag<10> : k_fold_diag<20>;
             hipLaunchKernelGGL(kern, dim3(gf), dim3(256), 0, st, s.mesh->n_elems, dmm, elpos, val, four);
             NLQ_CHECK_LAUNCH();
         }
@@ -1898,13 +2365,13 @@ int64_t integrate_slots(Ctx *ctx, const System &s)
     const AsmArgs A = make_args(s, ctx->get_tables(s.mesh->dim, s.p.lmax));
     const bool plain = s.p.precision == NLQ_FP64_PLAIN;
     int per_cu;
-    const int ord = s.mesh->order, lc = leaf_cap_of(s);
+    const int ord = s.mesh->order, shp = s.mesh->shape, lc = leaf_cap_of(s);
     if (s.mesh->dim == 2)
-        per_cu = plain ? occupancy_of<2, 0>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, lc, ord)
-                       : occupancy_of<2, 1>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, lc, ord);
+        per_cu = plain ? occupancy_of<2, 0>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, lc, ord, shp)
+                       : occupancy_of<2, 1>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, lc, ord, shp);
     else
-        per_cu = plain ? occupancy_of<3, 0>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, lc, ord)
-                       : occupancy_of<3, 1>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, lc, ord);
+        per_cu = plain ? occupancy_of<3, 0>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, lc, ord, shp)
+                       : occupancy_of<3, 1>(s.p.kernel, s.cfg.occ, A.capl, A.rowcap, lc, ord, shp);
     if (s.cfg.wg_per_cu > 0 && s.cfg.wg_per_cu < per_cu) per_cu = s.cfg.wg_per_cu;
     return static_cast<int64_t>(ctx->n_cu) * per_cu;
 }

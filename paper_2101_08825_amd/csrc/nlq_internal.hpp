@@ -104,6 +104,13 @@ struct Tables {
     DevBuf pt32;
     // P2 elements: the monomial rows -> epilogue rows map of make_p2_map (double)
     DevBuf p2map;
+    // quadrilaterals / hexahedra (make_box_tables), per element order o = 1, 2:
+    // the 3^N rule ([nq][dim] points, then [nq] weights), and per order the basis
+    // at the rule points [nb][qs] (qs = 16 in 2D, 32 in 3D; padding zero), the
+    // basis functions and their products over the product monomials
+    // [nb][nr] and [nu][nr] (double)
+    DevBuf boxrule;
+    DevBuf boxpsi[2], boxphi[2], boxprod[2];
 };
 
 struct Server;
@@ -158,8 +165,11 @@ struct Mesh {
     double gmin[3] = {0, 0, 0}, gmax[3] = {0, 0, 0};
     double ext_max[3] = {0, 0, 0};   // largest element bbox extent per axis
     DevBuf coords;                   // [n_nodes][dim] double
-    int order = 1;                   // 1: P1; 2: P2 (vertices, then edge midpoints)
-    int nb = 0;                      // nodes per element: dim + 1 (P1), (dim+1)(dim+2)/2 (P2)
+    int shape = 0;                   // 0: simplices; 1: quadrilaterals / hexahedra (tensor order)
+    int order = 1;                   // 1: P1 / Q1; 2: P2 / serendipity (then the edge midpoints)
+    int nb = 0;                      // nodes per element: dim + 1 (P1), (dim+1)(dim+2)/2 (P2),
+                                     // 2^dim (Q1), 8 / 20 (serendipity)
+    int ngeo = 0;                    // geometric vertices: dim + 1, or the 2^dim corners
     DevBuf conn;                     // [n_elems][nb] int32
     DevBuf constrained;              // [n_nodes] uint8
     std::vector<double> h_coords;
@@ -294,6 +304,10 @@ void exclusive_scan_i64(Ctx *ctx, const int64_t *in, int64_t *out, int64_t n, hi
 double kernel_constant(int dim, int kernel, double delta, double eps);
 std::unique_ptr<Tables> make_tables(Ctx *ctx, int dim, int lmax);
 std::vector<double> make_p2_map(int dim);
+struct BoxTablesHost {
+    std::vector<double> rule, psi, phi, prod;
+};
+BoxTablesHost make_box_tables(int dim, int order);
 
 }  // namespace nlq
 

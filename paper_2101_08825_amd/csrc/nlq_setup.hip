@@ -5,6 +5,7 @@
 #include <cmath>
 
 #include "nlq_device.hpp"
+#include "nlq_box.hpp"
 #include "nlq_internal.hpp"
 
 namespace nlq {
@@ -157,18 +158,109 @@ __global__ void k_quad_boxes(int64_t ne, int nq, const double *__restrict__ vert
     }
 }
 
+// Quadrilaterals / hexahedra: the 2^DIM corners (SoA), their box (a multilinear
+// map takes its extremes at the corners) and the measure, the integral of
+// |det F'| by the 3^DIM Gauss rule (exact: degree <= DIM - 1 per variable).
+template <int DIM>
+__global__ void k_elem_tables_box(int64_t ne, int nb, const double *__restrict__ coords,
+                                  const int32_t *__restrict__ conn, double *__restrict__ vert,
+                                  double *__restrict__ lo, double *__restrict__ hi, double *__restrict__ meas)
+{
+    constexpr int NC = 1 << DIM;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    BoxVerts<DIM> P;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const int64_t node = conn[e * nb + c];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            P.v[c][k] = coords[node * DIM + k];
+            vert[(c * DIM + k) * ne + e] = P.v[c][k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        double a = P.v[0][k], b = P.v[0][k];
+#pragma unroll
+        for (int c = 1; c < NC; ++c) {
+            a = fmin(a, P.v[c][k]);
+            b = fmax(b, P.v[c][k]);
+        }
+        lo[k * ne + e] = a;
+        hi[k * ne + e] = b;
+    }
+    double m = 0.0;
+    for (int q = 0; q < box_nq(DIM); ++q) {
+        const int i[3] = {q % 3, (q / 3) % 3, q / 9};
+        double xi[DIM], w = 1.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            xi[k] = box_gauss_node(i[k]);
+            w *= box_gauss_weight(i[k]);
+        }
+        m = fma(w, box_jacdet<DIM>(P, xi), m);
+    }
+    meas[e] = m;
+}
+
+// Box of each box element's quadrature points y_b = F(g_b), formed as the
+// oracle forms them: the multilinear weights rounded as written, then the
+// products N_c P_c rounded and added in corner order (no fused multiply-add).
+template <int DIM>
+__global__ void k_quad_boxes_box(int64_t ne, const double *__restrict__ vert, double *__restrict__ qlo,
+                                 double *__restrict__ qhi)
+{
+    constexpr int NC = 1 << DIM;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    double a[DIM], b[DIM];
+    for (int q = 0; q < box_nq(DIM); ++q) {
+        const int i[3] = {q % 3, (q / 3) % 3, q / 9};
+        double xi[DIM], N[NC];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) xi[k] = box_gauss_node(i[k]);
+        box_corner_weights<DIM>(xi, N);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            double y = 0.0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) y = __dadd_rn(y, __dmul_rn(N[c], vert[(c * DIM + k) * ne + e]));
+            a[k] = q == 0 ? y : fmin(a[k], y);
+            b[k] = q == 0 ? y : fmax(b[k], y);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        qlo[k * ne + e] = a[k];
+        qhi[k * ne + e] = b[k];
+    }
+}
+
 }  // namespace
 
 void launch_elem_tables(System &s, hipStream_t st)
 {
     const Mesh &m = *s.mesh;
     const int64_t ne = m.n_elems;
-    const int nv = m.dim + 1;
+    const int nv = m.ngeo;
     s.vert.alloc(s.ctx, sizeof(double) * ne * nv * m.dim);
     s.lo.alloc(s.ctx, sizeof(double) * ne * m.dim);
     s.hi.alloc(s.ctx, sizeof(double) * ne * m.dim);
     s.meas.alloc(s.ctx, sizeof(double) * ne);
+    s.qlo.alloc(s.ctx, sizeof(double) * ne * m.dim);
+    s.qhi.alloc(s.ctx, sizeof(double) * ne * m.dim);
     dim3 grid((ne + 255) / 256), block(256);
+    if (m.shape == 1) {
+        auto kt = m.dim == 2 ? k_elem_tables_box<2> : k_elem_tables_box<3>;
+        hipLaunchKernelGGL(kt, grid, block, 0, st, ne, m.nb, m.coords.as<double>(), m.conn.as<int32_t>(),
+                           s.vert.as<double>(), s.lo.as<double>(), s.hi.as<double>(), s.meas.as<double>());
+        NLQ_CHECK_LAUNCH();
+        auto kq = m.dim == 2 ? k_quad_boxes_box<2> : k_quad_boxes_box<3>;
+        hipLaunchKernelGGL(kq, grid, block, 0, st, ne, s.vert.as<double>(), s.qlo.as<double>(), s.qhi.as<double>());
+        NLQ_CHECK_LAUNCH();
+        return;
+    }
     if (m.dim == 2)
         hipLaunchKernelGGL(k_elem_tables<2>, grid, block, 0, st, ne, m.nb, m.coords.as<double>(),
                            m.conn.as<int32_t>(), s.vert.as<double>(), s.lo.as<double>(),
@@ -180,8 +272,6 @@ void launch_elem_tables(System &s, hipStream_t st)
     NLQ_CHECK_LAUNCH();
     {
         const Tables &T = s.ctx->get_tables(m.dim, s.p.lmax);
-        s.qlo.alloc(s.ctx, sizeof(double) * ne * m.dim);
-        s.qhi.alloc(s.ctx, sizeof(double) * ne * m.dim);
         if (m.dim == 2)
             hipLaunchKernelGGL(k_quad_boxes<2>, grid, block, 0, st, ne, T.nq, s.vert.as<double>(),
                                T.rule.as<double>(), s.qlo.as<double>(), s.qhi.as<double>());
@@ -653,7 +743,11 @@ void build_pattern(System &s, hipStream_t st)
     DevBuf nb_off(s.ctx, sizeof(int64_t) * (ne + 1), st);
     NLQ_HIP(hipMemsetAsync(nb_cnt.as<void>(), 0, sizeof(int64_t) * (ne + 1), st));
     auto nbhd = [&](int32_t *out) {
-        auto kern = nv == 3 ? k_elem_nbhd<3> : nv == 4 ? k_elem_nbhd<4> : nv == 6 ? k_elem_nbhd<6> : k_elem_nbhd<10>;
+        auto kern = nv == 3 ? k_elem_nbhd<3>
+                  : nv == 4 ? k_elem_nbhd<4>
+                  : nv == 6 ? k_elem_nbhd<6>
+                  : nv == 8 ? k_elem_nbhd<8>
+                  : nv == 10 ? k_elem_nbhd<10> : k_elem_nbhd<20>;
         hipLaunchKernelGGL(kern, dim3(ne), dim3(kWave), 0, st, ne, m.conn.as<int32_t>(), s.pair_off.as<int64_t>(),
                            s.pair_m.as<int32_t>(), nb_cnt.as<int64_t>(), nb_off.as<int64_t>(), out, err.as<int>());
         NLQ_CHECK_LAUNCH();
@@ -701,7 +795,10 @@ void build_pattern(System &s, hipStream_t st)
     dim3 g2((ne * nv * nv + 255) / 256);
     {
         auto kern = nv == 3 ? k_elem_block_pos<3>
-                            : nv == 4 ? k_elem_block_pos<4> : nv == 6 ? k_elem_block_pos<6> : k_elem_block_pos<10>;
+                  : nv == 4 ? k_elem_block_pos<4>
+                  : nv == 6 ? k_elem_block_pos<6>
+                  : nv == 8 ? k_elem_block_pos<8>
+                  : nv == 10 ? k_elem_block_pos<10> : k_elem_block_pos<20>;
         hipLaunchKernelGGL(kern, g2, b1, 0, st, ne, m.conn.as<int32_t>(), s.row_ptr.as<int64_t>(),
                            s.col.as<int32_t>(), s.elpos.as<int32_t>(), err.as<int>());
     }

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "nlq_device.hpp"
+#include "nlq_box.hpp"
 #include "nlq_internal.hpp"
 
 namespace nlq {
@@ -73,6 +74,45 @@ __global__ void k_load(int64_t ne, const int32_t *__restrict__ conn, const doubl
 #pragma unroll
     for (int a = 0; a < NB; ++a)
         if (!constrained[id[a]]) unsafeAtomicAdd(&F[id[a]], s[a] * me);
+}
+
+// Quadrilaterals / hexahedra: F_i += sum_q w_q |det F_e'(g_q)| f_h(g_q) phi_i(g_q)
+// with the 3^DIM Gauss rule and the basis values at its points (psi [NB][QS])
+template <int DIM, int NB>
+__global__ void k_load_box(int64_t ne, const int32_t *__restrict__ conn, const double *__restrict__ vert,
+                           const double *__restrict__ rule, const double *__restrict__ psi,
+                           const double *__restrict__ f, const uint8_t *__restrict__ constrained,
+                           double *__restrict__ F)
+{
+    constexpr int NQ = DIM == 2 ? 9 : 27, QS = DIM == 2 ? 16 : 32, NC = 1 << DIM;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    BoxVerts<DIM> P;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) P.v[c][k] = vert[(c * DIM + k) * ne + e];
+    double fv[NB];
+    int32_t id[NB];
+#pragma unroll
+    for (int v = 0; v < NB; ++v) {
+        id[v] = conn[e * NB + v];
+        fv[v] = f[id[v]];
+    }
+    double s[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) s[a] = 0.0;
+    for (int q = 0; q < NQ; ++q) {
+        const double wq = rule[NQ * DIM + q] * box_jacdet<DIM>(P, rule + q * DIM);
+        double fq = 0.0;
+#pragma unroll
+        for (int v = 0; v < NB; ++v) fq += fv[v] * psi[v * QS + q];
+#pragma unroll
+        for (int a = 0; a < NB; ++a) s[a] += wq * fq * psi[a * QS + q];
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+        if (!constrained[id[a]]) unsafeAtomicAdd(&F[id[a]], s[a]);
 }
 
 // The same load vector summed per node over its elements in ascending order
@@ -436,6 +476,12 @@ void launch_load_lift(System &s, hipStream_t st, const double *f_dev, const doub
                                m.conn.as<int32_t>(), s.meas.as<double>(), T.rule.as<double>(), f_dev,
                                m.constrained.as<uint8_t>(), s.F.as<double>());
     } else if (ne == 0) {
+    } else if (m.shape == 1) {
+        auto kern = m.dim == 2 ? (m.order == 2 ? k_load_box<2, 8> : k_load_box<2, 4>)
+                               : (m.order == 2 ? k_load_box<3, 20> : k_load_box<3, 8>);
+        hipLaunchKernelGGL(kern, g1, b1, 0, st, ne, m.conn.as<int32_t>(), s.vert.as<double>(),
+                           T.boxrule.as<double>(), T.boxpsi[m.order - 1].as<double>(), f_dev,
+                           m.constrained.as<uint8_t>(), s.F.as<double>());
     } else {
         auto kern = m.dim == 2 ? (m.order == 2 ? k_load<2, 2> : k_load<2, 1>)
                                : (m.order == 2 ? k_load<3, 2> : k_load<3, 1>);

@@ -6,6 +6,7 @@
 #include <map>
 #include <vector>
 
+#include "nlq_box.hpp"
 #include "nlq_internal.hpp"
 #include "nlq_p2.hpp"
 #include "nlq_refine.hpp"
@@ -198,6 +199,134 @@ std::vector<double> make_p2_map(int dim)
     return map;
 }
 
+// Tables of quadrilateral / hexahedral elements (see nlq_box.hpp).  The nodal
+// basis is built from its definition: phi_I is the function of the element's
+// space (Q1 or serendipity monomials on [0,1]^N) with phi_I(node_J) = delta_IJ,
+// from the inverse of the space's Vandermonde matrix at the nodes.  Returns
+//   rule  [nq][dim] points, then [nq] weights (product order of nlq_box.hpp);
+//   psi   [nb][qs]  phi_J at rule point b (qs = 16 in 2D, 32 in 3D, padding 0);
+//   phi   [nb][nr]  phi_I over the product monomials of BoxMono;
+//   prod  [nu][nr]  phi_I phi_J, slot u: u < nb the diagonal, then I < J in
+//                   lexicographic order.
+BoxTablesHost make_box_tables(int dim, int order)
+{
+    const int nq = box_nq(dim), qs = dim == 2 ? 16 : 32, nb = box_node_count(dim, order);
+    const int nu = nb * (nb + 1) / 2;
+    BoxTablesHost T;
+    T.rule.assign(static_cast<size_t>(nq) * (dim + 1), 0.0);
+    for (int q = 0; q < nq; ++q) {
+        const int i[3] = {q % 3, (q / 3) % 3, q / 9};
+        double w = 1.0;
+        for (int k = 0; k < dim; ++k) {
+            T.rule[q * dim + k] = box_gauss_node(i[k]);
+            w *= box_gauss_weight(i[k]);
+        }
+        T.rule[nq * dim + q] = w;
+    }
+    using E3 = std::vector<int>;
+    std::vector<E3> rows, space;
+    for (int q = 0; q < (dim == 2 ? 25 : 125); ++q) {
+        int e[3] = {q % 5, (q / 5) % 5, q / 25};
+        if (box_is_product(order, dim, e)) rows.push_back(E3(e, e + dim));
+    }
+    for (int q = 0; q < (dim == 2 ? 9 : 27); ++q) {
+        int e[3] = {q % 3, (q / 3) % 3, q / 9};
+        if (box_in_space(order, dim, e)) space.push_back(E3(e, e + dim));
+    }
+    if (static_cast<int>(space.size()) != nb) fail(NLQ_EDEVICE, "box element space size mismatch");
+    std::vector<E3> nodes;
+    for (int c = 0; c < (1 << dim); ++c) {
+        E3 t(dim);
+        for (int k = 0; k < dim; ++k) t[k] = 2 * ((c >> k) & 1);
+        nodes.push_back(t);
+    }
+    if (order == 2)
+        for (int q = 0; q < (dim == 2 ? 9 : 27); ++q) {
+            E3 t(dim);
+            int odd = 0;
+            for (int k = 0; k < dim; ++k) {
+                t[k] = (q / (k == 0 ? 1 : (k == 1 ? 3 : 9))) % 3;
+                odd += t[k] == 1;
+            }
+            if (odd == 1) nodes.push_back(t);
+        }
+    auto mono = [&](const E3 &e, const double *x) {
+        double v = 1.0;
+        for (int k = 0; k < dim; ++k) v *= std::pow(x[k], e[k]);
+        return v;
+    };
+    // Vandermonde V[i][j] = space_j(node_i), inverted by Gauss-Jordan elimination
+    std::vector<double> V(static_cast<size_t>(nb) * nb), Cinv(static_cast<size_t>(nb) * nb, 0.0);
+    for (int i = 0; i < nb; ++i) {
+        double x[3];
+        for (int k = 0; k < dim; ++k) x[k] = 0.5 * nodes[i][k];
+        for (int j = 0; j < nb; ++j) V[i * nb + j] = mono(space[j], x);
+        Cinv[i * nb + i] = 1.0;
+    }
+    for (int col = 0; col < nb; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < nb; ++r)
+            if (std::fabs(V[r * nb + col]) > std::fabs(V[piv * nb + col])) piv = r;
+        if (std::fabs(V[piv * nb + col]) < 1e-12) fail(NLQ_EDEVICE, "box basis: singular Vandermonde matrix");
+        for (int c = 0; c < nb; ++c) {
+            std::swap(V[col * nb + c], V[piv * nb + c]);
+            std::swap(Cinv[col * nb + c], Cinv[piv * nb + c]);
+        }
+        const double d = V[col * nb + col];
+        for (int c = 0; c < nb; ++c) {
+            V[col * nb + c] /= d;
+            Cinv[col * nb + c] /= d;
+        }
+        for (int r = 0; r < nb; ++r) {
+            if (r == col) continue;
+            const double f = V[r * nb + col];
+            if (f == 0.0) continue;
+            for (int c = 0; c < nb; ++c) {
+                V[r * nb + c] -= f * V[col * nb + c];
+                Cinv[r * nb + c] -= f * Cinv[col * nb + c];
+            }
+        }
+    }
+    // phi_I = sum_j Cinv[j][I] space_j
+    const int nr = static_cast<int>(rows.size());
+    auto row_of = [&](const E3 &e) {
+        for (int r = 0; r < nr; ++r)
+            if (rows[r] == e) return r;
+        fail(NLQ_EDEVICE, "box basis: a product is not among the rows");
+        return -1;
+    };
+    T.phi.assign(static_cast<size_t>(nb) * nr, 0.0);
+    for (int I = 0; I < nb; ++I)
+        for (int j = 0; j < nb; ++j) T.phi[I * nr + row_of(space[j])] += Cinv[j * nb + I];
+    T.prod.assign(static_cast<size_t>(nu) * nr, 0.0);
+    for (int u = 0; u < nu; ++u) {
+        int I = u, J = u;
+        if (u >= nb) {
+            int r = nb;
+            for (int a = 0; a < nb; ++a)
+                for (int c = a + 1; c < nb; ++c, ++r)
+                    if (r == u) {
+                        I = a;
+                        J = c;
+                    }
+        }
+        for (int j = 0; j < nb; ++j)
+            for (int jj = 0; jj < nb; ++jj) {
+                E3 e(dim);
+                for (int k = 0; k < dim; ++k) e[k] = space[j][k] + space[jj][k];
+                T.prod[u * nr + row_of(e)] += Cinv[j * nb + I] * Cinv[jj * nb + J];
+            }
+    }
+    T.psi.assign(static_cast<size_t>(nb) * qs, 0.0);
+    for (int J = 0; J < nb; ++J)
+        for (int b = 0; b < nq; ++b) {
+            double v = 0.0;
+            for (int j = 0; j < nb; ++j) v += Cinv[j * nb + J] * mono(space[j], &T.rule[b * dim]);
+            T.psi[J * qs + b] = v;
+        }
+    return T;
+}
+
 // Kernel constant C.  eta = 1: C_{delta,eps} of Section 6 (kappa = 1).  Gaussian
 // eta: c such that c * omega_N * int_0^{delta+eps} rho^{N+1} eta mu drho = N
 // (L_eps u = Laplacian u for quadratic u), 40 Gauss-Legendre points on each
@@ -301,6 +430,17 @@ std::unique_ptr<Tables> make_tables(Ctx *ctx, int dim, int lmax)
     const std::vector<double> p2 = make_p2_map(dim);
     t->p2map.alloc(ctx, p2.size() * sizeof(double));
     NLQ_HIP(hipMemcpy(t->p2map.as<void>(), p2.data(), p2.size() * sizeof(double), hipMemcpyHostToDevice));
+    auto upload = [&](DevBuf &b, const std::vector<double> &v) {
+        b.alloc(ctx, v.size() * sizeof(double));
+        NLQ_HIP(hipMemcpy(b.as<void>(), v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+    };
+    for (int order = 1; order <= 2; ++order) {
+        const BoxTablesHost bt = make_box_tables(dim, order);
+        if (order == 1) upload(t->boxrule, bt.rule);
+        upload(t->boxpsi[order - 1], bt.psi);
+        upload(t->boxphi[order - 1], bt.phi);
+        upload(t->boxprod[order - 1], bt.prod);
+    }
     return t;
 }
 

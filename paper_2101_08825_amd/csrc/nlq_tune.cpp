@@ -14,7 +14,8 @@ TuneKey tune_key(const System &s)
 {
     int lg = 0;
     while ((int64_t(1) << lg) < std::max<int64_t>(s.max_pairs, 1)) ++lg;
-    return TuneKey(s.mesh->dim, s.mesh->order, s.p.precision, s.p.kernel, s.p.lmax, lg);
+    // element type: 1 P1, 2 P2, 3 Q1, 4 serendipity
+    return TuneKey(s.mesh->dim, s.mesh->order + 2 * s.mesh->shape, s.p.precision, s.p.kernel, s.p.lmax, lg);
 }
 
 namespace {
@@ -62,10 +63,10 @@ int autotune(System &s, hipStream_t st, double budget_s, double *best_ms, double
     *best_ms = *default_ms = 0.0;
     if (s.p.deterministic) return 0;   // sample ranges are not integrated on their own in this mode
     // stage 1 candidates: the default first, then the register variant (P1
-    // only: P2 has one), one workgroup less per CU, and other work-item sizes
-    // where the pair lists get cut
+    // simplices only: the other element types have one), one workgroup less per
+    // CU, and other work-item sizes where the pair lists get cut
     std::vector<TuneConfig> cand{base};
-    for (int occ = 0; occ < (s.mesh->order == 1 ? 2 : 1); ++occ)
+    for (int occ = 0; occ < (s.mesh->order == 1 && s.mesh->shape == 0 ? 2 : 1); ++occ)
         for (int less = 0; less < 2; ++less)
             for (int ppi : {512, 256, 1024}) {
                 if (ppi != 512 && s.max_pairs <= 256) continue;

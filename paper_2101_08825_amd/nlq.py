@@ -20,6 +20,7 @@ NLQ_OK, NLQ_EINVAL, NLQ_ENOMEM, NLQ_EDEVICE, NLQ_ENOTREADY, NLQ_ECANCELLED, NLQ_
 NLQ_ETA_CONST, NLQ_ETA_GAUSS = 0, 1
 NLQ_FORM_SYM4, NLQ_FORM_PAPER2, NLQ_FORM_PAPER2_INNER = 0, 1, 2
 NLQ_FP64_PLAIN, NLQ_FP32_MIXED = 0, 1
+NLQ_SHAPE_SIMPLEX, NLQ_SHAPE_BOX = 0, 1
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTREADY",
                 -5: "ECANCELLED", -6: "EBUSY", -7: "ENOCONV"}
@@ -27,7 +28,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOTREA
 # every extern "C" symbol declared in include/nlq.h
 EXPORTS = [
     "nlq_ctx_create", "nlq_ctx_set_stream", "nlq_ctx_memory", "nlq_ctx_destroy",
-    "nlq_mesh_create", "nlq_mesh_create_order", "nlq_mesh_box", "nlq_mesh_info", "nlq_mesh_copy", "nlq_mesh_destroy",
+    "nlq_mesh_create", "nlq_mesh_create_order", "nlq_mesh_create_shape", "nlq_mesh_box", "nlq_mesh_info", "nlq_mesh_copy", "nlq_mesh_destroy",
     "nlq_assemble", "nlq_prepare", "nlq_integrate_range", "nlq_integrate_ranges", "nlq_assemble_batch", "nlq_assemble_info_get",
     "nlq_autotune", "nlq_tune_save", "nlq_tune_load", "nlq_reassemble", "nlq_set_data",
     "nlq_set_data_device", "nlq_solve", "nlq_solve_noalloc", "nlq_solution_device",
@@ -114,6 +115,7 @@ def lib():
             "nlq_ctx_destroy": [vp],
             "nlq_mesh_create": [vp, i32, i64, vp, i64, vp, vp, P(vp)],
             "nlq_mesh_create_order": [vp, i32, i32, i64, vp, i64, vp, vp, P(vp)],
+            "nlq_mesh_create_shape": [vp, i32, i32, i32, i64, vp, i64, vp, vp, P(vp)],
             "nlq_mesh_box": [vp, i32, i32, i32, P(vp)],
             "nlq_mesh_info": [vp, P(i32), P(i64), P(i64), P(i64)],
             "nlq_mesh_copy": [vp, vp, vp, vp],
@@ -221,29 +223,36 @@ class Context:
 
 
 class Mesh:
-    def __init__(self, ctx: Context, h, order: int = 1):
+    def __init__(self, ctx: Context, h, order: int = 1, shape: int = 0):
         self.ctx = ctx
         self.h = h
         self.order = order
+        self.shape = shape
         self._systems = weakref.WeakSet()
         ctx._meshes.add(self)
         d, nn, ne, nf = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64()
         _check(lib().nlq_mesh_info(h, C.byref(d), C.byref(nn), C.byref(ne), C.byref(nf)))
         self.dim, self.n_nodes, self.n_elems, self.n_free = d.value, nn.value, ne.value, nf.value
-        # nodes per element: the vertices, then (P2) the edge midpoints
-        self.nb = (self.dim + 1) if order == 1 else (self.dim + 1) * (self.dim + 2) // 2
+        # nodes per element: the vertices (corners), then (order 2) the edge midpoints
+        if shape == NLQ_SHAPE_BOX:
+            self.nb = (1 << self.dim) if order == 1 else (8 if self.dim == 2 else 20)
+        else:
+            self.nb = (self.dim + 1) if order == 1 else (self.dim + 1) * (self.dim + 2) // 2
 
     @classmethod
-    def create(cls, ctx, coords, conn, constrained, order: int = 1):
-        """P1 (order 1, conn [e][dim+1]) or P2 (order 2, conn [e][(dim+1)(dim+2)/2]:
-        vertices, then the edge midpoints of edges (0,1),(0,2),... in lexicographic order)."""
+    def create(cls, ctx, coords, conn, constrained, order: int = 1, shape: int = 0):
+        """Simplices (shape 0): P1 (order 1, conn [e][dim+1]) or P2 (order 2,
+        conn [e][(dim+1)(dim+2)/2]: vertices, then the edge midpoints of edges
+        (0,1),(0,2),... in lexicographic order).  Quadrilaterals / hexahedra
+        (shape 1): Q1 (corners in tensor order) or serendipity (then the edge
+        midpoints), see nlq_mesh_create_shape."""
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         conn = np.ascontiguousarray(conn, dtype=np.int32)
         cst = np.ascontiguousarray(constrained, dtype=np.uint8)
         h = C.c_void_p()
-        _check(lib().nlq_mesh_create_order(ctx.h, coords.shape[1], order, coords.shape[0], _ptr(coords),
+        _check(lib().nlq_mesh_create_shape(ctx.h, coords.shape[1], shape, order, coords.shape[0], _ptr(coords),
                                            conn.shape[0], _ptr(conn), _ptr(cst), C.byref(h)))
-        return cls(ctx, h, order)
+        return cls(ctx, h, order, shape)
 
     @classmethod
     def box(cls, ctx, dim, n, k_gamma):
