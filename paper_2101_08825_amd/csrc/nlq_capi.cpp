@@ -307,7 +307,8 @@ void collect_counters(System &s, hipStream_t st)
     AsmCounters c{};
     NLQ_HIP(hipMemcpyAsync(&c, s.counters.as<void>(), sizeof(AsmCounters), hipMemcpyDeviceToHost, st));
     NLQ_HIP(hipStreamSynchronize(st));
-    const int nq = s.mesh->dim == 2 ? 7 : 15;
+    // rule points per element: 7 / 15 on simplices, 9 / 27 on boxes
+    const int nq = s.mesh->shape == 1 ? (s.mesh->dim == 2 ? 9 : 27) : (s.mesh->dim == 2 ? 7 : 15);
     int64_t leaves = 0;
     for (int q = 0; q < 9; ++q) {
         s.info.n_leaf[q] = (q >= 1 && q <= 8) ? static_cast<int64_t>(c.leaf[q]) : 0;

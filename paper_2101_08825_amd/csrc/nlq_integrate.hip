@@ -277,6 +277,18 @@ template <int ETA> __device__ __forceinline__ float kernel32(CArgs &A, float d2,
 // the plateau, 0 beyond) and the square root and xi are skipped for the whole
 // register: a wave-uniform branch.  Both sides of the branch give the same
 // values up to the band edges, where xi is within (1e-7)^5 of 1 or 0.
+// kernel64 with the band test taken once per wave: a register none of whose
+// distances lies in the band skips the square root and xi (same values)
+template <int ETA> __device__ __forceinline__ double kernel64_reg(CArgs &A, double d2)
+{
+    const bool plateau = d2 < A.dme2;
+    const bool band = !plateau && d2 <= A.dpe2;
+    if (__builtin_amdgcn_ballot_w64(band)) return kernel64<ETA>(A, d2);
+    double g = plateau ? 1.0 : 0.0;
+    if (ETA == NLQ_ETA_GAUSS) g *= exp(-d2 / (A.delta * A.delta));
+    return g;
+}
+
 template <int ETA> __device__ __forceinline__ float kernel32_reg(CArgs &A, float d2, float doe)
 {
     const bool plateau = d2 < A.f_dme2;
@@ -535,6 +547,7 @@ template <int DIM, int ETA, int ORD = 1> struct PlainAcc {
     double acc[S::NR];
     double yh[DIM];   // inner point relative to the anchor
     bool active;
+    __device__ void set_rule(const double *) {}   // the points come from the barycentric tables
     __device__ void init(const double *y, int lane, char *)
     {
 #pragma unroll
@@ -688,6 +701,7 @@ template <int DIM, int ETA, int ORD> struct BoxAcc {
         active = (lane % NYP) < NQ;
         grp = lane / NYP;
     }
+    __device__ void set_rule(const double *rule) { g = rule; }
     __device__ In fetch(CArgs &A, bool valid, int sub, int a, int lev, float, double wa) const
     {
         In in;
@@ -820,6 +834,107 @@ template <int DIM, int ETA, int ORD> struct BoxAcc {
             }
         }
     }
+};
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// FP64 accumulator with the contraction on the matrix cores
+// (v_mfma_f64_16x16x4f64): the staging of Base (PlainAcc or BoxAcc: FP64
+// coordinates and NR rows per point), then per step of 4 staged points every
+// lane evaluates gamma for one (point k, inner point j) pair, lane j + 16k --
+// the B operand G[k][j] -- and the A operand P[i][k] (row 16t + i of point k,
+// lane i + 16k) is read from the staged rows; D[i][j] += sum_k P[i][k] G[k][j]
+// for every 16-row tile t and 16-column tile c of the inner points.  Distances
+// and gamma stay on the vector ALU in FP64; the NR multiply-adds per
+// evaluation move to the matrix cores.  The FP64 instruction's D[i][j] is held
+// in lane j + 16 (i % 4), register i / 4 (unlike the FP32 16x16x4 one: lane
+// j + 16 (i / 4), register i % 4).
+template <class Base, int DIM, int ETA, int NR, int NQ, int NYPV, int BATCH> struct Mfma64 {
+    static constexpr int NRT = (NR + 15) / 16, NCT = (NQ + 15) / 16;
+    static constexpr int NYP = NYPV;   // lane period of the inner points given to init
+    static constexpr int kStageBytes = Base::kStageBytes;
+    using In = typename Base::In;
+    Base base;
+    doublex4 acc[NRT][NCT];
+    double yc[NCT][DIM];   // inner points of this lane's columns j and 16 + j
+    bool colv[NCT];
+    __device__ void init(const double *y, int lane, char *work)
+    {
+#pragma unroll
+        for (int t = 0; t < NRT; ++t)
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) acc[t][c] = doublex4{0.0, 0.0, 0.0, 0.0};
+        const int x = lane & 15;
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) {
+            // the lane holding inner point 16c + x (period NYP >= 16 * NCT)
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) yc[c][d] = __shfl(y[d], 16 * c + x, kWave);
+            colv[c] = 16 * c + x < NQ;
+        }
+    }
+    __device__ void set_rule(const double *g) { base.set_rule(g); }
+    __device__ In fetch(CArgs &A, bool valid, int sub, int a, int lev, float w32, double wa) const
+    {
+        return base.fetch(A, valid, sub, a, lev, w32, wa);
+    }
+    template <class Frame> __device__ static void stage(char *work, int t, const In &in, const Frame &F)
+    {
+        Base::stage(work, t, in, F);
+    }
+    __device__ void run(CArgs &A, const char *work, int npts)
+    {
+        const double *sx = reinterpret_cast<const double *>(work);
+        const double *sp = sx + BATCH * DIM;
+        const int lane = lane_id(), x = lane & 15, k = lane >> 4;
+        for (int p0 = 0; p0 < npts; p0 += 4) {
+            const int p = p0 + k;
+            const bool pv = p < npts;
+            double xp[DIM];
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) xp[d] = pv ? sx[p * DIM + d] : 0.0;
+            double b[NCT];
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) {
+                double d2 = 0.0;
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) {
+                    const double dx = xp[d] - yc[c][d];
+                    d2 = fma(dx, dx, d2);
+                }
+                const double gv = kernel64_reg<ETA>(A, d2);
+                b[c] = pv && colv[c] ? gv : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < NRT; ++t) {
+                const int r = 16 * t + x;
+                const double a = pv && r < NR ? sp[p * NR + r] : 0.0;
+#pragma unroll
+                for (int c = 0; c < NCT; ++c) acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[c], acc[t][c], 0, 0, 0);
+            }
+        }
+    }
+    // rows -> out[r * QS + b] (QS = the epilogue's row stride), times the inner
+    // point's factor jm (held by lane b: period NYP)
+    template <int QS> __device__ void finish_rows(double *out, double jm)
+    {
+        const int lane = lane_id(), x = lane & 15, q = lane >> 4;
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) {
+            const double f = __shfl(jm, 16 * c + x, kWave);
+#pragma unroll
+            for (int t = 0; t < NRT; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * t + 4 * r + q, col = 16 * c + x;
+                    if (row < NR && col < NQ) out[row * QS + col] = acc[t][c][r] * f;
+                }
+        }
+    }
+    // simplices: the epilogue's stride 16 (the tile argument is unused)
+    __device__ void finish(double *out, double *) { finish_rows<16>(out, 1.0); }
+    // boxes: stride 16 (2D) / 32 (3D), times |det F_m'| / |E_m|
+    __device__ void finish(double *out, double jm) { finish_rows<(DIM == 2 ? 16 : 32)>(out, jm); }
 };
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -1382,10 +1497,19 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     constexpr int NQ = SHP == 1 ? BS::NQ : S::NQ, RS = SHP == 1 ? DIM : NV;
     constexpr int NB = SHP == 1 ? BS::NB : O::NB, NU = SHP == 1 ? BS::NU : O::NU;
     constexpr int NOUT = SHP == 1 ? BS::NOUT : O::NOUT;
-    using Acc = typename std::conditional<
-        SHP == 1, BoxAcc<DIM, ETA, ORD>,
-        typename std::conditional<PREC == 0, PlainAcc<DIM, ETA, ORD>, MixedAcc<DIM, ETA>>::type>::type;
     constexpr int BATCH = SHP == 1 ? BoxAcc<DIM, ETA, ORD>::kPoints : kBatch;
+    // FP64: the contraction on the matrix cores (Mfma64) for the 3D elements with
+    // many rows (P2 tetrahedra: 35, hexahedra: 27 / 90); measured slower for P1
+    // tetrahedra (10 rows: one FP64 MFMA per 64 evaluations takes longer than the
+    // ten vector multiply-adds) and no faster in 2D (7 or 9 of a tile's 16 columns
+    // carry inner points)
+    constexpr bool kMfma64 = PREC == 0 && DIM == 3 && (ORD == 2 || SHP == 1);
+    using Base64 = typename std::conditional<SHP == 1, BoxAcc<DIM, ETA, ORD>, PlainAcc<DIM, ETA, ORD>>::type;
+    constexpr int BNR = SHP == 1 ? BS::NR : O::NR;
+    // lane period of the inner points handed to the accumulator
+    constexpr int YS = SHP == 1 ? BS::QS : (kMfma64 ? 16 : (PREC == 0 ? PlainAcc<DIM, ETA>::NYP : (DIM == 2 ? 8 : 16)));
+    using Acc64 = typename std::conditional<kMfma64, Mfma64<Base64, DIM, ETA, BNR, NQ, YS, BATCH>, Base64>::type;
+    using Acc = typename std::conditional<PREC == 0, Acc64, MixedAcc<DIM, ETA>>::type;
     using Real = typename std::conditional<PREC == 0, double, float>::type;
     using WM = WaveMem<DIM, PREC, ORD, SHP>;
     const int lane = lane_id();
@@ -1432,10 +1556,7 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     const int32_t mj1 = kP1 ? A.conn[static_cast<int64_t>(m) * NV + lane % NV] : 0;
 
     // inner point of this lane, relative to the anchor v0(l)
-    int bsel;
-    if (SHP == 1) bsel = lane % BS::QS;
-    else if (PREC == 0) bsel = lane % PlainAcc<DIM, ETA>::NYP;
-    else bsel = DIM == 2 ? (lane & 7) : (lane & 15);
+    const int bsel = lane % YS;
     const int bq = bsel < NQ ? bsel : 0;
     double y[DIM];
     double jm = 1.0;   // boxes: |det F_m'(g_b)| / |E_m|
@@ -1482,7 +1603,7 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
 
     Acc acc;
     acc.init(y, lane, work);
-    if constexpr (SHP == 1) acc.g = bary;
+    if constexpr (SHP == 1) acc.set_rule(bary);
     if constexpr (PREC == 1) acc.set_column(A, y, bsel < NQ);
 
     // integrate the leaves in leafbuf[0..nleaf)
@@ -1777,11 +1898,11 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
 
 // Occupancy hint: more waves per SIMD cover LDS and table latency at the cost of
 // registers (5 waves in 2D, 3 in 3D were fastest on the 2D 128^2 and 3D 8^3 cases).
-// (box elements: 2 waves per SIMD in 2D, 1 in 3D, so that their wider
-// accumulators and frames stay in registers instead of spilling)
+// (P2 and box elements: 2 waves per SIMD, 1 for hexahedra, so that their wider
+// rows, frames and accumulators stay in registers instead of spilling)
 template <int DIM, int PREC, int ETA, int OCC, int ORD, int SHP = 0>
 __global__ void __launch_bounds__(kThreads)
-    __attribute__((amdgpu_waves_per_eu(SHP == 1 ? (DIM == 2 ? 2 : 1) : waves_per_eu<DIM, PREC, OCC>())))
+    __attribute__((amdgpu_waves_per_eu(SHP == 1 && DIM == 3 ? 1 : (SHP == 1 || ORD == 2 ? 2 : waves_per_eu<DIM, PREC, OCC>()))))
 k_integrate(LaunchArgs L)
 {
     using S = Shape<DIM>;

@@ -41,16 +41,18 @@ def main():
         wl = W.WORKLOADS[a.workload]
         mesh = wl.mesh()
         ctx = nlq.Context(0)
-        m = nlq.Mesh.create(ctx, mesh.coords, mesh.conn, mesh.constrained)
-        s = nlq.System(ctx, m, nlq.params(mesh.dim, wl.delta, wl.eps, wl.lmax, precision=a.precision,
+        m = nlq.Mesh.create(ctx, mesh.coords, mesh.conn, mesh.constrained, order=wl.order, shape=wl.shape)
+        precision = a.precision if (wl.order == 1 and wl.shape == 0) else nlq.NLQ_FP64_PLAIN
+        s = nlq.System(ctx, m, nlq.params(mesh.dim, wl.delta, wl.eps, wl.lmax, precision=precision,
                                           kernel=wl.kernel))
         times = [s.info().t_kernel]
         for _ in range(a.reps - 1):
             s.reassemble()
             times.append(s.info().t_kernel)
         inf = s.info()
-        out.update(workload=a.workload, precision=a.precision, t_kernel_ms=[1e3 * t for t in times],
-                   n_pairs=inf.n_pairs, n_evals=inf.n_evals, nnz=inf.nnz)
+        out.update(workload=a.workload, precision=precision, t_kernel_ms=[1e3 * t for t in times],
+                   n_pairs=inf.n_pairs, n_evals=inf.n_evals, n_leaf_zero=inf.n_leaf_zero, nnz=inf.nnz,
+                   n_leaf=list(inf.n_leaf))
         s.close()
         m.close()
         ctx.close()

@@ -151,9 +151,11 @@ def jittered_mesh(dim: int, n: int, k_gamma: int, frac: float = 0.2, seed: int =
                 k_gamma=k_gamma)
 
 
-def box_mesh(dim: int, n: int, k_gamma: int, order: int = 1, frac: float = 0.0, seed: int = 0) -> Mesh:
-    """Structured mesh of [0,1]^dim into n^dim squares / cubes (cell id
-    c0 + n*(c1 + n*c2)), quadrilateral or hexahedral elements.
+def box_mesh(dim: int, n: int, k_gamma: int, order: int = 1, frac: float = 0.0, seed: int = 0,
+             cells=None) -> Mesh:
+    """Structured mesh of squares / cubes of side h = 1/n, n cells per axis
+    ([0,1]^dim) or cells[k] along axis k ([0, cells[k]/n] per axis), cell id
+    c0 + n0*(c1 + n1*c2), quadrilateral or hexahedral elements.
       * order 1 (Q1): nodes x = i/n (one correctly rounded FP64 division), node id
         i0 + (n+1)*(i1 + (n+1)*i2); element nodes = the cell's corners in tensor
         order (corner c = c0 + 2 c1 + 4 c2 at offset (c0, c1, c2));
@@ -162,8 +164,10 @@ def box_mesh(dim: int, n: int, k_gamma: int, order: int = 1, frac: float = 0.0, 
         increasing j0 + (2n+1)*(j1 + (2n+1)*j2); element nodes = the corners in
         tensor order, then the edge midpoints in increasing t0 + 3 t1 + 9 t2 of
         their offset t in half cells (exactly one t_k = 1).
+    (With cells given, the strides n+1 / 2n+1 above are cells[k]+1 / 2 cells[k]+1
+    per axis and the coordinates i/n, j/(2n) run to cells[k]/n.)
     A node is constrained when some coordinate index lies in the layer of K =
-    k_gamma cells (i_k <= K or >= n - K; half-grid j_k <= 2K or >= 2n - 2K).
+    k_gamma cells (i_k <= K or >= n_k - K; half-grid j_k <= 2K or >= 2n_k - 2K).
     frac > 0 moves every corner node not on the boundary of [0,1]^dim by
     independent U(-frac h, frac h) offsets per coordinate (seeded PCG64), giving
     non-affine (bilinear / trilinear) elements; edge midpoints are then placed
@@ -173,33 +177,35 @@ def box_mesh(dim: int, n: int, k_gamma: int, order: int = 1, frac: float = 0.0, 
     if n < 1 or k_gamma < 0:
         raise ValueError("bad mesh size")
     rng = np.random.default_rng(seed)
+    nc = [int(c) for c in cells] if cells is not None else [n] * dim
     s = 2 if order == 2 else 1          # grid steps per cell
-    ng = s * n + 1
-    grid = np.array(list(itertools.product(range(ng), repeat=dim)))[:, ::-1]   # j0 fastest
+    ngk = [s * c + 1 for c in nc]
+    grid = np.array(list(itertools.product(*[range(g) for g in ngk[::-1]])))[:, ::-1]   # j0 fastest
     if order == 2:
         keep = (grid % 2 == 1).sum(axis=1) <= 1
         grid = grid[keep]
-    key = sum(grid[:, k].astype(np.int64) * ng ** k for k in range(dim))
-    ident = -np.ones(ng ** dim, dtype=np.int64)
+    stride = [int(np.prod(ngk[:k])) for k in range(dim)]
+    key = sum(grid[:, k].astype(np.int64) * stride[k] for k in range(dim))
+    ident = -np.ones(int(np.prod(ngk)), dtype=np.int64)
     ident[key] = np.arange(grid.shape[0])
     coords = grid.astype(np.float64) / float(s * n)
     constrained = np.zeros(grid.shape[0], dtype=np.uint8)
     for k in range(dim):
-        constrained |= ((grid[:, k] <= s * k_gamma) | (grid[:, k] >= s * (n - k_gamma))).astype(np.uint8)
-    cells = np.array(list(itertools.product(range(n), repeat=dim)))[:, ::-1]     # c0 fastest
+        constrained |= ((grid[:, k] <= s * k_gamma) | (grid[:, k] >= s * (nc[k] - k_gamma))).astype(np.uint8)
+    cells_ = np.array(list(itertools.product(*[range(c) for c in nc[::-1]])))[:, ::-1]     # c0 fastest
     offsets = [tuple(2 * ((c >> k) & 1) for k in range(dim)) for c in range(1 << dim)]
     if order == 2:
         offsets += [t for t in (tuple((q // 3 ** k) % 3 for k in range(dim)) for q in range(3 ** dim))
                     if sum(x == 1 for x in t) == 1]
     cols = []
     for t in offsets:
-        j = cells * s + np.array(t) * s // 2
-        cols.append(ident[sum(j[:, k].astype(np.int64) * ng ** k for k in range(dim))])
+        j = cells_ * s + np.array(t) * s // 2
+        cols.append(ident[sum(j[:, k].astype(np.int64) * stride[k] for k in range(dim))])
     conn = np.stack(cols, axis=1).astype(np.int32)
     if frac > 0.0:
         off = rng.uniform(-frac, frac, size=coords.shape) / float(n)
         even = np.all(grid % s == 0, axis=1)
-        inner = np.all((coords > 0.0) & (coords < 1.0), axis=1) & even
+        inner = np.all((grid > 0) & (grid < np.array(ngk) - 1), axis=1) & even
         coords[inner] += off[inner]
         if order == 2:
             for e_col in range(1 << dim, conn.shape[1]):
@@ -283,6 +289,8 @@ class Workload:
     lmax: int
     kernel: int             # 0 = constant eta, 1 = truncated Gaussian eta
     u: Quadratic
+    shape: int = 0          # 0: Kuhn simplices; 1: squares / cubes (box_mesh)
+    order: int = 1          # 1: P1 / Q1; 2: P2 / serendipity
 
     @property
     def h(self) -> float:
@@ -297,6 +305,10 @@ class Workload:
         return self.delta / self.eps_div
 
     def mesh(self) -> Mesh:
+        if self.shape == 1:
+            return box_mesh(self.dim, self.n, self.k_delta, self.order)
+        if self.order == 2:
+            return kuhn_mesh_p2(self.dim, self.n, self.k_delta)
         return kuhn_mesh(self.dim, self.n, self.k_delta)
 
 
@@ -316,6 +328,14 @@ WORKLOADS = {
     "c3_3d24": Workload("c3_3d24", 3, 24, 3, 16, 4, 0, _ux1sq(3)),
     # 3D 48^3 x 6 tets, truncated Gaussian, delta = 3h, eps = delta/32, depth 6
     "c5_3d48_gauss": Workload("c5_3d48_gauss", 3, 48, 3, 32, 6, 1, _ux1sq(3)),
+    # other element types (FP64), with the ratios of the paper's runs:
+    # 20-node serendipity hexahedra, the 3D scaling run's delta = 4h, eps = h/2,
+    # depth 2, on a 24^3 cube (13,824 hexes, 60,625 nodes)
+    "hex20_3d24": Workload("hex20_3d24", 3, 24, 4, 8, 2, 0, _ux1sq(3), shape=1, order=2),
+    # 8-node serendipity quadrilaterals, delta = 4h, eps = h/2, depth 3, 128^2
+    "quad8_2d128": Workload("quad8_2d128", 2, 128, 4, 8, 3, 0, Quadratic(np.ones(2)), shape=1, order=2),
+    # 10-node P2 tetrahedra, delta = 3h, eps = delta/16, depth 3, 16^3 x 6
+    "p2tet_3d16": Workload("p2tet_3d16", 3, 16, 3, 16, 3, 0, _ux1sq(3), order=2),
 }
 
 
