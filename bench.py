@@ -20,6 +20,11 @@ not hold it:
    spread over the mesh (32 strata, one launch), whole-mesh time extrapolated by
    the sample's share of the pairs;
  * the 2D 128^2 problems (delta = 2h and 4h, eps = delta/32, depth 5);
+ * other element types in FP64, whole assembly + solve: 20-node serendipity
+   hexahedra (24^3, the paper's 3D scaling ratios delta = 4h, eps = h/2, depth
+   2), 10-node P2 tetrahedra (16^3 x 6, delta = 3h, eps = delta/16, depth 3),
+   8-node serendipity quadrilaterals (128^2, delta = 4h, eps = h/2, depth 3),
+   each with the oracle on one seeded outer element on one core;
  * serving: the seeded 256-request stream (2D 8^2..96^2 / 3D 6^3..20^3, delta
    2h..4h, eps = delta/16, depth 3) replayed open loop, first at 20 requests/s
    (beyond capacity: its wall time gives the capacity), then at 0.8 of that
@@ -46,7 +51,10 @@ METRIC = "element-pair integrals/s + p50/p99 assemble+solve latency vs FP64 plai
 HEADLINE = "c3_3d24"
 LARGE = "c5_3d48_gauss"
 WORKLOADS_2D = ("c2a_2d128_d2h", "c2b_2d128_d4h")
+# other element types, FP64: (workload, contraction rows per evaluation)
+ELEMENT_WORKLOADS = (("hex20_3d24", 90), ("p2tet_3d16", 35), ("quad8_2d128", 22))
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
 GOLDEN = os.path.join(ROOT, "tests", "golden", "c3_oracle.json")
 
 
@@ -168,6 +176,57 @@ def run_steps(nlq, ctx, torch, problems, precision, steps, warmup, label, keep_l
                 zero_evals=zero_evals, value=pairs / (ms * 1e-3) if step_times else None, kept=kept)
 
 
+def element_case(nlq, ctx, torch, name, rows):
+    """One warm and one timed FP64 assembly + load + solve of an element workload."""
+    wl = W.WORKLOADS[name]
+    host = wl.mesh()
+    mesh = nlq.Mesh.create(ctx, host.coords, host.conn, host.constrained, order=wl.order, shape=wl.shape)
+    _, f, g = W.nodal_data(host, wl.u)
+    fd = torch.as_tensor(f, dtype=torch.float64, device="cuda")
+    gd = torch.as_tensor(g, dtype=torch.float64, device="cuda")
+    prm = nlq.params(host.dim, wl.delta, wl.eps, wl.lmax, kernel=wl.kernel, precision=nlq.NLQ_FP64_PLAIN)
+    res = None
+    for it in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = nlq.System(ctx, mesh, prm)
+        s.set_data_device(fd.data_ptr(), gd.data_ptr())
+        s.solve(rtol=1e-10, copy=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        info = s.info()
+        s.close()
+        nq = (9 if host.dim == 2 else 27) if wl.shape == 1 else (7 if host.dim == 2 else 15)
+        evaluated = info.n_evals - info.n_leaf_zero * nq * nq
+        fpe = 3 * host.dim - 1 + 2 * rows
+        res = {"pairs": int(info.n_pairs), "ms_per_step": 1e3 * dt, "pairs_per_s": info.n_pairs / dt,
+               "kernel_ms": 1e3 * info.t_kernel, "nnz": int(info.nnz),
+               "evaluated_kernel_evals": int(evaluated), "flops_per_eval": fpe,
+               "kernel_tflops": evaluated * fpe / info.t_kernel / 1e12,
+               "frac_of_fp64_peak": evaluated * fpe / info.t_kernel / 1e12 / FP64_PEAK_TFLOPS}
+        progress(f"{name} step {it + 1}/2 {1e3 * dt:.1f} ms")
+    mesh.close()
+    # the oracle on one seeded outer element away from the boundary, one core
+    import oracle
+    om = oracle.OracleMesh(host.coords, host.conn, order=wl.order, shape=wl.shape)
+    opr = oracle.params(wl.delta, wl.eps, wl.lmax, kernel=wl.kernel)
+    c = host.n // 2
+    if wl.shape == 1:
+        sel = [c + host.n * (c + (host.n * c if host.dim == 3 else 0))]
+    else:
+        per = 2 if host.dim == 2 else 6
+        sel = [per * (c + host.n * (c + (host.n * c if host.dim == 3 else 0)))]
+    k = 8 if host.dim == 2 else 1
+    sel = np.arange(sel[0], sel[0] + k, dtype=np.int64)
+    pairs = int(sum(len(oracle.pairs_of(om, wl.delta + wl.eps, int(l))) for l in sel))
+    t0 = time.perf_counter()
+    oracle.outer_blocks(om, opr, sel, nthreads=1)
+    secs = time.perf_counter() - t0
+    res["cpu_oracle_one_core"] = {"pairs_per_s": pairs / secs, "sample": f"{k} outer element(s), {pairs} pairs, "
+                                                                        f"{secs:.2f} s"}
+    return res
+
+
 def stream(rate):
     return W.serving_stream(rate_per_s=rate)
 
@@ -265,6 +324,7 @@ def main():
     ap.add_argument("--large-fraction", type=float, default=1.0 / 1024)
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-2d", action="store_true")
+    ap.add_argument("--no-elements", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -377,6 +437,16 @@ def main():
         for p in probs:
             p.mesh.close()
 
+    # ---- other element types (FP64)
+    elements = {}
+    if not args.no_elements and fits("element_types", 60.0):
+        for name, rows in ELEMENT_WORKLOADS:
+            elements[name] = element_case(nlq, ctx, torch, name, rows)
+            progress(f"{name}: {elements[name]}")
+        elements["what"] = ("FP64 whole assembly + load + solve of one step after a warm one; kernel_tflops = "
+                            "evaluated kernel evaluations x (distance + 2 x rows) flops / integration time; "
+                            f"frac_of_fp64_peak against {FP64_PEAK_TFLOPS} TFLOP/s")
+
     # ---- serving: capacity at 20/s, then 0.8 of it for both precisions
     serving = {}
     if args.serve_requests > 0 and fits("serving", 150.0):
@@ -460,6 +530,8 @@ def main():
         out["large_48cubed_gauss"] = large
     if two_d:
         out["2d_128"] = two_d
+    if elements:
+        out["element_types"] = elements
     if tuned:
         out["autotune"] = tuned
     head.mesh.close()
