@@ -126,6 +126,7 @@ struct AsmArgs {
     int64_t pb_base;
     const double *rule;   // [nq][nv] barycentric points, then [nq] weights
     double delta, eps, dme, dpe, dme2, dpe2, C;
+    double inv_eps, inv_delta2;   // 1 / eps, 1 / delta^2
     double dme_sq;        // s* with (sqrt(s) < delta - eps) <=> (s < s*), s >= 0
     double *dmm;          // [ne][NU] upper-triangle diagonal-block sums per element
     float f_inv_eps, f_delta_over_eps, f_inv_delta2;
@@ -226,19 +227,36 @@ __device__ __forceinline__ float xi32(float r)
     return r < 0.0f ? w : 1.0f - w;
 }
 
-// gamma_eps / C at squared distance d2: eta * mu (FP64)
+// Square root of a squared distance inside the band (a normal FP64 number far
+// from 0 and from overflow, so no rescaling is needed): Goldschmidt's iteration
+// from the hardware reciprocal square root estimate y ~ 1/sqrt(x), with g -> sqrt(x)
+// and h -> 1/(2 sqrt(x)) refined together, then two Newton corrections of g
+// through the residual x - g^2.
+__device__ __forceinline__ double sqrt_band(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-h, g, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double e = fma(-g, g, x);
+    g = fma(e, h, g);
+    e = fma(-g, g, x);
+    return fma(e, h, g);
+}
+
+// gamma_eps / C at squared distance d2: eta * mu (FP64), without branches.  d2 is
+// clamped into the band's range [dme2, dpe2] before the square root, the band
+// coordinate r = (delta - d) / eps (as (delta - d) * (1 / eps)) to [-1, 1], where
+// xi is exactly 1 and 0; the plateau and the outside are then selected on d2
+// itself (dme2 and dpe2 are (delta -+ eps)^2 moved outwards by a relative 1e-12,
+// so a d2 between either pair of values gives the clamped r of its side).
 template <int ETA> __device__ __forceinline__ double kernel64(CArgs &A, double d2)
 {
-    double mu;
-    if (d2 < A.dme2) {
-        mu = 1.0;
-    } else if (d2 > A.dpe2) {
-        mu = 0.0;
-    } else {
-        const double d = sqrt(d2);
-        mu = d < A.dme ? 1.0 : (d > A.dpe ? 0.0 : xi64((A.delta - d) / A.eps));
-    }
-    if (ETA == NLQ_ETA_GAUSS) mu *= exp(-d2 / (A.delta * A.delta));
+    const double d = sqrt_band(fmin(fmax(d2, A.dme2), A.dpe2));
+    const double xi = xi64(fmin(fmax((A.delta - d) * A.inv_eps, -1.0), 1.0));
+    double mu = d2 < A.dme2 ? 1.0 : (d2 > A.dpe2 ? 0.0 : xi);
+    if (ETA == NLQ_ETA_GAUSS) mu *= exp(-d2 * A.inv_delta2);
     return mu;
 }
 
@@ -284,9 +302,8 @@ template <int ETA> __device__ __forceinline__ double kernel64_reg(CArgs &A, doub
     const bool plateau = d2 < A.dme2;
     const bool band = !plateau && d2 <= A.dpe2;
     if (__builtin_amdgcn_ballot_w64(band)) return kernel64<ETA>(A, d2);
-    double g = plateau ? 1.0 : 0.0;
-    if (ETA == NLQ_ETA_GAUSS) g *= exp(-d2 / (A.delta * A.delta));
-    return g;
+    if (ETA == NLQ_ETA_GAUSS) return plateau ? exp(-d2 * A.inv_delta2) : 0.0;
+    return plateau ? 1.0 : 0.0;
 }
 
 template <int ETA> __device__ __forceinline__ float kernel32_reg(CArgs &A, float d2, float doe)
@@ -622,7 +639,7 @@ template <int DIM, int ETA, int ORD = 1> struct PlainAcc {
                 const double dx = sx[p * DIM + k] - yh[k];
                 d2 = fma(dx, dx, d2);
             }
-            const double g = kernel64<ETA>(A, d2);
+            const double g = kernel64_reg<ETA>(A, d2);
 #pragma unroll
             for (int r = 0; r < S::NR; ++r) acc[r] = fma(sp[p * S::NR + r], g, acc[r]);
         }
@@ -796,7 +813,7 @@ template <int DIM, int ETA, int ORD> struct BoxAcc {
                 const double dx = sx[p * DIM + k] - yh[k];
                 d2 = fma(dx, dx, d2);
             }
-            const double gv = kernel64<ETA>(A, d2);
+            const double gv = kernel64_reg<ETA>(A, d2);
             if constexpr (ROWS) {
 #pragma unroll
                 for (int r = 0; r < NRL; ++r) {
@@ -1133,11 +1150,19 @@ template <int DIM, int ETA> struct MixedAccMfma {
         dst[3] = make_float2(in.r1[2], in.r1[3]);
         dst[4] = make_float2(in.r2[0], in.r2[1]);
     }
-    // gamma_eps / C of tile value v = |x|^2 - 2 x.y + |y|^2 = |x - y|^2, clamped
-    // at 0 against the cancellation of nearly equal points
+    // gamma_eps / C of tile value v = |x|^2 - 2 x.y + |y|^2 = |x - y|^2.  The
+    // band test and the plateau take v as it is (a slightly negative v from the
+    // cancellation of nearly equal points lies on the plateau); only the square
+    // root of the band path needs it clamped at 0.
     __device__ __forceinline__ float gamma(CArgs &A, float v) const
     {
-        return kernel32_reg<ETA>(A, __builtin_amdgcn_fmed3f(v, 0.0f, 3.0e38f), doe);
+        const bool plateau = v < A.f_dme2;
+        const bool band = !plateau && v <= A.f_dpe2;
+        const float d2 = __builtin_amdgcn_fmed3f(v, 0.0f, 3.0e38f);
+        if (__builtin_amdgcn_ballot_w64(band)) return kernel32<ETA>(A, d2, doe);
+        float g = plateau ? 1.0f : 0.0f;
+        if (ETA == NLQ_ETA_GAUSS) g = plateau ? __expf(-d2 * A.f_inv_delta2) : 0.0f;
+        return g;
     }
     __device__ void run(CArgs &A, const char *work, int npts)
     {
@@ -1151,15 +1176,22 @@ template <int DIM, int ETA> struct MixedAccMfma {
             const int p0 = ss * 16;
             const float a_d = sx[(p0 + arow) * XS + acol];
             // C = |y_j|^2 in every row: the tile is |x_i - y_j|^2 directly
+            // the wave issues its matrix-core instructions at a raised priority (and
+            // drops back for the vector work), so that a wave waiting to issue them
+            // is not held behind the other waves' vector instructions
+            __builtin_amdgcn_s_setprio(2);
             const floatx4 v = __builtin_amdgcn_mfma_f32_16x16x4f32(a_d, bop, floatx4{yb2, yb2, yb2, yb2}, 0, 0, 0);
+            __builtin_amdgcn_s_setprio(0);
             float g[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) g[r] = gamma(A, v[r]);
+            float a4[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float a = sp[(p0 + 4 * acol + r) * PS + arow];
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, g[r], acc, 0, 0, 0);
-            }
+            for (int r = 0; r < 4; ++r) a4[r] = sp[(p0 + 4 * acol + r) * PS + arow];
+            __builtin_amdgcn_s_setprio(2);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[r], g[r], acc, 0, 0, 0);
+            __builtin_amdgcn_s_setprio(0);
         }
         facc = acc;
         if (++nb == kFlushBatches) flush();
@@ -2333,6 +2365,8 @@ AsmArgs make_args(const System &s, const Tables &T)
     A.dme2 = A.dme * A.dme * (1.0 - 1e-12);
     A.dpe2 = A.dpe * A.dpe * (1.0 + 1e-12);
     A.C = s.C;
+    A.inv_eps = 1.0 / s.p.eps;
+    A.inv_delta2 = 1.0 / (s.p.delta * s.p.delta);
     A.f_inv_eps = static_cast<float>(1.0 / s.p.eps);
     A.f_delta_over_eps = static_cast<float>(s.p.delta / s.p.eps);
     A.f_inv_delta2 = static_cast<float>(1.0 / (s.p.delta * s.p.delta));
