@@ -227,6 +227,25 @@ __device__ __forceinline__ float xi32(float r)
     return r < 0.0f ? w : 1.0f - w;
 }
 
+// The constants of the FP64 kernel evaluation, copied into vector registers once
+// per batch: read through the argument block inside the loops, their scalar
+// loads would share a wait counter with the LDS loads of the next step's
+// operands and hold those back.
+struct Band64 {
+    double delta, inv_eps, dme2, dpe2, inv_delta2;
+};
+__device__ __forceinline__ double in_vgpr64(double x)
+{
+    double r;
+    asm("v_mov_b64 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+__device__ __forceinline__ Band64 band64(const CArgs &A)
+{
+    return Band64{in_vgpr64(A.delta), in_vgpr64(A.inv_eps), in_vgpr64(A.dme2), in_vgpr64(A.dpe2),
+                  in_vgpr64(A.inv_delta2)};
+}
+
 // Square root of a squared distance inside the band (a normal FP64 number far
 // from 0 and from overflow, so no rescaling is needed): Goldschmidt's iteration
 // from the hardware reciprocal square root estimate y ~ 1/sqrt(x), with g -> sqrt(x)
@@ -251,12 +270,12 @@ __device__ __forceinline__ double sqrt_band(double x)
 // xi is exactly 1 and 0; the plateau and the outside are then selected on d2
 // itself (dme2 and dpe2 are (delta -+ eps)^2 moved outwards by a relative 1e-12,
 // so a d2 between either pair of values gives the clamped r of its side).
-template <int ETA> __device__ __forceinline__ double kernel64(CArgs &A, double d2)
+template <int ETA> __device__ __forceinline__ double kernel64(const Band64 &K, double d2)
 {
-    const double d = sqrt_band(fmin(fmax(d2, A.dme2), A.dpe2));
-    const double xi = xi64(fmin(fmax((A.delta - d) * A.inv_eps, -1.0), 1.0));
-    double mu = d2 < A.dme2 ? 1.0 : (d2 > A.dpe2 ? 0.0 : xi);
-    if (ETA == NLQ_ETA_GAUSS) mu *= exp(-d2 * A.inv_delta2);
+    const double d = sqrt_band(fmin(fmax(d2, K.dme2), K.dpe2));
+    const double xi = xi64(fmin(fmax((K.delta - d) * K.inv_eps, -1.0), 1.0));
+    double mu = d2 < K.dme2 ? 1.0 : (d2 > K.dpe2 ? 0.0 : xi);
+    if (ETA == NLQ_ETA_GAUSS) mu *= exp(-d2 * K.inv_delta2);
     return mu;
 }
 
@@ -297,12 +316,12 @@ template <int ETA> __device__ __forceinline__ float kernel32(CArgs &A, float d2,
 // values up to the band edges, where xi is within (1e-7)^5 of 1 or 0.
 // kernel64 with the band test taken once per wave: a register none of whose
 // distances lies in the band skips the square root and xi (same values)
-template <int ETA> __device__ __forceinline__ double kernel64_reg(CArgs &A, double d2)
+template <int ETA> __device__ __forceinline__ double kernel64_reg(const Band64 &K, double d2)
 {
-    const bool plateau = d2 < A.dme2;
-    const bool band = !plateau && d2 <= A.dpe2;
-    if (__builtin_amdgcn_ballot_w64(band)) return kernel64<ETA>(A, d2);
-    if (ETA == NLQ_ETA_GAUSS) return plateau ? exp(-d2 * A.inv_delta2) : 0.0;
+    const bool plateau = d2 < K.dme2;
+    const bool band = !plateau && d2 <= K.dpe2;
+    if (__builtin_amdgcn_ballot_w64(band)) return kernel64<ETA>(K, d2);
+    if (ETA == NLQ_ETA_GAUSS) return plateau ? exp(-d2 * K.inv_delta2) : 0.0;
     return plateau ? 1.0 : 0.0;
 }
 
@@ -628,6 +647,7 @@ template <int DIM, int ETA, int ORD = 1> struct PlainAcc {
     }
     __device__ void run(CArgs &A, const char *work, int npts)
     {
+        const Band64 KB = band64(A);
         const double *sx = reinterpret_cast<const double *>(work);
         const double *sp = sx + kBatch * DIM;
         const int k0 = lane_id() / NYP;
@@ -639,7 +659,7 @@ template <int DIM, int ETA, int ORD = 1> struct PlainAcc {
                 const double dx = sx[p * DIM + k] - yh[k];
                 d2 = fma(dx, dx, d2);
             }
-            const double g = kernel64_reg<ETA>(A, d2);
+            const double g = kernel64_reg<ETA>(KB, d2);
 #pragma unroll
             for (int r = 0; r < S::NR; ++r) acc[r] = fma(sp[p * S::NR + r], g, acc[r]);
         }
@@ -802,6 +822,7 @@ template <int DIM, int ETA, int ORD> struct BoxAcc {
     }
     __device__ void run(CArgs &A, const char *work, int npts)
     {
+        const Band64 KB = band64(A);
         const double *sx = reinterpret_cast<const double *>(work);
         const double *sp = sx + kPoints * DIM;
         if (!active) return;
@@ -813,7 +834,7 @@ template <int DIM, int ETA, int ORD> struct BoxAcc {
                 const double dx = sx[p * DIM + k] - yh[k];
                 d2 = fma(dx, dx, d2);
             }
-            const double gv = kernel64_reg<ETA>(A, d2);
+            const double gv = kernel64_reg<ETA>(KB, d2);
             if constexpr (ROWS) {
 #pragma unroll
                 for (int r = 0; r < NRL; ++r) {
@@ -899,17 +920,39 @@ template <class Base, int DIM, int ETA, int NR, int NQ, int NYPV, int BATCH> str
     {
         Base::stage(work, t, in, F);
     }
+    // Step p0 takes the outer points p0 + k (k = lane / 16).  Its operands are read
+    // without conditions (a lane past npts, or a row past NR, reads point 0 / row 0
+    // of the batch, which is always staged, and its value is masked to 0), and
+    // the next step's are loaded before this step's kernel values and MFMAs, so
+    // the LDS latency overlaps them.
+    __device__ void load(const double *sx, const double *sp, int p0, int npts, double *xp, double *a) const
+    {
+        const int lane = lane_id(), x = lane & 15, k = lane >> 4;
+        const int p = p0 + k < npts ? p0 + k : 0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) xp[d] = sx[p * DIM + d];
+#pragma unroll
+        for (int t = 0; t < NRT; ++t) {
+            const int r = 16 * t + x;
+            a[t] = sp[p * NR + (r < NR ? r : 0)];
+        }
+    }
     __device__ void run(CArgs &A, const char *work, int npts)
     {
+        const Band64 KB = band64(A);
         const double *sx = reinterpret_cast<const double *>(work);
         const double *sp = sx + BATCH * DIM;
         const int lane = lane_id(), x = lane & 15, k = lane >> 4;
+        double xp[DIM], a[NRT];
+        load(sx, sp, 0, npts, xp, a);
         for (int p0 = 0; p0 < npts; p0 += 4) {
-            const int p = p0 + k;
-            const bool pv = p < npts;
-            double xp[DIM];
+            const bool pv = p0 + k < npts;
+            double xn[DIM], an[NRT];
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) xp[d] = pv ? sx[p * DIM + d] : 0.0;
+            for (int d = 0; d < DIM; ++d) xn[d] = xp[d];
+#pragma unroll
+            for (int t = 0; t < NRT; ++t) an[t] = a[t];
+            if (p0 + 4 < npts) load(sx, sp, p0 + 4, npts, xn, an);
             double b[NCT];
 #pragma unroll
             for (int c = 0; c < NCT; ++c) {
@@ -919,16 +962,19 @@ template <class Base, int DIM, int ETA, int NR, int NQ, int NYPV, int BATCH> str
                     const double dx = xp[d] - yc[c][d];
                     d2 = fma(dx, dx, d2);
                 }
-                const double gv = kernel64_reg<ETA>(A, d2);
+                const double gv = kernel64_reg<ETA>(KB, d2);
                 b[c] = pv && colv[c] ? gv : 0.0;
             }
 #pragma unroll
             for (int t = 0; t < NRT; ++t) {
-                const int r = 16 * t + x;
-                const double a = pv && r < NR ? sp[p * NR + r] : 0.0;
+                const double at = pv && 16 * t + x < NR ? a[t] : 0.0;
 #pragma unroll
-                for (int c = 0; c < NCT; ++c) acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[c], acc[t][c], 0, 0, 0);
+                for (int c = 0; c < NCT; ++c) acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(at, b[c], acc[t][c], 0, 0, 0);
             }
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) xp[d] = xn[d];
+#pragma unroll
+            for (int t = 0; t < NRT; ++t) a[t] = an[t];
         }
     }
     // rows -> out[r * QS + b] (QS = the epilogue's row stride), times the inner
@@ -1857,10 +1903,24 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     // refined (outer) element, 2 B_ll and 2 B_lm (see the oracle's form 2)
     const bool inner = A.form == NLQ_FORM_PAPER2_INNER;
     constexpr int NPASS = (NOUT + kWave - 1) / kWave;
-    for (int pass = 0; pass < NPASS; ++pass) {
+    // Boxes accumulated into the CSR matrix: B_ll = sum_r prod_u[r] R1[r] is linear in
+    // the weighted row sums R1, so the pair adds its scaled R1 to the outer
+    // element's sums (in s_bll; NR <= NU) and the work item forms B_ll from them
+    // once (k_integrate); explicit blocks form B_ll per pair
+    const bool box_r1 = SHP == 1 && !ex_block && !A.pb;
+    if constexpr (SHP == 1) {
+        if (box_r1 && (four || inner)) {
+            const double *R1 = HQ + BS::NR * BS::QS + BS::NB * BS::QS;
+            const double f = inner ? 2.0 * Sc : Sc;
+            for (int r = lane; r < BS::NR; r += kWave) atomicAdd(&s_bll[r], f * R1[r]);
+        }
+    }
+    const int npass = box_r1 ? (NB * NB + NU + kWave - 1) / kWave : NPASS;
+    for (int pass = 0; pass < npass; ++pass) {
         const int o = pass * kWave + lane;
         const int desc = s_desc[o];
         const int kind = desc & 3;
+        if (box_r1 && kind == kOutLL) continue;
         int i, j, u;
         double v = 0.0;
         if constexpr (SHP == 1) {
@@ -1952,6 +2012,7 @@ k_integrate(LaunchArgs L)
     __shared__ int s_desc[(NOUT + kWave - 1) / kWave * kWave];
     __shared__ double s_map[ORD == 1 || SHP == 1 ? 1 : O::NRX * O::NR];
     __shared__ double s_bll[NU];
+    static_assert(SHP != 1 || BS::NR <= NU, "a box's weighted row sums are summed in s_bll");
     __shared__ int64_t s_seg[kMaxSeg + 1];
     __shared__ int64_t s_item;
     __shared__ int s_sys;
@@ -2040,9 +2101,17 @@ k_integrate(LaunchArgs L)
         }
         __syncthreads();
         // B_ll of l (upper triangle; doubled for the adaptive-inner two-term form)
-        // joins the diagonal-block sums of l
-        if (A.form != NLQ_FORM_PAPER2 && !A.pb && threadIdx.x < NU)
-            unsafeAtomicAdd(&A.dmm[l * NU + threadIdx.x], s_bll[threadIdx.x]);
+        // joins the diagonal-block sums of l; boxes form it here from the summed
+        // weighted row sums
+        if (A.form != NLQ_FORM_PAPER2 && !A.pb && threadIdx.x < NU) {
+            double v = s_bll[threadIdx.x];
+            if constexpr (SHP == 1) {
+                const double *pr = A.boxprod + threadIdx.x * BS::NR;
+                v = 0.0;
+                for (int r = 0; r < BS::NR; ++r) v = fma(pr[r], s_bll[r], v);
+            }
+            unsafeAtomicAdd(&A.dmm[l * NU + threadIdx.x], v);
+        }
         if (threadIdx.x >= 1 && threadIdx.x <= A.lmax && s_leaf[threadIdx.x])
             atomicAdd(&A.counters->leaf[threadIdx.x], s_leaf[threadIdx.x]);
         if (threadIdx.x == 0 && s_leaf[0]) atomicAdd(&A.counters->zero_leaves, s_leaf[0]);
