@@ -1412,7 +1412,7 @@ int64_t or_rows(const or_mesh *m, const or_params *p, double thr, int32_t nthrea
     double *hi = (double *)malloc(sizeof(double) * ne * m->dim);
     all_bboxes(m, lo, hi);
     adjacency na = node_elements(m);
-    int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (ne + 1));
+    int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (m->n_nodes + 1));   /* one row's columns */
     /* pairs touching the rows: (e, x) with e containing the row node, x in J_e,
      * and (x, e) with e in J_x (found by the same brute-force test, from x's side) */
     int64_t cap = 1024, np = 0;

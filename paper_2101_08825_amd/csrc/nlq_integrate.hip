@@ -1320,14 +1320,44 @@ struct RowCache {
     int32_t first[20];
     int64_t base[20];
     int64_t len[20];
+    // a row that does not fit keeps every step-th column (int32) in its LDS area
+    // instead: the search narrows to one block of `step` columns there, then
+    // searches that block in the global row (0 samples: the whole global row)
+    const int32_t *samp[20];
+    int step[20];
+    int nsamp[20];
 };
+
+// int32 samples that fit in a row's LDS area of rowcap 16-bit entries, after
+// aligning its start to 4 bytes
+__host__ __device__ constexpr int row_sample_cap(int rowcap) { return (rowcap - 1) / 2; }
 
 // position of column c in cached row r, or -1 (a cached row holds at most
 // rowcap < 2^16 entries, so the lower-bound search runs in 32-bit arithmetic)
 __device__ __forceinline__ int64_t row_find(const RowCache *rc, int r, int32_t c)
 {
     const uint16_t *q = rc->c16[r];
-    if (!q) return search(rc->cols[r], rc->len[r], c);
+    if (!q) {
+        const int ns = rc->nsamp[r];
+        if (ns == 0) return search(rc->cols[r], rc->len[r], c);
+        const int32_t *sm = rc->samp[r];
+        if (c < sm[0]) return -1;
+        // k = the last sample <= c (sm[0] is the row's first column)
+        int lo = 0, n = ns;
+        while (n > 0) {
+            const int half = n >> 1;
+            if (sm[lo + half] <= c) {
+                lo += half + 1;
+                n -= half + 1;
+            } else {
+                n = half;
+            }
+        }
+        const int64_t b0 = static_cast<int64_t>(lo - 1) * rc->step[r];
+        const int64_t blen = rc->len[r] - b0 < rc->step[r] ? rc->len[r] - b0 : rc->step[r];
+        const int64_t at = search(rc->cols[r] + b0, blen, c);
+        return at < 0 ? -1 : b0 + at;
+    }
     const int32_t d = c - rc->first[r];
     if (d < 0 || d > 65535) return -1;
     const int len = static_cast<int>(rc->len[r]);
@@ -2074,13 +2104,28 @@ k_integrate(LaunchArgs L)
             s_rc.first[threadIdx.x] = first;
             s_rc.cols[threadIdx.x] = A.col + b;
             s_rc.c16[threadIdx.x] = fits ? rows_lds + threadIdx.x * L.rowcap : nullptr;
+            const int scap = row_sample_cap(L.rowcap);
+            int step = 0, ns = 0;
+            if (!fits && scap > 0) {
+                step = static_cast<int>((len + scap - 1) / scap);
+                ns = static_cast<int>((len + step - 1) / step);
+            }
+            const uintptr_t area = reinterpret_cast<uintptr_t>(rows_lds + threadIdx.x * L.rowcap);
+            s_rc.samp[threadIdx.x] = reinterpret_cast<const int32_t *>((area + 3) & ~static_cast<uintptr_t>(3));
+            s_rc.step[threadIdx.x] = step;
+            s_rc.nsamp[threadIdx.x] = ns;
         }
         __syncthreads();
         for (int r = 0; r < NB; ++r) {
             uint16_t *dst = const_cast<uint16_t *>(s_rc.c16[r]);
-            if (!dst) continue;
-            for (int64_t k = threadIdx.x; k < s_rc.len[r]; k += kThreads)
-                dst[k] = static_cast<uint16_t>(A.col[s_rc.base[r] + k] - s_rc.first[r]);
+            if (dst) {
+                for (int64_t k = threadIdx.x; k < s_rc.len[r]; k += kThreads)
+                    dst[k] = static_cast<uint16_t>(A.col[s_rc.base[r] + k] - s_rc.first[r]);
+            } else {
+                int32_t *sm = const_cast<int32_t *>(s_rc.samp[r]);
+                for (int k = threadIdx.x; k < s_rc.nsamp[r]; k += kThreads)
+                    sm[k] = A.col[s_rc.base[r] + static_cast<int64_t>(k) * s_rc.step[r]];
+            }
         }
         __syncthreads();
         const int64_t b0 = A.pair_off[l];

@@ -162,3 +162,37 @@ def test_box_rejects_fp32_and_deterministic(nlq_ctx):
     m.close()
     with pytest.raises(nlq.NlqError):
         nlq.Mesh.create(nlq_ctx, mesh.coords, mesh.conn, mesh.constrained, order=1, shape=2)
+
+
+def test_box_long_rows_vs_oracle(nlq_ctx, oracle_lib):
+    """Rows longer than the LDS row cache: 10^3 20-node hexahedra with
+    delta = 4h, so every row holds all 4,961 nodes, far beyond what the
+    hexahedral kernel keeps in LDS next to its per-wave buffers (rows of a few
+    hundred entries).  The epilogue then finds CSR positions through the sampled
+    columns in LDS and a search of one block of the global row.  The centre
+    node's row against the oracle's (pattern bit-exact, values <= 1e-12), and
+    every row sums to zero (SYM4: constants lie in the kernel of the operator)."""
+    from paper_2101_08825_amd import nlq
+    O = oracle_lib
+    _case("box_long_rows", n=10, order=2, lmax=2)
+    mesh = W.box_mesh(3, 10, 2, 2)
+    h = 0.1
+    delta, eps, lmax = 4 * h, h / 2, 2
+    m = nlq.Mesh.create(nlq_ctx, mesh.coords, mesh.conn, mesh.constrained, order=2, shape=1)
+    s = nlq.System(nlq_ctx, m, nlq.params(3, delta, eps, lmax, precision=0))
+    rp, col, val = s.csr()
+    assert int(np.max(np.diff(rp))) == mesh.n_nodes
+    mid = int(np.argmin(np.sum((mesh.coords - 0.5) ** 2, axis=1)))
+    om = O.OracleMesh(mesh.coords, mesh.conn, order=2, shape=1)
+    (ecols, evals), = O.rows(om, O.params(delta, eps, lmax), delta + eps, [mid])
+    got_c, got_v = col[rp[mid]:rp[mid + 1]], val[rp[mid]:rp[mid + 1]]
+    assert np.array_equal(got_c, ecols)
+    err = _maxrel(got_v, evals)
+    rs = np.add.reduceat(val, rp[:-1])
+    scale = np.max(np.abs(val))
+    print(f"  row {mid}: {len(ecols)} entries, error {err:.3e}; largest row sum {np.max(np.abs(rs)) / scale:.3e}",
+          flush=True)
+    assert err <= TOL64
+    assert np.max(np.abs(rs)) <= 1e-12 * scale * mesh.n_nodes
+    s.close()
+    m.close()
