@@ -575,7 +575,10 @@ template <int DIM, int ETA, int ORD = 1> struct PlainAcc {
     };
     static constexpr int NYP = DIM == 2 ? 8 : 16;
     static constexpr int K = kWave / NYP;
-    static constexpr int kStageBytes = kBatch * (DIM + S::NR) * 8;
+    // points per batch: 32 for P2 tetrahedra (35 rows a point), so that two
+    // workgroups' staging fits the LDS of a CU beside the row caches
+    static constexpr int kPoints = DIM == 3 && ORD == 2 ? 32 : kBatch;
+    static constexpr int kStageBytes = kPoints * (DIM + S::NR) * 8;
     struct In {
         double lam[S::NV];
         double w;
@@ -610,7 +613,7 @@ template <int DIM, int ETA, int ORD = 1> struct PlainAcc {
     template <class Edge> __device__ static void stage(char *work, int t, const In &in, const Edge &E)
     {
         double *sx = reinterpret_cast<double *>(work);
-        double *sp = sx + kBatch * DIM;
+        double *sp = sx + kPoints * DIM;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             double s = 0.0;
@@ -649,7 +652,7 @@ template <int DIM, int ETA, int ORD = 1> struct PlainAcc {
     {
         const Band64 KB = band64(A);
         const double *sx = reinterpret_cast<const double *>(work);
-        const double *sp = sx + kBatch * DIM;
+        const double *sp = sx + kPoints * DIM;
         const int k0 = lane_id() / NYP;
         if (!active) return;
         for (int p = k0; p < npts; p += K) {
@@ -1498,16 +1501,16 @@ template <int DIM> __device__ __forceinline__ void extend_rows(double *HQ)
 }
 
 // P2: rows NR + k = sum_r map[k][r] * (monomial total r), k < NRX
-template <int DIM> __device__ __forceinline__ void map_rows(double *HQ, const double *map)
+template <int DIM> __device__ __forceinline__ void map_rows(double *HQ, const float *map)
 {
     using O = OShape<DIM, 2>;
     constexpr int BW = Shape<DIM>::NQ <= 8 ? 8 : 16;
     for (int t = lane_id(); t < O::NRX * BW; t += kWave) {
         const int k = t / BW, b = t % BW;
-        const double *mk = map + k * O::NR;
+        const float *mk = map + k * O::NR;
         double v = 0.0;
 #pragma unroll
-        for (int r = 0; r < O::NR; ++r) v = fma(mk[r], HQ[r * 16 + b], v);
+        for (int r = 0; r < O::NR; ++r) v = fma(static_cast<double>(mk[r]), HQ[r * 16 + b], v);
         HQ[(O::NR + k) * 16 + b] = v;
     }
 }
@@ -1593,7 +1596,7 @@ template <int DIM, int ORD> __device__ void box_epilogue_tables(CArgs &A0, doubl
 template <int DIM, int PREC, int ETA, int ORD, int SHP = 0>
 __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pidx, char *wmem,
                              const double *s_rule, const float *s_w32, const double *s_T, const int *s_desc,
-                             const double *s_map, double *s_bll, const RowCache *rc, double *ex_block,
+                             const float *s_map, double *s_bll, const RowCache *rc, double *ex_block,
                              unsigned long long *s_leaf, int leafcap)
 {
     using S = Shape<DIM>;
@@ -1605,7 +1608,7 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     constexpr int NQ = SHP == 1 ? BS::NQ : S::NQ, RS = SHP == 1 ? DIM : NV;
     constexpr int NB = SHP == 1 ? BS::NB : O::NB, NU = SHP == 1 ? BS::NU : O::NU;
     constexpr int NOUT = SHP == 1 ? BS::NOUT : O::NOUT;
-    constexpr int BATCH = SHP == 1 ? BoxAcc<DIM, ETA, ORD>::kPoints : kBatch;
+    constexpr int BATCH = SHP == 1 ? BoxAcc<DIM, ETA, ORD>::kPoints : (PREC == 0 ? PlainAcc<DIM, ETA, ORD>::kPoints : kBatch);
     // FP64: the contraction on the matrix cores (Mfma64) for the 3D elements with
     // many rows (P2 tetrahedra: 35, hexahedra: 27 / 90); measured slower for P1
     // tetrahedra (10 rows: one FP64 MFMA per 64 evaluations takes longer than the
@@ -2022,9 +2025,14 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
 // registers (5 waves in 2D, 3 in 3D were fastest on the 2D 128^2 and 3D 8^3 cases).
 // (P2 and box elements: 2 waves per SIMD, 1 for hexahedra, so that their wider
 // rows, frames and accumulators stay in registers instead of spilling)
+template <int DIM, int PREC, int OCC, int ORD, int SHP> constexpr int kernel_waves()
+{
+    return SHP == 1 && DIM == 3 ? 1 : (SHP == 1 || ORD == 2 ? 2 : waves_per_eu<DIM, PREC, OCC>());
+}
+
 template <int DIM, int PREC, int ETA, int OCC, int ORD, int SHP = 0>
 __global__ void __launch_bounds__(kThreads)
-    __attribute__((amdgpu_waves_per_eu(SHP == 1 && DIM == 3 ? 1 : (SHP == 1 || ORD == 2 ? 2 : waves_per_eu<DIM, PREC, OCC>()))))
+    __attribute__((amdgpu_waves_per_eu(kernel_waves<DIM, PREC, OCC, ORD, SHP>())))
 k_integrate(LaunchArgs L)
 {
     using S = Shape<DIM>;
@@ -2040,7 +2048,8 @@ k_integrate(LaunchArgs L)
     // simplices: the constant rows of epilogue_tables; boxes: the inner basis [NB][QS]
     __shared__ __align__(16) double s_T[SHP == 1 ? NB * BS::QS : (NB + NU + 1) * 16];
     __shared__ int s_desc[(NOUT + kWave - 1) / kWave * kWave];
-    __shared__ double s_map[ORD == 1 || SHP == 1 ? 1 : O::NRX * O::NR];
+    // the P2 row map: small integers, exact in FP32 (checked where it is built)
+    __shared__ float s_map[ORD == 1 || SHP == 1 ? 1 : O::NRX * O::NR];
     __shared__ double s_bll[NU];
     static_assert(SHP != 1 || BS::NR <= NU, "a box's weighted row sums are summed in s_bll");
     __shared__ int64_t s_seg[kMaxSeg + 1];
@@ -2059,7 +2068,7 @@ k_integrate(LaunchArgs L)
     const double *rule0 = SHP == 1 ? A0.boxrule : A0.rule;
     for (int t = threadIdx.x; t < NQ * RS + NQ; t += kThreads) s_rule[t] = rule0[t];
     if constexpr (ORD == 2 && SHP == 0)
-        for (int t = threadIdx.x; t < O::NRX * O::NR; t += kThreads) s_map[t] = A0.p2map[t];
+        for (int t = threadIdx.x; t < O::NRX * O::NR; t += kThreads) s_map[t] = static_cast<float>(A0.p2map[t]);
     if (SHP == 0 && threadIdx.x < NQ) s_w32[threadIdx.x] = static_cast<float>(A0.rule[NQ * NV + threadIdx.x]);
     for (int t = threadIdx.x; t <= L.nseg; t += kThreads) s_seg[t] = L.seg_start[t];
     __syncthreads();
@@ -2183,7 +2192,8 @@ k_pair_blocks(LaunchArgs L)
     __shared__ float s_w32[16];
     __shared__ __align__(16) double s_T[SHP == 1 ? NB * BS::QS : (NB + NU + 1) * 16];
     __shared__ int s_desc[(NOUT + kWave - 1) / kWave * kWave];
-    __shared__ double s_map[ORD == 1 || SHP == 1 ? 1 : O::NRX * O::NR];
+    // the P2 row map: small integers, exact in FP32 (checked where it is built)
+    __shared__ float s_map[ORD == 1 || SHP == 1 ? 1 : O::NRX * O::NR];
     CArgs &A = *(CArgs *)(L.sys);
     const int wid = threadIdx.x / kWave;
     char *wmem = smem + wid * WaveMem<DIM, PREC, ORD, SHP>::bytes(L.capl, L.leafcap);
@@ -2191,7 +2201,7 @@ k_pair_blocks(LaunchArgs L)
     for (int t = threadIdx.x; t < NQ * RS + NQ; t += kThreads) s_rule[t] = rule0[t];
     if (SHP == 0 && threadIdx.x < NQ) s_w32[threadIdx.x] = static_cast<float>(A.rule[NQ * NV + threadIdx.x]);
     if constexpr (ORD == 2 && SHP == 0)
-        for (int t = threadIdx.x; t < O::NRX * O::NR; t += kThreads) s_map[t] = A.p2map[t];
+        for (int t = threadIdx.x; t < O::NRX * O::NR; t += kThreads) s_map[t] = static_cast<float>(A.p2map[t]);
     __syncthreads();
     if constexpr (SHP == 1) box_epilogue_tables<DIM, ORD>(A, s_T, s_desc);
     else epilogue_tables<DIM, ORD>(s_rule, s_T, s_desc);
@@ -2263,8 +2273,13 @@ int fit_rowcap(int capl, int rowcap, int leafcap)
     hipFuncAttributes fa{};
     NLQ_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(kern)));
     const int nb = SHP == 1 ? BoxShape<DIM, ORD>::NB : OShape<DIM, ORD>::NB;
-    const int room = kLdsBytes - static_cast<int>(fa.sharedSizeBytes) - 16 -
-                     kWaves * WaveMem<DIM, PREC, ORD, SHP>::bytes(capl, leafcap);
+    const int fixed = static_cast<int>(fa.sharedSizeBytes) + 16 + kWaves * WaveMem<DIM, PREC, ORD, SHP>::bytes(capl, leafcap);
+    // the LDS share of one workgroup when a CU holds as many as its registers
+    // allow (one wave per SIMD each); if that leaves under 64 entries a row, one
+    // workgroup takes the whole LDS instead (rows that do not fit are searched
+    // through their sampled columns, see RowCache)
+    int room = kLdsBytes / kernel_waves<DIM, PREC, OCC, ORD, SHP>() - fixed;
+    if (room / (2 * nb) - 8 < 64) room = kLdsBytes - fixed;
     const int fit = room / (2 * nb) - 8;
     return std::max(1, std::min(rowcap, fit));
 }

@@ -196,6 +196,10 @@ std::vector<double> make_p2_map(int dim)
             if (it == index.end()) fail(NLQ_EDEVICE, "P2 map: a product is not a quartic");
             map[r * nr + it->second] += t.second;
         }
+    // the kernels keep the map in FP32: every coefficient is a small integer
+    for (double v : map)
+        if (static_cast<double>(static_cast<float>(v)) != v || v != std::floor(v))
+            fail(NLQ_EDEVICE, "P2 map: a coefficient is not a small integer");
     return map;
 }
 
