@@ -1519,14 +1519,14 @@ template <int DIM> __device__ __forceinline__ void map_rows(double *HQ, const fl
 // b, sum_a w_a xi_a^{e_r} g_ab (times |det F_m'(g_b)| / |E_m|).  Then
 //   PHI[I][b] = sum_r phi_I[r] HQ[r][b]   (the outer basis function phi_I),
 //   R1[r]     = sum_b w_b HQ[r][b]        (the rows summed against the inner weights).
-template <int DIM, int ORD> __device__ __forceinline__ void box_rows(CArgs &A, double *HQ, const double *wq)
+template <int DIM, int ORD> __device__ __forceinline__ void box_rows(const double *phi, double *HQ, const double *wq)
 {
     using BS = BoxShape<DIM, ORD>;
     constexpr int NR = BS::NR, NB = BS::NB, NQ = BS::NQ, QS = BS::QS;
     double *PHI = HQ + NR * QS, *R1 = PHI + NB * QS;
     for (int t = lane_id(); t < NB * NQ; t += kWave) {
         const int I = t / NQ, b = t - I * NQ;
-        const double *ph = A.boxphi + I * NR;
+        const double *ph = phi + I * NR;
         double v = 0.0;
         for (int r = 0; r < NR; ++r) v = fma(ph[r], HQ[r * QS + b], v);
         PHI[I * QS + b] = v;
@@ -1572,6 +1572,8 @@ template <int DIM, int ORD> __device__ void box_epilogue_tables(CArgs &A0, doubl
     using BS = BoxShape<DIM, ORD>;
     constexpr int NB = BS::NB, NU = BS::NU, NPASS = (BS::NOUT + kWave - 1) / kWave;
     for (int t = threadIdx.x; t < NB * BS::QS; t += kThreads) s_psi[t] = A0.boxpsi[t];
+    // then the outer basis over the product monomials, [NB][NR] (box_rows)
+    for (int t = threadIdx.x; t < NB * BS::NR; t += kThreads) s_psi[NB * BS::QS + t] = A0.boxphi[t];
     for (int o = threadIdx.x; o < NPASS * kWave; o += kThreads) {
         int kind = kOutNone, i = 0, j = 0, u = 0;
         if (o < NB * NB) {
@@ -1922,7 +1924,7 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
     if constexpr (SHP == 1) {
         acc.finish(HQ, jm);
         wave_sync();
-        box_rows<DIM, ORD>(A, HQ, wq);
+        box_rows<DIM, ORD>(s_T + NB * BS::QS, HQ, wq);
     } else {
         acc.finish(HQ, tile);
         wave_sync();
@@ -2045,8 +2047,8 @@ k_integrate(LaunchArgs L)
     extern __shared__ __align__(16) char smem[];
     __shared__ double s_rule[NQ * RS + NQ];
     __shared__ float s_w32[16];
-    // simplices: the constant rows of epilogue_tables; boxes: the inner basis [NB][QS]
-    __shared__ __align__(16) double s_T[SHP == 1 ? NB * BS::QS : (NB + NU + 1) * 16];
+    // simplices: the constant rows of epilogue_tables; boxes: the inner basis [NB][QS], then the outer basis [NB][NR]
+    __shared__ __align__(16) double s_T[SHP == 1 ? NB * (BS::QS + BS::NR) : (NB + NU + 1) * 16];
     __shared__ int s_desc[(NOUT + kWave - 1) / kWave * kWave];
     // the P2 row map: small integers, exact in FP32 (checked where it is built)
     __shared__ float s_map[ORD == 1 || SHP == 1 ? 1 : O::NRX * O::NR];
@@ -2190,7 +2192,7 @@ k_pair_blocks(LaunchArgs L)
     extern __shared__ __align__(16) char smem[];
     __shared__ double s_rule[NQ * RS + NQ];
     __shared__ float s_w32[16];
-    __shared__ __align__(16) double s_T[SHP == 1 ? NB * BS::QS : (NB + NU + 1) * 16];
+    __shared__ __align__(16) double s_T[SHP == 1 ? NB * (BS::QS + BS::NR) : (NB + NU + 1) * 16];
     __shared__ int s_desc[(NOUT + kWave - 1) / kWave * kWave];
     // the P2 row map: small integers, exact in FP32 (checked where it is built)
     __shared__ float s_map[ORD == 1 || SHP == 1 ? 1 : O::NRX * O::NR];
