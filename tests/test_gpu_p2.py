@@ -164,3 +164,42 @@ def test_p2_rejects_fp32_and_deterministic(nlq_ctx):
         with pytest.raises(nlq.NlqError):
             nlq.System(nlq_ctx, m, nlq.params(2, 0.5, 0.05, 2, **kw))
     m.close()
+
+
+def test_p2_long_rows_vs_oracle(nlq_ctx, oracle_lib):
+    """Rows longer than the LDS row cache for P2 tetrahedra: 6^3 x 6 10-node
+    tetrahedra with delta = 3h, so every row holds all 2,197 nodes, while the
+    3D P2 kernel, run at two workgroups per CU, keeps only a few dozen entries
+    a row in LDS.  The epilogue then finds CSR positions through the sampled
+    columns in LDS and one block of the global row.  The centre node's row
+    against the oracle's (pattern bit-exact, values <= 1e-12), every row sums to
+    zero, and A is symmetric bit for bit."""
+    from paper_2101_08825_amd import nlq
+    O = oracle_lib
+    _case("p2_long_rows", n=6, lmax=2)
+    mesh = W.kuhn_mesh_p2(3, 6, 1)
+    h = 1.0 / 6
+    delta, eps, lmax = 3 * h, 3 * h / 16, 2
+    m = nlq.Mesh.create(nlq_ctx, mesh.coords, mesh.conn, mesh.constrained, order=2)
+    s = nlq.System(nlq_ctx, m, nlq.params(3, delta, eps, lmax, precision=0))
+    rp, col, val = s.csr()
+    nn = mesh.coords.shape[0]
+    assert int(np.max(np.diff(rp))) == nn
+    mid = int(np.argmin(np.sum((mesh.coords - 0.5) ** 2, axis=1)))
+    om = O.OracleMesh(mesh.coords, mesh.conn, order=2)
+    (ecols, evals), = O.rows(om, O.params(delta, eps, lmax), delta + eps, [mid])
+    got_c, got_v = col[rp[mid]:rp[mid + 1]], val[rp[mid]:rp[mid + 1]]
+    assert np.array_equal(got_c, ecols)
+    err = _maxrel(got_v, evals)
+    rs = np.add.reduceat(val, rp[:-1])
+    scale = np.max(np.abs(val))
+    import scipy.sparse as sp
+    A = sp.csr_matrix((val, col, rp), shape=(nn, nn))
+    asym = abs(A - A.T).max()
+    print(f"  row {mid}: {len(ecols)} entries, error {err:.3e}; largest row sum {np.max(np.abs(rs)) / scale:.3e}; "
+          f"asymmetry {asym:.1e}", flush=True)
+    assert err <= TOL64
+    assert np.max(np.abs(rs)) <= 1e-12 * scale * nn
+    assert asym == 0.0
+    s.close()
+    m.close()
