@@ -10,19 +10,22 @@
 //     part of its pair list) from a global counter, stages the CSR rows of l's
 //     nodes in LDS, and its waves take the pairs (l, m), m in J_l, from an LDS
 //     counter;
-//   * a wave walks the refinement tree of its pair level by level: lanes
-//     classify sub-elements in FP64 (every rounding as written, so the leaf set
-//     is reproducible bit for bit), wave ballots + prefix counts compact the
-//     integrate / refine lists in LDS;
+//   * a wave walks the refinement tree of its pair depth first with a bounded
+//     stack in LDS, up to 64 sub-elements a pass: lanes classify them in FP64
+//     (every rounding as written, so the leaf set is reproducible bit for bit),
+//     wave ballots + prefix counts push the refined ones' children and append
+//     the leaves to a leaf buffer;
 //   * the pair's leaves are integrated in batches of 64 outer points staged in
 //     LDS (the table loads of the next batch are issued before the current
 //     batch runs):
 //       plain  (FP64): each lane owns one inner point and a slice of the batch,
 //                      evaluates gamma_eps in FP64 and accumulates
-//                      H_ib = sum_a P_i(a) g_ab, Q_kb = sum_a P_k(a) g_ab in FP64;
+//                      H_ib = sum_a P_i(a) g_ab, Q_kb = sum_a P_k(a) g_ab in FP64
+//                      (3D P2 and box elements: the same sums on the FP64
+//                      matrix cores, v_mfma_f64_16x16x4f64);
 //       mixed  (FP32): anchor-relative FP32 coordinates, gamma_eps in FP32 and the
 //                      contraction H = P^T G on the matrix cores
-//                      (v_mfma_f32_16x16x4f32), flushed to FP64 every batch;
+//                      (v_mfma_f32_16x16x4f32), flushed to FP64 every two batches;
 //     with P_i(a) = w_a 2^{-N(lev-1)} lambda_i(x_a) (rows i < N+1) and
 //     P_k(a) = w_a 2^{-N(lev-1)} lambda_i lambda_j (k = off-diagonal pair i < j);
 //   * FP64 epilogue: S = C |E_l| |E_m|,
@@ -34,7 +37,7 @@
 //     one output per lane as a dot product over b with a constant row;
 //   * accumulation (FP64): SYM4 blocks are symmetric and B_ml = B_lm^T, so the
 //     launch builds a half matrix R with A = R + R^T: B_lm goes to (l_i, m_j)
-//     through the LDS-cached row of l_i, the upper triangles of B_mm (per pair)
+//     through the LDS-cached row of l_i (or its sampled columns), the upper triangles of B_mm (per pair)
 //     and B_ll (per outer element, summed in LDS) go to a per-element array;
 //     a fold pass adds that array to R and a last pass forms R + R^T in place,
 //     which makes A symmetric bit for bit.  The two-term form writes its
@@ -2024,9 +2027,10 @@ __device__ __forceinline__ void process_pair(CArgs &A, int l, int m, int64_t pid
 // -------------------------------------------------------------- kernels
 
 // Occupancy hint: more waves per SIMD cover LDS and table latency at the cost of
-// registers (5 waves in 2D, 3 in 3D were fastest on the 2D 128^2 and 3D 8^3 cases).
-// (P2 and box elements: 2 waves per SIMD, 1 for hexahedra, so that their wider
-// rows, frames and accumulators stay in registers instead of spilling)
+// registers (5 waves in 2D, 4 for the 3D FP32 path and 3 for the 3D FP64 path
+// were fastest on the 2D 128^2 and 3D 8^3 cases; see waves_per_eu).  P2 and box
+// elements: 2 waves per SIMD, 1 for hexahedra, so that their wider rows, frames
+// and accumulators stay in registers instead of spilling.
 template <int DIM, int PREC, int OCC, int ORD, int SHP> constexpr int kernel_waves()
 {
     return SHP == 1 && DIM == 3 ? 1 : (SHP == 1 || ORD == 2 ? 2 : waves_per_eu<DIM, PREC, OCC>());
