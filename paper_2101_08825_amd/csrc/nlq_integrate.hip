@@ -283,11 +283,11 @@ template <int ETA> __device__ __forceinline__ double kernel64(const Band64 &K, d
 }
 
 // mu at distance d (FP32), without branches: the band coordinate
-// r = (delta - d) / eps is clamped to [-1, 1], where the Horner form of xi gives
-// exactly 0 and 1 (all its partial sums are multiples of 1/256), so the plateau
-// and the outside need no separate case.  Every evaluation costs the same, but a
-// wave no longer diverges between the three cases (a leaf that straddles the
-// band nearly always holds all three).
+// r = (delta - d) / eps is clamped to [-1, 1], where the factored form of xi
+// gives exactly 0 and 1 (s = 1 - |r| is 0 there), so the plateau and the
+// outside need no separate case.  Every evaluation costs the same, but a wave
+// no longer diverges between the three cases (a leaf that straddles the band
+// nearly always holds all three).
 // doe = delta / eps, held in a vector register by the caller (a multiply-add
 // reads at most one scalar register, and 1 / eps is the other operand).
 __device__ __forceinline__ float mu32(CArgs &A, float d, float doe)
@@ -313,12 +313,11 @@ template <int ETA> __device__ __forceinline__ float kernel32(CArgs &A, float d2,
 }
 
 // gamma_eps / C of the 64 squared distances one register holds across the wave
-// (one per lane).  When no lane's distance is in the band, mu is a step (1 on
-// the plateau, 0 beyond) and the square root and xi are skipped for the whole
-// register: a wave-uniform branch.  Both sides of the branch give the same
-// values up to the band edges, where xi is within (1e-7)^5 of 1 or 0.
-// kernel64 with the band test taken once per wave: a register none of whose
-// distances lies in the band skips the square root and xi (same values)
+// (one per lane), with the band test taken once per register: when no lane's
+// distance is in the band, mu is a step (1 on the plateau, 0 beyond) and the
+// square root and xi are skipped for the whole register (a wave-uniform
+// branch).  Both sides of the branch give the same values up to the band edges,
+// where xi is within (1e-7)^5 of 1 or 0 in FP32.  FP64 here, FP32 below.
 template <int ETA> __device__ __forceinline__ double kernel64_reg(const Band64 &K, double d2)
 {
     const bool plateau = d2 < K.dme2;
