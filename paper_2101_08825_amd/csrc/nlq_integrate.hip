@@ -1233,15 +1233,22 @@ template <int DIM, int ETA> struct MixedAccMfma {
             __builtin_amdgcn_s_setprio(2);
             const floatx4 v = __builtin_amdgcn_mfma_f32_16x16x4f32(a_d, bop, floatx4{yb2, yb2, yb2, yb2}, 0, 0, 0);
             __builtin_amdgcn_s_setprio(0);
+            // a register whose 64 distances all lie beyond delta + eps has gamma = 0
+            // everywhere: its contraction step would add exact zeros and is skipped
             float g[4];
+            unsigned long long inside[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) g[r] = gamma(A, v[r]);
+            for (int r = 0; r < 4; ++r) {
+                inside[r] = __builtin_amdgcn_ballot_w64(v[r] <= A.f_dpe2);
+                g[r] = gamma(A, v[r]);
+            }
             float a4[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) a4[r] = sp[(p0 + 4 * acol + r) * PS + arow];
             __builtin_amdgcn_s_setprio(2);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[r], g[r], acc, 0, 0, 0);
+            for (int r = 0; r < 4; ++r)
+                if (inside[r]) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[r], g[r], acc, 0, 0, 0);
             __builtin_amdgcn_s_setprio(0);
         }
         facc = acc;
