@@ -203,3 +203,44 @@ def test_p2_long_rows_vs_oracle(nlq_ctx, oracle_lib):
     assert asym == 0.0
     s.close()
     m.close()
+
+
+def test_p2_row_cache_modes_agree(tmp_path, nlq_ctx):
+    """The two row-cache modes of the P2 kernel on the mesh of the long-row test:
+    default capacities leave room for two workgroups per CU and a row cache far
+    shorter than the rows (sampled columns), while stack 512 / leaf buffer 256
+    (loaded from a tuning cache file) leave room for one workgroup only, whose
+    row cache then takes the whole LDS and holds every row.  Leaf counts equal,
+    values equal to FP64 rounding."""
+    from paper_2101_08825_amd import nlq
+    _case("p2_row_cache_modes", n=6, lmax=2)
+    mesh = W.kuhn_mesh_p2(3, 6, 1)
+    h = 1.0 / 6
+    prm = nlq.params(3, 3 * h, 3 * h / 16, 2, precision=0)
+    m = nlq.Mesh.create(nlq_ctx, mesh.coords, mesh.conn, mesh.constrained, order=2)
+    ref = nlq.System(nlq_ctx, m, prm)
+    _, _, v_ref = ref.csr()
+    leaves_ref = list(ref.info().n_leaf)
+    ref.autotune(budget_s=0.5)        # puts the system's key into the cache file
+    path = tmp_path / "t.txt"
+    nlq_ctx.tune_save(path)
+    ref.close()
+    m.close()
+    lines = path.read_text().splitlines()
+    head, keyed = lines[0], [ln for ln in lines[1:] if ln.split()[2] == "2"]
+    assert keyed, lines
+    f = keyed[0].split()
+    f[10], f[11] = "512", "256"
+    path.write_text(head + "\n" + " ".join(f) + "\n")
+    c2 = nlq.Context(0)
+    assert c2.tune_load(path) == 1
+    m2 = nlq.Mesh.create(c2, mesh.coords, mesh.conn, mesh.constrained, order=2)
+    s2 = nlq.System(c2, m2, prm)
+    _, _, v = s2.csr()
+    err = _rel(v, v_ref)
+    print(f"  stack 512 / leaf 256 vs default: rel {err:.3e}", flush=True)
+    assert list(s2.info().n_leaf) == leaves_ref
+    assert err <= 1e-13
+    s2.close()
+    m2.close()
+    c2.close()
