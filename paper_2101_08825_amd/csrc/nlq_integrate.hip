@@ -1234,12 +1234,16 @@ template <int DIM, int ETA> struct MixedAccMfma {
             const floatx4 v = __builtin_amdgcn_mfma_f32_16x16x4f32(a_d, bop, floatx4{yb2, yb2, yb2, yb2}, 0, 0, 0);
             __builtin_amdgcn_s_setprio(0);
             // a register whose 64 distances all lie beyond delta + eps has gamma = 0
-            // everywhere: its contraction step would add exact zeros and is skipped
+            // everywhere: its contraction step would add exact zeros and is skipped.
+            // The mask is the wave's ordered v <= (delta + eps)^2 comparison (LLVM
+            // predicate 5, FCMP_OLE), the same comparison as the band test's, which
+            // the compiler then shares (a ballot of the boolean was re-materialised
+            // through two vector instructions for one of the four registers).
             float g[4];
             unsigned long long inside[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                inside[r] = __builtin_amdgcn_ballot_w64(v[r] <= A.f_dpe2);
+                inside[r] = __builtin_amdgcn_fcmpf(v[r], A.f_dpe2, 5);
                 g[r] = gamma(A, v[r]);
             }
             float a4[4];
