@@ -191,17 +191,16 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // xi(-|r|) = s^5 Q(s) and xi(|r|) = 1 - xi(-|r|).
 __device__ __forceinline__ double xi64(double r)
 {
-    const double a = fabs(r);
-    const double t = 0.5 - a;
-    const double sg = 1.0 - a;
+    const double sgn = copysign(1.0, r);
+    const double t = 0.5 - fabs(r);
+    const double ss = sgn - r;    // sgn * s
     double q = 35.0 / 256.0;
     q = fma(q, t, -245.0 / 256.0);
     q = fma(q, t, 660.0 / 256.0);
     q = fma(q, t, -3275.0 / 1024.0);
     q = fma(q, t, 6413.0 / 4096.0);
-    const double s2 = sg * sg;
-    const double w = (s2 * s2) * (sg * q);
-    return r < 0.0 ? w : 1.0 - w;
+    const double s2 = ss * ss;
+    return fma(-(s2 * s2), ss * q, fma(sgn, 0.5, 0.5));
 }
 
 // xi in FP32 with relative accuracy where it is small.  xi' = (315/256)(1 - r^2)^4
@@ -215,19 +214,22 @@ __device__ __forceinline__ double xi64(double r)
 // relative, down to xi = 0 at the outer band edge (the plain Horner form in r,
 // 1/2 + r p(r^2), carries an absolute error of ~1e-7 there, where xi ~ (1+r)^5).
 // At |r| = 1 sigma is 0, so the clamped plateau and outside give exactly 1 and 0.
+// The two sides are one expression: with g = sign(r) (+1 at r = +0) and
+// m = (1 + g) / 2, xi = m - g sigma^5 Q, where g sigma = g - r is formed exactly as
+// sigma would be; both sides then round as 1 - sigma^5 Q (one multiply-add) and
+// sigma^5 Q (one multiply) would, without a compare and a select.
 __device__ __forceinline__ float xi32(float r)
 {
-    const float a = fabsf(r);
-    const float t = 0.5f - a;
-    const float sg = 1.0f - a;
+    const float sgn = copysignf(1.0f, r);
+    const float t = 0.5f - fabsf(r);
+    const float ss = sgn - r;    // sgn * sigma
     float q = 35.0f / 256.0f;
     q = fmaf(q, t, -245.0f / 256.0f);
     q = fmaf(q, t, 660.0f / 256.0f);
     q = fmaf(q, t, -3275.0f / 1024.0f);
     q = fmaf(q, t, 6413.0f / 4096.0f);
-    const float s2 = sg * sg;
-    const float w = (s2 * s2) * (sg * q);
-    return r < 0.0f ? w : 1.0f - w;
+    const float s2 = ss * ss;
+    return fmaf(-(s2 * s2), ss * q, fmaf(sgn, 0.5f, 0.5f));
 }
 
 // The constants of the FP64 kernel evaluation, copied into vector registers once
@@ -1203,13 +1205,14 @@ template <int DIM, int ETA> struct MixedAccMfma {
     }
     // gamma_eps / C of tile value v = |x|^2 - 2 x.y + |y|^2 = |x - y|^2.  The
     // band test and the plateau take v as it is (a slightly negative v from the
-    // cancellation of nearly equal points lies on the plateau); only the square
-    // root of the band path needs it clamped at 0.
+    // cancellation of nearly equal points lies on the plateau); the band path
+    // takes |v| (a source modifier of the square root), which for such a v is a
+    // distance far inside the plateau as well.
     __device__ __forceinline__ float gamma(CArgs &A, float v) const
     {
         const bool plateau = v < A.f_dme2;
         const bool band = !plateau && v <= A.f_dpe2;
-        const float d2 = __builtin_amdgcn_fmed3f(v, 0.0f, 3.0e38f);
+        const float d2 = fabsf(v);
         if (__builtin_amdgcn_ballot_w64(band)) return kernel32<ETA>(A, d2, doe);
         float g = plateau ? 1.0f : 0.0f;
         if (ETA == NLQ_ETA_GAUSS) g = plateau ? __expf(-d2 * A.f_inv_delta2) : 0.0f;
