@@ -1143,9 +1143,13 @@ template <int DIM, int ETA> struct MixedAccMfma {
     static constexpr int PS = S::NR;
     static constexpr int kXBytes = kBatch * XS * 4;
     static constexpr int kStageBytes = kXBytes + kBatch * PS * 4;
-    // one point: its row of the precomputed table (P0..P9, lambda_1..lambda_3)
+    // one point: its row of the precomputed table (P0..P9, lambda_1..lambda_3; the
+    // row's last three floats are padding and not loaded: registers loaded but
+    // never read are reused while the load is in flight, which makes the wave
+    // wait for it)
     struct In {
-        floatx4 r0, r1, r2, r3;
+        floatx4 r0, r1, r2;
+        float l3;
     };
     double dacc[4];
     floatx4 facc;    // FP32 sums of the batches since the last flush
@@ -1182,14 +1186,14 @@ template <int DIM, int ETA> struct MixedAccMfma {
     {
         const int row = valid ? sub * S::NQ + a : A.pt32_zero;
         const floatx4 *t = reinterpret_cast<const floatx4 *>(A.pt32 + static_cast<int64_t>(row) * 16);
-        return In{t[0], t[1], t[2], t[3]};
+        return In{t[0], t[1], t[2], reinterpret_cast<const float *>(t)[12]};
     }
     // point t of the batch: anchor-relative coordinates, |x|^2 and the P rows
     template <class Edge> __device__ static void stage(char *work, int t, const In &in, const Edge &E)
     {
         float *sx = reinterpret_cast<float *>(work);
         float *sp = reinterpret_cast<float *>(work + kXBytes);
-        const float l1 = in.r2[2], l2 = in.r2[3], l3 = in.r3[0];
+        const float l1 = in.r2[2], l2 = in.r2[3], l3 = in.l3;
         float x[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) x[k] = fmaf(l3, E.e[2][k], fmaf(l2, E.e[1][k], l1 * E.e[0][k]));
@@ -1224,11 +1228,14 @@ template <int DIM, int ETA> struct MixedAccMfma {
         const float *sp = reinterpret_cast<const float *>(work + kXBytes);
         floatx4 acc = facc;
         const int tiles = (npts + 15) / 16;
+        // the distance operand of the next tile is read one tile ahead
+        float a_next = sx[arow * XS + acol];
 #pragma unroll
         for (int ss = 0; ss < kBatch / 16; ++ss) {
             if (ss >= tiles) break;
             const int p0 = ss * 16;
-            const float a_d = sx[(p0 + arow) * XS + acol];
+            const float a_d = a_next;
+            if (ss + 1 < kBatch / 16) a_next = sx[(p0 + 16 + arow) * XS + acol];
             // C = |y_j|^2 in every row: the tile is |x_i - y_j|^2 directly
             // the wave issues its matrix-core instructions at a raised priority (and
             // drops back for the vector work), so that a wave waiting to issue them
@@ -1236,6 +1243,11 @@ template <int DIM, int ETA> struct MixedAccMfma {
             __builtin_amdgcn_s_setprio(2);
             const floatx4 v = __builtin_amdgcn_mfma_f32_16x16x4f32(a_d, bop, floatx4{yb2, yb2, yb2, yb2}, 0, 0, 0);
             __builtin_amdgcn_s_setprio(0);
+            // the contraction's A operands, read before the mollifier so that the LDS
+            // latency passes under its vector work
+            float a4[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a4[r] = sp[(p0 + 4 * acol + r) * PS + arow];
             // a register whose 64 distances all lie beyond delta + eps has gamma = 0
             // everywhere: its contraction step would add exact zeros and is skipped.
             // The mask is the wave's ordered v <= (delta + eps)^2 comparison (LLVM
@@ -1249,9 +1261,6 @@ template <int DIM, int ETA> struct MixedAccMfma {
                 inside[r] = __builtin_amdgcn_fcmpf(v[r], A.f_dpe2, 5);
                 g[r] = gamma(A, v[r]);
             }
-            float a4[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) a4[r] = sp[(p0 + 4 * acol + r) * PS + arow];
             __builtin_amdgcn_s_setprio(2);
 #pragma unroll
             for (int r = 0; r < 4; ++r)
