@@ -1084,11 +1084,19 @@ template <int DIM, int ETA> struct MixedAccDirect {
         const float *sp = reinterpret_cast<const float *>(work) + kBatch * XS + poff * PS + sub;
         floatx4 acc = facc;
         const int steps = (npts + PPS - 1) / PPS;
+        // each step's operands are read one step ahead, so that their LDS latency
+        // passes under the previous step's vector work
+        float a_next = sp[0];
+        float2 x_next = *reinterpret_cast<const float2 *>(sx);
 #pragma unroll
         for (int t = 0; t < STEPS; ++t) {
             if (t >= steps) break;
-            const float a = sp[t * PPS * PS];
-            const float2 x = *reinterpret_cast<const float2 *>(sx + t * PPS * XS);
+            const float a = a_next;
+            const float2 x = x_next;
+            if (t + 1 < STEPS) {
+                a_next = sp[(t + 1) * PPS * PS];
+                x_next = *reinterpret_cast<const float2 *>(sx + (t + 1) * PPS * XS);
+            }
             const float dx = x.x - yh[0], dy = x.y - yh[1];
             const float d2 = fmaf(dx, dx, dy * dy);
             const float g = kernel32_reg<ETA>(A, d2, doe);
