@@ -1150,7 +1150,10 @@ template <int DIM, int ETA> struct MixedAccMfma {
     static constexpr int XS = 4;                            // x, y, z, |x|^2 per point
     static constexpr int PS = S::NR;
     static constexpr int kXBytes = kBatch * XS * 4;
-    static constexpr int kStageBytes = kXBytes + kBatch * PS * 4;
+    // the P rows come first, so that the contraction operands of a batch's first two
+    // tiles are read at the instruction's own offsets, without an address add
+    static constexpr int kPBytes = kBatch * PS * 4;
+    static constexpr int kStageBytes = kXBytes + kPBytes;
     // one point: its row of the precomputed table (P0..P9, lambda_1..lambda_3; the
     // row's last three floats are padding and not loaded: registers loaded but
     // never read are reused while the load is in flight, which makes the wave
@@ -1199,8 +1202,8 @@ template <int DIM, int ETA> struct MixedAccMfma {
     // point t of the batch: anchor-relative coordinates, |x|^2 and the P rows
     template <class Edge> __device__ static void stage(char *work, int t, const In &in, const Edge &E)
     {
-        float *sx = reinterpret_cast<float *>(work);
-        float *sp = reinterpret_cast<float *>(work + kXBytes);
+        float *sx = reinterpret_cast<float *>(work + kPBytes);
+        float *sp = reinterpret_cast<float *>(work);
         const float l1 = in.r2[2], l2 = in.r2[3], l3 = in.l3;
         float x[3];
 #pragma unroll
@@ -1232,8 +1235,8 @@ template <int DIM, int ETA> struct MixedAccMfma {
     }
     __device__ void run(CArgs &A, const char *work, int npts)
     {
-        const float *sx = reinterpret_cast<const float *>(work);
-        const float *sp = reinterpret_cast<const float *>(work + kXBytes);
+        const float *sx = reinterpret_cast<const float *>(work + kPBytes);
+        const float *sp = reinterpret_cast<const float *>(work);
         floatx4 acc = facc;
         const int tiles = (npts + 15) / 16;
         // the distance operand of the next tile is read one tile ahead
