@@ -1247,9 +1247,7 @@ template <int DIM, int ETA> struct MixedAccMfma {
             const int p0 = ss * 16;
             const float a_d = a_next;
             if (ss + 1 < kBatch / 16) a_next = sx[(p0 + 16 + arow) * XS + acol];
-            // C = |y_j|^2 in every row: the tile is |x_i - y_j|^2 directly (issued at
-            // the normal priority: the scheduler moved it out of a raised-priority
-            // bracket, and the empty bracket's two scalar instructions cost 0.6%)
+            // C = |y_j|^2 in every row: the tile is |x_i - y_j|^2 directly
             const floatx4 v = __builtin_amdgcn_mfma_f32_16x16x4f32(a_d, bop, floatx4{yb2, yb2, yb2, yb2}, 0, 0, 0);
             // the contraction's A operands, read before the mollifier so that the LDS
             // latency passes under its vector work
@@ -1269,14 +1267,9 @@ template <int DIM, int ETA> struct MixedAccMfma {
                 inside[r] = __builtin_amdgcn_fcmpf(v[r], A.f_dpe2, 5);
                 g[r] = gamma(A, v[r]);
             }
-            // the wave issues its contraction steps at a raised priority (and drops back
-            // for the vector work), so that a wave waiting to issue them is not held
-            // behind the other waves' vector instructions
-            __builtin_amdgcn_s_setprio(2);
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 if (inside[r]) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[r], g[r], acc, 0, 0, 0);
-            __builtin_amdgcn_s_setprio(0);
         }
         facc = acc;
         if (++nb == kFlushBatches) flush();
